@@ -1,0 +1,234 @@
+"""CPU FP64 oracle for the Lanczos Dirac propagator -- TEST INFRASTRUCTURE.
+
+Thin ctypes wrapper over ``dirac_oracle.c`` (plain C, double precision,
+literal Fig. 1 of Beerwerth & Bauke, arXiv:1407.7370).  Only the tests, the
+smoke check and the CPU-baseline leg of the benchmark may import this module;
+the GPU library never does.  It shares no code with the GPU library.
+
+Functions take a plain ``dict`` describing the physical problem (the keys of
+``ORC_KEYS``) and numpy complex128 arrays of shape ``(2, ny, nx)``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "dirac_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+             "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("x_min", ctypes.c_double), ("x_max", ctypes.c_double),
+        ("y_min", ctypes.c_double), ("y_max", ctypes.c_double),
+        ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32),
+        ("mass", ctypes.c_double), ("c", ctypes.c_double), ("charge", ctypes.c_double),
+        ("bz", ctypes.c_double),
+        ("pot_kind", ctypes.c_int32), ("pot_z", ctypes.c_double), ("pot_a", ctypes.c_double),
+        ("v_table", ctypes.c_void_p),
+        ("pulse_kind", ctypes.c_int32),
+        ("pulse_e", ctypes.c_double * 2), ("a0", ctypes.c_double), ("omega", ctypes.c_double),
+        ("t_pulse", ctypes.c_double),
+        ("n_coef", ctypes.c_int32), ("coef", ctypes.c_void_p),
+    ]
+
+
+class _Stat(ctypes.Structure):
+    _fields_ = [("k_eff", ctypes.c_int32), ("err_est", ctypes.c_double),
+                ("cum_bound", ctypes.c_double), ("norm2", ctypes.c_double)]
+
+
+ORC_KEYS = ("nx", "ny", "x_min", "x_max", "y_min", "y_max", "bc_x", "bc_y", "mass", "c",
+            "charge", "bz", "pot_kind", "pot_z", "pot_a", "v_table", "pulse_kind", "pulse_e",
+            "a0", "omega", "t_pulse", "coef")
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.POINTER(_Params)
+        D = ctypes.POINTER(ctypes.c_double)
+        lib.orc_apply_h.argtypes = [P, D, D, D]
+        lib.orc_pulse.argtypes = [P, ctypes.c_double, D]
+        lib.orc_field_average.argtypes = [P, ctypes.c_double, ctypes.c_double, D]
+        lib.orc_lanczos.argtypes = [P, D, ctypes.c_double, D, ctypes.c_int, ctypes.c_int, D, D, D]
+        lib.orc_lanczos.restype = ctypes.c_int
+        lib.orc_tridiag_eig.argtypes = [ctypes.c_int, D, D, D, D]
+        lib.orc_expm_e1.argtypes = [ctypes.c_int, D, D, ctypes.c_double, D]
+        lib.orc_propagate.argtypes = [P, D, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                      ctypes.c_int, ctypes.POINTER(_Stat)]
+        lib.orc_propagate.restype = ctypes.c_int
+        lib.orc_eigen.argtypes = [P, D, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_double, ctypes.c_int, D, D,
+                                  ctypes.POINTER(ctypes.c_int)]
+        lib.orc_eigen.restype = ctypes.c_int
+        lib.orc_pauli.argtypes = [ctypes.c_int, D]
+        _lib = lib
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class _Problem:
+    """Keeps the ctypes struct and the arrays it points to alive together."""
+
+    def __init__(self, prob: dict):
+        self.p = _Params()
+        self.keep = []
+        for k in ("nx", "ny", "bc_x", "bc_y", "pot_kind", "pulse_kind"):
+            setattr(self.p, k, int(prob.get(k, 0)))
+        defaults = {"mass": 1.0, "c": 137.036, "charge": -1.0}
+        for k in ("x_min", "x_max", "y_min", "y_max", "mass", "c", "charge", "bz", "pot_z",
+                  "pot_a", "a0", "omega", "t_pulse"):
+            setattr(self.p, k, float(prob.get(k, defaults.get(k, 0.0))))
+        e = prob.get("pulse_e", (0.0, 0.0))
+        self.p.pulse_e[0], self.p.pulse_e[1] = float(e[0]), float(e[1])
+        vt = prob.get("v_table")
+        if vt is not None:
+            vt = np.ascontiguousarray(vt, dtype=np.float64)
+            assert vt.shape == (self.p.ny, self.p.nx)
+            self.keep.append(vt)
+            self.p.v_table = vt.ctypes.data
+        coef = prob.get("coef")
+        if coef is not None and len(coef) > 0:
+            coef = np.ascontiguousarray(coef, dtype=np.float64)
+            self.keep.append(coef)
+            self.p.coef = coef.ctypes.data
+            self.p.n_coef = len(coef)
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.p)
+
+
+def _check_psi(prob, psi):
+    psi = np.ascontiguousarray(psi, dtype=np.complex128)
+    assert psi.shape == (2, int(prob["ny"]), int(prob["nx"])), psi.shape
+    return psi
+
+
+def apply_h(prob: dict, psi: np.ndarray, a_hom=(0.0, 0.0)) -> np.ndarray:
+    """H psi with homogeneous extra vector potential ``a_hom`` (Sec. 3 Hamiltonian)."""
+    lib = _load()
+    pb = _Problem(prob)
+    psi = _check_psi(prob, psi)
+    out = np.empty_like(psi)
+    a = np.array(a_hom, dtype=np.float64)
+    lib.orc_apply_h(pb.ref, _dp(a), _dp(psi.view(np.float64)), _dp(out.view(np.float64)))
+    return out
+
+
+def pulse(prob: dict, t: float) -> np.ndarray:
+    lib = _load()
+    pb = _Problem(prob)
+    a = np.zeros(2)
+    lib.orc_pulse(pb.ref, float(t), _dp(a))
+    return a
+
+
+def field_average(prob: dict, t0: float, dt: float) -> np.ndarray:
+    lib = _load()
+    pb = _Problem(prob)
+    a = np.zeros(2)
+    lib.orc_field_average(pb.ref, float(t0), float(dt), _dp(a))
+    return a
+
+
+def lanczos(prob: dict, psi: np.ndarray, k: int, dt: float = 1.0, a_hom=(0.0, 0.0),
+            reorth: bool = False):
+    """Fig. 1 on A = dt*H.  Returns (k_eff, Q[k_eff], alpha[k_eff], beta[k_eff])."""
+    lib = _load()
+    pb = _Problem(prob)
+    psi = _check_psi(prob, psi)
+    Q = np.zeros((k,) + psi.shape, dtype=np.complex128)
+    al = np.zeros(k)
+    be = np.zeros(k)
+    a = np.array(a_hom, dtype=np.float64)
+    keff = lib.orc_lanczos(pb.ref, _dp(a), float(dt), _dp(psi.view(np.float64)), int(k),
+                           int(bool(reorth)), _dp(Q.view(np.float64)), _dp(al), _dp(be))
+    return keff, Q[:keff], al[:keff], be[:keff]
+
+
+def tridiag_eig(alpha, beta):
+    lib = _load()
+    al = np.ascontiguousarray(alpha, dtype=np.float64)
+    k = len(al)
+    be = np.zeros(max(k, 1))
+    be[:len(beta)] = beta
+    ev = np.zeros(k)
+    V = np.zeros((k, k))
+    lib.orc_tridiag_eig(k, _dp(al), _dp(be), _dp(ev), _dp(V))
+    return ev, V
+
+
+def expm_e1(alpha, beta, nrm: float = 1.0) -> np.ndarray:
+    lib = _load()
+    al = np.ascontiguousarray(alpha, dtype=np.float64)
+    k = len(al)
+    be = np.zeros(max(k, 1))
+    be[:len(beta)] = beta
+    out = np.zeros(k, dtype=np.complex128)
+    lib.orc_expm_e1(k, _dp(al), _dp(be), float(nrm), _dp(out.view(np.float64)))
+    return out
+
+
+def propagate(prob: dict, psi: np.ndarray, t0: float, dt: float, n_steps: int, m: int):
+    """n_steps Lanczos short-time steps.  Returns (psi_new, stats dict of arrays)."""
+    lib = _load()
+    pb = _Problem(prob)
+    psi = _check_psi(prob, psi).copy()
+    st = (_Stat * max(n_steps, 1))()
+    lib.orc_propagate(pb.ref, _dp(psi.view(np.float64)), float(t0), float(dt), int(n_steps),
+                      int(m), st)
+    stats = {
+        "k_eff": np.array([s.k_eff for s in st[:n_steps]], dtype=np.int32),
+        "err_est": np.array([s.err_est for s in st[:n_steps]]),
+        "cum_bound": np.array([s.cum_bound for s in st[:n_steps]]),
+        "norm2": np.array([s.norm2 for s in st[:n_steps]]),
+    }
+    return psi, stats
+
+
+def eigen(prob: dict, psi0: np.ndarray, k: int, e_lo: float, e_hi: float, tol: float,
+          reorth: bool = False, max_out: int = 64):
+    """Ritz values of H in [e_lo, e_hi] converged to ``tol`` after k Lanczos steps."""
+    lib = _load()
+    pb = _Problem(prob)
+    psi0 = _check_psi(prob, psi0)
+    ev = np.zeros(max_out)
+    bd = np.zeros(max_out)
+    nf = ctypes.c_int(0)
+    keff = lib.orc_eigen(pb.ref, _dp(psi0.view(np.float64)), int(k), int(bool(reorth)),
+                         float(e_lo), float(e_hi), float(tol), int(max_out), _dp(ev), _dp(bd),
+                         ctypes.byref(nf))
+    return ev[:nf.value].copy(), bd[:nf.value].copy(), keff
+
+
+def pauli(which: int) -> np.ndarray:
+    lib = _load()
+    out = np.zeros(8)
+    lib.orc_pauli(int(which), _dp(out))
+    return out.view(np.complex128).reshape(2, 2)

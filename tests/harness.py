@@ -1,0 +1,147 @@
+"""Independent numpy/scipy checks for the oracle (third code base).
+
+Nothing here is shared with the oracle or with the GPU library: the dense
+Hamiltonian is assembled from Kronecker products of 1-D difference matrices
+and the Pauli matrices typed in here, the free lattice propagator is applied
+mode by mode after an FFT, and the Landau levels are the textbook closed form.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.integrate
+import scipy.sparse as sp
+
+SX = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+SY = np.array([[0, -1j], [1j, 0]], dtype=np.complex128)
+SZ = np.array([[1, 0], [0, -1]], dtype=np.complex128)
+ID2 = np.eye(2, dtype=np.complex128)
+
+
+def axes(prob):
+    hx = (prob["x_max"] - prob["x_min"]) / prob["nx"]
+    hy = (prob["y_max"] - prob["y_min"]) / prob["ny"]
+    return (prob["x_min"] + hx * np.arange(prob["nx"]), prob["y_min"] + hy * np.arange(prob["ny"]),
+            hx, hy)
+
+
+def diff_1d(n, h, periodic):
+    """Central first-derivative matrix (f[i+1]-f[i-1])/(2h)."""
+    d = sp.lil_matrix((n, n), dtype=np.complex128)
+    for i in range(n):
+        for off, sgn in ((1, 1.0), (-1, -1.0)):
+            j = i + off
+            if 0 <= j < n:
+                d[i, j] += sgn / (2 * h)
+            elif periodic:
+                d[i, j % n] += sgn / (2 * h)
+    return d.tocsr()
+
+
+def potential_grid(prob):
+    x, y, _, _ = axes(prob)
+    X, Y = np.meshgrid(x, y)
+    r2 = X * X + Y * Y
+    v = np.zeros_like(X)
+    if prob.get("pot_kind", 0) == 1:
+        v = -prob["pot_z"] / np.sqrt(r2 + prob["pot_a"] ** 2)
+    elif prob.get("pot_kind", 0) == 2:
+        z = prob["pot_z"]
+        v = -1.5 * z / np.sqrt(r2 + 3.0 / (z * z))
+    if prob.get("v_table") is not None:
+        v = v + np.asarray(prob["v_table"])
+    return v
+
+
+def dense_h(prob, a_hom=(0.0, 0.0)):
+    """Sparse matrix of H on the flattened (2, ny, nx) spinor."""
+    nx, ny = prob["nx"], prob["ny"]
+    x, y, hx, hy = axes(prob)
+    q, c, m = prob.get("charge", -1.0), prob.get("c", 137.036), prob.get("mass", 1.0)
+    bz = prob.get("bz", 0.0)
+    Dx = sp.kron(sp.identity(ny), diff_1d(nx, hx, prob["bc_x"]))
+    Dy = sp.kron(diff_1d(ny, hy, prob["bc_y"]), sp.identity(nx))
+    X = sp.diags(np.tile(x, ny))
+    Y = sp.diags(np.repeat(y, nx))
+    Ieye = sp.identity(nx * ny)
+    Ax = -0.5 * bz * Y + a_hom[0] * Ieye
+    Ay = 0.5 * bz * X + a_hom[1] * Ieye
+    PIx = -1j * Dx - q * Ax
+    PIy = -1j * Dy - q * Ay
+    V = sp.diags(potential_grid(prob).ravel())
+    H = (c * (sp.kron(SX, PIx) + sp.kron(SY, PIy)) + m * c * c * sp.kron(SZ, Ieye)
+         + sp.kron(ID2, V))
+    return H.tocsr()
+
+
+def pulse_value(prob, t):
+    """A_L(t) typed in from the workload definitions."""
+    T = prob["t_pulse"]
+    if prob.get("pulse_kind", 0) == 0 or t < 0 or t > T:
+        return np.zeros(2)
+    env2 = math.sin(math.pi * t / T) ** 2
+    if prob["pulse_kind"] == 1:
+        f = prob["a0"] * math.sin(prob["omega"] * t) * env2
+        return f * np.asarray(prob["pulse_e"], dtype=float)
+    w0 = 2 * math.pi / T
+    cf = np.asarray(prob["coef"], dtype=float).reshape(-1, 4)
+    ax = sum(cf[k, 0] * math.sin((k + 1) * w0 * t) + cf[k, 1] * math.cos((k + 1) * w0 * t)
+             for k in range(len(cf)))
+    ay = sum(cf[k, 2] * math.sin((k + 1) * w0 * t) + cf[k, 3] * math.cos((k + 1) * w0 * t)
+             for k in range(len(cf)))
+    return env2 * np.array([ax, ay])
+
+
+def pulse_average_quad(prob, t0, dt):
+    """(1/dt) integral over [t0, t0+dt] of A_L by adaptive quadrature."""
+    if prob.get("pulse_kind", 0) == 0:
+        return np.zeros(2)
+    lo, hi = min(t0, t0 + dt), max(t0, t0 + dt)
+    out = np.zeros(2)
+    for comp in range(2):
+        val, _ = scipy.integrate.quad(lambda t: pulse_value(prob, t)[comp], lo, hi,
+                                      epsabs=1e-15, epsrel=1e-14, limit=200,
+                                      points=[prob["t_pulse"]] if lo < prob["t_pulse"] < hi else None)
+        out[comp] = val / abs(dt)
+    return out
+
+
+def lattice_energy(prob, kx, ky, a_hom=(0.0, 0.0)):
+    """Closed form: plane-wave eigenvalues +-sqrt(m^2c^4 + c^2 |sin(kh)/h - qA|^2)."""
+    _, _, hx, hy = axes(prob)
+    q, c, m = prob.get("charge", -1.0), prob.get("c", 137.036), prob.get("mass", 1.0)
+    px = math.sin(kx * hx) / hx - q * a_hom[0]
+    py = math.sin(ky * hy) / hy - q * a_hom[1]
+    e = math.sqrt((m * c * c) ** 2 + c * c * (px * px + py * py))
+    return e, px, py
+
+
+def free_propagate_fft(prob, psi, t):
+    """Exact solution of the free periodic lattice problem: each DFT mode evolves
+    with exp(-i H0(k) t) = cos(Et) - i sin(Et) H0/E."""
+    _, _, hx, hy = axes(prob)
+    c, m = prob.get("c", 137.036), prob.get("mass", 1.0)
+    kx = np.sin(2 * np.pi * np.fft.fftfreq(prob["nx"])) / hx
+    ky = np.sin(2 * np.pi * np.fft.fftfreq(prob["ny"])) / hy
+    KX, KY = np.meshgrid(kx, ky)
+    mc2 = m * c * c
+    E = np.sqrt(mc2 ** 2 + c * c * (KX ** 2 + KY ** 2))
+    f0, f1 = np.fft.fft2(psi[0]), np.fft.fft2(psi[1])
+    h0 = mc2 * f0 + c * (KX - 1j * KY) * f1
+    h1 = c * (KX + 1j * KY) * f0 - mc2 * f1
+    cs, sn = np.cos(E * t), np.sin(E * t)
+    g0 = cs * f0 - 1j * sn * h0 / E
+    g1 = cs * f1 - 1j * sn * h1 / E
+    return np.stack([np.fft.ifft2(g0), np.fft.ifft2(g1)])
+
+
+def landau_levels(prob, n_max):
+    """Relativistic Landau levels sqrt(m^2c^4 + 2 n c^2 |qB|), n = 1..n_max."""
+    c, m, q, b = prob.get("c", 137.036), prob.get("mass", 1.0), prob.get("charge", -1.0), prob["bz"]
+    return np.array([math.sqrt((m * c * c) ** 2 + 2 * n * c * c * abs(q * b))
+                     for n in range(1, n_max + 1)])
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))

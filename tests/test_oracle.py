@@ -1,0 +1,368 @@
+"""Pins of the CPU oracle against closed forms, invariants and brute force.
+
+Every check here compares the oracle with something that is not the oracle:
+a dense Hamiltonian assembled independently (tests/harness.py), the exact
+lattice dispersion, scipy's matrix exponential and quadrature, an FFT-exact
+free propagator, or textbook Landau levels.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import harness as hz
+from paper_1407_7370_amd import packets
+
+C = 137.036
+
+
+def small_prob(nx=6, ny=5, bc=0, bz=0.0, pot_kind=0, lo=-3.0, hi=3.0, v_table=None, **kw):
+    p = dict(nx=nx, ny=ny, x_min=lo, x_max=hi, y_min=lo * 0.8, y_max=hi * 1.1, bc_x=bc, bc_y=bc,
+             mass=1.0, c=C, charge=-1.0, bz=bz, pot_kind=pot_kind, pot_z=1.3, pot_a=0.7,
+             pulse_kind=0, pulse_e=(0.0, 0.0), a0=0.0, omega=0.0, t_pulse=1.0, coef=None,
+             v_table=v_table)
+    p.update(kw)
+    return p
+
+
+# ---------------------------------------------------------------------------
+# Dirac algebra (eq. dirac_matrices_conditions) on the matrices the oracle uses
+# ---------------------------------------------------------------------------
+def test_dirac_algebra(orc):
+    a1, a2, b = orc.pauli(1), orc.pauli(2), orc.pauli(3)
+    I2 = np.eye(2)
+    for m in (a1, a2, b):
+        assert np.array_equal(m @ m, I2)
+        assert np.array_equal(m.conj().T, m)
+    for a in (a1, a2):
+        assert np.array_equal(a @ b + b @ a, np.zeros((2, 2)))
+    assert np.array_equal(a1 @ a2 + a2 @ a1, np.zeros((2, 2)))
+    # and they are the 2D representation alpha1=sigma1, alpha2=sigma2, beta=sigma3
+    assert np.array_equal(a1, hz.SX) and np.array_equal(a2, hz.SY) and np.array_equal(b, hz.SZ)
+
+
+# ---------------------------------------------------------------------------
+# Stencil vs dense H assembled independently
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("bc", [0, 1])
+@pytest.mark.parametrize("shape", [(4, 4), (6, 5), (8, 7)])
+@pytest.mark.parametrize("fields", ["free", "bz", "soft1", "soft2", "table", "all"])
+def test_apply_h_vs_dense(orc, bc, shape, fields):
+    nx, ny = shape
+    rng = np.random.default_rng(nx * 100 + ny + bc)
+    kw = {}
+    if fields in ("bz", "all"):
+        kw["bz"] = 0.7
+    if fields in ("soft1", "all"):
+        kw["pot_kind"] = 1
+    if fields == "soft2":
+        kw["pot_kind"] = 2
+    if fields in ("table", "all"):
+        kw["v_table"] = rng.standard_normal((ny, nx))
+    prob = small_prob(nx, ny, bc, **kw)
+    a_hom = (0.3, -1.1) if fields == "all" else (0.0, 0.0)
+    psi = packets.random_spinor(prob, seed=7)
+    got = orc.apply_h(prob, psi, a_hom)
+    ref = (hz.dense_h(prob, a_hom) @ psi.ravel()).reshape(psi.shape)
+    assert hz.rel_l2(got, ref) <= 1e-14
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_hermiticity(orc, bc):
+    rng = np.random.default_rng(3)
+    prob = small_prob(16, 12, bc, bz=1.3, pot_kind=1, v_table=rng.standard_normal((12, 16)))
+    u = packets.random_spinor(prob, 1)
+    v = packets.random_spinor(prob, 2)
+    a = (0.4, 2.0)
+    lhs = np.vdot(u, orc.apply_h(prob, v, a))
+    rhs = np.vdot(orc.apply_h(prob, u, a), v)
+    hn = np.linalg.norm(orc.apply_h(prob, u, a)) / np.linalg.norm(u)
+    assert abs(lhs - rhs) <= 1e-14 * hn * np.linalg.norm(u) * np.linalg.norm(v)
+
+
+# ---------------------------------------------------------------------------
+# Closed form: plane waves on the periodic lattice
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("mass", [1.0, 0.0])
+@pytest.mark.parametrize("a_hom", [(0.0, 0.0), (0.8, -2.5)])
+@pytest.mark.parametrize("mode", [(1, 0), (3, 5), (7, 2), (15, 11)])
+def test_plane_wave_dispersion(orc, mass, a_hom, mode):
+    prob = small_prob(16, 12, 1, mass=mass, lo=-4.0, hi=4.0)
+    x, y, hx, hy = hz.axes(prob)
+    Lx, Ly = prob["x_max"] - prob["x_min"], prob["y_max"] - prob["y_min"]
+    kx, ky = 2 * math.pi * mode[0] / Lx, 2 * math.pi * mode[1] / Ly
+    e, px, py = hz.lattice_energy(prob, kx, ky, a_hom)
+    h0 = C * (px * hz.SX + py * hz.SY) + mass * C * C * hz.SZ
+    w, vec = np.linalg.eigh(h0)
+    X, Y = np.meshgrid(x, y)
+    wave = np.exp(1j * (kx * X + ky * Y))
+    for sgn, col in ((-1, 0), (1, 1)):
+        assert abs(w[col] - sgn * e) <= 1e-12 * e
+        psi = np.stack([vec[0, col] * wave, vec[1, col] * wave])
+        got = orc.apply_h(prob, psi, a_hom)
+        assert hz.rel_l2(got, sgn * e * psi) <= 1e-13
+
+
+# ---------------------------------------------------------------------------
+# Field step averages (first Magnus term)
+# ---------------------------------------------------------------------------
+def test_pulse_and_average(orc):
+    cfgs = [packets.laser_4096(), packets.fourier_pulse_512()]
+    for cfg in cfgs:
+        prob = cfg["problem"]
+        for t in (0.0, 0.0123, 0.05, 0.0999, 0.7, 1.99, 2.5):
+            assert np.allclose(orc.pulse(prob, t), hz.pulse_value(prob, t), rtol=1e-13, atol=1e-12)
+        dt = cfg["dt"]
+        for t0 in (0.0, 0.031, 0.0998, 1.2345, prob["t_pulse"] - 0.5 * dt):
+            for d in (dt, -dt):
+                got = orc.field_average(prob, t0, d)
+                ref = hz.pulse_average_quad(prob, t0, d)
+                assert np.allclose(got, ref, rtol=1e-11, atol=1e-11), (t0, d, got, ref)
+
+
+# ---------------------------------------------------------------------------
+# Small dense pieces
+# ---------------------------------------------------------------------------
+def _tridiag(alpha, beta):
+    return np.diag(alpha) + np.diag(beta[:len(alpha) - 1], 1) + np.diag(beta[:len(alpha) - 1], -1)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 8, 20, 40])
+def test_tridiag_eig(orc, k):
+    rng = np.random.default_rng(k)
+    al, be = rng.standard_normal(k) * 3, rng.random(k)
+    ev, V = orc.tridiag_eig(al, be)
+    T = _tridiag(al, be)
+    assert np.allclose(np.sort(ev), np.linalg.eigvalsh(T), atol=1e-13 * max(1, np.abs(T).max()))
+    assert np.allclose(V.T @ V, np.eye(k), atol=1e-13)
+    assert np.allclose(T @ V, V * ev, atol=1e-12)
+
+
+@pytest.mark.parametrize("k", [1, 2, 5, 12, 30])
+def test_expm_e1(orc, k):
+    rng = np.random.default_rng(10 + k)
+    al, be = rng.standard_normal(k) * 4 + 9, rng.random(k) * 0.5
+    got = orc.expm_e1(al, be, 2.5)
+    ref = 2.5 * scipy.linalg.expm(-1j * _tridiag(al, be))[:, 0]
+    assert np.allclose(got, ref, atol=1e-13)
+
+
+def test_expm_closed_forms(orc):
+    # 1x1: exp(-i alpha)
+    assert abs(orc.expm_e1([0.7], [])[0] - np.exp(-0.7j)) < 1e-15
+    # 2x2 with beta = 0: diagonal phases, second entry exactly zero
+    c = orc.expm_e1([0.3, -1.2], [0.0])
+    assert abs(c[0] - np.exp(-0.3j)) < 1e-15 and c[1] == 0
+    # 2x2 closed form: exp(-i(a I + b sx)) e1 = e^{-ia}(cos b, -i sin b)
+    a, b = 1.7, 0.45
+    c = orc.expm_e1([a, a], [b])
+    assert np.allclose(c, np.exp(-1j * a) * np.array([np.cos(b), -1j * np.sin(b)]), atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Lanczos relation eq. Lanczos_relation and orthogonality
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("k", [3, 10, 20])
+def test_lanczos_relation(orc, k):
+    rng = np.random.default_rng(5)
+    prob = small_prob(12, 10, 0, bz=0.5, pot_kind=1, v_table=rng.standard_normal((10, 12)))
+    dt = 2e-4
+    psi = packets.random_spinor(prob, 11)
+    keff, Q, al, be = orc.lanczos(prob, psi, k, dt=dt)
+    assert keff == k
+    A = dt * hz.dense_h(prob)
+    Qm = Q.reshape(k, -1).T
+    T = _tridiag(al, be)
+    R = A @ Qm - Qm @ T
+    anorm = scipy.sparse.linalg.norm(A, 1)
+    assert np.linalg.norm(R[:, :-1]) <= 1e-13 * anorm
+    assert abs(np.linalg.norm(R[:, -1]) - be[-1]) <= 1e-12 * anorm
+    # Paige: local orthogonality is lost at the rate eps ||A|| / beta_i
+    tol = 1e-14 * k * anorm / be[:-1].min()
+    assert np.linalg.norm(Qm.conj().T @ Qm - np.eye(k)) <= tol
+    assert np.allclose(Qm[:, 0], psi.ravel() / np.linalg.norm(psi))
+
+
+def test_lanczos_breakdown_and_zero(orc):
+    # fine grid so that c k_eff ~ m c^2 (no large cancellation in the first residual)
+    prob = small_prob(8, 8, 1, lo=-0.04, hi=0.04)
+    # plane wave with spinor (1, 0): combination of the +-E eigenvectors -> k_eff = 2
+    x, y, hx, hy = hz.axes(prob)
+    X, Y = np.meshgrid(x, y)
+    kx = 2 * math.pi * 2 / 0.08
+    psi = np.stack([np.exp(1j * kx * X), np.zeros_like(X, dtype=complex)])
+    keff, _, al, be = orc.lanczos(prob, psi, 10, dt=1e-3)
+    assert keff == 2
+    # c = 0: H = m c^2 sigma3 is diagonal, an upper-component state is an eigenvector
+    prob0 = dict(prob, c=1e-300)
+    keff, _, al, _ = orc.lanczos(prob0, psi, 6, dt=1e-3)
+    assert keff == 1
+    # zero state
+    keff, _, _, _ = orc.lanczos(prob, np.zeros_like(psi), 6, dt=1e-3)
+    assert keff == 0
+    out, st = orc.propagate(prob, np.zeros_like(psi), 0.0, 1e-3, 3, 6)
+    assert np.all(out == 0) and np.all(st["k_eff"] == 0)
+
+
+# ---------------------------------------------------------------------------
+# Propagator vs exact exponential
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("case", ["periodic_free", "dirichlet_b_v", "pulse"])
+def test_propagate_vs_dense_expm(orc, case):
+    if case == "periodic_free":
+        prob = small_prob(6, 6, 1)
+    elif case == "dirichlet_b_v":
+        prob = small_prob(8, 8, 0, bz=0.9, pot_kind=1)
+    else:
+        cfg = packets.laser_4096()
+        prob = dict(cfg["problem"], nx=8, ny=6, x_min=-2.0, x_max=2.0, y_min=-1.5, y_max=1.5,
+                    a0=400.0, t_pulse=0.004)
+    H = hz.dense_h(prob).toarray()
+    hn = np.abs(np.linalg.eigvalsh(H)).max()
+    dt = 1.5 / hn  # ||A|| ~ 1.5
+    psi0 = packets.random_spinor(prob, 4)
+    psi0 /= np.linalg.norm(psi0)
+    n = 5
+    m = 30
+    got, st = orc.propagate(prob, psi0, 0.0, dt, n, m)
+    ref = psi0.ravel()
+    for s in range(n):
+        a = hz.pulse_average_quad(prob, s * dt, dt)
+        Hs = hz.dense_h(prob, a).toarray()
+        w, v = np.linalg.eigh(Hs)
+        ref = v @ (np.exp(-1j * dt * w) * (v.conj().T @ ref))
+    assert hz.rel_l2(got.ravel(), ref) <= 1e-12
+    assert np.all(st["err_est"] <= 1e-12)
+
+
+def test_free_packet_fft_exact(orc):
+    cfg = packets.free_packet_64(seed=0)
+    prob = cfg["problem"]
+    psi0 = packets.initial_state(cfg)
+    n = 100
+    got, st = orc.propagate(prob, psi0, 0.0, cfg["dt"], n, cfg["m"])
+    ref = hz.free_propagate_fft(prob, psi0, n * cfg["dt"])
+    # Rounding only: the step phase exp(-i alpha_1) carries |alpha_1| eps with
+    # |alpha_1| = m c^2 dt ~ 18.8, accumulated linearly over the steps
+    # (measured 1.8e-14 after one step, 2.9e-12 after 100).
+    assert hz.rel_l2(got, ref) <= 1e-11
+    # norm conservation (never renormalised)
+    n0 = float(np.sum(np.abs(psi0) ** 2))
+    assert np.max(np.abs(st["norm2"] / n0 - 1.0)) <= 1e-12
+    assert np.all(st["k_eff"] == cfg["m"])
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_free_packet_fft_exact_seeds(orc, seed):
+    cfg = packets.free_packet_64(seed=seed)
+    prob = cfg["problem"]
+    psi0 = packets.initial_state(cfg)
+    got, _ = orc.propagate(prob, psi0, 0.0, cfg["dt"], 20, cfg["m"])
+    ref = hz.free_propagate_fft(prob, psi0, 20 * cfg["dt"])
+    assert hz.rel_l2(got, ref) <= 2e-12
+
+
+def test_time_reversal(orc):
+    cfg = packets.laser_4096()
+    prob = dict(cfg["problem"], nx=48, ny=40, t_pulse=0.02, a0=200.0)
+    psi0 = packets.gaussian_packet(prob, 3.0, (4.0, -3.0))
+    n, dt = 60, 2e-4
+    fw, _ = orc.propagate(prob, psi0, 0.0, dt, n, 16)
+    bw, _ = orc.propagate(prob, fw, n * dt, -dt, n, 16)
+    assert hz.rel_l2(bw, psi0) <= 1e-11
+    assert hz.rel_l2(fw, psi0) > 1e-3  # it did move
+
+
+def test_error_estimate_overestimates(orc):
+    """eq. matrix_exponential_error tends to overestimate the Krylov error."""
+    # massless and random: a wide spectrum, so small m leaves a visible Krylov error
+    prob = small_prob(8, 8, 1, lo=-2.0, hi=2.0, mass=0.0)
+    H = hz.dense_h(prob).toarray()
+    w, v = np.linalg.eigh(H)
+    psi = packets.random_spinor(prob, 9)
+    psi /= np.linalg.norm(psi)
+    for m, dt in ((4, 1.0 / np.abs(w).max()), (6, 1.5 / np.abs(w).max()),
+                  (8, 2.0 / np.abs(w).max())):
+        got, st = orc.propagate(prob, psi, 0.0, dt, 1, m)
+        ref = v @ (np.exp(-1j * dt * w) * (v.conj().T @ psi.ravel()))
+        actual = np.linalg.norm(got.ravel() - ref)
+        assert actual > 1e-13  # Krylov error dominates rounding here
+        assert actual <= st["err_est"][0]
+
+
+def test_positive_energy_projection():
+    cfg = packets.free_packet_64(seed=3)
+    prob = cfg["problem"]
+    psi = packets.initial_state(cfg)
+    H = hz.dense_h(prob)
+    e = np.vdot(psi.ravel(), H @ psi.ravel()).real / np.vdot(psi.ravel(), psi.ravel()).real
+    assert e > prob["c"] ** 2  # positive branch
+    # exactly positive energy: evolving with exp(-iHt) = FFT phases only
+    x, y, hx, hy = hz.axes(prob)
+    assert abs(hx * hy * np.sum(np.abs(psi) ** 2) - 1.0) < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# Eigenvalue mode: relativistic Landau levels
+# ---------------------------------------------------------------------------
+def _landau_prob(n, bz=2.0):
+    return dict(nx=n, ny=n, x_min=-5.0, x_max=5.0, y_min=-5.0, y_max=5.0, bc_x=0, bc_y=0,
+                mass=1.0, c=C, charge=-1.0, bz=bz, pot_kind=0, pot_z=0.0, pot_a=0.0,
+                pulse_kind=0, pulse_e=(0.0, 0.0), a0=0.0, omega=0.0, t_pulse=1.0, coef=None)
+
+
+# The Ritz bound |beta_k t_i^k| has an FP64 floor near beta_k eps ||T|| / gap; with
+# beta ~ 1e3 and ||T|| ~ m c^2 it sits near 1e-7, so 1e-5 a.u. (5e-10 relative to
+# the energy) is the convergence tolerance used for the Landau checks.
+LANDAU_TOL = 1e-5
+
+
+def test_landau_level_richardson(orc):
+    """First relativistic Landau level sqrt(m^2c^4 + 2c^2|qB|): the FD error is O(h^2)
+    and Richardson extrapolation over h and h/2 removes it."""
+    mc2 = C * C
+    res = {}
+    for n in (64, 128):
+        prob = _landau_prob(n)
+        psi0 = packets.gaussian_packet(prob, 0.9, (0.0, 0.0), project=True)
+        ev, bd, keff = orc.eigen(prob, psi0, 200, mc2 - 0.5, mc2 + 9.0, LANDAU_TOL)
+        assert keff == 200 and len(ev) >= 1
+        res[n] = ev
+    lvl = hz.landau_levels(_landau_prob(64), 1)[0]
+    coarse = res[64][np.argmin(np.abs(res[64] - lvl))]
+    fine = res[128][np.argmin(np.abs(res[128] - lvl))]
+    rich = (4 * fine - coarse) / 3
+    assert abs(coarse - lvl) < 0.01 * (lvl - mc2)
+    assert abs(fine - lvl) < 0.25 * abs(coarse - lvl) * 1.1  # second order in h
+    assert abs(rich - lvl) <= 1e-4 * (lvl - mc2), (coarse - mc2, fine - mc2, rich - mc2)
+    # nothing converged strictly inside the gap (m c^2 - 0.5, first level) besides
+    # values of the discrete levels
+    for e in res[128]:
+        assert e > mc2 + 1.0
+
+
+@pytest.mark.parametrize("bz", [2.0, -2.0])
+def test_landau_zero_mode_sign(orc, bz):
+    """The n = 0 level sits at sgn(qB) m c^2 (q = -1): pins the sign of the coupling."""
+    mc2 = C * C
+    prob = _landau_prob(64, bz)
+    psi0 = packets.gaussian_packet(prob, 0.9, (0.0, 0.0), project=False)
+    psi0[1] = psi0[0]
+    sgn = np.sign(prob["charge"] * bz)
+    ev, _, _ = orc.eigen(prob, psi0, 200, sgn * mc2 - 1.0, sgn * mc2 + 1.0, LANDAU_TOL)
+    assert len(ev) == 1 and abs(ev[0] - sgn * mc2) < 1e-6
+    ev, _, _ = orc.eigen(prob, psi0, 200, -sgn * mc2 - 1.0, -sgn * mc2 + 1.0, LANDAU_TOL)
+    assert len(ev) == 0
+
+
+def test_eigen_small_dense(orc):
+    """Ritz values with full reorthogonalisation reproduce dense eigenvalues."""
+    prob = small_prob(8, 8, 0, bz=1.0, pot_kind=1, lo=-4, hi=4)
+    H = hz.dense_h(prob).toarray()
+    w = np.linalg.eigvalsh(H)
+    psi0 = packets.random_spinor(prob, 2)
+    ev, bd, keff = orc.eigen(prob, psi0, 128, -1e9, 1e9, 1e-6, reorth=True, max_out=256)
+    assert keff == 128
+    assert len(ev) == 128
+    assert np.allclose(ev, w, atol=1e-8 * np.abs(w).max())
