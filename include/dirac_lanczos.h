@@ -1,0 +1,188 @@
+/*
+ * dirac_lanczos.h -- C ABI of the MI355X (gfx950) Lanczos short-time propagator
+ * for the two-dimensional Dirac equation.
+ *
+ * Method: Beerwerth & Bauke, "Krylov subspace methods for the Dirac equation",
+ * arXiv:1407.7370.  One time step is psi <- exp(-i A) psi with
+ * A = dt * H(t_bar) (Sec. 3, eq. time_evolution_approx, first Magnus term),
+ * approximated in an m-dimensional Krylov space built by the Lanczos recurrence
+ * (Sec. 2, Fig. 1) as ||psi|| Q exp(-i T) e_1 (Sec. 4, eq. matrix_exp_approx).
+ *
+ * Hamiltonian (Sec. 3, 2D representation alpha1 = sigma1, alpha2 = sigma2,
+ * beta = sigma3):
+ *     H = c [sigma1 (p_x - q A_x) + sigma2 (p_y - q A_y)] + m c^2 sigma3 + V
+ * with p = -i d/dx realised by central first-derivative differences
+ * (f[i+1] - f[i-1]) / (2h) (Sec. 7 "first order finite differences"),
+ * A = (B/2)(-y, x) + A_L(t) (uniform B_z in the symmetric gauge plus a
+ * homogeneous laser field), and V the potential energy q*phi.
+ *
+ * Conventions shared by every call:
+ *   - Grid: x_i = x_min + i*h_x, h_x = (x_max - x_min)/nx, i = 0..nx-1; same
+ *     for y.  bc = 0 (Dirichlet): psi = 0 outside the grid; bc = 1: periodic.
+ *   - Spinor layout: device array of 2*ny*nx complex128 values (interleaved
+ *     re, im doubles), index ((s*ny + j)*nx + i) for component s, row j,
+ *     column i -- i.e. a contiguous (2, ny, nx) complex128 tensor.
+ *   - Inner product <u,v> = sum over sites and components of conj(u) v;
+ *     alpha = Re <q, z>; the norm is Euclidean (no h^2 weight).
+ *   - Atomic units: m = 1, c = 137.036, q = -1 for an electron.
+ *
+ * Ownership: the caller owns every device buffer (psi, the workspace, an
+ * optional potential table) and the HIP stream.  The library owns only the
+ * opaque host context; it never allocates or frees device memory.
+ *
+ * Errors: every call returns a dl_status; nothing is thrown across the ABI.
+ * dirac_lanczos_last_error() returns a message for the last failing call on a
+ * context.  Krylov breakdown (an invariant subspace) is not an error.
+ */
+#ifndef DIRAC_LANCZOS_H
+#define DIRAC_LANCZOS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dl_context dl_context;
+
+typedef enum {
+    DL_OK = 0,
+    DL_ERR_INVALID = 1,     /* invalid parameters or arguments */
+    DL_ERR_DEVICE = 2,      /* HIP runtime error (message in last_error) */
+    DL_ERR_NONFINITE = 3,   /* a Lanczos reduction became NaN/Inf */
+    DL_ERR_WORKSPACE = 4,   /* workspace missing, too small or misaligned */
+    DL_ERR_UNSUPPORTED = 5  /* valid request that this build does not provide */
+} dl_status;
+
+enum { DL_BC_DIRICHLET = 0, DL_BC_PERIODIC = 1 };
+enum { DL_PREC_FP64 = 0, DL_PREC_MIXED = 1 };
+enum { DL_POT_NONE = 0, DL_POT_SOFTCORE = 1, DL_POT_PAPER_SOFTCORE = 2 };
+enum { DL_PULSE_NONE = 0, DL_PULSE_SIN_SIN2 = 1, DL_PULSE_FOURIER_SIN2 = 2 };
+enum { DL_MODE_STEP = 0, DL_MODE_EIGEN = 1 };
+
+/*
+ * Problem description (Sec. 3 Hamiltonian, Sec. 7 grid).
+ *   nx, ny >= 3; x_min < x_max; y_min < y_max.
+ *   krylov_dim: m, 1..64 (Lanczos iterations per step, Fig. 1's k).
+ *   precision: DL_PREC_FP64 -- every vector and every operation in double;
+ *              DL_PREC_MIXED -- Krylov vectors 2..m stored as complex64, all
+ *              arithmetic, the state psi, reductions, T, exp(-iT) and the
+ *              recombination coefficients in double.
+ *   bz: uniform B_z, vector potential (bz/2)(-y, x) about the origin.
+ *   pot_kind: DL_POT_SOFTCORE V = -pot_z / sqrt(r^2 + pot_a^2);
+ *             DL_POT_PAPER_SOFTCORE V = -(3/2) pot_z / sqrt(r^2 + 3/pot_z^2)
+ *             (eq. soft_core_pot).
+ *   v_table: optional DEVICE pointer to ny*nx doubles (row-major [j][i])
+ *            added to V; must stay valid for the context's lifetime. NULL: none.
+ *   pulse_kind: homogeneous laser vector potential A_L(t), zero outside [0, T]:
+ *     DL_PULSE_SIN_SIN2: a0 sin(omega t) sin^2(pi t/T) (pulse_e[0], pulse_e[1]);
+ *     DL_PULSE_FOURIER_SIN2: sin^2(pi t/T) sum_{k=1}^{n_coef/4}
+ *        [(a_k^x sin k w0 t + b_k^x cos k w0 t), (a_k^y sin .. + b_k^y cos ..)]
+ *        with w0 = 2 pi / T and coef[4(k-1) + {0,1,2,3}] = {a_k^x, b_k^x,
+ *        a_k^y, b_k^y}.  coef is a HOST pointer, copied during init.
+ *   t_pulse: T > 0 when pulse_kind != 0.
+ */
+typedef struct {
+    int32_t nx, ny;
+    double x_min, x_max, y_min, y_max;
+    int32_t bc_x, bc_y;
+    double mass, c, charge;
+    int32_t krylov_dim;
+    int32_t precision;
+    double bz;
+    int32_t pot_kind;
+    double pot_z, pot_a;
+    const double *v_table;
+    int32_t pulse_kind;
+    double pulse_e[2], a0, omega, t_pulse;
+    int32_t n_coef;
+    const double *coef;
+} dl_params;
+
+/* Per-step statistics (Sec. 4 eq. matrix_exponential_error and its running
+ * sum over the steps of one call, Sec. 6). */
+typedef struct {
+    int32_t k_eff;     /* Krylov dimension used (< m after breakdown, 0 for psi = 0) */
+    double err_est;    /* beta_k ||psi|| |e_k^T exp(-iT) e_1| */
+    double cum_bound;  /* sum of err_est over the steps of this call so far */
+    double norm2;      /* ||psi||^2 after the step (never renormalised) */
+} dl_step_stat;
+
+/*
+ * Bytes of caller-provided device workspace a context needs.
+ * mode DL_MODE_STEP: for step/apply; DL_MODE_EIGEN: additionally for
+ * eigen() with up to k_eigen Lanczos iterations.  Returns 0 for invalid
+ * parameters.  The workspace must be 256-byte aligned.
+ */
+size_t dirac_lanczos_workspace_bytes(const dl_params *params, int32_t mode, int32_t k_eigen);
+
+/*
+ * Validate params, bind the workspace and stream, and create a context.
+ * workspace: DEVICE pointer, ws_bytes >= dirac_lanczos_workspace_bytes(params,
+ * mode, k) for every mode used later.  hip_stream: hipStream_t (NULL = the
+ * default stream).  On success *out receives the context.  The workspace is
+ * initialised on the stream.  Errors: DL_ERR_INVALID, DL_ERR_WORKSPACE,
+ * DL_ERR_DEVICE (no gfx950 device / HIP failure).  On error *out is NULL.
+ */
+dl_status dirac_lanczos_init(const dl_params *params, void *workspace, size_t ws_bytes,
+                             void *hip_stream, dl_context **out);
+
+/*
+ * y = H(t) x (Sec. 3 Hamiltonian, finite differences of Sec. 7) with the
+ * instantaneous laser field A_L(t).  x, y: DEVICE spinors (layout above),
+ * must not overlap.  Asynchronous on the context's stream.
+ */
+dl_status dirac_lanczos_apply(dl_context *ctx, const void *x, void *y, double t);
+
+/*
+ * n_steps short-time steps psi(t + dt) = exp(-i dt H(t_bar)) psi(t) starting at
+ * time t0 (dt may be negative: backward propagation).  Step n uses the exact
+ * average of A_L over [t0 + n dt, t0 + (n+1) dt] (first Magnus term).  Each step
+ * runs the m-step Lanczos recurrence of Fig. 1 (in an algebraically equal,
+ * single-sweep-per-iteration order), exp(-iT) by an eigendecomposition of T,
+ * and recombines the Krylov basis (eq. matrix_exp_approx).  psi (DEVICE) is
+ * updated in place and never renormalised.  stats: HOST array of n_steps
+ * entries, or NULL.
+ * The call returns after the stream has finished the work.  On
+ * DL_ERR_NONFINITE psi holds the state after the last completed step and the
+ * stats of the completed steps are filled (later entries have k_eff = -1).
+ */
+dl_status dirac_lanczos_step(dl_context *ctx, void *psi, double t0, double dt, int32_t n_steps,
+                             dl_step_stat *stats);
+
+/*
+ * Eigenvalue mode (Sec. 2 eq. A_approx, eq. error_est; Sec. 5): k_max plain
+ * Lanczos iterations on H (static fields, laser off) from psi0 (DEVICE).
+ * Ritz values of T in [e_lo, e_hi] are grouped into clusters of neighbours
+ * closer than tol; a cluster whose bound beta_k ||last components of its
+ * eigenvectors|| is <= tol is reported as its mean.  Up to n_wanted values go
+ * to evals/bounds (HOST arrays of n_wanted doubles), ascending; *n_found
+ * receives the count.  reorth != 0 (full reorthogonalisation) returns
+ * DL_ERR_UNSUPPORTED.  Needs a workspace sized for DL_MODE_EIGEN with
+ * k_eigen >= k_max.  Synchronous.
+ */
+dl_status dirac_lanczos_eigen(dl_context *ctx, const void *psi0, int32_t k_max, int32_t reorth,
+                              double e_lo, double e_hi, double tol, int32_t n_wanted,
+                              double *evals, double *bounds, int32_t *n_found);
+
+/*
+ * Gradient of a final observable with respect to the laser coefficients
+ * (forward run with checkpoints every ckpt_every steps, backward propagation
+ * with exp(+i A)).  Not provided by this build: returns DL_ERR_UNSUPPORTED.
+ */
+dl_status dirac_lanczos_adjoint(dl_context *ctx, const void *psi0, double t0, double dt,
+                                int32_t n_steps, int32_t ckpt_every, int32_t loss_kind,
+                                double *loss, double *grad);
+
+/* Free the host context (the caller frees its own device buffers). */
+dl_status dirac_lanczos_destroy(dl_context *ctx);
+
+/* Message of the last failing call on ctx (never NULL; "" if none). */
+const char *dirac_lanczos_last_error(const dl_context *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DIRAC_LANCZOS_H */

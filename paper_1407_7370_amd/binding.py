@@ -1,0 +1,259 @@
+"""ctypes binding of libdirac_lanczos.so (include/dirac_lanczos.h).
+
+Argument marshalling only: every step of the propagator runs in the HIP
+library.  Device memory and streams come from PyTorch (the caller's tensors,
+a uint8 workspace tensor, torch's current stream).  There is no CPU fallback:
+if the shared library or a gfx950 device is missing, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdirac_lanczos.so")
+
+DL_OK, DL_ERR_INVALID, DL_ERR_DEVICE, DL_ERR_NONFINITE, DL_ERR_WORKSPACE, DL_ERR_UNSUPPORTED = range(6)
+DL_PREC_FP64, DL_PREC_MIXED = 0, 1
+DL_MODE_STEP, DL_MODE_EIGEN = 0, 1
+STATUS_NAMES = {0: "DL_OK", 1: "DL_ERR_INVALID", 2: "DL_ERR_DEVICE", 3: "DL_ERR_NONFINITE",
+                4: "DL_ERR_WORKSPACE", 5: "DL_ERR_UNSUPPORTED"}
+
+# every symbol declared in include/dirac_lanczos.h
+EXPORTS = ("dirac_lanczos_workspace_bytes", "dirac_lanczos_init", "dirac_lanczos_apply",
+           "dirac_lanczos_step", "dirac_lanczos_eigen", "dirac_lanczos_adjoint",
+           "dirac_lanczos_destroy", "dirac_lanczos_last_error")
+
+
+class DlParams(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("x_min", ctypes.c_double), ("x_max", ctypes.c_double),
+        ("y_min", ctypes.c_double), ("y_max", ctypes.c_double),
+        ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32),
+        ("mass", ctypes.c_double), ("c", ctypes.c_double), ("charge", ctypes.c_double),
+        ("krylov_dim", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("bz", ctypes.c_double),
+        ("pot_kind", ctypes.c_int32), ("pot_z", ctypes.c_double), ("pot_a", ctypes.c_double),
+        ("v_table", ctypes.c_void_p),
+        ("pulse_kind", ctypes.c_int32),
+        ("pulse_e", ctypes.c_double * 2), ("a0", ctypes.c_double), ("omega", ctypes.c_double),
+        ("t_pulse", ctypes.c_double),
+        ("n_coef", ctypes.c_int32), ("coef", ctypes.c_void_p),
+    ]
+
+
+class DlStepStat(ctypes.Structure):
+    _fields_ = [("k_eff", ctypes.c_int32), ("err_est", ctypes.c_double),
+                ("cum_bound", ctypes.c_double), ("norm2", ctypes.c_double)]
+
+
+class DlError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library():
+    """Load the HIP library (after torch, so that both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  (loads torch's HIP runtime first)
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1407_7370_amd.build`"
+                           " (there is no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER(DlParams)
+    vp, D = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
+    lib.dirac_lanczos_workspace_bytes.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
+    lib.dirac_lanczos_workspace_bytes.restype = ctypes.c_size_t
+    lib.dirac_lanczos_init.argtypes = [P, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    lib.dirac_lanczos_init.restype = ctypes.c_int
+    lib.dirac_lanczos_apply.argtypes = [vp, vp, vp, ctypes.c_double]
+    lib.dirac_lanczos_apply.restype = ctypes.c_int
+    lib.dirac_lanczos_step.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                       ctypes.POINTER(DlStepStat)]
+    lib.dirac_lanczos_step.restype = ctypes.c_int
+    lib.dirac_lanczos_eigen.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_double, ctypes.c_int32, D, D,
+                                        ctypes.POINTER(ctypes.c_int32)]
+    lib.dirac_lanczos_eigen.restype = ctypes.c_int
+    lib.dirac_lanczos_adjoint.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                          ctypes.c_int32, ctypes.c_int32, D, D]
+    lib.dirac_lanczos_adjoint.restype = ctypes.c_int
+    lib.dirac_lanczos_destroy.argtypes = [vp]
+    lib.dirac_lanczos_destroy.restype = ctypes.c_int
+    lib.dirac_lanczos_last_error.argtypes = [vp]
+    lib.dirac_lanczos_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def make_params(problem: dict, krylov_dim: int, precision: int = DL_PREC_FP64, v_table_ptr: int = 0):
+    """dl_params from a problem dict (keys as in packets.py).  Returns (struct, keepalive)."""
+    p = DlParams()
+    keep = []
+    for k in ("nx", "ny", "bc_x", "bc_y", "pot_kind", "pulse_kind"):
+        setattr(p, k, int(problem.get(k, 0)))
+    defaults = {"mass": 1.0, "c": 137.036, "charge": -1.0}
+    for k in ("x_min", "x_max", "y_min", "y_max", "mass", "c", "charge", "bz", "pot_z", "pot_a",
+              "a0", "omega", "t_pulse"):
+        setattr(p, k, float(problem.get(k, defaults.get(k, 0.0))))
+    e = problem.get("pulse_e", (0.0, 0.0))
+    p.pulse_e[0], p.pulse_e[1] = float(e[0]), float(e[1])
+    p.krylov_dim = int(krylov_dim)
+    p.precision = int(precision)
+    p.v_table = int(v_table_ptr) if v_table_ptr else None
+    coef = problem.get("coef")
+    if coef is not None and len(coef) > 0:
+        arr = np.ascontiguousarray(coef, dtype=np.float64)
+        keep.append(arr)
+        p.coef = arr.ctypes.data
+        p.n_coef = len(arr)
+    return p, keep
+
+
+def _err(lib, ctx):
+    msg = lib.dirac_lanczos_last_error(ctx)
+    return msg.decode() if msg else ""
+
+
+def _check(lib, ctx, status):
+    if status != DL_OK:
+        raise DlError(status, _err(lib, ctx))
+
+
+# ---------------------------------------------------------------------------
+# Functions with the C names (raw pointers in, status codes out)
+# ---------------------------------------------------------------------------
+def dirac_lanczos_workspace_bytes(params: DlParams, mode: int = DL_MODE_STEP, k_eigen: int = 0) -> int:
+    return int(load_library().dirac_lanczos_workspace_bytes(ctypes.byref(params), mode, k_eigen))
+
+
+def dirac_lanczos_init(params: DlParams, workspace_ptr: int, ws_bytes: int, stream_ptr: int):
+    lib = load_library()
+    ctx = ctypes.c_void_p()
+    st = lib.dirac_lanczos_init(ctypes.byref(params), ctypes.c_void_p(workspace_ptr), ws_bytes,
+                                ctypes.c_void_p(stream_ptr), ctypes.byref(ctx))
+    if st != DL_OK:
+        raise DlError(st, _err(lib, None))
+    return ctx
+
+
+def dirac_lanczos_apply(ctx, x_ptr: int, y_ptr: int, t: float) -> int:
+    return load_library().dirac_lanczos_apply(ctx, ctypes.c_void_p(x_ptr), ctypes.c_void_p(y_ptr), t)
+
+
+def dirac_lanczos_step(ctx, psi_ptr: int, t0: float, dt: float, n_steps: int, stats=None) -> int:
+    return load_library().dirac_lanczos_step(ctx, ctypes.c_void_p(psi_ptr), t0, dt, n_steps, stats)
+
+
+def dirac_lanczos_eigen(ctx, psi_ptr: int, k_max: int, reorth: int, e_lo: float, e_hi: float,
+                        tol: float, n_wanted: int, evals, bounds, n_found) -> int:
+    return load_library().dirac_lanczos_eigen(ctx, ctypes.c_void_p(psi_ptr), k_max, reorth, e_lo, e_hi,
+                                              tol, n_wanted, evals, bounds, n_found)
+
+
+def dirac_lanczos_adjoint(ctx, psi_ptr: int, t0: float, dt: float, n_steps: int, ckpt_every: int,
+                          loss_kind: int, loss, grad) -> int:
+    return load_library().dirac_lanczos_adjoint(ctx, ctypes.c_void_p(psi_ptr), t0, dt, n_steps,
+                                                ckpt_every, loss_kind, loss, grad)
+
+
+def dirac_lanczos_destroy(ctx) -> int:
+    return load_library().dirac_lanczos_destroy(ctx)
+
+
+def dirac_lanczos_last_error(ctx) -> str:
+    return _err(load_library(), ctx)
+
+
+# ---------------------------------------------------------------------------
+# Convenience wrapper over torch tensors
+# ---------------------------------------------------------------------------
+class Propagator:
+    """Owns a context and its torch-allocated workspace on the current device.
+
+    psi tensors are complex128 of shape (2, ny, nx), contiguous, on the GPU.
+    """
+
+    def __init__(self, problem: dict, krylov_dim: int, precision: str = "fp64", k_eigen: int = 0,
+                 stream=None, v_table=None):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        self.problem = dict(problem)
+        self.prec = DL_PREC_MIXED if precision == "mixed" else DL_PREC_FP64
+        self.v_table = None
+        vptr = 0
+        if v_table is not None:
+            self.v_table = torch.as_tensor(v_table, dtype=torch.float64, device="cuda").contiguous()
+            vptr = self.v_table.data_ptr()
+        self.params, self._keep = make_params(problem, krylov_dim, self.prec, vptr)
+        mode = DL_MODE_EIGEN if k_eigen > 0 else DL_MODE_STEP
+        nbytes = dirac_lanczos_workspace_bytes(self.params, mode, k_eigen)
+        if nbytes == 0:
+            raise DlError(DL_ERR_INVALID, "invalid parameters (workspace_bytes returned 0)")
+        self.ws_bytes = nbytes
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        base = self.workspace.data_ptr()
+        self.ws_ptr = (base + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.ctx = dirac_lanczos_init(self.params, self.ws_ptr, nbytes, self.stream.cuda_stream)
+        self.shape = (2, int(problem["ny"]), int(problem["nx"]))
+
+    def _check_psi(self, psi):
+        t = self.torch
+        if not (isinstance(psi, t.Tensor) and psi.is_cuda and psi.dtype == t.complex128
+                and tuple(psi.shape) == self.shape and psi.is_contiguous()):
+            raise ValueError(f"psi must be a contiguous complex128 CUDA tensor of shape {self.shape}")
+
+    def apply(self, x, t: float = 0.0):
+        self._check_psi(x)
+        y = self.torch.empty_like(x)
+        _check(self.lib, self.ctx, dirac_lanczos_apply(self.ctx, x.data_ptr(), y.data_ptr(), t))
+        return y
+
+    def step(self, psi, t0: float, dt: float, n_steps: int, want_stats: bool = True):
+        """In-place propagation of psi by n_steps steps.  Returns a dict of numpy stats."""
+        self._check_psi(psi)
+        stats = (DlStepStat * max(n_steps, 1))() if want_stats else None
+        st = dirac_lanczos_step(self.ctx, psi.data_ptr(), t0, dt, n_steps, stats)
+        out = None
+        if want_stats:
+            out = {
+                "k_eff": np.array([s.k_eff for s in stats[:n_steps]], dtype=np.int32),
+                "err_est": np.array([s.err_est for s in stats[:n_steps]]),
+                "cum_bound": np.array([s.cum_bound for s in stats[:n_steps]]),
+                "norm2": np.array([s.norm2 for s in stats[:n_steps]]),
+            }
+        _check(self.lib, self.ctx, st)
+        return out
+
+    def eigen(self, psi0, k_max: int, e_lo: float, e_hi: float, tol: float, n_wanted: int = 64,
+              reorth: bool = False):
+        self._check_psi(psi0)
+        ev = (ctypes.c_double * n_wanted)()
+        bd = (ctypes.c_double * n_wanted)()
+        nf = ctypes.c_int32(0)
+        st = dirac_lanczos_eigen(self.ctx, psi0.data_ptr(), k_max, int(bool(reorth)), e_lo, e_hi, tol,
+                                 n_wanted, ev, bd, ctypes.byref(nf))
+        _check(self.lib, self.ctx, st)
+        return np.array(ev[:nf.value]), np.array(bd[:nf.value])
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            dirac_lanczos_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,105 @@
+// Internal interface between the host runtime (host.cpp) and the gfx950
+// kernels (kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace dl {
+
+constexpr int kMaxM = 64;        // largest Krylov dimension of a time step
+constexpr int kBlock = 256;      // threads per workgroup (four wave64)
+constexpr int kWaves = kBlock / 64;
+constexpr int kMaxBlocks = 8192; // capacity of the per-workgroup partial-sum table
+constexpr int kChunk = 2048;     // time steps whose fields/stats are staged per batch
+
+// Device-resident scalars of the running Lanczos step.  Written only by the
+// last workgroup of a sweep (deterministic fixed-order reductions) and by the
+// single-wave tridiagonal kernel; read by every later kernel on the stream.
+struct Scalars {
+    double coef[2 * (kMaxM + 2)];  // c_j / gamma_j (re, im) for the recombination, j = 1..k
+    double scale;                  // running max of |alpha_j|, beta_j (breakdown test)
+    double cabs_k;                 // |c_k|, input of the error estimate
+    int kstop;                     // sweeps with index > kstop do nothing this step
+    int keff;                      // Krylov dimension in use (set at the end of the recurrence)
+    int status;                    // 0 ok, 3 non-finite (whole call aborted)
+    int steps_done;                // completed steps of the current call
+    unsigned int ticket;           // last-workgroup-done counter (self-resetting)
+    int pad[3];
+};
+
+struct StepStat {
+    double err_est;
+    double norm2;
+    int keff;
+    int pad;
+};
+
+// Coefficients of the operator A = s * H applied by the sweeps, s = dt for a
+// time step and s = 1 for the plain Hamiltonian.
+struct Op {
+    int nx, ny, bcx, bcy;
+    double xmin, ymin, hx, hy;
+    double kx, ky;        // s c / (2 h_x), s c / (2 h_y)
+    double mc2;           // s m c^2
+    double bq;            // s c q B / 2: gx = gx_hom + bq y, gy = gy_hom - bq x
+    int pot_kind;         // 0 none, 1 s*(-zc / sqrt(r^2 + a2))
+    int has_table;
+    double vz, va2;       // s*zc, a2
+    const double *vtab;   // optional potential table (device), multiplied by s
+    double vscale;
+};
+
+// Wave-to-tile mapping of one sweep: every wave owns `own` consecutive columns
+// of one strip and `rows` consecutive rows of it (its chunk).
+struct Tiles {
+    int halo, own, nstrips, nchunks, rows, nblocks;
+};
+
+// Arguments of a recurrence sweep (Lanczos iteration p >= 2).
+struct PassArgs {
+    Op op;
+    Tiles t;
+    const void *u1;      // u_{p-1}
+    const void *u2;      // u_{p-2} (unused for p = 2)
+    void *uo;            // u_p (written)
+    const double *field; // (gx_hom, gy_hom) of this step
+    double *alpha;       // alpha[1..]
+    double *gamma;       // gamma[1..]: gamma_1 = ||psi||, gamma_p = beta_{p-1}
+    Scalars *sc;
+    double *partials;
+    int pass;
+    int m;
+};
+
+// Arguments of the recombination sweep.
+struct RecArgs {
+    Op op;
+    Tiles t;
+    const double2 *psi;  // u_1
+    const void *basis;   // u_2..u_m, consecutive vectors of vec_elems elements
+    size_t vec_elems;    // 2*nx*ny
+    double2 *out;        // new state
+    const double *field;
+    const double *alpha;
+    const double *gamma;
+    Scalars *sc;
+    double *partials;
+    StepStat *stat;      // entry of this step
+};
+
+void launch_first(const Op &op, const Tiles &t, const double2 *psi, const double *field,
+                  double *alpha, double *gamma, Scalars *sc, double *partials, int m,
+                  hipStream_t st);
+void launch_recur(const PassArgs &a, bool mixed, hipStream_t st);
+void launch_tridiag(const double *alpha, const double *gamma, Scalars *sc, hipStream_t st);
+void launch_recombine(const RecArgs &a, bool mixed, hipStream_t st);
+void launch_apply(const Op &op, const Tiles &t, const double2 *x, double2 *y, double gxh,
+                  double gyh, hipStream_t st);
+void launch_reset(Scalars *sc, hipStream_t st);
+
+Tiles make_tiles(int nx, int ny, int halo, int target_waves);
+
+}  // namespace dl

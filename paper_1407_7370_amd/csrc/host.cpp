@@ -1,0 +1,613 @@
+// Host runtime of the C ABI declared in include/dirac_lanczos.h: parameter
+// validation, workspace planning, the per-step field averages (first Magnus
+// term, Sec. 3 eq. time_evolution_approx), the launch sequence of a time step
+// (Sec. 4 eq. matrix_exp_approx) and the Ritz-value extraction of the
+// eigenvalue mode (Sec. 2 eq. error_est).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dirac_lanczos.h"
+#include "dl_internal.h"
+
+using dl::kChunk;
+using dl::kMaxBlocks;
+using dl::kMaxM;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+struct Layout {
+    size_t sc = 0, alpha = 0, gamma = 0, partials = 0, fields = 0, stats = 0, vecs = 0, total = 0;
+    int ab_len = 0;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+size_t vec_elems(const dl_params &p) { return (size_t)2 * (size_t)p.nx * (size_t)p.ny; }
+
+// Workspace plan.  Vector region: step mode holds the second state buffer
+// (complex128) and the Krylov vectors u_2..u_m (complex128, or complex64 in
+// mixed precision); eigen mode needs three rolling complex128 vectors.
+Layout plan(const dl_params &p, int mode, int k_eigen)
+{
+    Layout L;
+    const int m = p.krylov_dim;
+    L.ab_len = std::max(m, mode == DL_MODE_EIGEN ? k_eigen + 1 : 0) + 3;
+    size_t off = 0;
+    L.sc = off;
+    off = align256(off + sizeof(dl::Scalars));
+    L.alpha = off;
+    off = align256(off + sizeof(double) * L.ab_len);
+    L.gamma = off;
+    off = align256(off + sizeof(double) * L.ab_len);
+    L.partials = off;
+    off = align256(off + sizeof(double) * 4 * kMaxBlocks);
+    L.fields = off;
+    off = align256(off + sizeof(double) * 2 * kChunk);
+    L.stats = off;
+    off = align256(off + sizeof(dl::StepStat) * kChunk);
+    L.vecs = off;
+    const size_t n = vec_elems(p);
+    const size_t basis_elem = p.precision == DL_PREC_MIXED ? 8 : 16;
+    size_t step_region = align256(n * 16) + (size_t)(m - 1) * align256(n * basis_elem);
+    size_t eig_region = mode == DL_MODE_EIGEN ? 3 * align256(n * 16) : 0;
+    off += std::max(step_region, eig_region);
+    L.total = off;
+    return L;
+}
+
+const char *validate(const dl_params *p)
+{
+    if (!p) return "params is NULL";
+    if (p->nx < 3 || p->ny < 3) return "nx and ny must be >= 3";
+    if ((double)p->nx * (double)p->ny > 2.0e9) return "grid too large (nx*ny > 2e9)";
+    if (!(p->x_max > p->x_min) || !(p->y_max > p->y_min)) return "empty box (x_max <= x_min or y_max <= y_min)";
+    if (!std::isfinite(p->x_min) || !std::isfinite(p->x_max) || !std::isfinite(p->y_min) ||
+        !std::isfinite(p->y_max))
+        return "box bounds must be finite";
+    if ((p->bc_x != 0 && p->bc_x != 1) || (p->bc_y != 0 && p->bc_y != 1)) return "bc must be 0 or 1";
+    if (!(p->c > 0.0) || !std::isfinite(p->c)) return "c must be positive";
+    if (!(p->mass >= 0.0) || !std::isfinite(p->mass)) return "mass must be >= 0";
+    if (!std::isfinite(p->charge) || !std::isfinite(p->bz)) return "charge and bz must be finite";
+    if (p->krylov_dim < 1 || p->krylov_dim > kMaxM) return "krylov_dim must be in 1..64";
+    if (p->precision != DL_PREC_FP64 && p->precision != DL_PREC_MIXED) return "unknown precision";
+    if (p->pot_kind < 0 || p->pot_kind > 2) return "unknown pot_kind";
+    if (p->pot_kind == 1 && !(p->pot_a != 0.0 && std::isfinite(p->pot_a) && std::isfinite(p->pot_z)))
+        return "soft-core potential needs pot_a != 0";
+    if (p->pot_kind == 2 && !(p->pot_z != 0.0 && std::isfinite(p->pot_z)))
+        return "paper soft-core potential needs pot_z != 0";
+    if (p->pulse_kind < 0 || p->pulse_kind > 2) return "unknown pulse_kind";
+    if (p->pulse_kind != 0 && !(p->t_pulse > 0.0 && std::isfinite(p->t_pulse))) return "t_pulse must be > 0";
+    if (p->pulse_kind == 1 && !(std::isfinite(p->a0) && std::isfinite(p->omega) &&
+                                std::isfinite(p->pulse_e[0]) && std::isfinite(p->pulse_e[1])))
+        return "pulse parameters must be finite";
+    if (p->pulse_kind == 2) {
+        if (p->n_coef <= 0 || p->n_coef % 4 != 0 || p->n_coef > 1024 || !p->coef)
+            return "Fourier pulse needs coef with n_coef a positive multiple of 4 (<= 1024)";
+        for (int i = 0; i < p->n_coef; ++i)
+            if (!std::isfinite(p->coef[i])) return "Fourier coefficients must be finite";
+    }
+    return nullptr;
+}
+
+// --- homogeneous laser field --------------------------------------------------
+const double kPi = 3.14159265358979323846;
+
+void pulse_now(const dl_params &p, const std::vector<double> &coef, double t, double *a)
+{
+    a[0] = a[1] = 0.0;
+    if (p.pulse_kind == 0 || t < 0.0 || t > p.t_pulse) return;
+    const double s = std::sin(kPi * t / p.t_pulse), env = s * s;
+    if (p.pulse_kind == 1) {
+        const double f = p.a0 * std::sin(p.omega * t) * env;
+        a[0] = f * p.pulse_e[0];
+        a[1] = f * p.pulse_e[1];
+        return;
+    }
+    const double w0 = 2.0 * kPi / p.t_pulse;
+    for (size_t k = 1; 4 * k <= coef.size(); ++k) {
+        const double sk = std::sin(k * w0 * t), ck = std::cos(k * w0 * t);
+        a[0] += coef[4 * (k - 1)] * sk + coef[4 * (k - 1) + 1] * ck;
+        a[1] += coef[4 * (k - 1) + 2] * sk + coef[4 * (k - 1) + 3] * ck;
+    }
+    a[0] *= env;
+    a[1] *= env;
+}
+
+// Exact integrals over [lo, hi] written without cancellation:
+//   int sin(nu t) = (2/nu) sin(nu tm) sin(nu h2), int cos(nu t) = (2/nu) cos(nu tm) sin(nu h2)
+// with tm the midpoint and h2 the half width.
+double int_sin(double nu, double tm, double h2)
+{
+    if (nu == 0.0) return 0.0;
+    return 2.0 / nu * std::sin(nu * tm) * std::sin(nu * h2);
+}
+
+double int_cos(double nu, double tm, double h2)
+{
+    if (nu == 0.0) return 2.0 * h2;
+    return 2.0 / nu * std::cos(nu * tm) * std::sin(nu * h2);
+}
+
+// (1/|dt|) integral of A_L over the step [t0, t0 + dt]; the envelope
+// sin^2(pi t/T) = (1 - cos(W t))/2 (W = 2 pi/T) turns every term into single
+// sines and cosines whose integrals are closed forms.
+void pulse_average(const dl_params &p, const std::vector<double> &coef, double t0, double dt,
+                   double *a)
+{
+    a[0] = a[1] = 0.0;
+    if (p.pulse_kind == 0) return;
+    double lo = std::min(t0, t0 + dt), hi = std::max(t0, t0 + dt);
+    lo = std::max(lo, 0.0);
+    hi = std::min(hi, p.t_pulse);
+    if (!(hi > lo)) return;
+    const double tm = 0.5 * (lo + hi), h2 = 0.5 * (hi - lo);
+    const double W = 2.0 * kPi / p.t_pulse;
+    if (p.pulse_kind == 1) {
+        const double w = p.omega;
+        const double v = 0.5 * int_sin(w, tm, h2) - 0.25 * (int_sin(w + W, tm, h2) + int_sin(w - W, tm, h2));
+        a[0] = p.a0 * v * p.pulse_e[0];
+        a[1] = p.a0 * v * p.pulse_e[1];
+    } else {
+        for (size_t k = 1; 4 * k <= coef.size(); ++k) {
+            const double nu = k * W;
+            const double is = 0.5 * int_sin(nu, tm, h2) -
+                              0.25 * (int_sin(nu + W, tm, h2) + int_sin(nu - W, tm, h2));
+            const double ic = 0.5 * int_cos(nu, tm, h2) -
+                              0.25 * (int_cos(nu + W, tm, h2) + int_cos(nu - W, tm, h2));
+            a[0] += coef[4 * (k - 1)] * is + coef[4 * (k - 1) + 1] * ic;
+            a[1] += coef[4 * (k - 1) + 2] * is + coef[4 * (k - 1) + 3] * ic;
+        }
+    }
+    a[0] /= std::fabs(dt);
+    a[1] /= std::fabs(dt);
+}
+
+// Symmetric tridiagonal eigenvalues and the last component of each
+// eigenvector: implicit QR steps with Wilkinson shift (Golub & Van Loan,
+// symmetric QR algorithm), accumulating only the last row of the eigenvector
+// matrix.
+void tridiag_last_row(std::vector<double> d, std::vector<double> e, std::vector<double> &lam,
+                      std::vector<double> &zlast)
+{
+    const int k = (int)d.size();
+    zlast.assign(k, 0.0);
+    zlast[k - 1] = 1.0;
+    e.resize(k, 0.0);
+    const double eps = 2.220446049250313e-16;
+    int h = k - 1, iter = 0;
+    while (h > 0) {
+        if (std::fabs(e[h - 1]) <= eps * (std::fabs(d[h - 1]) + std::fabs(d[h]))) {
+            e[h - 1] = 0.0;
+            --h;
+            iter = 0;
+            continue;
+        }
+        if (++iter > 200) break;
+        int l = h - 1;
+        while (l > 0 && std::fabs(e[l - 1]) > eps * (std::fabs(d[l - 1]) + std::fabs(d[l]))) --l;
+        const double delta = 0.5 * (d[h - 1] - d[h]);
+        const double b2 = e[h - 1] * e[h - 1];
+        const double mu = d[h] - b2 / (delta + std::copysign(std::sqrt(delta * delta + b2), delta));
+        double x = d[l] - mu, z = e[l];
+        for (int q = l; q < h; ++q) {
+            const double r = std::hypot(x, z);
+            double c = 1.0, s = 0.0;
+            if (r != 0.0) {
+                c = x / r;
+                s = -z / r;
+            }
+            if (q > l) e[q - 1] = r;
+            const double aq = d[q], aq1 = d[q + 1], bq = e[q];
+            const double cc = c * c, ss = s * s, cs = c * s;
+            d[q] = cc * aq - 2.0 * cs * bq + ss * aq1;
+            d[q + 1] = ss * aq + 2.0 * cs * bq + cc * aq1;
+            e[q] = cs * (aq - aq1) + (cc - ss) * bq;
+            if (q + 1 < h) {
+                const double bq1 = e[q + 1];
+                x = e[q];
+                z = -s * bq1;
+                e[q + 1] = c * bq1;
+            }
+            const double zq = zlast[q], zq1 = zlast[q + 1];
+            zlast[q] = c * zq - s * zq1;
+            zlast[q + 1] = s * zq + c * zq1;
+        }
+    }
+    lam = d;
+}
+
+}  // namespace
+
+struct dl_context {
+    dl_params p{};
+    std::vector<double> coef;
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    Layout L;
+    int target_waves = 4096;
+    std::vector<double> host_fields;
+    std::vector<dl::StepStat> host_stats;
+    std::string err;
+
+    dl_status fail(dl_status s, const std::string &msg)
+    {
+        err = msg;
+        return s;
+    }
+    dl_status hip_fail(hipError_t e, const char *what)
+    {
+        err = std::string(what) + ": " + hipGetErrorString(e);
+        return DL_ERR_DEVICE;
+    }
+    dl::Scalars *sc() const { return reinterpret_cast<dl::Scalars *>(ws + L.sc); }
+
+    // A = s H with the geometry and static fields of the problem.
+    dl::Op op(double s) const
+    {
+        dl::Op o{};
+        o.nx = p.nx;
+        o.ny = p.ny;
+        o.bcx = p.bc_x;
+        o.bcy = p.bc_y;
+        o.hx = (p.x_max - p.x_min) / p.nx;
+        o.hy = (p.y_max - p.y_min) / p.ny;
+        o.xmin = p.x_min;
+        o.ymin = p.y_min;
+        o.kx = s * p.c / (2.0 * o.hx);
+        o.ky = s * p.c / (2.0 * o.hy);
+        o.mc2 = s * p.mass * p.c * p.c;
+        o.bq = s * p.c * p.charge * p.bz * 0.5;
+        o.pot_kind = p.pot_kind ? 1 : 0;
+        if (p.pot_kind == 1) {
+            o.vz = s * p.pot_z;
+            o.va2 = p.pot_a * p.pot_a;
+        } else if (p.pot_kind == 2) {
+            o.vz = s * 1.5 * p.pot_z;
+            o.va2 = 3.0 / (p.pot_z * p.pot_z);
+        }
+        o.has_table = p.v_table ? 1 : 0;
+        o.vtab = p.v_table;
+        o.vscale = s;
+        return o;
+    }
+};
+
+#define DL_HIP(ctx, call)                                      \
+    do {                                                       \
+        hipError_t e_ = (call);                                \
+        if (e_ != hipSuccess) return (ctx)->hip_fail(e_, #call); \
+    } while (0)
+
+extern "C" {
+
+size_t dirac_lanczos_workspace_bytes(const dl_params *params, int32_t mode, int32_t k_eigen)
+{
+    if (validate(params)) return 0;
+    if (mode != DL_MODE_STEP && mode != DL_MODE_EIGEN) return 0;
+    if (mode == DL_MODE_EIGEN && (k_eigen < 1 || k_eigen > 1000000)) return 0;
+    return plan(*params, mode, mode == DL_MODE_EIGEN ? k_eigen : 0).total;
+}
+
+dl_status dirac_lanczos_init(const dl_params *params, void *workspace, size_t ws_bytes,
+                             void *hip_stream, dl_context **out)
+{
+    if (!out) {
+        g_init_error = "out is NULL";
+        return DL_ERR_INVALID;
+    }
+    *out = nullptr;
+    if (const char *msg = validate(params)) {
+        g_init_error = msg;
+        return DL_ERR_INVALID;
+    }
+    const Layout L = plan(*params, DL_MODE_STEP, 0);
+    if (!workspace || ((uintptr_t)workspace & 255u) != 0) {
+        g_init_error = "workspace must be a non-NULL, 256-byte aligned device pointer";
+        return DL_ERR_WORKSPACE;
+    }
+    if (ws_bytes < L.total) {
+        g_init_error = "workspace too small: need " + std::to_string(L.total) + " bytes";
+        return DL_ERR_WORKSPACE;
+    }
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        g_init_error = "no HIP device";
+        return DL_ERR_DEVICE;
+    }
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        g_init_error = std::string("built for gfx950 only, device is ") + prop.gcnArchName;
+        return DL_ERR_DEVICE;
+    }
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, workspace) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+        (void)hipGetLastError();
+        g_init_error = "workspace is not device memory";
+        return DL_ERR_WORKSPACE;
+    }
+    dl_context *ctx = new dl_context();
+    ctx->p = *params;
+    if (params->pulse_kind == 2) ctx->coef.assign(params->coef, params->coef + params->n_coef);
+    ctx->p.coef = nullptr;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    ctx->ws = static_cast<char *>(workspace);
+    ctx->ws_bytes = ws_bytes;
+    ctx->L = L;
+    ctx->target_waves = 16 * prop.multiProcessorCount;
+    dl::launch_reset(ctx->sc(), ctx->stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        g_init_error = std::string("kernel launch failed: ") + hipGetErrorString(e);
+        delete ctx;
+        return DL_ERR_DEVICE;
+    }
+    *out = ctx;
+    return DL_OK;
+}
+
+dl_status dirac_lanczos_apply(dl_context *ctx, const void *x, void *y, double t)
+{
+    if (!ctx) return DL_ERR_INVALID;
+    if (!x || !y || x == y) return ctx->fail(DL_ERR_INVALID, "apply needs distinct non-NULL x and y");
+    if (!std::isfinite(t)) return ctx->fail(DL_ERR_INVALID, "t must be finite");
+    const dl::Op op = ctx->op(1.0);
+    double a[2];
+    pulse_now(ctx->p, ctx->coef, t, a);
+    const double k = -ctx->p.c * ctx->p.charge;
+    const dl::Tiles tl = dl::make_tiles(ctx->p.nx, ctx->p.ny, 1, ctx->target_waves);
+    dl::launch_apply(op, tl, static_cast<const double2 *>(x), static_cast<double2 *>(y), k * a[0],
+                     k * a[1], ctx->stream);
+    DL_HIP(ctx, hipGetLastError());
+    return DL_OK;
+}
+
+dl_status dirac_lanczos_step(dl_context *ctx, void *psi_v, double t0, double dt, int32_t n_steps,
+                             dl_step_stat *stats)
+{
+    if (!ctx) return DL_ERR_INVALID;
+    if (!psi_v) return ctx->fail(DL_ERR_INVALID, "psi is NULL");
+    if (n_steps < 0) return ctx->fail(DL_ERR_INVALID, "n_steps must be >= 0");
+    if (!(dt != 0.0) || !std::isfinite(dt) || !std::isfinite(t0))
+        return ctx->fail(DL_ERR_INVALID, "dt must be finite and non-zero, t0 finite");
+    if (n_steps == 0) return DL_OK;
+    const dl_params &p = ctx->p;
+    const int m = p.krylov_dim;
+    const bool mixed = p.precision == DL_PREC_MIXED;
+    const size_t n = vec_elems(p);
+    const size_t belem = mixed ? 8 : 16;
+    char *ws = ctx->ws;
+    const Layout &L = ctx->L;
+    dl::Scalars *sc = ctx->sc();
+    double *alpha = reinterpret_cast<double *>(ws + L.alpha);
+    double *gamma = reinterpret_cast<double *>(ws + L.gamma);
+    double *partials = reinterpret_cast<double *>(ws + L.partials);
+    double *fields = reinterpret_cast<double *>(ws + L.fields);
+    dl::StepStat *dstats = reinterpret_cast<dl::StepStat *>(ws + L.stats);
+    double2 *psi = static_cast<double2 *>(psi_v);
+    double2 *state = reinterpret_cast<double2 *>(ws + L.vecs);
+    char *basis = ws + L.vecs + align256(n * 16);
+    auto bvec = [&](int j) -> void * { return basis + (size_t)(j - 2) * align256(n * belem); };
+
+    const dl::Op op = ctx->op(dt);
+    const dl::Tiles t1 = dl::make_tiles(p.nx, p.ny, 1, ctx->target_waves);
+    const dl::Tiles t2 = dl::make_tiles(p.nx, p.ny, 2, ctx->target_waves);
+    const double kf = -dt * p.c * p.charge;
+    hipStream_t st = ctx->stream;
+
+    dl::launch_reset(sc, st);
+    DL_HIP(ctx, hipGetLastError());
+    double cum = 0.0;
+    int completed = 0;
+    bool aborted = false;
+    ctx->host_fields.resize(2 * kChunk);
+    ctx->host_stats.resize(kChunk);
+    for (int s0 = 0; s0 < n_steps && !aborted; s0 += kChunk) {
+        const int nc = std::min(kChunk, n_steps - s0);
+        for (int i = 0; i < nc; ++i) {
+            double a[2];
+            pulse_average(p, ctx->coef, t0 + (double)(s0 + i) * dt, dt, a);
+            ctx->host_fields[2 * i] = kf * a[0];
+            ctx->host_fields[2 * i + 1] = kf * a[1];
+        }
+        DL_HIP(ctx, hipMemcpyAsync(fields, ctx->host_fields.data(), sizeof(double) * 2 * nc,
+                                   hipMemcpyHostToDevice, st));
+        for (int i = 0; i < nc; ++i) {
+            const int g = s0 + i;
+            double2 *in = (g % 2 == 0) ? psi : state;
+            double2 *out = (g % 2 == 0) ? state : psi;
+            const double *fp = fields + 2 * i;
+            dl::launch_first(op, t1, in, fp, alpha, gamma, sc, partials, m, st);
+            for (int pp = 2; pp <= m; ++pp) {
+                dl::PassArgs a{};
+                a.op = op;
+                a.t = t2;
+                a.u1 = (pp - 1 == 1) ? static_cast<const void *>(in) : bvec(pp - 1);
+                a.u2 = (pp - 2 == 1) ? static_cast<const void *>(in)
+                                     : (pp - 2 >= 2 ? bvec(pp - 2) : nullptr);
+                a.uo = bvec(pp);
+                a.field = fp;
+                a.alpha = alpha;
+                a.gamma = gamma;
+                a.sc = sc;
+                a.partials = partials;
+                a.pass = pp;
+                a.m = m;
+                dl::launch_recur(a, mixed, st);
+            }
+            dl::launch_tridiag(alpha, gamma, sc, st);
+            dl::RecArgs r{};
+            r.op = op;
+            r.t = t1;
+            r.psi = in;
+            r.basis = basis;
+            r.vec_elems = align256(n * belem) / belem;
+            r.out = out;
+            r.field = fp;
+            r.alpha = alpha;
+            r.gamma = gamma;
+            r.sc = sc;
+            r.partials = partials;
+            r.stat = dstats + i;
+            dl::launch_recombine(r, mixed, st);
+        }
+        DL_HIP(ctx, hipGetLastError());
+        dl::Scalars hs;
+        DL_HIP(ctx, hipMemcpyAsync(ctx->host_stats.data(), dstats, sizeof(dl::StepStat) * nc,
+                                   hipMemcpyDeviceToHost, st));
+        DL_HIP(ctx, hipMemcpyAsync(&hs, sc, sizeof(hs), hipMemcpyDeviceToHost, st));
+        DL_HIP(ctx, hipStreamSynchronize(st));
+        const int done_here = hs.steps_done - completed;
+        for (int i = 0; i < nc; ++i) {
+            if (!stats) break;
+            dl_step_stat &o = stats[s0 + i];
+            if (i < done_here) {
+                cum += ctx->host_stats[i].err_est;
+                o.k_eff = ctx->host_stats[i].keff;
+                o.err_est = ctx->host_stats[i].err_est;
+                o.cum_bound = cum;
+                o.norm2 = ctx->host_stats[i].norm2;
+            } else {
+                o.k_eff = -1;
+                o.err_est = o.cum_bound = o.norm2 = 0.0;
+            }
+        }
+        completed = hs.steps_done;
+        if (hs.status != 0) aborted = true;
+    }
+    if (stats && aborted)
+        for (int i = completed; i < n_steps; ++i) {
+            stats[i].k_eff = -1;
+            stats[i].err_est = stats[i].cum_bound = stats[i].norm2 = 0.0;
+        }
+    // the state after `completed` steps sits in psi (even) or in the workspace (odd)
+    if (completed % 2 == 1) {
+        DL_HIP(ctx, hipMemcpyAsync(psi, state, n * 16, hipMemcpyDeviceToDevice, st));
+        DL_HIP(ctx, hipStreamSynchronize(st));
+    }
+    if (aborted)
+        return ctx->fail(DL_ERR_NONFINITE, "non-finite Lanczos reduction after " +
+                                               std::to_string(completed) + " completed steps");
+    return DL_OK;
+}
+
+dl_status dirac_lanczos_eigen(dl_context *ctx, const void *psi0, int32_t k_max, int32_t reorth,
+                              double e_lo, double e_hi, double tol, int32_t n_wanted, double *evals,
+                              double *bounds, int32_t *n_found)
+{
+    if (!ctx) return DL_ERR_INVALID;
+    if (!psi0 || !evals || !bounds || !n_found || n_wanted < 1 || k_max < 1 || !(tol >= 0.0) ||
+        !(e_hi >= e_lo))
+        return ctx->fail(DL_ERR_INVALID, "invalid eigen arguments");
+    *n_found = 0;
+    if (reorth) return ctx->fail(DL_ERR_UNSUPPORTED, "full reorthogonalisation is not provided on the GPU");
+    const dl_params &p = ctx->p;
+    const Layout E = plan(p, DL_MODE_EIGEN, k_max);
+    if (ctx->ws_bytes < E.total)
+        return ctx->fail(DL_ERR_WORKSPACE, "workspace too small for eigen mode: need " +
+                                               std::to_string(E.total) + " bytes");
+    const size_t n = vec_elems(p);
+    char *ws = ctx->ws;
+    dl::Scalars *sc = ctx->sc();
+    double *alpha = reinterpret_cast<double *>(ws + E.alpha);
+    double *gamma = reinterpret_cast<double *>(ws + E.gamma);
+    double *partials = reinterpret_cast<double *>(ws + E.partials);
+    double *fields = reinterpret_cast<double *>(ws + E.fields);
+    double2 *v[3];
+    for (int i = 0; i < 3; ++i) v[i] = reinterpret_cast<double2 *>(ws + E.vecs + i * align256(n * 16));
+    hipStream_t st = ctx->stream;
+    const dl::Op op = ctx->op(1.0);
+    const dl::Tiles t1 = dl::make_tiles(p.nx, p.ny, 1, ctx->target_waves);
+    const dl::Tiles t2 = dl::make_tiles(p.nx, p.ny, 2, ctx->target_waves);
+    const double zero[2] = {0.0, 0.0};
+    DL_HIP(ctx, hipMemcpyAsync(fields, zero, sizeof(zero), hipMemcpyHostToDevice, st));
+    DL_HIP(ctx, hipMemcpyAsync(v[1], psi0, n * 16, hipMemcpyDeviceToDevice, st));
+    dl::launch_reset(sc, st);
+    const int K1 = k_max + 1;  // the extra iteration yields beta_k for the bounds
+    dl::launch_first(op, t1, v[1], fields, alpha, gamma, sc, partials, K1, st);
+    for (int pp = 2; pp <= K1; ++pp) {
+        dl::PassArgs a{};
+        a.op = op;
+        a.t = t2;
+        a.u1 = v[(pp - 1) % 3];
+        a.u2 = pp >= 3 ? v[(pp - 2) % 3] : nullptr;
+        a.uo = v[pp % 3];
+        a.field = fields;
+        a.alpha = alpha;
+        a.gamma = gamma;
+        a.sc = sc;
+        a.partials = partials;
+        a.pass = pp;
+        a.m = K1;
+        dl::launch_recur(a, false, st);
+    }
+    DL_HIP(ctx, hipGetLastError());
+    std::vector<double> ha(K1 + 1), hg(K1 + 1);
+    dl::Scalars hs;
+    DL_HIP(ctx, hipMemcpyAsync(ha.data(), alpha, sizeof(double) * (K1 + 1), hipMemcpyDeviceToHost, st));
+    DL_HIP(ctx, hipMemcpyAsync(hg.data(), gamma, sizeof(double) * (K1 + 1), hipMemcpyDeviceToHost, st));
+    DL_HIP(ctx, hipMemcpyAsync(&hs, sc, sizeof(hs), hipMemcpyDeviceToHost, st));
+    DL_HIP(ctx, hipStreamSynchronize(st));
+    if (hs.status != 0) return ctx->fail(DL_ERR_NONFINITE, "non-finite Lanczos reduction in eigen mode");
+    const int k = std::min(hs.keff, k_max);
+    if (k <= 0) return DL_OK;
+    std::vector<double> d(ha.begin() + 1, ha.begin() + 1 + k), e(k, 0.0), lam, zl;
+    for (int j = 0; j + 1 < k; ++j) e[j] = hg[j + 2];
+    const double beta_k = hg[k + 1];
+    tridiag_last_row(d, e, lam, zl);
+    std::vector<std::pair<double, double>> cand;
+    for (int i = 0; i < k; ++i)
+        if (lam[i] >= e_lo && lam[i] <= e_hi) cand.push_back({lam[i], zl[i]});
+    std::sort(cand.begin(), cand.end(),
+              [](const std::pair<double, double> &a, const std::pair<double, double> &b) {
+                  return a.first < b.first;
+              });
+    int nf = 0;
+    for (size_t a = 0; a < cand.size();) {
+        size_t b = a + 1;
+        while (b < cand.size() && cand[b].first - cand[b - 1].first <= tol) ++b;
+        double sum = 0.0, t2s = 0.0;
+        for (size_t c = a; c < b; ++c) {
+            sum += cand[c].first;
+            t2s += cand[c].second * cand[c].second;
+        }
+        const double bound = std::fabs(beta_k) * std::sqrt(t2s);
+        if (bound <= tol && nf < n_wanted) {
+            evals[nf] = sum / (double)(b - a);
+            bounds[nf] = bound;
+            ++nf;
+        }
+        a = b;
+    }
+    *n_found = nf;
+    return DL_OK;
+}
+
+dl_status dirac_lanczos_adjoint(dl_context *ctx, const void *, double, double, int32_t, int32_t,
+                                int32_t, double *, double *)
+{
+    if (!ctx) return DL_ERR_INVALID;
+    return ctx->fail(DL_ERR_UNSUPPORTED, "adjoint propagation is not provided by this build");
+}
+
+dl_status dirac_lanczos_destroy(dl_context *ctx)
+{
+    delete ctx;
+    return DL_OK;
+}
+
+const char *dirac_lanczos_last_error(const dl_context *ctx)
+{
+    if (!ctx) return g_init_error.c_str();
+    return ctx->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,111 @@
+"""CPU checks of the C ABI: the library loads, exports every declared symbol,
+its ctypes mirror matches the C struct layout, and host-side validation
+rejects bad arguments before any device work."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1407_7370_amd import binding, packets
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dirac_lanczos.h")
+
+
+def header_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(dirac_lanczos_\w+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = binding.load_library()
+    names = header_functions()
+    assert set(names) == set(binding.EXPORTS)
+    out = subprocess.run(["nm", "-D", "--defined-only", binding.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if ln.strip()}
+    for n in names:
+        assert n in exported, n
+        getattr(lib, n)
+
+
+def test_params_layout_matches_c(tmp_path):
+    fields = [f[0] for f in binding.DlParams._fields_]
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "dirac_lanczos.h"', "int main(){",
+           'printf("%zu\\n", sizeof(dl_params));', 'printf("%zu\\n", sizeof(dl_step_stat));']
+    for f in fields:
+        src.append(f'printf("%zu\\n", offsetof(dl_params, {f}));')
+    for f in ("k_eff", "err_est", "cum_bound", "norm2"):
+        src.append(f'printf("%zu\\n", offsetof(dl_step_stat, {f}));')
+    src.append("return 0;}")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.dirname(HEADER), str(c), "-o", str(exe)])
+    vals = [int(v) for v in subprocess.check_output([str(exe)], text=True).split()]
+    assert vals[0] == ctypes.sizeof(binding.DlParams)
+    assert vals[1] == ctypes.sizeof(binding.DlStepStat)
+    for f, off in zip(fields, vals[2:2 + len(fields)]):
+        assert getattr(binding.DlParams, f).offset == off, f
+    for f, off in zip(("k_eff", "err_est", "cum_bound", "norm2"), vals[2 + len(fields):]):
+        assert getattr(binding.DlStepStat, f).offset == off, f
+
+
+def _params(cfg, m, prec):
+    return binding.make_params(cfg["problem"], m, prec)[0]
+
+
+def test_workspace_bytes_plan():
+    cfg = packets.laser_4096()
+    n = 2 * 4096 * 4096
+    pm = _params(cfg, 16, binding.DL_PREC_MIXED)
+    pf = _params(cfg, 16, binding.DL_PREC_FP64)
+    bm = binding.dirac_lanczos_workspace_bytes(pm)
+    bf = binding.dirac_lanczos_workspace_bytes(pf)
+    # second state buffer (complex128) + 15 Krylov vectors + < 4 MiB of scalars/tables
+    assert n * 16 + 15 * n * 8 <= bm <= n * 16 + 15 * n * 8 + (4 << 20)
+    assert n * 16 + 15 * n * 16 <= bf <= n * 16 + 15 * n * 16 + (4 << 20)
+    # eigen mode: at least three complex128 vectors
+    small = packets.with_grid(cfg, 64)
+    p1 = _params(small, 1, binding.DL_PREC_FP64)
+    assert binding.dirac_lanczos_workspace_bytes(p1, binding.DL_MODE_EIGEN, 100) >= 3 * 2 * 64 * 64 * 16
+    assert binding.dirac_lanczos_workspace_bytes(p1, binding.DL_MODE_EIGEN, 0) == 0
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=2), dict(ny=1), dict(x_max=-50.0), dict(bc_x=2), dict(c=0.0), dict(mass=-1.0),
+    dict(pot_kind=3), dict(pot_kind=1, pot_a=0.0), dict(pot_kind=2, pot_z=0.0), dict(pulse_kind=5),
+    dict(pulse_kind=1, t_pulse=0.0), dict(pulse_kind=2, coef=[1.0, 2.0, 3.0]),
+    dict(bz=float("nan")),
+])
+def test_invalid_params_rejected(bad):
+    cfg = packets.with_grid(packets.laser_4096(), 64)
+    prob = dict(cfg["problem"], **bad)
+    p, _ = binding.make_params(prob, 16, binding.DL_PREC_FP64)
+    assert binding.dirac_lanczos_workspace_bytes(p) == 0
+    with pytest.raises(binding.DlError) as ei:
+        binding.dirac_lanczos_init(p, 256, 1 << 40, 0)
+    assert ei.value.status == binding.DL_ERR_INVALID
+
+
+@pytest.mark.parametrize("m,prec", [(0, 0), (65, 0), (16, 2)])
+def test_invalid_krylov_or_precision(m, prec):
+    cfg = packets.with_grid(packets.laser_4096(), 64)
+    p, _ = binding.make_params(cfg["problem"], m, prec)
+    assert binding.dirac_lanczos_workspace_bytes(p) == 0
+    with pytest.raises(binding.DlError) as ei:
+        binding.dirac_lanczos_init(p, 256, 1 << 40, 0)
+    assert ei.value.status == binding.DL_ERR_INVALID
+
+
+def test_workspace_errors():
+    cfg = packets.with_grid(packets.laser_4096(), 64)
+    p, _ = binding.make_params(cfg["problem"], 16, binding.DL_PREC_FP64)
+    need = binding.dirac_lanczos_workspace_bytes(p)
+    for ptr, size in ((0, need), (256 + 8, need), (256, need - 1)):
+        with pytest.raises(binding.DlError) as ei:
+            binding.dirac_lanczos_init(p, ptr, size, 0)
+        assert ei.value.status == binding.DL_ERR_WORKSPACE

@@ -1,0 +1,315 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle.
+
+FP64 results must match the oracle to 1e-10 relative L2 (the bound stated for
+the FP64 propagator); single-operator applications to 1e-13.  Every case
+prints its name before touching the GPU.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import harness as hz
+from paper_1407_7370_amd import packets
+
+pytestmark = pytest.mark.gpu
+
+C = 137.036
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def Prop(torch_cuda):
+    from paper_1407_7370_amd.binding import Propagator
+    return Propagator
+
+
+def say(msg):
+    print(f"[gpu case] {msg}", flush=True)
+
+
+def gpu_run(torch, Prop, prob, m, prec, psi0, t0, dt, n, **kw):
+    prop = Prop(prob, m, prec, **kw)
+    psi = torch.from_numpy(np.ascontiguousarray(psi0)).to("cuda")
+    st = prop.step(psi, t0, dt, n)
+    out = psi.cpu().numpy()
+    prop.close()
+    return out, st
+
+
+def box(nx, ny, bc, lo=-6.0, hi=6.0, **kw):
+    p = dict(nx=nx, ny=ny, x_min=lo, x_max=hi, y_min=lo * 0.9, y_max=hi * 1.2, bc_x=bc, bc_y=bc,
+             mass=1.0, c=C, charge=-1.0, bz=0.0, pot_kind=0, pot_z=0.0, pot_a=0.0, pulse_kind=0,
+             pulse_e=(0.0, 0.0), a0=0.0, omega=0.0, t_pulse=1.0, coef=None)
+    p.update(kw)
+    return p
+
+
+# ---------------------------------------------------------------------------
+# Single application of H
+# ---------------------------------------------------------------------------
+APPLY_CASES = {
+    "free_64_periodic": (box(64, 64, 1), 0.0),
+    "ragged_131x77_dirichlet_b_soft": (box(131, 77, 0, bz=0.8, pot_kind=1, pot_z=1.0, pot_a=1.0), 0.0),
+    "ragged_61x5_periodic_b": (box(61, 5, 1, bz=-1.3), 0.0),
+    "tiny_3x3_dirichlet": (box(3, 3, 0, bz=0.4), 0.0),
+    "tiny_4x3_periodic": (box(4, 3, 1, pot_kind=2, pot_z=2.0), 0.0),
+    "x_periodic_y_dirichlet_200x130": (dict(box(200, 130, 0, bz=0.3), bc_x=1), 0.0),
+    "laser_t": (dict(box(96, 70, 0), pulse_kind=1, pulse_e=(0.6, 0.8), a0=50.0, omega=1.0,
+                     t_pulse=0.1), 0.037),
+    "fourier_t": (dict(box(70, 96, 0), pulse_kind=2, t_pulse=2.0,
+                       coef=np.random.default_rng(3).uniform(-20, 20, 16)), 0.71),
+    "one_strip_boundary_124x200": (box(124, 200, 0, bz=0.5), 0.0),
+}
+
+
+@pytest.mark.parametrize("case", sorted(APPLY_CASES))
+def test_apply_vs_oracle(torch_cuda, Prop, orc, case):
+    prob, t = APPLY_CASES[case]
+    say(f"apply {case} {prob['nx']}x{prob['ny']}")
+    torch = torch_cuda
+    psi = packets.random_spinor(prob, 5)
+    prop = Prop(prob, 4, "fp64")
+    y = prop.apply(torch.from_numpy(psi).cuda(), t).cpu().numpy()
+    prop.close()
+    ref = orc.apply_h(prob, psi, orc.pulse(prob, t))
+    assert np.max(np.abs(y - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+def test_apply_potential_table(torch_cuda, Prop, orc):
+    prob = box(90, 66, 0, bz=0.2)
+    say("apply potential table 90x66")
+    vt = np.random.default_rng(1).standard_normal((66, 90))
+    psi = packets.random_spinor(prob, 6)
+    prop = Prop(prob, 4, "fp64", v_table=vt)
+    y = prop.apply(torch_cuda.from_numpy(psi).cuda(), 0.0).cpu().numpy()
+    prop.close()
+    ref = orc.apply_h(dict(prob, v_table=vt), psi)
+    assert np.max(np.abs(y - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+# ---------------------------------------------------------------------------
+# Time steps, FP64
+# ---------------------------------------------------------------------------
+def test_free_packet_64_full(torch_cuda, Prop, orc):
+    cfg = packets.free_packet_64(seed=0)
+    say("free packet 64x64 periodic m=10 100 steps fp64")
+    prob = cfg["problem"]
+    psi0 = packets.initial_state(cfg)
+    got, st = gpu_run(torch_cuda, Prop, prob, cfg["m"], "fp64", psi0, 0.0, cfg["dt"], cfg["steps"])
+    ref, rst = orc.propagate(prob, psi0, 0.0, cfg["dt"], cfg["steps"], cfg["m"])
+    assert hz.rel_l2(got, ref) <= 1e-10
+    assert np.array_equal(st["k_eff"], rst["k_eff"])
+    assert np.allclose(st["norm2"], rst["norm2"], rtol=1e-12)
+    # also the exact lattice solution
+    assert hz.rel_l2(got, hz.free_propagate_fft(prob, psi0, cfg["steps"] * cfg["dt"])) <= 1e-10
+
+
+@pytest.mark.parametrize("n", [96, 160])
+def test_landau_softcore_reduced(torch_cuda, Prop, orc, n):
+    cfg = packets.landau_softcore_1024()
+    cfg = packets.with_grid(cfg, n)
+    prob = dict(cfg["problem"], ny=n - 27)  # ragged, non-square
+    say(f"B + soft-core Dirichlet {prob['nx']}x{prob['ny']} m=20 40 steps fp64")
+    psi0 = packets.gaussian_packet(prob, cfg["sigma"], (0.0, 0.0))
+    got, st = gpu_run(torch_cuda, Prop, prob, cfg["m"], "fp64", psi0, 0.0, cfg["dt"], 40)
+    ref, rst = orc.propagate(prob, psi0, 0.0, cfg["dt"], 40, cfg["m"])
+    assert hz.rel_l2(got, ref) <= 1e-10
+    assert np.array_equal(st["k_eff"], rst["k_eff"])
+
+
+def test_landau_softcore_full_grid(torch_cuda, Prop, orc):
+    cfg = packets.landau_softcore_1024()
+    say("B + soft-core Dirichlet 1024x1024 m=20 3 steps fp64 (full grid)")
+    prob = cfg["problem"]
+    psi0 = packets.initial_state(cfg)
+    got, st = gpu_run(torch_cuda, Prop, prob, cfg["m"], "fp64", psi0, 0.0, cfg["dt"], 3)
+    ref, _ = orc.propagate(prob, psi0, 0.0, cfg["dt"], 3, cfg["m"])
+    assert hz.rel_l2(got, ref) <= 1e-10
+
+
+@pytest.mark.parametrize("n", [128, 250])
+def test_laser_reduced_fp64(torch_cuda, Prop, orc, n):
+    cfg = packets.with_grid(packets.laser_4096(precision="fp64"), n)
+    prob = dict(cfg["problem"], t_pulse=40 * cfg["dt"])
+    say(f"laser pulse Dirichlet {n}x{n} m=16 40 steps fp64")
+    psi0 = packets.initial_state(cfg)
+    got, _ = gpu_run(torch_cuda, Prop, prob, cfg["m"], "fp64", psi0, 0.0, cfg["dt"], 40)
+    ref, _ = orc.propagate(prob, psi0, 0.0, cfg["dt"], 40, cfg["m"])
+    assert hz.rel_l2(got, ref) <= 1e-10
+
+
+def test_fourier_pulse_reduced_fp64(torch_cuda, Prop, orc):
+    cfg = packets.with_grid(packets.fourier_pulse_512(), 100)
+    prob = dict(cfg["problem"], t_pulse=0.06)
+    say("Fourier pulse Dirichlet 100x100 m=12 80 steps fp64")
+    psi0 = packets.initial_state(cfg)
+    got, _ = gpu_run(torch_cuda, Prop, prob, cfg["m"], "fp64", psi0, 0.0, cfg["dt"], 80)
+    ref, _ = orc.propagate(prob, psi0, 0.0, cfg["dt"], 80, cfg["m"])
+    assert hz.rel_l2(got, ref) <= 1e-10
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 5])
+def test_small_krylov_dims(torch_cuda, Prop, orc, m):
+    prob = box(70, 45, 0, bz=0.7, pot_kind=1, pot_z=1.0, pot_a=1.0)
+    say(f"small Krylov m={m} 70x45")
+    psi0 = packets.gaussian_packet(prob, 1.5, (2.0, -1.0))
+    got, st = gpu_run(torch_cuda, Prop, prob, m, "fp64", psi0, 0.0, 2e-4, 5)
+    ref, rst = orc.propagate(prob, psi0, 0.0, 2e-4, 5, m)
+    assert hz.rel_l2(got, ref) <= 1e-10
+    assert np.allclose(st["err_est"], rst["err_est"], rtol=1e-6, atol=1e-300)
+
+
+def test_backward_returns(torch_cuda, Prop, orc):
+    cfg = packets.with_grid(packets.laser_4096(precision="fp64"), 120)
+    prob = dict(cfg["problem"], t_pulse=0.01, a0=300.0)
+    say("time reversal 120x120 laser 50+50 steps")
+    torch = torch_cuda
+    psi0 = packets.initial_state(cfg)
+    prop = Prop(prob, 16, "fp64")
+    psi = torch.from_numpy(psi0).cuda()
+    prop.step(psi, 0.0, 2e-4, 50)
+    mid = psi.cpu().numpy()
+    prop.step(psi, 50 * 2e-4, -2e-4, 50)
+    back = psi.cpu().numpy()
+    prop.close()
+    assert hz.rel_l2(mid, psi0) > 1e-3
+    assert hz.rel_l2(back, psi0) <= 1e-11
+
+
+# ---------------------------------------------------------------------------
+# Determinism and resume
+# ---------------------------------------------------------------------------
+def test_bitwise_repeat_and_resume(torch_cuda, Prop):
+    cfg = packets.with_grid(packets.landau_softcore_1024(), 200)
+    prob = cfg["problem"]
+    say("determinism 200x200 B+soft-core 20 steps: repeat and 7+13 resume")
+    torch = torch_cuda
+    psi0 = packets.initial_state(cfg)
+    outs = []
+    for split in (None, None, 7):
+        prop = Prop(prob, 20, "fp64")
+        psi = torch.from_numpy(psi0).cuda()
+        if split is None:
+            prop.step(psi, 0.0, 5e-4, 20)
+        else:
+            prop.step(psi, 0.0, 5e-4, split)
+            prop.step(psi, split * 5e-4, 5e-4, 20 - split)
+        outs.append(psi.cpu().numpy())
+        prop.close()
+    assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(outs[0], outs[2])
+
+
+# ---------------------------------------------------------------------------
+# Degenerate cases
+# ---------------------------------------------------------------------------
+def test_breakdown_plane_wave_and_zero(torch_cuda, Prop, orc):
+    torch = torch_cuda
+    prob = box(8, 8, 1, lo=-0.04, hi=0.04)
+    prob["y_min"], prob["y_max"] = -0.04, 0.04
+    x, y, hx, hy = hz.axes(prob)
+    X, Y = np.meshgrid(x, y)
+    psi0 = np.stack([np.exp(1j * 2 * math.pi * 2 / 0.08 * X), np.zeros_like(X, dtype=complex)])
+    say("breakdown: periodic plane wave 8x8 (k_eff 2)")
+    got, st = gpu_run(torch, Prop, prob, 10, "fp64", psi0, 0.0, 1e-3, 3)
+    ref, rst = orc.propagate(prob, psi0, 0.0, 1e-3, 3, 10)
+    assert np.all(st["k_eff"] == 2) and np.all(rst["k_eff"] == 2)
+    assert hz.rel_l2(got, ref) <= 1e-12
+    say("zero state 8x8")
+    z, st = gpu_run(torch, Prop, prob, 10, "fp64", np.zeros_like(psi0), 0.0, 1e-3, 3)
+    assert np.all(z == 0) and np.all(st["k_eff"] == 0) and np.all(st["norm2"] == 0)
+    say("uniform upper spinor 8x8 periodic: exact eigenvector, k_eff 1")
+    const = np.stack([np.ones_like(X, dtype=complex), np.zeros_like(X, dtype=complex)])
+    got, st = gpu_run(torch, Prop, prob, 6, "fp64", const, 0.0, 1e-3, 2)
+    assert np.all(st["k_eff"] == 1)
+    assert np.allclose(got, const * np.exp(-2j * 1e-3 * C * C), atol=1e-12)
+
+
+def test_nonfinite_input(torch_cuda, Prop):
+    from paper_1407_7370_amd import binding
+    torch = torch_cuda
+    prob = box(40, 40, 0)
+    say("non-finite input 40x40")
+    psi0 = packets.gaussian_packet(prob, 1.0, (0.0, 0.0))
+    psi0[1, 20, 20] = np.nan
+    prop = Prop(prob, 8, "fp64")
+    psi = torch.from_numpy(psi0).cuda()
+    with pytest.raises(binding.DlError) as ei:
+        prop.step(psi, 0.0, 1e-3, 4)
+    assert ei.value.status == binding.DL_ERR_NONFINITE
+    # nothing completed: psi still holds the input
+    back = psi.cpu().numpy()
+    assert np.array_equal(np.isnan(back), np.isnan(psi0))
+    assert np.array_equal(back[~np.isnan(back)], psi0[~np.isnan(psi0)])
+    prop.close()
+
+
+def test_invalid_calls(torch_cuda, Prop):
+    from paper_1407_7370_amd import binding
+    torch = torch_cuda
+    prob = box(16, 16, 0)
+    say("invalid calls 16x16")
+    prop = Prop(prob, 4, "fp64")
+    psi = torch.zeros((2, 16, 16), dtype=torch.complex128, device="cuda")
+    for dt in (0.0, float("nan")):
+        with pytest.raises(binding.DlError) as ei:
+            prop.step(psi, 0.0, dt, 1)
+        assert ei.value.status == binding.DL_ERR_INVALID
+    with pytest.raises(binding.DlError) as ei:
+        prop.step(psi, 0.0, 1e-3, -1)
+    assert ei.value.status == binding.DL_ERR_INVALID
+    with pytest.raises(binding.DlError) as ei:
+        prop.eigen(psi, 10, -1.0, 1.0, 1e-6, reorth=True)
+    assert ei.value.status in (binding.DL_ERR_UNSUPPORTED, binding.DL_ERR_WORKSPACE)
+    import ctypes
+    loss = ctypes.c_double(0)
+    grad = (ctypes.c_double * 16)()
+    st = binding.dirac_lanczos_adjoint(prop.ctx, psi.data_ptr(), 0.0, 1e-3, 10, 5, 0,
+                                       ctypes.byref(loss), grad)
+    assert st == binding.DL_ERR_UNSUPPORTED
+    prop.close()
+
+
+# ---------------------------------------------------------------------------
+# Mixed precision
+# ---------------------------------------------------------------------------
+def test_mixed_vs_fp64_reduced(torch_cuda, Prop, orc):
+    cfg = packets.with_grid(packets.laser_4096(), 256)
+    prob = dict(cfg["problem"], t_pulse=100 * cfg["dt"])
+    say("mixed vs fp64 laser 256x256 m=16 100 steps")
+    psi0 = packets.initial_state(cfg)
+    mx, smx = gpu_run(torch_cuda, Prop, prob, 16, "mixed", psi0, 0.0, cfg["dt"], 100)
+    ref, _ = orc.propagate(prob, psi0, 0.0, cfg["dt"], 100, 16)
+    err = hz.rel_l2(mx, ref)
+    print(f"mixed rel-L2 vs oracle after 100 steps: {err:.3e}", flush=True)
+    assert err <= 1e-6
+    assert np.all(smx["k_eff"] == 16)
+
+
+# ---------------------------------------------------------------------------
+# Eigenvalue mode
+# ---------------------------------------------------------------------------
+def test_eigen_landau_vs_oracle(torch_cuda, Prop, orc):
+    torch = torch_cuda
+    mc2 = C * C
+    prob = dict(nx=64, ny=64, x_min=-5.0, x_max=5.0, y_min=-5.0, y_max=5.0, bc_x=0, bc_y=0,
+                mass=1.0, c=C, charge=-1.0, bz=2.0, pot_kind=0, pot_z=0.0, pot_a=0.0,
+                pulse_kind=0, pulse_e=(0.0, 0.0), a0=0.0, omega=0.0, t_pulse=1.0, coef=None)
+    say("eigen Landau 64x64 K=200")
+    psi0 = packets.gaussian_packet(prob, 0.9, (0.0, 0.0))
+    prop = Prop(prob, 1, "fp64", k_eigen=200)
+    ev, bd = prop.eigen(torch.from_numpy(psi0).cuda(), 200, mc2 - 0.5, mc2 + 9.0, 1e-5)
+    prop.close()
+    rev, rbd, _ = orc.eigen(prob, psi0, 200, mc2 - 0.5, mc2 + 9.0, 1e-5)
+    assert len(ev) >= 1 and len(ev) == len(rev)
+    assert np.allclose(ev, rev, atol=1e-8)
+    # first Landau level of this lattice (h = 10/64) within its O(h^2) error
+    lvl = hz.landau_levels(prob, 1)[0]
+    assert abs(ev[0] - lvl) < 0.01 * (lvl - mc2)
