@@ -175,6 +175,24 @@ dl_status dirac_lanczos_adjoint(dl_context *ctx, const void *psi0, double t0, do
                                 int32_t n_steps, int32_t ckpt_every, int32_t loss_kind,
                                 double *loss, double *grad);
 
+/*
+ * Kernel timing with HIP events recorded on the context's stream around every
+ * launch of dirac_lanczos_step (a diagnostic for roofline measurements).
+ * Classes: 0 first Lanczos iteration; 1 recurrence sweeps whose operands are
+ * all Krylov vectors (iterations >= 4, each reads u_{p-1}, u_{p-2} and writes
+ * u_p); 2 recurrence sweeps that read psi (iterations 2 and 3); 3 tridiagonal
+ * exponential; 4 recombination.
+ * enable = 1 clears the accumulators and starts recording, enable = 0 stops.
+ * out (HOST, may be NULL) receives the accumulated counts and milliseconds;
+ * reading them waits for the recorded events.
+ */
+typedef struct {
+    int64_t launches[5];
+    double total_ms[5];
+} dl_timing;
+
+dl_status dirac_lanczos_timing(dl_context *ctx, int32_t enable, dl_timing *out);
+
 /* Free the host context (the caller frees its own device buffers). */
 dl_status dirac_lanczos_destroy(dl_context *ctx);
 

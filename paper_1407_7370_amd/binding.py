@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "DL_OK", 1: "DL_ERR_INVALID", 2: "DL_ERR_DEVICE", 3: "DL_ERR_
 # every symbol declared in include/dirac_lanczos.h
 EXPORTS = ("dirac_lanczos_workspace_bytes", "dirac_lanczos_init", "dirac_lanczos_apply",
            "dirac_lanczos_step", "dirac_lanczos_eigen", "dirac_lanczos_adjoint",
-           "dirac_lanczos_destroy", "dirac_lanczos_last_error")
+           "dirac_lanczos_timing", "dirac_lanczos_destroy", "dirac_lanczos_last_error")
 
 
 class DlParams(ctypes.Structure):
@@ -48,6 +48,13 @@ class DlParams(ctypes.Structure):
 class DlStepStat(ctypes.Structure):
     _fields_ = [("k_eff", ctypes.c_int32), ("err_est", ctypes.c_double),
                 ("cum_bound", ctypes.c_double), ("norm2", ctypes.c_double)]
+
+
+class DlTiming(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64 * 5), ("total_ms", ctypes.c_double * 5)]
+
+
+TIMING_CLASSES = ("first", "recur_basis", "recur_psi", "tridiag", "recombine")
 
 
 class DlError(RuntimeError):
@@ -87,6 +94,8 @@ def load_library():
     lib.dirac_lanczos_adjoint.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                           ctypes.c_int32, ctypes.c_int32, D, D]
     lib.dirac_lanczos_adjoint.restype = ctypes.c_int
+    lib.dirac_lanczos_timing.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(DlTiming)]
+    lib.dirac_lanczos_timing.restype = ctypes.c_int
     lib.dirac_lanczos_destroy.argtypes = [vp]
     lib.dirac_lanczos_destroy.restype = ctypes.c_int
     lib.dirac_lanczos_last_error.argtypes = [vp]
@@ -164,6 +173,10 @@ def dirac_lanczos_adjoint(ctx, psi_ptr: int, t0: float, dt: float, n_steps: int,
                           loss_kind: int, loss, grad) -> int:
     return load_library().dirac_lanczos_adjoint(ctx, ctypes.c_void_p(psi_ptr), t0, dt, n_steps,
                                                 ckpt_every, loss_kind, loss, grad)
+
+
+def dirac_lanczos_timing(ctx, enable: int, out=None) -> int:
+    return load_library().dirac_lanczos_timing(ctx, enable, out)
 
 
 def dirac_lanczos_destroy(ctx) -> int:
@@ -246,6 +259,13 @@ class Propagator:
                                  n_wanted, ev, bd, ctypes.byref(nf))
         _check(self.lib, self.ctx, st)
         return np.array(ev[:nf.value]), np.array(bd[:nf.value])
+
+    def timing(self, enable: bool):
+        """Start (True) or stop (False) event timing; returns the accumulated
+        {class: (launches, total_ms)} collected so far."""
+        t = DlTiming()
+        _check(self.lib, self.ctx, dirac_lanczos_timing(self.ctx, int(bool(enable)), ctypes.byref(t)))
+        return {name: (int(t.launches[i]), float(t.total_ms[i])) for i, name in enumerate(TIMING_CLASSES)}
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -237,6 +237,57 @@ struct dl_context {
     std::vector<double> host_fields;
     std::vector<dl::StepStat> host_stats;
     std::string err;
+    // event timing (dirac_lanczos_timing)
+    bool timing = false;
+    std::vector<hipEvent_t> ev0, ev1;
+    std::vector<int> ev_cls;
+    size_t ev_used = 0;
+    int64_t t_launches[5] = {0, 0, 0, 0, 0};
+    double t_ms[5] = {0, 0, 0, 0, 0};
+
+    ~dl_context()
+    {
+        for (hipEvent_t e : ev0) (void)hipEventDestroy(e);
+        for (hipEvent_t e : ev1) (void)hipEventDestroy(e);
+    }
+
+    // Fold the recorded event pairs into the per-class totals.
+    hipError_t harvest()
+    {
+        if (ev_used == 0) return hipSuccess;
+        hipError_t e = hipEventSynchronize(ev1[ev_used - 1]);
+        if (e != hipSuccess) return e;
+        for (size_t i = 0; i < ev_used; ++i) {
+            float ms = 0.0f;
+            e = hipEventElapsedTime(&ms, ev0[i], ev1[i]);
+            if (e != hipSuccess) return e;
+            t_ms[ev_cls[i]] += ms;
+            t_launches[ev_cls[i]] += 1;
+        }
+        ev_used = 0;
+        return hipSuccess;
+    }
+
+    // Launch `fn` bracketed by an event pair when timing is on.
+    template <class F>
+    hipError_t timed(int cls, F &&fn)
+    {
+        if (!timing) {
+            fn();
+            return hipSuccess;
+        }
+        if (ev_used == ev0.size()) {
+            hipError_t e = harvest();
+            if (e != hipSuccess) return e;
+        }
+        hipError_t e = hipEventRecord(ev0[ev_used], stream);
+        if (e != hipSuccess) return e;
+        fn();
+        e = hipEventRecord(ev1[ev_used], stream);
+        if (e != hipSuccess) return e;
+        ev_cls[ev_used++] = cls;
+        return hipSuccess;
+    }
 
     dl_status fail(dl_status s, const std::string &msg)
     {
@@ -425,7 +476,9 @@ dl_status dirac_lanczos_step(dl_context *ctx, void *psi_v, double t0, double dt,
             double2 *in = (g % 2 == 0) ? psi : state;
             double2 *out = (g % 2 == 0) ? state : psi;
             const double *fp = fields + 2 * i;
-            dl::launch_first(op, t1, in, fp, alpha, gamma, sc, partials, m, st);
+            DL_HIP(ctx, ctx->timed(0, [&] {
+                dl::launch_first(op, t1, in, fp, alpha, gamma, sc, partials, m, st);
+            }));
             for (int pp = 2; pp <= m; ++pp) {
                 dl::PassArgs a{};
                 a.op = op;
@@ -441,9 +494,9 @@ dl_status dirac_lanczos_step(dl_context *ctx, void *psi_v, double t0, double dt,
                 a.partials = partials;
                 a.pass = pp;
                 a.m = m;
-                dl::launch_recur(a, mixed, st);
+                DL_HIP(ctx, ctx->timed(pp >= 4 ? 1 : 2, [&] { dl::launch_recur(a, mixed, st); }));
             }
-            dl::launch_tridiag(alpha, gamma, sc, st);
+            DL_HIP(ctx, ctx->timed(3, [&] { dl::launch_tridiag(alpha, gamma, sc, st); }));
             dl::RecArgs r{};
             r.op = op;
             r.t = t1;
@@ -457,7 +510,7 @@ dl_status dirac_lanczos_step(dl_context *ctx, void *psi_v, double t0, double dt,
             r.sc = sc;
             r.partials = partials;
             r.stat = dstats + i;
-            dl::launch_recombine(r, mixed, st);
+            DL_HIP(ctx, ctx->timed(4, [&] { dl::launch_recombine(r, mixed, st); }));
         }
         DL_HIP(ctx, hipGetLastError());
         dl::Scalars hs;
@@ -596,6 +649,38 @@ dl_status dirac_lanczos_adjoint(dl_context *ctx, const void *, double, double, i
 {
     if (!ctx) return DL_ERR_INVALID;
     return ctx->fail(DL_ERR_UNSUPPORTED, "adjoint propagation is not provided by this build");
+}
+
+dl_status dirac_lanczos_timing(dl_context *ctx, int32_t enable, dl_timing *out)
+{
+    if (!ctx) return DL_ERR_INVALID;
+    DL_HIP(ctx, ctx->harvest());
+    if (out) {
+        for (int i = 0; i < 5; ++i) {
+            out->launches[i] = ctx->t_launches[i];
+            out->total_ms[i] = ctx->t_ms[i];
+        }
+    }
+    if (enable) {
+        if (ctx->ev0.empty()) {
+            const size_t n = 512;
+            ctx->ev0.resize(n);
+            ctx->ev1.resize(n);
+            ctx->ev_cls.resize(n);
+            for (size_t i = 0; i < n; ++i) {
+                DL_HIP(ctx, hipEventCreate(&ctx->ev0[i]));
+                DL_HIP(ctx, hipEventCreate(&ctx->ev1[i]));
+            }
+        }
+        for (int i = 0; i < 5; ++i) {
+            ctx->t_launches[i] = 0;
+            ctx->t_ms[i] = 0.0;
+        }
+        ctx->timing = true;
+    } else {
+        ctx->timing = false;
+    }
+    return DL_OK;
 }
 
 dl_status dirac_lanczos_destroy(dl_context *ctx)
