@@ -9,11 +9,15 @@
 
 namespace dl {
 
-constexpr int kMaxM = 64;        // largest Krylov dimension of a time step
-constexpr int kBlock = 256;      // threads per workgroup (four wave64)
+constexpr int kMaxM = 64;         // largest Krylov dimension of a time step
+constexpr int kBlock = 256;       // threads per workgroup (four wave64)
 constexpr int kWaves = kBlock / 64;
-constexpr int kMaxBlocks = 8192; // capacity of the per-workgroup partial-sum table
-constexpr int kChunk = 2048;     // time steps whose fields/stats are staged per batch
+constexpr int kMaxBlocks = 8192;  // capacity of the per-workgroup partial-sum table
+constexpr int kPartialStride = 8; // doubles per workgroup in the partial-sum table
+constexpr int kChunk = 2048;      // time steps whose fields/stats are staged per batch
+// Extra bytes between consecutive Krylov vectors so that the vectors a sweep
+// streams concurrently do not sit a power of two apart in HBM.
+constexpr size_t kVecPad = 4096 + 768;
 
 // Device-resident scalars of the running Lanczos step.  Written only by the
 // last workgroup of a sweep (deterministic fixed-order reductions) and by the
@@ -22,6 +26,8 @@ struct Scalars {
     double coef[2 * (kMaxM + 2)];  // c_j / gamma_j (re, im) for the recombination, j = 1..k
     double scale;                  // running max of |alpha_j|, beta_j (breakdown test)
     double cabs_k;                 // |c_k|, input of the error estimate
+    double beta_k;                 // beta_k of the step (error estimate)
+    double sigma;                  // spectral shift of the sweeps: they run on A - sigma I
     int kstop;                     // sweeps with index > kstop do nothing this step
     int keff;                      // Krylov dimension in use (set at the end of the recurrence)
     int status;                    // 0 ok, 3 non-finite (whole call aborted)
@@ -58,12 +64,17 @@ struct Tiles {
     int halo, own, nstrips, nchunks, rows, nblocks;
 };
 
+// Vector layouts.  The state psi (and its ping-pong partner) uses the caller's
+// layout: two planes of nx*ny complex128 values.  Krylov vectors u_2.. hold
+// both components of a site next to each other ([site][component]), complex64
+// in mixed precision or complex128 in FP64.
+
 // Arguments of a recurrence sweep (Lanczos iteration p >= 2).
 struct PassArgs {
     Op op;
     Tiles t;
-    const void *u1;      // u_{p-1}
-    const void *u2;      // u_{p-2} (unused for p = 2)
+    const void *u1;      // u_{p-1} (psi layout when p == 2)
+    const void *u2;      // u_{p-2} (psi layout when p == 3; unused when p == 2)
     void *uo;            // u_p (written)
     const double *field; // (gx_hom, gy_hom) of this step
     double *alpha;       // alpha[1..]
@@ -74,17 +85,13 @@ struct PassArgs {
     int m;
 };
 
-// Arguments of the recombination sweep.
-struct RecArgs {
-    Op op;
-    Tiles t;
-    const double2 *psi;  // u_1
-    const void *basis;   // u_2..u_m, consecutive vectors of vec_elems elements
-    size_t vec_elems;    // 2*nx*ny
-    double2 *out;        // new state
-    const double *field;
-    const double *alpha;
-    const double *gamma;
+// Arguments of the recombination psi_new = sum_j coef_j u_j (flat streaming).
+struct CombArgs {
+    const double2 *psi;  // u_1 (psi layout)
+    const void *basis;   // u_2..u_m
+    size_t vec_bytes;    // byte stride between consecutive Krylov vectors
+    size_t sites;        // nx*ny
+    double2 *out;        // new state (psi layout)
     Scalars *sc;
     double *partials;
     StepStat *stat;      // entry of this step
@@ -92,14 +99,18 @@ struct RecArgs {
 
 void launch_first(const Op &op, const Tiles &t, const double2 *psi, const double *field,
                   double *alpha, double *gamma, Scalars *sc, double *partials, int m,
-                  hipStream_t st);
+                  int shift, hipStream_t st);
 void launch_recur(const PassArgs &a, bool mixed, hipStream_t st);
-void launch_tridiag(const double *alpha, const double *gamma, Scalars *sc, hipStream_t st);
-void launch_recombine(const RecArgs &a, bool mixed, hipStream_t st);
+void launch_tridiag(const double *alpha, const double *gamma, Scalars *sc, StepStat *stat,
+                    hipStream_t st);
+void launch_combine(const CombArgs &a, bool mixed, int nblocks, hipStream_t st);
 void launch_apply(const Op &op, const Tiles &t, const double2 *x, double2 *y, double gxh,
                   double gyh, hipStream_t st);
 void launch_reset(Scalars *sc, hipStream_t st);
 
 Tiles make_tiles(int nx, int ny, int halo, int target_waves);
+// Resident waves per compute unit of a kernel family: 0 first iteration,
+// 1 recurrence sweep, 2 recombination, 3 apply.
+int sweep_waves_per_cu(int which, bool mixed);
 
 }  // namespace dl

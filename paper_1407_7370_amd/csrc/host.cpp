@@ -32,6 +32,10 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 size_t vec_elems(const dl_params &p) { return (size_t)2 * (size_t)p.nx * (size_t)p.ny; }
 
+// Byte stride between workspace vectors: padded so that vectors streamed
+// together are not a power of two apart.
+size_t vec_stride(size_t n, size_t elem) { return align256(n * elem) + dl::kVecPad; }
+
 // Workspace plan.  Vector region: step mode holds the second state buffer
 // (complex128) and the Krylov vectors u_2..u_m (complex128, or complex64 in
 // mixed precision); eigen mode needs three rolling complex128 vectors.
@@ -48,7 +52,7 @@ Layout plan(const dl_params &p, int mode, int k_eigen)
     L.gamma = off;
     off = align256(off + sizeof(double) * L.ab_len);
     L.partials = off;
-    off = align256(off + sizeof(double) * 4 * kMaxBlocks);
+    off = align256(off + sizeof(double) * dl::kPartialStride * kMaxBlocks);
     L.fields = off;
     off = align256(off + sizeof(double) * 2 * kChunk);
     L.stats = off;
@@ -56,8 +60,8 @@ Layout plan(const dl_params &p, int mode, int k_eigen)
     L.vecs = off;
     const size_t n = vec_elems(p);
     const size_t basis_elem = p.precision == DL_PREC_MIXED ? 8 : 16;
-    size_t step_region = align256(n * 16) + (size_t)(m - 1) * align256(n * basis_elem);
-    size_t eig_region = mode == DL_MODE_EIGEN ? 3 * align256(n * 16) : 0;
+    size_t step_region = align256(n * 16) + (size_t)(m - 1) * vec_stride(n, basis_elem);
+    size_t eig_region = mode == DL_MODE_EIGEN ? 3 * vec_stride(n, 16) : 0;
     off += std::max(step_region, eig_region);
     L.total = off;
     return L;
@@ -233,7 +237,9 @@ struct dl_context {
     char *ws = nullptr;
     size_t ws_bytes = 0;
     Layout L;
-    int target_waves = 4096;
+    int cus = 256;
+    dl::Tiles tiles_first{}, tiles_recur{}, tiles_apply{};
+    int combine_blocks = 1024;
     std::vector<double> host_fields;
     std::vector<dl::StepStat> host_stats;
     std::string err;
@@ -393,7 +399,23 @@ dl_status dirac_lanczos_init(const dl_params *params, void *workspace, size_t ws
     ctx->ws = static_cast<char *>(workspace);
     ctx->ws_bytes = ws_bytes;
     ctx->L = L;
-    ctx->target_waves = 16 * prop.multiProcessorCount;
+    ctx->cus = prop.multiProcessorCount;
+    {
+        // one resident round of waves per sweep (each wave marches its row chunk)
+        const bool mixed = params->precision == DL_PREC_MIXED;
+        const int wf = dl::sweep_waves_per_cu(0, mixed), wr = dl::sweep_waves_per_cu(1, mixed);
+        const int wc = dl::sweep_waves_per_cu(2, mixed), wa = dl::sweep_waves_per_cu(3, mixed);
+        ctx->tiles_first = dl::make_tiles(params->nx, params->ny, 1, wf * ctx->cus);
+        ctx->tiles_recur = dl::make_tiles(params->nx, params->ny, 2, wr * ctx->cus);
+        ctx->tiles_apply = dl::make_tiles(params->nx, params->ny, 1, wa * ctx->cus);
+        const size_t items = vec_elems(*params) / 2;  // one site per thread
+        const size_t need = (items + dl::kBlock - 1) / dl::kBlock;
+        size_t nb = (size_t)(wc / dl::kWaves) * ctx->cus;
+        if (nb > need) nb = need;
+        if (nb < 1) nb = 1;
+        if (nb > (size_t)kMaxBlocks) nb = kMaxBlocks;
+        ctx->combine_blocks = (int)nb;
+    }
     dl::launch_reset(ctx->sc(), ctx->stream);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
@@ -414,8 +436,7 @@ dl_status dirac_lanczos_apply(dl_context *ctx, const void *x, void *y, double t)
     double a[2];
     pulse_now(ctx->p, ctx->coef, t, a);
     const double k = -ctx->p.c * ctx->p.charge;
-    const dl::Tiles tl = dl::make_tiles(ctx->p.nx, ctx->p.ny, 1, ctx->target_waves);
-    dl::launch_apply(op, tl, static_cast<const double2 *>(x), static_cast<double2 *>(y), k * a[0],
+    dl::launch_apply(op, ctx->tiles_apply, static_cast<const double2 *>(x), static_cast<double2 *>(y), k * a[0],
                      k * a[1], ctx->stream);
     DL_HIP(ctx, hipGetLastError());
     return DL_OK;
@@ -446,11 +467,12 @@ dl_status dirac_lanczos_step(dl_context *ctx, void *psi_v, double t0, double dt,
     double2 *psi = static_cast<double2 *>(psi_v);
     double2 *state = reinterpret_cast<double2 *>(ws + L.vecs);
     char *basis = ws + L.vecs + align256(n * 16);
-    auto bvec = [&](int j) -> void * { return basis + (size_t)(j - 2) * align256(n * belem); };
+    const size_t vstride = vec_stride(n, belem);
+    auto bvec = [&](int j) -> void * { return basis + (size_t)(j - 2) * vstride; };
 
     const dl::Op op = ctx->op(dt);
-    const dl::Tiles t1 = dl::make_tiles(p.nx, p.ny, 1, ctx->target_waves);
-    const dl::Tiles t2 = dl::make_tiles(p.nx, p.ny, 2, ctx->target_waves);
+    const dl::Tiles &t1 = ctx->tiles_first;
+    const dl::Tiles &t2 = ctx->tiles_recur;
     const double kf = -dt * p.c * p.charge;
     hipStream_t st = ctx->stream;
 
@@ -477,7 +499,7 @@ dl_status dirac_lanczos_step(dl_context *ctx, void *psi_v, double t0, double dt,
             double2 *out = (g % 2 == 0) ? state : psi;
             const double *fp = fields + 2 * i;
             DL_HIP(ctx, ctx->timed(0, [&] {
-                dl::launch_first(op, t1, in, fp, alpha, gamma, sc, partials, m, st);
+                dl::launch_first(op, t1, in, fp, alpha, gamma, sc, partials, m, 1, st);
             }));
             for (int pp = 2; pp <= m; ++pp) {
                 dl::PassArgs a{};
@@ -496,21 +518,17 @@ dl_status dirac_lanczos_step(dl_context *ctx, void *psi_v, double t0, double dt,
                 a.m = m;
                 DL_HIP(ctx, ctx->timed(pp >= 4 ? 1 : 2, [&] { dl::launch_recur(a, mixed, st); }));
             }
-            DL_HIP(ctx, ctx->timed(3, [&] { dl::launch_tridiag(alpha, gamma, sc, st); }));
-            dl::RecArgs r{};
-            r.op = op;
-            r.t = t1;
+            DL_HIP(ctx, ctx->timed(3, [&] { dl::launch_tridiag(alpha, gamma, sc, dstats + i, st); }));
+            dl::CombArgs r{};
             r.psi = in;
             r.basis = basis;
-            r.vec_elems = align256(n * belem) / belem;
+            r.vec_bytes = vstride;
+            r.sites = n / 2;
             r.out = out;
-            r.field = fp;
-            r.alpha = alpha;
-            r.gamma = gamma;
             r.sc = sc;
             r.partials = partials;
             r.stat = dstats + i;
-            DL_HIP(ctx, ctx->timed(4, [&] { dl::launch_recombine(r, mixed, st); }));
+            DL_HIP(ctx, ctx->timed(4, [&] { dl::launch_combine(r, mixed, ctx->combine_blocks, st); }));
         }
         DL_HIP(ctx, hipGetLastError());
         dl::Scalars hs;
@@ -575,17 +593,17 @@ dl_status dirac_lanczos_eigen(dl_context *ctx, const void *psi0, int32_t k_max, 
     double *partials = reinterpret_cast<double *>(ws + E.partials);
     double *fields = reinterpret_cast<double *>(ws + E.fields);
     double2 *v[3];
-    for (int i = 0; i < 3; ++i) v[i] = reinterpret_cast<double2 *>(ws + E.vecs + i * align256(n * 16));
+    for (int i = 0; i < 3; ++i) v[i] = reinterpret_cast<double2 *>(ws + E.vecs + i * vec_stride(n, 16));
     hipStream_t st = ctx->stream;
     const dl::Op op = ctx->op(1.0);
-    const dl::Tiles t1 = dl::make_tiles(p.nx, p.ny, 1, ctx->target_waves);
-    const dl::Tiles t2 = dl::make_tiles(p.nx, p.ny, 2, ctx->target_waves);
+    const dl::Tiles &t1 = ctx->tiles_first;
+    const dl::Tiles &t2 = ctx->tiles_recur;
     const double zero[2] = {0.0, 0.0};
     DL_HIP(ctx, hipMemcpyAsync(fields, zero, sizeof(zero), hipMemcpyHostToDevice, st));
     DL_HIP(ctx, hipMemcpyAsync(v[1], psi0, n * 16, hipMemcpyDeviceToDevice, st));
     dl::launch_reset(sc, st);
     const int K1 = k_max + 1;  // the extra iteration yields beta_k for the bounds
-    dl::launch_first(op, t1, v[1], fields, alpha, gamma, sc, partials, K1, st);
+    dl::launch_first(op, t1, v[1], fields, alpha, gamma, sc, partials, K1, 0, st);
     for (int pp = 2; pp <= K1; ++pp) {
         dl::PassArgs a{};
         a.op = op;

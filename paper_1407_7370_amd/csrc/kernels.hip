@@ -1,15 +1,17 @@
 // gfx950 kernels of the Lanczos short-time propagator for the 2D Dirac
 // equation (Beerwerth & Bauke, arXiv:1407.7370).
 //
-// Layout: a spinor is two planes (components) of ny rows of nx complex values,
-// x fastest.  Every sweep kernel maps one wave64 to a strip of columns and a
-// chunk of rows and marches down the rows: lane l holds column
-// strip*own - halo + l, neighbours in x come from the adjacent lanes through
-// DPP wave rotations, neighbours in y from a three-row register ring.  No LDS
-// tile and no barrier is needed inside the march; the `halo` edge lanes of a
-// wave only feed their neighbours.  Reductions are per-lane FP64 sums folded
-// by a fixed butterfly, per workgroup, and finally by the last workgroup to
-// finish in fixed order, so results are bitwise reproducible.
+// Stencil sweeps.  One wave64 owns a strip of columns and a chunk of rows and
+// marches down the rows: lane l holds column strip*own - halo + l, neighbours
+// in x come from the adjacent lanes through DPP wave rotations, neighbours in
+// y from a register ring of the last rows, and the rows ahead sit in a
+// register FIFO of loads in flight.  The march is unrolled by four so that
+// every ring and FIFO slot is a fixed register (no moves).  Row addresses are
+// scalar (one base per row) plus a fixed 32-bit lane offset.  No LDS tile and
+// no barrier is needed inside the march; the `halo` edge lanes of a wave only
+// feed their neighbours.  Reductions are per-lane FP64 sums folded by a fixed
+// butterfly, per workgroup, and finally by the last workgroup to finish in
+// fixed order, so results are bitwise reproducible.
 //
 // A sweep p >= 2 fuses one whole Lanczos iteration of Fig. 1 (Sec. 2) into one
 // pass over memory: with u_i = gamma_i q_i (gamma_i = ||u_i|| = beta_{i-1})
@@ -19,15 +21,22 @@
 // from u_{p-1} with a two-site rim), stored, and A u_p is applied on the tile
 // to reduce ||u_p||^2, Re<u_p, A u_p> and Re<u_p, u_{p-1}>.  From these the
 // last workgroup forms gamma_p and alpha_p = Re<q_p, A q_p> - beta_{p-1}
-// Re<q_p, q_{p-1}>, the modified Gram-Schmidt form of Fig. 1.
+// Re<q_p, q_{p-1}>, the modified Gram-Schmidt form of Fig. 1.  The last sweep
+// also reduces ||A u_m||^2 and Re<A u_m, u_{m-1}>, from which beta_m (input of
+// the error estimate eq. matrix_exponential_error) follows without another
+// pass over memory.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "dl_internal.h"
 
 namespace dl {
 namespace {
+
+template <int K>
+using IC = std::integral_constant<int, K>;
 
 struct Sp {
     double r0, i0, r1, i1;  // component 0 (re, im), component 1 (re, im)
@@ -40,15 +49,15 @@ __device__ __forceinline__ Sp sp_zero() { return Sp{0.0, 0.0, 0.0, 0.0}; }
 // that only feed rim lanes whose results are discarded.
 __device__ __forceinline__ double from_left(double v)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x13C, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x13C, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x13C, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x13C, 0xF, 0xF, true);
     return __hiloint2double(hi, lo);
 }
 
 __device__ __forceinline__ double from_right(double v)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x134, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x134, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x134, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x134, 0xF, 0xF, true);
     return __hiloint2double(hi, lo);
 }
 
@@ -62,43 +71,130 @@ __device__ __forceinline__ Sp sp_right(const Sp &s)
     return Sp{from_right(s.r0), from_right(s.i0), from_right(s.r1), from_right(s.i1)};
 }
 
+// One site of a stored vector: both components in the storage type (aligned
+// so that a paired site is one 16-byte access in complex64).
 template <class T>
-struct Vec;
-
-template <>
-struct Vec<double2> {
-    static __device__ __forceinline__ Sp load(const double2 *b, size_t plane, size_t off)
-    {
-        const double2 a = b[off];
-        const double2 c = b[plane + off];
-        return Sp{a.x, a.y, c.x, c.y};
-    }
-    static __device__ __forceinline__ void store(double2 *b, size_t plane, size_t off, const Sp &s)
-    {
-        b[off] = make_double2(s.r0, s.i0);
-        b[plane + off] = make_double2(s.r1, s.i1);
-    }
-    static __device__ __forceinline__ Sp round(const Sp &s) { return s; }
+struct alignas(2 * sizeof(T)) Raw {
+    T a, b;
 };
 
+template <class T>
+__device__ __forceinline__ T tzero();
 template <>
-struct Vec<float2> {
-    static __device__ __forceinline__ Sp load(const float2 *b, size_t plane, size_t off)
+__device__ __forceinline__ double2 tzero<double2>() { return make_double2(0.0, 0.0); }
+template <>
+__device__ __forceinline__ float2 tzero<float2>() { return make_float2(0.0f, 0.0f); }
+
+template <class T>
+__device__ __forceinline__ Raw<T> raw_zero() { return Raw<T>{tzero<T>(), tzero<T>()}; }
+
+template <class T>
+__device__ __forceinline__ Sp to_sp(const Raw<T> &r)
+{
+    return Sp{(double)r.a.x, (double)r.a.y, (double)r.b.x, (double)r.b.y};
+}
+
+// The value that a later sweep reads back from storage of type T.
+template <class T>
+__device__ __forceinline__ Sp stored_value(const Sp &s);
+template <>
+__device__ __forceinline__ Sp stored_value<double2>(const Sp &s) { return s; }
+template <>
+__device__ __forceinline__ Sp stored_value<float2>(const Sp &s)
+{
+    return Sp{(double)(float)s.r0, (double)(float)s.i0, (double)(float)s.r1, (double)(float)s.i1};
+}
+
+template <class T>
+__device__ __forceinline__ Raw<T> to_raw(const Sp &s);
+template <>
+__device__ __forceinline__ Raw<double2> to_raw<double2>(const Sp &s)
+{
+    return Raw<double2>{make_double2(s.r0, s.i0), make_double2(s.r1, s.i1)};
+}
+template <>
+__device__ __forceinline__ Raw<float2> to_raw<float2>(const Sp &s)
+{
+    return Raw<float2>{make_float2((float)s.r0, (float)s.i0), make_float2((float)s.r1, (float)s.i1)};
+}
+
+// Buffer access.  Every row of a vector gets its own buffer descriptor
+// (scalar registers) whose size is the row length, or zero for a row outside a
+// Dirichlet domain; lanes outside the domain use an offset past any row.  The
+// hardware returns zero for such loads and drops such stores, so the domain
+// boundary costs no branches and no register fills.
+typedef int v4i __attribute__((ext_vector_type(4)));
+constexpr uint32_t kOob = 0x80000000u;
+constexpr int kRsrcWord3 = 0x00020000;  // raw 32-bit buffer format (gfx9 family)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const char *p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(p), (short)0, (int)bytes, kRsrcWord3);
+}
+
+template <class X>
+__device__ __forceinline__ X ld16(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    static_assert(sizeof(X) == 16, "16-byte access");
+    return __builtin_bit_cast(X, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+
+template <class X>
+__device__ __forceinline__ void st16(__amdgpu_buffer_rsrc_t r, uint32_t off, const X &v)
+{
+    static_assert(sizeof(X) == 16, "16-byte access");
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4i, v), r, off, 0, 0);
+}
+
+// Vector views.  Planar: the caller's state layout (two component planes of
+// complex128).  Paired: Krylov vectors, both components of a site adjacent.
+struct Planar {
+    using T = double2;
+    const char *base;
+    size_t plane_bytes;
+    uint32_t row_bytes;  // nx * 16
+    __device__ __forceinline__ Raw<double2> load(int jw, bool row_ok, uint32_t off) const
     {
-        const float2 a = b[off];
-        const float2 c = b[plane + off];
-        return Sp{(double)a.x, (double)a.y, (double)c.x, (double)c.y};
+        const char *r = base + (size_t)jw * row_bytes;
+        const uint32_t n = row_ok ? row_bytes : 0u;
+        Raw<double2> v;
+        v.a = ld16<double2>(row_rsrc(r, n), off);
+        v.b = ld16<double2>(row_rsrc(r + plane_bytes, n), off);
+        return v;
     }
-    static __device__ __forceinline__ void store(float2 *b, size_t plane, size_t off, const Sp &s)
+    static __device__ __forceinline__ uint32_t lane_offset(int colw) { return (uint32_t)colw * 16u; }
+};
+
+template <class TT>
+struct Paired {
+    using T = TT;
+    const char *base;
+    uint32_t row_bytes;  // nx * 2 * sizeof(T)
+    __device__ __forceinline__ Raw<T> load(int jw, bool row_ok, uint32_t off) const
     {
-        b[off] = make_float2((float)s.r0, (float)s.i0);
-        b[plane + off] = make_float2((float)s.r1, (float)s.i1);
+        const __amdgpu_buffer_rsrc_t r = row_rsrc(base + (size_t)jw * row_bytes, row_ok ? row_bytes : 0u);
+        if constexpr (sizeof(T) == 8) {
+            return ld16<Raw<T>>(r, off);
+        } else {
+            Raw<T> v;
+            v.a = ld16<T>(r, off);
+            v.b = ld16<T>(r, off + 16u);
+            return v;
+        }
     }
-    // The value that a later sweep will read back from storage.
-    static __device__ __forceinline__ Sp round(const Sp &s)
+    __device__ __forceinline__ void store(int jw, uint32_t off, const Raw<T> &v) const
     {
-        return Sp{(double)(float)s.r0, (double)(float)s.i0, (double)(float)s.r1,
-                  (double)(float)s.i1};
+        const __amdgpu_buffer_rsrc_t r = row_rsrc(base + (size_t)jw * row_bytes, row_bytes);
+        if constexpr (sizeof(T) == 8) {
+            st16(r, off, v);
+        } else {
+            st16(r, off, v.a);
+            st16(r, off + 16u, v.b);
+        }
+    }
+    static __device__ __forceinline__ uint32_t lane_offset(int colw)
+    {
+        return (uint32_t)colw * (uint32_t)(2 * sizeof(T));
     }
 };
 
@@ -132,21 +228,26 @@ struct RowGeo {
 __device__ __forceinline__ RowGeo row_geo(const Op &op, int r)
 {
     RowGeo g;
+    // sweeps touch rows -2 .. ny+1 only (rim of two rows, ny >= 3): one wrap suffices
     const bool inside = r >= 0 && r < op.ny;
-    int jw = r;
-    if (!inside) jw = op.bcy ? ((r % op.ny) + op.ny) % op.ny : 0;
+    int jw = r < 0 ? r + op.ny : (r >= op.ny ? r - op.ny : r);
+    if (!inside && !op.bcy) jw = 0;
     g.jw = jw;
     g.iny = inside || op.bcy;
     g.y = op.ymin + jw * op.hy;
     return g;
 }
 
-template <class T>
-__device__ __forceinline__ Sp load_site(const T *b, const Op &op, const LaneGeo &lg, const RowGeo &rg)
+// Load one site of row r (zero outside a Dirichlet domain; `off` is the lane
+// offset, or kOob for a lane outside the domain).  A row that is not `needed`
+// gets an empty descriptor: the load returns zeros without touching memory,
+// so FIFO refills can be unconditional.
+template <class V>
+__device__ __forceinline__ Raw<typename V::T> load_row(const V &v, const Op &op, uint32_t off, int r,
+                                                       bool needed = true)
 {
-    if (!(lg.inx && rg.iny)) return sp_zero();
-    const size_t plane = (size_t)op.nx * op.ny;
-    return Vec<T>::load(b, plane, (size_t)rg.jw * op.nx + lg.colw);
+    const RowGeo rg = row_geo(op, r);
+    return v.load(rg.jw, rg.iny && needed, off);
 }
 
 // Potential energy (times the operator scale) at a site.
@@ -165,11 +266,12 @@ __device__ __forceinline__ double site_pot(const Op &op, const LaneGeo &lg, cons
 //   (A psi)_1 = (V - mc2) psi_1 + kx (-i)(psi_0[x+1] - psi_0[x-1])
 //               + ky (psi_0[y+1] - psi_0[y-1]) + (gx + i gy) psi_0
 // i.e. c[sigma1 (p_x - qA_x) + sigma2 (p_y - qA_y)] + sigma3 m c^2 + V scaled
-// by s, with gx = -s c q A_x and gy = -s c q A_y (Sec. 3 Hamiltonian).
+// by s, with gx = -s c q A_x and gy = -s c q A_y (Sec. 3 Hamiltonian); the
+// optional shift returns (A - shift I) psi.
 __device__ __forceinline__ Sp hop(const Op &op, const Sp &c, const Sp &l, const Sp &r, const Sp &d,
-                                  const Sp &u, double v, double gx, double gy)
+                                  const Sp &u, double v, double gx, double gy, double shift = 0.0)
 {
-    const double d0 = op.mc2 + v, d1 = v - op.mc2;
+    const double d0 = op.mc2 + v - shift, d1 = v - op.mc2 - shift;
     const double x0r = r.r0 - l.r0, x0i = r.i0 - l.i0, x1r = r.r1 - l.r1, x1i = r.i1 - l.i1;
     const double y0r = u.r0 - d.r0, y0i = u.i0 - d.i0, y1r = u.r1 - d.r1, y1i = u.i1 - d.i1;
     Sp o;
@@ -206,6 +308,7 @@ __device__ __forceinline__ void wave_sum(double (&v)[NV])
 template <int NV>
 __device__ bool grid_reduce(double (&v)[NV], double *partials, unsigned int *ticket, double (&tot)[NV])
 {
+    static_assert(NV <= kPartialStride, "partial table stride");
     __shared__ double red[kWaves][NV];
     __shared__ int last;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -219,7 +322,7 @@ __device__ bool grid_reduce(double (&v)[NV], double *partials, unsigned int *tic
         for (int k = 0; k < NV; ++k) {
             double s = red[0][k];
             for (int i = 1; i < kWaves; ++i) s += red[i][k];
-            partials[(size_t)blockIdx.x * NV + k] = s;
+            partials[(size_t)blockIdx.x * kPartialStride + k] = s;
         }
         __threadfence();
         const unsigned int t = atomicAdd(ticket, 1u);
@@ -233,7 +336,8 @@ __device__ bool grid_reduce(double (&v)[NV], double *partials, unsigned int *tic
     for (int k = 0; k < NV; ++k) s[k] = 0.0;
     for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock)
 #pragma unroll
-        for (int k = 0; k < NV; ++k) s[k] += __builtin_nontemporal_load(&partials[(size_t)b * NV + k]);
+        for (int k = 0; k < NV; ++k)
+            s[k] += __builtin_nontemporal_load(&partials[(size_t)b * kPartialStride + k]);
     wave_sum(s);
     __syncthreads();
     if (lane == 0)
@@ -250,6 +354,8 @@ __device__ bool grid_reduce(double (&v)[NV], double *partials, unsigned int *tic
     return true;
 }
 
+// Tile of this wave.  The wave index is made wave-uniform explicitly so that
+// the whole march (row indices, bounds, addresses) runs on the scalar unit.
 struct WaveTask {
     bool active;
     int strip, y0, y1;
@@ -258,7 +364,8 @@ struct WaveTask {
 __device__ __forceinline__ WaveTask wave_task(const Op &op, const Tiles &t)
 {
     WaveTask w;
-    const int task = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int task = (int)blockIdx.x * kWaves + wave;
     w.active = task < t.nstrips * t.nchunks;
     w.strip = task % t.nstrips;
     const int chunk = task / t.nstrips;
@@ -269,41 +376,61 @@ __device__ __forceinline__ WaveTask wave_task(const Op &op, const Tiles &t)
 }
 
 // ---------------------------------------------------------------------------
-// Lanczos iteration 1: gamma_1 = ||psi||, alpha_1 = Re<psi, A psi>/||psi||^2.
+// Lanczos iteration 1: gamma_1 = ||psi||, alpha_1 = Re<psi, A psi>/||psi||^2,
+// and for m = 1 also beta_1 = ||A q_1 - alpha_1 q_1||.
+// Rows marched: psi rows y0-1 .. y1 (ring slot = row - (y0-1) mod 4).
 // ---------------------------------------------------------------------------
+template <int PF>
 __global__ __launch_bounds__(kBlock) void k_first(Op op, Tiles t, const double2 *__restrict__ psi,
                                                   const double *__restrict__ field, double *alpha,
-                                                  double *gamma, Scalars *sc, double *partials, int m)
+                                                  double *gamma, Scalars *sc, double *partials, int m,
+                                                  int shift)
 {
+    static_assert(4 % PF == 0, "FIFO depth must divide the unroll");
     if (sc->status != 0) return;
     const int lane = threadIdx.x & 63;
     const WaveTask wt = wave_task(op, t);
     const double gxh = field[0], gyh = field[1];
-    double acc[2] = {0.0, 0.0};
+    double acc[3] = {0.0, 0.0, 0.0};
     if (wt.active) {
         const LaneGeo lg = lane_geo(op, t, wt.strip, lane);
         const double gy = gyh - op.bq * lg.x;
-        Sp p0 = sp_zero(), p1 = sp_zero();
-        Sp p2 = load_site(psi, op, lg, row_geo(op, wt.y0 - 1));
-        for (int R = wt.y0; R <= wt.y1; ++R) {
-            p0 = p1;
-            p1 = p2;
-            p2 = load_site(psi, op, lg, row_geo(op, R));
-            if (R - 1 < wt.y0) continue;  // rows y0-1 and y0 are still filling the ring
+        const Planar vin{reinterpret_cast<const char *>(psi), (size_t)op.nx * op.ny * 16,
+                         (uint32_t)op.nx * 16u};
+        const uint32_t off = lg.inx ? Planar::lane_offset(lg.colw) : kOob;
+        const int y0 = wt.y0, y1 = wt.y1, base = y0 - 1;
+        Raw<double2> F[PF];
+#pragma unroll
+        for (int i = 0; i < PF; ++i) F[i] = load_row(vin, op, off, base + i, base + i <= y1);
+        Sp P[4] = {sp_zero(), sp_zero(), sp_zero(), sp_zero()};
+        auto step = [&](auto kc, int R) {
+            constexpr int k = decltype(kc)::value;
+            if (R > y1) return;
+            P[k] = to_sp(F[k % PF]);
+            F[k % PF] = load_row(vin, op, off, R + PF, R + PF <= y1);
+            if (R - 1 < y0) return;
+            const Sp &c = P[(k + 3) & 3];  // row R-1
             const RowGeo rg = row_geo(op, R - 1);
-            const Sp y = hop(op, p1, sp_left(p1), sp_right(p1), p0, p2, site_pot(op, lg, rg),
+            const Sp y = hop(op, c, sp_left(c), sp_right(c), P[(k + 2) & 3], P[k], site_pot(op, lg, rg),
                              gxh + op.bq * rg.y, gy);
             if (lg.own) {
-                acc[0] += sp_norm2(p1);
-                acc[1] += sp_redot(p1, y);
+                acc[0] += sp_norm2(c);
+                acc[1] += sp_redot(c, y);
+                acc[2] += sp_norm2(y);
             }
+        };
+        for (int R = base; R <= y1; R += 4) {
+            step(IC<0>{}, R);
+            step(IC<1>{}, R + 1);
+            step(IC<2>{}, R + 2);
+            step(IC<3>{}, R + 3);
         }
     }
-    double tot[2];
+    double tot[3];
     if (!grid_reduce(acc, partials, &sc->ticket, tot)) return;
     if (threadIdx.x == 0) {
-        const double n = tot[0], a = tot[1];
-        if (!isfinite(n) || !isfinite(a)) {
+        const double n = tot[0], a = tot[1], yy = tot[2];
+        if (!isfinite(n) || !isfinite(a) || !isfinite(yy)) {
             sc->status = 3;
             sc->kstop = -1;
             return;
@@ -311,28 +438,44 @@ __global__ __launch_bounds__(kBlock) void k_first(Op op, Tiles t, const double2 
         if (n == 0.0) {
             gamma[1] = 0.0;
             alpha[1] = 0.0;
+            sc->sigma = 0.0;
             sc->keff = 0;
             sc->kstop = 0;
+            sc->beta_k = 0.0;
             return;
         }
-        gamma[1] = sqrt(n);
-        alpha[1] = a / n;
-        sc->scale = fabs(alpha[1]);
+        const double g = sqrt(n);
+        const double al = a / n;
+        gamma[1] = g;
+        // With the shift on, the later sweeps run on A' = A - alpha_1 I: the same
+        // Krylov space, T' = T - alpha_1 I, so alpha'_1 = 0 and the residuals
+        // A' u - alpha' u no longer cancel by |alpha| / beta.
+        sc->sigma = shift ? al : 0.0;
+        alpha[1] = shift ? 0.0 : al;
+        sc->scale = fabs(al);
         sc->keff = m;
         sc->kstop = m;
+        // ||A psi - alpha_1 psi||^2 = ||A psi||^2 - a^2/n
+        sc->beta_k = sqrt(fmax(yy - a * (a / n), 0.0)) / g;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Lanczos iteration p >= 2 (see the file comment).  T1, T2, TO: storage types
-// of u_{p-1}, u_{p-2}, u_p.
+// Lanczos iteration p >= 2 (see the file comment).  V1, V2: views of u_{p-1},
+// u_{p-2}; TO: storage type of u_p (paired layout); PF: FIFO depth in rows.
+// Rows marched: R = y0-2 .. y1+1 (u_{p-1} row R enters, u_p row R-1 is formed,
+// A u_p row R-2 is applied); ring slot of row r = (r - (y0-2)) mod 4.
 // ---------------------------------------------------------------------------
-template <class T1, class T2, class TO, bool HAS2>
+template <class V1, class V2, class TO, bool HAS2, int PF>
 __global__ __launch_bounds__(kBlock) void k_recur(PassArgs a)
 {
+    static_assert(4 % PF == 0, "FIFO depth must divide the unroll");
+    using T1 = typename V1::T;
+    using T2 = typename V2::T;
     Scalars *sc = a.sc;
     const int p = a.pass;
     if (sc->kstop < p) return;
+    const bool last = (p == a.m);
     const Op &op = a.op;
     const int lane = threadIdx.x & 63;
     const WaveTask wt = wave_task(op, a.t);
@@ -340,269 +483,311 @@ __global__ __launch_bounds__(kBlock) void k_recur(PassArgs a)
     const double inv_g1 = 1.0 / g1;
     const double ca = a.alpha[p - 1] * inv_g1;
     const double cb = HAS2 ? g1 / a.gamma[p - 2] : 0.0;
+    const double sig = sc->sigma;
     const double gxh = a.field[0], gyh = a.field[1];
-    const T1 *__restrict__ u1 = static_cast<const T1 *>(a.u1);
-    const T2 *__restrict__ u2 = static_cast<const T2 *>(a.u2);
-    TO *__restrict__ uo = static_cast<TO *>(a.uo);
-    const size_t plane = (size_t)op.nx * op.ny;
-    double acc[3] = {0.0, 0.0, 0.0};
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (wt.active) {
         const LaneGeo lg = lane_geo(op, a.t, wt.strip, lane);
         const double gy = gyh - op.bq * lg.x;
-        // ring of u_{p-1}: rows R-2, R-1, R; ring of u_p: rows R-3, R-2, R-1
-        Sp p0 = sp_zero(), p1 = sp_zero(), p2 = sp_zero();
-        Sp q0 = sp_zero(), q1 = sp_zero(), q2 = sp_zero();
-        double v_prev = 0.0, v_cur = 0.0;
-        p2 = load_site(u1, op, lg, row_geo(op, wt.y0 - 2));
-        for (int R = wt.y0 - 1; R <= wt.y1 + 1; ++R) {
-            p0 = p1;
-            p1 = p2;
-            p2 = load_site(u1, op, lg, row_geo(op, R));
-            q0 = q1;
-            q1 = q2;
-            v_prev = v_cur;
-            // u_p at row R-1 (rows y0-1 .. y1)
-            if (R >= wt.y0) {
-                const RowGeo rg = row_geo(op, R - 1);
-                v_cur = site_pot(op, lg, rg);
-                const Sp w = hop(op, p1, sp_left(p1), sp_right(p1), p0, p2, v_cur,
-                                 gxh + op.bq * rg.y, gy);
-                Sp o = HAS2 ? load_site(u2, op, lg, rg) : sp_zero();
-                Sp u;
-                u.r0 = inv_g1 * w.r0 - ca * p1.r0 - cb * o.r0;
-                u.i0 = inv_g1 * w.i0 - ca * p1.i0 - cb * o.i0;
-                u.r1 = inv_g1 * w.r1 - ca * p1.r1 - cb * o.r1;
-                u.i1 = inv_g1 * w.i1 - ca * p1.i1 - cb * o.i1;
-                if (!(lg.inx && rg.iny)) u = sp_zero();
-                u = Vec<TO>::round(u);
-                q2 = u;
-                if (lg.own && R - 1 >= wt.y0 && R - 1 < wt.y1)
-                    Vec<TO>::store(uo, plane, (size_t)(R - 1) * op.nx + lg.colw, u);
+        const size_t plane = (size_t)op.nx * op.ny;
+        V1 v1;
+        V2 v2;
+        if constexpr (std::is_same<V1, Planar>::value)
+            v1 = V1{static_cast<const char *>(a.u1), plane * 16, (uint32_t)op.nx * 16u};
+        else
+            v1 = V1{static_cast<const char *>(a.u1), (uint32_t)(op.nx * 2 * sizeof(T1))};
+        if constexpr (std::is_same<V2, Planar>::value)
+            v2 = V2{static_cast<const char *>(a.u2), plane * 16, (uint32_t)op.nx * 16u};
+        else
+            v2 = V2{static_cast<const char *>(a.u2), (uint32_t)(op.nx * 2 * sizeof(T2))};
+        const Paired<TO> vo{static_cast<const char *>(a.uo), (uint32_t)(op.nx * 2 * sizeof(TO))};
+        const uint32_t off1 = lg.inx ? V1::lane_offset(lg.colw) : kOob;
+        const uint32_t off2 = lg.inx ? V2::lane_offset(lg.colw) : kOob;
+        const uint32_t offo = lg.own ? Paired<TO>::lane_offset(lg.colw) : kOob;
+        const int y0 = wt.y0, y1 = wt.y1, base = y0 - 2;
+        // FIFOs: u_{p-1} row r in slot (r-base) mod PF, needed rows y0-2 .. y1+1;
+        //        u_{p-2} row r-1 in the same slot, needed rows y0-1 .. y1.
+        // Slots beyond the needed rows are simply not refilled.
+        Raw<T1> F1[PF];
+        Raw<T2> F2[PF];
+#pragma unroll
+        for (int i = 0; i < PF; ++i) {
+            const int r = base + i;
+            F1[i] = load_row(v1, op, off1, r, r <= y1 + 1);
+            F2[i] = HAS2 ? load_row(v2, op, off2, r - 1, r - 1 >= y0 - 1 && r - 1 <= y1) : raw_zero<T2>();
+        }
+        Sp P[4] = {sp_zero(), sp_zero(), sp_zero(), sp_zero()};  // u_{p-1} rows
+        Sp Q[4] = {sp_zero(), sp_zero(), sp_zero(), sp_zero()};  // u_p rows
+        double Vr[4] = {0.0, 0.0, 0.0, 0.0};                      // potential of the rows
+        auto step = [&](auto kc, int R) {
+            constexpr int k = decltype(kc)::value;
+            if (R > y1 + 1) return;
+            P[k] = to_sp(F1[k % PF]);
+            const Sp o2 = to_sp(F2[k % PF]);
+            {
+                const int r = R + PF;
+                F1[k % PF] = load_row(v1, op, off1, r, r <= y1 + 1);
+                if (HAS2) F2[k % PF] = load_row(v2, op, off2, r - 1, r - 1 <= y1);
             }
-            // A u_p at row R-2 (rows y0 .. y1-1) and the three reductions
-            if (R >= wt.y0 + 2) {
+            // u_p at row R-1 (rows y0-1 .. y1)
+            if (R >= y0) {
+                const RowGeo rg = row_geo(op, R - 1);
+                const Sp &c = P[(k + 3) & 3];
+                const double v = site_pot(op, lg, rg);
+                Vr[(k + 3) & 3] = v;
+                const Sp w = hop(op, c, sp_left(c), sp_right(c), P[(k + 2) & 3], P[k], v,
+                                 gxh + op.bq * rg.y, gy, sig);
+                Sp u;
+                u.r0 = inv_g1 * w.r0 - ca * c.r0 - cb * o2.r0;
+                u.i0 = inv_g1 * w.i0 - ca * c.i0 - cb * o2.i0;
+                u.r1 = inv_g1 * w.r1 - ca * c.r1 - cb * o2.r1;
+                u.i1 = inv_g1 * w.i1 - ca * c.i1 - cb * o2.i1;
+                if (!(lg.inx && rg.iny)) u = sp_zero();
+                const Raw<TO> ur = to_raw<TO>(u);
+                Q[(k + 3) & 3] = to_sp(ur);
+                if (R - 1 >= y0 && R - 1 < y1) vo.store(R - 1, offo, ur);
+            }
+            // A u_p at row R-2 (rows y0 .. y1-1) and the reductions
+            if (R >= y0 + 2) {
                 const RowGeo rg = row_geo(op, R - 2);
-                const Sp y = hop(op, q1, sp_left(q1), sp_right(q1), q0, q2, v_prev,
-                                 gxh + op.bq * rg.y, gy);
+                const Sp &c = Q[(k + 2) & 3];
+                const Sp y = hop(op, c, sp_left(c), sp_right(c), Q[(k + 1) & 3], Q[(k + 3) & 3],
+                                 Vr[(k + 2) & 3], gxh + op.bq * rg.y, gy, sig);
                 if (lg.own) {
-                    acc[0] += sp_norm2(q1);
-                    acc[1] += sp_redot(q1, y);
-                    acc[2] += sp_redot(q1, p0);
+                    const Sp &prev = P[(k + 2) & 3];  // u_{p-1} row R-2
+                    acc[0] += sp_norm2(c);
+                    acc[1] += sp_redot(c, y);
+                    acc[2] += sp_redot(c, prev);
+                    if (last) {
+                        acc[3] += sp_norm2(y);
+                        acc[4] += sp_redot(y, prev);
+                    }
                 }
             }
+        };
+        for (int R = base; R <= y1 + 1; R += 4) {
+            step(IC<0>{}, R);
+            step(IC<1>{}, R + 1);
+            step(IC<2>{}, R + 2);
+            step(IC<3>{}, R + 3);
         }
     }
-    double tot[3];
+    double tot[5];
     if (!grid_reduce(acc, a.partials, &sc->ticket, tot)) return;
     if (threadIdx.x == 0) {
-        const double n = tot[0], an = tot[1], o = tot[2];
-        if (!isfinite(n) || !isfinite(an) || !isfinite(o)) {
+        const double n = tot[0], an = tot[1], o = tot[2], yy = tot[3], yv = tot[4];
+        if (!isfinite(n) || !isfinite(an) || !isfinite(o) || !isfinite(yy) || !isfinite(yv)) {
             sc->status = 3;
             sc->kstop = -1;
             return;
         }
         const double gp = sqrt(n);  // beta_{p-1}
-        const double scale = fmax(sc->scale, fabs(a.alpha[p - 1]));
+        // breakdown scale on the unshifted alpha (the reading shared with the oracle)
+        const double scale = fmax(sc->scale, fabs(a.alpha[p - 1] + sig));
         a.gamma[p] = gp;
         if (gp <= 1e-13 * scale) {
-            // invariant Krylov subspace: stop with k_eff = p - 1
+            // invariant Krylov subspace: stop with k_eff = p - 1, beta_k = gamma_p
             sc->keff = p - 1;
             sc->kstop = p - 1;
+            sc->beta_k = gp;
             return;
         }
         sc->scale = fmax(scale, gp);
-        a.alpha[p] = an / n - o / g1;
+        const double al = an / n - o / g1;
+        a.alpha[p] = al;
+        if (last) {
+            // w = A u_m - alpha_m u_m - (gamma_m^2/gamma_{m-1}) u_{m-1} = gamma_m u_{m+1}
+            const double bp = n / g1;
+            const double w2 = yy + al * al * n + bp * bp * (g1 * g1) - 2.0 * al * an - 2.0 * bp * yv +
+                              2.0 * al * bp * o;
+            sc->beta_k = sqrt(fmax(w2, 0.0)) / gp;
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
 // exp(-iT) e_1 through the eigendecomposition of the k x k tridiagonal T
-// (Sec. 4): implicit symmetric QR steps with Wilkinson shift, eigenvectors
-// accumulated row-wise (lane j owns row j).  Every lane runs the same scalar
-// bulge chase on its own private copy of the diagonals (lane-interleaved LDS
-// columns), so no lane reads another lane's data until the final sum.
-// Output: coef[j] = c_j / gamma_j with c = ||psi|| V exp(-i Lambda) V^T e_1.
+// (Sec. 4): implicit symmetric QR steps with Wilkinson shift.  One wave: lane
+// i holds diagonal d_i and coupling e_i (between i and i+1) in registers, the
+// bulge chase carries the two entries it is working on in registers and
+// fetches the next ones by lane shuffles one step ahead; deflation is a
+// ballot over the lanes.  Lane j owns row j of the eigenvector matrix in its
+// own LDS column.  Output: coef[j] = c_j / gamma_j with
+// c = ||psi|| V exp(-i Lambda) V^T e_1, and the step's error estimate
+// beta_k |c_k| (eq. matrix_exponential_error).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_tridiag(const double *alpha, const double *gamma, Scalars *sc)
+__global__ __launch_bounds__(64) void k_tridiag(const double *alpha, const double *gamma, Scalars *sc,
+                                                StepStat *stat)
 {
-    __shared__ double dpr[kMaxM * 64];
-    __shared__ double epr[kMaxM * 64];
-    __shared__ double zpr[kMaxM * 64];
+    __shared__ double zpr[(kMaxM + 1) * 64];
+    __shared__ double wre[kMaxM], wim[kMaxM];
     const int lane = threadIdx.x;
     if (sc->status != 0) return;
     const int k = sc->keff;
     if (k <= 0) {
         for (int j = lane; j < 2 * (kMaxM + 2); j += 64) sc->coef[j] = 0.0;
-        if (lane == 0) sc->cabs_k = 0.0;
+        if (lane == 0) {
+            sc->cabs_k = 0.0;
+            stat->keff = 0;
+            stat->err_est = 0.0;
+        }
         return;
     }
-#define DD(i) dpr[(i) * 64 + lane]
-#define EE(i) epr[(i) * 64 + lane]
 #define ZZ(i) zpr[(i) * 64 + lane]
-    for (int i = 0; i < k; ++i) {
-        DD(i) = alpha[i + 1];
-        EE(i) = (i + 1 < k) ? gamma[i + 2] : 0.0;
-        ZZ(i) = (i == lane) ? 1.0 : 0.0;
-    }
+    double d = (lane < k) ? alpha[lane + 1] : 0.0;
+    double e = (lane + 1 < k) ? gamma[lane + 2] : 0.0;
+    for (int i = 0; i < k; ++i) ZZ(i) = (i == lane) ? 1.0 : 0.0;
     const double eps = 2.220446049250313e-16;
-    int h = k - 1, iter = 0;
-    while (h > 0) {
-        if (fabs(EE(h - 1)) <= eps * (fabs(DD(h - 1)) + fabs(DD(h)))) {
-            EE(h - 1) = 0.0;
-            --h;
-            iter = 0;
-            continue;
-        }
-        if (++iter > 100) break;
-        int l = h - 1;
-        while (l > 0 && fabs(EE(l - 1)) > eps * (fabs(DD(l - 1)) + fabs(DD(l)))) --l;
-        // Wilkinson shift from the trailing 2x2 block
-        const double delta = 0.5 * (DD(h - 1) - DD(h));
-        const double b2 = EE(h - 1) * EE(h - 1);
-        const double mu = DD(h) - b2 / (delta + copysign(sqrt(delta * delta + b2), delta));
-        double x = DD(l) - mu, z = EE(l);
+    for (int iter = 0; iter < 40 * kMaxM; ++iter) {
+        // negligible couplings are set to zero; find the last unreduced block [l, h]
+        const double dn = __shfl_down(d, 1, 64);
+        const bool live = lane + 1 < k && e != 0.0;
+        const bool tiny = live && fabs(e) <= eps * (fabs(d) + fabs(dn));
+        if (tiny) e = 0.0;
+        const unsigned long long mask = __ballot(live && !tiny);
+        if (mask == 0ull) break;
+        const int hb = 63 - __clzll(mask);  // highest coupling still live
+        const unsigned long long below = ~mask & ((1ull << hb) - 1ull);
+        const int l = below ? 64 - __clzll(below) : 0;
+        const int h = hb + 1;
+        // Wilkinson shift from the trailing 2x2 block of [l, h]
+        const double dh1 = __shfl(d, h - 1, 64), dh = __shfl(d, h, 64), eh1 = __shfl(e, h - 1, 64);
+        const double delta = 0.5 * (dh1 - dh);
+        const double b2 = eh1 * eh1;
+        const double mu = dh - b2 / (delta + copysign(sqrt(delta * delta + b2), delta));
+        double aq = __shfl(d, l, 64);  // current d_q
+        double bq = __shfl(e, l, 64);  // current e_q
+        double x = aq - mu, z = bq;
+        double aq1n = __shfl(d, l + 1, 64);
+        double bq1n = (l + 1 < h) ? __shfl(e, l + 1, 64) : 0.0;
+        double zq = ZZ(l);
         for (int q = l; q < h; ++q) {
-            const double r = hypot(x, z);
-            double c = 1.0, s = 0.0;
-            if (r != 0.0) {
-                const double ir = 1.0 / r;
+            const double aq1 = aq1n, bq1 = bq1n;
+            // entries of the next step, fetched ahead (lanes > q+1 are untouched so far)
+            aq1n = __shfl(d, min(q + 2, 63), 64);
+            bq1n = (q + 2 < h) ? __shfl(e, min(q + 2, 63), 64) : 0.0;
+            const double zq1 = ZZ(q + 1);
+            const double rr = x * x + z * z;
+            double c = 1.0, s = 0.0, r = 0.0;
+            if (rr > 0.0) {
+                const double ir = rsqrt(rr);
                 c = x * ir;
                 s = -z * ir;
+                r = rr * ir;
             }
-            if (q > l) EE(q - 1) = r;
-            const double aq = DD(q), aq1 = DD(q + 1), bq = EE(q);
+            if (q > l && lane == q - 1) e = r;
             const double cc = c * c, ss = s * s, cs = c * s;
-            DD(q) = cc * aq - 2.0 * cs * bq + ss * aq1;
-            DD(q + 1) = ss * aq + 2.0 * cs * bq + cc * aq1;
-            EE(q) = cs * (aq - aq1) + (cc - ss) * bq;
-            if (q + 1 < h) {
-                const double bq1 = EE(q + 1);
-                x = EE(q);
-                z = -s * bq1;
-                EE(q + 1) = c * bq1;
-            }
-            const double zq = ZZ(q), zq1 = ZZ(q + 1);
+            const double dq = cc * aq - 2.0 * cs * bq + ss * aq1;
+            const double dq1 = ss * aq + 2.0 * cs * bq + cc * aq1;
+            const double eq = cs * (aq - aq1) + (cc - ss) * bq;
+            if (lane == q) d = dq;
             ZZ(q) = c * zq - s * zq1;
-            ZZ(q + 1) = s * zq + c * zq1;
+            zq = s * zq + c * zq1;
+            aq = dq1;
+            if (q + 1 < h) {
+                x = eq;
+                z = -s * bq1;
+                bq = c * bq1;
+            } else {
+                if (lane == q) e = eq;
+                if (lane == q + 1) d = dq1;
+            }
         }
+        ZZ(h) = zq;
+    }
+    // c_j = gamma_1 sum_i Z[j][i] exp(-i lambda_i) Z[0][i]; lambda_i is lane i's d
+    __syncthreads();
+    if (lane < k) {
+        double sn, cs;
+        sincos(d, &sn, &cs);
+        const double z0 = zpr[lane * 64 + 0];
+        wre[lane] = z0 * cs;
+        wim[lane] = -z0 * sn;
     }
     __syncthreads();
-    // c_j = gamma_1 sum_i Z[j][i] exp(-i lambda_i) Z[0][i]; row 0 belongs to lane 0
     const double g1 = gamma[1];
     if (lane < k) {
         double cr = 0.0, ci = 0.0;
         for (int i = 0; i < k; ++i) {
-            double sn, cs;
-            sincos(DD(i), &sn, &cs);
-            const double w = zpr[i * 64 + 0] * ZZ(i);
-            cr += w * cs;
-            ci -= w * sn;
+            const double zji = ZZ(i);
+            cr += zji * wre[i];
+            ci += zji * wim[i];
         }
-        cr *= g1;
-        ci *= g1;
+        // exp(-iT) = exp(-i sigma) exp(-iT') for the shifted tridiagonal T'
+        double ss, sc0;
+        sincos(sc->sigma, &ss, &sc0);
+        const double tr = g1 * (cr * sc0 + ci * ss), ti = g1 * (ci * sc0 - cr * ss);
+        cr = tr;
+        ci = ti;
         const double ig = 1.0 / gamma[lane + 1];
         sc->coef[2 * (lane + 1)] = cr * ig;
         sc->coef[2 * (lane + 1) + 1] = ci * ig;
-        if (lane == k - 1) sc->cabs_k = sqrt(cr * cr + ci * ci);
+        if (lane == k - 1) {
+            const double ck = sqrt(cr * cr + ci * ci);
+            sc->cabs_k = ck;
+            stat->keff = k;
+            stat->err_est = sc->beta_k * ck;
+        }
     }
-#undef DD
-#undef EE
 #undef ZZ
 }
 
 // ---------------------------------------------------------------------------
 // Recombination psi_new = sum_j c_j q_j = sum_j (c_j / gamma_j) u_j
-// (eq. matrix_exp_approx), plus u_{k+1} = (A u_k - alpha_k u_k)/gamma_k
-// - (gamma_k/gamma_{k-1}) u_{k-1} for beta_k = ||u_{k+1}|| of the error
-// estimate eq. matrix_exponential_error, and ||psi_new||^2.
+// (eq. matrix_exp_approx): a site-local multi-axpy streamed over the sites,
+// one site (both components) per thread and eight Krylov vectors in flight,
+// plus ||psi_new||^2 for the step statistics.
 // ---------------------------------------------------------------------------
 template <class TB>
-__device__ __forceinline__ Sp load_u(const RecArgs &a, const Op &op, const LaneGeo &lg,
-                                     const RowGeo &rg, int j)
-{
-    if (j == 1) return load_site(a.psi, op, lg, rg);
-    return load_site(static_cast<const TB *>(a.basis) + (size_t)(j - 2) * a.vec_elems, op, lg, rg);
-}
-
-template <class TB>
-__global__ __launch_bounds__(kBlock) void k_recombine(RecArgs a)
+__global__ __launch_bounds__(kBlock) void k_combine(CombArgs a)
 {
     Scalars *sc = a.sc;
     if (sc->status != 0) return;
-    const Op &op = a.op;
     const int k = sc->keff;
-    const int lane = threadIdx.x & 63;
-    const WaveTask wt = wave_task(op, a.t);
-    const size_t plane = (size_t)op.nx * op.ny;
-    const double gxh = a.field[0], gyh = a.field[1];
-    double inv_gk = 0.0, ca = 0.0, cb = 0.0;
-    if (k >= 1) {
-        inv_gk = 1.0 / a.gamma[k];
-        ca = a.alpha[k] * inv_gk;
-        if (k >= 2) cb = a.gamma[k] / a.gamma[k - 1];
-    }
-    double acc[2] = {0.0, 0.0};
-    if (wt.active) {
-        const LaneGeo lg = lane_geo(op, a.t, wt.strip, lane);
-        const double gy = gyh - op.bq * lg.x;
-        Sp p0 = sp_zero(), p1 = sp_zero(), p2 = sp_zero();
-        if (k >= 1) p2 = load_u<TB>(a, op, lg, row_geo(op, wt.y0 - 1), k);
-        for (int R = wt.y0; R <= wt.y1; ++R) {
-            const int rr = R - 1;
-            p0 = p1;
-            p1 = p2;
-            if (k >= 1) p2 = load_u<TB>(a, op, lg, row_geo(op, R), k);
-            if (rr < wt.y0) continue;
-            const RowGeo rg = row_geo(op, rr);
-            Sp s = sp_zero();
-            if (k >= 1) {
-                const Sp w = hop(op, p1, sp_left(p1), sp_right(p1), p0, p2, site_pot(op, lg, rg),
-                                 gxh + op.bq * rg.y, gy);
-                const Sp um = (k >= 2) ? load_u<TB>(a, op, lg, rg, k - 1) : sp_zero();
-                Sp res;
-                res.r0 = inv_gk * w.r0 - ca * p1.r0 - cb * um.r0;
-                res.i0 = inv_gk * w.i0 - ca * p1.i0 - cb * um.i0;
-                res.r1 = inv_gk * w.r1 - ca * p1.r1 - cb * um.r1;
-                res.i1 = inv_gk * w.i1 - ca * p1.i1 - cb * um.i1;
-                if (lg.own) acc[0] += sp_norm2(res);
-                // sum over the basis, four loads in flight at a time
-                for (int jb = 1; jb <= k; jb += 4) {
-                    Sp v[4];
+    const char *__restrict__ basis = static_cast<const char *>(a.basis);
+    const size_t sites = a.sites;
+    double nrm = 0.0;
+    const double c1r = sc->coef[2], c1i = sc->coef[3];
+    for (size_t s = (size_t)blockIdx.x * kBlock + threadIdx.x; s < sites; s += (size_t)gridDim.x * kBlock) {
+        const double2 p0 = a.psi[s], p1 = a.psi[sites + s];
+        Sp acc;
+        if (k >= 1) {
+            acc.r0 = c1r * p0.x - c1i * p0.y;
+            acc.i0 = c1r * p0.y + c1i * p0.x;
+            acc.r1 = c1r * p1.x - c1i * p1.y;
+            acc.i1 = c1r * p1.y + c1i * p1.x;
+        } else {
+            acc = sp_zero();
+        }
+        const size_t soff = s * sizeof(Raw<TB>);
+        for (int jb = 2; jb <= k; jb += 8) {
+            Raw<TB> v[8];
 #pragma unroll
-                    for (int t2 = 0; t2 < 4; ++t2) {
-                        const int j = jb + t2;
-                        if (j == k) v[t2] = p1;
-                        else if (j == k - 1) v[t2] = um;
-                        else if (j < k) v[t2] = load_u<TB>(a, op, lg, rg, j);
-                        else v[t2] = sp_zero();
-                    }
+            for (int t = 0; t < 8; ++t)
+                if (jb + t <= k)
+                    v[t] = *reinterpret_cast<const Raw<TB> *>(basis + (size_t)(jb + t - 2) * a.vec_bytes + soff);
 #pragma unroll
-                    for (int t2 = 0; t2 < 4; ++t2) {
-                        const int j = jb + t2;
-                        if (j <= k) {
-                            const double cr = sc->coef[2 * j], ci = sc->coef[2 * j + 1];
-                            s.r0 += cr * v[t2].r0 - ci * v[t2].i0;
-                            s.i0 += cr * v[t2].i0 + ci * v[t2].r0;
-                            s.r1 += cr * v[t2].r1 - ci * v[t2].i1;
-                            s.i1 += cr * v[t2].i1 + ci * v[t2].r1;
-                        }
-                    }
+            for (int t = 0; t < 8; ++t) {
+                const int j = jb + t;
+                if (j <= k) {
+                    const Sp u = to_sp(v[t]);
+                    const double cr = sc->coef[2 * j], ci = sc->coef[2 * j + 1];
+                    acc.r0 += cr * u.r0 - ci * u.i0;
+                    acc.i0 += cr * u.i0 + ci * u.r0;
+                    acc.r1 += cr * u.r1 - ci * u.i1;
+                    acc.i1 += cr * u.i1 + ci * u.r1;
                 }
             }
-            if (lg.own) {
-                Vec<double2>::store(a.out, plane, (size_t)rr * op.nx + lg.colw, s);
-                acc[1] += sp_norm2(s);
-            }
         }
+        a.out[s] = make_double2(acc.r0, acc.i0);
+        a.out[sites + s] = make_double2(acc.r1, acc.i1);
+        nrm += sp_norm2(acc);
     }
-    double tot[2];
-    if (!grid_reduce(acc, a.partials, &sc->ticket, tot)) return;
+    double accv[1] = {nrm}, tot[1];
+    if (!grid_reduce(accv, a.partials, &sc->ticket, tot)) return;
     if (threadIdx.x == 0) {
-        const double beta_k = sqrt(tot[0]);
-        a.stat->err_est = (k >= 1) ? beta_k * sc->cabs_k : 0.0;
-        a.stat->norm2 = tot[1];
-        a.stat->keff = k;
-        if (!isfinite(tot[0]) || !isfinite(tot[1])) {
+        a.stat->norm2 = tot[0];
+        if (!isfinite(tot[0])) {
             sc->status = 3;
             sc->kstop = -1;
             return;
@@ -623,17 +808,23 @@ __global__ __launch_bounds__(kBlock) void k_apply(Op op, Tiles t, const double2 
     const size_t plane = (size_t)op.nx * op.ny;
     const LaneGeo lg = lane_geo(op, t, wt.strip, lane);
     const double gy = gyh - op.bq * lg.x;
+    const Planar vin{reinterpret_cast<const char *>(x), plane * 16, (uint32_t)op.nx * 16u};
+    const uint32_t off = lg.inx ? Planar::lane_offset(lg.colw) : kOob;
     Sp p0 = sp_zero(), p1 = sp_zero();
-    Sp p2 = load_site(x, op, lg, row_geo(op, wt.y0 - 1));
+    Sp p2 = to_sp(load_row(vin, op, off, wt.y0 - 1));
     for (int R = wt.y0; R <= wt.y1; ++R) {
         p0 = p1;
         p1 = p2;
-        p2 = load_site(x, op, lg, row_geo(op, R));
+        p2 = to_sp(load_row(vin, op, off, R));
         if (R - 1 < wt.y0) continue;
         const RowGeo rg = row_geo(op, R - 1);
         const Sp o = hop(op, p1, sp_left(p1), sp_right(p1), p0, p2, site_pot(op, lg, rg),
                          gxh + op.bq * rg.y, gy);
-        if (lg.own) Vec<double2>::store(y, plane, (size_t)(R - 1) * op.nx + lg.colw, o);
+        if (lg.own) {
+            const size_t idx = (size_t)(R - 1) * op.nx + lg.colw;
+            y[idx] = make_double2(o.r0, o.i0);
+            y[plane + idx] = make_double2(o.r1, o.i1);
+        }
     }
 }
 
@@ -647,10 +838,44 @@ __global__ void k_reset(Scalars *sc)
         sc->keff = 0;
         sc->scale = 0.0;
         sc->cabs_k = 0.0;
+        sc->beta_k = 0.0;
+        sc->sigma = 0.0;
     }
 }
 
+// FIFO depths (rows of loads in flight per wave).
+constexpr int kPfFirst = 4;
+constexpr int kPfMixed = 4;
+constexpr int kPfFp64 = 2;
+
+using PlanarV = Planar;
+template <class T>
+using PairedV = Paired<T>;
+
+template <class K>
+int waves_per_cu(K kernel)
+{
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kernel, kBlock, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 8;
+    }
+    return blocks * kWaves;
+}
+
 }  // namespace
+
+int sweep_waves_per_cu(int which, bool mixed)
+{
+    switch (which) {
+    case 0: return waves_per_cu(k_first<kPfFirst>);
+    case 1:
+        return mixed ? waves_per_cu(k_recur<PairedV<float2>, PairedV<float2>, float2, true, kPfMixed>)
+                     : waves_per_cu(k_recur<PairedV<double2>, PairedV<double2>, double2, true, kPfFp64>);
+    case 2: return mixed ? waves_per_cu(k_combine<float2>) : waves_per_cu(k_combine<double2>);
+    default: return waves_per_cu(k_apply);
+    }
+}
 
 Tiles make_tiles(int nx, int ny, int halo, int target_waves)
 {
@@ -673,10 +898,11 @@ Tiles make_tiles(int nx, int ny, int halo, int target_waves)
 }
 
 void launch_first(const Op &op, const Tiles &t, const double2 *psi, const double *field,
-                  double *alpha, double *gamma, Scalars *sc, double *partials, int m, hipStream_t st)
+                  double *alpha, double *gamma, Scalars *sc, double *partials, int m, int shift,
+                  hipStream_t st)
 {
-    hipLaunchKernelGGL(k_first, dim3(t.nblocks), dim3(kBlock), 0, st, op, t, psi, field, alpha,
-                       gamma, sc, partials, m);
+    hipLaunchKernelGGL(k_first<kPfFirst>, dim3(t.nblocks), dim3(kBlock), 0, st, op, t, psi, field,
+                       alpha, gamma, sc, partials, m, shift);
 }
 
 void launch_recur(const PassArgs &a, bool mixed, hipStream_t st)
@@ -684,30 +910,35 @@ void launch_recur(const PassArgs &a, bool mixed, hipStream_t st)
     const dim3 g(a.t.nblocks), b(kBlock);
     if (!mixed) {
         if (a.pass == 2)
-            hipLaunchKernelGGL((k_recur<double2, double2, double2, false>), g, b, 0, st, a);
+            hipLaunchKernelGGL((k_recur<PlanarV, PlanarV, double2, false, kPfFp64>), g, b, 0, st, a);
+        else if (a.pass == 3)
+            hipLaunchKernelGGL((k_recur<PairedV<double2>, PlanarV, double2, true, kPfFp64>), g, b, 0, st, a);
         else
-            hipLaunchKernelGGL((k_recur<double2, double2, double2, true>), g, b, 0, st, a);
+            hipLaunchKernelGGL((k_recur<PairedV<double2>, PairedV<double2>, double2, true, kPfFp64>), g, b,
+                               0, st, a);
     } else {
         if (a.pass == 2)
-            hipLaunchKernelGGL((k_recur<double2, double2, float2, false>), g, b, 0, st, a);
+            hipLaunchKernelGGL((k_recur<PlanarV, PlanarV, float2, false, kPfMixed>), g, b, 0, st, a);
         else if (a.pass == 3)
-            hipLaunchKernelGGL((k_recur<float2, double2, float2, true>), g, b, 0, st, a);
+            hipLaunchKernelGGL((k_recur<PairedV<float2>, PlanarV, float2, true, kPfMixed>), g, b, 0, st, a);
         else
-            hipLaunchKernelGGL((k_recur<float2, float2, float2, true>), g, b, 0, st, a);
+            hipLaunchKernelGGL((k_recur<PairedV<float2>, PairedV<float2>, float2, true, kPfMixed>), g, b, 0,
+                               st, a);
     }
 }
 
-void launch_tridiag(const double *alpha, const double *gamma, Scalars *sc, hipStream_t st)
+void launch_tridiag(const double *alpha, const double *gamma, Scalars *sc, StepStat *stat,
+                    hipStream_t st)
 {
-    hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(64), 0, st, alpha, gamma, sc);
+    hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(64), 0, st, alpha, gamma, sc, stat);
 }
 
-void launch_recombine(const RecArgs &a, bool mixed, hipStream_t st)
+void launch_combine(const CombArgs &a, bool mixed, int nblocks, hipStream_t st)
 {
     if (mixed)
-        hipLaunchKernelGGL(k_recombine<float2>, dim3(a.t.nblocks), dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL(k_combine<float2>, dim3(nblocks), dim3(kBlock), 0, st, a);
     else
-        hipLaunchKernelGGL(k_recombine<double2>, dim3(a.t.nblocks), dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL(k_combine<double2>, dim3(nblocks), dim3(kBlock), 0, st, a);
 }
 
 void launch_apply(const Op &op, const Tiles &t, const double2 *x, double2 *y, double gxh,
