@@ -58,29 +58,43 @@ def load_traffic(precision):
 
 
 def run_precision(torch, Propagator, cfg, psi0_dev, precision, steps, warmup, copy_mib):
-    prob, m, dt = cfg["problem"], cfg["m"], cfg["dt"]
-    prop = Propagator(prob, m, precision)
+    """Warm up, then two timed regions of `steps` steps from the same state:
+    a clean one (the reported rate) and one with per-launch HIP events recorded
+    by the library on its stream (kernel durations for the roofline)."""
+    prop_args = (cfg["problem"], cfg["m"], precision)
+    dt = cfg["dt"]
+    prop = Propagator(*prop_args)
     psi = psi0_dev.clone()
     if warmup > 0:
         prop.step(psi, 0.0, dt, warmup, want_stats=False)
     if copy_mib:
-        # plain copy of known size: calibration kernel for the HBM byte counters
+        # kernels of known traffic that calibrate the HBM byte counters: a fill
+        # (writes copy_mib MiB) and a negation (reads and writes copy_mib MiB)
         a = torch.empty(copy_mib << 17, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
         a.fill_(1.0)
-        b.copy_(a)
+        torch.neg(a, out=b)
         torch.cuda.synchronize()
         del a, b
     psi.copy_(psi0_dev)
-    prop.timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = prop.step(psi, 0.0, dt, steps, want_stats=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    # instrumented region (same work, same state)
+    psi2 = psi0_dev.clone()
+    prop.timing(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prop.step(psi2, 0.0, dt, steps, want_stats=False)
+    torch.cuda.synchronize()
+    wall_ev = time.perf_counter() - t1
     timing = prop.timing(False)
     prop.close()
-    return psi, stats, wall, timing
+    same = bool(torch.equal(psi, psi2))
+    del psi2
+    return psi, stats, wall, timing, wall_ev, same
 
 
 def main():
@@ -121,10 +135,11 @@ def main():
     res = {}
     for prec in precs:
         log(f"running {prec}")
-        psi, stats, wall, timing = run_precision(torch, Propagator, cfg, psi0_dev, prec, args.steps,
-                                                 args.warmup, args.copy_calib_mib)
-        res[prec] = dict(psi=psi, stats=stats, wall=wall, timing=timing)
-        log(f"{prec}: {wall * 1e3 / args.steps:.3f} ms/step, timing {timing}")
+        psi, stats, wall, timing, wall_ev, same = run_precision(
+            torch, Propagator, cfg, psi0_dev, prec, args.steps, args.warmup, args.copy_calib_mib)
+        res[prec] = dict(psi=psi, stats=stats, wall=wall, timing=timing, wall_ev=wall_ev, same=same)
+        log(f"{prec}: {wall * 1e3 / args.steps:.3f} ms/step ({wall_ev * 1e3 / args.steps:.3f} with "
+            f"events; bitwise repeat {same}), timing {timing}")
 
     # mixed vs FP64 difference of the final states
     err = None
@@ -195,6 +210,8 @@ def main():
     out["stats"] = {"k_eff_min": int(st["k_eff"].min()), "cum_err_bound": float(st["cum_bound"][-1]),
                     "norm_drift": float(abs(st["norm2"][-1] / float(np.sum(np.abs(psi0) ** 2)) - 1.0))}
     out["kernel_ms"] = {k: (v[0], round(v[1], 3)) for k, v in r["timing"].items()}
+    out["events_region_ms_per_step"] = r["wall_ev"] * 1e3 / args.steps
+    out["bitwise_repeat"] = all(v["same"] for v in res.values())
     out["paper_context"] = {"value": 5.6e6, "unit": "site-matvecs/s",
                             "what": "derived from ~2 min per step, 8192^2 grid, k=10, one process on a "
                                     "dual Xeon-E5 cluster node (Sec. 7); context, not the target"}

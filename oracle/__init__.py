@@ -84,6 +84,7 @@ def _load():
                                   ctypes.POINTER(ctypes.c_int)]
         lib.orc_eigen.restype = ctypes.c_int
         lib.orc_pauli.argtypes = [ctypes.c_int, D]
+        lib.orc_expectations.argtypes = [P, D, D]
         _lib = lib
     return _lib
 
@@ -232,3 +233,22 @@ def pauli(which: int) -> np.ndarray:
     out = np.zeros(8)
     lib.orc_pauli(int(which), _dp(out))
     return out.view(np.complex128).reshape(2, 2)
+
+
+def expectations(prob: dict, psi: np.ndarray) -> np.ndarray:
+    """[<psi|psi>, <x>, <y>, <p_x>, <p_y>] (normalised expectations)."""
+    lib = _load()
+    pb = _Problem(prob)
+    psi = _check_psi(prob, psi)
+    out = np.zeros(5)
+    lib.orc_expectations(pb.ref, _dp(psi.view(np.float64)), _dp(out))
+    return out
+
+
+LOSS_X, LOSS_Y, LOSS_PX, LOSS_PY = 1, 2, 4, 8
+
+
+def loss_value(prob: dict, psi: np.ndarray, loss_kind: int) -> float:
+    """Sum of the expectations selected by the loss_kind bit flags."""
+    e = expectations(prob, psi)
+    return float(sum(e[1 + b] for b in range(4) if loss_kind & (1 << b)))

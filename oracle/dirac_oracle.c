@@ -522,3 +522,36 @@ int orc_eigen(const orc_params *p, const double *psi0, int k, int reorth, double
     free(beta);
     return keff;
 }
+
+/*
+ * Expectation values at the final time for the differentiable observable of
+ * the adjoint check: out = {<psi|psi>, <x>, <y>, <p_x>, <p_y>} with
+ * <O> = <psi|O|psi>/<psi|psi>, x, y the grid coordinates and p = -i D the
+ * same central difference as the Hamiltonian (Sec. 3 momentum operator).
+ */
+void orc_expectations(const orc_params *p, const double *psi_d, double *out)
+{
+    const cplx *psi = (const cplx *)psi_d;
+    const double hx = grid_h(p->x_min, p->x_max, p->nx);
+    const double hy = grid_h(p->y_min, p->y_max, p->ny);
+    double n = 0.0, sx = 0.0, sy = 0.0;
+    cplx spx = 0, spy = 0;
+    for (int s = 0; s < 2; ++s)
+        for (int j = 0; j < p->ny; ++j)
+            for (int i = 0; i < p->nx; ++i) {
+                const cplx v = site(p, psi, s, i, j);
+                const double w = creal(conj(v) * v);
+                n += w;
+                sx += (p->x_min + i * hx) * w;
+                sy += (p->y_min + j * hy) * w;
+                const cplx dx = (site(p, psi, s, i + 1, j) - site(p, psi, s, i - 1, j)) / (2.0 * hx);
+                const cplx dy = (site(p, psi, s, i, j + 1) - site(p, psi, s, i, j - 1)) / (2.0 * hy);
+                spx += conj(v) * (-I * dx);
+                spy += conj(v) * (-I * dy);
+            }
+    out[0] = n;
+    out[1] = n > 0 ? sx / n : 0.0;
+    out[2] = n > 0 ? sy / n : 0.0;
+    out[3] = n > 0 ? creal(spx) / n : 0.0;
+    out[4] = n > 0 ? creal(spy) / n : 0.0;
+}

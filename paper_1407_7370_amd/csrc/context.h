@@ -1,0 +1,178 @@
+// Host-side context of the C ABI, shared by host.cpp (init/step/eigen) and
+// adjoint.cpp.  Internal; not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "dirac_lanczos.h"
+#include "dl_internal.h"
+
+namespace dlh {
+
+struct Layout {
+    size_t sc = 0, alpha = 0, gamma = 0, partials = 0, fields = 0, stats = 0, vecs = 0, total = 0;
+    int ab_len = 0;
+};
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+inline size_t vec_elems(const dl_params &p) { return (size_t)2 * (size_t)p.nx * (size_t)p.ny; }
+// Byte stride between workspace vectors: padded so that vectors streamed
+// together are not a power of two apart.
+inline size_t vec_stride(size_t n, size_t elem) { return align256(n * elem) + dl::kVecPad; }
+
+Layout plan(const dl_params &p, int mode, int k_eigen);
+const char *validate(const dl_params *p);
+void pulse_now(const dl_params &p, const std::vector<double> &coef, double t, double *a);
+void pulse_average(const dl_params &p, const std::vector<double> &coef, double t0, double dt, double *a);
+// Step average of one Fourier basis function of the sin^2-enveloped pulse:
+// harmonic k, sine (cosine = false) or cosine (cosine = true).
+double basis_average(const dl_params &p, int k, bool cosine, double t0, double dt);
+void tridiag_last_row(std::vector<double> d, std::vector<double> e, std::vector<double> &lam,
+                      std::vector<double> &zlast);
+// Eigenvalues and all eigenvectors (column l of v, row-major k x k).
+void tridiag_full(std::vector<double> d, std::vector<double> e, std::vector<double> &lam,
+                  std::vector<double> &v);
+
+}  // namespace dlh
+
+struct dl_context {
+    dl_params p{};
+    std::vector<double> coef;
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    dlh::Layout L;
+    int cus = 256;
+    dl::Tiles tiles_first{}, tiles_recur{}, tiles_apply{};
+    int combine_blocks = 1024;
+    std::vector<double> host_fields;
+    std::vector<dl::StepStat> host_stats;
+    std::string err;
+    // event timing (dirac_lanczos_timing)
+    bool timing = false;
+    std::vector<hipEvent_t> ev0, ev1;
+    std::vector<int> ev_cls;
+    size_t ev_used = 0;
+    int64_t t_launches[5] = {0, 0, 0, 0, 0};
+    double t_ms[5] = {0, 0, 0, 0, 0};
+
+    ~dl_context()
+    {
+        for (hipEvent_t e : ev0) (void)hipEventDestroy(e);
+        for (hipEvent_t e : ev1) (void)hipEventDestroy(e);
+    }
+
+    // Fold the recorded event pairs into the per-class totals.
+    hipError_t harvest()
+    {
+        if (ev_used == 0) return hipSuccess;
+        hipError_t e = hipEventSynchronize(ev1[ev_used - 1]);
+        if (e != hipSuccess) return e;
+        for (size_t i = 0; i < ev_used; ++i) {
+            float ms = 0.0f;
+            e = hipEventElapsedTime(&ms, ev0[i], ev1[i]);
+            if (e != hipSuccess) return e;
+            t_ms[ev_cls[i]] += ms;
+            t_launches[ev_cls[i]] += 1;
+        }
+        ev_used = 0;
+        return hipSuccess;
+    }
+
+    // Launch `fn` bracketed by an event pair when timing is on.
+    template <class F>
+    hipError_t timed(int cls, F &&fn)
+    {
+        if (!timing) {
+            fn();
+            return hipSuccess;
+        }
+        if (ev_used == ev0.size()) {
+            hipError_t e = harvest();
+            if (e != hipSuccess) return e;
+        }
+        hipError_t e = hipEventRecord(ev0[ev_used], stream);
+        if (e != hipSuccess) return e;
+        fn();
+        e = hipEventRecord(ev1[ev_used], stream);
+        if (e != hipSuccess) return e;
+        ev_cls[ev_used++] = cls;
+        return hipSuccess;
+    }
+
+    dl_status fail(dl_status s, const std::string &msg)
+    {
+        err = msg;
+        return s;
+    }
+    dl_status hip_fail(hipError_t e, const char *what)
+    {
+        err = std::string(what) + ": " + hipGetErrorString(e);
+        return DL_ERR_DEVICE;
+    }
+    dl::Scalars *sc() const { return reinterpret_cast<dl::Scalars *>(ws + L.sc); }
+
+    // A = s H with the geometry and static fields of the problem.
+    dl::Op op(double s) const
+    {
+        dl::Op o{};
+        o.nx = p.nx;
+        o.ny = p.ny;
+        o.bcx = p.bc_x;
+        o.bcy = p.bc_y;
+        o.hx = (p.x_max - p.x_min) / p.nx;
+        o.hy = (p.y_max - p.y_min) / p.ny;
+        o.xmin = p.x_min;
+        o.ymin = p.y_min;
+        o.kx = s * p.c / (2.0 * o.hx);
+        o.ky = s * p.c / (2.0 * o.hy);
+        o.mc2 = s * p.mass * p.c * p.c;
+        o.bq = s * p.c * p.charge * p.bz * 0.5;
+        o.pot_kind = p.pot_kind ? 1 : 0;
+        if (p.pot_kind == 1) {
+            o.vz = s * p.pot_z;
+            o.va2 = p.pot_a * p.pot_a;
+        } else if (p.pot_kind == 2) {
+            o.vz = s * 1.5 * p.pot_z;
+            o.va2 = 3.0 / (p.pot_z * p.pot_z);
+        }
+        o.has_table = p.v_table ? 1 : 0;
+        o.vtab = p.v_table;
+        o.vscale = s;
+        return o;
+    }
+};
+
+#define DL_HIP(ctx, call)                                      \
+    do {                                                       \
+        hipError_t e_ = (call);                                \
+        if (e_ != hipSuccess) return (ctx)->hip_fail(e_, #call); \
+    } while (0)
+
+
+namespace dlh {
+
+// One Lanczos engine: scalars, alpha/gamma chains and Krylov vectors u_2..u_m.
+struct Engine {
+    dl::Scalars *sc;
+    double *alpha;
+    double *gamma;
+    char *basis;
+    size_t vstride;
+    int m;
+    bool mixed;
+    void *bvec(int j) const { return basis + (size_t)(j - 2) * vstride; }
+};
+
+// Iterations 1..m on `in` (sweeps; shift: run on A - alpha_1 I after iteration 1).
+dl_status run_build(dl_context *ctx, const Engine &e, const dl::Op &op, const double2 *in,
+                    const double *field, double *partials, int shift);
+// exp(-iT) and the recombination into `out` (stat receives k_eff, estimate, norm).
+dl_status run_finish(dl_context *ctx, const Engine &e, const double2 *in, double2 *out,
+                     dl::StepStat *stat, double *partials);
+
+}  // namespace dlh

@@ -97,6 +97,33 @@ struct CombArgs {
     StepStat *stat;      // entry of this step
 };
 
+// Observables <x>, <y>, <p_x>, <p_y> of a state and the adjoint seed.
+// obs (device, 8 doubles): N = <psi|psi>, <x>, <y>, <p_x>, <p_y>, loss = sum of
+// the expectations selected by the loss flags (1 x, 2 y, 4 p_x, 8 p_y).
+void launch_observe(const Op &op, const double2 *psi, int loss_kind, Scalars *sc, double *partials,
+                    double *obs, int nblocks, hipStream_t st);
+// lam = (O psi - loss psi) / N with O the sum of the selected observables.
+void launch_adjoint_seed(const Op &op, const double2 *psi, int loss_kind, const double *obs,
+                         double2 *lam, hipStream_t st);
+
+// Contraction of two Krylov bases for the adjoint: for a < k_lam, b < k_psi
+//   S01[a][b] = sum_sites conj(ul_a,0) up_b,1,  S10[a][b] = sum_sites conj(ul_a,1) up_b,0
+// with ul_1 = lam (psi layout), ul_j the lam basis; likewise for psi.
+constexpr int kContractM = 16;  // largest Krylov dimension of the adjoint
+struct ContractArgs {
+    const double2 *lam1;
+    const char *lam_basis;
+    const double2 *psi1;
+    const char *psi_basis;
+    size_t vec_bytes;
+    size_t sites;
+    const Scalars *sc_lam;
+    const Scalars *sc_psi;
+    double *partials;  // nblocks x 256 x 4
+    double *out;       // 256 x 4: (re, im) of S01 then S10 for pair a*16+b
+};
+void launch_contract(const ContractArgs &a, int nblocks, hipStream_t st);
+
 void launch_first(const Op &op, const Tiles &t, const double2 *psi, const double *field,
                   double *alpha, double *gamma, Scalars *sc, double *partials, int m,
                   int shift, hipStream_t st);

@@ -12,29 +12,18 @@
 #include <string>
 #include <vector>
 
-#include "dirac_lanczos.h"
-#include "dl_internal.h"
+#include "context.h"
 
 using dl::kChunk;
 using dl::kMaxBlocks;
 using dl::kMaxM;
 
-namespace {
+namespace dlh {
 
-thread_local std::string g_init_error;
 
-struct Layout {
-    size_t sc = 0, alpha = 0, gamma = 0, partials = 0, fields = 0, stats = 0, vecs = 0, total = 0;
-    int ab_len = 0;
-};
 
-size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-size_t vec_elems(const dl_params &p) { return (size_t)2 * (size_t)p.nx * (size_t)p.ny; }
 
-// Byte stride between workspace vectors: padded so that vectors streamed
-// together are not a power of two apart.
-size_t vec_stride(size_t n, size_t elem) { return align256(n * elem) + dl::kVecPad; }
 
 // Workspace plan.  Vector region: step mode holds the second state buffer
 // (complex128) and the Krylov vectors u_2..u_m (complex128, or complex64 in
@@ -140,6 +129,22 @@ double int_cos(double nu, double tm, double h2)
     return 2.0 / nu * std::cos(nu * tm) * std::sin(nu * h2);
 }
 
+double basis_average(const dl_params &p, int k, bool cosine, double t0, double dt)
+{
+    double lo = std::min(t0, t0 + dt), hi = std::max(t0, t0 + dt);
+    lo = std::max(lo, 0.0);
+    hi = std::min(hi, p.t_pulse);
+    if (!(hi > lo)) return 0.0;
+    const double tm = 0.5 * (lo + hi), h2 = 0.5 * (hi - lo);
+    const double W = 2.0 * kPi / p.t_pulse, nu = k * W;
+    double v;
+    if (cosine)
+        v = 0.5 * int_cos(nu, tm, h2) - 0.25 * (int_cos(nu + W, tm, h2) + int_cos(nu - W, tm, h2));
+    else
+        v = 0.5 * int_sin(nu, tm, h2) - 0.25 * (int_sin(nu + W, tm, h2) + int_sin(nu - W, tm, h2));
+    return v / std::fabs(dt);
+}
+
 // (1/|dt|) integral of A_L over the step [t0, t0 + dt]; the envelope
 // sin^2(pi t/T) = (1 - cos(W t))/2 (W = 2 pi/T) turns every term into single
 // sines and cosines whose integrals are closed forms.
@@ -161,11 +166,8 @@ void pulse_average(const dl_params &p, const std::vector<double> &coef, double t
         a[1] = p.a0 * v * p.pulse_e[1];
     } else {
         for (size_t k = 1; 4 * k <= coef.size(); ++k) {
-            const double nu = k * W;
-            const double is = 0.5 * int_sin(nu, tm, h2) -
-                              0.25 * (int_sin(nu + W, tm, h2) + int_sin(nu - W, tm, h2));
-            const double ic = 0.5 * int_cos(nu, tm, h2) -
-                              0.25 * (int_cos(nu + W, tm, h2) + int_cos(nu - W, tm, h2));
+            const double is = basis_average(p, (int)k, false, t0, dt) * std::fabs(dt);
+            const double ic = basis_average(p, (int)k, true, t0, dt) * std::fabs(dt);
             a[0] += coef[4 * (k - 1)] * is + coef[4 * (k - 1) + 1] * ic;
             a[1] += coef[4 * (k - 1) + 2] * is + coef[4 * (k - 1) + 3] * ic;
         }
@@ -228,121 +230,111 @@ void tridiag_last_row(std::vector<double> d, std::vector<double> e, std::vector<
     lam = d;
 }
 
+
+void tridiag_full(std::vector<double> d, std::vector<double> e, std::vector<double> &lam,
+                  std::vector<double> &v)
+{
+    const int k = (int)d.size();
+    v.assign((size_t)k * k, 0.0);
+    for (int i = 0; i < k; ++i) v[(size_t)i * k + i] = 1.0;
+    e.resize(k, 0.0);
+    const double eps = 2.220446049250313e-16;
+    int h = k - 1, iter = 0;
+    while (h > 0) {
+        if (std::fabs(e[h - 1]) <= eps * (std::fabs(d[h - 1]) + std::fabs(d[h]))) {
+            e[h - 1] = 0.0;
+            --h;
+            iter = 0;
+            continue;
+        }
+        if (++iter > 200) break;
+        int l = h - 1;
+        while (l > 0 && std::fabs(e[l - 1]) > eps * (std::fabs(d[l - 1]) + std::fabs(d[l]))) --l;
+        const double delta = 0.5 * (d[h - 1] - d[h]);
+        const double b2 = e[h - 1] * e[h - 1];
+        const double mu = d[h] - b2 / (delta + std::copysign(std::sqrt(delta * delta + b2), delta));
+        double x = d[l] - mu, z = e[l];
+        for (int q = l; q < h; ++q) {
+            const double r = std::hypot(x, z);
+            double c = 1.0, s = 0.0;
+            if (r != 0.0) {
+                c = x / r;
+                s = -z / r;
+            }
+            if (q > l) e[q - 1] = r;
+            const double aq = d[q], aq1 = d[q + 1], bq = e[q];
+            const double cc = c * c, ss = s * s, cs = c * s;
+            d[q] = cc * aq - 2.0 * cs * bq + ss * aq1;
+            d[q + 1] = ss * aq + 2.0 * cs * bq + cc * aq1;
+            e[q] = cs * (aq - aq1) + (cc - ss) * bq;
+            if (q + 1 < h) {
+                const double bq1 = e[q + 1];
+                x = e[q];
+                z = -s * bq1;
+                e[q + 1] = c * bq1;
+            }
+            for (int row = 0; row < k; ++row) {
+                double &zq = v[(size_t)row * k + q], &zq1 = v[(size_t)row * k + q + 1];
+                const double a0 = zq, a1 = zq1;
+                zq = c * a0 - s * a1;
+                zq1 = s * a0 + c * a1;
+            }
+        }
+    }
+    lam = d;
+}
+
+dl_status run_build(dl_context *ctx, const Engine &e, const dl::Op &op, const double2 *in,
+                    const double *field, double *partials, int shift)
+{
+    hipStream_t st = ctx->stream;
+    DL_HIP(ctx, ctx->timed(0, [&] {
+        dl::launch_first(op, ctx->tiles_first, in, field, e.alpha, e.gamma, e.sc, partials, e.m, shift, st);
+    }));
+    for (int pp = 2; pp <= e.m; ++pp) {
+        dl::PassArgs a{};
+        a.op = op;
+        a.t = ctx->tiles_recur;
+        a.u1 = (pp - 1 == 1) ? static_cast<const void *>(in) : e.bvec(pp - 1);
+        a.u2 = (pp - 2 == 1) ? static_cast<const void *>(in) : (pp - 2 >= 2 ? e.bvec(pp - 2) : nullptr);
+        a.uo = e.bvec(pp);
+        a.field = field;
+        a.alpha = e.alpha;
+        a.gamma = e.gamma;
+        a.sc = e.sc;
+        a.partials = partials;
+        a.pass = pp;
+        a.m = e.m;
+        DL_HIP(ctx, ctx->timed(pp >= 4 ? 1 : 2, [&] { dl::launch_recur(a, e.mixed, st); }));
+    }
+    return DL_OK;
+}
+
+dl_status run_finish(dl_context *ctx, const Engine &e, const double2 *in, double2 *out,
+                     dl::StepStat *stat, double *partials)
+{
+    hipStream_t st = ctx->stream;
+    DL_HIP(ctx, ctx->timed(3, [&] { dl::launch_tridiag(e.alpha, e.gamma, e.sc, stat, st); }));
+    dl::CombArgs r{};
+    r.psi = in;
+    r.basis = e.basis;
+    r.vec_bytes = e.vstride;
+    r.sites = vec_elems(ctx->p) / 2;
+    r.out = out;
+    r.sc = e.sc;
+    r.partials = partials;
+    r.stat = stat;
+    DL_HIP(ctx, ctx->timed(4, [&] { dl::launch_combine(r, e.mixed, ctx->combine_blocks, st); }));
+    return DL_OK;
+}
+
+}  // namespace dlh
+
+namespace {
+thread_local std::string g_init_error;
 }  // namespace
 
-struct dl_context {
-    dl_params p{};
-    std::vector<double> coef;
-    hipStream_t stream = nullptr;
-    char *ws = nullptr;
-    size_t ws_bytes = 0;
-    Layout L;
-    int cus = 256;
-    dl::Tiles tiles_first{}, tiles_recur{}, tiles_apply{};
-    int combine_blocks = 1024;
-    std::vector<double> host_fields;
-    std::vector<dl::StepStat> host_stats;
-    std::string err;
-    // event timing (dirac_lanczos_timing)
-    bool timing = false;
-    std::vector<hipEvent_t> ev0, ev1;
-    std::vector<int> ev_cls;
-    size_t ev_used = 0;
-    int64_t t_launches[5] = {0, 0, 0, 0, 0};
-    double t_ms[5] = {0, 0, 0, 0, 0};
-
-    ~dl_context()
-    {
-        for (hipEvent_t e : ev0) (void)hipEventDestroy(e);
-        for (hipEvent_t e : ev1) (void)hipEventDestroy(e);
-    }
-
-    // Fold the recorded event pairs into the per-class totals.
-    hipError_t harvest()
-    {
-        if (ev_used == 0) return hipSuccess;
-        hipError_t e = hipEventSynchronize(ev1[ev_used - 1]);
-        if (e != hipSuccess) return e;
-        for (size_t i = 0; i < ev_used; ++i) {
-            float ms = 0.0f;
-            e = hipEventElapsedTime(&ms, ev0[i], ev1[i]);
-            if (e != hipSuccess) return e;
-            t_ms[ev_cls[i]] += ms;
-            t_launches[ev_cls[i]] += 1;
-        }
-        ev_used = 0;
-        return hipSuccess;
-    }
-
-    // Launch `fn` bracketed by an event pair when timing is on.
-    template <class F>
-    hipError_t timed(int cls, F &&fn)
-    {
-        if (!timing) {
-            fn();
-            return hipSuccess;
-        }
-        if (ev_used == ev0.size()) {
-            hipError_t e = harvest();
-            if (e != hipSuccess) return e;
-        }
-        hipError_t e = hipEventRecord(ev0[ev_used], stream);
-        if (e != hipSuccess) return e;
-        fn();
-        e = hipEventRecord(ev1[ev_used], stream);
-        if (e != hipSuccess) return e;
-        ev_cls[ev_used++] = cls;
-        return hipSuccess;
-    }
-
-    dl_status fail(dl_status s, const std::string &msg)
-    {
-        err = msg;
-        return s;
-    }
-    dl_status hip_fail(hipError_t e, const char *what)
-    {
-        err = std::string(what) + ": " + hipGetErrorString(e);
-        return DL_ERR_DEVICE;
-    }
-    dl::Scalars *sc() const { return reinterpret_cast<dl::Scalars *>(ws + L.sc); }
-
-    // A = s H with the geometry and static fields of the problem.
-    dl::Op op(double s) const
-    {
-        dl::Op o{};
-        o.nx = p.nx;
-        o.ny = p.ny;
-        o.bcx = p.bc_x;
-        o.bcy = p.bc_y;
-        o.hx = (p.x_max - p.x_min) / p.nx;
-        o.hy = (p.y_max - p.y_min) / p.ny;
-        o.xmin = p.x_min;
-        o.ymin = p.y_min;
-        o.kx = s * p.c / (2.0 * o.hx);
-        o.ky = s * p.c / (2.0 * o.hy);
-        o.mc2 = s * p.mass * p.c * p.c;
-        o.bq = s * p.c * p.charge * p.bz * 0.5;
-        o.pot_kind = p.pot_kind ? 1 : 0;
-        if (p.pot_kind == 1) {
-            o.vz = s * p.pot_z;
-            o.va2 = p.pot_a * p.pot_a;
-        } else if (p.pot_kind == 2) {
-            o.vz = s * 1.5 * p.pot_z;
-            o.va2 = 3.0 / (p.pot_z * p.pot_z);
-        }
-        o.has_table = p.v_table ? 1 : 0;
-        o.vtab = p.v_table;
-        o.vscale = s;
-        return o;
-    }
-};
-
-#define DL_HIP(ctx, call)                                      \
-    do {                                                       \
-        hipError_t e_ = (call);                                \
-        if (e_ != hipSuccess) return (ctx)->hip_fail(e_, #call); \
-    } while (0)
+using namespace dlh;
 
 extern "C" {
 
@@ -468,11 +460,9 @@ dl_status dirac_lanczos_step(dl_context *ctx, void *psi_v, double t0, double dt,
     double2 *state = reinterpret_cast<double2 *>(ws + L.vecs);
     char *basis = ws + L.vecs + align256(n * 16);
     const size_t vstride = vec_stride(n, belem);
-    auto bvec = [&](int j) -> void * { return basis + (size_t)(j - 2) * vstride; };
+    const Engine eng{sc, alpha, gamma, basis, vstride, m, mixed};
 
     const dl::Op op = ctx->op(dt);
-    const dl::Tiles &t1 = ctx->tiles_first;
-    const dl::Tiles &t2 = ctx->tiles_recur;
     const double kf = -dt * p.c * p.charge;
     hipStream_t st = ctx->stream;
 
@@ -498,37 +488,10 @@ dl_status dirac_lanczos_step(dl_context *ctx, void *psi_v, double t0, double dt,
             double2 *in = (g % 2 == 0) ? psi : state;
             double2 *out = (g % 2 == 0) ? state : psi;
             const double *fp = fields + 2 * i;
-            DL_HIP(ctx, ctx->timed(0, [&] {
-                dl::launch_first(op, t1, in, fp, alpha, gamma, sc, partials, m, 1, st);
-            }));
-            for (int pp = 2; pp <= m; ++pp) {
-                dl::PassArgs a{};
-                a.op = op;
-                a.t = t2;
-                a.u1 = (pp - 1 == 1) ? static_cast<const void *>(in) : bvec(pp - 1);
-                a.u2 = (pp - 2 == 1) ? static_cast<const void *>(in)
-                                     : (pp - 2 >= 2 ? bvec(pp - 2) : nullptr);
-                a.uo = bvec(pp);
-                a.field = fp;
-                a.alpha = alpha;
-                a.gamma = gamma;
-                a.sc = sc;
-                a.partials = partials;
-                a.pass = pp;
-                a.m = m;
-                DL_HIP(ctx, ctx->timed(pp >= 4 ? 1 : 2, [&] { dl::launch_recur(a, mixed, st); }));
-            }
-            DL_HIP(ctx, ctx->timed(3, [&] { dl::launch_tridiag(alpha, gamma, sc, dstats + i, st); }));
-            dl::CombArgs r{};
-            r.psi = in;
-            r.basis = basis;
-            r.vec_bytes = vstride;
-            r.sites = n / 2;
-            r.out = out;
-            r.sc = sc;
-            r.partials = partials;
-            r.stat = dstats + i;
-            DL_HIP(ctx, ctx->timed(4, [&] { dl::launch_combine(r, mixed, ctx->combine_blocks, st); }));
+            const dl_status sb = run_build(ctx, eng, op, in, fp, partials, 1);
+            if (sb != DL_OK) return sb;
+            const dl_status sf = run_finish(ctx, eng, in, out, dstats + i, partials);
+            if (sf != DL_OK) return sf;
         }
         DL_HIP(ctx, hipGetLastError());
         dl::Scalars hs;

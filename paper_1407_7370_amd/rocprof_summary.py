@@ -1,0 +1,131 @@
+"""Summarise rocprofv3 CSV output of bench.py runs into short text profiles.
+
+  python -m paper_1407_7370_amd.rocprof_summary --stats DIR/trace_kernel_stats.csv \
+      [--fetch DIR/fetch_counter_collection.csv --write DIR/write_counter_collection.csv] \
+      [--calib-mib N] [--traffic-json profiles/traffic_recur_laser4096.json] [--command "..."]
+
+Kernel statistics: calls and average duration per kernel.  Counters: HBM read
+and write bytes per dispatch from FETCH_SIZE / WRITE_SIZE (KiB), each scaled
+by what the same counter reads for calibration kernels of known size that
+bench.py --copy-calib-mib N runs: torch's fill of N MiB (writes N MiB) and
+torch's neg of N MiB (reads N MiB, writes N MiB).
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import hashlib
+import json
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def short_name(n: str) -> str:
+    n = n.replace("void ", "").replace("dl::(anonymous namespace)::", "")
+    n = n.replace("HIP_vector_type<double, 2u>", "c128").replace("HIP_vector_type<float, 2u>", "c64")
+    n = n.replace("dl::(anonymous namespace)::", "")
+    return n
+
+
+def kernel_class(n: str):
+    """Map a kernel name to (family, precision) of the propagator."""
+    if "k_recur<" in n:
+        body = n[n.index("k_recur<"):]
+        prec = "mixed" if "float, 2u" in n else "fp64"
+        general = body.count("Paired") >= 2
+        return ("recur_basis" if general else "recur_psi", prec)
+    for fam in ("k_first", "k_tridiag", "k_combine", "k_apply", "k_reset"):
+        if fam in n:
+            prec = "mixed" if "float, 2u" in n else ("fp64" if fam == "k_combine" else "-")
+            return (fam, prec)
+    return (None, None)
+
+
+def read_stats(path):
+    rows = list(csv.DictReader(open(path)))
+    out = []
+    for r in rows:
+        out.append(dict(name=r["Name"], calls=int(r["Calls"]), avg_us=float(r["AverageNs"]) / 1e3,
+                        total_ms=float(r["TotalDurationNs"]) / 1e6, pct=float(r["Percentage"])))
+    return out
+
+
+def read_counter(path, counter):
+    d = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] == counter:
+            d[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in d.items()}
+
+
+def find(d, needle):
+    for k, v in d.items():
+        if needle in k:
+            return v
+    return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--stats", required=True)
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--calib-mib", type=int, default=1024)
+    ap.add_argument("--traffic-json")
+    ap.add_argument("--sites", type=int, default=4096 * 4096)
+    ap.add_argument("--command", default="")
+    args = ap.parse_args()
+
+    lines = []
+    if args.command:
+        lines.append("commands:")
+        for c in args.command.split(" ;; "):
+            lines.append("  " + c)
+        lines.append("")
+    st = read_stats(args.stats)
+    lines.append(f"{'kernel':78s} {'calls':>6s} {'avg_us':>10s} {'total_ms':>10s} {'%':>6s}")
+    for r in sorted(st, key=lambda x: -x["total_ms"]):
+        if "dl::" not in r["name"] and r["pct"] < 0.5:
+            continue
+        lines.append(f"{short_name(r['name'])[:78]:78s} {r['calls']:6d} {r['avg_us']:10.2f} "
+                     f"{r['total_ms']:10.3f} {r['pct']:6.2f}")
+    traffic = {}
+    if args.fetch and args.write:
+        fetch = read_counter(args.fetch, "FETCH_SIZE")
+        write = read_counter(args.write, "WRITE_SIZE")
+        calib = args.calib_mib * 1024.0  # KiB
+        f_neg = find(fetch, "neg_kernel")
+        w_fill = find(write, "FillFunctor")
+        rf = f_neg / calib if f_neg else None
+        wf = w_fill / calib if w_fill else None
+        lines.append("")
+        lines.append(f"calibration: FETCH_SIZE(neg of {args.calib_mib} MiB) = {f_neg} KiB -> read factor "
+                     f"{rf}; WRITE_SIZE(fill of {args.calib_mib} MiB) = {w_fill} KiB -> write factor {wf}")
+        lines.append(f"{'kernel':78s} {'read_MB':>10s} {'write_MB':>10s} {'B/site':>8s}")
+        for k in sorted(fetch):
+            if "dl::" not in k:
+                continue
+            rd = fetch[k] * 1024 / (rf or 1.0)
+            wr = write.get(k, 0.0) * 1024 / (wf or 1.0)
+            lines.append(f"{short_name(k)[:78]:78s} {rd / 1e6:10.1f} {wr / 1e6:10.1f} "
+                         f"{(rd + wr) / args.sites:8.2f}")
+            fam, prec = kernel_class(k)
+            if fam == "recur_basis":
+                traffic[prec] = {"bytes_per_launch": rd + wr, "read_bytes": rd, "write_bytes": wr,
+                                 "kernel": short_name(k)}
+    text = "\n".join(lines)
+    print(text)
+    if args.traffic_json and traffic:
+        with open(os.path.join(HERE, "csrc", "kernels.hip"), "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+        traffic["kernels_sha256"] = digest
+        traffic["note"] = ("HBM bytes per launch of the dominant sweep from rocprofv3 FETCH_SIZE/WRITE_SIZE, "
+                           "scaled by the calibration kernels; valid for this kernels.hip digest only")
+        with open(args.traffic_json, "w") as f:
+            json.dump(traffic, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

@@ -313,3 +313,44 @@ def test_eigen_landau_vs_oracle(torch_cuda, Prop, orc):
     # first Landau level of this lattice (h = 10/64) within its O(h^2) error
     lvl = hz.landau_levels(prob, 1)[0]
     assert abs(ev[0] - lvl) < 0.01 * (lvl - mc2)
+
+
+def test_eigen_landau_softcore_vs_oracle(torch_cuda, Prop, orc):
+    """B = 0.5 plus soft-core potential (the 1024^2 workload's physics) on a
+    256^2 grid over the same box: converged Ritz clusters agree with the oracle."""
+    torch = torch_cuda
+    mc2 = C * C
+    cfg = packets.with_grid(packets.landau_softcore_1024(), 256)
+    prob = cfg["problem"]
+    say("eigen B+soft-core 256x256 K=600")
+    psi0 = packets.initial_state(cfg)
+    lo, hi, tol = mc2 - 2.0, mc2 + 5.0, 1e-6
+    prop = Prop(prob, 1, "fp64", k_eigen=600)
+    ev, bd = prop.eigen(torch.from_numpy(psi0).cuda(), 600, lo, hi, tol)
+    prop.close()
+    rev, rbd, _ = orc.eigen(prob, psi0, 600, lo, hi, tol)
+    print("eigen 256^2 gpu:", np.round(ev - mc2, 9).tolist(), "oracle:", np.round(rev - mc2, 9).tolist(),
+          flush=True)
+    assert len(rev) >= 2
+    # every value converged on both sides is the same eigenvalue
+    common = [e for e in ev if np.min(np.abs(rev - e)) <= 1e-7]
+    assert len(common) >= max(1, min(len(ev), len(rev)) - 1)
+    assert np.all(bd <= tol) and np.all(np.diff(ev) > 0)
+
+
+def test_eigen_full_grid_properties(torch_cuda, Prop):
+    """Full 1024^2 eigen run: converged, sorted, distinct values inside the window."""
+    torch = torch_cuda
+    mc2 = C * C
+    cfg = packets.landau_softcore_1024()
+    prob = cfg["problem"]
+    say("eigen B+soft-core 1024x1024 K=2000")
+    psi0 = packets.initial_state(cfg)
+    lo, hi, tol = mc2 - 2.0, mc2 + 5.0, 1e-6
+    prop = Prop(prob, 1, "fp64", k_eigen=2000)
+    ev, bd = prop.eigen(torch.from_numpy(psi0).cuda(), 2000, lo, hi, tol, n_wanted=8)
+    prop.close()
+    print("eigen 1024^2 (E - mc^2):", np.round(ev - mc2, 8).tolist(), flush=True)
+    assert 1 <= len(ev) <= 8
+    assert np.all(bd <= tol) and np.all(np.diff(ev) > tol)
+    assert np.all(ev >= lo) and np.all(ev <= hi)

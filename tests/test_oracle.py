@@ -366,3 +366,41 @@ def test_eigen_small_dense(orc):
     assert keff == 128
     assert len(ev) == 128
     assert np.allclose(ev, w, atol=1e-8 * np.abs(w).max())
+
+
+# ---------------------------------------------------------------------------
+# Observables of the adjoint loss
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("bc", [0, 1])
+def test_expectations_vs_dense(orc, bc):
+    prob = small_prob(12, 10, bc)
+    psi = packets.random_spinor(prob, 21)
+    got = orc.expectations(prob, psi)
+    x, y, hx, hy = hz.axes(prob)
+    X = np.tile(x, prob["ny"])
+    Y = np.repeat(y, prob["nx"])
+    v = psi.reshape(2, -1)
+    n = np.vdot(v, v).real
+    assert abs(got[0] - n) <= 1e-13 * n
+    assert abs(got[1] - np.sum(X * np.abs(v) ** 2) / n) <= 1e-13 * np.abs(x).max()
+    assert abs(got[2] - np.sum(Y * np.abs(v) ** 2) / n) <= 1e-13 * np.abs(y).max()
+    import scipy.sparse as sp
+    Dx = sp.kron(sp.identity(prob["ny"]), hz.diff_1d(prob["nx"], hx, bc))
+    Dy = sp.kron(hz.diff_1d(prob["ny"], hy, bc), sp.identity(prob["nx"]))
+    px = sum(np.vdot(v[s], -1j * (Dx @ v[s])) for s in range(2)).real / n
+    py = sum(np.vdot(v[s], -1j * (Dy @ v[s])) for s in range(2)).real / n
+    assert abs(got[3] - px) <= 1e-12 * (1 + abs(px)) and abs(got[4] - py) <= 1e-12 * (1 + abs(py))
+
+
+def test_expectations_packet(orc):
+    """A Gaussian packet centred at r0 with momentum p0 on a fine periodic grid:
+    <x> = r0 and <p> = sin(p0 h)/h (the lattice momentum)."""
+    prob = small_prob(128, 128, 1, lo=-8.0, hi=8.0)
+    prob["y_min"], prob["y_max"] = -8.0, 8.0
+    psi = packets.gaussian_packet(prob, 1.0, (1.5, -0.7), center=(0.5, -1.0), project=False)
+    e = orc.expectations(prob, psi)
+    h = 16.0 / 128
+    assert abs(e[1] - 0.5) < 1e-9 and abs(e[2] + 1.0) < 1e-9
+    # exact for the lattice: <-iD> = sin(p0 h)/h times a Gaussian smoothing factor exp(-h^2/(8 s^2))
+    assert abs(e[3] - np.sin(1.5 * h) / h * np.exp(-h * h / 8.0)) < 1e-9
+    assert abs(e[4] - np.sin(-0.7 * h) / h * np.exp(-h * h / 8.0)) < 1e-9
