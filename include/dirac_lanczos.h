@@ -167,13 +167,44 @@ dl_status dirac_lanczos_eigen(dl_context *ctx, const void *psi0, int32_t k_max, 
                               double *evals, double *bounds, int32_t *n_found);
 
 /*
- * Gradient of a final observable with respect to the laser coefficients
- * (forward run with checkpoints every ckpt_every steps, backward propagation
- * with exp(+i A)).  Not provided by this build: returns DL_ERR_UNSUPPORTED.
+ * Adjoint (gradient) mode: the derivative of a final observable with respect
+ * to the coefficients of the DL_PULSE_FOURIER_SIN2 laser field.  This extends
+ * the paper (whose method is the forward propagator of Sec. 4 and the
+ * eigenvalue mode of Sec. 5): the forward map is the same chain of short-time
+ * steps, each U_n = exp(-i dt H(A_n)) with the step-averaged field A_n
+ * (Sec. 3, first Magnus term).
+ *
+ * Loss: L = sum of the expectation values selected by loss_kind (bit flags
+ * DL_LOSS_X, DL_LOSS_Y, DL_LOSS_PX, DL_LOSS_PY) in the final state psi_N,
+ * each <psi_N|O|psi_N> / <psi_N|psi_N>, with x, y the grid coordinates and
+ * p = -i d/dx by the central differences of the Hamiltonian.
+ * Gradient: dL/dcoef_j = sum_n 2 Re <lam_{n+1}| dU_n/dcoef_j |psi_n> with
+ * lam_N = (O - L) psi_N / <psi_N|psi_N> and lam_n = U_n^dagger lam_{n+1}
+ * (a step with -dt at the same field).  dU_n/dA is the Frechet derivative of
+ * the matrix exponential, evaluated in the eigenbases of the two Krylov
+ * spaces of step n (the forward one of psi_n and the backward one of
+ * lam_{n+1}), with the divided difference of exp(-i .) between their Ritz
+ * values.  States psi_n are stored every ckpt_every steps during the forward
+ * pass and recomputed segment by segment during the backward pass.
+ *
+ * Requirements: precision DL_PREC_FP64, krylov_dim <= 16, pulse_kind
+ * DL_PULSE_FOURIER_SIN2, loss_kind in 1..15, n_steps >= 1, ckpt_every >= 1,
+ * dt > 0.  adj_ws: DEVICE, 256-byte aligned, adj_bytes >=
+ * dirac_lanczos_adjoint_workspace_bytes(params, n_steps, ckpt_every); the
+ * context's own workspace is used for the forward Krylov basis.
+ * psi0 (DEVICE) is read only.  loss (HOST, 1 double) receives L, grad (HOST,
+ * n_coef doubles) the gradient in the order of params->coef.  Synchronous.
+ * Errors: DL_ERR_INVALID, DL_ERR_WORKSPACE, DL_ERR_UNSUPPORTED (other
+ * precision/pulse/krylov_dim), DL_ERR_NONFINITE, DL_ERR_DEVICE.
  */
+enum { DL_LOSS_X = 1, DL_LOSS_Y = 2, DL_LOSS_PX = 4, DL_LOSS_PY = 8 };
+
+size_t dirac_lanczos_adjoint_workspace_bytes(const dl_params *params, int32_t n_steps,
+                                             int32_t ckpt_every);
+
 dl_status dirac_lanczos_adjoint(dl_context *ctx, const void *psi0, double t0, double dt,
                                 int32_t n_steps, int32_t ckpt_every, int32_t loss_kind,
-                                double *loss, double *grad);
+                                void *adj_ws, size_t adj_bytes, double *loss, double *grad);
 
 /*
  * Kernel timing with HIP events recorded on the context's stream around every

@@ -252,3 +252,117 @@ def loss_value(prob: dict, psi: np.ndarray, loss_kind: int) -> float:
     """Sum of the expectations selected by the loss_kind bit flags."""
     e = expectations(prob, psi)
     return float(sum(e[1 + b] for b in range(4) if loss_kind & (1 << b)))
+
+
+# ---------------------------------------------------------------------------
+# Gradient of a final observable with respect to the Fourier laser
+# coefficients (the adjoint mode's target).  Two independent definitions:
+#   fd_gradient          -- central differences of the oracle's own Lanczos
+#                           forward map (the derivative of what is computed);
+#   dense_exact_gradient -- tiny grids only: exact propagators
+#                           exp(-i dt H(Abar_n)) and their Frechet derivatives
+#                           by the block-triangular exponential
+#                           expm([[X, E], [0, X]]) = [[e^X, L(X, E)], [0, e^X]],
+#                           propagated forward (tangent mode).
+# Both take the loss as the sum of the final expectations selected by
+# loss_kind (expectations() above), the step-averaged field of Sec. 3 (first
+# Magnus term) from field_average().
+# ---------------------------------------------------------------------------
+def final_loss(prob: dict, psi0: np.ndarray, t0: float, dt: float, n_steps: int, m: int,
+               loss_kind: int) -> float:
+    """Loss of the state after n_steps oracle steps."""
+    psi, _ = propagate(prob, psi0, t0, dt, n_steps, m)
+    return loss_value(prob, psi, loss_kind)
+
+
+def fd_gradient(prob: dict, psi0: np.ndarray, t0: float, dt: float, n_steps: int, m: int,
+                loss_kind: int, h: float = 1e-3, idx=None, richardson: bool = True) -> np.ndarray:
+    """Central-difference gradient over prob["coef"] (entries ``idx``, default
+    all); with ``richardson`` the steps h and h/2 are combined to cancel the
+    O(h^2) term."""
+    coef = np.asarray(prob["coef"], dtype=np.float64)
+    idx = range(len(coef)) if idx is None else idx
+    out = np.zeros(len(coef))
+
+    def central(j, step):
+        cp = coef.copy()
+        cp[j] += step
+        lp = final_loss(dict(prob, coef=cp), psi0, t0, dt, n_steps, m, loss_kind)
+        cp[j] -= 2 * step
+        lm = final_loss(dict(prob, coef=cp), psi0, t0, dt, n_steps, m, loss_kind)
+        return (lp - lm) / (2 * step)
+
+    for j in idx:
+        d1 = central(j, h)
+        out[j] = (4.0 * central(j, h / 2) - d1) / 3.0 if richardson else d1
+    return out
+
+
+def dense_matrix(prob: dict, a_hom=(0.0, 0.0)) -> np.ndarray:
+    """H (static fields plus a homogeneous vector potential) as a dense matrix
+    in the flattened (2, ny, nx) basis, one column per unit vector."""
+    shape = (2, int(prob["ny"]), int(prob["nx"]))
+    d = int(np.prod(shape))
+    H = np.zeros((d, d), dtype=np.complex128)
+    e = np.zeros(d, dtype=np.complex128)
+    for col in range(d):
+        e[:] = 0.0
+        e[col] = 1.0
+        H[:, col] = apply_h(prob, e.reshape(shape), a_hom).reshape(-1)
+    return H
+
+
+def _loss_quadratic(prob: dict, v: np.ndarray, loss_kind: int) -> float:
+    """<v|O|v> for the selected observables (unnormalised)."""
+    e = expectations(prob, v)
+    return float(e[0] * sum(e[1 + b] for b in range(4) if loss_kind & (1 << b)))
+
+
+def dense_exact_gradient(prob: dict, psi0: np.ndarray, t0: float, dt: float, n_steps: int,
+                         loss_kind: int):
+    """(loss, gradient) of the exact (dense exp) propagation, tiny grids only."""
+    from scipy.linalg import expm
+
+    shape = (2, int(prob["ny"]), int(prob["nx"]))
+    d = int(np.prod(shape))
+    assert d <= 512, "dense_exact_gradient is for tiny grids"
+    coef = np.asarray(prob["coef"], dtype=np.float64)
+    nc = len(coef)
+    static = dict(prob, pulse_kind=0)
+    H0 = dense_matrix(static)
+    Hx = dense_matrix(static, (1.0, 0.0)) - H0
+    Hy = dense_matrix(static, (0.0, 1.0)) - H0
+    # step weights w[n, j, axis]: the field average is linear in the coefficients
+    w = np.zeros((n_steps, nc, 2))
+    for j in range(nc):
+        unit = np.zeros(nc)
+        unit[j] = 1.0
+        pj = dict(prob, coef=unit)
+        for n in range(n_steps):
+            w[n, j] = field_average(pj, t0 + n * dt, dt)
+    psi = _check_psi(prob, psi0).reshape(-1).copy()
+    tang = np.zeros((nc, d), dtype=np.complex128)
+    Z = np.zeros((d, d), dtype=np.complex128)
+    for n in range(n_steps):
+        a = field_average(prob, t0 + n * dt, dt)
+        X = -1j * dt * (H0 + a[0] * Hx + a[1] * Hy)
+        frechet = []
+        for E in (-1j * dt * Hx, -1j * dt * Hy):
+            B = expm(np.block([[X, E], [Z, X]]))
+            frechet.append(B[:d, d:] @ psi)
+        U = B[:d, :d]
+        tang = tang @ U.T + np.outer(w[n, :, 0], frechet[0]) + np.outer(w[n, :, 1], frechet[1])
+        psi = U @ psi
+    v = psi.reshape(shape)
+    nrm = float(np.vdot(psi, psi).real)
+    loss = _loss_quadratic(prob, v, loss_kind) / nrm
+    grad = np.zeros(nc)
+    for j in range(nc):
+        t = tang[j]
+        s = np.sqrt(nrm / max(float(np.vdot(t, t).real), 1e-300))
+        tv = (s * t).reshape(shape)
+        # Re<psi|O|t> by polarisation of the quadratic form
+        re_o = (_loss_quadratic(prob, v + tv, loss_kind) - _loss_quadratic(prob, v - tv, loss_kind)) / (4 * s)
+        re_n = float(np.vdot(psi, t).real)
+        grad[j] = 2.0 * (re_o - loss * re_n) / nrm
+    return loss, grad

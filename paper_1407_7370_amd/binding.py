@@ -23,8 +23,10 @@ STATUS_NAMES = {0: "DL_OK", 1: "DL_ERR_INVALID", 2: "DL_ERR_DEVICE", 3: "DL_ERR_
 
 # every symbol declared in include/dirac_lanczos.h
 EXPORTS = ("dirac_lanczos_workspace_bytes", "dirac_lanczos_init", "dirac_lanczos_apply",
-           "dirac_lanczos_step", "dirac_lanczos_eigen", "dirac_lanczos_adjoint",
-           "dirac_lanczos_timing", "dirac_lanczos_destroy", "dirac_lanczos_last_error")
+           "dirac_lanczos_step", "dirac_lanczos_eigen", "dirac_lanczos_adjoint_workspace_bytes",
+           "dirac_lanczos_adjoint", "dirac_lanczos_timing", "dirac_lanczos_destroy",
+           "dirac_lanczos_last_error")
+DL_LOSS_X, DL_LOSS_Y, DL_LOSS_PX, DL_LOSS_PY = 1, 2, 4, 8
 
 
 class DlParams(ctypes.Structure):
@@ -91,8 +93,10 @@ def load_library():
                                         ctypes.c_double, ctypes.c_double, ctypes.c_int32, D, D,
                                         ctypes.POINTER(ctypes.c_int32)]
     lib.dirac_lanczos_eigen.restype = ctypes.c_int
+    lib.dirac_lanczos_adjoint_workspace_bytes.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
+    lib.dirac_lanczos_adjoint_workspace_bytes.restype = ctypes.c_size_t
     lib.dirac_lanczos_adjoint.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
-                                          ctypes.c_int32, ctypes.c_int32, D, D]
+                                          ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_size_t, D, D]
     lib.dirac_lanczos_adjoint.restype = ctypes.c_int
     lib.dirac_lanczos_timing.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(DlTiming)]
     lib.dirac_lanczos_timing.restype = ctypes.c_int
@@ -169,10 +173,16 @@ def dirac_lanczos_eigen(ctx, psi_ptr: int, k_max: int, reorth: int, e_lo: float,
                                               tol, n_wanted, evals, bounds, n_found)
 
 
+def dirac_lanczos_adjoint_workspace_bytes(params: DlParams, n_steps: int, ckpt_every: int) -> int:
+    return int(load_library().dirac_lanczos_adjoint_workspace_bytes(ctypes.byref(params), n_steps,
+                                                                     ckpt_every))
+
+
 def dirac_lanczos_adjoint(ctx, psi_ptr: int, t0: float, dt: float, n_steps: int, ckpt_every: int,
-                          loss_kind: int, loss, grad) -> int:
+                          loss_kind: int, adj_ptr: int, adj_bytes: int, loss, grad) -> int:
     return load_library().dirac_lanczos_adjoint(ctx, ctypes.c_void_p(psi_ptr), t0, dt, n_steps,
-                                                ckpt_every, loss_kind, loss, grad)
+                                                ckpt_every, loss_kind, ctypes.c_void_p(adj_ptr),
+                                                adj_bytes, loss, grad)
 
 
 def dirac_lanczos_timing(ctx, enable: int, out=None) -> int:
@@ -259,6 +269,25 @@ class Propagator:
                                  n_wanted, ev, bd, ctypes.byref(nf))
         _check(self.lib, self.ctx, st)
         return np.array(ev[:nf.value]), np.array(bd[:nf.value])
+
+    def adjoint(self, psi0, t0: float, dt: float, n_steps: int, ckpt_every: int, loss_kind: int):
+        """Loss (sum of the final expectations selected by loss_kind) and its
+        gradient with respect to the Fourier laser coefficients (numpy array in
+        the order of problem["coef"]).  psi0 is not modified."""
+        self._check_psi(psi0)
+        nbytes = dirac_lanczos_adjoint_workspace_bytes(self.params, n_steps, ckpt_every)
+        if nbytes == 0:
+            raise DlError(DL_ERR_INVALID, "invalid adjoint arguments (adjoint_workspace_bytes returned 0)")
+        ws = self.torch.empty(nbytes + 256, dtype=self.torch.uint8, device="cuda")
+        ptr = (ws.data_ptr() + 255) & ~255
+        ncoef = max(int(self.params.n_coef), 1)
+        loss = ctypes.c_double(0.0)
+        grad = (ctypes.c_double * ncoef)()
+        st = dirac_lanczos_adjoint(self.ctx, psi0.data_ptr(), t0, dt, n_steps, ckpt_every, loss_kind,
+                                   ptr, nbytes, ctypes.byref(loss), grad)
+        _check(self.lib, self.ctx, st)
+        del ws
+        return float(loss.value), np.array(grad[:int(self.params.n_coef)])
 
     def timing(self, enable: bool):
         """Start (True) or stop (False) event timing; returns the accumulated

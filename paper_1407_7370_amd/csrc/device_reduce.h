@@ -1,0 +1,75 @@
+// Deterministic FP64 reductions shared by the kernels of the library:
+// a butterfly inside a wave, then per-workgroup partials folded in fixed order
+// by the last workgroup to finish.  Internal header (device code only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "dl_internal.h"
+
+namespace dl {
+namespace {
+
+template <int NV>
+__device__ __forceinline__ void wave_sum(double (&v)[NV])
+{
+    // Butterfly: after each stage partner lanes hold bitwise equal sums.
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] += __shfl_xor(v[k], s, 64);
+}
+
+// Fold the per-lane sums of the whole grid in a fixed order.  Returns true in
+// the last workgroup to finish, where every thread then holds the totals.
+template <int NV>
+__device__ bool grid_reduce(double (&v)[NV], double *partials, unsigned int *ticket, double (&tot)[NV])
+{
+    static_assert(NV <= kPartialStride, "partial table stride");
+    __shared__ double red[kWaves][NV];
+    __shared__ int last;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    wave_sum(v);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) red[w][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double s = red[0][k];
+            for (int i = 1; i < kWaves; ++i) s += red[i][k];
+            partials[(size_t)blockIdx.x * kPartialStride + k] = s;
+        }
+        __threadfence();
+        const unsigned int t = atomicAdd(ticket, 1u);
+        last = (t == gridDim.x - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!last) return false;
+    __threadfence();
+    double s[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) s[k] = 0.0;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock)
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+            s[k] += __builtin_nontemporal_load(&partials[(size_t)b * kPartialStride + k]);
+    wave_sum(s);
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) red[w][k] = s[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double a = red[0][k];
+        for (int i = 1; i < kWaves; ++i) a += red[i][k];
+        tot[k] = a;
+    }
+    if (threadIdx.x == 0) *ticket = 0u;
+    return true;
+}
+
+}  // namespace
+}  // namespace dl

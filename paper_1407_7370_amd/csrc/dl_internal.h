@@ -110,6 +110,16 @@ void launch_adjoint_seed(const Op &op, const double2 *psi, int loss_kind, const 
 //   S01[a][b] = sum_sites conj(ul_a,0) up_b,1,  S10[a][b] = sum_sites conj(ul_a,1) up_b,0
 // with ul_1 = lam (psi layout), ul_j the lam basis; likewise for psi.
 constexpr int kContractM = 16;  // largest Krylov dimension of the adjoint
+// Per-step record of the adjoint (doubles): the contraction, then both
+// tridiagonal chains and the scalars needed to rebuild T and the basis norms.
+constexpr int kRecS = 0;                                // 256 pairs x (S01 re, im, S10 re, im)
+constexpr int kRecAlphaL = kRecS + 4 * kContractM * kContractM;
+constexpr int kRecGammaL = kRecAlphaL + kContractM + 2;  // index 0..kContractM+1 as on the device
+constexpr int kRecAlphaP = kRecGammaL + kContractM + 2;
+constexpr int kRecGammaP = kRecAlphaP + kContractM + 2;
+constexpr int kRecMeta = kRecGammaP + kContractM + 2;    // sigma_l, sigma_p, keff_l, keff_p, status_l, status_p
+constexpr int kRecLen = 1120;                            // padded: 8960 bytes per record
+static_assert(kRecMeta + 6 <= kRecLen, "adjoint record overflow");
 struct ContractArgs {
     const double2 *lam1;
     const char *lam_basis;
@@ -119,8 +129,9 @@ struct ContractArgs {
     size_t sites;
     const Scalars *sc_lam;
     const Scalars *sc_psi;
+    const double *alpha_lam, *gamma_lam, *alpha_psi, *gamma_psi;
     double *partials;  // nblocks x 256 x 4
-    double *out;       // 256 x 4: (re, im) of S01 then S10 for pair a*16+b
+    double *rec;       // record of this step (kRecLen doubles)
 };
 void launch_contract(const ContractArgs &a, int nblocks, hipStream_t st);
 

@@ -625,13 +625,6 @@ dl_status dirac_lanczos_eigen(dl_context *ctx, const void *psi0, int32_t k_max, 
     return DL_OK;
 }
 
-dl_status dirac_lanczos_adjoint(dl_context *ctx, const void *, double, double, int32_t, int32_t,
-                                int32_t, double *, double *)
-{
-    if (!ctx) return DL_ERR_INVALID;
-    return ctx->fail(DL_ERR_UNSUPPORTED, "adjoint propagation is not provided by this build");
-}
-
 dl_status dirac_lanczos_timing(dl_context *ctx, int32_t enable, dl_timing *out)
 {
     if (!ctx) return DL_ERR_INVALID;

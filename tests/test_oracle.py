@@ -404,3 +404,43 @@ def test_expectations_packet(orc):
     # exact for the lattice: <-iD> = sin(p0 h)/h times a Gaussian smoothing factor exp(-h^2/(8 s^2))
     assert abs(e[3] - np.sin(1.5 * h) / h * np.exp(-h * h / 8.0)) < 1e-9
     assert abs(e[4] - np.sin(-0.7 * h) / h * np.exp(-h * h / 8.0)) < 1e-9
+
+
+# ---------------------------------------------------------------------------
+# Gradient of a final observable w.r.t. the Fourier laser coefficients: the
+# oracle's central differences of its Lanczos map against the exact gradient
+# of the exact propagation (dense exponential and its Frechet derivative by
+# the block-triangular exponential), and the conservation law that makes the
+# momentum gradient vanish.
+# ---------------------------------------------------------------------------
+def _tiny_fourier(bc=0, **kw):
+    p = dict(nx=6, ny=6, x_min=-3.0, x_max=3.0, y_min=-3.0, y_max=3.0, bc_x=bc, bc_y=bc, mass=1.0,
+             c=137.036, charge=-1.0, bz=0.3, pot_kind=1, pot_z=1.0, pot_a=1.0, pulse_kind=2,
+             t_pulse=2e-3, coef=np.random.default_rng(3).uniform(-20, 20, 8))
+    p.update(kw)
+    return p
+
+
+@pytest.mark.parametrize("loss_kind", [1, 6, 9])
+def test_fd_gradient_matches_dense_exact(orc, loss_kind):
+    prob = _tiny_fourier()
+    rng = np.random.default_rng(4)
+    psi0 = rng.standard_normal((2, 6, 6)) + 1j * rng.standard_normal((2, 6, 6))
+    le, ge = orc.dense_exact_gradient(prob, psi0, 0.0, 1e-4, 20, loss_kind)
+    lo = orc.final_loss(prob, psi0, 0.0, 1e-4, 20, 12, loss_kind)
+    assert abs(le - lo) <= 1e-12 * abs(le)
+    gf = orc.fd_gradient(prob, psi0, 0.0, 1e-4, 20, 12, loss_kind, h=0.5)
+    assert np.max(np.abs(gf - ge)) <= 1e-7 * np.max(np.abs(ge))
+
+
+def test_momentum_gradient_vanishes_on_free_periodic_lattice(orc):
+    """No static field, no potential, periodic: -i D commutes with H(A) for any
+    homogeneous A, so <p> is independent of the laser."""
+    prob = _tiny_fourier(bc=1, bz=0.0, pot_kind=0)
+    rng = np.random.default_rng(6)
+    psi0 = rng.standard_normal((2, 6, 6)) + 1j * rng.standard_normal((2, 6, 6))
+    _, gx = orc.dense_exact_gradient(prob, psi0, 0.0, 1e-4, 20, 1)
+    _, gp = orc.dense_exact_gradient(prob, psi0, 0.0, 1e-4, 20, 12)
+    assert np.max(np.abs(gp)) <= 1e-9 * np.max(np.abs(gx))
+    gf = orc.fd_gradient(prob, psi0, 0.0, 1e-4, 20, 12, 12, h=0.5)
+    assert np.max(np.abs(gf)) <= 1e-8 * np.max(np.abs(gx))
