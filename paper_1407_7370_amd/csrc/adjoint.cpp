@@ -287,6 +287,7 @@ dl_status dirac_lanczos_adjoint(dl_context *ctx, const void *psi0_v, double t0, 
     // backward pass
     const size_t ncoef = ctx->coef.size();
     std::vector<double> gsum(ncoef, 0.0);
+    std::vector<double> gstep(2 * (size_t)n_steps, 0.0);  // dL/dAbar_x, dL/dAbar_y per step
     std::vector<double> hrec((size_t)dl::kRecLen * C);
     const int ncb = (int)std::max<size_t>(
         1, std::min<size_t>(kContractBlocks, (sites + 31) / 32));  // one 32-site tile per block and round
@@ -334,15 +335,22 @@ dl_status dirac_lanczos_adjoint(dl_context *ctx, const void *psi0_v, double t0, 
             step_gradient(r, dt, cq, &gx, &gy);
             if (!std::isfinite(gx) || !std::isfinite(gy))
                 return ctx->fail(DL_ERR_NONFINITE, "non-finite gradient contribution");
-            const double tn = t0 + (double)((size_t)g * C + i) * dt;
-            for (size_t k = 1; 4 * k <= ncoef; ++k) {
-                const double ws_ = basis_average(p, (int)k, false, tn, dt);
-                const double wc_ = basis_average(p, (int)k, true, tn, dt);
-                gsum[4 * (k - 1) + 0] += ws_ * gx;
-                gsum[4 * (k - 1) + 1] += wc_ * gx;
-                gsum[4 * (k - 1) + 2] += ws_ * gy;
-                gsum[4 * (k - 1) + 3] += wc_ * gy;
-            }
+            gstep[2 * ((size_t)g * C + i)] = gx;
+            gstep[2 * ((size_t)g * C + i) + 1] = gy;
+        }
+    }
+    // chain rule through the step averages, summed in step order (the result
+    // does not depend on the checkpoint interval)
+    for (int s = 0; s < n_steps; ++s) {
+        const double tn = t0 + (double)s * dt;
+        const double gx = gstep[2 * (size_t)s], gy = gstep[2 * (size_t)s + 1];
+        for (size_t k = 1; 4 * k <= ncoef; ++k) {
+            const double ws_ = basis_average(p, (int)k, false, tn, dt);
+            const double wc_ = basis_average(p, (int)k, true, tn, dt);
+            gsum[4 * (k - 1) + 0] += ws_ * gx;
+            gsum[4 * (k - 1) + 1] += wc_ * gx;
+            gsum[4 * (k - 1) + 2] += ws_ * gy;
+            gsum[4 * (k - 1) + 3] += wc_ * gy;
         }
     }
     *loss = hobs[5];

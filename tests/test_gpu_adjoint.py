@@ -133,7 +133,7 @@ def test_adjoint_autograd_function(torch_cuda, Prop):
     loss = final_observable(coef, prob, psi, 0.0, 1e-3, 24, 12, ckpt_every=5, loss_kind=9)
     (2.0 * loss).backward()
     l2, g2, _ = gpu_adjoint(torch, Prop, prob, 12, psi0, 0.0, 1e-3, 24, 5, 9)
-    assert float(loss) == l2
+    assert float(loss.detach()) == l2
     assert np.array_equal(coef.grad.numpy(), 2.0 * g2)
 
 
@@ -188,7 +188,9 @@ def test_adjoint_fourier_512_full(torch_cuda, Prop, orc):
     assert abs(loss - loss_at(c0)) <= 1e-10 * max(1.0, abs(loss))
     j_big = int(np.argmax(np.abs(grad)))
     for j in sorted({j_big, 1}):
-        h = 0.5
+        # over 2000 steps the loss is far from quadratic at h ~ 0.5; central
+        # differences enter their O(h^2) regime below h ~ 0.1
+        h = 0.0625
 
         def central(step):
             cp, cm = c0.copy(), c0.copy()
