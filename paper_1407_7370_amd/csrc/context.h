@@ -47,7 +47,9 @@ struct dl_context {
     size_t ws_bytes = 0;
     dlh::Layout L;
     int cus = 256;
-    dl::Tiles tiles_first{}, tiles_recur{}, tiles_apply{};
+    dl::Tiles tiles_first{}, tiles_recur{}, tiles_p2{}, tiles_p3{}, tiles_apply{};
+    // tiles of recurrence sweep p (each sweep kind has its own occupancy)
+    const dl::Tiles &tiles_pass(int p) const { return p == 2 ? tiles_p2 : (p == 3 ? tiles_p3 : tiles_recur); }
     int combine_blocks = 1024;
     std::vector<double> host_fields;
     std::vector<dl::StepStat> host_stats;

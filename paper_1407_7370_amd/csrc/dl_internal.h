@@ -147,8 +147,10 @@ void launch_apply(const Op &op, const Tiles &t, const double2 *x, double2 *y, do
 void launch_reset(Scalars *sc, hipStream_t st);
 
 Tiles make_tiles(int nx, int ny, int halo, int target_waves);
+// Workgroups of the recombination for `sites` sites (<= kMaxBlocks).
+int combine_grid(size_t sites, bool mixed, int cus);
 // Resident waves per compute unit of a kernel family: 0 first iteration,
-// 1 recurrence sweep, 2 recombination, 3 apply.
+// 1 recurrence sweep p >= 4, 2 sweep p = 2, 3 sweep p = 3, 4 apply.
 int sweep_waves_per_cu(int which, bool mixed);
 
 }  // namespace dl

@@ -294,7 +294,7 @@ dl_status run_build(dl_context *ctx, const Engine &e, const dl::Op &op, const do
     for (int pp = 2; pp <= e.m; ++pp) {
         dl::PassArgs a{};
         a.op = op;
-        a.t = ctx->tiles_recur;
+        a.t = ctx->tiles_pass(pp);
         a.u1 = (pp - 1 == 1) ? static_cast<const void *>(in) : e.bvec(pp - 1);
         a.u2 = (pp - 2 == 1) ? static_cast<const void *>(in) : (pp - 2 >= 2 ? e.bvec(pp - 2) : nullptr);
         a.uo = e.bvec(pp);
@@ -335,6 +335,11 @@ thread_local std::string g_init_error;
 }  // namespace
 
 using namespace dlh;
+
+// Rounds of resident waves per recurrence sweep (build-time tuning parameter).
+#ifndef DL_RECUR_ROUNDS
+#define DL_RECUR_ROUNDS 1
+#endif
 
 extern "C" {
 
@@ -396,17 +401,14 @@ dl_status dirac_lanczos_init(const dl_params *params, void *workspace, size_t ws
         // one resident round of waves per sweep (each wave marches its row chunk)
         const bool mixed = params->precision == DL_PREC_MIXED;
         const int wf = dl::sweep_waves_per_cu(0, mixed), wr = dl::sweep_waves_per_cu(1, mixed);
-        const int wc = dl::sweep_waves_per_cu(2, mixed), wa = dl::sweep_waves_per_cu(3, mixed);
+        const int wa = dl::sweep_waves_per_cu(4, mixed);
+        const int w2 = dl::sweep_waves_per_cu(2, mixed), w3 = dl::sweep_waves_per_cu(3, mixed);
         ctx->tiles_first = dl::make_tiles(params->nx, params->ny, 1, wf * ctx->cus);
-        ctx->tiles_recur = dl::make_tiles(params->nx, params->ny, 2, wr * ctx->cus);
+        ctx->tiles_recur = dl::make_tiles(params->nx, params->ny, 2, wr * ctx->cus * DL_RECUR_ROUNDS);
+        ctx->tiles_p2 = dl::make_tiles(params->nx, params->ny, 2, w2 * ctx->cus * DL_RECUR_ROUNDS);
+        ctx->tiles_p3 = dl::make_tiles(params->nx, params->ny, 2, w3 * ctx->cus * DL_RECUR_ROUNDS);
         ctx->tiles_apply = dl::make_tiles(params->nx, params->ny, 1, wa * ctx->cus);
-        const size_t items = vec_elems(*params) / 2;  // one site per thread
-        const size_t need = (items + dl::kBlock - 1) / dl::kBlock;
-        size_t nb = (size_t)(wc / dl::kWaves) * ctx->cus;
-        if (nb > need) nb = need;
-        if (nb < 1) nb = 1;
-        if (nb > (size_t)kMaxBlocks) nb = kMaxBlocks;
-        ctx->combine_blocks = (int)nb;
+        ctx->combine_blocks = dl::combine_grid(vec_elems(*params) / 2, mixed, ctx->cus);
     }
     dl::launch_reset(ctx->sc(), ctx->stream);
     hipError_t e = hipGetLastError();
@@ -560,7 +562,10 @@ dl_status dirac_lanczos_eigen(dl_context *ctx, const void *psi0, int32_t k_max, 
     hipStream_t st = ctx->stream;
     const dl::Op op = ctx->op(1.0);
     const dl::Tiles &t1 = ctx->tiles_first;
-    const dl::Tiles &t2 = ctx->tiles_recur;
+    // the eigen sweeps run the complex128 kernels whatever the context precision
+    dl::Tiles tp[3];
+    for (int kind = 0; kind < 3; ++kind)
+        tp[kind] = dl::make_tiles(p.nx, p.ny, 2, dl::sweep_waves_per_cu(kind == 2 ? 1 : kind + 2, false) * ctx->cus);
     const double zero[2] = {0.0, 0.0};
     DL_HIP(ctx, hipMemcpyAsync(fields, zero, sizeof(zero), hipMemcpyHostToDevice, st));
     DL_HIP(ctx, hipMemcpyAsync(v[1], psi0, n * 16, hipMemcpyDeviceToDevice, st));
@@ -570,7 +575,7 @@ dl_status dirac_lanczos_eigen(dl_context *ctx, const void *psi0, int32_t k_max, 
     for (int pp = 2; pp <= K1; ++pp) {
         dl::PassArgs a{};
         a.op = op;
-        a.t = t2;
+        a.t = tp[pp == 2 ? 0 : (pp == 3 ? 1 : 2)];
         a.u1 = v[(pp - 1) % 3];
         a.u2 = pp >= 3 ? v[(pp - 2) % 3] : nullptr;
         a.uo = v[pp % 3];

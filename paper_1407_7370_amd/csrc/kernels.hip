@@ -134,23 +134,32 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const char *p, uint32
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(p), (short)0, (int)bytes, kRsrcWord3);
 }
 
-template <class X>
+// Cache-policy operand of buffer loads and stores: 0 default, 2 the
+// nontemporal (streaming) hint.
+constexpr int kPolDefault = 0;
+constexpr int kPolStream = 2;
+#ifndef DL_SWEEP_STORE_POLICY
+#define DL_SWEEP_STORE_POLICY kPolDefault
+#endif
+
+template <class X, int POL = kPolDefault>
 __device__ __forceinline__ X ld16(__amdgpu_buffer_rsrc_t r, uint32_t off)
 {
     static_assert(sizeof(X) == 16, "16-byte access");
-    return __builtin_bit_cast(X, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    return __builtin_bit_cast(X, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, POL));
 }
 
 template <class X>
 __device__ __forceinline__ void st16(__amdgpu_buffer_rsrc_t r, uint32_t off, const X &v)
 {
     static_assert(sizeof(X) == 16, "16-byte access");
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4i, v), r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4i, v), r, off, 0, DL_SWEEP_STORE_POLICY);
 }
 
 // Vector views.  Planar: the caller's state layout (two component planes of
 // complex128).  Paired: Krylov vectors, both components of a site adjacent.
-struct Planar {
+template <int POL>
+struct PlanarT {
     using T = double2;
     const char *base;
     size_t plane_bytes;
@@ -160,14 +169,19 @@ struct Planar {
         const char *r = base + (size_t)jw * row_bytes;
         const uint32_t n = row_ok ? row_bytes : 0u;
         Raw<double2> v;
-        v.a = ld16<double2>(row_rsrc(r, n), off);
-        v.b = ld16<double2>(row_rsrc(r + plane_bytes, n), off);
+        v.a = ld16<double2, POL>(row_rsrc(r, n), off);
+        v.b = ld16<double2, POL>(row_rsrc(r + plane_bytes, n), off);
         return v;
     }
     static __device__ __forceinline__ uint32_t lane_offset(int colw) { return (uint32_t)colw * 16u; }
 };
+using Planar = PlanarT<kPolDefault>;
+template <class V>
+struct is_planar : std::false_type {};
+template <int POL>
+struct is_planar<PlanarT<POL>> : std::true_type {};
 
-template <class TT>
+template <class TT, int POL = kPolDefault>
 struct Paired {
     using T = TT;
     const char *base;
@@ -176,11 +190,11 @@ struct Paired {
     {
         const __amdgpu_buffer_rsrc_t r = row_rsrc(base + (size_t)jw * row_bytes, row_ok ? row_bytes : 0u);
         if constexpr (sizeof(T) == 8) {
-            return ld16<Raw<T>>(r, off);
+            return ld16<Raw<T>, POL>(r, off);
         } else {
             Raw<T> v;
-            v.a = ld16<T>(r, off);
-            v.b = ld16<T>(r, off + 16u);
+            v.a = ld16<T, POL>(r, off);
+            v.b = ld16<T, POL>(r, off + 16u);
             return v;
         }
     }
@@ -302,11 +316,29 @@ struct WaveTask {
     int strip, y0, y1;
 };
 
+// Workgroups are dispatched to the eight XCDs of the chip round robin
+// (workgroup b to XCD b mod 8), and each XCD has its own L2.  With the XCD
+// map on, consecutive logical workgroups -- adjacent strips of one row chunk,
+// which share their halo columns -- run on the same XCD.
+#ifndef DL_XCD_MAP
+#define DL_XCD_MAP 1
+#endif
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int logical_block()
+{
+    const int b = (int)blockIdx.x;
+    if (!DL_XCD_MAP) return b;
+    const int nb = (int)gridDim.x, q = nb / kXcds, r = nb % kXcds, x = b % kXcds;
+    const int first = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
+    return first + b / kXcds;
+}
+
 __device__ __forceinline__ WaveTask wave_task(const Op &op, const Tiles &t)
 {
     WaveTask w;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int task = (int)blockIdx.x * kWaves + wave;
+    const int task = logical_block() * kWaves + wave;
     w.active = task < t.nstrips * t.nchunks;
     w.strip = task % t.nstrips;
     const int chunk = task / t.nstrips;
@@ -403,12 +435,13 @@ __global__ __launch_bounds__(kBlock) void k_first(Op op, Tiles t, const double2 
 
 // ---------------------------------------------------------------------------
 // Lanczos iteration p >= 2 (see the file comment).  V1, V2: views of u_{p-1},
-// u_{p-2}; TO: storage type of u_p (paired layout); PF: FIFO depth in rows.
+// u_{p-2}; TO: storage type of u_p (paired layout); PF: FIFO depth in rows;
+// WPE: minimum resident waves per SIMD asked of the register allocator.
 // Rows marched: R = y0-2 .. y1+1 (u_{p-1} row R enters, u_p row R-1 is formed,
 // A u_p row R-2 is applied); ring slot of row r = (r - (y0-2)) mod 4.
 // ---------------------------------------------------------------------------
-template <class V1, class V2, class TO, bool HAS2, int PF>
-__global__ __launch_bounds__(kBlock) void k_recur(PassArgs a)
+template <class V1, class V2, class TO, bool HAS2, int PF, int WPE = 1>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_recur(PassArgs a)
 {
     static_assert(4 % PF == 0, "FIFO depth must divide the unroll");
     using T1 = typename V1::T;
@@ -433,11 +466,11 @@ __global__ __launch_bounds__(kBlock) void k_recur(PassArgs a)
         const size_t plane = (size_t)op.nx * op.ny;
         V1 v1;
         V2 v2;
-        if constexpr (std::is_same<V1, Planar>::value)
+        if constexpr (is_planar<V1>::value)
             v1 = V1{static_cast<const char *>(a.u1), plane * 16, (uint32_t)op.nx * 16u};
         else
             v1 = V1{static_cast<const char *>(a.u1), (uint32_t)(op.nx * 2 * sizeof(T1))};
-        if constexpr (std::is_same<V2, Planar>::value)
+        if constexpr (is_planar<V2>::value)
             v2 = V2{static_cast<const char *>(a.u2), plane * 16, (uint32_t)op.nx * 16u};
         else
             v2 = V2{static_cast<const char *>(a.u2), (uint32_t)(op.nx * 2 * sizeof(T2))};
@@ -675,54 +708,103 @@ __global__ __launch_bounds__(64) void k_tridiag(const double *alpha, const doubl
 
 // ---------------------------------------------------------------------------
 // Recombination psi_new = sum_j c_j q_j = sum_j (c_j / gamma_j) u_j
-// (eq. matrix_exp_approx): a site-local multi-axpy streamed over the sites,
-// one site (both components) per thread and eight Krylov vectors in flight,
-// plus ||psi_new||^2 for the step statistics.
+// (eq. matrix_exp_approx): a site-local multi-axpy, plus ||psi_new||^2 for the
+// step statistics.  A workgroup owns a tile of 256*S sites and streams the
+// Krylov vectors one after the other over it (S sites per thread, strided by
+// the workgroup so every load is coalesced), so each vector is read in long
+// contiguous runs.  The streams are read once and never reused: nontemporal
+// loads and stores keep them from displacing cache lines of the other
+// streams.
 // ---------------------------------------------------------------------------
+typedef double dv2 __attribute__((ext_vector_type(2)));
+typedef float fv4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double2 ld_stream(const double2 *p)
+{
+    const dv2 v = __builtin_nontemporal_load(reinterpret_cast<const dv2 *>(p));
+    return make_double2(v.x, v.y);
+}
+
+__device__ __forceinline__ void st_stream(double2 *p, double x, double y)
+{
+    dv2 v;
+    v.x = x;
+    v.y = y;
+    __builtin_nontemporal_store(v, reinterpret_cast<dv2 *>(p));
+}
+
 template <class TB>
-__global__ __launch_bounds__(kBlock) void k_combine(CombArgs a)
+__device__ __forceinline__ Raw<TB> ld_site(const char *p);
+template <>
+__device__ __forceinline__ Raw<float2> ld_site<float2>(const char *p)
+{
+    const fv4 v = __builtin_nontemporal_load(reinterpret_cast<const fv4 *>(p));
+    return Raw<float2>{make_float2(v.x, v.y), make_float2(v.z, v.w)};
+}
+template <>
+__device__ __forceinline__ Raw<double2> ld_site<double2>(const char *p)
+{
+    return Raw<double2>{ld_stream(reinterpret_cast<const double2 *>(p)),
+                        ld_stream(reinterpret_cast<const double2 *>(p) + 1)};
+}
+
+// WPE: minimum resident waves per SIMD asked of the register allocator.
+template <class TB, int S, int WPE>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_combine(CombArgs a)
 {
     Scalars *sc = a.sc;
     if (sc->status != 0) return;
     const int k = sc->keff;
     const char *__restrict__ basis = static_cast<const char *>(a.basis);
     const size_t sites = a.sites;
+    const size_t tile = (size_t)kBlock * S;
+    constexpr size_t kSite = 2 * sizeof(TB);
     double nrm = 0.0;
-    const double c1r = sc->coef[2], c1i = sc->coef[3];
-    for (size_t s = (size_t)blockIdx.x * kBlock + threadIdx.x; s < sites; s += (size_t)gridDim.x * kBlock) {
-        const double2 p0 = a.psi[s], p1 = a.psi[sites + s];
-        Sp acc;
-        if (k >= 1) {
-            acc.r0 = c1r * p0.x - c1i * p0.y;
-            acc.i0 = c1r * p0.y + c1i * p0.x;
-            acc.r1 = c1r * p1.x - c1i * p1.y;
-            acc.i1 = c1r * p1.y + c1i * p1.x;
-        } else {
-            acc = sp_zero();
-        }
-        const size_t soff = s * sizeof(Raw<TB>);
-        for (int jb = 2; jb <= k; jb += 8) {
-            Raw<TB> v[8];
+    for (size_t s0 = (size_t)blockIdx.x * tile; s0 < sites; s0 += (size_t)gridDim.x * tile) {
+        Sp acc[S];
+        {
+            const double cr = k >= 1 ? sc->coef[2] : 0.0, ci = k >= 1 ? sc->coef[3] : 0.0;
 #pragma unroll
-            for (int t = 0; t < 8; ++t)
-                if (jb + t <= k)
-                    v[t] = *reinterpret_cast<const Raw<TB> *>(basis + (size_t)(jb + t - 2) * a.vec_bytes + soff);
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const int j = jb + t;
-                if (j <= k) {
-                    const Sp u = to_sp(v[t]);
-                    const double cr = sc->coef[2 * j], ci = sc->coef[2 * j + 1];
-                    acc.r0 += cr * u.r0 - ci * u.i0;
-                    acc.i0 += cr * u.i0 + ci * u.r0;
-                    acc.r1 += cr * u.r1 - ci * u.i1;
-                    acc.i1 += cr * u.i1 + ci * u.r1;
+            for (int q = 0; q < S; ++q) {
+                const size_t s = s0 + (size_t)q * kBlock + threadIdx.x;
+                double2 p0 = make_double2(0.0, 0.0), p1 = p0;
+                if (s < sites) {
+                    p0 = ld_stream(a.psi + s);
+                    p1 = ld_stream(a.psi + sites + s);
                 }
+                acc[q].r0 = cr * p0.x - ci * p0.y;
+                acc[q].i0 = cr * p0.y + ci * p0.x;
+                acc[q].r1 = cr * p1.x - ci * p1.y;
+                acc[q].i1 = cr * p1.y + ci * p1.x;
             }
         }
-        a.out[s] = make_double2(acc.r0, acc.i0);
-        a.out[sites + s] = make_double2(acc.r1, acc.i1);
-        nrm += sp_norm2(acc);
+        for (int j = 2; j <= k; ++j) {
+            const char *u = basis + (size_t)(j - 2) * a.vec_bytes;
+            Raw<TB> v[S];
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                const size_t s = s0 + (size_t)q * kBlock + threadIdx.x;
+                v[q] = s < sites ? ld_site<TB>(u + s * kSite) : raw_zero<TB>();
+            }
+            const double cr = sc->coef[2 * j], ci = sc->coef[2 * j + 1];
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                const Sp w = to_sp(v[q]);
+                acc[q].r0 += cr * w.r0 - ci * w.i0;
+                acc[q].i0 += cr * w.i0 + ci * w.r0;
+                acc[q].r1 += cr * w.r1 - ci * w.i1;
+                acc[q].i1 += cr * w.i1 + ci * w.r1;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const size_t s = s0 + (size_t)q * kBlock + threadIdx.x;
+            if (s < sites) {
+                st_stream(a.out + s, acc[q].r0, acc[q].i0);
+                st_stream(a.out + sites + s, acc[q].r1, acc[q].i1);
+                nrm += sp_norm2(acc[q]);
+            }
+        }
     }
     double accv[1] = {nrm}, tot[1];
     if (!grid_reduce(accv, a.partials, &sc->ticket, tot)) return;
@@ -736,6 +818,13 @@ __global__ __launch_bounds__(kBlock) void k_combine(CombArgs a)
         sc->steps_done += 1;
     }
 }
+
+// sites per thread of the recombination and the occupancy asked for (five
+// waves per SIMD fit the complex64 form without spills)
+constexpr int kCombMixed = 4;
+constexpr int kCombFp64 = 8;
+constexpr int kCombWpeMixed = 5;
+constexpr int kCombWpeFp64 = 1;
 
 // ---------------------------------------------------------------------------
 // y = H x (test hook; operator scale 1).
@@ -785,13 +874,34 @@ __global__ void k_reset(Scalars *sc)
 }
 
 // FIFO depths (rows of loads in flight per wave).
+#ifndef DL_PF_MIXED
+#define DL_PF_MIXED 2
+#endif
+#ifndef DL_PF_FP64
+#define DL_PF_FP64 2
+#endif
+#ifndef DL_WPE_MIXED
+#define DL_WPE_MIXED 3
+#endif
 constexpr int kPfFirst = 4;
-constexpr int kPfMixed = 4;
-constexpr int kPfFp64 = 2;
+constexpr int kPfMixed = DL_PF_MIXED;
+constexpr int kPfFp64 = DL_PF_FP64;
+// three waves per SIMD fit the complex64 sweeps without spills; the
+// complex128 ones would spill
+constexpr int kWpeMixed = DL_WPE_MIXED;
 
-using PlanarV = Planar;
-template <class T>
-using PairedV = Paired<T>;
+// Load policy of the sweeps per precision (measured on the 4096^2 workload:
+// the streaming hint helps the complex64 sweeps and hurts the complex128 ones).
+#ifndef DL_LOAD_POL_MIXED
+#define DL_LOAD_POL_MIXED kPolStream
+#endif
+#ifndef DL_LOAD_POL_FP64
+#define DL_LOAD_POL_FP64 kPolDefault
+#endif
+using PlanarM = PlanarT<DL_LOAD_POL_MIXED>;
+using PairedM = Paired<float2, DL_LOAD_POL_MIXED>;
+using PlanarD = PlanarT<DL_LOAD_POL_FP64>;
+using PairedD = Paired<double2, DL_LOAD_POL_FP64>;
 
 template <class K>
 int waves_per_cu(K kernel)
@@ -811,11 +921,26 @@ int sweep_waves_per_cu(int which, bool mixed)
     switch (which) {
     case 0: return waves_per_cu(k_first<kPfFirst>);
     case 1:
-        return mixed ? waves_per_cu(k_recur<PairedV<float2>, PairedV<float2>, float2, true, kPfMixed>)
-                     : waves_per_cu(k_recur<PairedV<double2>, PairedV<double2>, double2, true, kPfFp64>);
-    case 2: return mixed ? waves_per_cu(k_combine<float2>) : waves_per_cu(k_combine<double2>);
+        return mixed ? waves_per_cu(k_recur<PairedM, PairedM, float2, true, kPfMixed, kWpeMixed>)
+                     : waves_per_cu(k_recur<PairedD, PairedD, double2, true, kPfFp64>);
+    case 2:
+        return mixed ? waves_per_cu(k_recur<PlanarM, PlanarM, float2, false, kPfMixed, kWpeMixed>)
+                     : waves_per_cu(k_recur<PlanarD, PlanarD, double2, false, kPfFp64>);
+    case 3:
+        return mixed ? waves_per_cu(k_recur<PairedM, PlanarM, float2, true, kPfMixed, 1>)
+                     : waves_per_cu(k_recur<PairedD, PlanarD, double2, true, kPfFp64>);
     default: return waves_per_cu(k_apply);
     }
+}
+
+int combine_grid(size_t sites, bool mixed, int cus)
+{
+    // eight workgroups per compute unit (measured best for the tiled stream),
+    // never more than there are tiles
+    const size_t tile = (size_t)kBlock * (mixed ? kCombMixed : kCombFp64);
+    size_t nb = std::min<size_t>((size_t)8 * cus, (sites + tile - 1) / tile);
+    nb = std::max<size_t>(nb, 1);
+    return (int)std::min<size_t>(nb, kMaxBlocks);
 }
 
 Tiles make_tiles(int nx, int ny, int halo, int target_waves)
@@ -851,20 +976,18 @@ void launch_recur(const PassArgs &a, bool mixed, hipStream_t st)
     const dim3 g(a.t.nblocks), b(kBlock);
     if (!mixed) {
         if (a.pass == 2)
-            hipLaunchKernelGGL((k_recur<PlanarV, PlanarV, double2, false, kPfFp64>), g, b, 0, st, a);
+            hipLaunchKernelGGL((k_recur<PlanarD, PlanarD, double2, false, kPfFp64>), g, b, 0, st, a);
         else if (a.pass == 3)
-            hipLaunchKernelGGL((k_recur<PairedV<double2>, PlanarV, double2, true, kPfFp64>), g, b, 0, st, a);
+            hipLaunchKernelGGL((k_recur<PairedD, PlanarD, double2, true, kPfFp64>), g, b, 0, st, a);
         else
-            hipLaunchKernelGGL((k_recur<PairedV<double2>, PairedV<double2>, double2, true, kPfFp64>), g, b,
-                               0, st, a);
+            hipLaunchKernelGGL((k_recur<PairedD, PairedD, double2, true, kPfFp64>), g, b, 0, st, a);
     } else {
         if (a.pass == 2)
-            hipLaunchKernelGGL((k_recur<PlanarV, PlanarV, float2, false, kPfMixed>), g, b, 0, st, a);
+            hipLaunchKernelGGL((k_recur<PlanarM, PlanarM, float2, false, kPfMixed, kWpeMixed>), g, b, 0, st, a);
         else if (a.pass == 3)
-            hipLaunchKernelGGL((k_recur<PairedV<float2>, PlanarV, float2, true, kPfMixed>), g, b, 0, st, a);
+            hipLaunchKernelGGL((k_recur<PairedM, PlanarM, float2, true, kPfMixed, 1>), g, b, 0, st, a);
         else
-            hipLaunchKernelGGL((k_recur<PairedV<float2>, PairedV<float2>, float2, true, kPfMixed>), g, b, 0,
-                               st, a);
+            hipLaunchKernelGGL((k_recur<PairedM, PairedM, float2, true, kPfMixed, kWpeMixed>), g, b, 0, st, a);
     }
 }
 
@@ -877,9 +1000,9 @@ void launch_tridiag(const double *alpha, const double *gamma, Scalars *sc, StepS
 void launch_combine(const CombArgs &a, bool mixed, int nblocks, hipStream_t st)
 {
     if (mixed)
-        hipLaunchKernelGGL(k_combine<float2>, dim3(nblocks), dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL((k_combine<float2, kCombMixed, kCombWpeMixed>), dim3(nblocks), dim3(kBlock), 0, st, a);
     else
-        hipLaunchKernelGGL(k_combine<double2>, dim3(nblocks), dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL((k_combine<double2, kCombFp64, kCombWpeFp64>), dim3(nblocks), dim3(kBlock), 0, st, a);
 }
 
 void launch_apply(const Op &op, const Tiles &t, const double2 *x, double2 *y, double gxh,

@@ -271,9 +271,13 @@ def test_invalid_calls(torch_cuda, Prop):
     import ctypes
     loss = ctypes.c_double(0)
     grad = (ctypes.c_double * 16)()
-    st = binding.dirac_lanczos_adjoint(prop.ctx, psi.data_ptr(), 0.0, 1e-3, 10, 5, 0,
+    # loss_kind 0 selects no observable; a missing adjoint workspace is also rejected
+    st = binding.dirac_lanczos_adjoint(prop.ctx, psi.data_ptr(), 0.0, 1e-3, 10, 5, 0, 0, 0,
                                        ctypes.byref(loss), grad)
-    assert st == binding.DL_ERR_UNSUPPORTED
+    assert st == binding.DL_ERR_INVALID
+    st = binding.dirac_lanczos_adjoint(prop.ctx, psi.data_ptr(), 0.0, 1e-3, 10, 5, 1, 0, 0,
+                                       ctypes.byref(loss), grad)
+    assert st in (binding.DL_ERR_UNSUPPORTED, binding.DL_ERR_WORKSPACE)
     prop.close()
 
 
