@@ -150,7 +150,9 @@ Tiles make_tiles(int nx, int ny, int halo, int target_waves);
 // Workgroups of the recombination for `sites` sites (<= kMaxBlocks).
 int combine_grid(size_t sites, bool mixed, int cus);
 // Resident waves per compute unit of a kernel family: 0 first iteration,
-// 1 recurrence sweep p >= 4, 2 sweep p = 2, 3 sweep p = 3, 4 apply.
-int sweep_waves_per_cu(int which, bool mixed);
+// 1 recurrence sweep p >= 4, 2 sweep p = 2, 3 sweep p = 3, 4 apply; py:
+// periodic in y, site: site-dependent diagonal or coupling (sweep_site_terms).
+int sweep_waves_per_cu(int which, bool mixed, bool py, bool site);
+bool sweep_site_terms(const Op &op);
 
 }  // namespace dl

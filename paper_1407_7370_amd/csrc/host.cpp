@@ -336,10 +336,20 @@ thread_local std::string g_init_error;
 
 using namespace dlh;
 
-// Rounds of resident waves per recurrence sweep (build-time tuning parameter).
+// Rounds of resident waves per recurrence sweep, and a cap on the waves per
+// compute unit of a sweep (0: as many as fit).  Build-time tuning parameters;
+// eight waves per compute unit (two per SIMD) measured best on the 4096^2
+// workload: more concurrent row streams lower the DRAM efficiency.
 #ifndef DL_RECUR_ROUNDS
 #define DL_RECUR_ROUNDS 1
 #endif
+#ifndef DL_RECUR_WAVES_PER_CU
+#define DL_RECUR_WAVES_PER_CU 8
+#endif
+
+namespace {
+int cap_waves(int w) { return DL_RECUR_WAVES_PER_CU > 0 ? std::min(w, DL_RECUR_WAVES_PER_CU) : w; }
+}  // namespace
 
 extern "C" {
 
@@ -400,10 +410,13 @@ dl_status dirac_lanczos_init(const dl_params *params, void *workspace, size_t ws
     {
         // one resident round of waves per sweep (each wave marches its row chunk)
         const bool mixed = params->precision == DL_PREC_MIXED;
-        const int wf = dl::sweep_waves_per_cu(0, mixed), wr = dl::sweep_waves_per_cu(1, mixed);
-        const int wa = dl::sweep_waves_per_cu(4, mixed);
-        const int w2 = dl::sweep_waves_per_cu(2, mixed), w3 = dl::sweep_waves_per_cu(3, mixed);
-        ctx->tiles_first = dl::make_tiles(params->nx, params->ny, 1, wf * ctx->cus);
+        const bool py = params->bc_y != 0, site = dl::sweep_site_terms(ctx->op(1.0));
+        const int wf = dl::sweep_waves_per_cu(0, mixed, py, site);
+        const int wr = cap_waves(dl::sweep_waves_per_cu(1, mixed, py, site));
+        const int wa = dl::sweep_waves_per_cu(4, mixed, py, site);
+        const int w2 = cap_waves(dl::sweep_waves_per_cu(2, mixed, py, site));
+        const int w3 = cap_waves(dl::sweep_waves_per_cu(3, mixed, py, site));
+        ctx->tiles_first = dl::make_tiles(params->nx, params->ny, 1, cap_waves(wf) * ctx->cus);
         ctx->tiles_recur = dl::make_tiles(params->nx, params->ny, 2, wr * ctx->cus * DL_RECUR_ROUNDS);
         ctx->tiles_p2 = dl::make_tiles(params->nx, params->ny, 2, w2 * ctx->cus * DL_RECUR_ROUNDS);
         ctx->tiles_p3 = dl::make_tiles(params->nx, params->ny, 2, w3 * ctx->cus * DL_RECUR_ROUNDS);
@@ -565,7 +578,9 @@ dl_status dirac_lanczos_eigen(dl_context *ctx, const void *psi0, int32_t k_max, 
     // the eigen sweeps run the complex128 kernels whatever the context precision
     dl::Tiles tp[3];
     for (int kind = 0; kind < 3; ++kind)
-        tp[kind] = dl::make_tiles(p.nx, p.ny, 2, dl::sweep_waves_per_cu(kind == 2 ? 1 : kind + 2, false) * ctx->cus);
+        tp[kind] = dl::make_tiles(p.nx, p.ny, 2,
+                                  dl::sweep_waves_per_cu(kind == 2 ? 1 : kind + 2, false, p.bc_y != 0,
+                                                         dl::sweep_site_terms(op)) * ctx->cus);
     const double zero[2] = {0.0, 0.0};
     DL_HIP(ctx, hipMemcpyAsync(fields, zero, sizeof(zero), hipMemcpyHostToDevice, st));
     DL_HIP(ctx, hipMemcpyAsync(v[1], psi0, n * 16, hipMemcpyDeviceToDevice, st));

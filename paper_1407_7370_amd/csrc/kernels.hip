@@ -30,6 +30,7 @@
 #include <algorithm>
 #include <cmath>
 #include <type_traits>
+#include <utility>
 
 #include "dl_internal.h"
 #include "device_reduce.h"
@@ -39,6 +40,13 @@ namespace {
 
 template <int K>
 using IC = std::integral_constant<int, K>;
+
+// f(IC<0>{}), ..., f(IC<N-1>{}) in order (compile-time unrolled steps).
+template <class F, int... K>
+__device__ __forceinline__ void unroll_steps(F &&f, std::integer_sequence<int, K...>)
+{
+    (f(IC<K>{}), ...);
+}
 
 struct Sp {
     double r0, i0, r1, i1;  // component 0 (re, im), component 1 (re, im)
@@ -173,6 +181,14 @@ struct PlanarT {
         v.b = ld16<double2, POL>(row_rsrc(r + plane_bytes, n), off);
         return v;
     }
+    // Row at address `row` (first plane) with `n` valid bytes (0: returns zeros).
+    __device__ __forceinline__ Raw<double2> load_at(const char *row, uint32_t n, uint32_t off) const
+    {
+        Raw<double2> v;
+        v.a = ld16<double2, POL>(row_rsrc(row, n), off);
+        v.b = ld16<double2, POL>(row_rsrc(row + plane_bytes, n), off);
+        return v;
+    }
     static __device__ __forceinline__ uint32_t lane_offset(int colw) { return (uint32_t)colw * 16u; }
 };
 using Planar = PlanarT<kPolDefault>;
@@ -196,6 +212,29 @@ struct Paired {
             v.a = ld16<T, POL>(r, off);
             v.b = ld16<T, POL>(r, off + 16u);
             return v;
+        }
+    }
+    __device__ __forceinline__ Raw<T> load_at(const char *row, uint32_t n, uint32_t off) const
+    {
+        const __amdgpu_buffer_rsrc_t r = row_rsrc(row, n);
+        if constexpr (sizeof(T) == 8) {
+            return ld16<Raw<T>, POL>(r, off);
+        } else {
+            Raw<T> v;
+            v.a = ld16<T, POL>(r, off);
+            v.b = ld16<T, POL>(r, off + 16u);
+            return v;
+        }
+    }
+    // Store to the row at `row` with `n` valid bytes (0: the store is dropped).
+    __device__ __forceinline__ void store_at(const char *row, uint32_t n, uint32_t off, const Raw<T> &v) const
+    {
+        const __amdgpu_buffer_rsrc_t r = row_rsrc(row, n);
+        if constexpr (sizeof(T) == 8) {
+            st16(r, off, v);
+        } else {
+            st16(r, off, v.a);
+            st16(r, off + 16u, v.b);
         }
     }
     __device__ __forceinline__ void store(int jw, uint32_t off, const Raw<T> &v) const
@@ -348,56 +387,133 @@ __device__ __forceinline__ WaveTask wave_task(const Op &op, const Tiles &t)
     return w;
 }
 
+// Scalar cursor over the rows of one vector: the (unwrapped) address of row r,
+// advanced by one row per step.  Rows outside a Dirichlet domain or outside
+// the needed range get a zero-size descriptor: loads return zeros and stores
+// are dropped, with no branch.
+template <bool PY>
+struct RowCursor {
+    uint64_t addr;  // base + r * rb
+    int r;
+    uint32_t rb;    // bytes per row
+    uint64_t span;  // ny * rb (periodic wrap)
+    int lo;         // first valid row
+    uint32_t width; // number of valid rows: lo .. lo + width - 1
+    __device__ __forceinline__ const char *ptr(int ny) const
+    {
+        uint64_t x = addr;
+        if constexpr (PY) x = r < 0 ? x + span : (r >= ny ? x - span : x);
+        return reinterpret_cast<const char *>(x);
+    }
+    __device__ __forceinline__ uint32_t bytes() const { return (uint32_t)(r - lo) < width ? rb : 0u; }
+    __device__ __forceinline__ void next()
+    {
+        addr += rb;
+        ++r;
+    }
+};
+
+// Cursor at row r whose valid rows are lo .. hi intersected with the domain
+// (Dirichlet) -- every row of the rim is a valid periodic image.
+template <bool PY>
+__device__ __forceinline__ RowCursor<PY> row_cursor(const void *base, uint32_t rb, int ny, int r, int lo, int hi)
+{
+    RowCursor<PY> c;
+    c.addr = reinterpret_cast<uint64_t>(base) + (uint64_t)((int64_t)r * (int64_t)rb);
+    c.r = r;
+    c.rb = rb;
+    c.span = (uint64_t)ny * rb;
+    if (!PY) {
+        lo = max(lo, 0);
+        hi = min(hi, ny - 1);
+    }
+    c.lo = lo;
+    c.width = hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
+    return c;
+}
+
+// Potential energy (times the operator scale) at column lg, wrapped row jw.
+__device__ __forceinline__ double site_pot_row(const Op &op, const LaneGeo &lg, int jw, double y)
+{
+    double v = 0.0;
+    if (op.pot_kind) v = -op.vz / sqrt(lg.x * lg.x + y * y + op.va2);
+    if (op.has_table && lg.inx) v += op.vscale * op.vtab[(size_t)jw * op.nx + lg.colw];
+    return v;
+}
+
+template <class V>
+__device__ __forceinline__ V make_view(const void *p, const Op &op)
+{
+    if constexpr (is_planar<V>::value)
+        return V{static_cast<const char *>(p), (size_t)op.nx * op.ny * 16, (uint32_t)op.nx * 16u};
+    else
+        return V{static_cast<const char *>(p), (uint32_t)(op.nx * 2 * sizeof(typename V::T))};
+}
+
+// Load policy of the first iteration's reads of psi.
+#ifndef DL_LOAD_POL_FIRST
+#define DL_LOAD_POL_FIRST kPolStream
+#endif
+using PlanarF = PlanarT<DL_LOAD_POL_FIRST>;
+
 // ---------------------------------------------------------------------------
 // Lanczos iteration 1: gamma_1 = ||psi||, alpha_1 = Re<psi, A psi>/||psi||^2,
 // and for m = 1 also beta_1 = ||A q_1 - alpha_1 q_1||.
 // Rows marched: psi rows y0-1 .. y1 (ring slot = row - (y0-1) mod 4).
 // ---------------------------------------------------------------------------
-template <int PF>
+template <int PF, bool PY, bool SITE>
 __global__ __launch_bounds__(kBlock) void k_first(Op op, Tiles t, const double2 *__restrict__ psi,
                                                   const double *__restrict__ field, double *alpha,
                                                   double *gamma, Scalars *sc, double *partials, int m,
                                                   int shift)
 {
-    static_assert(4 % PF == 0, "FIFO depth must divide the unroll");
+    constexpr int U = PF > 4 ? PF : 4;
+    static_assert(U % PF == 0 && U % 4 == 0, "FIFO depth must divide the unroll");
     if (sc->status != 0) return;
     const int lane = threadIdx.x & 63;
+    const int ny = op.ny;
     const WaveTask wt = wave_task(op, t);
     const double gxh = field[0], gyh = field[1];
     double acc[3] = {0.0, 0.0, 0.0};
     if (wt.active) {
         const LaneGeo lg = lane_geo(op, t, wt.strip, lane);
-        const double gy = gyh - op.bq * lg.x;
-        const Planar vin{reinterpret_cast<const char *>(psi), (size_t)op.nx * op.ny * 16,
-                         (uint32_t)op.nx * 16u};
-        const uint32_t off = lg.inx ? Planar::lane_offset(lg.colw) : kOob;
+        const double gy = SITE ? gyh - op.bq * lg.x : gyh;
+        const PlanarF vin = make_view<PlanarF>(psi, op);
+        const uint32_t off = lg.inx ? PlanarF::lane_offset(lg.colw) : kOob;
         const int y0 = wt.y0, y1 = wt.y1, base = y0 - 1;
+        RowCursor<PY> cin = row_cursor<PY>(psi, vin.row_bytes, ny, base, base, y1);
         Raw<double2> F[PF];
 #pragma unroll
-        for (int i = 0; i < PF; ++i) F[i] = load_row(vin, op, off, base + i, base + i <= y1);
+        for (int i = 0; i < PF; ++i) {
+            F[i] = vin.load_at(cin.ptr(ny), cin.bytes(), off);
+            cin.next();
+        }
         Sp P[4] = {sp_zero(), sp_zero(), sp_zero(), sp_zero()};
-        auto step = [&](auto kc, int R) {
-            constexpr int k = decltype(kc)::value;
+        int R0 = base;
+        auto step = [&](auto kc) {
+            constexpr int k = decltype(kc)::value & 3;
+            constexpr int f = decltype(kc)::value % PF;
+            const int R = R0 + decltype(kc)::value;
             if (R > y1) return;
-            P[k] = to_sp(F[k % PF]);
-            F[k % PF] = load_row(vin, op, off, R + PF, R + PF <= y1);
+            P[k] = to_sp(F[f]);
+            F[f] = vin.load_at(cin.ptr(ny), cin.bytes(), off);
+            cin.next();
             if (R - 1 < y0) return;
-            const Sp &c = P[(k + 3) & 3];  // row R-1
-            const RowGeo rg = row_geo(op, R - 1);
-            const Sp y = hop(op, c, sp_left(c), sp_right(c), P[(k + 2) & 3], P[k], site_pot(op, lg, rg),
-                             gxh + op.bq * rg.y, gy);
+            const Sp &c = P[(k + 3) & 3];  // row R-1 (inside the domain)
+            double v = 0.0, gx = gxh;
+            if constexpr (SITE) {
+                const double y = op.ymin + (R - 1) * op.hy;
+                v = site_pot_row(op, lg, R - 1, y);
+                gx = gxh + op.bq * y;
+            }
+            const Sp y = hop(op, c, sp_left(c), sp_right(c), P[(k + 2) & 3], P[k], v, gx, gy);
             if (lg.own) {
                 acc[0] += sp_norm2(c);
                 acc[1] += sp_redot(c, y);
                 acc[2] += sp_norm2(y);
             }
         };
-        for (int R = base; R <= y1; R += 4) {
-            step(IC<0>{}, R);
-            step(IC<1>{}, R + 1);
-            step(IC<2>{}, R + 2);
-            step(IC<3>{}, R + 3);
-        }
+        for (; R0 <= y1; R0 += U) unroll_steps(step, std::make_integer_sequence<int, U>{});
     }
     double tot[3];
     if (!grid_reduce(acc, partials, &sc->ticket, tot)) return;
@@ -436,14 +552,20 @@ __global__ __launch_bounds__(kBlock) void k_first(Op op, Tiles t, const double2 
 // ---------------------------------------------------------------------------
 // Lanczos iteration p >= 2 (see the file comment).  V1, V2: views of u_{p-1},
 // u_{p-2}; TO: storage type of u_p (paired layout); PF: FIFO depth in rows;
-// WPE: minimum resident waves per SIMD asked of the register allocator.
+// PY: periodic in y; SITE: the diagonal or the coupling varies over the grid
+// (potential, potential table or magnetic field), otherwise both are uniform
+// and computed once.
 // Rows marched: R = y0-2 .. y1+1 (u_{p-1} row R enters, u_p row R-1 is formed,
 // A u_p row R-2 is applied); ring slot of row r = (r - (y0-2)) mod 4.
 // ---------------------------------------------------------------------------
-template <class V1, class V2, class TO, bool HAS2, int PF, int WPE = 1>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_recur(PassArgs a)
+
+template <class V1, class V2, class TO, bool HAS2, int PF, bool PY, bool SITE>
+__global__ __launch_bounds__(kBlock) void k_recur(PassArgs a)
 {
-    static_assert(4 % PF == 0, "FIFO depth must divide the unroll");
+    // rows are marched U at a time so that every ring and FIFO slot index is a
+    // compile-time constant; the rings hold four rows (slot = row mod 4)
+    constexpr int U = PF > 4 ? PF : 4;
+    static_assert(U % PF == 0 && U % 4 == 0, "FIFO depth must divide the unroll");
     using T1 = typename V1::T;
     using T2 = typename V2::T;
     Scalars *sc = a.sc;
@@ -451,6 +573,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE, 8))
     if (sc->kstop < p) return;
     const bool last = (p == a.m);
     const Op &op = a.op;
+    const int ny = op.ny;
     const int lane = threadIdx.x & 63;
     const WaveTask wt = wave_task(op, a.t);
     const double g1 = a.gamma[p - 1];
@@ -462,71 +585,89 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE, 8))
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (wt.active) {
         const LaneGeo lg = lane_geo(op, a.t, wt.strip, lane);
-        const double gy = gyh - op.bq * lg.x;
-        const size_t plane = (size_t)op.nx * op.ny;
-        V1 v1;
-        V2 v2;
-        if constexpr (is_planar<V1>::value)
-            v1 = V1{static_cast<const char *>(a.u1), plane * 16, (uint32_t)op.nx * 16u};
-        else
-            v1 = V1{static_cast<const char *>(a.u1), (uint32_t)(op.nx * 2 * sizeof(T1))};
-        if constexpr (is_planar<V2>::value)
-            v2 = V2{static_cast<const char *>(a.u2), plane * 16, (uint32_t)op.nx * 16u};
-        else
-            v2 = V2{static_cast<const char *>(a.u2), (uint32_t)(op.nx * 2 * sizeof(T2))};
+        const double gy = SITE ? gyh - op.bq * lg.x : gyh;
+        // u_p = cw (A' u_{p-1}) - cc u_{p-1} - cu u_{p-2}; lanes outside the domain
+        // get zero coefficients, so their u_p is zero without a select
+        const double m = lg.inx ? 1.0 : 0.0;
+        const double cw = m * inv_g1, cc = m * ca, cu = m * cb;
+        const V1 v1 = make_view<V1>(a.u1, op);
+        const V2 v2 = make_view<V2>(a.u2, op);
         const Paired<TO> vo{static_cast<const char *>(a.uo), (uint32_t)(op.nx * 2 * sizeof(TO))};
         const uint32_t off1 = lg.inx ? V1::lane_offset(lg.colw) : kOob;
         const uint32_t off2 = lg.inx ? V2::lane_offset(lg.colw) : kOob;
         const uint32_t offo = lg.own ? Paired<TO>::lane_offset(lg.colw) : kOob;
         const int y0 = wt.y0, y1 = wt.y1, base = y0 - 2;
+        // cursors: u_{p-1} rows from base, u_{p-2} rows from base-1, u_p rows from base-1
+        RowCursor<PY> c1 = row_cursor<PY>(a.u1, v1.row_bytes, ny, base, base, y1 + 1);
+        RowCursor<PY> c2 = row_cursor<PY>(a.u2, v2.row_bytes, ny, base - 1, y0 - 1, y1);
+        RowCursor<PY> co = row_cursor<PY>(a.uo, vo.row_bytes, ny, base - 1, y0, y1 - 1);
         // FIFOs: u_{p-1} row r in slot (r-base) mod PF, needed rows y0-2 .. y1+1;
         //        u_{p-2} row r-1 in the same slot, needed rows y0-1 .. y1.
-        // Slots beyond the needed rows are simply not refilled.
         Raw<T1> F1[PF];
         Raw<T2> F2[PF];
 #pragma unroll
         for (int i = 0; i < PF; ++i) {
-            const int r = base + i;
-            F1[i] = load_row(v1, op, off1, r, r <= y1 + 1);
-            F2[i] = HAS2 ? load_row(v2, op, off2, r - 1, r - 1 >= y0 - 1 && r - 1 <= y1) : raw_zero<T2>();
+            F1[i] = v1.load_at(c1.ptr(ny), c1.bytes(), off1);
+            c1.next();
+            if (HAS2) {
+                F2[i] = v2.load_at(c2.ptr(ny), c2.bytes(), off2);
+                c2.next();
+            } else {
+                F2[i] = raw_zero<T2>();
+            }
         }
         Sp P[4] = {sp_zero(), sp_zero(), sp_zero(), sp_zero()};  // u_{p-1} rows
         Sp Q[4] = {sp_zero(), sp_zero(), sp_zero(), sp_zero()};  // u_p rows
-        double Vr[4] = {0.0, 0.0, 0.0, 0.0};                      // potential of the rows
-        auto step = [&](auto kc, int R) {
-            constexpr int k = decltype(kc)::value;
+        double Vr[4] = {0.0, 0.0, 0.0, 0.0};                      // potential of the rows (SITE)
+        int R0 = base;
+        auto step = [&](auto kc) {
+            constexpr int k = decltype(kc)::value & 3;   // ring slot of row R
+            constexpr int f = decltype(kc)::value % PF;  // FIFO slot of row R
+            const int R = R0 + decltype(kc)::value;
             if (R > y1 + 1) return;
-            P[k] = to_sp(F1[k % PF]);
-            const Sp o2 = to_sp(F2[k % PF]);
-            {
-                const int r = R + PF;
-                F1[k % PF] = load_row(v1, op, off1, r, r <= y1 + 1);
-                if (HAS2) F2[k % PF] = load_row(v2, op, off2, r - 1, r - 1 <= y1);
+            P[k] = to_sp(F1[f]);
+            const Sp o2 = to_sp(F2[f]);
+            // refill: u_{p-1} row R+PF, u_{p-2} row R+PF-1
+            F1[f] = v1.load_at(c1.ptr(ny), c1.bytes(), off1);
+            c1.next();
+            if (HAS2) {
+                F2[f] = v2.load_at(c2.ptr(ny), c2.bytes(), off2);
+                c2.next();
             }
             // u_p at row R-1 (rows y0-1 .. y1)
             if (R >= y0) {
-                const RowGeo rg = row_geo(op, R - 1);
-                const Sp &c = P[(k + 3) & 3];
-                const double v = site_pot(op, lg, rg);
-                Vr[(k + 3) & 3] = v;
-                const Sp w = hop(op, c, sp_left(c), sp_right(c), P[(k + 2) & 3], P[k], v,
-                                 gxh + op.bq * rg.y, gy, sig);
-                Sp u;
-                u.r0 = inv_g1 * w.r0 - ca * c.r0 - cb * o2.r0;
-                u.i0 = inv_g1 * w.i0 - ca * c.i0 - cb * o2.i0;
-                u.r1 = inv_g1 * w.r1 - ca * c.r1 - cb * o2.r1;
-                u.i1 = inv_g1 * w.i1 - ca * c.i1 - cb * o2.i1;
-                if (!(lg.inx && rg.iny)) u = sp_zero();
+                const int rr = R - 1;
+                Sp u = sp_zero();
+                if (PY || (unsigned)rr < (unsigned)ny) {
+                    const Sp &c = P[(k + 3) & 3];
+                    double v = 0.0, gx = gxh;
+                    if constexpr (SITE) {
+                        const int jw = rr < 0 ? rr + ny : (rr >= ny ? rr - ny : rr);
+                        const double y = op.ymin + jw * op.hy;
+                        v = site_pot_row(op, lg, jw, y);
+                        gx = gxh + op.bq * y;
+                        Vr[(k + 3) & 3] = v;
+                    }
+                    const Sp w = hop(op, c, sp_left(c), sp_right(c), P[(k + 2) & 3], P[k], v, gx, gy, sig);
+                    u.r0 = cw * w.r0 - cc * c.r0 - cu * o2.r0;
+                    u.i0 = cw * w.i0 - cc * c.i0 - cu * o2.i0;
+                    u.r1 = cw * w.r1 - cc * c.r1 - cu * o2.r1;
+                    u.i1 = cw * w.i1 - cc * c.i1 - cu * o2.i1;
+                }
                 const Raw<TO> ur = to_raw<TO>(u);
                 Q[(k + 3) & 3] = to_sp(ur);
-                if (R - 1 >= y0 && R - 1 < y1) vo.store(R - 1, offo, ur);
+                vo.store_at(co.ptr(ny), co.bytes(), offo, ur);
             }
-            // A u_p at row R-2 (rows y0 .. y1-1) and the reductions
+            co.next();
+            // A u_p at row R-2 (rows y0 .. y1-1, inside the domain) and the reductions
             if (R >= y0 + 2) {
-                const RowGeo rg = row_geo(op, R - 2);
                 const Sp &c = Q[(k + 2) & 3];
-                const Sp y = hop(op, c, sp_left(c), sp_right(c), Q[(k + 1) & 3], Q[(k + 3) & 3],
-                                 Vr[(k + 2) & 3], gxh + op.bq * rg.y, gy, sig);
+                double v = 0.0, gx = gxh;
+                if constexpr (SITE) {
+                    v = Vr[(k + 2) & 3];
+                    gx = gxh + op.bq * (op.ymin + (R - 2) * op.hy);
+                }
+                const Sp y = hop(op, c, sp_left(c), sp_right(c), Q[(k + 1) & 3], Q[(k + 3) & 3], v, gx, gy, sig);
                 if (lg.own) {
                     const Sp &prev = P[(k + 2) & 3];  // u_{p-1} row R-2
                     acc[0] += sp_norm2(c);
@@ -539,12 +680,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE, 8))
                 }
             }
         };
-        for (int R = base; R <= y1 + 1; R += 4) {
-            step(IC<0>{}, R);
-            step(IC<1>{}, R + 1);
-            step(IC<2>{}, R + 2);
-            step(IC<3>{}, R + 3);
-        }
+        for (; R0 <= y1 + 1; R0 += U) unroll_steps(step, std::make_integer_sequence<int, U>{});
     }
     double tot[5];
     if (!grid_reduce(acc, a.partials, &sc->ticket, tot)) return;
@@ -580,16 +716,32 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE, 8))
 }
 
 // ---------------------------------------------------------------------------
-// exp(-iT) e_1 through the eigendecomposition of the k x k tridiagonal T
-// (Sec. 4): implicit symmetric QR steps with Wilkinson shift.  One wave: lane
-// i holds diagonal d_i and coupling e_i (between i and i+1) in registers, the
-// bulge chase carries the two entries it is working on in registers and
-// fetches the next ones by lane shuffles one step ahead; deflation is a
-// ballot over the lanes.  Lane j owns row j of the eigenvector matrix in its
-// own LDS column.  Output: coef[j] = c_j / gamma_j with
-// c = ||psi|| V exp(-i Lambda) V^T e_1, and the step's error estimate
-// beta_k |c_k| (eq. matrix_exponential_error).
+// exp(-iT') e_1 for the k x k tridiagonal T' (Sec. 4, any standard method for
+// the small exponential; T' = T - sigma I is the shifted matrix of the sweeps)
+// in one wave, lane j holding row j.  Two methods, chosen by the Gershgorin
+// bound B of T':
+//  - B <= 64: scaling and Taylor series on the vector, exp(-iT') e_1 =
+//    (exp(-iT'/2^s))^(2^s) e_1 with 2^s >= B and 20 terms per factor (the
+//    truncation error of each factor is below 1/20!); one term is a
+//    tridiagonal product from the neighbouring lanes.  A few microseconds.
+//  - otherwise the eigendecomposition T' = Z Lambda Z^T by implicit symmetric
+//    QR steps with Wilkinson shift: lane i holds d_i and the coupling e_i in
+//    registers, the bulge chase fetches the next entries by shuffles one step
+//    ahead, deflation is a ballot, lane j owns row j of Z in its own LDS
+//    column; exp(-iT') e_1 = Z exp(-i Lambda) Z^T e_1.
+// Output: coef[j] = c_j / gamma_j with c = ||psi|| exp(-i sigma) exp(-iT') e_1,
+// and the step's error estimate beta_k |c_k| (eq. matrix_exponential_error).
 // ---------------------------------------------------------------------------
+constexpr int kTaylorTerms = 20;
+constexpr int kTaylorMaxDoublings = 6;
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) v = fmax(v, __shfl_xor(v, s, 64));
+    return v;
+}
+
 __global__ __launch_bounds__(64) void k_tridiag(const double *alpha, const double *gamma, Scalars *sc,
                                                 StepStat *stat)
 {
@@ -607,103 +759,131 @@ __global__ __launch_bounds__(64) void k_tridiag(const double *alpha, const doubl
         }
         return;
     }
-#define ZZ(i) zpr[(i) * 64 + lane]
     double d = (lane < k) ? alpha[lane + 1] : 0.0;
-    double e = (lane + 1 < k) ? gamma[lane + 2] : 0.0;
-    for (int i = 0; i < k; ++i) ZZ(i) = (i == lane) ? 1.0 : 0.0;
-    const double eps = 2.220446049250313e-16;
-    for (int iter = 0; iter < 40 * kMaxM; ++iter) {
-        // negligible couplings are set to zero; find the last unreduced block [l, h]
-        const double dn = __shfl_down(d, 1, 64);
-        const bool live = lane + 1 < k && e != 0.0;
-        const bool tiny = live && fabs(e) <= eps * (fabs(d) + fabs(dn));
-        if (tiny) e = 0.0;
-        const unsigned long long mask = __ballot(live && !tiny);
-        if (mask == 0ull) break;
-        const int hb = 63 - __clzll(mask);  // highest coupling still live
-        const unsigned long long below = ~mask & ((1ull << hb) - 1ull);
-        const int l = below ? 64 - __clzll(below) : 0;
-        const int h = hb + 1;
-        // Wilkinson shift from the trailing 2x2 block of [l, h]
-        const double dh1 = __shfl(d, h - 1, 64), dh = __shfl(d, h, 64), eh1 = __shfl(e, h - 1, 64);
-        const double delta = 0.5 * (dh1 - dh);
-        const double b2 = eh1 * eh1;
-        const double mu = dh - b2 / (delta + copysign(sqrt(delta * delta + b2), delta));
-        double aq = __shfl(d, l, 64);  // current d_q
-        double bq = __shfl(e, l, 64);  // current e_q
-        double x = aq - mu, z = bq;
-        double aq1n = __shfl(d, l + 1, 64);
-        double bq1n = (l + 1 < h) ? __shfl(e, l + 1, 64) : 0.0;
-        double zq = ZZ(l);
-        for (int q = l; q < h; ++q) {
-            const double aq1 = aq1n, bq1 = bq1n;
-            // entries of the next step, fetched ahead (lanes > q+1 are untouched so far)
-            aq1n = __shfl(d, min(q + 2, 63), 64);
-            bq1n = (q + 2 < h) ? __shfl(e, min(q + 2, 63), 64) : 0.0;
-            const double zq1 = ZZ(q + 1);
-            const double rr = x * x + z * z;
-            double c = 1.0, s = 0.0, r = 0.0;
-            if (rr > 0.0) {
-                const double ir = rsqrt(rr);
-                c = x * ir;
-                s = -z * ir;
-                r = rr * ir;
+    double e = (lane + 1 < k) ? gamma[lane + 2] : 0.0;  // zero for lanes >= k-1
+    double em = from_left(e);                           // e_{j-1}
+    if (lane == 0) em = 0.0;
+    const double bound = wave_max(fabs(d) + fabs(e) + fabs(em));
+    int sdbl = 0;
+    while (sdbl <= kTaylorMaxDoublings && ldexp(1.0, sdbl) < bound) ++sdbl;
+    double cr = 0.0, ci = 0.0;
+    if (sdbl <= kTaylorMaxDoublings) {
+        // v <- exp(-i h T') v, 2^s times, h = 2^-s
+        const double h = ldexp(1.0, -sdbl);
+        double vr = lane == 0 ? 1.0 : 0.0, vi = 0.0;
+        for (int rep = 0; rep < (1 << sdbl); ++rep) {
+            double tr = vr, ti = vi, wr = vr, wi = vi;
+            for (int n = 1; n <= kTaylorTerms; ++n) {
+                // u = T' t from the neighbouring lanes; t <- (-i h / n) u
+                const double ur = em * from_left(tr) + d * tr + e * from_right(tr);
+                const double ui = em * from_left(ti) + d * ti + e * from_right(ti);
+                const double f = h / n;
+                tr = f * ui;
+                ti = -f * ur;
+                wr += tr;
+                wi += ti;
             }
-            if (q > l && lane == q - 1) e = r;
-            const double cc = c * c, ss = s * s, cs = c * s;
-            const double dq = cc * aq - 2.0 * cs * bq + ss * aq1;
-            const double dq1 = ss * aq + 2.0 * cs * bq + cc * aq1;
-            const double eq = cs * (aq - aq1) + (cc - ss) * bq;
-            if (lane == q) d = dq;
-            ZZ(q) = c * zq - s * zq1;
-            zq = s * zq + c * zq1;
-            aq = dq1;
-            if (q + 1 < h) {
-                x = eq;
-                z = -s * bq1;
-                bq = c * bq1;
-            } else {
-                if (lane == q) e = eq;
-                if (lane == q + 1) d = dq1;
+            vr = wr;
+            vi = wi;
+        }
+        cr = vr;
+        ci = vi;
+    } else {
+#define ZZ(i) zpr[(i) * 64 + lane]
+        for (int i = 0; i < k; ++i) ZZ(i) = (i == lane) ? 1.0 : 0.0;
+        const double eps = 2.220446049250313e-16;
+        for (int iter = 0; iter < 40 * kMaxM; ++iter) {
+            // negligible couplings are set to zero; find the last unreduced block [l, h]
+            const double dn = __shfl_down(d, 1, 64);
+            const bool live = lane + 1 < k && e != 0.0;
+            const bool tiny = live && fabs(e) <= eps * (fabs(d) + fabs(dn));
+            if (tiny) e = 0.0;
+            const unsigned long long mask = __ballot(live && !tiny);
+            if (mask == 0ull) break;
+            const int hb = 63 - __clzll(mask);  // highest coupling still live
+            const unsigned long long below = ~mask & ((1ull << hb) - 1ull);
+            const int l = below ? 64 - __clzll(below) : 0;
+            const int h = hb + 1;
+            // Wilkinson shift from the trailing 2x2 block of [l, h]
+            const double dh1 = __shfl(d, h - 1, 64), dh = __shfl(d, h, 64), eh1 = __shfl(e, h - 1, 64);
+            const double delta = 0.5 * (dh1 - dh);
+            const double b2 = eh1 * eh1;
+            const double mu = dh - b2 / (delta + copysign(sqrt(delta * delta + b2), delta));
+            double aq = __shfl(d, l, 64);  // current d_q
+            double bq = __shfl(e, l, 64);  // current e_q
+            double x = aq - mu, z = bq;
+            double aq1n = __shfl(d, l + 1, 64);
+            double bq1n = (l + 1 < h) ? __shfl(e, l + 1, 64) : 0.0;
+            double zq = ZZ(l);
+            for (int q = l; q < h; ++q) {
+                const double aq1 = aq1n, bq1 = bq1n;
+                // entries of the next step, fetched ahead (lanes > q+1 are untouched so far)
+                aq1n = __shfl(d, min(q + 2, 63), 64);
+                bq1n = (q + 2 < h) ? __shfl(e, min(q + 2, 63), 64) : 0.0;
+                const double zq1 = ZZ(q + 1);
+                const double rr = x * x + z * z;
+                double c = 1.0, s = 0.0, r = 0.0;
+                if (rr > 0.0) {
+                    const double ir = rsqrt(rr);
+                    c = x * ir;
+                    s = -z * ir;
+                    r = rr * ir;
+                }
+                if (q > l && lane == q - 1) e = r;
+                const double cc = c * c, ss = s * s, cs = c * s;
+                const double dq = cc * aq - 2.0 * cs * bq + ss * aq1;
+                const double dq1 = ss * aq + 2.0 * cs * bq + cc * aq1;
+                const double eq = cs * (aq - aq1) + (cc - ss) * bq;
+                if (lane == q) d = dq;
+                ZZ(q) = c * zq - s * zq1;
+                zq = s * zq + c * zq1;
+                aq = dq1;
+                if (q + 1 < h) {
+                    x = eq;
+                    z = -s * bq1;
+                    bq = c * bq1;
+                } else {
+                    if (lane == q) e = eq;
+                    if (lane == q + 1) d = dq1;
+                }
+            }
+            ZZ(h) = zq;
+        }
+        // c_j = sum_i Z[j][i] exp(-i lambda_i) Z[0][i]; lambda_i is lane i's d
+        __syncthreads();
+        if (lane < k) {
+            double sn, cs;
+            sincos(d, &sn, &cs);
+            const double z0 = zpr[lane * 64 + 0];
+            wre[lane] = z0 * cs;
+            wim[lane] = -z0 * sn;
+        }
+        __syncthreads();
+        if (lane < k) {
+            for (int i = 0; i < k; ++i) {
+                const double zji = ZZ(i);
+                cr += zji * wre[i];
+                ci += zji * wim[i];
             }
         }
-        ZZ(h) = zq;
+#undef ZZ
     }
-    // c_j = gamma_1 sum_i Z[j][i] exp(-i lambda_i) Z[0][i]; lambda_i is lane i's d
-    __syncthreads();
     if (lane < k) {
-        double sn, cs;
-        sincos(d, &sn, &cs);
-        const double z0 = zpr[lane * 64 + 0];
-        wre[lane] = z0 * cs;
-        wim[lane] = -z0 * sn;
-    }
-    __syncthreads();
-    const double g1 = gamma[1];
-    if (lane < k) {
-        double cr = 0.0, ci = 0.0;
-        for (int i = 0; i < k; ++i) {
-            const double zji = ZZ(i);
-            cr += zji * wre[i];
-            ci += zji * wim[i];
-        }
         // exp(-iT) = exp(-i sigma) exp(-iT') for the shifted tridiagonal T'
         double ss, sc0;
         sincos(sc->sigma, &ss, &sc0);
+        const double g1 = gamma[1];
         const double tr = g1 * (cr * sc0 + ci * ss), ti = g1 * (ci * sc0 - cr * ss);
-        cr = tr;
-        ci = ti;
         const double ig = 1.0 / gamma[lane + 1];
-        sc->coef[2 * (lane + 1)] = cr * ig;
-        sc->coef[2 * (lane + 1) + 1] = ci * ig;
+        sc->coef[2 * (lane + 1)] = tr * ig;
+        sc->coef[2 * (lane + 1) + 1] = ti * ig;
         if (lane == k - 1) {
-            const double ck = sqrt(cr * cr + ci * ci);
+            const double ck = sqrt(tr * tr + ti * ti);
             sc->cabs_k = ck;
             stat->keff = k;
             stat->err_est = sc->beta_k * ck;
         }
     }
-#undef ZZ
 }
 
 // ---------------------------------------------------------------------------
@@ -821,7 +1001,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE, 8))
 
 // sites per thread of the recombination and the occupancy asked for (five
 // waves per SIMD fit the complex64 form without spills)
-constexpr int kCombMixed = 4;
+#ifndef DL_COMB_S_MIXED
+#define DL_COMB_S_MIXED 4
+#endif
+#ifndef DL_COMB_BLOCKS_PER_CU
+#define DL_COMB_BLOCKS_PER_CU 4
+#endif
+constexpr int kCombMixed = DL_COMB_S_MIXED;
 constexpr int kCombFp64 = 8;
 constexpr int kCombWpeMixed = 5;
 constexpr int kCombWpeFp64 = 1;
@@ -881,13 +1067,13 @@ __global__ void k_reset(Scalars *sc)
 #define DL_PF_FP64 2
 #endif
 #ifndef DL_WPE_MIXED
-#define DL_WPE_MIXED 3
+#define DL_WPE_MIXED 1
 #endif
 constexpr int kPfFirst = 4;
 constexpr int kPfMixed = DL_PF_MIXED;
 constexpr int kPfFp64 = DL_PF_FP64;
-// three waves per SIMD fit the complex64 sweeps without spills; the
-// complex128 ones would spill
+// occupancy hint of the complex64 sweeps (1: none).  Three waves per SIMD fit
+// them without spills but measured slower than the two the allocator picks.
 constexpr int kWpeMixed = DL_WPE_MIXED;
 
 // Load policy of the sweeps per precision (measured on the 4096^2 workload:
@@ -914,31 +1100,62 @@ int waves_per_cu(K kernel)
     return blocks * kWaves;
 }
 
+
+// The four specialisations (periodic y, site-dependent terms) of one sweep kind.
+template <class V1, class V2, class TO, bool HAS2, int PF>
+struct RecurKind {
+    template <bool PY, bool SITE>
+    static constexpr auto kernel() { return k_recur<V1, V2, TO, HAS2, PF, PY, SITE>; }
+    template <class F>
+    static auto dispatch(bool py, bool site, F &&f)
+    {
+        if (py) return site ? f(kernel<true, true>()) : f(kernel<true, false>());
+        return site ? f(kernel<false, true>()) : f(kernel<false, false>());
+    }
+};
+
+template <bool M>
+using RecurP2 = RecurKind<std::conditional_t<M, PlanarM, PlanarD>, std::conditional_t<M, PlanarM, PlanarD>,
+                          std::conditional_t<M, float2, double2>, false, M ? kPfMixed : kPfFp64>;
+template <bool M>
+using RecurP3 = RecurKind<std::conditional_t<M, PairedM, PairedD>, std::conditional_t<M, PlanarM, PlanarD>,
+                          std::conditional_t<M, float2, double2>, true, M ? kPfMixed : kPfFp64>;
+template <bool M>
+using RecurPn = RecurKind<std::conditional_t<M, PairedM, PairedD>, std::conditional_t<M, PairedM, PairedD>,
+                          std::conditional_t<M, float2, double2>, true, M ? kPfMixed : kPfFp64>;
+
+bool op_site(const Op &op) { return op.pot_kind != 0 || op.has_table != 0 || op.bq != 0.0; }
+
+template <template <bool> class Kind, class F>
+auto with_kind(bool mixed, bool py, bool site, F &&f)
+{
+    if (mixed) return Kind<true>::dispatch(py, site, f);
+    return Kind<false>::dispatch(py, site, f);
+}
+
 }  // namespace
 
-int sweep_waves_per_cu(int which, bool mixed)
+int sweep_waves_per_cu(int which, bool mixed, bool py, bool site)
 {
+    auto occ = [](auto kernel) { return waves_per_cu(kernel); };
     switch (which) {
-    case 0: return waves_per_cu(k_first<kPfFirst>);
-    case 1:
-        return mixed ? waves_per_cu(k_recur<PairedM, PairedM, float2, true, kPfMixed, kWpeMixed>)
-                     : waves_per_cu(k_recur<PairedD, PairedD, double2, true, kPfFp64>);
-    case 2:
-        return mixed ? waves_per_cu(k_recur<PlanarM, PlanarM, float2, false, kPfMixed, kWpeMixed>)
-                     : waves_per_cu(k_recur<PlanarD, PlanarD, double2, false, kPfFp64>);
-    case 3:
-        return mixed ? waves_per_cu(k_recur<PairedM, PlanarM, float2, true, kPfMixed, 1>)
-                     : waves_per_cu(k_recur<PairedD, PlanarD, double2, true, kPfFp64>);
+    case 0: return py ? (site ? waves_per_cu(k_first<kPfFirst, true, true>) : waves_per_cu(k_first<kPfFirst, true, false>))
+                      : (site ? waves_per_cu(k_first<kPfFirst, false, true>) : waves_per_cu(k_first<kPfFirst, false, false>));
+    case 1: return with_kind<RecurPn>(mixed, py, site, occ);
+    case 2: return with_kind<RecurP2>(mixed, py, site, occ);
+    case 3: return with_kind<RecurP3>(mixed, py, site, occ);
     default: return waves_per_cu(k_apply);
     }
 }
 
+bool sweep_site_terms(const Op &op) { return op_site(op); }
+
 int combine_grid(size_t sites, bool mixed, int cus)
 {
-    // eight workgroups per compute unit (measured best for the tiled stream),
-    // never more than there are tiles
+    // a fixed number of workgroups per compute unit (four measured best for
+    // the tiled stream), never more than there are tiles
     const size_t tile = (size_t)kBlock * (mixed ? kCombMixed : kCombFp64);
-    size_t nb = std::min<size_t>((size_t)8 * cus, (sites + tile - 1) / tile);
+    size_t nb = std::min<size_t>((size_t)DL_COMB_BLOCKS_PER_CU * cus, (sites + tile - 1) / tile);
     nb = std::max<size_t>(nb, 1);
     return (int)std::min<size_t>(nb, kMaxBlocks);
 }
@@ -967,28 +1184,35 @@ void launch_first(const Op &op, const Tiles &t, const double2 *psi, const double
                   double *alpha, double *gamma, Scalars *sc, double *partials, int m, int shift,
                   hipStream_t st)
 {
-    hipLaunchKernelGGL(k_first<kPfFirst>, dim3(t.nblocks), dim3(kBlock), 0, st, op, t, psi, field,
-                       alpha, gamma, sc, partials, m, shift);
+    const dim3 g(t.nblocks), b(kBlock);
+    const bool py = op.bcy != 0, site = op_site(op);
+    if (py) {
+        if (site)
+            hipLaunchKernelGGL((k_first<kPfFirst, true, true>), g, b, 0, st, op, t, psi, field, alpha, gamma, sc, partials, m, shift);
+        else
+            hipLaunchKernelGGL((k_first<kPfFirst, true, false>), g, b, 0, st, op, t, psi, field, alpha, gamma, sc, partials, m, shift);
+    } else {
+        if (site)
+            hipLaunchKernelGGL((k_first<kPfFirst, false, true>), g, b, 0, st, op, t, psi, field, alpha, gamma, sc, partials, m, shift);
+        else
+            hipLaunchKernelGGL((k_first<kPfFirst, false, false>), g, b, 0, st, op, t, psi, field, alpha, gamma, sc, partials, m, shift);
+    }
 }
 
 void launch_recur(const PassArgs &a, bool mixed, hipStream_t st)
 {
     const dim3 g(a.t.nblocks), b(kBlock);
-    if (!mixed) {
-        if (a.pass == 2)
-            hipLaunchKernelGGL((k_recur<PlanarD, PlanarD, double2, false, kPfFp64>), g, b, 0, st, a);
-        else if (a.pass == 3)
-            hipLaunchKernelGGL((k_recur<PairedD, PlanarD, double2, true, kPfFp64>), g, b, 0, st, a);
-        else
-            hipLaunchKernelGGL((k_recur<PairedD, PairedD, double2, true, kPfFp64>), g, b, 0, st, a);
-    } else {
-        if (a.pass == 2)
-            hipLaunchKernelGGL((k_recur<PlanarM, PlanarM, float2, false, kPfMixed, kWpeMixed>), g, b, 0, st, a);
-        else if (a.pass == 3)
-            hipLaunchKernelGGL((k_recur<PairedM, PlanarM, float2, true, kPfMixed, 1>), g, b, 0, st, a);
-        else
-            hipLaunchKernelGGL((k_recur<PairedM, PairedM, float2, true, kPfMixed, kWpeMixed>), g, b, 0, st, a);
-    }
+    auto go = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, g, b, 0, st, a);
+        return 0;
+    };
+    const bool py = a.op.bcy != 0, site = op_site(a.op);
+    if (a.pass == 2)
+        with_kind<RecurP2>(mixed, py, site, go);
+    else if (a.pass == 3)
+        with_kind<RecurP3>(mixed, py, site, go);
+    else
+        with_kind<RecurPn>(mixed, py, site, go);
 }
 
 void launch_tridiag(const double *alpha, const double *gamma, Scalars *sc, StepStat *stat,
