@@ -76,6 +76,9 @@ def main():
     ap.add_argument("--traffic-json")
     ap.add_argument("--sites", type=int, default=4096 * 4096)
     ap.add_argument("--command", default="")
+    ap.add_argument("--sq", help="counter CSV of SQ_WAVES, SQ_INSTS_VALU, SQ_INSTS_SALU, SQ_BUSY_CYCLES")
+    ap.add_argument("--clock-ghz", type=float, default=2.4)
+    ap.add_argument("--simds", type=int, default=1024)
     args = ap.parse_args()
 
     lines = []
@@ -91,6 +94,16 @@ def main():
             continue
         lines.append(f"{short_name(r['name'])[:78]:78s} {r['calls']:6d} {r['avg_us']:10.2f} "
                      f"{r['total_ms']:10.3f} {r['pct']:6.2f}")
+    # calibration kernels of known traffic, timed in the same trace: the
+    # practical streaming bandwidth of the device
+    mib = args.calib_mib * (1 << 20)
+    for r in st:
+        if "neg_kernel" in r["name"]:
+            lines.append(f"calibration torch.neg ({args.calib_mib} MiB read + write): {r['avg_us']:.1f} us = "
+                         f"{2 * mib / (r['avg_us'] * 1e-6) / 1e9:.0f} GB/s")
+        elif "FillFunctor" in r["name"]:
+            lines.append(f"calibration torch.fill ({args.calib_mib} MiB write): {r['avg_us']:.1f} us = "
+                         f"{mib / (r['avg_us'] * 1e-6) / 1e9:.0f} GB/s")
     traffic = {}
     if args.fetch and args.write:
         fetch = read_counter(args.fetch, "FETCH_SIZE")
@@ -115,6 +128,22 @@ def main():
             if fam == "recur_basis":
                 traffic[prec] = {"bytes_per_launch": rd + wr, "read_bytes": rd, "write_bytes": wr,
                                  "kernel": short_name(k)}
+    if args.sq:
+        # instruction mix per kernel: VALU issue utilisation = wave-instructions /
+        # (SIMDs x duration / 4 cycles per wave64 instruction)
+        sq = collections.defaultdict(lambda: collections.defaultdict(list))
+        for r in csv.DictReader(open(args.sq)):
+            sq[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        dur = {r["name"]: r["avg_us"] for r in st}
+        lines.append("")
+        lines.append(f"{'kernel':78s} {'waves':>7s} {'VALU_M':>8s} {'SALU_M':>8s} {'VALU_util':>9s}")
+        for k in sorted(sq):
+            if "dl::" not in k or k not in dur:
+                continue
+            a = {c: sum(v) / len(v) for c, v in sq[k].items()}
+            cap = args.simds * dur[k] * 1e-6 * args.clock_ghz * 1e9 / 4.0
+            lines.append(f"{short_name(k)[:78]:78s} {a.get('SQ_WAVES', 0):7.0f} {a.get('SQ_INSTS_VALU', 0) / 1e6:8.1f} "
+                         f"{a.get('SQ_INSTS_SALU', 0) / 1e6:8.1f} {a.get('SQ_INSTS_VALU', 0) / cap * 100:8.1f}%")
     text = "\n".join(lines)
     print(text)
     if args.traffic_json and traffic:
