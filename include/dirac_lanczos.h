@@ -207,6 +207,41 @@ dl_status dirac_lanczos_adjoint(dl_context *ctx, const void *psi0, double t0, do
                                 void *adj_ws, size_t adj_bytes, double *loss, double *grad);
 
 /*
+ * Batches of independent packets (hundreds of small
+ * grids of different sizes and fields propagated together).  Each packet is
+ * described by its own dl_params (grid, box, boundaries, fields, pulse); all
+ * packets share krylov_dim, precision and bc_y.  One step of the batch is one
+ * launch per Lanczos iteration over all packets (plus the small exponentials
+ * and the recombination), with every packet's reductions folded separately
+ * in fixed order; the mathematics of each packet is that of
+ * dirac_lanczos_step.
+ *
+ * dirac_lanczos_batch_workspace_bytes: bytes of DEVICE workspace (256-byte
+ *   aligned) for the batch; 0 for invalid parameters.
+ * dirac_lanczos_batch_init: params is a HOST array of n_packets entries (their
+ *   coef arrays are copied; v_table pointers must stay valid).  Errors:
+ *   DL_ERR_INVALID, DL_ERR_UNSUPPORTED (packets differ in bc_y),
+ *   DL_ERR_WORKSPACE, DL_ERR_DEVICE.
+ * dirac_lanczos_batch_step: psi is a HOST array of n_packets DEVICE pointers
+ *   (spinor layout above, updated in place); stats is a HOST array of
+ *   n_packets * n_steps entries (packet-major) or NULL.  Synchronous.  A
+ *   packet whose reduction becomes non-finite stops (its psi holds its last
+ *   completed step, later stats have k_eff = -1) while the others continue;
+ *   the call then returns DL_ERR_NONFINITE naming the packets.
+ */
+typedef struct dl_batch dl_batch;
+
+size_t dirac_lanczos_batch_workspace_bytes(const dl_params *params, int32_t n_packets);
+dl_status dirac_lanczos_batch_init(const dl_params *params, int32_t n_packets, void *workspace,
+                                   size_t ws_bytes, void *hip_stream, dl_batch **out);
+dl_status dirac_lanczos_batch_step(dl_batch *batch, void *const *psi, double t0, double dt,
+                                   int32_t n_steps, dl_step_stat *stats);
+dl_status dirac_lanczos_batch_destroy(dl_batch *batch);
+/* Message of the last failing call on batch, or of the last failing
+ * batch_init on this thread when batch is NULL. */
+const char *dirac_lanczos_batch_last_error(const dl_batch *batch);
+
+/*
  * Kernel timing with HIP events recorded on the context's stream around every
  * launch of dirac_lanczos_step (a diagnostic for roofline measurements).
  * Classes: 0 first Lanczos iteration; 1 recurrence sweeps whose operands are

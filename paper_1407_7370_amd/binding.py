@@ -25,7 +25,8 @@ STATUS_NAMES = {0: "DL_OK", 1: "DL_ERR_INVALID", 2: "DL_ERR_DEVICE", 3: "DL_ERR_
 EXPORTS = ("dirac_lanczos_workspace_bytes", "dirac_lanczos_init", "dirac_lanczos_apply",
            "dirac_lanczos_step", "dirac_lanczos_eigen", "dirac_lanczos_adjoint_workspace_bytes",
            "dirac_lanczos_adjoint", "dirac_lanczos_timing", "dirac_lanczos_destroy",
-           "dirac_lanczos_last_error")
+           "dirac_lanczos_last_error", "dirac_lanczos_batch_workspace_bytes", "dirac_lanczos_batch_init",
+           "dirac_lanczos_batch_step", "dirac_lanczos_batch_destroy", "dirac_lanczos_batch_last_error")
 DL_LOSS_X, DL_LOSS_Y, DL_LOSS_PX, DL_LOSS_PY = 1, 2, 4, 8
 
 
@@ -104,6 +105,17 @@ def load_library():
     lib.dirac_lanczos_destroy.restype = ctypes.c_int
     lib.dirac_lanczos_last_error.argtypes = [vp]
     lib.dirac_lanczos_last_error.restype = ctypes.c_char_p
+    lib.dirac_lanczos_batch_workspace_bytes.argtypes = [P, ctypes.c_int32]
+    lib.dirac_lanczos_batch_workspace_bytes.restype = ctypes.c_size_t
+    lib.dirac_lanczos_batch_init.argtypes = [P, ctypes.c_int32, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    lib.dirac_lanczos_batch_init.restype = ctypes.c_int
+    lib.dirac_lanczos_batch_step.argtypes = [vp, ctypes.POINTER(vp), ctypes.c_double, ctypes.c_double,
+                                             ctypes.c_int32, ctypes.POINTER(DlStepStat)]
+    lib.dirac_lanczos_batch_step.restype = ctypes.c_int
+    lib.dirac_lanczos_batch_destroy.argtypes = [vp]
+    lib.dirac_lanczos_batch_destroy.restype = ctypes.c_int
+    lib.dirac_lanczos_batch_last_error.argtypes = [vp]
+    lib.dirac_lanczos_batch_last_error.restype = ctypes.c_char_p
     _lib = lib
     return lib
 
@@ -195,6 +207,35 @@ def dirac_lanczos_destroy(ctx) -> int:
 
 def dirac_lanczos_last_error(ctx) -> str:
     return _err(load_library(), ctx)
+
+
+def dirac_lanczos_batch_workspace_bytes(params_array, n_packets: int) -> int:
+    return int(load_library().dirac_lanczos_batch_workspace_bytes(params_array, n_packets))
+
+
+def dirac_lanczos_batch_init(params_array, n_packets: int, workspace_ptr: int, ws_bytes: int, stream_ptr: int):
+    lib = load_library()
+    b = ctypes.c_void_p()
+    st = lib.dirac_lanczos_batch_init(params_array, n_packets, ctypes.c_void_p(workspace_ptr), ws_bytes,
+                                      ctypes.c_void_p(stream_ptr), ctypes.byref(b))
+    if st != DL_OK:
+        msg = lib.dirac_lanczos_batch_last_error(None)
+        raise DlError(st, msg.decode() if msg else "")
+    return b
+
+
+def dirac_lanczos_batch_step(batch, psi_ptrs, t0: float, dt: float, n_steps: int, stats=None) -> int:
+    arr = (ctypes.c_void_p * len(psi_ptrs))(*[ctypes.c_void_p(p) for p in psi_ptrs])
+    return load_library().dirac_lanczos_batch_step(batch, arr, t0, dt, n_steps, stats)
+
+
+def dirac_lanczos_batch_destroy(batch) -> int:
+    return load_library().dirac_lanczos_batch_destroy(batch)
+
+
+def dirac_lanczos_batch_last_error(batch) -> str:
+    msg = load_library().dirac_lanczos_batch_last_error(batch)
+    return msg.decode() if msg else ""
 
 
 # ---------------------------------------------------------------------------
@@ -300,6 +341,70 @@ class Propagator:
         if getattr(self, "ctx", None):
             dirac_lanczos_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchPropagator:
+    """A batch of independent packets (one dict per packet, keys as in
+    packets.py) sharing krylov_dim, precision and bc_y; psi tensors are
+    complex128 of shape (2, ny_i, nx_i), contiguous, on the GPU."""
+
+    def __init__(self, problems, krylov_dim: int, precision: str = "fp64", stream=None):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        self.prec = DL_PREC_MIXED if precision == "mixed" else DL_PREC_FP64
+        self.n = len(problems)
+        arr = (DlParams * self.n)()
+        self._keep = []
+        for i, prob in enumerate(problems):
+            p, keep = make_params(prob, krylov_dim, self.prec)
+            arr[i] = p
+            self._keep.append(keep)
+        self.params = arr
+        nbytes = dirac_lanczos_batch_workspace_bytes(arr, self.n)
+        if nbytes == 0:
+            raise DlError(DL_ERR_INVALID, "invalid batch parameters (batch_workspace_bytes returned 0)")
+        self.ws_bytes = nbytes
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        self.ws_ptr = (self.workspace.data_ptr() + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.batch = dirac_lanczos_batch_init(arr, self.n, self.ws_ptr, nbytes, self.stream.cuda_stream)
+        self.shapes = [(2, int(p["ny"]), int(p["nx"])) for p in problems]
+
+    def step(self, psis, t0: float, dt: float, n_steps: int, want_stats: bool = True):
+        """In-place propagation of every packet.  Returns per-packet stats dicts."""
+        t = self.torch
+        if len(psis) != self.n:
+            raise ValueError(f"expected {self.n} states")
+        for psi, shp in zip(psis, self.shapes):
+            if not (isinstance(psi, t.Tensor) and psi.is_cuda and psi.dtype == t.complex128
+                    and tuple(psi.shape) == shp and psi.is_contiguous()):
+                raise ValueError(f"every psi must be a contiguous complex128 CUDA tensor of its packet's shape")
+        stats = (DlStepStat * max(self.n * n_steps, 1))() if want_stats else None
+        st = dirac_lanczos_batch_step(self.batch, [p.data_ptr() for p in psis], t0, dt, n_steps, stats)
+        out = None
+        if want_stats:
+            out = []
+            for i in range(self.n):
+                ss = stats[i * n_steps:(i + 1) * n_steps]
+                out.append({"k_eff": np.array([s.k_eff for s in ss], dtype=np.int32),
+                            "err_est": np.array([s.err_est for s in ss]),
+                            "cum_bound": np.array([s.cum_bound for s in ss]),
+                            "norm2": np.array([s.norm2 for s in ss])})
+        if st != DL_OK:
+            raise DlError(st, dirac_lanczos_batch_last_error(self.batch))
+        return out
+
+    def close(self):
+        if getattr(self, "batch", None):
+            dirac_lanczos_batch_destroy(self.batch)
+            self.batch = None
 
     def __del__(self):
         try:

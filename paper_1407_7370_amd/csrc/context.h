@@ -37,6 +37,37 @@ void tridiag_last_row(std::vector<double> d, std::vector<double> e, std::vector<
 void tridiag_full(std::vector<double> d, std::vector<double> e, std::vector<double> &lam,
                   std::vector<double> &v);
 
+// A = s H with the geometry and static fields of the problem (the homogeneous
+// laser term is passed to the kernels per step).
+inline dl::Op make_op(const dl_params &p, double s)
+{
+    dl::Op o{};
+    o.nx = p.nx;
+    o.ny = p.ny;
+    o.bcx = p.bc_x;
+    o.bcy = p.bc_y;
+    o.hx = (p.x_max - p.x_min) / p.nx;
+    o.hy = (p.y_max - p.y_min) / p.ny;
+    o.xmin = p.x_min;
+    o.ymin = p.y_min;
+    o.kx = s * p.c / (2.0 * o.hx);
+    o.ky = s * p.c / (2.0 * o.hy);
+    o.mc2 = s * p.mass * p.c * p.c;
+    o.bq = s * p.c * p.charge * p.bz * 0.5;
+    o.pot_kind = p.pot_kind ? 1 : 0;
+    if (p.pot_kind == 1) {
+        o.vz = s * p.pot_z;
+        o.va2 = p.pot_a * p.pot_a;
+    } else if (p.pot_kind == 2) {
+        o.vz = s * 1.5 * p.pot_z;
+        o.va2 = 3.0 / (p.pot_z * p.pot_z);
+    }
+    o.has_table = p.v_table ? 1 : 0;
+    o.vtab = p.v_table;
+    o.vscale = s;
+    return o;
+}
+
 }  // namespace dlh
 
 struct dl_context {
@@ -119,34 +150,7 @@ struct dl_context {
     dl::Scalars *sc() const { return reinterpret_cast<dl::Scalars *>(ws + L.sc); }
 
     // A = s H with the geometry and static fields of the problem.
-    dl::Op op(double s) const
-    {
-        dl::Op o{};
-        o.nx = p.nx;
-        o.ny = p.ny;
-        o.bcx = p.bc_x;
-        o.bcy = p.bc_y;
-        o.hx = (p.x_max - p.x_min) / p.nx;
-        o.hy = (p.y_max - p.y_min) / p.ny;
-        o.xmin = p.x_min;
-        o.ymin = p.y_min;
-        o.kx = s * p.c / (2.0 * o.hx);
-        o.ky = s * p.c / (2.0 * o.hy);
-        o.mc2 = s * p.mass * p.c * p.c;
-        o.bq = s * p.c * p.charge * p.bz * 0.5;
-        o.pot_kind = p.pot_kind ? 1 : 0;
-        if (p.pot_kind == 1) {
-            o.vz = s * p.pot_z;
-            o.va2 = p.pot_a * p.pot_a;
-        } else if (p.pot_kind == 2) {
-            o.vz = s * 1.5 * p.pot_z;
-            o.va2 = 3.0 / (p.pot_z * p.pot_z);
-        }
-        o.has_table = p.v_table ? 1 : 0;
-        o.vtab = p.v_table;
-        o.vscale = s;
-        return o;
-    }
+    dl::Op op(double s) const { return dlh::make_op(p, s); }
 };
 
 #define DL_HIP(ctx, call)                                      \

@@ -20,10 +20,14 @@ __device__ __forceinline__ void wave_sum(double (&v)[NV])
         for (int k = 0; k < NV; ++k) v[k] += __shfl_xor(v[k], s, 64);
 }
 
-// Fold the per-lane sums of the whole grid in a fixed order.  Returns true in
-// the last workgroup to finish, where every thread then holds the totals.
+// Fold the per-lane sums of a segment of `nblk` workgroups (this one is number
+// `blk` of the segment) in a fixed order: per-workgroup partials in
+// partials[0 .. nblk), a ticket counting the finished workgroups.  Returns true
+// in the last workgroup of the segment to finish, where every thread then
+// holds the totals; that workgroup also resets the ticket.
 template <int NV>
-__device__ bool grid_reduce(double (&v)[NV], double *partials, unsigned int *ticket, double (&tot)[NV])
+__device__ bool seg_reduce(double (&v)[NV], double *partials, unsigned int *ticket, int nblk, int blk,
+                           double (&tot)[NV])
 {
     static_assert(NV <= kPartialStride, "partial table stride");
     __shared__ double red[kWaves][NV];
@@ -39,11 +43,11 @@ __device__ bool grid_reduce(double (&v)[NV], double *partials, unsigned int *tic
         for (int k = 0; k < NV; ++k) {
             double s = red[0][k];
             for (int i = 1; i < kWaves; ++i) s += red[i][k];
-            partials[(size_t)blockIdx.x * kPartialStride + k] = s;
+            partials[(size_t)blk * kPartialStride + k] = s;
         }
         __threadfence();
         const unsigned int t = atomicAdd(ticket, 1u);
-        last = (t == gridDim.x - 1) ? 1 : 0;
+        last = (t == (unsigned int)nblk - 1u) ? 1 : 0;
     }
     __syncthreads();
     if (!last) return false;
@@ -51,7 +55,7 @@ __device__ bool grid_reduce(double (&v)[NV], double *partials, unsigned int *tic
     double s[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) s[k] = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock)
+    for (int b = threadIdx.x; b < nblk; b += kBlock)
 #pragma unroll
         for (int k = 0; k < NV; ++k)
             s[k] += __builtin_nontemporal_load(&partials[(size_t)b * kPartialStride + k]);
@@ -69,6 +73,14 @@ __device__ bool grid_reduce(double (&v)[NV], double *partials, unsigned int *tic
     }
     if (threadIdx.x == 0) *ticket = 0u;
     return true;
+}
+
+// The whole grid as one segment.
+template <int NV>
+__device__ __forceinline__ bool grid_reduce(double (&v)[NV], double *partials, unsigned int *ticket,
+                                            double (&tot)[NV])
+{
+    return seg_reduce(v, partials, ticket, (int)gridDim.x, (int)blockIdx.x, tot);
 }
 
 }  // namespace

@@ -146,6 +146,59 @@ void launch_apply(const Op &op, const Tiles &t, const double2 *x, double2 *y, do
                   double gyh, hipStream_t st);
 void launch_reset(Scalars *sc, hipStream_t st);
 
+// ---------------------------------------------------------------------------
+// Batches of independent packets (grids of different sizes and fields, one
+// Krylov dimension and precision): every kernel of a step is one launch over
+// all packets.  Workgroups of a launch are grouped by packet (the four waves
+// of a workgroup belong to one packet), so each packet's reductions are a
+// segment of the workgroups, folded in fixed order by the segment's last
+// workgroup with the packet's own ticket.
+// ---------------------------------------------------------------------------
+enum { kGridSweep = 0, kGridFirst = 1, kGridCombine = 2, kGridKinds = 3 };
+
+struct BatchPacket {
+    Op op;             // A = dt H of the packet (static part; the laser term per step in `fields`)
+    Tiles tiles[2];    // strip geometry of the sweeps (halo 2) and of iteration 1 (halo 1)
+    double2 *psi;      // caller's state
+    double2 *state;    // ping-pong partner (workspace)
+    char *basis;       // u_2 .. u_m
+    size_t vstride;    // bytes between consecutive Krylov vectors
+    size_t sites;      // nx * ny
+    double *alpha, *gamma;
+    Scalars *sc;
+    StepStat *stats;   // kChunk entries
+    double *fields;    // (gx_hom, gy_hom) per step of the chunk
+};
+
+struct BatchBlock {    // one workgroup of a batched launch
+    int packet;        // packet of the workgroup
+    int local;         // index of the workgroup within its packet's segment
+    int nblk;          // workgroups of the segment
+    int first;         // first workgroup of the segment (partials offset)
+};
+
+struct BatchTask {     // one wave of a batched sweep (inactive when y0 >= y1)
+    int strip, y0, y1, pad;
+};
+
+struct BatchArgs {
+    const BatchPacket *pk;
+    const BatchBlock *blocks;  // of this launch's grid kind
+    const BatchTask *tasks;    // kWaves per workgroup (sweeps and iteration 1)
+    double *partials;          // kPartialStride doubles per workgroup
+    int pass, m, step, parity; // step: index in the chunk tables; parity 1: the input is `state`
+};
+
+void launch_first_batch(const BatchArgs &b, int nblocks, bool py, bool site, hipStream_t st);
+void launch_recur_batch(const BatchArgs &b, int nblocks, bool mixed, bool py, bool site, hipStream_t st);
+void launch_tridiag_batch(const BatchArgs &b, int npackets, hipStream_t st);
+void launch_reset_batch(const BatchPacket *pk, int n, hipStream_t st);
+void launch_combine_batch(const BatchArgs &b, int nblocks, bool mixed, hipStream_t st);
+// Resident waves per compute unit of the batched kernels (0 first, 1 sweeps).
+int batch_waves_per_cu(int which, bool mixed, bool py, bool site);
+// Sites per recombination tile.
+int combine_tile_sites(bool mixed);
+
 Tiles make_tiles(int nx, int ny, int halo, int target_waves);
 // Workgroups of the recombination for `sites` sites (<= kMaxBlocks).
 int combine_grid(size_t sites, bool mixed, int cus);

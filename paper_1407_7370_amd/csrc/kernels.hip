@@ -1,1139 +1,12 @@
-// gfx950 kernels of the Lanczos short-time propagator for the 2D Dirac
-// equation (Beerwerth & Bauke, arXiv:1407.7370).
-//
-// Stencil sweeps.  One wave64 owns a strip of columns and a chunk of rows and
-// marches down the rows: lane l holds column strip*own - halo + l, neighbours
-// in x come from the adjacent lanes through DPP wave rotations, neighbours in
-// y from a register ring of the last rows, and the rows ahead sit in a
-// register FIFO of loads in flight.  The march is unrolled by four so that
-// every ring and FIFO slot is a fixed register (no moves).  Row addresses are
-// scalar (one base per row) plus a fixed 32-bit lane offset.  No LDS tile and
-// no barrier is needed inside the march; the `halo` edge lanes of a wave only
-// feed their neighbours.  Reductions are per-lane FP64 sums folded by a fixed
-// butterfly, per workgroup, and finally by the last workgroup to finish in
-// fixed order, so results are bitwise reproducible.
-//
-// A sweep p >= 2 fuses one whole Lanczos iteration of Fig. 1 (Sec. 2) into one
-// pass over memory: with u_i = gamma_i q_i (gamma_i = ||u_i|| = beta_{i-1})
-//   u_p = (A u_{p-1} - alpha_{p-1} u_{p-1}) / gamma_{p-1}
-//         - (gamma_{p-1} / gamma_{p-2}) u_{p-2}                  (eq. lanczos_base)
-// is formed on the tile plus a one-site rim (A u_{p-1} is recomputed there
-// from u_{p-1} with a two-site rim), stored, and A u_p is applied on the tile
-// to reduce ||u_p||^2, Re<u_p, A u_p> and Re<u_p, u_{p-1}>.  From these the
-// last workgroup forms gamma_p and alpha_p = Re<q_p, A q_p> - beta_{p-1}
-// Re<q_p, q_{p-1}>, the modified Gram-Schmidt form of Fig. 1.  The last sweep
-// also reduces ||A u_m||^2 and Re<A u_m, u_{m-1}>, from which beta_m (input of
-// the error estimate eq. matrix_exponential_error) follows without another
-// pass over memory.
+// Single-grid launches of the sweep kernels (device code in sweeps.h) and
+// the launch-shape queries of the host runtime.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <cmath>
-#include <type_traits>
-#include <utility>
 
-#include "dl_internal.h"
-#include "device_reduce.h"
+#include "sweeps.h"
 
 namespace dl {
-namespace {
-
-template <int K>
-using IC = std::integral_constant<int, K>;
-
-// f(IC<0>{}), ..., f(IC<N-1>{}) in order (compile-time unrolled steps).
-template <class F, int... K>
-__device__ __forceinline__ void unroll_steps(F &&f, std::integer_sequence<int, K...>)
-{
-    (f(IC<K>{}), ...);
-}
-
-struct Sp {
-    double r0, i0, r1, i1;  // component 0 (re, im), component 1 (re, im)
-};
-
-__device__ __forceinline__ Sp sp_zero() { return Sp{0.0, 0.0, 0.0, 0.0}; }
-
-// DPP wave rotations: wave_ror:1 delivers the value of lane l-1 to lane l,
-// wave_rol:1 the value of lane l+1.  Lanes 0 and 63 receive wrapped values
-// that only feed rim lanes whose results are discarded.
-__device__ __forceinline__ double from_left(double v)
-{
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x13C, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x13C, 0xF, 0xF, true);
-    return __hiloint2double(hi, lo);
-}
-
-__device__ __forceinline__ double from_right(double v)
-{
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x134, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x134, 0xF, 0xF, true);
-    return __hiloint2double(hi, lo);
-}
-
-__device__ __forceinline__ Sp sp_left(const Sp &s)
-{
-    return Sp{from_left(s.r0), from_left(s.i0), from_left(s.r1), from_left(s.i1)};
-}
-
-__device__ __forceinline__ Sp sp_right(const Sp &s)
-{
-    return Sp{from_right(s.r0), from_right(s.i0), from_right(s.r1), from_right(s.i1)};
-}
-
-// One site of a stored vector: both components in the storage type (aligned
-// so that a paired site is one 16-byte access in complex64).
-template <class T>
-struct alignas(2 * sizeof(T)) Raw {
-    T a, b;
-};
-
-template <class T>
-__device__ __forceinline__ T tzero();
-template <>
-__device__ __forceinline__ double2 tzero<double2>() { return make_double2(0.0, 0.0); }
-template <>
-__device__ __forceinline__ float2 tzero<float2>() { return make_float2(0.0f, 0.0f); }
-
-template <class T>
-__device__ __forceinline__ Raw<T> raw_zero() { return Raw<T>{tzero<T>(), tzero<T>()}; }
-
-template <class T>
-__device__ __forceinline__ Sp to_sp(const Raw<T> &r)
-{
-    return Sp{(double)r.a.x, (double)r.a.y, (double)r.b.x, (double)r.b.y};
-}
-
-// The value that a later sweep reads back from storage of type T.
-template <class T>
-__device__ __forceinline__ Sp stored_value(const Sp &s);
-template <>
-__device__ __forceinline__ Sp stored_value<double2>(const Sp &s) { return s; }
-template <>
-__device__ __forceinline__ Sp stored_value<float2>(const Sp &s)
-{
-    return Sp{(double)(float)s.r0, (double)(float)s.i0, (double)(float)s.r1, (double)(float)s.i1};
-}
-
-template <class T>
-__device__ __forceinline__ Raw<T> to_raw(const Sp &s);
-template <>
-__device__ __forceinline__ Raw<double2> to_raw<double2>(const Sp &s)
-{
-    return Raw<double2>{make_double2(s.r0, s.i0), make_double2(s.r1, s.i1)};
-}
-template <>
-__device__ __forceinline__ Raw<float2> to_raw<float2>(const Sp &s)
-{
-    return Raw<float2>{make_float2((float)s.r0, (float)s.i0), make_float2((float)s.r1, (float)s.i1)};
-}
-
-// Buffer access.  Every row of a vector gets its own buffer descriptor
-// (scalar registers) whose size is the row length, or zero for a row outside a
-// Dirichlet domain; lanes outside the domain use an offset past any row.  The
-// hardware returns zero for such loads and drops such stores, so the domain
-// boundary costs no branches and no register fills.
-typedef int v4i __attribute__((ext_vector_type(4)));
-constexpr uint32_t kOob = 0x80000000u;
-constexpr int kRsrcWord3 = 0x00020000;  // raw 32-bit buffer format (gfx9 family)
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const char *p, uint32_t bytes)
-{
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(p), (short)0, (int)bytes, kRsrcWord3);
-}
-
-// Cache-policy operand of buffer loads and stores: 0 default, 2 the
-// nontemporal (streaming) hint.
-constexpr int kPolDefault = 0;
-constexpr int kPolStream = 2;
-#ifndef DL_SWEEP_STORE_POLICY
-#define DL_SWEEP_STORE_POLICY kPolDefault
-#endif
-
-template <class X, int POL = kPolDefault>
-__device__ __forceinline__ X ld16(__amdgpu_buffer_rsrc_t r, uint32_t off)
-{
-    static_assert(sizeof(X) == 16, "16-byte access");
-    return __builtin_bit_cast(X, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, POL));
-}
-
-template <class X>
-__device__ __forceinline__ void st16(__amdgpu_buffer_rsrc_t r, uint32_t off, const X &v)
-{
-    static_assert(sizeof(X) == 16, "16-byte access");
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4i, v), r, off, 0, DL_SWEEP_STORE_POLICY);
-}
-
-// Vector views.  Planar: the caller's state layout (two component planes of
-// complex128).  Paired: Krylov vectors, both components of a site adjacent.
-template <int POL>
-struct PlanarT {
-    using T = double2;
-    const char *base;
-    size_t plane_bytes;
-    uint32_t row_bytes;  // nx * 16
-    __device__ __forceinline__ Raw<double2> load(int jw, bool row_ok, uint32_t off) const
-    {
-        const char *r = base + (size_t)jw * row_bytes;
-        const uint32_t n = row_ok ? row_bytes : 0u;
-        Raw<double2> v;
-        v.a = ld16<double2, POL>(row_rsrc(r, n), off);
-        v.b = ld16<double2, POL>(row_rsrc(r + plane_bytes, n), off);
-        return v;
-    }
-    // Row at address `row` (first plane) with `n` valid bytes (0: returns zeros).
-    __device__ __forceinline__ Raw<double2> load_at(const char *row, uint32_t n, uint32_t off) const
-    {
-        Raw<double2> v;
-        v.a = ld16<double2, POL>(row_rsrc(row, n), off);
-        v.b = ld16<double2, POL>(row_rsrc(row + plane_bytes, n), off);
-        return v;
-    }
-    static __device__ __forceinline__ uint32_t lane_offset(int colw) { return (uint32_t)colw * 16u; }
-};
-using Planar = PlanarT<kPolDefault>;
-template <class V>
-struct is_planar : std::false_type {};
-template <int POL>
-struct is_planar<PlanarT<POL>> : std::true_type {};
-
-template <class TT, int POL = kPolDefault>
-struct Paired {
-    using T = TT;
-    const char *base;
-    uint32_t row_bytes;  // nx * 2 * sizeof(T)
-    __device__ __forceinline__ Raw<T> load(int jw, bool row_ok, uint32_t off) const
-    {
-        const __amdgpu_buffer_rsrc_t r = row_rsrc(base + (size_t)jw * row_bytes, row_ok ? row_bytes : 0u);
-        if constexpr (sizeof(T) == 8) {
-            return ld16<Raw<T>, POL>(r, off);
-        } else {
-            Raw<T> v;
-            v.a = ld16<T, POL>(r, off);
-            v.b = ld16<T, POL>(r, off + 16u);
-            return v;
-        }
-    }
-    __device__ __forceinline__ Raw<T> load_at(const char *row, uint32_t n, uint32_t off) const
-    {
-        const __amdgpu_buffer_rsrc_t r = row_rsrc(row, n);
-        if constexpr (sizeof(T) == 8) {
-            return ld16<Raw<T>, POL>(r, off);
-        } else {
-            Raw<T> v;
-            v.a = ld16<T, POL>(r, off);
-            v.b = ld16<T, POL>(r, off + 16u);
-            return v;
-        }
-    }
-    // Store to the row at `row` with `n` valid bytes (0: the store is dropped).
-    __device__ __forceinline__ void store_at(const char *row, uint32_t n, uint32_t off, const Raw<T> &v) const
-    {
-        const __amdgpu_buffer_rsrc_t r = row_rsrc(row, n);
-        if constexpr (sizeof(T) == 8) {
-            st16(r, off, v);
-        } else {
-            st16(r, off, v.a);
-            st16(r, off + 16u, v.b);
-        }
-    }
-    __device__ __forceinline__ void store(int jw, uint32_t off, const Raw<T> &v) const
-    {
-        const __amdgpu_buffer_rsrc_t r = row_rsrc(base + (size_t)jw * row_bytes, row_bytes);
-        if constexpr (sizeof(T) == 8) {
-            st16(r, off, v);
-        } else {
-            st16(r, off, v.a);
-            st16(r, off + 16u, v.b);
-        }
-    }
-    static __device__ __forceinline__ uint32_t lane_offset(int colw)
-    {
-        return (uint32_t)colw * (uint32_t)(2 * sizeof(T));
-    }
-};
-
-struct LaneGeo {
-    int colw;   // column index used for memory (wrapped when periodic)
-    bool inx;   // column exists (inside, or periodic image)
-    bool own;   // lane writes and reduces its column
-    double x;   // coordinate of colw
-};
-
-__device__ __forceinline__ LaneGeo lane_geo(const Op &op, const Tiles &t, int strip, int lane)
-{
-    LaneGeo g;
-    const int col = strip * t.own - t.halo + lane;
-    const bool inside = col >= 0 && col < op.nx;
-    int colw = col;
-    if (!inside) colw = op.bcx ? ((col % op.nx) + op.nx) % op.nx : 0;
-    g.colw = colw;
-    g.inx = inside || op.bcx;
-    g.own = inside && lane >= t.halo && lane < 64 - t.halo;
-    g.x = op.xmin + colw * op.hx;
-    return g;
-}
-
-struct RowGeo {
-    int jw;
-    bool iny;
-    double y;
-};
-
-__device__ __forceinline__ RowGeo row_geo(const Op &op, int r)
-{
-    RowGeo g;
-    // sweeps touch rows -2 .. ny+1 only (rim of two rows, ny >= 3): one wrap suffices
-    const bool inside = r >= 0 && r < op.ny;
-    int jw = r < 0 ? r + op.ny : (r >= op.ny ? r - op.ny : r);
-    if (!inside && !op.bcy) jw = 0;
-    g.jw = jw;
-    g.iny = inside || op.bcy;
-    g.y = op.ymin + jw * op.hy;
-    return g;
-}
-
-// Load one site of row r (zero outside a Dirichlet domain; `off` is the lane
-// offset, or kOob for a lane outside the domain).  A row that is not `needed`
-// gets an empty descriptor: the load returns zeros without touching memory,
-// so FIFO refills can be unconditional.
-template <class V>
-__device__ __forceinline__ Raw<typename V::T> load_row(const V &v, const Op &op, uint32_t off, int r,
-                                                       bool needed = true)
-{
-    const RowGeo rg = row_geo(op, r);
-    return v.load(rg.jw, rg.iny && needed, off);
-}
-
-// Potential energy (times the operator scale) at a site.
-__device__ __forceinline__ double site_pot(const Op &op, const LaneGeo &lg, const RowGeo &rg)
-{
-    double v = 0.0;
-    if (op.pot_kind) v = -op.vz / sqrt(lg.x * lg.x + rg.y * rg.y + op.va2);
-    if (op.has_table && lg.inx && rg.iny) v += op.vscale * op.vtab[(size_t)rg.jw * op.nx + lg.colw];
-    return v;
-}
-
-// (A psi) at one site from the site value c, its x neighbours l, r and its y
-// neighbours d (row below), u (row above):
-//   (A psi)_0 = (mc2 + V) psi_0 + kx (-i)(psi_1[x+1] - psi_1[x-1])
-//               - ky (psi_1[y+1] - psi_1[y-1]) + (gx - i gy) psi_1
-//   (A psi)_1 = (V - mc2) psi_1 + kx (-i)(psi_0[x+1] - psi_0[x-1])
-//               + ky (psi_0[y+1] - psi_0[y-1]) + (gx + i gy) psi_0
-// i.e. c[sigma1 (p_x - qA_x) + sigma2 (p_y - qA_y)] + sigma3 m c^2 + V scaled
-// by s, with gx = -s c q A_x and gy = -s c q A_y (Sec. 3 Hamiltonian); the
-// optional shift returns (A - shift I) psi.
-__device__ __forceinline__ Sp hop(const Op &op, const Sp &c, const Sp &l, const Sp &r, const Sp &d,
-                                  const Sp &u, double v, double gx, double gy, double shift = 0.0)
-{
-    const double d0 = op.mc2 + v - shift, d1 = v - op.mc2 - shift;
-    const double x0r = r.r0 - l.r0, x0i = r.i0 - l.i0, x1r = r.r1 - l.r1, x1i = r.i1 - l.i1;
-    const double y0r = u.r0 - d.r0, y0i = u.i0 - d.i0, y1r = u.r1 - d.r1, y1i = u.i1 - d.i1;
-    Sp o;
-    o.r0 = d0 * c.r0 + op.kx * x1i - op.ky * y1r + gx * c.r1 + gy * c.i1;
-    o.i0 = d0 * c.i0 - op.kx * x1r - op.ky * y1i + gx * c.i1 - gy * c.r1;
-    o.r1 = d1 * c.r1 + op.kx * x0i + op.ky * y0r + gx * c.r0 - gy * c.i0;
-    o.i1 = d1 * c.i1 - op.kx * x0r + op.ky * y0i + gx * c.i0 + gy * c.r0;
-    return o;
-}
-
-__device__ __forceinline__ double sp_norm2(const Sp &a)
-{
-    return a.r0 * a.r0 + a.i0 * a.i0 + a.r1 * a.r1 + a.i1 * a.i1;
-}
-
-// Re <a, b> at one site.
-__device__ __forceinline__ double sp_redot(const Sp &a, const Sp &b)
-{
-    return a.r0 * b.r0 + a.i0 * b.i0 + a.r1 * b.r1 + a.i1 * b.i1;
-}
-
-// Tile of this wave.  The wave index is made wave-uniform explicitly so that
-// the whole march (row indices, bounds, addresses) runs on the scalar unit.
-struct WaveTask {
-    bool active;
-    int strip, y0, y1;
-};
-
-// Workgroups are dispatched to the eight XCDs of the chip round robin
-// (workgroup b to XCD b mod 8), and each XCD has its own L2.  With the XCD
-// map on, consecutive logical workgroups -- adjacent strips of one row chunk,
-// which share their halo columns -- run on the same XCD.
-#ifndef DL_XCD_MAP
-#define DL_XCD_MAP 1
-#endif
-constexpr int kXcds = 8;
-
-__device__ __forceinline__ int logical_block()
-{
-    const int b = (int)blockIdx.x;
-    if (!DL_XCD_MAP) return b;
-    const int nb = (int)gridDim.x, q = nb / kXcds, r = nb % kXcds, x = b % kXcds;
-    const int first = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
-    return first + b / kXcds;
-}
-
-__device__ __forceinline__ WaveTask wave_task(const Op &op, const Tiles &t)
-{
-    WaveTask w;
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int task = logical_block() * kWaves + wave;
-    w.active = task < t.nstrips * t.nchunks;
-    w.strip = task % t.nstrips;
-    const int chunk = task / t.nstrips;
-    w.y0 = chunk * t.rows;
-    w.y1 = min(w.y0 + t.rows, op.ny);
-    if (w.y0 >= op.ny) w.active = false;
-    return w;
-}
-
-// Scalar cursor over the rows of one vector: the (unwrapped) address of row r,
-// advanced by one row per step.  Rows outside a Dirichlet domain or outside
-// the needed range get a zero-size descriptor: loads return zeros and stores
-// are dropped, with no branch.
-template <bool PY>
-struct RowCursor {
-    uint64_t addr;  // base + r * rb
-    int r;
-    uint32_t rb;    // bytes per row
-    uint64_t span;  // ny * rb (periodic wrap)
-    int lo;         // first valid row
-    uint32_t width; // number of valid rows: lo .. lo + width - 1
-    __device__ __forceinline__ const char *ptr(int ny) const
-    {
-        uint64_t x = addr;
-        if constexpr (PY) x = r < 0 ? x + span : (r >= ny ? x - span : x);
-        return reinterpret_cast<const char *>(x);
-    }
-    __device__ __forceinline__ uint32_t bytes() const { return (uint32_t)(r - lo) < width ? rb : 0u; }
-    __device__ __forceinline__ void next()
-    {
-        addr += rb;
-        ++r;
-    }
-};
-
-// Cursor at row r whose valid rows are lo .. hi intersected with the domain
-// (Dirichlet) -- every row of the rim is a valid periodic image.
-template <bool PY>
-__device__ __forceinline__ RowCursor<PY> row_cursor(const void *base, uint32_t rb, int ny, int r, int lo, int hi)
-{
-    RowCursor<PY> c;
-    c.addr = reinterpret_cast<uint64_t>(base) + (uint64_t)((int64_t)r * (int64_t)rb);
-    c.r = r;
-    c.rb = rb;
-    c.span = (uint64_t)ny * rb;
-    if (!PY) {
-        lo = max(lo, 0);
-        hi = min(hi, ny - 1);
-    }
-    c.lo = lo;
-    c.width = hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
-    return c;
-}
-
-// Potential energy (times the operator scale) at column lg, wrapped row jw.
-__device__ __forceinline__ double site_pot_row(const Op &op, const LaneGeo &lg, int jw, double y)
-{
-    double v = 0.0;
-    if (op.pot_kind) v = -op.vz / sqrt(lg.x * lg.x + y * y + op.va2);
-    if (op.has_table && lg.inx) v += op.vscale * op.vtab[(size_t)jw * op.nx + lg.colw];
-    return v;
-}
-
-template <class V>
-__device__ __forceinline__ V make_view(const void *p, const Op &op)
-{
-    if constexpr (is_planar<V>::value)
-        return V{static_cast<const char *>(p), (size_t)op.nx * op.ny * 16, (uint32_t)op.nx * 16u};
-    else
-        return V{static_cast<const char *>(p), (uint32_t)(op.nx * 2 * sizeof(typename V::T))};
-}
-
-// Load policy of the first iteration's reads of psi.
-#ifndef DL_LOAD_POL_FIRST
-#define DL_LOAD_POL_FIRST kPolStream
-#endif
-using PlanarF = PlanarT<DL_LOAD_POL_FIRST>;
-
-// ---------------------------------------------------------------------------
-// Lanczos iteration 1: gamma_1 = ||psi||, alpha_1 = Re<psi, A psi>/||psi||^2,
-// and for m = 1 also beta_1 = ||A q_1 - alpha_1 q_1||.
-// Rows marched: psi rows y0-1 .. y1 (ring slot = row - (y0-1) mod 4).
-// ---------------------------------------------------------------------------
-template <int PF, bool PY, bool SITE>
-__global__ __launch_bounds__(kBlock) void k_first(Op op, Tiles t, const double2 *__restrict__ psi,
-                                                  const double *__restrict__ field, double *alpha,
-                                                  double *gamma, Scalars *sc, double *partials, int m,
-                                                  int shift)
-{
-    constexpr int U = PF > 4 ? PF : 4;
-    static_assert(U % PF == 0 && U % 4 == 0, "FIFO depth must divide the unroll");
-    if (sc->status != 0) return;
-    const int lane = threadIdx.x & 63;
-    const int ny = op.ny;
-    const WaveTask wt = wave_task(op, t);
-    const double gxh = field[0], gyh = field[1];
-    double acc[3] = {0.0, 0.0, 0.0};
-    if (wt.active) {
-        const LaneGeo lg = lane_geo(op, t, wt.strip, lane);
-        const double gy = SITE ? gyh - op.bq * lg.x : gyh;
-        const PlanarF vin = make_view<PlanarF>(psi, op);
-        const uint32_t off = lg.inx ? PlanarF::lane_offset(lg.colw) : kOob;
-        const int y0 = wt.y0, y1 = wt.y1, base = y0 - 1;
-        RowCursor<PY> cin = row_cursor<PY>(psi, vin.row_bytes, ny, base, base, y1);
-        Raw<double2> F[PF];
-#pragma unroll
-        for (int i = 0; i < PF; ++i) {
-            F[i] = vin.load_at(cin.ptr(ny), cin.bytes(), off);
-            cin.next();
-        }
-        Sp P[4] = {sp_zero(), sp_zero(), sp_zero(), sp_zero()};
-        int R0 = base;
-        auto step = [&](auto kc) {
-            constexpr int k = decltype(kc)::value & 3;
-            constexpr int f = decltype(kc)::value % PF;
-            const int R = R0 + decltype(kc)::value;
-            if (R > y1) return;
-            P[k] = to_sp(F[f]);
-            F[f] = vin.load_at(cin.ptr(ny), cin.bytes(), off);
-            cin.next();
-            if (R - 1 < y0) return;
-            const Sp &c = P[(k + 3) & 3];  // row R-1 (inside the domain)
-            double v = 0.0, gx = gxh;
-            if constexpr (SITE) {
-                const double y = op.ymin + (R - 1) * op.hy;
-                v = site_pot_row(op, lg, R - 1, y);
-                gx = gxh + op.bq * y;
-            }
-            const Sp y = hop(op, c, sp_left(c), sp_right(c), P[(k + 2) & 3], P[k], v, gx, gy);
-            if (lg.own) {
-                acc[0] += sp_norm2(c);
-                acc[1] += sp_redot(c, y);
-                acc[2] += sp_norm2(y);
-            }
-        };
-        for (; R0 <= y1; R0 += U) unroll_steps(step, std::make_integer_sequence<int, U>{});
-    }
-    double tot[3];
-    if (!grid_reduce(acc, partials, &sc->ticket, tot)) return;
-    if (threadIdx.x == 0) {
-        const double n = tot[0], a = tot[1], yy = tot[2];
-        if (!isfinite(n) || !isfinite(a) || !isfinite(yy)) {
-            sc->status = 3;
-            sc->kstop = -1;
-            return;
-        }
-        if (n == 0.0) {
-            gamma[1] = 0.0;
-            alpha[1] = 0.0;
-            sc->sigma = 0.0;
-            sc->keff = 0;
-            sc->kstop = 0;
-            sc->beta_k = 0.0;
-            return;
-        }
-        const double g = sqrt(n);
-        const double al = a / n;
-        gamma[1] = g;
-        // With the shift on, the later sweeps run on A' = A - alpha_1 I: the same
-        // Krylov space, T' = T - alpha_1 I, so alpha'_1 = 0 and the residuals
-        // A' u - alpha' u no longer cancel by |alpha| / beta.
-        sc->sigma = shift ? al : 0.0;
-        alpha[1] = shift ? 0.0 : al;
-        sc->scale = fabs(al);
-        sc->keff = m;
-        sc->kstop = m;
-        // ||A psi - alpha_1 psi||^2 = ||A psi||^2 - a^2/n
-        sc->beta_k = sqrt(fmax(yy - a * (a / n), 0.0)) / g;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Lanczos iteration p >= 2 (see the file comment).  V1, V2: views of u_{p-1},
-// u_{p-2}; TO: storage type of u_p (paired layout); PF: FIFO depth in rows;
-// PY: periodic in y; SITE: the diagonal or the coupling varies over the grid
-// (potential, potential table or magnetic field), otherwise both are uniform
-// and computed once.
-// Rows marched: R = y0-2 .. y1+1 (u_{p-1} row R enters, u_p row R-1 is formed,
-// A u_p row R-2 is applied); ring slot of row r = (r - (y0-2)) mod 4.
-// ---------------------------------------------------------------------------
-
-template <class V1, class V2, class TO, bool HAS2, int PF, bool PY, bool SITE>
-__global__ __launch_bounds__(kBlock) void k_recur(PassArgs a)
-{
-    // rows are marched U at a time so that every ring and FIFO slot index is a
-    // compile-time constant; the rings hold four rows (slot = row mod 4)
-    constexpr int U = PF > 4 ? PF : 4;
-    static_assert(U % PF == 0 && U % 4 == 0, "FIFO depth must divide the unroll");
-    using T1 = typename V1::T;
-    using T2 = typename V2::T;
-    Scalars *sc = a.sc;
-    const int p = a.pass;
-    if (sc->kstop < p) return;
-    const bool last = (p == a.m);
-    const Op &op = a.op;
-    const int ny = op.ny;
-    const int lane = threadIdx.x & 63;
-    const WaveTask wt = wave_task(op, a.t);
-    const double g1 = a.gamma[p - 1];
-    const double inv_g1 = 1.0 / g1;
-    const double ca = a.alpha[p - 1] * inv_g1;
-    const double cb = HAS2 ? g1 / a.gamma[p - 2] : 0.0;
-    const double sig = sc->sigma;
-    const double gxh = a.field[0], gyh = a.field[1];
-    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (wt.active) {
-        const LaneGeo lg = lane_geo(op, a.t, wt.strip, lane);
-        const double gy = SITE ? gyh - op.bq * lg.x : gyh;
-        // u_p = cw (A' u_{p-1}) - cc u_{p-1} - cu u_{p-2}; lanes outside the domain
-        // get zero coefficients, so their u_p is zero without a select
-        const double m = lg.inx ? 1.0 : 0.0;
-        const double cw = m * inv_g1, cc = m * ca, cu = m * cb;
-        const V1 v1 = make_view<V1>(a.u1, op);
-        const V2 v2 = make_view<V2>(a.u2, op);
-        const Paired<TO> vo{static_cast<const char *>(a.uo), (uint32_t)(op.nx * 2 * sizeof(TO))};
-        const uint32_t off1 = lg.inx ? V1::lane_offset(lg.colw) : kOob;
-        const uint32_t off2 = lg.inx ? V2::lane_offset(lg.colw) : kOob;
-        const uint32_t offo = lg.own ? Paired<TO>::lane_offset(lg.colw) : kOob;
-        const int y0 = wt.y0, y1 = wt.y1, base = y0 - 2;
-        // cursors: u_{p-1} rows from base, u_{p-2} rows from base-1, u_p rows from base-1
-        RowCursor<PY> c1 = row_cursor<PY>(a.u1, v1.row_bytes, ny, base, base, y1 + 1);
-        RowCursor<PY> c2 = row_cursor<PY>(a.u2, v2.row_bytes, ny, base - 1, y0 - 1, y1);
-        RowCursor<PY> co = row_cursor<PY>(a.uo, vo.row_bytes, ny, base - 1, y0, y1 - 1);
-        // FIFOs: u_{p-1} row r in slot (r-base) mod PF, needed rows y0-2 .. y1+1;
-        //        u_{p-2} row r-1 in the same slot, needed rows y0-1 .. y1.
-        Raw<T1> F1[PF];
-        Raw<T2> F2[PF];
-#pragma unroll
-        for (int i = 0; i < PF; ++i) {
-            F1[i] = v1.load_at(c1.ptr(ny), c1.bytes(), off1);
-            c1.next();
-            if (HAS2) {
-                F2[i] = v2.load_at(c2.ptr(ny), c2.bytes(), off2);
-                c2.next();
-            } else {
-                F2[i] = raw_zero<T2>();
-            }
-        }
-        Sp P[4] = {sp_zero(), sp_zero(), sp_zero(), sp_zero()};  // u_{p-1} rows
-        Sp Q[4] = {sp_zero(), sp_zero(), sp_zero(), sp_zero()};  // u_p rows
-        double Vr[4] = {0.0, 0.0, 0.0, 0.0};                      // potential of the rows (SITE)
-        int R0 = base;
-        auto step = [&](auto kc) {
-            constexpr int k = decltype(kc)::value & 3;   // ring slot of row R
-            constexpr int f = decltype(kc)::value % PF;  // FIFO slot of row R
-            const int R = R0 + decltype(kc)::value;
-            if (R > y1 + 1) return;
-            P[k] = to_sp(F1[f]);
-            const Sp o2 = to_sp(F2[f]);
-            // refill: u_{p-1} row R+PF, u_{p-2} row R+PF-1
-            F1[f] = v1.load_at(c1.ptr(ny), c1.bytes(), off1);
-            c1.next();
-            if (HAS2) {
-                F2[f] = v2.load_at(c2.ptr(ny), c2.bytes(), off2);
-                c2.next();
-            }
-            // u_p at row R-1 (rows y0-1 .. y1)
-            if (R >= y0) {
-                const int rr = R - 1;
-                Sp u = sp_zero();
-                if (PY || (unsigned)rr < (unsigned)ny) {
-                    const Sp &c = P[(k + 3) & 3];
-                    double v = 0.0, gx = gxh;
-                    if constexpr (SITE) {
-                        const int jw = rr < 0 ? rr + ny : (rr >= ny ? rr - ny : rr);
-                        const double y = op.ymin + jw * op.hy;
-                        v = site_pot_row(op, lg, jw, y);
-                        gx = gxh + op.bq * y;
-                        Vr[(k + 3) & 3] = v;
-                    }
-                    const Sp w = hop(op, c, sp_left(c), sp_right(c), P[(k + 2) & 3], P[k], v, gx, gy, sig);
-                    u.r0 = cw * w.r0 - cc * c.r0 - cu * o2.r0;
-                    u.i0 = cw * w.i0 - cc * c.i0 - cu * o2.i0;
-                    u.r1 = cw * w.r1 - cc * c.r1 - cu * o2.r1;
-                    u.i1 = cw * w.i1 - cc * c.i1 - cu * o2.i1;
-                }
-                const Raw<TO> ur = to_raw<TO>(u);
-                Q[(k + 3) & 3] = to_sp(ur);
-                vo.store_at(co.ptr(ny), co.bytes(), offo, ur);
-            }
-            co.next();
-            // A u_p at row R-2 (rows y0 .. y1-1, inside the domain) and the reductions
-            if (R >= y0 + 2) {
-                const Sp &c = Q[(k + 2) & 3];
-                double v = 0.0, gx = gxh;
-                if constexpr (SITE) {
-                    v = Vr[(k + 2) & 3];
-                    gx = gxh + op.bq * (op.ymin + (R - 2) * op.hy);
-                }
-                const Sp y = hop(op, c, sp_left(c), sp_right(c), Q[(k + 1) & 3], Q[(k + 3) & 3], v, gx, gy, sig);
-                if (lg.own) {
-                    const Sp &prev = P[(k + 2) & 3];  // u_{p-1} row R-2
-                    acc[0] += sp_norm2(c);
-                    acc[1] += sp_redot(c, y);
-                    acc[2] += sp_redot(c, prev);
-                    if (last) {
-                        acc[3] += sp_norm2(y);
-                        acc[4] += sp_redot(y, prev);
-                    }
-                }
-            }
-        };
-        for (; R0 <= y1 + 1; R0 += U) unroll_steps(step, std::make_integer_sequence<int, U>{});
-    }
-    double tot[5];
-    if (!grid_reduce(acc, a.partials, &sc->ticket, tot)) return;
-    if (threadIdx.x == 0) {
-        const double n = tot[0], an = tot[1], o = tot[2], yy = tot[3], yv = tot[4];
-        if (!isfinite(n) || !isfinite(an) || !isfinite(o) || !isfinite(yy) || !isfinite(yv)) {
-            sc->status = 3;
-            sc->kstop = -1;
-            return;
-        }
-        const double gp = sqrt(n);  // beta_{p-1}
-        // breakdown scale on the unshifted alpha (the reading shared with the oracle)
-        const double scale = fmax(sc->scale, fabs(a.alpha[p - 1] + sig));
-        a.gamma[p] = gp;
-        if (gp <= 1e-13 * scale) {
-            // invariant Krylov subspace: stop with k_eff = p - 1, beta_k = gamma_p
-            sc->keff = p - 1;
-            sc->kstop = p - 1;
-            sc->beta_k = gp;
-            return;
-        }
-        sc->scale = fmax(scale, gp);
-        const double al = an / n - o / g1;
-        a.alpha[p] = al;
-        if (last) {
-            // w = A u_m - alpha_m u_m - (gamma_m^2/gamma_{m-1}) u_{m-1} = gamma_m u_{m+1}
-            const double bp = n / g1;
-            const double w2 = yy + al * al * n + bp * bp * (g1 * g1) - 2.0 * al * an - 2.0 * bp * yv +
-                              2.0 * al * bp * o;
-            sc->beta_k = sqrt(fmax(w2, 0.0)) / gp;
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// exp(-iT') e_1 for the k x k tridiagonal T' (Sec. 4, any standard method for
-// the small exponential; T' = T - sigma I is the shifted matrix of the sweeps)
-// in one wave, lane j holding row j.  Two methods, chosen by the Gershgorin
-// bound B of T':
-//  - B <= 64: scaling and Taylor series on the vector, exp(-iT') e_1 =
-//    (exp(-iT'/2^s))^(2^s) e_1 with 2^s >= B and 20 terms per factor (the
-//    truncation error of each factor is below 1/20!); one term is a
-//    tridiagonal product from the neighbouring lanes.  A few microseconds.
-//  - otherwise the eigendecomposition T' = Z Lambda Z^T by implicit symmetric
-//    QR steps with Wilkinson shift: lane i holds d_i and the coupling e_i in
-//    registers, the bulge chase fetches the next entries by shuffles one step
-//    ahead, deflation is a ballot, lane j owns row j of Z in its own LDS
-//    column; exp(-iT') e_1 = Z exp(-i Lambda) Z^T e_1.
-// Output: coef[j] = c_j / gamma_j with c = ||psi|| exp(-i sigma) exp(-iT') e_1,
-// and the step's error estimate beta_k |c_k| (eq. matrix_exponential_error).
-// ---------------------------------------------------------------------------
-constexpr int kTaylorTerms = 20;
-constexpr int kTaylorMaxDoublings = 6;
-
-__device__ __forceinline__ double wave_max(double v)
-{
-#pragma unroll
-    for (int s = 32; s >= 1; s >>= 1) v = fmax(v, __shfl_xor(v, s, 64));
-    return v;
-}
-
-__global__ __launch_bounds__(64) void k_tridiag(const double *alpha, const double *gamma, Scalars *sc,
-                                                StepStat *stat)
-{
-    __shared__ double zpr[(kMaxM + 1) * 64];
-    __shared__ double wre[kMaxM], wim[kMaxM];
-    const int lane = threadIdx.x;
-    if (sc->status != 0) return;
-    const int k = sc->keff;
-    if (k <= 0) {
-        for (int j = lane; j < 2 * (kMaxM + 2); j += 64) sc->coef[j] = 0.0;
-        if (lane == 0) {
-            sc->cabs_k = 0.0;
-            stat->keff = 0;
-            stat->err_est = 0.0;
-        }
-        return;
-    }
-    double d = (lane < k) ? alpha[lane + 1] : 0.0;
-    double e = (lane + 1 < k) ? gamma[lane + 2] : 0.0;  // zero for lanes >= k-1
-    double em = from_left(e);                           // e_{j-1}
-    if (lane == 0) em = 0.0;
-    const double bound = wave_max(fabs(d) + fabs(e) + fabs(em));
-    int sdbl = 0;
-    while (sdbl <= kTaylorMaxDoublings && ldexp(1.0, sdbl) < bound) ++sdbl;
-    double cr = 0.0, ci = 0.0;
-    if (sdbl <= kTaylorMaxDoublings) {
-        // v <- exp(-i h T') v, 2^s times, h = 2^-s
-        const double h = ldexp(1.0, -sdbl);
-        double vr = lane == 0 ? 1.0 : 0.0, vi = 0.0;
-        for (int rep = 0; rep < (1 << sdbl); ++rep) {
-            double tr = vr, ti = vi, wr = vr, wi = vi;
-            for (int n = 1; n <= kTaylorTerms; ++n) {
-                // u = T' t from the neighbouring lanes; t <- (-i h / n) u
-                const double ur = em * from_left(tr) + d * tr + e * from_right(tr);
-                const double ui = em * from_left(ti) + d * ti + e * from_right(ti);
-                const double f = h / n;
-                tr = f * ui;
-                ti = -f * ur;
-                wr += tr;
-                wi += ti;
-            }
-            vr = wr;
-            vi = wi;
-        }
-        cr = vr;
-        ci = vi;
-    } else {
-#define ZZ(i) zpr[(i) * 64 + lane]
-        for (int i = 0; i < k; ++i) ZZ(i) = (i == lane) ? 1.0 : 0.0;
-        const double eps = 2.220446049250313e-16;
-        for (int iter = 0; iter < 40 * kMaxM; ++iter) {
-            // negligible couplings are set to zero; find the last unreduced block [l, h]
-            const double dn = __shfl_down(d, 1, 64);
-            const bool live = lane + 1 < k && e != 0.0;
-            const bool tiny = live && fabs(e) <= eps * (fabs(d) + fabs(dn));
-            if (tiny) e = 0.0;
-            const unsigned long long mask = __ballot(live && !tiny);
-            if (mask == 0ull) break;
-            const int hb = 63 - __clzll(mask);  // highest coupling still live
-            const unsigned long long below = ~mask & ((1ull << hb) - 1ull);
-            const int l = below ? 64 - __clzll(below) : 0;
-            const int h = hb + 1;
-            // Wilkinson shift from the trailing 2x2 block of [l, h]
-            const double dh1 = __shfl(d, h - 1, 64), dh = __shfl(d, h, 64), eh1 = __shfl(e, h - 1, 64);
-            const double delta = 0.5 * (dh1 - dh);
-            const double b2 = eh1 * eh1;
-            const double mu = dh - b2 / (delta + copysign(sqrt(delta * delta + b2), delta));
-            double aq = __shfl(d, l, 64);  // current d_q
-            double bq = __shfl(e, l, 64);  // current e_q
-            double x = aq - mu, z = bq;
-            double aq1n = __shfl(d, l + 1, 64);
-            double bq1n = (l + 1 < h) ? __shfl(e, l + 1, 64) : 0.0;
-            double zq = ZZ(l);
-            for (int q = l; q < h; ++q) {
-                const double aq1 = aq1n, bq1 = bq1n;
-                // entries of the next step, fetched ahead (lanes > q+1 are untouched so far)
-                aq1n = __shfl(d, min(q + 2, 63), 64);
-                bq1n = (q + 2 < h) ? __shfl(e, min(q + 2, 63), 64) : 0.0;
-                const double zq1 = ZZ(q + 1);
-                const double rr = x * x + z * z;
-                double c = 1.0, s = 0.0, r = 0.0;
-                if (rr > 0.0) {
-                    const double ir = rsqrt(rr);
-                    c = x * ir;
-                    s = -z * ir;
-                    r = rr * ir;
-                }
-                if (q > l && lane == q - 1) e = r;
-                const double cc = c * c, ss = s * s, cs = c * s;
-                const double dq = cc * aq - 2.0 * cs * bq + ss * aq1;
-                const double dq1 = ss * aq + 2.0 * cs * bq + cc * aq1;
-                const double eq = cs * (aq - aq1) + (cc - ss) * bq;
-                if (lane == q) d = dq;
-                ZZ(q) = c * zq - s * zq1;
-                zq = s * zq + c * zq1;
-                aq = dq1;
-                if (q + 1 < h) {
-                    x = eq;
-                    z = -s * bq1;
-                    bq = c * bq1;
-                } else {
-                    if (lane == q) e = eq;
-                    if (lane == q + 1) d = dq1;
-                }
-            }
-            ZZ(h) = zq;
-        }
-        // c_j = sum_i Z[j][i] exp(-i lambda_i) Z[0][i]; lambda_i is lane i's d
-        __syncthreads();
-        if (lane < k) {
-            double sn, cs;
-            sincos(d, &sn, &cs);
-            const double z0 = zpr[lane * 64 + 0];
-            wre[lane] = z0 * cs;
-            wim[lane] = -z0 * sn;
-        }
-        __syncthreads();
-        if (lane < k) {
-            for (int i = 0; i < k; ++i) {
-                const double zji = ZZ(i);
-                cr += zji * wre[i];
-                ci += zji * wim[i];
-            }
-        }
-#undef ZZ
-    }
-    if (lane < k) {
-        // exp(-iT) = exp(-i sigma) exp(-iT') for the shifted tridiagonal T'
-        double ss, sc0;
-        sincos(sc->sigma, &ss, &sc0);
-        const double g1 = gamma[1];
-        const double tr = g1 * (cr * sc0 + ci * ss), ti = g1 * (ci * sc0 - cr * ss);
-        const double ig = 1.0 / gamma[lane + 1];
-        sc->coef[2 * (lane + 1)] = tr * ig;
-        sc->coef[2 * (lane + 1) + 1] = ti * ig;
-        if (lane == k - 1) {
-            const double ck = sqrt(tr * tr + ti * ti);
-            sc->cabs_k = ck;
-            stat->keff = k;
-            stat->err_est = sc->beta_k * ck;
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Recombination psi_new = sum_j c_j q_j = sum_j (c_j / gamma_j) u_j
-// (eq. matrix_exp_approx): a site-local multi-axpy, plus ||psi_new||^2 for the
-// step statistics.  A workgroup owns a tile of 256*S sites and streams the
-// Krylov vectors one after the other over it (S sites per thread, strided by
-// the workgroup so every load is coalesced), so each vector is read in long
-// contiguous runs.  The streams are read once and never reused: nontemporal
-// loads and stores keep them from displacing cache lines of the other
-// streams.
-// ---------------------------------------------------------------------------
-typedef double dv2 __attribute__((ext_vector_type(2)));
-typedef float fv4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ double2 ld_stream(const double2 *p)
-{
-    const dv2 v = __builtin_nontemporal_load(reinterpret_cast<const dv2 *>(p));
-    return make_double2(v.x, v.y);
-}
-
-__device__ __forceinline__ void st_stream(double2 *p, double x, double y)
-{
-    dv2 v;
-    v.x = x;
-    v.y = y;
-    __builtin_nontemporal_store(v, reinterpret_cast<dv2 *>(p));
-}
-
-template <class TB>
-__device__ __forceinline__ Raw<TB> ld_site(const char *p);
-template <>
-__device__ __forceinline__ Raw<float2> ld_site<float2>(const char *p)
-{
-    const fv4 v = __builtin_nontemporal_load(reinterpret_cast<const fv4 *>(p));
-    return Raw<float2>{make_float2(v.x, v.y), make_float2(v.z, v.w)};
-}
-template <>
-__device__ __forceinline__ Raw<double2> ld_site<double2>(const char *p)
-{
-    return Raw<double2>{ld_stream(reinterpret_cast<const double2 *>(p)),
-                        ld_stream(reinterpret_cast<const double2 *>(p) + 1)};
-}
-
-// WPE: minimum resident waves per SIMD asked of the register allocator.
-template <class TB, int S, int WPE>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_combine(CombArgs a)
-{
-    Scalars *sc = a.sc;
-    if (sc->status != 0) return;
-    const int k = sc->keff;
-    const char *__restrict__ basis = static_cast<const char *>(a.basis);
-    const size_t sites = a.sites;
-    const size_t tile = (size_t)kBlock * S;
-    constexpr size_t kSite = 2 * sizeof(TB);
-    double nrm = 0.0;
-    for (size_t s0 = (size_t)blockIdx.x * tile; s0 < sites; s0 += (size_t)gridDim.x * tile) {
-        Sp acc[S];
-        {
-            const double cr = k >= 1 ? sc->coef[2] : 0.0, ci = k >= 1 ? sc->coef[3] : 0.0;
-#pragma unroll
-            for (int q = 0; q < S; ++q) {
-                const size_t s = s0 + (size_t)q * kBlock + threadIdx.x;
-                double2 p0 = make_double2(0.0, 0.0), p1 = p0;
-                if (s < sites) {
-                    p0 = ld_stream(a.psi + s);
-                    p1 = ld_stream(a.psi + sites + s);
-                }
-                acc[q].r0 = cr * p0.x - ci * p0.y;
-                acc[q].i0 = cr * p0.y + ci * p0.x;
-                acc[q].r1 = cr * p1.x - ci * p1.y;
-                acc[q].i1 = cr * p1.y + ci * p1.x;
-            }
-        }
-        for (int j = 2; j <= k; ++j) {
-            const char *u = basis + (size_t)(j - 2) * a.vec_bytes;
-            Raw<TB> v[S];
-#pragma unroll
-            for (int q = 0; q < S; ++q) {
-                const size_t s = s0 + (size_t)q * kBlock + threadIdx.x;
-                v[q] = s < sites ? ld_site<TB>(u + s * kSite) : raw_zero<TB>();
-            }
-            const double cr = sc->coef[2 * j], ci = sc->coef[2 * j + 1];
-#pragma unroll
-            for (int q = 0; q < S; ++q) {
-                const Sp w = to_sp(v[q]);
-                acc[q].r0 += cr * w.r0 - ci * w.i0;
-                acc[q].i0 += cr * w.i0 + ci * w.r0;
-                acc[q].r1 += cr * w.r1 - ci * w.i1;
-                acc[q].i1 += cr * w.i1 + ci * w.r1;
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < S; ++q) {
-            const size_t s = s0 + (size_t)q * kBlock + threadIdx.x;
-            if (s < sites) {
-                st_stream(a.out + s, acc[q].r0, acc[q].i0);
-                st_stream(a.out + sites + s, acc[q].r1, acc[q].i1);
-                nrm += sp_norm2(acc[q]);
-            }
-        }
-    }
-    double accv[1] = {nrm}, tot[1];
-    if (!grid_reduce(accv, a.partials, &sc->ticket, tot)) return;
-    if (threadIdx.x == 0) {
-        a.stat->norm2 = tot[0];
-        if (!isfinite(tot[0])) {
-            sc->status = 3;
-            sc->kstop = -1;
-            return;
-        }
-        sc->steps_done += 1;
-    }
-}
-
-// sites per thread of the recombination and the occupancy asked for (five
-// waves per SIMD fit the complex64 form without spills)
-#ifndef DL_COMB_S_MIXED
-#define DL_COMB_S_MIXED 4
-#endif
-#ifndef DL_COMB_BLOCKS_PER_CU
-#define DL_COMB_BLOCKS_PER_CU 4
-#endif
-constexpr int kCombMixed = DL_COMB_S_MIXED;
-constexpr int kCombFp64 = 8;
-constexpr int kCombWpeMixed = 5;
-constexpr int kCombWpeFp64 = 1;
-
-// ---------------------------------------------------------------------------
-// y = H x (test hook; operator scale 1).
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_apply(Op op, Tiles t, const double2 *__restrict__ x,
-                                                  double2 *__restrict__ y, double gxh, double gyh)
-{
-    const int lane = threadIdx.x & 63;
-    const WaveTask wt = wave_task(op, t);
-    if (!wt.active) return;
-    const size_t plane = (size_t)op.nx * op.ny;
-    const LaneGeo lg = lane_geo(op, t, wt.strip, lane);
-    const double gy = gyh - op.bq * lg.x;
-    const Planar vin{reinterpret_cast<const char *>(x), plane * 16, (uint32_t)op.nx * 16u};
-    const uint32_t off = lg.inx ? Planar::lane_offset(lg.colw) : kOob;
-    Sp p0 = sp_zero(), p1 = sp_zero();
-    Sp p2 = to_sp(load_row(vin, op, off, wt.y0 - 1));
-    for (int R = wt.y0; R <= wt.y1; ++R) {
-        p0 = p1;
-        p1 = p2;
-        p2 = to_sp(load_row(vin, op, off, R));
-        if (R - 1 < wt.y0) continue;
-        const RowGeo rg = row_geo(op, R - 1);
-        const Sp o = hop(op, p1, sp_left(p1), sp_right(p1), p0, p2, site_pot(op, lg, rg),
-                         gxh + op.bq * rg.y, gy);
-        if (lg.own) {
-            const size_t idx = (size_t)(R - 1) * op.nx + lg.colw;
-            y[idx] = make_double2(o.r0, o.i0);
-            y[plane + idx] = make_double2(o.r1, o.i1);
-        }
-    }
-}
-
-__global__ void k_reset(Scalars *sc)
-{
-    if (threadIdx.x == 0) {
-        sc->status = 0;
-        sc->steps_done = 0;
-        sc->ticket = 0u;
-        sc->kstop = 0;
-        sc->keff = 0;
-        sc->scale = 0.0;
-        sc->cabs_k = 0.0;
-        sc->beta_k = 0.0;
-        sc->sigma = 0.0;
-    }
-}
-
-// FIFO depths (rows of loads in flight per wave).
-#ifndef DL_PF_MIXED
-#define DL_PF_MIXED 2
-#endif
-#ifndef DL_PF_FP64
-#define DL_PF_FP64 2
-#endif
-#ifndef DL_WPE_MIXED
-#define DL_WPE_MIXED 1
-#endif
-constexpr int kPfFirst = 4;
-constexpr int kPfMixed = DL_PF_MIXED;
-constexpr int kPfFp64 = DL_PF_FP64;
-// occupancy hint of the complex64 sweeps (1: none).  Three waves per SIMD fit
-// them without spills but measured slower than the two the allocator picks.
-constexpr int kWpeMixed = DL_WPE_MIXED;
-
-// Load policy of the sweeps per precision (measured on the 4096^2 workload:
-// the streaming hint helps the complex64 sweeps and hurts the complex128 ones).
-#ifndef DL_LOAD_POL_MIXED
-#define DL_LOAD_POL_MIXED kPolStream
-#endif
-#ifndef DL_LOAD_POL_FP64
-#define DL_LOAD_POL_FP64 kPolDefault
-#endif
-using PlanarM = PlanarT<DL_LOAD_POL_MIXED>;
-using PairedM = Paired<float2, DL_LOAD_POL_MIXED>;
-using PlanarD = PlanarT<DL_LOAD_POL_FP64>;
-using PairedD = Paired<double2, DL_LOAD_POL_FP64>;
-
-template <class K>
-int waves_per_cu(K kernel)
-{
-    int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kernel, kBlock, 0) != hipSuccess) {
-        (void)hipGetLastError();
-        return 8;
-    }
-    return blocks * kWaves;
-}
-
-
-// The four specialisations (periodic y, site-dependent terms) of one sweep kind.
-template <class V1, class V2, class TO, bool HAS2, int PF>
-struct RecurKind {
-    template <bool PY, bool SITE>
-    static constexpr auto kernel() { return k_recur<V1, V2, TO, HAS2, PF, PY, SITE>; }
-    template <class F>
-    static auto dispatch(bool py, bool site, F &&f)
-    {
-        if (py) return site ? f(kernel<true, true>()) : f(kernel<true, false>());
-        return site ? f(kernel<false, true>()) : f(kernel<false, false>());
-    }
-};
-
-template <bool M>
-using RecurP2 = RecurKind<std::conditional_t<M, PlanarM, PlanarD>, std::conditional_t<M, PlanarM, PlanarD>,
-                          std::conditional_t<M, float2, double2>, false, M ? kPfMixed : kPfFp64>;
-template <bool M>
-using RecurP3 = RecurKind<std::conditional_t<M, PairedM, PairedD>, std::conditional_t<M, PlanarM, PlanarD>,
-                          std::conditional_t<M, float2, double2>, true, M ? kPfMixed : kPfFp64>;
-template <bool M>
-using RecurPn = RecurKind<std::conditional_t<M, PairedM, PairedD>, std::conditional_t<M, PairedM, PairedD>,
-                          std::conditional_t<M, float2, double2>, true, M ? kPfMixed : kPfFp64>;
-
-bool op_site(const Op &op) { return op.pot_kind != 0 || op.has_table != 0 || op.bq != 0.0; }
-
-template <template <bool> class Kind, class F>
-auto with_kind(bool mixed, bool py, bool site, F &&f)
-{
-    if (mixed) return Kind<true>::dispatch(py, site, f);
-    return Kind<false>::dispatch(py, site, f);
-}
-
-}  // namespace
 
 int sweep_waves_per_cu(int which, bool mixed, bool py, bool site)
 {
@@ -1141,9 +14,9 @@ int sweep_waves_per_cu(int which, bool mixed, bool py, bool site)
     switch (which) {
     case 0: return py ? (site ? waves_per_cu(k_first<kPfFirst, true, true>) : waves_per_cu(k_first<kPfFirst, true, false>))
                       : (site ? waves_per_cu(k_first<kPfFirst, false, true>) : waves_per_cu(k_first<kPfFirst, false, false>));
-    case 1: return with_kind<RecurPn>(mixed, py, site, occ);
-    case 2: return with_kind<RecurP2>(mixed, py, site, occ);
-    case 3: return with_kind<RecurP3>(mixed, py, site, occ);
+    case 1: return with_kind<RecurPn, SingleRecur>(mixed, py, site, occ);
+    case 2: return with_kind<RecurP2, SingleRecur>(mixed, py, site, occ);
+    case 3: return with_kind<RecurP3, SingleRecur>(mixed, py, site, occ);
     default: return waves_per_cu(k_apply);
     }
 }
@@ -1208,11 +81,11 @@ void launch_recur(const PassArgs &a, bool mixed, hipStream_t st)
     };
     const bool py = a.op.bcy != 0, site = op_site(a.op);
     if (a.pass == 2)
-        with_kind<RecurP2>(mixed, py, site, go);
+        with_kind<RecurP2, SingleRecur>(mixed, py, site, go);
     else if (a.pass == 3)
-        with_kind<RecurP3>(mixed, py, site, go);
+        with_kind<RecurP3, SingleRecur>(mixed, py, site, go);
     else
-        with_kind<RecurPn>(mixed, py, site, go);
+        with_kind<RecurPn, SingleRecur>(mixed, py, site, go);
 }
 
 void launch_tridiag(const double *alpha, const double *gamma, Scalars *sc, StepStat *stat,

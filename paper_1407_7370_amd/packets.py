@@ -83,6 +83,26 @@ def paper_packet_8192(seed: int = 0):
                 precision="fp64")
 
 
+def packet_batch(seed: int = 0, n_packets: int = 256, sizes=(128, 192, 256, 384, 512), h: float = 0.078125):
+    """A batch of independent packets of different sizes and fields: grid
+    n_b x n_b with n_b drawn from `sizes`, fixed spacing h (box n_b*h, centred),
+    Dirichlet, uniform B_z ~ U[0, 2], no potential, packet centre uniform in
+    [-n_b h/4, n_b h/4]^2, |p0| <= 5 uniform in the disk, sigma = 2; mixed,
+    m = 12, dt = 1e-3, 200 steps.  Returns a list of workload dicts."""
+    rng = np.random.default_rng(5000 + seed)
+    out = []
+    for b in range(n_packets):
+        n = int(rng.choice(sizes))
+        half = 0.5 * n * h
+        prob = _base(n, -half, half, 0)
+        prob["bz"] = float(rng.uniform(0.0, 2.0))
+        q = 0.25 * n * h
+        center = (float(rng.uniform(-q, q)), float(rng.uniform(-q, q)))
+        out.append(dict(name=f"batch_{n}x{n}", problem=prob, m=12, dt=1e-3, steps=200, sigma=2.0, p_max=5.0,
+                        center=center, seed=int(rng.integers(0, 2 ** 31)), precision="mixed"))
+    return out
+
+
 def with_grid(cfg: dict, n: int):
     """Same workload on an n x n grid over the same box (reduced-size parity cases)."""
     cfg = dict(cfg)

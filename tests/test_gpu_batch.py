@@ -1,0 +1,142 @@
+"""GPU batched propagation (one launch per Lanczos iteration over all packets)
+through the C ABI: every packet against its own single-grid run and against
+the oracle.  The batch folds each packet's reductions over its own segment of
+workgroups, with other tile shapes than the single-grid launch, so packet
+results agree with single-grid results to rounding (FP64: 1e-12 relative
+L2), not bitwise; against the oracle the FP64 bar is 1e-10.
+"""
+import numpy as np
+import pytest
+
+from paper_1407_7370_amd import packets
+
+pytestmark = pytest.mark.gpu
+
+C = 137.036
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def say(msg):
+    print(f"[gpu case] {msg}", flush=True)
+
+
+def prob(nx, ny, bc=0, **kw):
+    p = dict(nx=nx, ny=ny, x_min=-0.06 * nx, x_max=0.06 * nx, y_min=-0.05 * ny, y_max=0.05 * ny, bc_x=bc,
+             bc_y=bc, mass=1.0, c=C, charge=-1.0, bz=0.0, pot_kind=0, pot_z=0.0, pot_a=0.0, pulse_kind=0,
+             pulse_e=(0.0, 0.0), a0=0.0, omega=0.0, t_pulse=1.0, coef=None)
+    p.update(kw)
+    return p
+
+
+def small_batch(bc=0):
+    rng = np.random.default_rng(7)
+    return [
+        prob(70, 33, bc, bz=0.7),
+        prob(64, 64, bc, pulse_kind=1, pulse_e=(0.6, 0.8), a0=30.0, omega=1.0, t_pulse=0.02),
+        prob(17, 90, bc, pot_kind=1, pot_z=1.0, pot_a=1.0),
+        prob(131, 40, bc, pulse_kind=2, t_pulse=0.02, coef=rng.uniform(-20, 20, 8)),
+        prob(8, 8, bc, bz=-1.1, pot_kind=2, pot_z=2.0),
+    ]
+
+
+def states(probs, seed):
+    return [packets.gaussian_packet(p, 0.6, packets.draw_momentum(seed + i, 3.0), project=True)
+            for i, p in enumerate(probs)]
+
+
+def run_batch(torch, probs, psi0, m, prec, dt, n):
+    from paper_1407_7370_amd.binding import BatchPropagator
+    bp = BatchPropagator(probs, m, prec)
+    psis = [torch.from_numpy(np.ascontiguousarray(x)).to("cuda") for x in psi0]
+    st = bp.step(psis, 0.0, dt, n)
+    out = [x.cpu().numpy() for x in psis]
+    bp.close()
+    return out, st
+
+
+def run_single(torch, p, psi0, m, prec, dt, n):
+    from paper_1407_7370_amd.binding import Propagator
+    prop = Propagator(p, m, prec)
+    psi = torch.from_numpy(np.ascontiguousarray(psi0)).to("cuda")
+    st = prop.step(psi, 0.0, dt, n)
+    out = psi.cpu().numpy()
+    prop.close()
+    return out, st
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_batch_fp64_vs_single_and_oracle(torch_cuda, orc, bc):
+    probs = small_batch(bc)
+    psi0 = states(probs, 10)
+    dt, n, m = 1e-3, 15, 10
+    say(f"batch fp64 bc={bc} {len(probs)} packets {n} steps")
+    outb, stb = run_batch(torch_cuda, probs, psi0, m, "fp64", dt, n)
+    for i, p in enumerate(probs):
+        outs, sts = run_single(torch_cuda, p, psi0[i], m, "fp64", dt, n)
+        assert rel(outb[i], outs) <= 1e-12, i
+        assert np.array_equal(stb[i]["k_eff"], sts["k_eff"])
+        np.testing.assert_allclose(stb[i]["norm2"], sts["norm2"], rtol=1e-12)
+        ref, _ = orc.propagate(p, psi0[i], 0.0, dt, n, m)
+        assert rel(outb[i], ref) <= 1e-10, i
+
+
+def test_batch_mixed_vs_single(torch_cuda):
+    probs = small_batch(0)
+    psi0 = states(probs, 20)
+    dt, n, m = 1e-3, 12, 12
+    say(f"batch mixed {len(probs)} packets {n} steps")
+    outb, _ = run_batch(torch_cuda, probs, psi0, m, "mixed", dt, n)
+    for i, p in enumerate(probs):
+        outs, _ = run_single(torch_cuda, p, psi0[i], m, "mixed", dt, n)
+        ref, _ = run_single(torch_cuda, p, psi0[i], m, "fp64", dt, n)
+        assert rel(outb[i], outs) <= 1e-8, i
+        assert rel(outb[i], ref) <= 1e-6, i
+
+
+def test_batch_odd_and_even_step_counts(torch_cuda):
+    """The ping-pong between psi and the workspace ends in psi for both parities."""
+    probs = small_batch(0)[:3]
+    psi0 = states(probs, 30)
+    say("batch parity 1 and 2 steps")
+    for n in (1, 2):
+        outb, _ = run_batch(torch_cuda, probs, psi0, 8, "fp64", 1e-3, n)
+        for i, p in enumerate(probs):
+            outs, _ = run_single(torch_cuda, p, psi0[i], 8, "fp64", 1e-3, n)
+            assert rel(outb[i], outs) <= 1e-12
+
+
+def test_batch_rejections(torch_cuda):
+    from paper_1407_7370_amd.binding import BatchPropagator, DlError, DL_ERR_UNSUPPORTED, DL_ERR_INVALID
+    say("batch rejections")
+    with pytest.raises(DlError) as e:
+        BatchPropagator([prob(16, 16, 0), prob(16, 16, 1)], 8, "fp64")
+    assert e.value.status == DL_ERR_UNSUPPORTED
+    with pytest.raises(DlError) as e:
+        BatchPropagator([prob(16, 16, 0), prob(2, 16, 0)], 8, "fp64")
+    assert e.value.status == DL_ERR_INVALID
+
+
+def test_batch_256_packets_sampled(torch_cuda):
+    """The 256-packet workload (28M sites, mixed, m = 12): a few steps of the
+    whole batch, sampled packets against their single-grid runs."""
+    torch = torch_cuda
+    cfgs = packets.packet_batch(seed=0)
+    probs = [c["problem"] for c in cfgs]
+    psi0 = [packets.initial_state(c) for c in cfgs]
+    m, dt, n = cfgs[0]["m"], cfgs[0]["dt"], 4
+    say(f"batch 256 packets mixed {n} steps")
+    outb, stb = run_batch(torch, probs, psi0, m, "mixed", dt, n)
+    assert all(np.all(s["k_eff"] == m) for s in stb)
+    for i in (0, 1, 77, 128, 255):
+        outs, _ = run_single(torch, probs[i], psi0[i], m, "mixed", dt, n)
+        assert rel(outb[i], outs) <= 1e-8, i
