@@ -97,6 +97,52 @@ def run_precision(torch, Propagator, cfg, psi0_dev, precision, steps, warmup, co
     return psi, stats, wall, timing, wall_ev, same
 
 
+def run_batch(torch, packets, steps):
+    """The 256-packet batch (grids 128^2..512^2, B_z ~ U[0,2], mixed, m = 12):
+    one batched step call vs the same packets propagated one context at a
+    time (a few steps each, rate extrapolated)."""
+    from paper_1407_7370_amd.binding import BatchPropagator, Propagator
+    cfgs = packets.packet_batch(seed=0)
+    probs = [c["problem"] for c in cfgs]
+    m, dt = cfgs[0]["m"], cfgs[0]["dt"]
+    sites = sum(p["nx"] * p["ny"] for p in probs)
+    psi0 = [torch.from_numpy(packets.initial_state(c)).to("cuda") for c in cfgs]
+    log(f"batch: {len(probs)} packets, {sites / 1e6:.1f}M sites, m={m}, {steps} steps")
+    bp = BatchPropagator(probs, m, "mixed", tuning_cache=True)
+    psis = [x.clone() for x in psi0]
+    bp.step(psis, 0.0, dt, 2, want_stats=False)
+    psis = [x.clone() for x in psi0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bp.step(psis, 0.0, dt, steps, want_stats=False)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    bp.close()
+    # one context per packet, 2 steps each
+    seq_steps = 2
+    props = [Propagator(p, m, "mixed") for p in probs]
+    qs = [x.clone() for x in psi0]
+    props[0].step(qs[0], 0.0, dt, 1, want_stats=False)
+    qs = [x.clone() for x in psi0]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for pr, q in zip(props, qs):
+        pr.step(q, 0.0, dt, seq_steps, want_stats=False)
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t1
+    for pr in props:
+        pr.close()
+    rate = sites * m * steps / wall
+    seq_rate = sites * m * seq_steps / seq
+    log(f"batch: {wall * 1e3 / steps:.3f} ms/step ({rate:.3e} site-matvecs/s); one context per packet: "
+        f"{seq * 1e3 / seq_steps:.2f} ms/step")
+    return {"workload": "packet_batch_256 (grids 128^2..512^2, mixed, m=12, dt=1e-3)", "packets": len(probs),
+            "sites": sites, "steps": steps, "ms_per_step": wall * 1e3 / steps, "value": rate,
+            "unit": "site-matvecs/s", "per_packet_contexts": {"ms_per_step": seq * 1e3 / seq_steps,
+                                                              "value": seq_rate},
+            "speedup": seq_rate and rate / seq_rate}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +151,8 @@ def main():
     ap.add_argument("--grid", type=int, default=4096, help="grid size (default: the 4096^2 workload)")
     ap.add_argument("--precision", choices=("both", "mixed", "fp64"), default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=50,
+                    help="steps of the 256-packet batch measurement (0: skip)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run a plain copy of this many MiB (counter calibration for rocprofv3)")
     args = ap.parse_args()
@@ -215,6 +263,9 @@ def main():
     out["paper_context"] = {"value": 5.6e6, "unit": "site-matvecs/s",
                             "what": "derived from ~2 min per step, 8192^2 grid, k=10, one process on a "
                                     "dual Xeon-E5 cluster node (Sec. 7); context, not the target"}
+
+    if args.batch_steps > 0:
+        out["batch_packets"] = run_batch(torch, packets, args.batch_steps)
 
     if not args.no_cpu_baseline:
         import oracle

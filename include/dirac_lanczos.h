@@ -242,6 +242,20 @@ dl_status dirac_lanczos_batch_destroy(dl_batch *batch);
 const char *dirac_lanczos_batch_last_error(const dl_batch *batch);
 
 /*
+ * Launch shape (tuning; results are equal to rounding for every shape).
+ * dirac_lanczos_set_launch: at most sweep_waves_per_cu waves per compute unit
+ *   in the Lanczos sweeps (0: the built-in default, eight); the row chunks
+ *   are re-planned for one resident round of waves.  *waves_out (HOST, may
+ *   be NULL) receives the value in use (capped by occupancy).
+ * dirac_lanczos_batch_set_launch: rows per chunk of the batched sweeps
+ *   (>= 4; 0: the default choice, the smallest power of two giving at most
+ *   one resident round of waves).  *rows_out (HOST, may be NULL) receives it.
+ * The autotuner of the Python package times candidates and caches the best.
+ */
+dl_status dirac_lanczos_set_launch(dl_context *ctx, int32_t sweep_waves_per_cu, int32_t *waves_out);
+dl_status dirac_lanczos_batch_set_launch(dl_batch *batch, int32_t rows_per_chunk, int32_t *rows_out);
+
+/*
  * Kernel timing with HIP events recorded on the context's stream around every
  * launch of dirac_lanczos_step (a diagnostic for roofline measurements).
  * Classes: 0 first Lanczos iteration; 1 recurrence sweeps whose operands are

@@ -26,7 +26,8 @@ EXPORTS = ("dirac_lanczos_workspace_bytes", "dirac_lanczos_init", "dirac_lanczos
            "dirac_lanczos_step", "dirac_lanczos_eigen", "dirac_lanczos_adjoint_workspace_bytes",
            "dirac_lanczos_adjoint", "dirac_lanczos_timing", "dirac_lanczos_destroy",
            "dirac_lanczos_last_error", "dirac_lanczos_batch_workspace_bytes", "dirac_lanczos_batch_init",
-           "dirac_lanczos_batch_step", "dirac_lanczos_batch_destroy", "dirac_lanczos_batch_last_error")
+           "dirac_lanczos_batch_step", "dirac_lanczos_batch_destroy", "dirac_lanczos_batch_last_error",
+           "dirac_lanczos_set_launch", "dirac_lanczos_batch_set_launch")
 DL_LOSS_X, DL_LOSS_Y, DL_LOSS_PX, DL_LOSS_PY = 1, 2, 4, 8
 
 
@@ -116,6 +117,11 @@ def load_library():
     lib.dirac_lanczos_batch_destroy.restype = ctypes.c_int
     lib.dirac_lanczos_batch_last_error.argtypes = [vp]
     lib.dirac_lanczos_batch_last_error.restype = ctypes.c_char_p
+    I = ctypes.POINTER(ctypes.c_int32)
+    lib.dirac_lanczos_set_launch.argtypes = [vp, ctypes.c_int32, I]
+    lib.dirac_lanczos_set_launch.restype = ctypes.c_int
+    lib.dirac_lanczos_batch_set_launch.argtypes = [vp, ctypes.c_int32, I]
+    lib.dirac_lanczos_batch_set_launch.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -248,7 +254,7 @@ class Propagator:
     """
 
     def __init__(self, problem: dict, krylov_dim: int, precision: str = "fp64", k_eigen: int = 0,
-                 stream=None, v_table=None):
+                 stream=None, v_table=None, tuning_cache=None):
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -271,6 +277,14 @@ class Propagator:
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.ctx = dirac_lanczos_init(self.params, self.ws_ptr, nbytes, self.stream.cuda_stream)
         self.shape = (2, int(problem["ny"]), int(problem["nx"]))
+        if tuning_cache:
+            # launch shape from the autotuner's cache (True: the package's cache file)
+            from . import autotune
+            path = autotune.DEFAULT_CACHE if tuning_cache is True else tuning_cache
+            best = autotune.lookup(autotune.key_single(problem, krylov_dim, precision, autotune.device_arch()),
+                                   path)
+            if best is not None:
+                self.set_launch(best)
 
     def _check_psi(self, psi):
         t = self.torch
@@ -330,6 +344,13 @@ class Propagator:
         del ws
         return float(loss.value), np.array(grad[:int(self.params.n_coef)])
 
+    def set_launch(self, sweep_waves_per_cu: int) -> int:
+        """Sweep launch shape (0: default); returns the waves per CU in use."""
+        w = ctypes.c_int32(0)
+        _check(self.lib, self.ctx, self.lib.dirac_lanczos_set_launch(self.ctx, int(sweep_waves_per_cu),
+                                                                     ctypes.byref(w)))
+        return int(w.value)
+
     def timing(self, enable: bool):
         """Start (True) or stop (False) event timing; returns the accumulated
         {class: (launches, total_ms)} collected so far."""
@@ -354,7 +375,7 @@ class BatchPropagator:
     packets.py) sharing krylov_dim, precision and bc_y; psi tensors are
     complex128 of shape (2, ny_i, nx_i), contiguous, on the GPU."""
 
-    def __init__(self, problems, krylov_dim: int, precision: str = "fp64", stream=None):
+    def __init__(self, problems, krylov_dim: int, precision: str = "fp64", stream=None, tuning_cache=None):
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -376,6 +397,12 @@ class BatchPropagator:
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.batch = dirac_lanczos_batch_init(arr, self.n, self.ws_ptr, nbytes, self.stream.cuda_stream)
         self.shapes = [(2, int(p["ny"]), int(p["nx"])) for p in problems]
+        if tuning_cache:
+            from . import autotune
+            path = autotune.DEFAULT_CACHE if tuning_cache is True else tuning_cache
+            best = autotune.lookup(autotune.key_batch(problems, krylov_dim, precision, autotune.device_arch()), path)
+            if best is not None:
+                self.set_launch(best)
 
     def step(self, psis, t0: float, dt: float, n_steps: int, want_stats: bool = True):
         """In-place propagation of every packet.  Returns per-packet stats dicts."""
@@ -400,6 +427,14 @@ class BatchPropagator:
         if st != DL_OK:
             raise DlError(st, dirac_lanczos_batch_last_error(self.batch))
         return out
+
+    def set_launch(self, rows_per_chunk: int) -> int:
+        """Rows per chunk of the batched sweeps (0: default); returns the value in use."""
+        r = ctypes.c_int32(0)
+        st = self.lib.dirac_lanczos_batch_set_launch(self.batch, int(rows_per_chunk), ctypes.byref(r))
+        if st != DL_OK:
+            raise DlError(st, dirac_lanczos_batch_last_error(self.batch))
+        return int(r.value)
 
     def close(self):
         if getattr(self, "batch", None):

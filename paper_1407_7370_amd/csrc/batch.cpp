@@ -41,6 +41,8 @@ struct dl_batch {
     char *scalars = nullptr;       // n x scalar stride
     size_t sc_stride = 0;
     int nblk[dl::kGridKinds] = {0, 0, 0};
+    size_t max_blocks[dl::kGridKinds] = {0, 0, 0};
+    int rows = 0;  // rows per chunk of the sweeps
     std::vector<dl::BatchPacket> h_pk;
     std::vector<double> h_fields;
     std::vector<dl::StepStat> h_stats;
@@ -148,6 +150,81 @@ const char *batch_validate(const dl_params *params, int n)
     return nullptr;
 }
 
+// Task and workgroup tables for rows_per_chunk R (0: the default choice):
+// the smallest power of two >= 4 with at most one resident round of sweep
+// waves, or one chunk per strip when even that is more.
+dl_status build_tables(dl_batch *b, int rows_per_chunk)
+{
+    const int n = b->n;
+    const std::vector<dl_params> &params = b->p;
+    int R = rows_per_chunk;
+    if (R <= 0) {
+        const int wr = std::min(dl::batch_waves_per_cu(1, b->mixed, b->py, b->site), 8);
+        const size_t target = (size_t)wr * b->cus;
+        int max_ny = 0;
+        for (int i = 0; i < n; ++i) max_ny = std::max(max_ny, params[i].ny);
+        R = 4;
+        for (;;) {
+            size_t t = 0;
+            for (int i = 0; i < n; ++i) t += (size_t)strips(params[i].nx, 2) * ceil_div(params[i].ny, R);
+            if (t <= target || R >= max_ny) break;
+            R *= 2;
+        }
+    }
+    if (R < 4) return b->fail(DL_ERR_INVALID, "rows per chunk must be >= 4");
+    b->rows = R;
+    std::vector<dl::BatchBlock> blk[dl::kGridKinds];
+    std::vector<dl::BatchTask> task[2];
+    for (int k = 0; k < 2; ++k) {
+        const int halo = k == 0 ? 2 : 1;
+        const int kind = k == 0 ? dl::kGridSweep : dl::kGridFirst;
+        for (int i = 0; i < n; ++i) {
+            const int ns = strips(params[i].nx, halo), nch = (int)ceil_div(params[i].ny, R);
+            const size_t first_task = task[k].size();
+            for (int c = 0; c < nch; ++c)
+                for (int s = 0; s < ns; ++s)
+                    task[k].push_back(dl::BatchTask{s, c * R, std::min((c + 1) * R, params[i].ny), 0});
+            while ((task[k].size() - first_task) % dl::kWaves) task[k].push_back(dl::BatchTask{0, 0, 0, 0});
+            const int nb = (int)((task[k].size() - first_task) / dl::kWaves);
+            const int first = (int)blk[kind].size();
+            for (int l = 0; l < nb; ++l) blk[kind].push_back(dl::BatchBlock{i, l, nb, first});
+            dl::Tiles &t = b->h_pk[i].tiles[k];
+            t.halo = halo;
+            t.own = 64 - 2 * halo;
+            t.nstrips = ns;
+            t.rows = R;
+            t.nchunks = nch;
+        }
+    }
+    {
+        const int tile = dl::combine_tile_sites(b->mixed);
+        size_t total_tiles = 0;
+        std::vector<size_t> tiles(n);
+        for (int i = 0; i < n; ++i) {
+            tiles[i] = ceil_div((size_t)params[i].nx * params[i].ny, tile);
+            total_tiles += tiles[i];
+        }
+        const double per = (double)(4 * b->cus) / (double)total_tiles;  // workgroups per tile
+        for (int i = 0; i < n; ++i) {
+            int nb = (int)std::ceil(per * (double)tiles[i]);
+            nb = std::max(1, std::min(nb, (int)tiles[i]));
+            const int first = (int)blk[dl::kGridCombine].size();
+            for (int l = 0; l < nb; ++l) blk[dl::kGridCombine].push_back(dl::BatchBlock{i, l, nb, first});
+        }
+    }
+    for (int k = 0; k < dl::kGridKinds; ++k) {
+        if (blk[k].size() > b->max_blocks[k]) return b->fail(DL_ERR_WORKSPACE, "batch tables exceed the workspace");
+        b->nblk[k] = (int)blk[k].size();
+        DL_HIP(b, hipMemcpyAsync(b->d_blk[k], blk[k].data(), sizeof(dl::BatchBlock) * blk[k].size(),
+                                 hipMemcpyHostToDevice, b->stream));
+    }
+    for (int k = 0; k < 2; ++k)
+        DL_HIP(b, hipMemcpyAsync(b->d_task[k], task[k].data(), sizeof(dl::BatchTask) * task[k].size(),
+                                 hipMemcpyHostToDevice, b->stream));
+    DL_HIP(b, hipStreamSynchronize(b->stream));
+    return DL_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -220,52 +297,6 @@ dl_status dirac_lanczos_batch_init(const dl_params *params, int32_t n_packets, v
     b->cus = prop.multiProcessorCount;
     b->sc_stride = B.sc_stride;
 
-    // common rows per chunk: at most one resident round of sweep waves
-    const int wr = std::min(dl::batch_waves_per_cu(1, b->mixed, b->py, b->site), 8);
-    const size_t target = (size_t)wr * b->cus;
-    int max_ny = 0;
-    for (int i = 0; i < n; ++i) max_ny = std::max(max_ny, params[i].ny);
-    int R = 4;
-    for (;;) {
-        size_t t = 0;
-        for (int i = 0; i < n; ++i) t += (size_t)strips(params[i].nx, 2) * ceil_div(params[i].ny, R);
-        if (t <= target || R >= max_ny) break;
-        R *= 2;
-    }
-    // tables
-    std::vector<dl::BatchBlock> blk[dl::kGridKinds];
-    std::vector<dl::BatchTask> task[2];
-    for (int k = 0; k < 2; ++k) {
-        const int halo = k == 0 ? 2 : 1;
-        const int kind = k == 0 ? dl::kGridSweep : dl::kGridFirst;
-        for (int i = 0; i < n; ++i) {
-            const int ns = strips(params[i].nx, halo), nch = (int)ceil_div(params[i].ny, R);
-            const size_t first_task = task[k].size();
-            for (int c = 0; c < nch; ++c)
-                for (int s = 0; s < ns; ++s)
-                    task[k].push_back(dl::BatchTask{s, c * R, std::min((c + 1) * R, params[i].ny), 0});
-            while ((task[k].size() - first_task) % dl::kWaves) task[k].push_back(dl::BatchTask{0, 0, 0, 0});
-            const int nb = (int)((task[k].size() - first_task) / dl::kWaves);
-            const int first = (int)blk[kind].size();
-            for (int l = 0; l < nb; ++l) blk[kind].push_back(dl::BatchBlock{i, l, nb, first});
-        }
-    }
-    {
-        const int tile = dl::combine_tile_sites(b->mixed);
-        size_t total_tiles = 0;
-        std::vector<size_t> tiles(n);
-        for (int i = 0; i < n; ++i) {
-            tiles[i] = ceil_div((size_t)params[i].nx * params[i].ny, tile);
-            total_tiles += tiles[i];
-        }
-        const double per = (double)(4 * b->cus) / (double)total_tiles;  // workgroups per tile
-        for (int i = 0; i < n; ++i) {
-            int nb = (int)std::ceil(per * (double)tiles[i]);
-            nb = std::max(1, std::min(nb, (int)tiles[i]));
-            const int first = (int)blk[dl::kGridCombine].size();
-            for (int l = 0; l < nb; ++l) blk[dl::kGridCombine].push_back(dl::BatchBlock{i, l, nb, first});
-        }
-    }
     // packet table (the operator is filled per call, it depends on dt)
     b->h_pk.resize(n);
     const size_t belem = b->mixed ? 8 : 16;
@@ -273,14 +304,6 @@ dl_status dirac_lanczos_batch_init(const dl_params *params, int32_t n_packets, v
         dl::BatchPacket &pk = b->h_pk[i];
         std::memset(&pk, 0, sizeof(pk));
         const dl_params &pi = b->p[i];
-        for (int k = 0; k < 2; ++k) {
-            const int halo = k == 0 ? 2 : 1;
-            pk.tiles[k].halo = halo;
-            pk.tiles[k].own = 64 - 2 * halo;
-            pk.tiles[k].nstrips = strips(pi.nx, halo);
-            pk.tiles[k].rows = R;
-            pk.tiles[k].nchunks = (int)ceil_div(pi.ny, R);
-        }
         const size_t ne = vec_elems(pi);
         pk.psi = nullptr;
         pk.state = reinterpret_cast<double2 *>(b->ws + B.vec_off[i]);
@@ -296,25 +319,18 @@ dl_status dirac_lanczos_batch_init(const dl_params *params, int32_t n_packets, v
     b->d_pk = reinterpret_cast<dl::BatchPacket *>(b->ws + B.pk);
     for (int k = 0; k < dl::kGridKinds; ++k) {
         b->d_blk[k] = reinterpret_cast<dl::BatchBlock *>(b->ws + B.blk[k]);
-        b->nblk[k] = (int)blk[k].size();
+        b->max_blocks[k] = B.max_blocks[k];
     }
     for (int k = 0; k < 2; ++k) b->d_task[k] = reinterpret_cast<dl::BatchTask *>(b->ws + B.task[k]);
     b->partials = reinterpret_cast<double *>(b->ws + B.partials);
     b->fields = reinterpret_cast<double *>(b->ws + B.fields);
     b->stats = reinterpret_cast<dl::StepStat *>(b->ws + B.stats);
     b->scalars = b->ws + B.scalars;
-    hipError_t e = hipSuccess;
-    for (int k = 0; k < dl::kGridKinds && e == hipSuccess; ++k)
-        e = hipMemcpyAsync(b->d_blk[k], blk[k].data(), sizeof(dl::BatchBlock) * blk[k].size(), hipMemcpyHostToDevice,
-                           b->stream);
-    for (int k = 0; k < 2 && e == hipSuccess; ++k)
-        e = hipMemcpyAsync(b->d_task[k], task[k].data(), sizeof(dl::BatchTask) * task[k].size(),
-                           hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-    if (e != hipSuccess) {
-        g_batch_init_error = std::string("table upload failed: ") + hipGetErrorString(e);
+    const dl_status sb = build_tables(b, 0);
+    if (sb != DL_OK) {
+        g_batch_init_error = b->err;
         delete b;
-        return DL_ERR_DEVICE;
+        return sb;
     }
     *out = b;
     return DL_OK;
@@ -421,6 +437,14 @@ dl_status dirac_lanczos_batch_step(dl_batch *b, void *const *psi, double t0, dou
         return b->fail(DL_ERR_NONFINITE, "non-finite Lanczos reduction in packet(s) " + who);
     }
     return DL_OK;
+}
+
+dl_status dirac_lanczos_batch_set_launch(dl_batch *b, int32_t rows_per_chunk, int32_t *rows_out)
+{
+    if (!b) return DL_ERR_INVALID;
+    const dl_status s = build_tables(b, rows_per_chunk);
+    if (s == DL_OK && rows_out) *rows_out = b->rows;
+    return s;
 }
 
 dl_status dirac_lanczos_batch_destroy(dl_batch *b)

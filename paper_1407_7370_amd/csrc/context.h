@@ -82,6 +82,7 @@ struct dl_context {
     // tiles of recurrence sweep p (each sweep kind has its own occupancy)
     const dl::Tiles &tiles_pass(int p) const { return p == 2 ? tiles_p2 : (p == 3 ? tiles_p3 : tiles_recur); }
     int combine_blocks = 1024;
+    int sweep_waves = 8;  // waves per compute unit of the sweeps (launch shape)
     std::vector<double> host_fields;
     std::vector<dl::StepStat> host_stats;
     std::string err;

@@ -348,7 +348,31 @@ using namespace dlh;
 #endif
 
 namespace {
-int cap_waves(int w) { return DL_RECUR_WAVES_PER_CU > 0 ? std::min(w, DL_RECUR_WAVES_PER_CU) : w; }
+
+// Launch shapes of the sweeps: one resident round of waves per sweep (each
+// wave marches its row chunk), with at most `cap` waves per compute unit
+// (0: the built-in cap).
+void set_tiles(dl_context *ctx, int cap)
+{
+    const dl_params &p = ctx->p;
+    const int lim = cap > 0 ? cap : DL_RECUR_WAVES_PER_CU;
+    auto capw = [&](int w) { return lim > 0 ? std::max(1, std::min(w, lim)) : w; };
+    const bool mixed = p.precision == DL_PREC_MIXED;
+    const bool py = p.bc_y != 0, site = dl::sweep_site_terms(ctx->op(1.0));
+    const int wf = capw(dl::sweep_waves_per_cu(0, mixed, py, site));
+    const int wr = capw(dl::sweep_waves_per_cu(1, mixed, py, site));
+    const int wa = dl::sweep_waves_per_cu(4, mixed, py, site);
+    const int w2 = capw(dl::sweep_waves_per_cu(2, mixed, py, site));
+    const int w3 = capw(dl::sweep_waves_per_cu(3, mixed, py, site));
+    ctx->sweep_waves = wr;
+    ctx->tiles_first = dl::make_tiles(p.nx, p.ny, 1, wf * ctx->cus);
+    ctx->tiles_recur = dl::make_tiles(p.nx, p.ny, 2, wr * ctx->cus * DL_RECUR_ROUNDS);
+    ctx->tiles_p2 = dl::make_tiles(p.nx, p.ny, 2, w2 * ctx->cus * DL_RECUR_ROUNDS);
+    ctx->tiles_p3 = dl::make_tiles(p.nx, p.ny, 2, w3 * ctx->cus * DL_RECUR_ROUNDS);
+    ctx->tiles_apply = dl::make_tiles(p.nx, p.ny, 1, wa * ctx->cus);
+    ctx->combine_blocks = dl::combine_grid(vec_elems(p) / 2, mixed, ctx->cus);
+}
+
 }  // namespace
 
 extern "C" {
@@ -407,22 +431,7 @@ dl_status dirac_lanczos_init(const dl_params *params, void *workspace, size_t ws
     ctx->ws_bytes = ws_bytes;
     ctx->L = L;
     ctx->cus = prop.multiProcessorCount;
-    {
-        // one resident round of waves per sweep (each wave marches its row chunk)
-        const bool mixed = params->precision == DL_PREC_MIXED;
-        const bool py = params->bc_y != 0, site = dl::sweep_site_terms(ctx->op(1.0));
-        const int wf = dl::sweep_waves_per_cu(0, mixed, py, site);
-        const int wr = cap_waves(dl::sweep_waves_per_cu(1, mixed, py, site));
-        const int wa = dl::sweep_waves_per_cu(4, mixed, py, site);
-        const int w2 = cap_waves(dl::sweep_waves_per_cu(2, mixed, py, site));
-        const int w3 = cap_waves(dl::sweep_waves_per_cu(3, mixed, py, site));
-        ctx->tiles_first = dl::make_tiles(params->nx, params->ny, 1, cap_waves(wf) * ctx->cus);
-        ctx->tiles_recur = dl::make_tiles(params->nx, params->ny, 2, wr * ctx->cus * DL_RECUR_ROUNDS);
-        ctx->tiles_p2 = dl::make_tiles(params->nx, params->ny, 2, w2 * ctx->cus * DL_RECUR_ROUNDS);
-        ctx->tiles_p3 = dl::make_tiles(params->nx, params->ny, 2, w3 * ctx->cus * DL_RECUR_ROUNDS);
-        ctx->tiles_apply = dl::make_tiles(params->nx, params->ny, 1, wa * ctx->cus);
-        ctx->combine_blocks = dl::combine_grid(vec_elems(*params) / 2, mixed, ctx->cus);
-    }
+    set_tiles(ctx, 0);
     dl::launch_reset(ctx->sc(), ctx->stream);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
@@ -642,6 +651,16 @@ dl_status dirac_lanczos_eigen(dl_context *ctx, const void *psi0, int32_t k_max, 
         a = b;
     }
     *n_found = nf;
+    return DL_OK;
+}
+
+dl_status dirac_lanczos_set_launch(dl_context *ctx, int32_t sweep_waves_per_cu, int32_t *waves_out)
+{
+    if (!ctx) return DL_ERR_INVALID;
+    if (sweep_waves_per_cu < 0 || sweep_waves_per_cu > 64)
+        return ctx->fail(DL_ERR_INVALID, "sweep_waves_per_cu must be in 0..64");
+    set_tiles(ctx, sweep_waves_per_cu);
+    if (waves_out) *waves_out = ctx->sweep_waves;
     return DL_OK;
 }
 

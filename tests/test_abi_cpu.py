@@ -109,3 +109,22 @@ def test_workspace_errors():
         with pytest.raises(binding.DlError) as ei:
             binding.dirac_lanczos_init(p, ptr, size, 0)
         assert ei.value.status == binding.DL_ERR_WORKSPACE
+
+
+def test_autotune_cache_roundtrip(tmp_path):
+    """Cache keys separate workload classes; entries survive a store/load."""
+    from paper_1407_7370_amd import autotune
+    a = dict(nx=64, ny=48, bc_y=0, bz=0.0, pot_kind=0)
+    b = dict(a, bz=0.5)
+    ka = autotune.key_single(a, 12, "mixed", "gfx950")
+    kb = autotune.key_single(b, 12, "mixed", "gfx950")
+    assert ka != kb and "64x48" in ka and "site1" in kb
+    kbat = autotune.key_batch([a, a, dict(a, nx=32)], 12, "mixed", "gfx950")
+    assert "64x48:2" in kbat and "32x48:1" in kbat
+    cache = str(tmp_path / "tune.json")
+    assert autotune.lookup(ka, cache) is None
+    autotune.store(ka, {"best": 6, "times": {}}, cache)
+    autotune.store(kbat, {"best": 64, "times": {}}, cache)
+    assert autotune.lookup(ka, cache) == 6
+    assert autotune.lookup(kbat, cache) == 64
+    assert autotune.lookup(kb, cache) is None

@@ -140,3 +140,42 @@ def test_batch_256_packets_sampled(torch_cuda):
     for i in (0, 1, 77, 128, 255):
         outs, _ = run_single(torch, probs[i], psi0[i], m, "mixed", dt, n)
         assert rel(outb[i], outs) <= 1e-8, i
+
+
+def test_launch_shapes_agree_to_rounding(torch_cuda, tmp_path):
+    """Every launch shape of the single-grid and batched sweeps gives the same
+    result to rounding; the autotuner stores its choice in the cache."""
+    torch = torch_cuda
+    from paper_1407_7370_amd import autotune
+    from paper_1407_7370_amd.binding import Propagator, BatchPropagator
+    say("launch shapes and autotuner")
+    p = prob(300, 130, 0, bz=0.3)
+    psi0 = states([p], 40)[0]
+    outs = []
+    for w in (4, 8, 16):
+        prop = Propagator(p, 10, "fp64")
+        prop.set_launch(w)
+        psi = torch.from_numpy(psi0).to("cuda")
+        prop.step(psi, 0.0, 1e-3, 5, want_stats=False)
+        outs.append(psi.cpu().numpy())
+        prop.close()
+    for o in outs[1:]:
+        assert rel(o, outs[0]) <= 1e-12
+    probs = small_batch(0)
+    ps = states(probs, 50)
+    res = []
+    for r in (4, 16, 0):
+        bp = BatchPropagator(probs, 10, "fp64")
+        bp.set_launch(r)
+        psis = [torch.from_numpy(x).to("cuda") for x in ps]
+        bp.step(psis, 0.0, 1e-3, 5, want_stats=False)
+        res.append([x.cpu().numpy() for x in psis])
+        bp.close()
+    for r in res[1:]:
+        for a, b in zip(r, res[0]):
+            assert rel(a, b) <= 1e-12
+    cache = str(tmp_path / "tune.json")
+    e = autotune.tune_batch(probs, [torch.from_numpy(x).to("cuda") for x in ps], 10, "fp64", 1e-3, steps=2,
+                            candidates=(8, 0), cache=cache)
+    assert e["best"] in (8, 0)
+    assert autotune.lookup(autotune.key_batch(probs, 10, "fp64", autotune.device_arch()), cache) == e["best"]
