@@ -30,7 +30,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 METRIC = "site-matvecs/s and % HBM peak, mixed vs FP64 propagator at ≤1e-6 err"
-KERNEL_SRC = os.path.join(ROOT, "paper_1407_7370_amd", "csrc", "kernels.hip")
+# sources of the sweep kernels: the HBM traffic counters are valid for these only
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1407_7370_amd", "csrc", f)
+               for f in ("kernels.hip", "sweeps.h", "device_reduce.h", "dl_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_recur_laser4096.json")
 
 
@@ -39,13 +41,16 @@ def log(msg):
 
 
 def kernel_digest():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def load_traffic(precision):
     """HBM bytes per launch of the dominant kernel from committed rocprofv3
-    counter runs, valid only while kernels.hip is unchanged."""
+    counter runs, valid only while the kernel sources are unchanged."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
@@ -63,7 +68,7 @@ def run_precision(torch, Propagator, cfg, psi0_dev, precision, steps, warmup, co
     by the library on its stream (kernel durations for the roofline)."""
     prop_args = (cfg["problem"], cfg["m"], precision)
     dt = cfg["dt"]
-    prop = Propagator(*prop_args)
+    prop = Propagator(*prop_args, tuning_cache=True)
     psi = psi0_dev.clone()
     if warmup > 0:
         prop.step(psi, 0.0, dt, warmup, want_stats=False)

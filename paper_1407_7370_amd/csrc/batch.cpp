@@ -24,7 +24,8 @@ using namespace dlh;
 
 struct dl_batch {
     int n = 0, m = 0;
-    bool mixed = false, py = false, site = false;
+    bool mixed = false, py = false;
+    int terms = 0;  // site-dependent terms present in any packet (dl::kTermPot | dl::kTermB)
     std::vector<dl_params> p;
     std::vector<std::vector<double>> coef;
     hipStream_t stream = nullptr;
@@ -74,9 +75,12 @@ struct BatchPlan {
     size_t max_blocks[dl::kGridKinds] = {0, 0, 0};
 };
 
-// The potential, a potential table or a magnetic field make the diagonal or
-// the coupling vary over the grid.
-bool site_terms(const dl_params &p) { return p.pot_kind != 0 || p.v_table != nullptr || p.bz != 0.0; }
+// The potential or a potential table make the diagonal vary over the grid, a
+// magnetic field the coupling.
+int site_terms(const dl_params &p)
+{
+    return ((p.pot_kind != 0 || p.v_table != nullptr) ? dl::kTermPot : 0) | (p.bz != 0.0 ? dl::kTermB : 0);
+}
 
 int strips(int nx, int halo) { return (nx + (64 - 2 * halo) - 1) / (64 - 2 * halo); }
 
@@ -159,7 +163,7 @@ dl_status build_tables(dl_batch *b, int rows_per_chunk)
     const std::vector<dl_params> &params = b->p;
     int R = rows_per_chunk;
     if (R <= 0) {
-        const int wr = std::min(dl::batch_waves_per_cu(1, b->mixed, b->py, b->site), 8);
+        const int wr = std::min(dl::batch_waves_per_cu(1, b->mixed, b->py, b->terms), 8);
         const size_t target = (size_t)wr * b->cus;
         int max_ny = 0;
         for (int i = 0; i < n; ++i) max_ny = std::max(max_ny, params[i].ny);
@@ -289,7 +293,7 @@ dl_status dirac_lanczos_batch_init(const dl_params *params, int32_t n_packets, v
         if (params[i].pulse_kind == DL_PULSE_FOURIER_SIN2)
             b->coef[i].assign(params[i].coef, params[i].coef + params[i].n_coef);
         b->p[i].coef = nullptr;
-        if (site_terms(b->p[i])) b->site = true;
+        b->terms |= site_terms(b->p[i]);
     }
     b->stream = static_cast<hipStream_t>(hip_stream);
     b->ws = static_cast<char *>(workspace);
@@ -386,12 +390,12 @@ dl_status dirac_lanczos_batch_step(dl_batch *b, void *const *psi, double t0, dou
             a.pass = 1;
             a.blocks = b->d_blk[dl::kGridFirst];
             a.tasks = b->d_task[1];
-            dl::launch_first_batch(a, b->nblk[dl::kGridFirst], b->py, b->site, st);
+            dl::launch_first_batch(a, b->nblk[dl::kGridFirst], b->py, b->terms, st);
             a.blocks = b->d_blk[dl::kGridSweep];
             a.tasks = b->d_task[0];
             for (int p = 2; p <= m; ++p) {
                 a.pass = p;
-                dl::launch_recur_batch(a, b->nblk[dl::kGridSweep], b->mixed, b->py, b->site, st);
+                dl::launch_recur_batch(a, b->nblk[dl::kGridSweep], b->mixed, b->py, b->terms, st);
             }
             dl::launch_tridiag_batch(a, n, st);
             a.blocks = b->d_blk[dl::kGridCombine];

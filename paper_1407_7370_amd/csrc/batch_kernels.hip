@@ -26,7 +26,7 @@ __device__ __forceinline__ WaveTask batch_wave_task(const BatchArgs &b)
     return w;
 }
 
-template <int PF, bool PY, bool SITE>
+template <int PF, bool PY, int TERMS>
 __global__ __launch_bounds__(kBlock) void k_first_batch(BatchArgs b)
 {
     const BatchBlock bb = b.blocks[blockIdx.x];
@@ -36,14 +36,14 @@ __global__ __launch_bounds__(kBlock) void k_first_batch(BatchArgs b)
     const WaveTask wt = batch_wave_task(b);
     const double2 *in = b.parity ? pk.state : pk.psi;
     double acc[3] = {0.0, 0.0, 0.0};
-    first_body<PF, PY, SITE>(pk.op, pk.tiles[1], wt, in, pk.fields + 2 * b.step, acc);
+    first_body<PF, PY, TERMS>(pk.op, pk.tiles[1], wt, in, pk.fields + 2 * b.step, acc);
     double tot[3];
     if (!seg_reduce(acc, b.partials + (size_t)bb.first * kPartialStride, &sc->ticket, bb.nblk, bb.local, tot))
         return;
     if (threadIdx.x == 0) first_tail(tot, pk.alpha, pk.gamma, sc, b.m, 1);
 }
 
-template <class V1, class V2, class TO, bool HAS2, int PF, bool PY, bool SITE>
+template <class V1, class V2, class TO, bool HAS2, int PF, bool PY, int TERMS>
 __global__ __launch_bounds__(kBlock) void k_recur_batch(BatchArgs b)
 {
     const BatchBlock bb = b.blocks[blockIdx.x];
@@ -67,7 +67,7 @@ __global__ __launch_bounds__(kBlock) void k_recur_batch(BatchArgs b)
     if (a.sc->kstop < p) return;
     const WaveTask wt = batch_wave_task(b);
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    recur_body<V1, V2, TO, HAS2, PF, PY, SITE>(a, wt, acc);
+    recur_body<V1, V2, TO, HAS2, PF, PY, TERMS>(a, wt, acc);
     double tot[5];
     if (!seg_reduce(acc, a.partials, &a.sc->ticket, bb.nblk, bb.local, tot)) return;
     if (threadIdx.x == 0) recur_tail(a, tot);
@@ -120,42 +120,37 @@ __global__ void k_reset_batch(const BatchPacket *pk, int n)
 }
 
 struct BatchRecur {
-    template <class V1, class V2, class TO, bool HAS2, int PF, bool PY, bool SITE>
-    static constexpr auto get() { return k_recur_batch<V1, V2, TO, HAS2, PF, PY, SITE>; }
+    template <class V1, class V2, class TO, bool HAS2, int PF, bool PY, int TERMS>
+    static constexpr auto get() { return k_recur_batch<V1, V2, TO, HAS2, PF, PY, TERMS>; }
 };
 
-template <bool PY, bool SITE>
-constexpr auto first_batch_kernel() { return k_first_batch<kPfFirst, PY, SITE>; }
-
-template <class F>
-auto with_first_batch(bool py, bool site, F &&f)
-{
-    if (py) return site ? f(first_batch_kernel<true, true>()) : f(first_batch_kernel<true, false>());
-    return site ? f(first_batch_kernel<false, true>()) : f(first_batch_kernel<false, false>());
-}
+template <bool PY, int TERMS>
+struct PickFirstBatch {
+    static constexpr auto get() { return k_first_batch<kPfFirst, PY, TERMS>; }
+};
 
 }  // namespace
 
-void launch_first_batch(const BatchArgs &b, int nblocks, bool py, bool site, hipStream_t st)
+void launch_first_batch(const BatchArgs &b, int nblocks, bool py, int terms, hipStream_t st)
 {
-    with_first_batch(py, site, [&](auto kernel) {
+    dispatch_terms<PickFirstBatch>(py, terms, [&](auto kernel) {
         hipLaunchKernelGGL(kernel, dim3(nblocks), dim3(kBlock), 0, st, b);
         return 0;
     });
 }
 
-void launch_recur_batch(const BatchArgs &b, int nblocks, bool mixed, bool py, bool site, hipStream_t st)
+void launch_recur_batch(const BatchArgs &b, int nblocks, bool mixed, bool py, int terms, hipStream_t st)
 {
     auto go = [&](auto kernel) {
         hipLaunchKernelGGL(kernel, dim3(nblocks), dim3(kBlock), 0, st, b);
         return 0;
     };
     if (b.pass == 2)
-        with_kind<RecurP2, BatchRecur>(mixed, py, site, go);
+        with_kind<RecurP2, BatchRecur>(mixed, py, terms, go);
     else if (b.pass == 3)
-        with_kind<RecurP3, BatchRecur>(mixed, py, site, go);
+        with_kind<RecurP3, BatchRecur>(mixed, py, terms, go);
     else
-        with_kind<RecurPn, BatchRecur>(mixed, py, site, go);
+        with_kind<RecurPn, BatchRecur>(mixed, py, terms, go);
 }
 
 void launch_tridiag_batch(const BatchArgs &b, int npackets, hipStream_t st)
@@ -173,11 +168,11 @@ void launch_combine_batch(const BatchArgs &b, int nblocks, bool mixed, hipStream
                            st, b);
 }
 
-int batch_waves_per_cu(int which, bool mixed, bool py, bool site)
+int batch_waves_per_cu(int which, bool mixed, bool py, int terms)
 {
     auto occ = [](auto kernel) { return waves_per_cu(kernel); };
-    if (which == 0) return with_first_batch(py, site, occ);
-    return with_kind<RecurPn, BatchRecur>(mixed, py, site, occ);
+    if (which == 0) return dispatch_terms<PickFirstBatch>(py, terms, occ);
+    return with_kind<RecurPn, BatchRecur>(mixed, py, terms, occ);
 }
 
 void launch_reset_batch(const BatchPacket *pk, int n, hipStream_t st)

@@ -58,6 +58,11 @@ struct Op {
     double vscale;
 };
 
+// Site-dependent terms of the operator (compile-time specialisations of the
+// sweeps): the potential (or potential table) and the magnetic field.
+constexpr int kTermPot = 1;
+constexpr int kTermB = 2;
+
 // Wave-to-tile mapping of one sweep: every wave owns `own` consecutive columns
 // of one strip and `rows` consecutive rows of it (its chunk).
 struct Tiles {
@@ -189,13 +194,13 @@ struct BatchArgs {
     int pass, m, step, parity; // step: index in the chunk tables; parity 1: the input is `state`
 };
 
-void launch_first_batch(const BatchArgs &b, int nblocks, bool py, bool site, hipStream_t st);
-void launch_recur_batch(const BatchArgs &b, int nblocks, bool mixed, bool py, bool site, hipStream_t st);
+void launch_first_batch(const BatchArgs &b, int nblocks, bool py, int terms, hipStream_t st);
+void launch_recur_batch(const BatchArgs &b, int nblocks, bool mixed, bool py, int terms, hipStream_t st);
 void launch_tridiag_batch(const BatchArgs &b, int npackets, hipStream_t st);
 void launch_reset_batch(const BatchPacket *pk, int n, hipStream_t st);
 void launch_combine_batch(const BatchArgs &b, int nblocks, bool mixed, hipStream_t st);
 // Resident waves per compute unit of the batched kernels (0 first, 1 sweeps).
-int batch_waves_per_cu(int which, bool mixed, bool py, bool site);
+int batch_waves_per_cu(int which, bool mixed, bool py, int terms);
 // Sites per recombination tile.
 int combine_tile_sites(bool mixed);
 
@@ -204,8 +209,8 @@ Tiles make_tiles(int nx, int ny, int halo, int target_waves);
 int combine_grid(size_t sites, bool mixed, int cus);
 // Resident waves per compute unit of a kernel family: 0 first iteration,
 // 1 recurrence sweep p >= 4, 2 sweep p = 2, 3 sweep p = 3, 4 apply; py:
-// periodic in y, site: site-dependent diagonal or coupling (sweep_site_terms).
-int sweep_waves_per_cu(int which, bool mixed, bool py, bool site);
-bool sweep_site_terms(const Op &op);
+// periodic in y, terms: site-dependent terms (sweep_terms).
+int sweep_waves_per_cu(int which, bool mixed, bool py, int terms);
+int sweep_terms(const Op &op);
 
 }  // namespace dl

@@ -358,7 +358,8 @@ void set_tiles(dl_context *ctx, int cap)
     const int lim = cap > 0 ? cap : DL_RECUR_WAVES_PER_CU;
     auto capw = [&](int w) { return lim > 0 ? std::max(1, std::min(w, lim)) : w; };
     const bool mixed = p.precision == DL_PREC_MIXED;
-    const bool py = p.bc_y != 0, site = dl::sweep_site_terms(ctx->op(1.0));
+    const bool py = p.bc_y != 0;
+    const int site = dl::sweep_terms(ctx->op(1.0));
     const int wf = capw(dl::sweep_waves_per_cu(0, mixed, py, site));
     const int wr = capw(dl::sweep_waves_per_cu(1, mixed, py, site));
     const int wa = dl::sweep_waves_per_cu(4, mixed, py, site);
@@ -589,7 +590,7 @@ dl_status dirac_lanczos_eigen(dl_context *ctx, const void *psi0, int32_t k_max, 
     for (int kind = 0; kind < 3; ++kind)
         tp[kind] = dl::make_tiles(p.nx, p.ny, 2,
                                   dl::sweep_waves_per_cu(kind == 2 ? 1 : kind + 2, false, p.bc_y != 0,
-                                                         dl::sweep_site_terms(op)) * ctx->cus);
+                                                         dl::sweep_terms(op)) * ctx->cus);
     const double zero[2] = {0.0, 0.0};
     DL_HIP(ctx, hipMemcpyAsync(fields, zero, sizeof(zero), hipMemcpyHostToDevice, st));
     DL_HIP(ctx, hipMemcpyAsync(v[1], psi0, n * 16, hipMemcpyDeviceToDevice, st));

@@ -8,20 +8,26 @@
 
 namespace dl {
 
-int sweep_waves_per_cu(int which, bool mixed, bool py, bool site)
+namespace {
+template <bool PY, int TERMS>
+struct PickFirst {
+    static constexpr auto get() { return k_first<kPfFirst, PY, TERMS>; }
+};
+}  // namespace
+
+int sweep_waves_per_cu(int which, bool mixed, bool py, int terms)
 {
     auto occ = [](auto kernel) { return waves_per_cu(kernel); };
     switch (which) {
-    case 0: return py ? (site ? waves_per_cu(k_first<kPfFirst, true, true>) : waves_per_cu(k_first<kPfFirst, true, false>))
-                      : (site ? waves_per_cu(k_first<kPfFirst, false, true>) : waves_per_cu(k_first<kPfFirst, false, false>));
-    case 1: return with_kind<RecurPn, SingleRecur>(mixed, py, site, occ);
-    case 2: return with_kind<RecurP2, SingleRecur>(mixed, py, site, occ);
-    case 3: return with_kind<RecurP3, SingleRecur>(mixed, py, site, occ);
+    case 0: return dispatch_terms<PickFirst>(py, terms, occ);
+    case 1: return with_kind<RecurPn, SingleRecur>(mixed, py, terms, occ);
+    case 2: return with_kind<RecurP2, SingleRecur>(mixed, py, terms, occ);
+    case 3: return with_kind<RecurP3, SingleRecur>(mixed, py, terms, occ);
     default: return waves_per_cu(k_apply);
     }
 }
 
-bool sweep_site_terms(const Op &op) { return op_site(op); }
+int sweep_terms(const Op &op) { return op_terms(op); }
 
 int combine_grid(size_t sites, bool mixed, int cus)
 {
@@ -57,19 +63,11 @@ void launch_first(const Op &op, const Tiles &t, const double2 *psi, const double
                   double *alpha, double *gamma, Scalars *sc, double *partials, int m, int shift,
                   hipStream_t st)
 {
-    const dim3 g(t.nblocks), b(kBlock);
-    const bool py = op.bcy != 0, site = op_site(op);
-    if (py) {
-        if (site)
-            hipLaunchKernelGGL((k_first<kPfFirst, true, true>), g, b, 0, st, op, t, psi, field, alpha, gamma, sc, partials, m, shift);
-        else
-            hipLaunchKernelGGL((k_first<kPfFirst, true, false>), g, b, 0, st, op, t, psi, field, alpha, gamma, sc, partials, m, shift);
-    } else {
-        if (site)
-            hipLaunchKernelGGL((k_first<kPfFirst, false, true>), g, b, 0, st, op, t, psi, field, alpha, gamma, sc, partials, m, shift);
-        else
-            hipLaunchKernelGGL((k_first<kPfFirst, false, false>), g, b, 0, st, op, t, psi, field, alpha, gamma, sc, partials, m, shift);
-    }
+    dispatch_terms<PickFirst>(op.bcy != 0, op_terms(op), [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, dim3(t.nblocks), dim3(kBlock), 0, st, op, t, psi, field, alpha, gamma, sc,
+                           partials, m, shift);
+        return 0;
+    });
 }
 
 void launch_recur(const PassArgs &a, bool mixed, hipStream_t st)
@@ -79,13 +77,14 @@ void launch_recur(const PassArgs &a, bool mixed, hipStream_t st)
         hipLaunchKernelGGL(kernel, g, b, 0, st, a);
         return 0;
     };
-    const bool py = a.op.bcy != 0, site = op_site(a.op);
+    const bool py = a.op.bcy != 0;
+    const int terms = op_terms(a.op);
     if (a.pass == 2)
-        with_kind<RecurP2, SingleRecur>(mixed, py, site, go);
+        with_kind<RecurP2, SingleRecur>(mixed, py, terms, go);
     else if (a.pass == 3)
-        with_kind<RecurP3, SingleRecur>(mixed, py, site, go);
+        with_kind<RecurP3, SingleRecur>(mixed, py, terms, go);
     else
-        with_kind<RecurPn, SingleRecur>(mixed, py, site, go);
+        with_kind<RecurPn, SingleRecur>(mixed, py, terms, go);
 }
 
 void launch_tridiag(const double *alpha, const double *gamma, Scalars *sc, StepStat *stat,

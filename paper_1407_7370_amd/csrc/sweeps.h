@@ -469,7 +469,7 @@ using PlanarF = PlanarT<DL_LOAD_POL_FIRST>;
 // ---------------------------------------------------------------------------
 // March of one wave of iteration 1 over its tile (acc: ||psi||^2, Re<psi, A psi>,
 // ||A psi||^2 of its owned sites).
-template <int PF, bool PY, bool SITE>
+template <int PF, bool PY, int TERMS>
 __device__ __forceinline__ void first_body(const Op &op, const Tiles &t, const WaveTask &wt,
                                            const double2 *__restrict__ psi, const double *__restrict__ field,
                                            double (&acc)[3])
@@ -481,7 +481,7 @@ __device__ __forceinline__ void first_body(const Op &op, const Tiles &t, const W
     const double gxh = field[0], gyh = field[1];
     if (wt.active) {
         const LaneGeo lg = lane_geo(op, t, wt.strip, lane);
-        const double gy = SITE ? gyh - op.bq * lg.x : gyh;
+        const double gy = (TERMS & kTermB) ? gyh - op.bq * lg.x : gyh;
         const PlanarF vin = make_view<PlanarF>(psi, op);
         const uint32_t off = lg.inx ? PlanarF::lane_offset(lg.colw) : kOob;
         const int y0 = wt.y0, y1 = wt.y1, base = y0 - 1;
@@ -505,10 +505,10 @@ __device__ __forceinline__ void first_body(const Op &op, const Tiles &t, const W
             if (R - 1 < y0) return;
             const Sp &c = P[(k + 3) & 3];  // row R-1 (inside the domain)
             double v = 0.0, gx = gxh;
-            if constexpr (SITE) {
+            if constexpr (TERMS != 0) {
                 const double y = op.ymin + (R - 1) * op.hy;
-                v = site_pot_row(op, lg, R - 1, y);
-                gx = gxh + op.bq * y;
+                if constexpr (TERMS & kTermPot) v = site_pot_row(op, lg, R - 1, y);
+                if constexpr (TERMS & kTermB) gx = gxh + op.bq * y;
             }
             const Sp y = hop(op, c, sp_left(c), sp_right(c), P[(k + 2) & 3], P[k], v, gx, gy);
             if (lg.own) {
@@ -555,7 +555,7 @@ __device__ __forceinline__ void first_tail(const double (&tot)[3], double *alpha
     sc->beta_k = sqrt(fmax(yy - a * (a / n), 0.0)) / g;
 }
 
-template <int PF, bool PY, bool SITE>
+template <int PF, bool PY, int TERMS>
 __global__ __launch_bounds__(kBlock) void k_first(Op op, Tiles t, const double2 *__restrict__ psi,
                                                   const double *__restrict__ field, double *alpha,
                                                   double *gamma, Scalars *sc, double *partials, int m,
@@ -564,7 +564,7 @@ __global__ __launch_bounds__(kBlock) void k_first(Op op, Tiles t, const double2 
     if (sc->status != 0) return;
     const WaveTask wt = wave_task(op, t);
     double acc[3] = {0.0, 0.0, 0.0};
-    first_body<PF, PY, SITE>(op, t, wt, psi, field, acc);
+    first_body<PF, PY, TERMS>(op, t, wt, psi, field, acc);
     double tot[3];
     if (!grid_reduce(acc, partials, &sc->ticket, tot)) return;
     if (threadIdx.x == 0) first_tail(tot, alpha, gamma, sc, m, shift);
@@ -573,9 +573,9 @@ __global__ __launch_bounds__(kBlock) void k_first(Op op, Tiles t, const double2 
 // ---------------------------------------------------------------------------
 // Lanczos iteration p >= 2 (see the file comment).  V1, V2: views of u_{p-1},
 // u_{p-2}; TO: storage type of u_p (paired layout); PF: FIFO depth in rows;
-// PY: periodic in y; SITE: the diagonal or the coupling varies over the grid
-// (potential, potential table or magnetic field), otherwise both are uniform
-// and computed once.
+// PY: periodic in y; TERMS: site-dependent terms present (kTermPot: potential
+// or potential table, the diagonal varies; kTermB: magnetic field, the
+// coupling varies); absent terms are uniform and computed once.
 // Rows marched: R = y0-2 .. y1+1 (u_{p-1} row R enters, u_p row R-1 is formed,
 // A u_p row R-2 is applied); ring slot of row r = (r - (y0-2)) mod 4.
 // ---------------------------------------------------------------------------
@@ -583,7 +583,7 @@ __global__ __launch_bounds__(kBlock) void k_first(Op op, Tiles t, const double2 
 // March of one wave of iteration p >= 2 over its tile (acc: ||u_p||^2,
 // Re<u_p, A u_p>, Re<u_p, u_(p-1)> and, in the last iteration, ||A u_p||^2 and
 // Re<A u_p, u_(p-1)> of its owned sites).
-template <class V1, class V2, class TO, bool HAS2, int PF, bool PY, bool SITE>
+template <class V1, class V2, class TO, bool HAS2, int PF, bool PY, int TERMS>
 __device__ __forceinline__ void recur_body(const PassArgs &a, const WaveTask &wt, double (&acc)[5])
 {
     // rows are marched U at a time so that every ring and FIFO slot index is a
@@ -606,7 +606,7 @@ __device__ __forceinline__ void recur_body(const PassArgs &a, const WaveTask &wt
     const double gxh = a.field[0], gyh = a.field[1];
     if (wt.active) {
         const LaneGeo lg = lane_geo(op, a.t, wt.strip, lane);
-        const double gy = SITE ? gyh - op.bq * lg.x : gyh;
+        const double gy = (TERMS & kTermB) ? gyh - op.bq * lg.x : gyh;
         // u_p = cw (A' u_{p-1}) - cc u_{p-1} - cu u_{p-2}; lanes outside the domain
         // get zero coefficients, so their u_p is zero without a select
         const double m = lg.inx ? 1.0 : 0.0;
@@ -639,7 +639,7 @@ __device__ __forceinline__ void recur_body(const PassArgs &a, const WaveTask &wt
         }
         Sp P[4] = {sp_zero(), sp_zero(), sp_zero(), sp_zero()};  // u_{p-1} rows
         Sp Q[4] = {sp_zero(), sp_zero(), sp_zero(), sp_zero()};  // u_p rows
-        double Vr[4] = {0.0, 0.0, 0.0, 0.0};                      // potential of the rows (SITE)
+        double Vr[4] = {0.0, 0.0, 0.0, 0.0};                      // potential of the rows (kTermPot)
         int R0 = base;
         auto step = [&](auto kc) {
             constexpr int k = decltype(kc)::value & 3;   // ring slot of row R
@@ -662,12 +662,14 @@ __device__ __forceinline__ void recur_body(const PassArgs &a, const WaveTask &wt
                 if (PY || (unsigned)rr < (unsigned)ny) {
                     const Sp &c = P[(k + 3) & 3];
                     double v = 0.0, gx = gxh;
-                    if constexpr (SITE) {
+                    if constexpr (TERMS != 0) {
                         const int jw = rr < 0 ? rr + ny : (rr >= ny ? rr - ny : rr);
                         const double y = op.ymin + jw * op.hy;
-                        v = site_pot_row(op, lg, jw, y);
-                        gx = gxh + op.bq * y;
-                        Vr[(k + 3) & 3] = v;
+                        if constexpr (TERMS & kTermPot) {
+                            v = site_pot_row(op, lg, jw, y);
+                            Vr[(k + 3) & 3] = v;
+                        }
+                        if constexpr (TERMS & kTermB) gx = gxh + op.bq * y;
                     }
                     const Sp w = hop(op, c, sp_left(c), sp_right(c), P[(k + 2) & 3], P[k], v, gx, gy, sig);
                     u.r0 = cw * w.r0 - cc * c.r0 - cu * o2.r0;
@@ -684,10 +686,8 @@ __device__ __forceinline__ void recur_body(const PassArgs &a, const WaveTask &wt
             if (R >= y0 + 2) {
                 const Sp &c = Q[(k + 2) & 3];
                 double v = 0.0, gx = gxh;
-                if constexpr (SITE) {
-                    v = Vr[(k + 2) & 3];
-                    gx = gxh + op.bq * (op.ymin + (R - 2) * op.hy);
-                }
+                if constexpr (TERMS & kTermPot) v = Vr[(k + 2) & 3];
+                if constexpr (TERMS & kTermB) gx = gxh + op.bq * (op.ymin + (R - 2) * op.hy);
                 const Sp y = hop(op, c, sp_left(c), sp_right(c), Q[(k + 1) & 3], Q[(k + 3) & 3], v, gx, gy, sig);
                 if (lg.own) {
                     const Sp &prev = P[(k + 2) & 3];  // u_{p-1} row R-2
@@ -742,13 +742,13 @@ __device__ __forceinline__ void recur_tail(const PassArgs &a, const double (&tot
     }
 }
 
-template <class V1, class V2, class TO, bool HAS2, int PF, bool PY, bool SITE>
+template <class V1, class V2, class TO, bool HAS2, int PF, bool PY, int TERMS>
 __global__ __launch_bounds__(kBlock) void k_recur(PassArgs a)
 {
     if (a.sc->kstop < a.pass) return;
     const WaveTask wt = wave_task(a.op, a.t);
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    recur_body<V1, V2, TO, HAS2, PF, PY, SITE>(a, wt, acc);
+    recur_body<V1, V2, TO, HAS2, PF, PY, TERMS>(a, wt, acc);
     double tot[5];
     if (!grid_reduce(acc, a.partials, &a.sc->ticket, tot)) return;
     if (threadIdx.x == 0) recur_tail(a, tot);
@@ -1159,21 +1159,35 @@ int waves_per_cu(K kernel)
 // Kernel families of the recurrence sweep: one launch per grid (single) or
 // per batch of packets (batch).
 struct SingleRecur {
-    template <class V1, class V2, class TO, bool HAS2, int PF, bool PY, bool SITE>
-    static constexpr auto get() { return k_recur<V1, V2, TO, HAS2, PF, PY, SITE>; }
+    template <class V1, class V2, class TO, bool HAS2, int PF, bool PY, int TERMS>
+    static constexpr auto get() { return k_recur<V1, V2, TO, HAS2, PF, PY, TERMS>; }
 };
 
-// The four specialisations (periodic y, site-dependent terms) of one sweep kind.
+// Calls f with the specialisation (periodic y, site terms) of a kernel.
+template <template <bool, int> class Pick, class F>
+auto dispatch_terms(bool py, int terms, F &&f)
+{
+    switch ((py ? 4 : 0) | (terms & 3)) {
+    case 0: return f(Pick<false, 0>::get());
+    case 1: return f(Pick<false, 1>::get());
+    case 2: return f(Pick<false, 2>::get());
+    case 3: return f(Pick<false, 3>::get());
+    case 4: return f(Pick<true, 0>::get());
+    case 5: return f(Pick<true, 1>::get());
+    case 6: return f(Pick<true, 2>::get());
+    default: return f(Pick<true, 3>::get());
+    }
+}
+
+// The eight specialisations (periodic y, site terms) of one sweep kind.
 template <class Fam, class V1, class V2, class TO, bool HAS2, int PF>
 struct RecurKind {
-    template <bool PY, bool SITE>
-    static constexpr auto kernel() { return Fam::template get<V1, V2, TO, HAS2, PF, PY, SITE>(); }
+    template <bool PY, int TERMS>
+    struct Pick {
+        static constexpr auto get() { return Fam::template get<V1, V2, TO, HAS2, PF, PY, TERMS>(); }
+    };
     template <class F>
-    static auto dispatch(bool py, bool site, F &&f)
-    {
-        if (py) return site ? f(kernel<true, true>()) : f(kernel<true, false>());
-        return site ? f(kernel<false, true>()) : f(kernel<false, false>());
-    }
+    static auto dispatch(bool py, int terms, F &&f) { return dispatch_terms<Pick>(py, terms, f); }
 };
 
 template <class Fam, bool M>
@@ -1186,13 +1200,16 @@ template <class Fam, bool M>
 using RecurPn = RecurKind<Fam, std::conditional_t<M, PairedM, PairedD>, std::conditional_t<M, PairedM, PairedD>,
                           std::conditional_t<M, float2, double2>, true, M ? kPfMixed : kPfFp64>;
 
-bool op_site(const Op &op) { return op.pot_kind != 0 || op.has_table != 0 || op.bq != 0.0; }
+int op_terms(const Op &op)
+{
+    return ((op.pot_kind != 0 || op.has_table != 0) ? kTermPot : 0) | (op.bq != 0.0 ? kTermB : 0);
+}
 
 template <template <class, bool> class Kind, class Fam, class F>
-auto with_kind(bool mixed, bool py, bool site, F &&f)
+auto with_kind(bool mixed, bool py, int terms, F &&f)
 {
-    if (mixed) return Kind<Fam, true>::dispatch(py, site, f);
-    return Kind<Fam, false>::dispatch(py, site, f);
+    if (mixed) return Kind<Fam, true>::dispatch(py, terms, f);
+    return Kind<Fam, false>::dispatch(py, terms, f);
 }
 
 }  // namespace

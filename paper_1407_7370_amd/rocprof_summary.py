@@ -147,11 +147,14 @@ def main():
     text = "\n".join(lines)
     print(text)
     if args.traffic_json and traffic:
-        with open(os.path.join(HERE, "csrc", "kernels.hip"), "rb") as f:
-            digest = hashlib.sha256(f.read()).hexdigest()
-        traffic["kernels_sha256"] = digest
+        h = hashlib.sha256()
+        for name in ("kernels.hip", "sweeps.h", "device_reduce.h", "dl_internal.h"):
+            with open(os.path.join(HERE, "csrc", name), "rb") as f:
+                h.update(f.read())
+        traffic["kernels_sha256"] = h.hexdigest()
         traffic["note"] = ("HBM bytes per launch of the dominant sweep from rocprofv3 FETCH_SIZE/WRITE_SIZE, "
-                           "scaled by the calibration kernels; valid for this kernels.hip digest only")
+                           "scaled by the calibration kernels; valid only for this digest of kernels.hip, "
+                           "sweeps.h, device_reduce.h and dl_internal.h")
         with open(args.traffic_json, "w") as f:
             json.dump(traffic, f, indent=1)
 
