@@ -82,6 +82,10 @@ enum { DL_MODE_STEP = 0, DL_MODE_EIGEN = 1 };
  *        with w0 = 2 pi / T and coef[4(k-1) + {0,1,2,3}] = {a_k^x, b_k^x,
  *        a_k^y, b_k^y}.  coef is a HOST pointer, copied during init.
  *   t_pulse: T > 0 when pulse_kind != 0.
+ *   chirality: +1 (or 0): alpha2 = sigma2 as above; -1: alpha2 = -sigma2, the
+ *     other inequivalent 2D representation (Sec. 3: the four-component 2D
+ *     equation splits into the two chiralities).  Every sigma2 term changes
+ *     sign: the y-derivative and the y components of the vector potential.
  */
 typedef struct {
     int32_t nx, ny;
@@ -98,6 +102,7 @@ typedef struct {
     double pulse_e[2], a0, omega, t_pulse;
     int32_t n_coef;
     const double *coef;
+    int32_t chirality;
 } dl_params;
 
 /* Per-step statistics (Sec. 4 eq. matrix_exponential_error and its running

@@ -46,6 +46,7 @@ class _Params(ctypes.Structure):
         ("pulse_e", ctypes.c_double * 2), ("a0", ctypes.c_double), ("omega", ctypes.c_double),
         ("t_pulse", ctypes.c_double),
         ("n_coef", ctypes.c_int32), ("coef", ctypes.c_void_p),
+        ("chirality", ctypes.c_int32),
     ]
 
 
@@ -56,7 +57,7 @@ class _Stat(ctypes.Structure):
 
 ORC_KEYS = ("nx", "ny", "x_min", "x_max", "y_min", "y_max", "bc_x", "bc_y", "mass", "c",
             "charge", "bz", "pot_kind", "pot_z", "pot_a", "v_table", "pulse_kind", "pulse_e",
-            "a0", "omega", "t_pulse", "coef")
+            "a0", "omega", "t_pulse", "coef", "chirality")
 
 _lib = None
 
@@ -99,7 +100,7 @@ class _Problem:
     def __init__(self, prob: dict):
         self.p = _Params()
         self.keep = []
-        for k in ("nx", "ny", "bc_x", "bc_y", "pot_kind", "pulse_kind"):
+        for k in ("nx", "ny", "bc_x", "bc_y", "pot_kind", "pulse_kind", "chirality"):
             setattr(self.p, k, int(prob.get(k, 0)))
         defaults = {"mass": 1.0, "c": 137.036, "charge": -1.0}
         for k in ("x_min", "x_max", "y_min", "y_max", "mass", "c", "charge", "bz", "pot_z",

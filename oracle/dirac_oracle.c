@@ -13,7 +13,8 @@
  * that it follows:
  *
  *   orc_apply_h       Sec. 3, Dirac Hamiltonian H(t) with the 2D Pauli
- *                     representation alpha1=sigma1, alpha2=sigma2, beta=sigma3;
+ *                     representation alpha1=sigma1, alpha2=sigma2, beta=sigma3
+ *                     (or alpha2=-sigma2: the other chirality, Sec. 3);
  *                     Sec. 7, derivatives by first-order (central) finite
  *                     differences on a rectangular grid.
  *   orc_field_average Sec. 3, eq. time_evolution_approx: first Magnus term,
@@ -66,6 +67,7 @@ typedef struct {
     double pulse_e[2], a0, omega, t_pulse;
     int32_t n_coef;
     const double *coef;          /* kind 2: for k=1..n/4: a_k^x, b_k^x, a_k^y, b_k^y */
+    int32_t chirality;           /* -1: alpha2 = -sigma2 (the other 2D representation); else +sigma2 */
 } orc_params;
 
 typedef struct {
@@ -149,6 +151,10 @@ void orc_apply_h(const orc_params *p, const double *a_hom, const double *in_d, d
     pauli(1, s1);
     pauli(2, s2);
     pauli(3, s3);
+    /* alpha2 = chi sigma2 */
+    const double chi = p->chirality < 0 ? -1.0 : 1.0;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) s2[a][b] *= chi;
     for (int j = 0; j < p->ny; ++j) {
         const double y = p->y_min + j * hy;
         for (int i = 0; i < p->nx; ++i) {

@@ -46,6 +46,7 @@ class DlParams(ctypes.Structure):
         ("pulse_e", ctypes.c_double * 2), ("a0", ctypes.c_double), ("omega", ctypes.c_double),
         ("t_pulse", ctypes.c_double),
         ("n_coef", ctypes.c_int32), ("coef", ctypes.c_void_p),
+        ("chirality", ctypes.c_int32),
     ]
 
 
@@ -140,6 +141,7 @@ def make_params(problem: dict, krylov_dim: int, precision: int = DL_PREC_FP64, v
     p.pulse_e[0], p.pulse_e[1] = float(e[0]), float(e[1])
     p.krylov_dim = int(krylov_dim)
     p.precision = int(precision)
+    p.chirality = int(problem.get("chirality", 0))
     p.v_table = int(v_table_ptr) if v_table_ptr else None
     coef = problem.get("coef")
     if coef is not None and len(coef) > 0:

@@ -226,9 +226,9 @@ dl_status dirac_lanczos_adjoint(dl_context *ctx, const void *psi0_v, double t0, 
         double a[2];
         pulse_average(p, ctx->coef, t0 + (double)i * dt, dt, a);
         hf[4 * (size_t)i + 0] = kf * a[0];
-        hf[4 * (size_t)i + 1] = kf * a[1];
+        hf[4 * (size_t)i + 1] = kf * chir(p) * a[1];
         hf[4 * (size_t)i + 2] = -kf * a[0];
-        hf[4 * (size_t)i + 3] = -kf * a[1];
+        hf[4 * (size_t)i + 3] = -kf * chir(p) * a[1];
     }
     DL_HIP(ctx, hipMemcpyAsync(fields, hf.data(), sizeof(double) * hf.size(), hipMemcpyHostToDevice, st));
     const dl::Op opf = ctx->op(dt), opb = ctx->op(-dt), op1 = ctx->op(1.0);
@@ -333,6 +333,7 @@ dl_status dirac_lanczos_adjoint(dl_context *ctx, const void *psi0_v, double t0, 
                 return ctx->fail(DL_ERR_NONFINITE, "non-finite Lanczos reduction in the backward pass");
             double gx, gy;
             step_gradient(r, dt, cq, &gx, &gy);
+            gy *= chir(p);  // dA/dAbar_y = -dt c q chir sigma2
             if (!std::isfinite(gx) || !std::isfinite(gy))
                 return ctx->fail(DL_ERR_NONFINITE, "non-finite gradient contribution");
             gstep[2 * ((size_t)g * C + i)] = gx;

@@ -378,7 +378,7 @@ dl_status dirac_lanczos_batch_step(dl_batch *b, void *const *psi, double t0, dou
                 double av[2];
                 pulse_average(b->p[i], b->coef[i], t0 + (double)(s0 + j) * dt, dt, av);
                 b->h_fields[(size_t)2 * dl::kChunk * i + 2 * j] = kf * av[0];
-                b->h_fields[(size_t)2 * dl::kChunk * i + 2 * j + 1] = kf * av[1];
+                b->h_fields[(size_t)2 * dl::kChunk * i + 2 * j + 1] = kf * chir(b->p[i]) * av[1];
             }
         }
         DL_HIP(b, hipMemcpy2DAsync(b->fields, sizeof(double) * 2 * dl::kChunk, b->h_fields.data(),

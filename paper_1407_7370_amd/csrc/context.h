@@ -37,8 +37,11 @@ void tridiag_last_row(std::vector<double> d, std::vector<double> e, std::vector<
 void tridiag_full(std::vector<double> d, std::vector<double> e, std::vector<double> &lam,
                   std::vector<double> &v);
 
+// Sign of the sigma2 terms: alpha2 = chir * sigma2.
+inline double chir(const dl_params &p) { return p.chirality < 0 ? -1.0 : 1.0; }
+
 // A = s H with the geometry and static fields of the problem (the homogeneous
-// laser term is passed to the kernels per step).
+// laser term is passed to the kernels per step, its y component times chir).
 inline dl::Op make_op(const dl_params &p, double s)
 {
     dl::Op o{};
@@ -51,9 +54,10 @@ inline dl::Op make_op(const dl_params &p, double s)
     o.xmin = p.x_min;
     o.ymin = p.y_min;
     o.kx = s * p.c / (2.0 * o.hx);
-    o.ky = s * p.c / (2.0 * o.hy);
+    o.ky = chir(p) * s * p.c / (2.0 * o.hy);
     o.mc2 = s * p.mass * p.c * p.c;
     o.bq = s * p.c * p.charge * p.bz * 0.5;
+    o.bqy = chir(p) * o.bq;
     o.pot_kind = p.pot_kind ? 1 : 0;
     if (p.pot_kind == 1) {
         o.vz = s * p.pot_z;

@@ -48,9 +48,10 @@ struct StepStat {
 struct Op {
     int nx, ny, bcx, bcy;
     double xmin, ymin, hx, hy;
-    double kx, ky;        // s c / (2 h_x), s c / (2 h_y)
+    double kx, ky;        // s c / (2 h_x), chir s c / (2 h_y) (chir = +-1: alpha2 = chir sigma2)
     double mc2;           // s m c^2
-    double bq;            // s c q B / 2: gx = gx_hom + bq y, gy = gy_hom - bq x
+    double bq;            // s c q B / 2: gx = gx_hom + bq y
+    double bqy;           // chir bq: gy = gy_hom - bqy x (gy_hom carries chir as well)
     int pot_kind;         // 0 none, 1 s*(-zc / sqrt(r^2 + a2))
     int has_table;
     double vz, va2;       // s*zc, a2

@@ -66,6 +66,7 @@ const char *validate(const dl_params *p)
         !std::isfinite(p->y_max))
         return "box bounds must be finite";
     if ((p->bc_x != 0 && p->bc_x != 1) || (p->bc_y != 0 && p->bc_y != 1)) return "bc must be 0 or 1";
+    if (p->chirality < -1 || p->chirality > 1) return "chirality must be -1, 0 or +1";
     if (!(p->c > 0.0) || !std::isfinite(p->c)) return "c must be positive";
     if (!(p->mass >= 0.0) || !std::isfinite(p->mass)) return "mass must be >= 0";
     if (!std::isfinite(p->charge) || !std::isfinite(p->bz)) return "charge and bz must be finite";
@@ -454,7 +455,7 @@ dl_status dirac_lanczos_apply(dl_context *ctx, const void *x, void *y, double t)
     pulse_now(ctx->p, ctx->coef, t, a);
     const double k = -ctx->p.c * ctx->p.charge;
     dl::launch_apply(op, ctx->tiles_apply, static_cast<const double2 *>(x), static_cast<double2 *>(y), k * a[0],
-                     k * a[1], ctx->stream);
+                     k * chir(ctx->p) * a[1], ctx->stream);
     DL_HIP(ctx, hipGetLastError());
     return DL_OK;
 }
@@ -504,7 +505,7 @@ dl_status dirac_lanczos_step(dl_context *ctx, void *psi_v, double t0, double dt,
             double a[2];
             pulse_average(p, ctx->coef, t0 + (double)(s0 + i) * dt, dt, a);
             ctx->host_fields[2 * i] = kf * a[0];
-            ctx->host_fields[2 * i + 1] = kf * a[1];
+            ctx->host_fields[2 * i + 1] = kf * chir(p) * a[1];
         }
         DL_HIP(ctx, hipMemcpyAsync(fields, ctx->host_fields.data(), sizeof(double) * 2 * nc,
                                    hipMemcpyHostToDevice, st));

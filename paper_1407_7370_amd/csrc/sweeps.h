@@ -481,7 +481,7 @@ __device__ __forceinline__ void first_body(const Op &op, const Tiles &t, const W
     const double gxh = field[0], gyh = field[1];
     if (wt.active) {
         const LaneGeo lg = lane_geo(op, t, wt.strip, lane);
-        const double gy = (TERMS & kTermB) ? gyh - op.bq * lg.x : gyh;
+        const double gy = (TERMS & kTermB) ? gyh - op.bqy * lg.x : gyh;
         const PlanarF vin = make_view<PlanarF>(psi, op);
         const uint32_t off = lg.inx ? PlanarF::lane_offset(lg.colw) : kOob;
         const int y0 = wt.y0, y1 = wt.y1, base = y0 - 1;
@@ -606,7 +606,7 @@ __device__ __forceinline__ void recur_body(const PassArgs &a, const WaveTask &wt
     const double gxh = a.field[0], gyh = a.field[1];
     if (wt.active) {
         const LaneGeo lg = lane_geo(op, a.t, wt.strip, lane);
-        const double gy = (TERMS & kTermB) ? gyh - op.bq * lg.x : gyh;
+        const double gy = (TERMS & kTermB) ? gyh - op.bqy * lg.x : gyh;
         // u_p = cw (A' u_{p-1}) - cc u_{p-1} - cu u_{p-2}; lanes outside the domain
         // get zero coefficients, so their u_p is zero without a select
         const double m = lg.inx ? 1.0 : 0.0;
@@ -1078,7 +1078,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(Op op, Tiles t, const double2 
     if (!wt.active) return;
     const size_t plane = (size_t)op.nx * op.ny;
     const LaneGeo lg = lane_geo(op, t, wt.strip, lane);
-    const double gy = gyh - op.bq * lg.x;
+    const double gy = gyh - op.bqy * lg.x;
     const Planar vin{reinterpret_cast<const char *>(x), plane * 16, (uint32_t)op.nx * 16u};
     const uint32_t off = lg.inx ? Planar::lane_offset(lg.colw) : kOob;
     Sp p0 = sp_zero(), p1 = sp_zero();

@@ -70,7 +70,8 @@ def dense_h(prob, a_hom=(0.0, 0.0)):
     PIx = -1j * Dx - q * Ax
     PIy = -1j * Dy - q * Ay
     V = sp.diags(potential_grid(prob).ravel())
-    H = (c * (sp.kron(SX, PIx) + sp.kron(SY, PIy)) + m * c * c * sp.kron(SZ, Ieye)
+    chi = -1.0 if prob.get("chirality", 0) < 0 else 1.0  # alpha2 = chi sigma2
+    H = (c * (sp.kron(SX, PIx) + chi * sp.kron(SY, PIy)) + m * c * c * sp.kron(SZ, Ieye)
          + sp.kron(ID2, V))
     return H.tocsr()
 
@@ -145,3 +146,28 @@ def landau_levels(prob, n_max):
 
 def rel_l2(a, b):
     return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def dense_h4(prob, a_hom=(0.0, 0.0)):
+    """Four-component H = c alpha.(p - qA) + beta m c^2 + V on the flattened
+    (4, ny, nx) spinor, standard Dirac representation alpha_i = [[0, s_i],
+    [s_i, 0]], beta = diag(1, 1, -1, -1), no z motion."""
+    nx, ny = prob["nx"], prob["ny"]
+    x, y, hx, hy = axes(prob)
+    per_x, per_y = prob["bc_x"] == 1, prob["bc_y"] == 1
+    Dx = sp.kron(sp.identity(ny), diff_1d(nx, hx, per_x))
+    Dy = sp.kron(diff_1d(ny, hy, per_y), sp.identity(nx))
+    X, Y = np.meshgrid(x, y)
+    q, c, m = prob["charge"], prob["c"], prob["mass"]
+    ax = (-0.5 * prob.get("bz", 0.0) * Y + a_hom[0]).ravel()
+    ay = (0.5 * prob.get("bz", 0.0) * X + a_hom[1]).ravel()
+    PIx = -1j * Dx - q * sp.diags(ax)
+    PIy = -1j * Dy - q * sp.diags(ay)
+    V = sp.diags(potential_grid(prob).ravel())
+    Z2 = np.zeros((2, 2), dtype=np.complex128)
+    ax4 = np.block([[Z2, SX], [SX, Z2]])
+    ay4 = np.block([[Z2, SY], [SY, Z2]])
+    b4 = np.diag([1.0, 1.0, -1.0, -1.0]).astype(np.complex128)
+    Ieye = sp.identity(nx * ny)
+    H = c * (sp.kron(ax4, PIx) + sp.kron(ay4, PIy)) + m * c * c * sp.kron(b4, Ieye) + sp.kron(np.eye(4), V)
+    return H.tocsr()

@@ -88,6 +88,16 @@ def test_adjoint_vs_oracle_fd(torch_cuda, Prop, orc, loss_kind):
     assert rel_max(grad, gf) <= 1e-6, (grad, gf)
 
 
+def test_adjoint_chirality_minus_vs_oracle_fd(torch_cuda, Prop, orc):
+    prob = small_case(bz=0.4, chirality=-1)
+    psi0 = packet(prob, 12, 1.5, 3.0)
+    say("adjoint chirality -1 vs oracle FD 88x40")
+    loss, grad, _ = gpu_adjoint(torch_cuda, Prop, prob, 12, psi0, 0.0, 1e-3, 24, 5, 10)
+    assert abs(loss - orc.final_loss(prob, psi0, 0.0, 1e-3, 24, 12, 10)) <= 1e-10 * max(1.0, abs(loss))
+    gf = orc.fd_gradient(prob, psi0, 0.0, 1e-3, 24, 12, 10, h=0.5)
+    assert rel_max(grad, gf) <= 1e-6, (grad, gf)
+
+
 def test_adjoint_checkpoint_interval_is_bitwise_neutral(torch_cuda, Prop):
     prob = small_case()
     psi0 = packet(prob, 3, 1.5, 3.0)

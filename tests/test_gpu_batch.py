@@ -42,6 +42,7 @@ def small_batch(bc=0):
         prob(17, 90, bc, pot_kind=1, pot_z=1.0, pot_a=1.0),
         prob(131, 40, bc, pulse_kind=2, t_pulse=0.02, coef=rng.uniform(-20, 20, 8)),
         prob(8, 8, bc, bz=-1.1, pot_kind=2, pot_z=2.0),
+        prob(40, 52, bc, bz=0.5, chirality=-1, pulse_kind=1, pulse_e=(0.0, 1.0), a0=30.0, omega=1.0, t_pulse=0.02),
     ]
 
 

@@ -66,6 +66,9 @@ APPLY_CASES = {
     "fourier_t": (dict(box(70, 96, 0), pulse_kind=2, t_pulse=2.0,
                        coef=np.random.default_rng(3).uniform(-20, 20, 16)), 0.71),
     "one_strip_boundary_124x200": (box(124, 200, 0, bz=0.5), 0.0),
+    "chirality_minus_b_laser": (dict(box(96, 70, 0, bz=0.6, pot_kind=1, pot_z=1.0, pot_a=1.0), pulse_kind=1,
+                                     pulse_e=(0.6, 0.8), a0=50.0, omega=1.0, t_pulse=0.1, chirality=-1), 0.037),
+    "chirality_minus_periodic": (dict(box(64, 48, 1, bz=-0.9), chirality=-1), 0.0),
 }
 
 
@@ -358,3 +361,19 @@ def test_eigen_full_grid_properties(torch_cuda, Prop):
     assert 1 <= len(ev) <= 8
     assert np.all(bd <= tol) and np.all(np.diff(ev) > tol)
     assert np.all(ev >= lo) and np.all(ev <= hi)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_chirality_minus_propagation(torch_cuda, Prop, orc, prec):
+    """alpha2 = -sigma2 with a magnetic field, a soft core and a y-polarised
+    laser: every sigma2 term (y derivative, A_y of both fields) changes sign."""
+    prob = dict(box(130, 77, 0, bz=0.8, pot_kind=1, pot_z=1.0, pot_a=1.0), pulse_kind=1, pulse_e=(0.3, 0.95),
+                a0=40.0, omega=1.0, t_pulse=0.02, chirality=-1)
+    psi0 = packets.gaussian_packet(prob, 0.8, packets.draw_momentum(4, 3.0), project=True)
+    say(f"chirality -1 propagation {prec}")
+    out, st = gpu_run(torch_cuda, Prop, prob, 12, prec, psi0, 0.0, 1e-3, 20)
+    ref, rst = orc.propagate(prob, psi0, 0.0, 1e-3, 20, 12)
+    err = hz.rel_l2(out, ref)
+    assert err <= (1e-10 if prec == "fp64" else 1e-6), err
+    plus, _ = orc.propagate(dict(prob, chirality=1), psi0, 0.0, 1e-3, 20, 12)
+    assert hz.rel_l2(plus, ref) > 1e-3  # the chirality matters for this state

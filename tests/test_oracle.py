@@ -45,10 +45,11 @@ def test_dirac_algebra(orc):
 # ---------------------------------------------------------------------------
 # Stencil vs dense H assembled independently
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("chirality", [1, -1])
 @pytest.mark.parametrize("bc", [0, 1])
 @pytest.mark.parametrize("shape", [(4, 4), (6, 5), (8, 7)])
 @pytest.mark.parametrize("fields", ["free", "bz", "soft1", "soft2", "table", "all"])
-def test_apply_h_vs_dense(orc, bc, shape, fields):
+def test_apply_h_vs_dense(orc, bc, shape, fields, chirality):
     nx, ny = shape
     rng = np.random.default_rng(nx * 100 + ny + bc)
     kw = {}
@@ -60,7 +61,7 @@ def test_apply_h_vs_dense(orc, bc, shape, fields):
         kw["pot_kind"] = 2
     if fields in ("table", "all"):
         kw["v_table"] = rng.standard_normal((ny, nx))
-    prob = small_prob(nx, ny, bc, **kw)
+    prob = small_prob(nx, ny, bc, chirality=chirality, **kw)
     a_hom = (0.3, -1.1) if fields == "all" else (0.0, 0.0)
     psi = packets.random_spinor(prob, seed=7)
     got = orc.apply_h(prob, psi, a_hom)
@@ -84,16 +85,17 @@ def test_hermiticity(orc, bc):
 # ---------------------------------------------------------------------------
 # Closed form: plane waves on the periodic lattice
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("chirality", [1, -1])
 @pytest.mark.parametrize("mass", [1.0, 0.0])
 @pytest.mark.parametrize("a_hom", [(0.0, 0.0), (0.8, -2.5)])
 @pytest.mark.parametrize("mode", [(1, 0), (3, 5), (7, 2), (15, 11)])
-def test_plane_wave_dispersion(orc, mass, a_hom, mode):
-    prob = small_prob(16, 12, 1, mass=mass, lo=-4.0, hi=4.0)
+def test_plane_wave_dispersion(orc, mass, a_hom, mode, chirality):
+    prob = small_prob(16, 12, 1, mass=mass, lo=-4.0, hi=4.0, chirality=chirality)
     x, y, hx, hy = hz.axes(prob)
     Lx, Ly = prob["x_max"] - prob["x_min"], prob["y_max"] - prob["y_min"]
     kx, ky = 2 * math.pi * mode[0] / Lx, 2 * math.pi * mode[1] / Ly
     e, px, py = hz.lattice_energy(prob, kx, ky, a_hom)
-    h0 = C * (px * hz.SX + py * hz.SY) + mass * C * C * hz.SZ
+    h0 = C * (px * hz.SX + chirality * py * hz.SY) + mass * C * C * hz.SZ
     w, vec = np.linalg.eigh(h0)
     X, Y = np.meshgrid(x, y)
     wave = np.exp(1j * (kx * X + ky * Y))
@@ -102,6 +104,23 @@ def test_plane_wave_dispersion(orc, mass, a_hom, mode):
         psi = np.stack([vec[0, col] * wave, vec[1, col] * wave])
         got = orc.apply_h(prob, psi, a_hom)
         assert hz.rel_l2(got, sgn * e * psi) <= 1e-13
+
+
+def test_four_component_splits_into_chiralities(orc):
+    """Sec. 3: in two dimensions the four-component Dirac equation decouples
+    into the two inequivalent two-component representations (alpha2 = +sigma2
+    and -sigma2).  The four-component H, built here from the standard 4x4
+    Dirac matrices, has the union of the two spectra."""
+    prob = small_prob(6, 5, 0, bz=0.7, pot_kind=1)
+    a_hom = (0.4, -0.9)
+    h4 = hz.dense_h4(prob, a_hom).toarray()
+    hp = orc.dense_matrix(prob, a_hom)
+    hm = orc.dense_matrix(dict(prob, chirality=-1), a_hom)
+    w4 = np.linalg.eigvalsh(h4)
+    w2 = np.sort(np.concatenate([np.linalg.eigvalsh(hp), np.linalg.eigvalsh(hm)]))
+    assert np.max(np.abs(w4 - w2)) <= 1e-11 * np.max(np.abs(w4))
+    # the two chiralities are different operators
+    assert np.max(np.abs(hp - hm)) > 1.0
 
 
 # ---------------------------------------------------------------------------
