@@ -157,6 +157,30 @@ dl_status dirac_lanczos_step(dl_context *ctx, void *psi, double t0, double dt, i
                              dl_step_stat *stats);
 
 /*
+ * Adaptive time steps (Sec. 4: the error estimate eq.
+ * matrix_exponential_error used to adjust the step size).  Propagates psi
+ * (DEVICE, in place) from t0 to t_end > t0 with steps of variable size, each
+ * one step of dirac_lanczos_step.  A step of size dt may spend
+ * tol * dt / (t_end - t0) of error estimate, so the cumulative bound stays
+ * below tol; a step over its share is rejected (psi untouched) and retried
+ * smaller; the next dt follows from the ratio (share / estimate)^(1/(k-1)),
+ * within [dt_min, dt_max], and the last step ends at t_end exactly.
+ * dt_taken: HOST array of max_steps doubles receiving the accepted sizes, or
+ * NULL.  out (HOST) receives the counts, the time reached, the next dt, the
+ * cumulative bound and ||psi||^2.  Errors: DL_ERR_INVALID (arguments; or
+ * max_steps exhausted / tol needing dt < dt_min: psi then holds the state at
+ * out->t_reached), DL_ERR_NONFINITE, DL_ERR_DEVICE.  Synchronous.
+ */
+typedef struct {
+    int32_t accepted, rejected;
+    double t_reached, dt_next, cum_bound, norm2;
+} dl_adapt_stat;
+
+dl_status dirac_lanczos_step_adaptive(dl_context *ctx, void *psi, double t0, double t_end, double dt_init,
+                                      double tol, double dt_min, double dt_max, int32_t max_steps,
+                                      double *dt_taken, dl_adapt_stat *out);
+
+/*
  * Eigenvalue mode (Sec. 2 eq. A_approx, eq. error_est; Sec. 5): k_max plain
  * Lanczos iterations on H (static fields, laser off) from psi0 (DEVICE).
  * Ritz values of T in [e_lo, e_hi] are grouped into clusters of neighbours

@@ -27,7 +27,7 @@ EXPORTS = ("dirac_lanczos_workspace_bytes", "dirac_lanczos_init", "dirac_lanczos
            "dirac_lanczos_adjoint", "dirac_lanczos_timing", "dirac_lanczos_destroy",
            "dirac_lanczos_last_error", "dirac_lanczos_batch_workspace_bytes", "dirac_lanczos_batch_init",
            "dirac_lanczos_batch_step", "dirac_lanczos_batch_destroy", "dirac_lanczos_batch_last_error",
-           "dirac_lanczos_set_launch", "dirac_lanczos_batch_set_launch")
+           "dirac_lanczos_set_launch", "dirac_lanczos_batch_set_launch", "dirac_lanczos_step_adaptive")
 DL_LOSS_X, DL_LOSS_Y, DL_LOSS_PX, DL_LOSS_PY = 1, 2, 4, 8
 
 
@@ -53,6 +53,11 @@ class DlParams(ctypes.Structure):
 class DlStepStat(ctypes.Structure):
     _fields_ = [("k_eff", ctypes.c_int32), ("err_est", ctypes.c_double),
                 ("cum_bound", ctypes.c_double), ("norm2", ctypes.c_double)]
+
+
+class DlAdaptStat(ctypes.Structure):
+    _fields_ = [("accepted", ctypes.c_int32), ("rejected", ctypes.c_int32), ("t_reached", ctypes.c_double),
+                ("dt_next", ctypes.c_double), ("cum_bound", ctypes.c_double), ("norm2", ctypes.c_double)]
 
 
 class DlTiming(ctypes.Structure):
@@ -123,6 +128,10 @@ def load_library():
     lib.dirac_lanczos_set_launch.restype = ctypes.c_int
     lib.dirac_lanczos_batch_set_launch.argtypes = [vp, ctypes.c_int32, I]
     lib.dirac_lanczos_batch_set_launch.restype = ctypes.c_int
+    lib.dirac_lanczos_step_adaptive.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                                ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                                D, ctypes.POINTER(DlAdaptStat)]
+    lib.dirac_lanczos_step_adaptive.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -315,6 +324,20 @@ class Propagator:
             }
         _check(self.lib, self.ctx, st)
         return out
+
+    def step_adaptive(self, psi, t0: float, t_end: float, dt_init: float, tol: float, dt_min: float,
+                      dt_max: float, max_steps: int = 100000):
+        """In-place propagation from t0 to t_end with adaptive step sizes
+        (cumulative error bound <= tol).  Returns (stats dict, accepted step sizes)."""
+        self._check_psi(psi)
+        out = DlAdaptStat()
+        dts = (ctypes.c_double * max_steps)()
+        st = self.lib.dirac_lanczos_step_adaptive(self.ctx, ctypes.c_void_p(psi.data_ptr()), t0, t_end, dt_init,
+                                                  tol, dt_min, dt_max, max_steps, dts, ctypes.byref(out))
+        stats = {"accepted": out.accepted, "rejected": out.rejected, "t_reached": out.t_reached,
+                 "dt_next": out.dt_next, "cum_bound": out.cum_bound, "norm2": out.norm2}
+        _check(self.lib, self.ctx, st)
+        return stats, np.array(dts[:out.accepted])
 
     def eigen(self, psi0, k_max: int, e_lo: float, e_hi: float, tol: float, n_wanted: int = 64,
               reorth: bool = False):

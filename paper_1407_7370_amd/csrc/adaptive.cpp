@@ -1,0 +1,119 @@
+// Adaptive time steps (C ABI dirac_lanczos_step_adaptive).
+//
+// The error estimate of one step (Sec. 4, eq. matrix_exponential_error) is
+// cheap, and the paper notes it can steer the step size.  Reading used here:
+// the cumulative bound over [t0, t_end] is to stay below tol, so a step of
+// size dt may spend tol * dt / (t_end - t0).  A step whose estimate exceeds
+// its share is rejected (the state is untouched: a step writes into the
+// ping-pong partner) and retried with a smaller dt; after every step dt is
+// rescaled by (share / estimate)^(1/(k-1)) -- the Krylov error of exp(-i dt H)
+// behaves like dt^k, its share like dt -- with a safety factor 0.9, at most
+// x2 and at least x1/4, within [dt_min, dt_max], and the last step lands on
+// t_end exactly.
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "context.h"
+
+using namespace dlh;
+
+extern "C" {
+
+dl_status dirac_lanczos_step_adaptive(dl_context *ctx, void *psi_v, double t0, double t_end, double dt_init,
+                                      double tol, double dt_min, double dt_max, int32_t max_steps,
+                                      double *dt_taken, dl_adapt_stat *out)
+{
+    if (!ctx) return DL_ERR_INVALID;
+    if (!psi_v || !out) return ctx->fail(DL_ERR_INVALID, "psi and out must be non-NULL");
+    if (!std::isfinite(t0) || !std::isfinite(t_end) || !(t_end > t0))
+        return ctx->fail(DL_ERR_INVALID, "need finite t0 < t_end");
+    if (!(tol > 0.0) || !(dt_min > 0.0) || !(dt_max >= dt_min) || !(dt_init > 0.0) || !std::isfinite(dt_max))
+        return ctx->fail(DL_ERR_INVALID, "need tol > 0 and 0 < dt_min <= dt_max, dt_init > 0");
+    if (max_steps < 1) return ctx->fail(DL_ERR_INVALID, "max_steps must be >= 1");
+    const dl_params &p = ctx->p;
+    const int m = p.krylov_dim;
+    const bool mixed = p.precision == DL_PREC_MIXED;
+    const size_t n = vec_elems(p);
+    char *ws = ctx->ws;
+    const Layout &L = ctx->L;
+    double *partials = reinterpret_cast<double *>(ws + L.partials);
+    double *fields = reinterpret_cast<double *>(ws + L.fields);
+    dl::StepStat *dstat = reinterpret_cast<dl::StepStat *>(ws + L.stats);
+    double2 *psi = static_cast<double2 *>(psi_v);
+    double2 *state = reinterpret_cast<double2 *>(ws + L.vecs);
+    const Engine eng{ctx->sc(), reinterpret_cast<double *>(ws + L.alpha), reinterpret_cast<double *>(ws + L.gamma),
+                     ws + L.vecs + align256(n * 16), vec_stride(n, mixed ? 8 : 16), m, mixed};
+    hipStream_t st = ctx->stream;
+    const double span = t_end - t0;
+    const double expo = 1.0 / std::max(1, m - 1);
+
+    *out = dl_adapt_stat{};
+    out->t_reached = t0;
+    double t = t0, dt = std::min(std::max(dt_init, dt_min), dt_max), cum = 0.0;
+    double2 *cur = psi, *nxt = state;
+    dl::launch_reset(eng.sc, st);
+    DL_HIP(ctx, hipGetLastError());
+    dl_status result = DL_OK;
+    std::string why;
+    while (t < t_end) {
+        if (out->accepted + out->rejected >= max_steps) {
+            result = DL_ERR_INVALID;
+            why = "max_steps reached before t_end";
+            break;
+        }
+        const bool last = t_end - t <= dt * (1.0 + 1e-12);
+        const double h = last ? t_end - t : dt;
+        double a[2], f[2];
+        pulse_average(p, ctx->coef, t, h, a);
+        f[0] = -h * p.c * p.charge * a[0];
+        f[1] = -h * p.c * p.charge * chir(p) * a[1];
+        DL_HIP(ctx, hipMemcpyAsync(fields, f, sizeof(f), hipMemcpyHostToDevice, st));
+        const dl::Op op = ctx->op(h);
+        dl_status s = run_build(ctx, eng, op, cur, fields, partials, 1);
+        if (s != DL_OK) return s;
+        s = run_finish(ctx, eng, cur, nxt, dstat, partials);
+        if (s != DL_OK) return s;
+        dl::StepStat hs;
+        int status = 0;
+        DL_HIP(ctx, hipMemcpyAsync(&hs, dstat, sizeof(hs), hipMemcpyDeviceToHost, st));
+        DL_HIP(ctx, hipMemcpyAsync(&status, &eng.sc->status, sizeof(int), hipMemcpyDeviceToHost, st));
+        DL_HIP(ctx, hipStreamSynchronize(st));
+        if (status != 0) {
+            result = DL_ERR_NONFINITE;
+            why = "non-finite Lanczos reduction";
+            break;
+        }
+        const double share = tol * h / span;
+        const double est = hs.err_est;
+        const double factor = est > 0.0 ? std::min(2.0, std::max(0.25, 0.9 * std::pow(share / est, expo))) : 2.0;
+        if (est <= share) {
+            if (dt_taken) dt_taken[out->accepted] = h;
+            out->accepted += 1;
+            cum += est;
+            t = last ? t_end : t + h;
+            out->norm2 = hs.norm2;
+            std::swap(cur, nxt);
+            if (!last) dt = std::min(dt_max, std::max(dt_min, h * factor));
+        } else {
+            out->rejected += 1;
+            if (h <= dt_min) {
+                result = DL_ERR_INVALID;
+                why = "the tolerance needs a step below dt_min";
+                break;
+            }
+            dt = std::max(dt_min, h * std::min(factor, 0.5));
+        }
+    }
+    out->t_reached = t;
+    out->cum_bound = cum;
+    out->dt_next = dt;
+    if (cur != psi) {
+        DL_HIP(ctx, hipMemcpyAsync(psi, cur, n * 16, hipMemcpyDeviceToDevice, st));
+        DL_HIP(ctx, hipStreamSynchronize(st));
+    }
+    if (result != DL_OK) return ctx->fail(result, why + " (state at t = " + std::to_string(t) + ")");
+    return DL_OK;
+}
+
+}  // extern "C"
