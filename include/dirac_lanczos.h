@@ -59,7 +59,7 @@ enum { DL_BC_DIRICHLET = 0, DL_BC_PERIODIC = 1 };
 enum { DL_PREC_FP64 = 0, DL_PREC_MIXED = 1 };
 enum { DL_POT_NONE = 0, DL_POT_SOFTCORE = 1, DL_POT_PAPER_SOFTCORE = 2 };
 enum { DL_PULSE_NONE = 0, DL_PULSE_SIN_SIN2 = 1, DL_PULSE_FOURIER_SIN2 = 2 };
-enum { DL_MODE_STEP = 0, DL_MODE_EIGEN = 1 };
+enum { DL_MODE_STEP = 0, DL_MODE_EIGEN = 1, DL_MODE_LOWMEM = 2 };
 
 /*
  * Problem description (Sec. 3 Hamiltonian, Sec. 7 grid).
@@ -116,8 +116,11 @@ typedef struct {
 
 /*
  * Bytes of caller-provided device workspace a context needs.
- * mode DL_MODE_STEP: for step/apply; DL_MODE_EIGEN: additionally for
- * eigen() with up to k_eigen Lanczos iterations.  Returns 0 for invalid
+ * mode DL_MODE_STEP: for step/apply (the stored Krylov basis, m - 1 vectors);
+ * DL_MODE_LOWMEM: for step_lowmem/apply (three Krylov vectors);
+ * DL_MODE_EIGEN: additionally for eigen() with up to k_eigen Lanczos
+ * iterations.  init accepts the smaller of the STEP and LOWMEM sizes; every
+ * call checks the size it needs (DL_ERR_WORKSPACE).  Returns 0 for invalid
  * parameters.  The workspace must be 256-byte aligned.
  */
 size_t dirac_lanczos_workspace_bytes(const dl_params *params, int32_t mode, int32_t k_eigen);
@@ -155,6 +158,17 @@ dl_status dirac_lanczos_apply(dl_context *ctx, const void *x, void *y, double t)
  */
 dl_status dirac_lanczos_step(dl_context *ctx, void *psi, double t0, double dt, int32_t n_steps,
                              dl_step_stat *stats);
+
+/*
+ * Memory-saving variant of dirac_lanczos_step (Sec. 4: instead of storing
+ * the Krylov basis, the Lanczos recurrence is run a second time when Q is
+ * multiplied by exp(-iT) e_1).  Same arguments and results as
+ * dirac_lanczos_step (to rounding of the recombination order); the
+ * workspace holds three Krylov vectors instead of m - 1, at the price of
+ * m - 1 more sweeps per step.
+ */
+dl_status dirac_lanczos_step_lowmem(dl_context *ctx, void *psi, double t0, double dt, int32_t n_steps,
+                                    dl_step_stat *stats);
 
 /*
  * Adaptive time steps (Sec. 4: the error estimate eq.

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libdirac_lanczos.so")
 
 DL_OK, DL_ERR_INVALID, DL_ERR_DEVICE, DL_ERR_NONFINITE, DL_ERR_WORKSPACE, DL_ERR_UNSUPPORTED = range(6)
 DL_PREC_FP64, DL_PREC_MIXED = 0, 1
-DL_MODE_STEP, DL_MODE_EIGEN = 0, 1
+DL_MODE_STEP, DL_MODE_EIGEN, DL_MODE_LOWMEM = 0, 1, 2
 STATUS_NAMES = {0: "DL_OK", 1: "DL_ERR_INVALID", 2: "DL_ERR_DEVICE", 3: "DL_ERR_NONFINITE",
                 4: "DL_ERR_WORKSPACE", 5: "DL_ERR_UNSUPPORTED"}
 
@@ -27,7 +27,8 @@ EXPORTS = ("dirac_lanczos_workspace_bytes", "dirac_lanczos_init", "dirac_lanczos
            "dirac_lanczos_adjoint", "dirac_lanczos_timing", "dirac_lanczos_destroy",
            "dirac_lanczos_last_error", "dirac_lanczos_batch_workspace_bytes", "dirac_lanczos_batch_init",
            "dirac_lanczos_batch_step", "dirac_lanczos_batch_destroy", "dirac_lanczos_batch_last_error",
-           "dirac_lanczos_set_launch", "dirac_lanczos_batch_set_launch", "dirac_lanczos_step_adaptive")
+           "dirac_lanczos_set_launch", "dirac_lanczos_batch_set_launch", "dirac_lanczos_step_adaptive",
+           "dirac_lanczos_step_lowmem")
 DL_LOSS_X, DL_LOSS_Y, DL_LOSS_PX, DL_LOSS_PY = 1, 2, 4, 8
 
 
@@ -97,6 +98,8 @@ def load_library():
     lib.dirac_lanczos_step.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                        ctypes.POINTER(DlStepStat)]
     lib.dirac_lanczos_step.restype = ctypes.c_int
+    lib.dirac_lanczos_step_lowmem.argtypes = lib.dirac_lanczos_step.argtypes
+    lib.dirac_lanczos_step_lowmem.restype = ctypes.c_int
     lib.dirac_lanczos_eigen.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                         ctypes.c_double, ctypes.c_double, ctypes.c_int32, D, D,
                                         ctypes.POINTER(ctypes.c_int32)]
@@ -265,7 +268,7 @@ class Propagator:
     """
 
     def __init__(self, problem: dict, krylov_dim: int, precision: str = "fp64", k_eigen: int = 0,
-                 stream=None, v_table=None, tuning_cache=None):
+                 stream=None, v_table=None, tuning_cache=None, lowmem: bool = False):
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -277,7 +280,7 @@ class Propagator:
             self.v_table = torch.as_tensor(v_table, dtype=torch.float64, device="cuda").contiguous()
             vptr = self.v_table.data_ptr()
         self.params, self._keep = make_params(problem, krylov_dim, self.prec, vptr)
-        mode = DL_MODE_EIGEN if k_eigen > 0 else DL_MODE_STEP
+        mode = DL_MODE_EIGEN if k_eigen > 0 else (DL_MODE_LOWMEM if lowmem else DL_MODE_STEP)
         nbytes = dirac_lanczos_workspace_bytes(self.params, mode, k_eigen)
         if nbytes == 0:
             raise DlError(DL_ERR_INVALID, "invalid parameters (workspace_bytes returned 0)")
@@ -309,11 +312,13 @@ class Propagator:
         _check(self.lib, self.ctx, dirac_lanczos_apply(self.ctx, x.data_ptr(), y.data_ptr(), t))
         return y
 
-    def step(self, psi, t0: float, dt: float, n_steps: int, want_stats: bool = True):
-        """In-place propagation of psi by n_steps steps.  Returns a dict of numpy stats."""
+    def step(self, psi, t0: float, dt: float, n_steps: int, want_stats: bool = True, lowmem: bool = False):
+        """In-place propagation of psi by n_steps steps (lowmem: the second-run
+        variant).  Returns a dict of numpy stats."""
         self._check_psi(psi)
         stats = (DlStepStat * max(n_steps, 1))() if want_stats else None
-        st = dirac_lanczos_step(self.ctx, psi.data_ptr(), t0, dt, n_steps, stats)
+        fn = self.lib.dirac_lanczos_step_lowmem if lowmem else self.lib.dirac_lanczos_step
+        st = fn(self.ctx, ctypes.c_void_p(psi.data_ptr()), t0, dt, n_steps, stats)
         out = None
         if want_stats:
             out = {

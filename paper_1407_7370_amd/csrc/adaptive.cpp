@@ -33,6 +33,8 @@ dl_status dirac_lanczos_step_adaptive(dl_context *ctx, void *psi_v, double t0, d
     if (max_steps < 1) return ctx->fail(DL_ERR_INVALID, "max_steps must be >= 1");
     const dl_params &p = ctx->p;
     const int m = p.krylov_dim;
+    if (ctx->ws_bytes < plan(ctx->p, DL_MODE_STEP, 0).total)
+        return ctx->fail(DL_ERR_WORKSPACE, "context workspace too small for the stored Krylov basis (DL_MODE_STEP)");
     const bool mixed = p.precision == DL_PREC_MIXED;
     const size_t n = vec_elems(p);
     char *ws = ctx->ws;

@@ -188,6 +188,8 @@ dl_status dirac_lanczos_adjoint(dl_context *ctx, const void *psi0_v, double t0, 
     if (m > dl::kContractM)
         return ctx->fail(DL_ERR_UNSUPPORTED, "the adjoint supports krylov_dim <= 16");
     const AdjLayout A = adj_plan(p, n_steps, ckpt_every);
+    if (ctx->ws_bytes < plan(ctx->p, DL_MODE_STEP, 0).total)
+        return ctx->fail(DL_ERR_WORKSPACE, "context workspace too small for the stored Krylov basis (DL_MODE_STEP)");
     if (!adj_ws || ((uintptr_t)adj_ws & 255u) != 0)
         return ctx->fail(DL_ERR_WORKSPACE, "adjoint workspace must be a non-NULL, 256-byte aligned device pointer");
     if (adj_bytes < A.total)

@@ -64,6 +64,7 @@ __global__ __launch_bounds__(kBlock) void k_recur_batch(BatchArgs b)
     a.partials = b.partials + (size_t)bb.first * kPartialStride;
     a.pass = p;
     a.m = b.m;
+    a.replay = 0;
     if (a.sc->kstop < p) return;
     const WaveTask wt = batch_wave_task(b);
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};

@@ -89,6 +89,7 @@ struct PassArgs {
     double *partials;
     int pass;
     int m;
+    int replay;          // 1: recompute u_p only (second Lanczos run), no reductions or scalar updates
 };
 
 // Arguments of the recombination psi_new = sum_j coef_j u_j (flat streaming).
@@ -102,6 +103,21 @@ struct CombArgs {
     double *partials;
     StepStat *stat;      // entry of this step
 };
+
+// One term of the recombination during a second Lanczos run (the basis is not
+// stored): out = c_1 psi for p = 1, out += c_p u_p for p = 2..k_eff; the
+// launch with p = k_eff also reduces ||out||^2 into the step statistics.
+struct AccumArgs {
+    const double2 *psi;  // u_1 (psi layout)
+    const void *u;       // u_p (paired layout), p >= 2
+    size_t sites;
+    double2 *out;        // new state (psi layout)
+    Scalars *sc;
+    double *partials;
+    StepStat *stat;
+    int p;
+};
+void launch_accum(const AccumArgs &a, bool mixed, int nblocks, hipStream_t st);
 
 // Observables <x>, <y>, <p_x>, <p_y> of a state and the adjoint seed.
 // obs (device, 8 doubles): N = <psi|psi>, <x>, <y>, <p_x>, <p_y>, loss = sum of

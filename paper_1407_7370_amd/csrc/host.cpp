@@ -49,7 +49,10 @@ Layout plan(const dl_params &p, int mode, int k_eigen)
     L.vecs = off;
     const size_t n = vec_elems(p);
     const size_t basis_elem = p.precision == DL_PREC_MIXED ? 8 : 16;
-    size_t step_region = align256(n * 16) + (size_t)(m - 1) * vec_stride(n, basis_elem);
+    // the second state buffer, then the Krylov basis u_2..u_m (stored basis) or
+    // three rolling vectors (second Lanczos run)
+    const size_t nbasis = mode == DL_MODE_LOWMEM ? (size_t)std::min(m - 1, 3) : (size_t)(m - 1);
+    size_t step_region = align256(n * 16) + nbasis * vec_stride(n, basis_elem);
     size_t eig_region = mode == DL_MODE_EIGEN ? 3 * vec_stride(n, 16) : 0;
     off += std::max(step_region, eig_region);
     L.total = off;
@@ -311,6 +314,55 @@ dl_status run_build(dl_context *ctx, const Engine &e, const dl::Op &op, const do
     return DL_OK;
 }
 
+// One step by the second Lanczos run (the basis is not stored): iterations
+// 1..m with three rolling vectors give T, exp(-iT) gives the coefficients,
+// then iterations 2..m are replayed bitwise identically (same inputs, no
+// scalar updates) and each u_p is added to the new state as it reappears.
+dl_status run_twice(dl_context *ctx, const Engine &e, const dl::Op &op, const double2 *in, double2 *out,
+                    const double *field, dl::StepStat *stat, double *partials)
+{
+    hipStream_t st = ctx->stream;
+    auto rb = [&](int j) -> void * { return e.basis + (size_t)(j % 3) * e.vstride; };
+    auto pass = [&](int pp, int replay) {
+        dl::PassArgs a{};
+        a.op = op;
+        a.t = ctx->tiles_pass(pp);
+        a.u1 = (pp - 1 == 1) ? static_cast<const void *>(in) : rb(pp - 1);
+        a.u2 = (pp - 2 == 1) ? static_cast<const void *>(in) : (pp - 2 >= 2 ? rb(pp - 2) : nullptr);
+        a.uo = rb(pp);
+        a.field = field;
+        a.alpha = e.alpha;
+        a.gamma = e.gamma;
+        a.sc = e.sc;
+        a.partials = partials;
+        a.pass = pp;
+        a.m = e.m;
+        a.replay = replay;
+        return ctx->timed(pp >= 4 ? 1 : 2, [&] { dl::launch_recur(a, e.mixed, st); });
+    };
+    DL_HIP(ctx, ctx->timed(0, [&] {
+        dl::launch_first(op, ctx->tiles_first, in, field, e.alpha, e.gamma, e.sc, partials, e.m, 1, st);
+    }));
+    for (int pp = 2; pp <= e.m; ++pp) DL_HIP(ctx, pass(pp, 0));
+    DL_HIP(ctx, ctx->timed(3, [&] { dl::launch_tridiag(e.alpha, e.gamma, e.sc, stat, st); }));
+    dl::AccumArgs c{};
+    c.psi = in;
+    c.sites = vec_elems(ctx->p) / 2;
+    c.out = out;
+    c.sc = e.sc;
+    c.partials = partials;
+    c.stat = stat;
+    c.p = 1;
+    DL_HIP(ctx, ctx->timed(4, [&] { dl::launch_accum(c, e.mixed, ctx->combine_blocks, st); }));
+    for (int pp = 2; pp <= e.m; ++pp) {
+        DL_HIP(ctx, pass(pp, 1));
+        c.p = pp;
+        c.u = rb(pp);
+        DL_HIP(ctx, ctx->timed(4, [&] { dl::launch_accum(c, e.mixed, ctx->combine_blocks, st); }));
+    }
+    return DL_OK;
+}
+
 dl_status run_finish(dl_context *ctx, const Engine &e, const double2 *in, double2 *out,
                      dl::StepStat *stat, double *partials)
 {
@@ -382,7 +434,7 @@ extern "C" {
 size_t dirac_lanczos_workspace_bytes(const dl_params *params, int32_t mode, int32_t k_eigen)
 {
     if (validate(params)) return 0;
-    if (mode != DL_MODE_STEP && mode != DL_MODE_EIGEN) return 0;
+    if (mode != DL_MODE_STEP && mode != DL_MODE_EIGEN && mode != DL_MODE_LOWMEM) return 0;
     if (mode == DL_MODE_EIGEN && (k_eigen < 1 || k_eigen > 1000000)) return 0;
     return plan(*params, mode, mode == DL_MODE_EIGEN ? k_eigen : 0).total;
 }
@@ -399,7 +451,11 @@ dl_status dirac_lanczos_init(const dl_params *params, void *workspace, size_t ws
         g_init_error = msg;
         return DL_ERR_INVALID;
     }
-    const Layout L = plan(*params, DL_MODE_STEP, 0);
+    // the smaller of the stored-basis and the second-run layouts; step() and
+    // step_lowmem() check their own need
+    Layout L = plan(*params, DL_MODE_STEP, 0);
+    const Layout Lm = plan(*params, DL_MODE_LOWMEM, 0);
+    if (Lm.total < L.total) L = Lm;
     if (!workspace || ((uintptr_t)workspace & 255u) != 0) {
         g_init_error = "workspace must be a non-NULL, 256-byte aligned device pointer";
         return DL_ERR_WORKSPACE;
@@ -460,8 +516,8 @@ dl_status dirac_lanczos_apply(dl_context *ctx, const void *x, void *y, double t)
     return DL_OK;
 }
 
-dl_status dirac_lanczos_step(dl_context *ctx, void *psi_v, double t0, double dt, int32_t n_steps,
-                             dl_step_stat *stats)
+static dl_status run_steps(dl_context *ctx, void *psi_v, double t0, double dt, int32_t n_steps,
+                           dl_step_stat *stats, bool lowmem)
 {
     if (!ctx) return DL_ERR_INVALID;
     if (!psi_v) return ctx->fail(DL_ERR_INVALID, "psi is NULL");
@@ -470,6 +526,11 @@ dl_status dirac_lanczos_step(dl_context *ctx, void *psi_v, double t0, double dt,
         return ctx->fail(DL_ERR_INVALID, "dt must be finite and non-zero, t0 finite");
     if (n_steps == 0) return DL_OK;
     const dl_params &p = ctx->p;
+    const size_t need = plan(p, lowmem ? DL_MODE_LOWMEM : DL_MODE_STEP, 0).total;
+    if (ctx->ws_bytes < need)
+        return ctx->fail(DL_ERR_WORKSPACE, std::string("workspace too small for ") +
+                                               (lowmem ? "the second-run mode" : "the stored Krylov basis") +
+                                               ": need " + std::to_string(need) + " bytes");
     const int m = p.krylov_dim;
     const bool mixed = p.precision == DL_PREC_MIXED;
     const size_t n = vec_elems(p);
@@ -514,10 +575,13 @@ dl_status dirac_lanczos_step(dl_context *ctx, void *psi_v, double t0, double dt,
             double2 *in = (g % 2 == 0) ? psi : state;
             double2 *out = (g % 2 == 0) ? state : psi;
             const double *fp = fields + 2 * i;
-            const dl_status sb = run_build(ctx, eng, op, in, fp, partials, 1);
+            const dl_status sb = lowmem ? run_twice(ctx, eng, op, in, out, fp, dstats + i, partials)
+                                        : run_build(ctx, eng, op, in, fp, partials, 1);
             if (sb != DL_OK) return sb;
-            const dl_status sf = run_finish(ctx, eng, in, out, dstats + i, partials);
-            if (sf != DL_OK) return sf;
+            if (!lowmem) {
+                const dl_status sf = run_finish(ctx, eng, in, out, dstats + i, partials);
+                if (sf != DL_OK) return sf;
+            }
         }
         DL_HIP(ctx, hipGetLastError());
         dl::Scalars hs;
@@ -557,6 +621,18 @@ dl_status dirac_lanczos_step(dl_context *ctx, void *psi_v, double t0, double dt,
         return ctx->fail(DL_ERR_NONFINITE, "non-finite Lanczos reduction after " +
                                                std::to_string(completed) + " completed steps");
     return DL_OK;
+}
+
+dl_status dirac_lanczos_step(dl_context *ctx, void *psi, double t0, double dt, int32_t n_steps,
+                             dl_step_stat *stats)
+{
+    return run_steps(ctx, psi, t0, dt, n_steps, stats, false);
+}
+
+dl_status dirac_lanczos_step_lowmem(dl_context *ctx, void *psi, double t0, double dt, int32_t n_steps,
+                                    dl_step_stat *stats)
+{
+    return run_steps(ctx, psi, t0, dt, n_steps, stats, true);
 }
 
 dl_status dirac_lanczos_eigen(dl_context *ctx, const void *psi0, int32_t k_max, int32_t reorth,

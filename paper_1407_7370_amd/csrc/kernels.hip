@@ -101,6 +101,14 @@ void launch_combine(const CombArgs &a, bool mixed, int nblocks, hipStream_t st)
         hipLaunchKernelGGL((k_combine<double2, kCombFp64, kCombWpeFp64>), dim3(nblocks), dim3(kBlock), 0, st, a);
 }
 
+void launch_accum(const AccumArgs &a, bool mixed, int nblocks, hipStream_t st)
+{
+    if (mixed)
+        hipLaunchKernelGGL((k_accum<float2, kCombMixed>), dim3(nblocks), dim3(kBlock), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_accum<double2, kCombFp64>), dim3(nblocks), dim3(kBlock), 0, st, a);
+}
+
 void launch_apply(const Op &op, const Tiles &t, const double2 *x, double2 *y, double gxh,
                   double gyh, hipStream_t st)
 {

@@ -749,6 +749,7 @@ __global__ __launch_bounds__(kBlock) void k_recur(PassArgs a)
     const WaveTask wt = wave_task(a.op, a.t);
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     recur_body<V1, V2, TO, HAS2, PF, PY, TERMS>(a, wt, acc);
+    if (a.replay) return;  // the second run only regenerates u_p
     double tot[5];
     if (!grid_reduce(acc, a.partials, &a.sc->ticket, tot)) return;
     if (threadIdx.x == 0) recur_tail(a, tot);
@@ -1052,6 +1053,61 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE, 8))
     double accv[1] = {nrm}, tot[1];
     if (!grid_reduce(accv, a.partials, &a.sc->ticket, tot)) return;
     if (threadIdx.x == 0) combine_tail(a, tot);
+}
+
+// One recombination term of the second Lanczos run (AccumArgs); the arithmetic
+// per site is that of combine_body, term by term.
+template <class TB, int S>
+__global__ __launch_bounds__(kBlock) void k_accum(AccumArgs a)
+{
+    Scalars *sc = a.sc;
+    if (sc->status != 0) return;
+    const int k = sc->keff;
+    const int p = a.p;
+    if (p > k || k <= 0) return;
+    const size_t sites = a.sites;
+    const size_t tile = (size_t)kBlock * S;
+    constexpr size_t kSite = 2 * sizeof(TB);
+    const double cr = sc->coef[2 * p], ci = sc->coef[2 * p + 1];
+    const char *__restrict__ u = static_cast<const char *>(a.u);
+    double nrm = 0.0;
+    for (size_t s0 = (size_t)blockIdx.x * tile; s0 < sites; s0 += (size_t)gridDim.x * tile) {
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const size_t s = s0 + (size_t)q * kBlock + threadIdx.x;
+            if (s >= sites) continue;
+            Sp acc;
+            if (p == 1) {
+                const double2 p0 = ld_stream(a.psi + s), p1 = ld_stream(a.psi + sites + s);
+                acc.r0 = cr * p0.x - ci * p0.y;
+                acc.i0 = cr * p0.y + ci * p0.x;
+                acc.r1 = cr * p1.x - ci * p1.y;
+                acc.i1 = cr * p1.y + ci * p1.x;
+            } else {
+                const double2 o0 = a.out[s], o1 = a.out[sites + s];
+                const Sp w = to_sp(ld_site<TB>(u + s * kSite));
+                acc.r0 = o0.x + (cr * w.r0 - ci * w.i0);
+                acc.i0 = o0.y + (cr * w.i0 + ci * w.r0);
+                acc.r1 = o1.x + (cr * w.r1 - ci * w.i1);
+                acc.i1 = o1.y + (cr * w.i1 + ci * w.r1);
+            }
+            a.out[s] = make_double2(acc.r0, acc.i0);
+            a.out[sites + s] = make_double2(acc.r1, acc.i1);
+            nrm += sp_norm2(acc);
+        }
+    }
+    if (p != k) return;
+    double accv[1] = {nrm}, tot[1];
+    if (!grid_reduce(accv, a.partials, &sc->ticket, tot)) return;
+    if (threadIdx.x == 0) {
+        a.stat->norm2 = tot[0];
+        if (!isfinite(tot[0])) {
+            sc->status = 3;
+            sc->kstop = -1;
+            return;
+        }
+        sc->steps_done += 1;
+    }
 }
 
 // sites per thread of the recombination and the occupancy asked for (five

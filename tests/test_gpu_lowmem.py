@@ -1,0 +1,87 @@
+"""Memory-saving step (the Lanczos recurrence run a second time instead of
+storing the Krylov basis) against the stored-basis step and the oracle."""
+import numpy as np
+import pytest
+
+import harness as hz
+from paper_1407_7370_amd import packets
+
+pytestmark = pytest.mark.gpu
+
+C = 137.036
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def say(msg):
+    print(f"[gpu case] {msg}", flush=True)
+
+
+def box(nx, ny, bc, **kw):
+    p = dict(nx=nx, ny=ny, x_min=-8.0, x_max=8.0, y_min=-6.0, y_max=6.0, bc_x=bc, bc_y=bc, mass=1.0, c=C,
+             charge=-1.0, bz=0.0, pot_kind=0, pot_z=0.0, pot_a=0.0, pulse_kind=0, pulse_e=(0.0, 0.0), a0=0.0,
+             omega=0.0, t_pulse=1.0, coef=None)
+    p.update(kw)
+    return p
+
+
+CASES = {
+    "laser_b_soft_150x90": dict(box(150, 90, 0, bz=0.6, pot_kind=1, pot_z=1.0, pot_a=1.0), pulse_kind=1,
+                                pulse_e=(0.6, 0.8), a0=40.0, omega=1.0, t_pulse=0.01),
+    "periodic_chiral_128x64": dict(box(128, 64, 1, bz=-0.4), chirality=-1),
+}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_lowmem_vs_stored_basis(torch_cuda, orc, case, prec):
+    from paper_1407_7370_amd.binding import Propagator
+    torch = torch_cuda
+    prob = CASES[case]
+    psi0 = packets.gaussian_packet(prob, 0.8, packets.draw_momentum(5, 4.0), project=True)
+    dt, n, m = 1e-3, 9, 12
+    say(f"lowmem {case} {prec}")
+    prop = Propagator(prob, m, prec)
+    a = torch.from_numpy(psi0).to("cuda")
+    b = torch.from_numpy(psi0).to("cuda")
+    sa = prop.step(a, 0.0, dt, n)
+    sb = prop.step(b, 0.0, dt, n, lowmem=True)
+    prop.close()
+    assert hz.rel_l2(b.cpu().numpy(), a.cpu().numpy()) <= 1e-14
+    assert np.array_equal(sa["k_eff"], sb["k_eff"])
+    np.testing.assert_allclose(sb["err_est"], sa["err_est"], rtol=1e-12, atol=0)
+    np.testing.assert_allclose(sb["norm2"], sa["norm2"], rtol=1e-13)
+    if prec == "fp64":
+        ref, _ = orc.propagate(prob, psi0, 0.0, dt, n, m)
+        assert hz.rel_l2(b.cpu().numpy(), ref) <= 1e-10
+
+
+def test_lowmem_breakdown_and_workspace(torch_cuda):
+    """A lattice plane wave spans a two-dimensional Krylov space (k_eff = 2);
+    a workspace sized for the second-run mode refuses the stored-basis step."""
+    from paper_1407_7370_amd.binding import Propagator, DlError, DL_ERR_WORKSPACE
+    torch = torch_cuda
+    prob = box(64, 48, 1)
+    x, y, hx, hy = hz.axes(prob)
+    X, Y = np.meshgrid(x, y)
+    kx = 2 * np.pi * 3 / 16.0
+    psi0 = np.stack([np.exp(1j * kx * X), np.zeros_like(X, dtype=complex)]).astype(np.complex128)
+    say("lowmem breakdown and workspace")
+    prop = Propagator(prob, 10, "fp64", lowmem=True)
+    a = torch.from_numpy(psi0).to("cuda")
+    st = prop.step(a, 0.0, 1e-3, 3, lowmem=True)
+    assert np.all(st["k_eff"] == 2)
+    with pytest.raises(DlError) as e:
+        prop.step(a, 0.0, 1e-3, 1)
+    assert e.value.status == DL_ERR_WORKSPACE
+    prop.close()
+    full = Propagator(prob, 10, "fp64")
+    b = torch.from_numpy(psi0).to("cuda")
+    full.step(b, 0.0, 1e-3, 3)
+    full.close()
+    assert hz.rel_l2(a.cpu().numpy(), b.cpu().numpy()) <= 1e-14
