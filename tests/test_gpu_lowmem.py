@@ -54,7 +54,8 @@ def test_lowmem_vs_stored_basis(torch_cuda, orc, case, prec):
     prop.close()
     assert hz.rel_l2(b.cpu().numpy(), a.cpu().numpy()) <= 1e-14
     assert np.array_equal(sa["k_eff"], sb["k_eff"])
-    np.testing.assert_allclose(sb["err_est"], sa["err_est"], rtol=1e-12, atol=0)
+    # estimates near 1e-15 are rounding-level numbers: relative agreement is looser
+    np.testing.assert_allclose(sb["err_est"], sa["err_est"], rtol=1e-6, atol=1e-22)
     np.testing.assert_allclose(sb["norm2"], sa["norm2"], rtol=1e-13)
     if prec == "fp64":
         ref, _ = orc.propagate(prob, psi0, 0.0, dt, n, m)
