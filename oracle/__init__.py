@@ -84,6 +84,10 @@ def _load():
                                   ctypes.c_double, ctypes.c_double, ctypes.c_int, D, D,
                                   ctypes.POINTER(ctypes.c_int)]
         lib.orc_eigen.restype = ctypes.c_int
+        lib.orc_eigen_vectors.argtypes = [P, D, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_double, ctypes.c_int, D, D,
+                                          ctypes.POINTER(ctypes.c_int), D]
+        lib.orc_eigen_vectors.restype = ctypes.c_int
         lib.orc_pauli.argtypes = [ctypes.c_int, D]
         lib.orc_expectations.argtypes = [P, D, D]
         _lib = lib
@@ -227,6 +231,25 @@ def eigen(prob: dict, psi0: np.ndarray, k: int, e_lo: float, e_hi: float, tol: f
                          float(e_lo), float(e_hi), float(tol), int(max_out), _dp(ev), _dp(bd),
                          ctypes.byref(nf))
     return ev[:nf.value].copy(), bd[:nf.value].copy(), keff
+
+
+def eigen_vectors(prob: dict, psi0: np.ndarray, k: int, e_lo: float, e_hi: float, tol: float,
+                  max_out: int = 16):
+    """Ritz values, bounds and Ritz vectors (full reorthogonalisation).
+
+    Vector i has shape (2, ny, nx) and the sign that makes <psi0, y_i> real
+    and positive (Sec. 2 eq. eigenvec_approx)."""
+    lib = _load()
+    pb = _Problem(prob)
+    psi0 = _check_psi(prob, psi0)
+    ev = np.zeros(max_out)
+    bd = np.zeros(max_out)
+    vecs = np.zeros((max_out,) + psi0.shape, dtype=np.complex128)
+    nf = ctypes.c_int(0)
+    keff = lib.orc_eigen_vectors(pb.ref, _dp(psi0.view(np.float64)), int(k), float(e_lo), float(e_hi),
+                                 float(tol), int(max_out), _dp(ev), _dp(bd), ctypes.byref(nf),
+                                 _dp(vecs.view(np.float64)))
+    return ev[:nf.value].copy(), bd[:nf.value].copy(), vecs[:nf.value].copy(), keff
 
 
 def pauli(which: int) -> np.ndarray:

@@ -29,6 +29,7 @@
  *                     eq. matrix_exponential_error and its cumulative sum
  *                     (Sec. 6).
  *   orc_eigen         Sec. 2, Ritz values and bound eq. error_est; Sec. 5.
+ *   orc_eigen_vectors Sec. 2 eq. eigenvec_approx (Ritz vectors, full reorth).
  *
  * Readings where the paper is silent (shared with the GPU library only as
  * written conventions, never as code):
@@ -451,6 +452,30 @@ int orc_propagate(const orc_params *p, double *psi_d, double t0, double dt, int 
 }
 
 /*
+ * Ritz vector y = sum_j t_j q_j (Sec. 2 eq. eigenvec_approx) of the
+ * eigenvector t = column l of V (keff x keff, row-major).  The sign of t is
+ * fixed so that t_1 = <q_1, y> > 0 (the overlap with the start vector is real
+ * and positive); a zero t_1 takes the sign of the component of largest
+ * magnitude instead.  A Ritz vector of a simple Ritz value is unique up to
+ * that sign.
+ */
+static void ritz_vector(size_t n, int keff, const double *Q_d, const double *V, int l, cplx *y)
+{
+    const cplx *Q = (const cplx *)Q_d;
+    int lead = 0;
+    for (int j = 1; j < keff; ++j)
+        if (fabs(V[j * keff + l]) > fabs(V[lead * keff + l])) lead = j;
+    const double piv = V[l] != 0.0 ? V[l] : V[lead * keff + l];
+    const double sgn = piv < 0.0 ? -1.0 : 1.0;
+    for (size_t t = 0; t < n; ++t) y[t] = 0.0;
+    for (int j = 0; j < keff; ++j) {
+        const double tj = sgn * V[j * keff + l];
+        const cplx *qj = Q + (size_t)j * n;
+        for (size_t t = 0; t < n; ++t) y[t] += tj * qj[t];
+    }
+}
+
+/*
  * Eigenvalue mode (Sec. 2 eq. A_approx / error_est, Sec. 5): k Lanczos
  * iterations on H (dt = 1, fields at t = 0) from psi0, optionally with full
  * reorthogonalisation applied twice.  The Ritz values of T_k in [e_lo, e_hi]
@@ -462,17 +487,18 @@ int orc_propagate(const orc_params *p, double *psi_d, double t0, double dt, int 
  * <= tol are reported, ascending, as their mean value.  Returns k_eff; the
  * number reported (at most max_out) goes to n_found.
  */
-int orc_eigen(const orc_params *p, const double *psi0, int k, int reorth, double e_lo, double e_hi,
-              double tol, int max_out, double *evals_out, double *bounds_out, int *n_found)
+static int eigen_core(const orc_params *p, const double *psi0, int k, int reorth, double e_lo, double e_hi,
+                      double tol, int max_out, double *evals_out, double *bounds_out, int *n_found,
+                      double *vecs_out)
 {
     const size_t n = (size_t)2 * p->nx * p->ny;
     double *Q = (double *)malloc(n * (size_t)k * sizeof(cplx));
     double *alpha = (double *)malloc(sizeof(double) * k), *beta = (double *)malloc(sizeof(double) * k);
     const double zero[2] = {0.0, 0.0};
     const int keff = orc_lanczos(p, zero, 1.0, psi0, k, reorth, Q, alpha, beta);
-    free(Q);
     *n_found = 0;
     if (keff == 0) {
+        free(Q);
         free(alpha);
         free(beta);
         return 0;
@@ -483,50 +509,78 @@ int orc_eigen(const orc_params *p, const double *psi0, int k, int reorth, double
     /* candidates in the window, with their last eigenvector components */
     int nc = 0;
     double *cv = (double *)malloc(sizeof(double) * keff), *ct = (double *)malloc(sizeof(double) * keff);
+    int *cl = (int *)malloc(sizeof(int) * keff);
     for (int l = 0; l < keff; ++l) {
         if (ev[l] >= e_lo && ev[l] <= e_hi) {
             cv[nc] = ev[l];
             ct[nc] = V[(keff - 1) * keff + l];
+            cl[nc] = l;
             ++nc;
         }
     }
     /* sort ascending (insertion sort) */
     for (int a = 1; a < nc; ++a) {
         const double v = cv[a], t = ct[a];
+        const int li = cl[a];
         int c = a - 1;
         while (c >= 0 && cv[c] > v) {
             cv[c + 1] = cv[c];
             ct[c + 1] = ct[c];
+            cl[c + 1] = cl[c];
             --c;
         }
         cv[c + 1] = v;
         ct[c + 1] = t;
+        cl[c + 1] = li;
     }
     int nf = 0;
     for (int a = 0; a < nc;) {
         int b = a + 1;
         while (b < nc && cv[b] - cv[b - 1] <= tol) ++b;
         double sum = 0.0, t2 = 0.0;
+        int rep = a;
         for (int c = a; c < b; ++c) {
             sum += cv[c];
             t2 += ct[c] * ct[c];
+            if (fabs(ct[c]) < fabs(ct[rep])) rep = c;
         }
         const double bound = fabs(beta[keff - 1]) * sqrt(t2);
         if (bound <= tol && nf < max_out) {
             evals_out[nf] = sum / (b - a);
             bounds_out[nf] = bound;
+            if (vecs_out) ritz_vector(n, keff, Q, V, cl[rep], (cplx *)vecs_out + (size_t)nf * n);
             ++nf;
         }
         a = b;
     }
     *n_found = nf;
+    free(cl);
     free(cv);
     free(ct);
     free(ev);
     free(V);
+    free(Q);
     free(alpha);
     free(beta);
     return keff;
+}
+
+int orc_eigen(const orc_params *p, const double *psi0, int k, int reorth, double e_lo, double e_hi,
+              double tol, int max_out, double *evals_out, double *bounds_out, int *n_found)
+{
+    return eigen_core(p, psi0, k, reorth, e_lo, e_hi, tol, max_out, evals_out, bounds_out, n_found, NULL);
+}
+
+/*
+ * Ritz vectors (Sec. 2 eq. eigenvec_approx) of the values orc_eigen reports,
+ * with full reorthogonalisation (the stored q_j are then orthonormal and
+ * y = Q_k t is a unit vector).  vecs_out receives max_out vectors of
+ * n = 2*nx*ny complex values.
+ */
+int orc_eigen_vectors(const orc_params *p, const double *psi0, int k, double e_lo, double e_hi, double tol,
+                      int max_out, double *evals_out, double *bounds_out, int *n_found, double *vecs_out)
+{
+    return eigen_core(p, psi0, k, 1, e_lo, e_hi, tol, max_out, evals_out, bounds_out, n_found, vecs_out);
 }
 
 /*

@@ -387,6 +387,47 @@ def test_eigen_small_dense(orc):
     assert np.allclose(ev, w, atol=1e-8 * np.abs(w).max())
 
 
+def test_ritz_vectors_small_dense(orc):
+    """With k = dim the Ritz vectors (eq. eigenvec_approx) are the dense
+    eigenvectors, in the sign convention <psi0, y> > 0."""
+    prob = small_prob(8, 8, 0, bz=1.0, pot_kind=1, lo=-4, hi=4)
+    H = hz.dense_h(prob).toarray()
+    w, U = np.linalg.eigh(H)
+    psi0 = packets.random_spinor(prob, 2)
+    ev, bd, Y, keff = orc.eigen_vectors(prob, psi0, 128, -1e9, 1e9, 1e-6, max_out=256)
+    assert keff == 128 and len(ev) == 128
+    assert np.allclose(ev, w, atol=1e-8 * np.abs(w).max())
+    b = psi0.reshape(-1)
+    for i in range(128):
+        u = U[:, i]
+        ph = np.vdot(b, u)
+        u = u * (np.conj(ph) / abs(ph))
+        y = Y[i].reshape(-1)
+        assert np.linalg.norm(y - u) <= 1e-8, i
+        ov = np.vdot(b, y)
+        assert ov.real > 0 and abs(ov.imag) <= 1e-10 * ov.real
+
+
+def test_ritz_vectors_residual_identity(orc):
+    """Full reorthogonalisation keeps Q orthonormal, so for a simple Ritz pair
+    ||H y - theta y|| = |beta_k t_k| (the bound of eq. error_est) and the Ritz
+    vectors are orthonormal; H from the independent sparse assembly."""
+    prob = small_prob(20, 20, 0, bz=0.7, pot_kind=1, c=5.0, lo=-4, hi=4)
+    H = hz.dense_h(prob)
+    psi0 = packets.random_spinor(prob, 5)
+    ev, bd, Y, keff = orc.eigen_vectors(prob, psi0, 140, -1e9, 1e9, 1e-4, max_out=64)
+    assert keff == 140 and len(ev) >= 8
+    # a spread of bounds, so that the identity is checked far above rounding
+    assert bd.max() >= 1e-7
+    M = Y.reshape(len(ev), -1)
+    assert np.allclose(M.conj() @ M.T, np.eye(len(ev)), atol=1e-10)
+    for th, b, y in zip(ev, bd, M):
+        r = np.linalg.norm(H @ y - th * y)
+        assert abs(r - b) <= 1e-6 * b + 1e-12, (th, r, b)
+    ov = M.conj() @ psi0.reshape(-1)
+    assert np.all(ov.real > 0) and np.all(np.abs(ov.imag) <= 1e-10 * ov.real)
+
+
 # ---------------------------------------------------------------------------
 # Observables of the adjoint loss
 # ---------------------------------------------------------------------------
