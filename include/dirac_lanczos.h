@@ -59,7 +59,7 @@ enum { DL_BC_DIRICHLET = 0, DL_BC_PERIODIC = 1 };
 enum { DL_PREC_FP64 = 0, DL_PREC_MIXED = 1 };
 enum { DL_POT_NONE = 0, DL_POT_SOFTCORE = 1, DL_POT_PAPER_SOFTCORE = 2 };
 enum { DL_PULSE_NONE = 0, DL_PULSE_SIN_SIN2 = 1, DL_PULSE_FOURIER_SIN2 = 2 };
-enum { DL_MODE_STEP = 0, DL_MODE_EIGEN = 1, DL_MODE_LOWMEM = 2 };
+enum { DL_MODE_STEP = 0, DL_MODE_EIGEN = 1, DL_MODE_LOWMEM = 2, DL_MODE_EIGEN_REORTH = 3 };
 
 /*
  * Problem description (Sec. 3 Hamiltonian, Sec. 7 grid).
@@ -119,7 +119,10 @@ typedef struct {
  * mode DL_MODE_STEP: for step/apply (the stored Krylov basis, m - 1 vectors);
  * DL_MODE_LOWMEM: for step_lowmem/apply (three Krylov vectors);
  * DL_MODE_EIGEN: additionally for eigen() with up to k_eigen Lanczos
- * iterations.  init accepts the smaller of the STEP and LOWMEM sizes; every
+ * iterations; DL_MODE_EIGEN_REORTH: additionally for eigen() with full
+ * reorthogonalisation and eigen_vectors() with up to k_eigen iterations
+ * (k_eigen stored complex128 vectors, about k_eigen * 32 * nx * ny bytes).
+ * init accepts the smaller of the STEP and LOWMEM sizes; every
  * call checks the size it needs (DL_ERR_WORKSPACE).  Returns 0 for invalid
  * parameters.  The workspace must be 256-byte aligned.
  */
@@ -195,19 +198,43 @@ dl_status dirac_lanczos_step_adaptive(dl_context *ctx, void *psi, double t0, dou
                                       double *dt_taken, dl_adapt_stat *out);
 
 /*
- * Eigenvalue mode (Sec. 2 eq. A_approx, eq. error_est; Sec. 5): k_max plain
+ * Eigenvalue mode (Sec. 2 eq. A_approx, eq. error_est; Sec. 5): k_max
  * Lanczos iterations on H (static fields, laser off) from psi0 (DEVICE).
  * Ritz values of T in [e_lo, e_hi] are grouped into clusters of neighbours
  * closer than tol; a cluster whose bound beta_k ||last components of its
  * eigenvectors|| is <= tol is reported as its mean.  Up to n_wanted values go
  * to evals/bounds (HOST arrays of n_wanted doubles), ascending; *n_found
- * receives the count.  reorth != 0 (full reorthogonalisation) returns
- * DL_ERR_UNSUPPORTED.  Needs a workspace sized for DL_MODE_EIGEN with
- * k_eigen >= k_max.  Synchronous.
+ * receives the count.  reorth == 0: the plain three-term recurrence in the
+ * fused sweep order, three rolling vectors, a workspace sized for
+ * DL_MODE_EIGEN with k_eigen >= k_max.  reorth != 0: full
+ * reorthogonalisation applied twice (Sec. 2), as classical Gram-Schmidt
+ * against all stored vectors (h = Q^H z, z -= Q h, two passes; the first
+ * pass also removes the alpha_i q_i and beta_{i-1} q_{i-1} terms of the
+ * recurrence, alpha_i = Re h_i of that pass), a workspace sized for
+ * DL_MODE_EIGEN_REORTH with k_eigen >= k_max.  A start vector of norm 0
+ * reports nothing; a breakdown (beta_i <= 1e-13 max(|alpha_j|, beta_{j-1}))
+ * ends the recurrence at k = i.  DL_ERR_NONFINITE for a non-finite
+ * reduction.  Synchronous.
  */
 dl_status dirac_lanczos_eigen(dl_context *ctx, const void *psi0, int32_t k_max, int32_t reorth,
                               double e_lo, double e_hi, double tol, int32_t n_wanted,
                               double *evals, double *bounds, int32_t *n_found);
+
+/*
+ * Ritz vectors (Sec. 2 eq. eigenvec_approx): dirac_lanczos_eigen with
+ * reorth != 0, plus for every reported value the Ritz vector y = Q_k t, t the
+ * eigenvector of T_k of the cluster member with the smallest bound
+ * |beta_k t_k|.  With the stored vectors orthonormal, ||y|| = 1 and
+ * ||H y - theta y|| = |beta_k t_k| (eq. error_est) up to rounding.  The sign
+ * of t makes <psi0, y> real and positive (a Ritz vector of a simple value is
+ * unique up to that sign).  vecs: DEVICE, n_wanted vectors of 2 * nx * ny
+ * complex128 in the state layout, vector i at vecs + i * 32 * nx * ny bytes;
+ * only the first *n_found are written.  Workspace as for reorth != 0.
+ * Synchronous.
+ */
+dl_status dirac_lanczos_eigen_vectors(dl_context *ctx, const void *psi0, int32_t k_max, double e_lo,
+                                      double e_hi, double tol, int32_t n_wanted, double *evals,
+                                      double *bounds, int32_t *n_found, void *vecs);
 
 /*
  * Adjoint (gradient) mode: the derivative of a final observable with respect

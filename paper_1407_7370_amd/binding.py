@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libdirac_lanczos.so")
 
 DL_OK, DL_ERR_INVALID, DL_ERR_DEVICE, DL_ERR_NONFINITE, DL_ERR_WORKSPACE, DL_ERR_UNSUPPORTED = range(6)
 DL_PREC_FP64, DL_PREC_MIXED = 0, 1
-DL_MODE_STEP, DL_MODE_EIGEN, DL_MODE_LOWMEM = 0, 1, 2
+DL_MODE_STEP, DL_MODE_EIGEN, DL_MODE_LOWMEM, DL_MODE_EIGEN_REORTH = 0, 1, 2, 3
 STATUS_NAMES = {0: "DL_OK", 1: "DL_ERR_INVALID", 2: "DL_ERR_DEVICE", 3: "DL_ERR_NONFINITE",
                 4: "DL_ERR_WORKSPACE", 5: "DL_ERR_UNSUPPORTED"}
 
@@ -28,7 +28,7 @@ EXPORTS = ("dirac_lanczos_workspace_bytes", "dirac_lanczos_init", "dirac_lanczos
            "dirac_lanczos_last_error", "dirac_lanczos_batch_workspace_bytes", "dirac_lanczos_batch_init",
            "dirac_lanczos_batch_step", "dirac_lanczos_batch_destroy", "dirac_lanczos_batch_last_error",
            "dirac_lanczos_set_launch", "dirac_lanczos_batch_set_launch", "dirac_lanczos_step_adaptive",
-           "dirac_lanczos_step_lowmem")
+           "dirac_lanczos_step_lowmem", "dirac_lanczos_eigen_vectors")
 DL_LOSS_X, DL_LOSS_Y, DL_LOSS_PX, DL_LOSS_PY = 1, 2, 4, 8
 
 
@@ -104,6 +104,10 @@ def load_library():
                                         ctypes.c_double, ctypes.c_double, ctypes.c_int32, D, D,
                                         ctypes.POINTER(ctypes.c_int32)]
     lib.dirac_lanczos_eigen.restype = ctypes.c_int
+    lib.dirac_lanczos_eigen_vectors.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                                ctypes.c_double, ctypes.c_int32, D, D,
+                                                ctypes.POINTER(ctypes.c_int32), vp]
+    lib.dirac_lanczos_eigen_vectors.restype = ctypes.c_int
     lib.dirac_lanczos_adjoint_workspace_bytes.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
     lib.dirac_lanczos_adjoint_workspace_bytes.restype = ctypes.c_size_t
     lib.dirac_lanczos_adjoint.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
@@ -205,6 +209,13 @@ def dirac_lanczos_eigen(ctx, psi_ptr: int, k_max: int, reorth: int, e_lo: float,
                                               tol, n_wanted, evals, bounds, n_found)
 
 
+def dirac_lanczos_eigen_vectors(ctx, psi_ptr: int, k_max: int, e_lo: float, e_hi: float, tol: float,
+                                n_wanted: int, evals, bounds, n_found, vecs_ptr: int) -> int:
+    return load_library().dirac_lanczos_eigen_vectors(ctx, ctypes.c_void_p(psi_ptr), k_max, e_lo, e_hi, tol,
+                                                      n_wanted, evals, bounds, n_found,
+                                                      ctypes.c_void_p(vecs_ptr))
+
+
 def dirac_lanczos_adjoint_workspace_bytes(params: DlParams, n_steps: int, ckpt_every: int) -> int:
     return int(load_library().dirac_lanczos_adjoint_workspace_bytes(ctypes.byref(params), n_steps,
                                                                      ckpt_every))
@@ -268,7 +279,7 @@ class Propagator:
     """
 
     def __init__(self, problem: dict, krylov_dim: int, precision: str = "fp64", k_eigen: int = 0,
-                 stream=None, v_table=None, tuning_cache=None, lowmem: bool = False):
+                 stream=None, v_table=None, tuning_cache=None, lowmem: bool = False, reorth: bool = False):
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -280,7 +291,10 @@ class Propagator:
             self.v_table = torch.as_tensor(v_table, dtype=torch.float64, device="cuda").contiguous()
             vptr = self.v_table.data_ptr()
         self.params, self._keep = make_params(problem, krylov_dim, self.prec, vptr)
-        mode = DL_MODE_EIGEN if k_eigen > 0 else (DL_MODE_LOWMEM if lowmem else DL_MODE_STEP)
+        if k_eigen > 0:
+            mode = DL_MODE_EIGEN_REORTH if reorth else DL_MODE_EIGEN
+        else:
+            mode = DL_MODE_LOWMEM if lowmem else DL_MODE_STEP
         nbytes = dirac_lanczos_workspace_bytes(self.params, mode, k_eigen)
         if nbytes == 0:
             raise DlError(DL_ERR_INVALID, "invalid parameters (workspace_bytes returned 0)")
@@ -354,6 +368,21 @@ class Propagator:
                                  n_wanted, ev, bd, ctypes.byref(nf))
         _check(self.lib, self.ctx, st)
         return np.array(ev[:nf.value]), np.array(bd[:nf.value])
+
+    def eigen_vectors(self, psi0, k_max: int, e_lo: float, e_hi: float, tol: float, n_wanted: int = 16):
+        """Ritz values, bounds and Ritz vectors (full reorthogonalisation; the
+        context needs k_eigen >= k_max and reorth=True).  Vectors: complex128
+        tensor (n_found, 2, ny, nx), <psi0, y> real and positive."""
+        self._check_psi(psi0)
+        ev = (ctypes.c_double * n_wanted)()
+        bd = (ctypes.c_double * n_wanted)()
+        nf = ctypes.c_int32(0)
+        vecs = self.torch.zeros((n_wanted,) + self.shape, dtype=self.torch.complex128, device="cuda")
+        st = dirac_lanczos_eigen_vectors(self.ctx, psi0.data_ptr(), k_max, e_lo, e_hi, tol, n_wanted, ev, bd,
+                                         ctypes.byref(nf), vecs.data_ptr())
+        _check(self.lib, self.ctx, st)
+        k = nf.value
+        return np.array(ev[:k]), np.array(bd[:k]), vecs[:k]
 
     def adjoint(self, psi0, t0: float, dt: float, n_steps: int, ckpt_every: int, loss_kind: int):
         """Loss (sum of the final expectations selected by loss_kind) and its

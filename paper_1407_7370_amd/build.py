@@ -4,6 +4,7 @@ Usage: python -m paper_1407_7370_amd.build   (or call build()).
 """
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import subprocess
 import sys
@@ -13,7 +14,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libdirac_lanczos.so")
-SOURCES = ["kernels.hip", "batch_kernels.hip", "adjoint_kernels.hip", "host.cpp", "batch.cpp", "adjoint.cpp", "adaptive.cpp"]
+SOURCES = ["kernels.hip", "batch_kernels.hip", "adjoint_kernels.hip", "host.cpp", "batch.cpp", "adjoint.cpp", "adaptive.cpp",
+           "eigen_kernels.hip", "eigen.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -25,16 +27,21 @@ FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
-    objs = []
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
-    for src in SOURCES:
-        obj = os.path.join(bdir, src + ".o")
-        cmd = [HIPCC, *FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
+    objs = [os.path.join(bdir, src + ".o") for src in SOURCES]
+
+    def compile_one(i):
+        cmd = [HIPCC, *FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, SOURCES[i]), "-o", objs[i]]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
-        objs.append(obj)
+
+    # translation units compile independently; a few at a time
+    jobs = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1)), 8))
+    with concurrent.futures.ThreadPoolExecutor(jobs) as pool:
+        for f in [pool.submit(compile_one, i) for i in range(len(SOURCES))]:
+            f.result()
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:

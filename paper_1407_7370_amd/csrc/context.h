@@ -25,6 +25,34 @@ inline size_t vec_elems(const dl_params &p) { return (size_t)2 * (size_t)p.nx * 
 inline size_t vec_stride(size_t n, size_t elem) { return align256(n * elem) + dl::kVecPad; }
 
 Layout plan(const dl_params &p, int mode, int k_eigen);
+
+// Vector region of the eigen mode with full reorthogonalisation (offsets from
+// Layout::vecs): z, the k stored complex128 basis vectors, the two projection
+// coefficient arrays (k complex each), the projection partial table and the
+// staged eigenvector columns of the Ritz vectors.
+struct ReorthLayout {
+    size_t z = 0, q = 0, h1 = 0, h2 = 0, pproj = 0, tsel = 0, total = 0;
+};
+inline ReorthLayout reorth_layout(size_t n, int k)
+{
+    ReorthLayout R;
+    const size_t vs = vec_stride(n, 16);
+    size_t off = 0;
+    R.z = off;
+    off += vs;
+    R.q = off;
+    off += (size_t)k * vs;
+    R.h1 = off;
+    off += align256(sizeof(double) * 2 * (size_t)k);
+    R.h2 = off;
+    off += align256(sizeof(double) * 2 * (size_t)k);
+    R.pproj = off;
+    off += align256(sizeof(double) * 2 * (size_t)dl::proj_tiles(n) * (size_t)k);
+    R.tsel = off;
+    off += align256(sizeof(double) * (size_t)dl::kRitzVecs * (size_t)k);
+    R.total = off;
+    return R;
+}
 const char *validate(const dl_params *p);
 void pulse_now(const dl_params &p, const std::vector<double> &coef, double t, double *a);
 void pulse_average(const dl_params &p, const std::vector<double> &coef, double t0, double dt, double *a);
@@ -36,6 +64,14 @@ void tridiag_last_row(std::vector<double> d, std::vector<double> e, std::vector<
 // Eigenvalues and all eigenvectors (column l of v, row-major k x k).
 void tridiag_full(std::vector<double> d, std::vector<double> e, std::vector<double> &lam,
                   std::vector<double> &v);
+
+// Ritz values of T (eigenvalues lam, last eigenvector components zl) in
+// [e_lo, e_hi], grouped into clusters of neighbours closer than tol; a
+// cluster with bound |beta_k| ||zl over the cluster|| <= tol is reported as its
+// mean (at most n_wanted, ascending).  rep (optional) receives, per reported
+// cluster, the index of its member with the smallest |zl|.  Returns the count.
+int ritz_select(const std::vector<double> &lam, const std::vector<double> &zl, double beta_k, double e_lo,
+                double e_hi, double tol, int n_wanted, double *evals, double *bounds, std::vector<int> *rep);
 
 // Sign of the sigma2 terms: alpha2 = chir * sigma2.
 inline double chir(const dl_params &p) { return p.chirality < 0 ? -1.0 : 1.0; }
@@ -188,5 +224,10 @@ dl_status run_twice(dl_context *ctx, const Engine &e, const dl::Op &op, const do
 // exp(-iT) and the recombination into `out` (stat receives k_eff, estimate, norm).
 dl_status run_finish(dl_context *ctx, const Engine &e, const double2 *in, double2 *out,
                      dl::StepStat *stat, double *partials);
+
+// Eigen mode with full reorthogonalisation (eigen.cpp); vecs (device, may be
+// NULL) receives the Ritz vectors of the reported values.
+dl_status eigen_reorth(dl_context *ctx, const void *psi0, int k_max, double e_lo, double e_hi, double tol,
+                       int n_wanted, double *evals, double *bounds, int32_t *n_found, void *vecs);
 
 }  // namespace dlh

@@ -230,4 +230,32 @@ int combine_grid(size_t sites, bool mixed, int cus);
 int sweep_waves_per_cu(int which, bool mixed, bool py, int terms);
 int sweep_terms(const Op &op);
 
+// Eigen mode with full reorthogonalisation (eigen_kernels.hip).  Stored
+// complex128 vectors q_1..q_K at q + (j-1) * vstride; the projection partial
+// table holds 2 * proj_tiles(n) doubles per vector.
+constexpr int kProjTiles = 1024;  // workgroups per vector chunk of a projection (cap)
+constexpr int kRitzVecs = 16;     // Ritz vectors formed per pass over the basis
+inline int proj_tiles(size_t nelem)
+{
+    const size_t t = (nelem + kBlock - 1) / kBlock;
+    return (int)(t < (size_t)kProjTiles ? (t < 1 ? 1 : t) : (size_t)kProjTiles);
+}
+// h = Q[0..nvec)^H z (complex, fixed-order reduction).
+void launch_proj(const char *q, size_t vstride, int nvec, const double2 *z, size_t nelem, double *pproj,
+                 double *h, hipStream_t st);
+// z -= Q[0..nvec) h.
+void launch_sub_q(const char *q, size_t vstride, int nvec, const double *h, double2 *z, size_t nelem,
+                  int nblocks, hipStream_t st);
+// beta_0 = ||psi||, q_1 = psi / beta_0 (kstop = 0 when psi = 0).
+void launch_first_q(const double2 *psi, size_t nelem, double2 *q1, Scalars *sc, double *beta, double *partials,
+                    int nblocks, hipStream_t st);
+// beta_i = ||z||, alpha_i = Re h1_i, breakdown test; then q_{i+1} = z / beta_i
+// when i < k and the recurrence goes on.
+void launch_norm_next(const double2 *z, size_t nelem, const double *h1, int i, int k, double *alpha, double *beta,
+                      Scalars *sc, double *partials, double2 *qn, int nblocks, hipStream_t st);
+// Y[:, v] = Q[0..nvec) t[:, v] for v < r <= kRitzVecs (t: nvec x kRitzVecs
+// row-major, real), y_v at y + v * nelem.
+void launch_ritz(const char *q, size_t vstride, int nvec, const double *t, int r, double2 *y, size_t nelem,
+                 int nblocks, hipStream_t st);
+
 }  // namespace dl

@@ -32,7 +32,8 @@ Layout plan(const dl_params &p, int mode, int k_eigen)
 {
     Layout L;
     const int m = p.krylov_dim;
-    L.ab_len = std::max(m, mode == DL_MODE_EIGEN ? k_eigen + 1 : 0) + 3;
+    const bool eig = mode == DL_MODE_EIGEN || mode == DL_MODE_EIGEN_REORTH;
+    L.ab_len = std::max(m, eig ? k_eigen + 1 : 0) + 3;
     size_t off = 0;
     L.sc = off;
     off = align256(off + sizeof(dl::Scalars));
@@ -54,6 +55,7 @@ Layout plan(const dl_params &p, int mode, int k_eigen)
     const size_t nbasis = mode == DL_MODE_LOWMEM ? (size_t)std::min(m - 1, 3) : (size_t)(m - 1);
     size_t step_region = align256(n * 16) + nbasis * vec_stride(n, basis_elem);
     size_t eig_region = mode == DL_MODE_EIGEN ? 3 * vec_stride(n, 16) : 0;
+    if (mode == DL_MODE_EIGEN_REORTH) eig_region = reorth_layout(n, k_eigen).total;
     off += std::max(step_region, eig_region);
     L.total = off;
     return L;
@@ -288,6 +290,37 @@ void tridiag_full(std::vector<double> d, std::vector<double> e, std::vector<doub
     lam = d;
 }
 
+int ritz_select(const std::vector<double> &lam, const std::vector<double> &zl, double beta_k, double e_lo,
+                double e_hi, double tol, int n_wanted, double *evals, double *bounds, std::vector<int> *rep)
+{
+    // candidates in the window, ascending, with their index into lam
+    std::vector<int> cand;
+    for (int i = 0; i < (int)lam.size(); ++i)
+        if (lam[i] >= e_lo && lam[i] <= e_hi) cand.push_back(i);
+    std::sort(cand.begin(), cand.end(), [&](int a, int b) { return lam[a] < lam[b]; });
+    int nf = 0;
+    for (size_t a = 0; a < cand.size();) {
+        size_t b = a + 1;
+        while (b < cand.size() && lam[cand[b]] - lam[cand[b - 1]] <= tol) ++b;
+        double sum = 0.0, t2s = 0.0;
+        int best = cand[a];
+        for (size_t c = a; c < b; ++c) {
+            sum += lam[cand[c]];
+            t2s += zl[cand[c]] * zl[cand[c]];
+            if (std::fabs(zl[cand[c]]) < std::fabs(zl[best])) best = cand[c];
+        }
+        const double bound = std::fabs(beta_k) * std::sqrt(t2s);
+        if (bound <= tol && nf < n_wanted) {
+            evals[nf] = sum / (double)(b - a);
+            bounds[nf] = bound;
+            if (rep) rep->push_back(best);
+            ++nf;
+        }
+        a = b;
+    }
+    return nf;
+}
+
 dl_status run_build(dl_context *ctx, const Engine &e, const dl::Op &op, const double2 *in,
                     const double *field, double *partials, int shift)
 {
@@ -434,9 +467,11 @@ extern "C" {
 size_t dirac_lanczos_workspace_bytes(const dl_params *params, int32_t mode, int32_t k_eigen)
 {
     if (validate(params)) return 0;
-    if (mode != DL_MODE_STEP && mode != DL_MODE_EIGEN && mode != DL_MODE_LOWMEM) return 0;
-    if (mode == DL_MODE_EIGEN && (k_eigen < 1 || k_eigen > 1000000)) return 0;
-    return plan(*params, mode, mode == DL_MODE_EIGEN ? k_eigen : 0).total;
+    if (mode != DL_MODE_STEP && mode != DL_MODE_EIGEN && mode != DL_MODE_LOWMEM && mode != DL_MODE_EIGEN_REORTH)
+        return 0;
+    const bool eig = mode == DL_MODE_EIGEN || mode == DL_MODE_EIGEN_REORTH;
+    if (eig && (k_eigen < 1 || k_eigen > 1000000)) return 0;
+    return plan(*params, mode, eig ? k_eigen : 0).total;
 }
 
 dl_status dirac_lanczos_init(const dl_params *params, void *workspace, size_t ws_bytes,
@@ -644,7 +679,7 @@ dl_status dirac_lanczos_eigen(dl_context *ctx, const void *psi0, int32_t k_max, 
         !(e_hi >= e_lo))
         return ctx->fail(DL_ERR_INVALID, "invalid eigen arguments");
     *n_found = 0;
-    if (reorth) return ctx->fail(DL_ERR_UNSUPPORTED, "full reorthogonalisation is not provided on the GPU");
+    if (reorth) return eigen_reorth(ctx, psi0, k_max, e_lo, e_hi, tol, n_wanted, evals, bounds, n_found, nullptr);
     const dl_params &p = ctx->p;
     const Layout E = plan(p, DL_MODE_EIGEN, k_max);
     if (ctx->ws_bytes < E.total)
@@ -704,30 +739,7 @@ dl_status dirac_lanczos_eigen(dl_context *ctx, const void *psi0, int32_t k_max, 
     for (int j = 0; j + 1 < k; ++j) e[j] = hg[j + 2];
     const double beta_k = hg[k + 1];
     tridiag_last_row(d, e, lam, zl);
-    std::vector<std::pair<double, double>> cand;
-    for (int i = 0; i < k; ++i)
-        if (lam[i] >= e_lo && lam[i] <= e_hi) cand.push_back({lam[i], zl[i]});
-    std::sort(cand.begin(), cand.end(),
-              [](const std::pair<double, double> &a, const std::pair<double, double> &b) {
-                  return a.first < b.first;
-              });
-    int nf = 0;
-    for (size_t a = 0; a < cand.size();) {
-        size_t b = a + 1;
-        while (b < cand.size() && cand[b].first - cand[b - 1].first <= tol) ++b;
-        double sum = 0.0, t2s = 0.0;
-        for (size_t c = a; c < b; ++c) {
-            sum += cand[c].first;
-            t2s += cand[c].second * cand[c].second;
-        }
-        const double bound = std::fabs(beta_k) * std::sqrt(t2s);
-        if (bound <= tol && nf < n_wanted) {
-            evals[nf] = sum / (double)(b - a);
-            bounds[nf] = bound;
-            ++nf;
-        }
-        a = b;
-    }
+    const int nf = ritz_select(lam, zl, beta_k, e_lo, e_hi, tol, n_wanted, evals, bounds, nullptr);
     *n_found = nf;
     return DL_OK;
 }

@@ -73,6 +73,14 @@ def test_workspace_bytes_plan():
     p1 = _params(small, 1, binding.DL_PREC_FP64)
     assert binding.dirac_lanczos_workspace_bytes(p1, binding.DL_MODE_EIGEN, 100) >= 3 * 2 * 64 * 64 * 16
     assert binding.dirac_lanczos_workspace_bytes(p1, binding.DL_MODE_EIGEN, 0) == 0
+    # full reorthogonalisation: z plus k stored complex128 vectors, growing with k
+    nv = 2 * 64 * 64 * 16
+    r100 = binding.dirac_lanczos_workspace_bytes(p1, binding.DL_MODE_EIGEN_REORTH, 100)
+    r200 = binding.dirac_lanczos_workspace_bytes(p1, binding.DL_MODE_EIGEN_REORTH, 200)
+    assert 101 * nv <= r100 <= 101 * (nv + 8192) + (8 << 20)
+    assert r200 - r100 >= 100 * nv
+    assert binding.dirac_lanczos_workspace_bytes(p1, binding.DL_MODE_EIGEN_REORTH, 0) == 0
+    assert binding.dirac_lanczos_workspace_bytes(p1, 4, 10) == 0
 
 
 @pytest.mark.parametrize("bad", [
