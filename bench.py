@@ -102,6 +102,36 @@ def run_precision(torch, Propagator, cfg, psi0_dev, precision, steps, warmup, co
     return psi, stats, wall, timing, wall_ev, same
 
 
+def run_lowmem(torch, Propagator, cfg, psi0_dev, steps):
+    """The memory-saving step (second Lanczos run, three rolling Krylov
+    vectors) on the same workload and precision as the headline, against the
+    stored-basis step over the same steps."""
+    from paper_1407_7370_amd.binding import dirac_lanczos_workspace_bytes, DL_MODE_LOWMEM, DL_MODE_STEP
+    prob, m, dt = cfg["problem"], cfg["m"], cfg["dt"]
+    sites = prob["nx"] * prob["ny"]
+    prop = Propagator(prob, m, "mixed", tuning_cache=True)
+    ws_low = dirac_lanczos_workspace_bytes(prop.params, DL_MODE_LOWMEM, 0)
+    ws_full = dirac_lanczos_workspace_bytes(prop.params, DL_MODE_STEP, 0)
+    ref = psi0_dev.clone()
+    prop.step(ref, 0.0, dt, steps, want_stats=False)
+    psi = psi0_dev.clone()
+    prop.step(psi, 0.0, dt, 1, want_stats=False, lowmem=True)
+    psi.copy_(psi0_dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prop.step(psi, 0.0, dt, steps, want_stats=False, lowmem=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prop.close()
+    err = float(torch.linalg.vector_norm(psi - ref) / torch.linalg.vector_norm(ref))
+    log(f"lowmem: {wall * 1e3 / steps:.3f} ms/step, workspace {ws_low / 2**30:.2f} GiB vs "
+        f"{ws_full / 2**30:.2f} GiB stored basis, rel-L2 vs stored basis {err:.1e}")
+    return {"what": "second Lanczos run instead of the stored basis (mixed, same workload)", "steps": steps,
+            "ms_per_step": wall * 1e3 / steps, "value": sites * m * steps / wall, "unit": "site-matvecs/s",
+            "workspace_bytes": ws_low, "stored_basis_workspace_bytes": ws_full,
+            "rel_l2_vs_stored_basis": err}
+
+
 def run_batch(torch, packets, steps):
     """The 256-packet batch (grids 128^2..512^2, B_z ~ U[0,2], mixed, m = 12):
     one batched step call vs the same packets propagated one context at a
@@ -158,6 +188,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=50,
                     help="steps of the 256-packet batch measurement (0: skip)")
+    ap.add_argument("--lowmem-steps", type=int, default=20,
+                    help="steps of the memory-saving (second Lanczos run) measurement (0: skip)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run a plain copy of this many MiB (counter calibration for rocprofv3)")
     args = ap.parse_args()
@@ -268,6 +300,9 @@ def main():
     out["paper_context"] = {"value": 5.6e6, "unit": "site-matvecs/s",
                             "what": "derived from ~2 min per step, 8192^2 grid, k=10, one process on a "
                                     "dual Xeon-E5 cluster node (Sec. 7); context, not the target"}
+
+    if args.lowmem_steps > 0 and "mixed" in res:
+        out["lowmem"] = run_lowmem(torch, Propagator, cfg, psi0_dev, args.lowmem_steps)
 
     if args.batch_steps > 0:
         out["batch_packets"] = run_batch(torch, packets, args.batch_steps)

@@ -211,10 +211,13 @@ dl_status dirac_lanczos_step_adaptive(dl_context *ctx, void *psi, double t0, dou
  * against all stored vectors (h = Q^H z, z -= Q h, two passes; the first
  * pass also removes the alpha_i q_i and beta_{i-1} q_{i-1} terms of the
  * recurrence, alpha_i = Re h_i of that pass), a workspace sized for
- * DL_MODE_EIGEN_REORTH with k_eigen >= k_max.  A start vector of norm 0
- * reports nothing; a breakdown (beta_i <= 1e-13 max(|alpha_j|, beta_{j-1}))
- * ends the recurrence at k = i.  DL_ERR_NONFINITE for a non-finite
- * reduction.  Synchronous.
+ * DL_MODE_EIGEN_REORTH with k_eigen >= k_max.  Every 64 iterations the
+ * Ritz values of the current T are computed on the host, and the recurrence
+ * stops early once n_wanted clusters have converged (the values are then
+ * those of that T); otherwise it runs k_max iterations.  A start vector of
+ * norm 0 reports nothing; a breakdown (beta_i <= 1e-13 max(|alpha_j|,
+ * beta_{j-1})) ends the recurrence at k = i.  DL_ERR_NONFINITE for a
+ * non-finite reduction.  Synchronous.
  */
 dl_status dirac_lanczos_eigen(dl_context *ctx, const void *psi0, int32_t k_max, int32_t reorth,
                               double e_lo, double e_hi, double tol, int32_t n_wanted,

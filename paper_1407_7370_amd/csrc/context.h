@@ -73,6 +73,16 @@ void tridiag_full(std::vector<double> d, std::vector<double> e, std::vector<doub
 int ritz_select(const std::vector<double> &lam, const std::vector<double> &zl, double beta_k, double e_lo,
                 double e_hi, double tol, int n_wanted, double *evals, double *bounds, std::vector<int> *rep);
 
+// Ritz values (and with V, all eigenvectors of T: column l of V, row-major
+// k x k) of the tridiagonal T_k with diagonal alpha1[0..k) and off-diagonal
+// beta1[0..k-1), bound factor beta1[k-1] = beta_k; selection as ritz_select.
+int ritz_chain(const double *alpha1, const double *beta1, int k, double e_lo, double e_hi, double tol, int n_wanted,
+               double *evals, double *bounds, std::vector<int> *rep, std::vector<double> *V);
+
+// The eigen mode computes the Ritz values every this many iterations and
+// stops once n_wanted clusters have converged.
+constexpr int kEigenCheckEvery = 64;
+
 // Sign of the sigma2 terms: alpha2 = chir * sigma2.
 inline double chir(const dl_params &p) { return p.chirality < 0 ? -1.0 : 1.0; }
 

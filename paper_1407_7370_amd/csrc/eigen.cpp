@@ -15,7 +15,9 @@
 // device: the scalars of the recurrence are updated by the last workgroup of
 // the norm reduction, and the host reads the breakdown flag every
 // kPollEvery iterations only (iterations past a breakdown are skipped by the
-// kernels: their scalar updates are masked).
+// kernels: their scalar updates are masked).  Every kEigenCheckEvery
+// iterations the host also computes the Ritz values of T and stops once
+// n_wanted clusters have converged.
 #include <algorithm>
 #include <cmath>
 #include <string>
@@ -63,15 +65,33 @@ dl_status eigen_reorth(dl_context *ctx, const void *psi0, int k_max, double e_lo
     dl::launch_reset(sc, st);
     dl::launch_first_q(static_cast<const double2 *>(psi0), n, qv(1), sc, beta, partials, nb, st);
     DL_HIP(ctx, hipGetLastError());
-    struct {
-        int kstop, status;
-    } poll{};
+    std::vector<double> ha(k_max + 1), hb(k_max + 1);
+    dl::Scalars hs;
+    auto fetch = [&](bool chain) -> dl_status {
+        if (chain) {
+            DL_HIP(ctx, hipMemcpyAsync(ha.data(), alpha, sizeof(double) * (k_max + 1), hipMemcpyDeviceToHost, st));
+            DL_HIP(ctx, hipMemcpyAsync(hb.data(), beta, sizeof(double) * (k_max + 1), hipMemcpyDeviceToHost, st));
+        }
+        DL_HIP(ctx, hipMemcpyAsync(&hs, sc, sizeof(hs), hipMemcpyDeviceToHost, st));
+        DL_HIP(ctx, hipStreamSynchronize(st));
+        return DL_OK;
+    };
+    // T_k after iteration k: alpha_1..alpha_k in ha[1..], beta_1..beta_k in hb[1..]
+    int k_early = 0;
     for (int i = 1; i <= k_max; ++i) {
         if ((i - 1) % kPollEvery == 0) {
-            DL_HIP(ctx, hipMemcpyAsync(&poll.kstop, &sc->kstop, sizeof(int), hipMemcpyDeviceToHost, st));
-            DL_HIP(ctx, hipMemcpyAsync(&poll.status, &sc->status, sizeof(int), hipMemcpyDeviceToHost, st));
-            DL_HIP(ctx, hipStreamSynchronize(st));
-            if (poll.status != 0 || poll.kstop < i) break;
+            const bool check = i > 1 && (i - 1) % kEigenCheckEvery == 0;
+            const dl_status s = fetch(check);
+            if (s != DL_OK) return s;
+            if (hs.status != 0 || hs.kstop < i) break;
+            if (check) {
+                std::vector<double> ev(n_wanted), bd(n_wanted);
+                if (ritz_chain(ha.data() + 1, hb.data() + 1, i - 1, e_lo, e_hi, tol, n_wanted, ev.data(), bd.data(),
+                               nullptr, nullptr) >= n_wanted) {
+                    k_early = i - 1;
+                    break;
+                }
+            }
         }
         dl::launch_apply(op, ctx->tiles_apply, qv(i), z, 0.0, 0.0, st);
         dl::launch_proj(Q, vs, i, z, n, pproj, h1, st);
@@ -82,26 +102,17 @@ dl_status eigen_reorth(dl_context *ctx, const void *psi0, int k_max, double e_lo
                              st);
         DL_HIP(ctx, hipGetLastError());
     }
-    std::vector<double> ha(k_max + 1), hb(k_max + 1);
-    dl::Scalars hs;
-    DL_HIP(ctx, hipMemcpyAsync(ha.data(), alpha, sizeof(double) * (k_max + 1), hipMemcpyDeviceToHost, st));
-    DL_HIP(ctx, hipMemcpyAsync(hb.data(), beta, sizeof(double) * (k_max + 1), hipMemcpyDeviceToHost, st));
-    DL_HIP(ctx, hipMemcpyAsync(&hs, sc, sizeof(hs), hipMemcpyDeviceToHost, st));
-    DL_HIP(ctx, hipStreamSynchronize(st));
-    if (hs.status != 0) return ctx->fail(DL_ERR_NONFINITE, "non-finite Lanczos reduction in eigen mode");
-    const int k = std::min(hs.keff, k_max);
-    if (k <= 0) return DL_OK;
-    std::vector<double> d(ha.begin() + 1, ha.begin() + 1 + k), e(k, 0.0), lam, zl, V;
-    for (int j = 0; j + 1 < k; ++j) e[j] = hb[j + 1];
-    const double beta_k = hb[k];
-    if (vecs) {
-        tridiag_full(d, e, lam, V);
-        zl.assign(V.begin() + (size_t)(k - 1) * k, V.begin() + (size_t)k * k);
-    } else {
-        tridiag_last_row(d, e, lam, zl);
+    {
+        const dl_status s = fetch(true);
+        if (s != DL_OK) return s;
     }
+    if (hs.status != 0) return ctx->fail(DL_ERR_NONFINITE, "non-finite Lanczos reduction in eigen mode");
+    const int k = k_early > 0 ? k_early : std::min(hs.keff, k_max);
+    if (k <= 0) return DL_OK;
+    std::vector<double> V;
     std::vector<int> rep;
-    const int nf = ritz_select(lam, zl, beta_k, e_lo, e_hi, tol, n_wanted, evals, bounds, vecs ? &rep : nullptr);
+    const int nf = ritz_chain(ha.data() + 1, hb.data() + 1, k, e_lo, e_hi, tol, n_wanted, evals, bounds,
+                              vecs ? &rep : nullptr, vecs ? &V : nullptr);
     *n_found = nf;
     if (!vecs || nf == 0) return DL_OK;
     // columns of the selected eigenvectors, kRitzVecs at a time, signed so that

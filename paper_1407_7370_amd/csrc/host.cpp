@@ -20,11 +20,6 @@ using dl::kMaxM;
 
 namespace dlh {
 
-
-
-
-
-
 // Workspace plan.  Vector region: step mode holds the second state buffer
 // (complex128) and the Krylov vectors u_2..u_m (complex128, or complex64 in
 // mixed precision); eigen mode needs three rolling complex128 vectors.
@@ -319,6 +314,20 @@ int ritz_select(const std::vector<double> &lam, const std::vector<double> &zl, d
         a = b;
     }
     return nf;
+}
+
+int ritz_chain(const double *alpha1, const double *beta1, int k, double e_lo, double e_hi, double tol, int n_wanted,
+               double *evals, double *bounds, std::vector<int> *rep, std::vector<double> *V)
+{
+    std::vector<double> d(alpha1, alpha1 + k), e(k, 0.0), lam, zl;
+    for (int j = 0; j + 1 < k; ++j) e[j] = beta1[j];
+    if (V) {
+        tridiag_full(d, e, lam, *V);
+        zl.assign(V->begin() + (size_t)(k - 1) * k, V->begin() + (size_t)k * k);
+    } else {
+        tridiag_last_row(d, e, lam, zl);
+    }
+    return ritz_select(lam, zl, beta1[k - 1], e_lo, e_hi, tol, n_wanted, evals, bounds, rep);
 }
 
 dl_status run_build(dl_context *ctx, const Engine &e, const dl::Op &op, const double2 *in,
@@ -709,6 +718,19 @@ dl_status dirac_lanczos_eigen(dl_context *ctx, const void *psi0, int32_t k_max, 
     dl::launch_reset(sc, st);
     const int K1 = k_max + 1;  // the extra iteration yields beta_k for the bounds
     dl::launch_first(op, t1, v[1], fields, alpha, gamma, sc, partials, K1, 0, st);
+    std::vector<double> ha(K1 + 1), hg(K1 + 1);
+    dl::Scalars hs;
+    auto fetch = [&]() -> dl_status {
+        DL_HIP(ctx, hipMemcpyAsync(ha.data(), alpha, sizeof(double) * (K1 + 1), hipMemcpyDeviceToHost, st));
+        DL_HIP(ctx, hipMemcpyAsync(hg.data(), gamma, sizeof(double) * (K1 + 1), hipMemcpyDeviceToHost, st));
+        DL_HIP(ctx, hipMemcpyAsync(&hs, sc, sizeof(hs), hipMemcpyDeviceToHost, st));
+        DL_HIP(ctx, hipStreamSynchronize(st));
+        if (hs.status != 0) return ctx->fail(DL_ERR_NONFINITE, "non-finite Lanczos reduction in eigen mode");
+        return DL_OK;
+    };
+    // T_k after pass p: alpha_1..alpha_k in ha[1..], beta_1..beta_k in hg[2..]
+    // (gamma_{j+1} = beta_j), so k = p - 1 is complete after pass p
+    int k_early = 0;
     for (int pp = 2; pp <= K1; ++pp) {
         dl::PassArgs a{};
         a.op = op;
@@ -724,23 +746,26 @@ dl_status dirac_lanczos_eigen(dl_context *ctx, const void *psi0, int32_t k_max, 
         a.pass = pp;
         a.m = K1;
         dl::launch_recur(a, false, st);
+        if (pp % kEigenCheckEvery == 0 && pp < K1) {
+            DL_HIP(ctx, hipGetLastError());
+            const dl_status s = fetch();
+            if (s != DL_OK) return s;
+            if (hs.kstop < pp) break;  // breakdown: the recurrence is over
+            std::vector<double> ev(n_wanted), bd(n_wanted);
+            if (ritz_chain(ha.data() + 1, hg.data() + 2, pp - 1, e_lo, e_hi, tol, n_wanted, ev.data(), bd.data(),
+                           nullptr, nullptr) >= n_wanted) {
+                k_early = pp - 1;
+                break;
+            }
+        }
     }
     DL_HIP(ctx, hipGetLastError());
-    std::vector<double> ha(K1 + 1), hg(K1 + 1);
-    dl::Scalars hs;
-    DL_HIP(ctx, hipMemcpyAsync(ha.data(), alpha, sizeof(double) * (K1 + 1), hipMemcpyDeviceToHost, st));
-    DL_HIP(ctx, hipMemcpyAsync(hg.data(), gamma, sizeof(double) * (K1 + 1), hipMemcpyDeviceToHost, st));
-    DL_HIP(ctx, hipMemcpyAsync(&hs, sc, sizeof(hs), hipMemcpyDeviceToHost, st));
-    DL_HIP(ctx, hipStreamSynchronize(st));
-    if (hs.status != 0) return ctx->fail(DL_ERR_NONFINITE, "non-finite Lanczos reduction in eigen mode");
-    const int k = std::min(hs.keff, k_max);
+    const dl_status s = fetch();
+    if (s != DL_OK) return s;
+    const int k = k_early > 0 ? k_early : std::min(hs.keff, k_max);
     if (k <= 0) return DL_OK;
-    std::vector<double> d(ha.begin() + 1, ha.begin() + 1 + k), e(k, 0.0), lam, zl;
-    for (int j = 0; j + 1 < k; ++j) e[j] = hg[j + 2];
-    const double beta_k = hg[k + 1];
-    tridiag_last_row(d, e, lam, zl);
-    const int nf = ritz_select(lam, zl, beta_k, e_lo, e_hi, tol, n_wanted, evals, bounds, nullptr);
-    *n_found = nf;
+    *n_found = ritz_chain(ha.data() + 1, hg.data() + 2, k, e_lo, e_hi, tol, n_wanted, evals, bounds, nullptr,
+                          nullptr);
     return DL_OK;
 }
 

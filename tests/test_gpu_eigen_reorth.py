@@ -231,3 +231,30 @@ def test_reorth_full_grid_properties(torch_cuda, Prop, orc):
     for th, b, y in zip(ev, bd, Yh):
         r = np.linalg.norm((orc.apply_h(prob, y) - th * y).reshape(-1))
         assert abs(r - b) <= 1e-6 * b + 1e-9, (th, r, b)
+
+
+def test_eigen_early_stop(torch_cuda, Prop):
+    """The recurrence stops at the first check (every 64 iterations) where
+    n_wanted clusters have converged: asking for fewer values returns values
+    of the longer run, sooner."""
+    torch = torch_cuda
+    mc2 = C * C
+    cfg = packets.landau_softcore_1024()
+    prob = cfg["problem"]
+    psi = torch.from_numpy(packets.initial_state(cfg)).cuda()
+    lo, hi, tol = mc2 - 2.0, mc2 + 5.0, 1e-6
+    say("eigen early stop 1024x1024 K<=2000, n_wanted 2 vs 8")
+    prop = Prop(prob, 1, "fp64", k_eigen=2000)
+    times, res = {}, {}
+    for nw in (8, 2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res[nw] = prop.eigen(psi, 2000, lo, hi, tol, n_wanted=nw)
+        times[nw] = time.perf_counter() - t0
+    prop.close()
+    print(f"n_wanted 8: {times[8]:.2f} s {np.round(res[8][0] - mc2, 8).tolist()}; n_wanted 2: {times[2]:.2f} s "
+          f"{np.round(res[2][0] - mc2, 8).tolist()}", flush=True)
+    ev2, bd2 = res[2]
+    assert len(ev2) == 2 and np.all(bd2 <= tol)
+    for e in ev2:
+        assert np.min(np.abs(res[8][0] - e)) <= 1e-7
