@@ -107,15 +107,19 @@ struct CombArgs {
 // One term of the recombination during a second Lanczos run (the basis is not
 // stored): out = c_1 psi for p = 1, out += c_p u_p for p = 2..k_eff; the
 // launch with p = k_eff also reduces ||out||^2 into the step statistics.
+// Recombination terms p0 .. p0 + nv - 1 (nv <= kAccumTerms) of the second
+// Lanczos run, added to the new state in term order; p0 = 1 starts the sum
+// with c_1 psi instead of reading the state.
+constexpr int kAccumTerms = 3;
 struct AccumArgs {
-    const double2 *psi;  // u_1 (psi layout)
-    const void *u;       // u_p (paired layout), p >= 2
+    const double2 *psi;           // u_1 (psi layout)
+    const void *u[kAccumTerms];   // u_{p0+v} (paired layout); unused for term 1
     size_t sites;
-    double2 *out;        // new state (psi layout)
+    double2 *out;                 // new state (psi layout)
     Scalars *sc;
     double *partials;
     StepStat *stat;
-    int p;
+    int p0, nv;
 };
 void launch_accum(const AccumArgs &a, bool mixed, int nblocks, hipStream_t st);
 

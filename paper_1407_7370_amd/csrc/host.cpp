@@ -394,13 +394,25 @@ dl_status run_twice(dl_context *ctx, const Engine &e, const dl::Op &op, const do
     c.sc = e.sc;
     c.partials = partials;
     c.stat = stat;
-    c.p = 1;
-    DL_HIP(ctx, ctx->timed(4, [&] { dl::launch_accum(c, e.mixed, ctx->combine_blocks, st); }));
+    // terms next..pp go into the state together once kAccumTerms of them are
+    // regenerated (the three rolling vectors hold u_{pp-2}, u_{pp-1}, u_pp)
+    auto accum = [&](int p0, int p1) {
+        c.p0 = p0;
+        c.nv = p1 - p0 + 1;
+        for (int v = 0; v < dl::kAccumTerms; ++v) c.u[v] = (p0 + v >= 2 && p0 + v <= p1) ? rb(p0 + v) : nullptr;
+        return ctx->timed(4, [&] { dl::launch_accum(c, e.mixed, ctx->combine_blocks, st); });
+    };
+    if (e.m == 1) {
+        DL_HIP(ctx, accum(1, 1));
+        return DL_OK;
+    }
+    int next = 1;
     for (int pp = 2; pp <= e.m; ++pp) {
         DL_HIP(ctx, pass(pp, 1));
-        c.p = pp;
-        c.u = rb(pp);
-        DL_HIP(ctx, ctx->timed(4, [&] { dl::launch_accum(c, e.mixed, ctx->combine_blocks, st); }));
+        if (pp - next + 1 == dl::kAccumTerms || pp == e.m) {
+            DL_HIP(ctx, accum(next, pp));
+            next = pp + 1;
+        }
     }
     return DL_OK;
 }

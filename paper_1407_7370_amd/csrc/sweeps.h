@@ -1055,21 +1055,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE, 8))
     if (threadIdx.x == 0) combine_tail(a, tot);
 }
 
-// One recombination term of the second Lanczos run (AccumArgs); the arithmetic
-// per site is that of combine_body, term by term.
+// Recombination terms p0 .. p0 + nv - 1 of the second Lanczos run (AccumArgs):
+// out = c_1 psi + ... in term order, the arithmetic per site that of
+// combine_body.  Terms beyond k_eff add nothing; the launch holding term k_eff
+// (or the first launch when k_eff = 0: psi = 0 gives out = 0) reduces the new
+// norm and completes the step.
 template <class TB, int S>
 __global__ __launch_bounds__(kBlock) void k_accum(AccumArgs a)
 {
     Scalars *sc = a.sc;
     if (sc->status != 0) return;
     const int k = sc->keff;
-    const int p = a.p;
-    if (p > k || k <= 0) return;
+    const int p0 = a.p0;
+    const int pend = min(p0 + a.nv - 1, k);  // last term of this launch that counts
+    const bool first = p0 == 1;
+    if (!first && p0 > k) return;
     const size_t sites = a.sites;
     const size_t tile = (size_t)kBlock * S;
     constexpr size_t kSite = 2 * sizeof(TB);
-    const double cr = sc->coef[2 * p], ci = sc->coef[2 * p + 1];
-    const char *__restrict__ u = static_cast<const char *>(a.u);
     double nrm = 0.0;
     for (size_t s0 = (size_t)blockIdx.x * tile; s0 < sites; s0 += (size_t)gridDim.x * tile) {
 #pragma unroll
@@ -1077,26 +1080,37 @@ __global__ __launch_bounds__(kBlock) void k_accum(AccumArgs a)
             const size_t s = s0 + (size_t)q * kBlock + threadIdx.x;
             if (s >= sites) continue;
             Sp acc;
-            if (p == 1) {
-                const double2 p0 = ld_stream(a.psi + s), p1 = ld_stream(a.psi + sites + s);
-                acc.r0 = cr * p0.x - ci * p0.y;
-                acc.i0 = cr * p0.y + ci * p0.x;
-                acc.r1 = cr * p1.x - ci * p1.y;
-                acc.i1 = cr * p1.y + ci * p1.x;
+            if (first) {
+                const double cr = k >= 1 ? sc->coef[2] : 0.0, ci = k >= 1 ? sc->coef[3] : 0.0;
+                const double2 p0v = ld_stream(a.psi + s), p1v = ld_stream(a.psi + sites + s);
+                acc.r0 = cr * p0v.x - ci * p0v.y;
+                acc.i0 = cr * p0v.y + ci * p0v.x;
+                acc.r1 = cr * p1v.x - ci * p1v.y;
+                acc.i1 = cr * p1v.y + ci * p1v.x;
             } else {
                 const double2 o0 = a.out[s], o1 = a.out[sites + s];
-                const Sp w = to_sp(ld_site<TB>(u + s * kSite));
-                acc.r0 = o0.x + (cr * w.r0 - ci * w.i0);
-                acc.i0 = o0.y + (cr * w.i0 + ci * w.r0);
-                acc.r1 = o1.x + (cr * w.r1 - ci * w.i1);
-                acc.i1 = o1.y + (cr * w.i1 + ci * w.r1);
+                acc.r0 = o0.x;
+                acc.i0 = o0.y;
+                acc.r1 = o1.x;
+                acc.i1 = o1.y;
+            }
+#pragma unroll
+            for (int v = 0; v < kAccumTerms; ++v) {
+                const int j = p0 + v;
+                if (j < 2 || j > pend) continue;
+                const Sp w = to_sp(ld_site<TB>(static_cast<const char *>(a.u[v]) + s * kSite));
+                const double cr = sc->coef[2 * j], ci = sc->coef[2 * j + 1];
+                acc.r0 += cr * w.r0 - ci * w.i0;
+                acc.i0 += cr * w.i0 + ci * w.r0;
+                acc.r1 += cr * w.r1 - ci * w.i1;
+                acc.i1 += cr * w.i1 + ci * w.r1;
             }
             a.out[s] = make_double2(acc.r0, acc.i0);
             a.out[sites + s] = make_double2(acc.r1, acc.i1);
             nrm += sp_norm2(acc);
         }
     }
-    if (p != k) return;
+    if (p0 + a.nv - 1 < k) return;  // term k_eff comes in a later launch
     double accv[1] = {nrm}, tot[1];
     if (!grid_reduce(accv, a.partials, &sc->ticket, tot)) return;
     if (threadIdx.x == 0) {

@@ -86,3 +86,36 @@ def test_lowmem_breakdown_and_workspace(torch_cuda):
     full.step(b, 0.0, 1e-3, 3)
     full.close()
     assert hz.rel_l2(a.cpu().numpy(), b.cpu().numpy()) <= 1e-14
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 5, 7])
+def test_lowmem_term_groups(torch_cuda, m):
+    """The second run adds the recombination terms three at a time: every
+    Krylov dimension around the group boundaries matches the stored basis."""
+    from paper_1407_7370_amd.binding import Propagator
+    torch = torch_cuda
+    prob = CASES["laser_b_soft_150x90"]
+    psi0 = packets.gaussian_packet(prob, 0.8, packets.draw_momentum(3, 4.0), project=True)
+    say(f"lowmem term groups m={m}")
+    prop = Propagator(prob, m, "fp64")
+    a = torch.from_numpy(psi0).to("cuda")
+    b = torch.from_numpy(psi0).to("cuda")
+    sa = prop.step(a, 0.0, 2e-4, 3)
+    sb = prop.step(b, 0.0, 2e-4, 3, lowmem=True)
+    prop.close()
+    assert hz.rel_l2(b.cpu().numpy(), a.cpu().numpy()) <= 1e-14
+    assert np.array_equal(sa["k_eff"], sb["k_eff"]) and np.all(sb["k_eff"] == m)
+    np.testing.assert_allclose(sb["norm2"], sa["norm2"], rtol=1e-13)
+
+
+def test_lowmem_zero_state(torch_cuda):
+    from paper_1407_7370_amd.binding import Propagator
+    torch = torch_cuda
+    prob = CASES["periodic_chiral_128x64"]
+    say("lowmem zero state")
+    prop = Propagator(prob, 8, "mixed", lowmem=True)
+    z = torch.zeros((2, 64, 128), dtype=torch.complex128, device="cuda")
+    st = prop.step(z, 0.0, 1e-3, 3, lowmem=True)
+    prop.close()
+    assert torch.count_nonzero(z).item() == 0
+    assert np.all(st["k_eff"] == 0) and np.all(st["norm2"] == 0)
