@@ -132,6 +132,69 @@ def run_lowmem(torch, Propagator, cfg, psi0_dev, steps):
             "rel_l2_vs_stored_basis": err}
 
 
+def run_adjoint(torch, Propagator, packets):
+    """Gradient of <x> + <p_y> after the 2000-step 512^2 Fourier-pulse workload
+    with respect to its 16 laser coefficients (checkpoints every 50 steps),
+    against one forward propagation of the same workload."""
+    cfg = packets.fourier_pulse_512(seed=0)
+    prob, m, dt, n = cfg["problem"], cfg["m"], cfg["dt"], cfg["steps"]
+    psi0 = torch.from_numpy(packets.initial_state(cfg)).to("cuda")
+    prop = Propagator(prob, m, "fp64")
+    psi = psi0.clone()
+    prop.step(psi, 0.0, dt, 10, want_stats=False)
+    psi.copy_(psi0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prop.step(psi, 0.0, dt, n, want_stats=False)
+    torch.cuda.synchronize()
+    fwd = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    loss, grad = prop.adjoint(psi0, 0.0, dt, n, cfg["ckpt_every"], 9)
+    torch.cuda.synchronize()
+    adj = time.perf_counter() - t1
+    prop.close()
+    ncoef = len(grad)
+    log(f"adjoint 512^2 x {n} steps: forward {fwd:.3f} s, loss + gradient ({ncoef} coefficients) {adj:.3f} s")
+    return {"workload": cfg["name"] + f" ({n} steps, m={m}, checkpoints every {cfg['ckpt_every']})",
+            "forward_s": fwd, "adjoint_s": adj, "adjoint_over_forward": adj / fwd, "coefficients": ncoef,
+            "central_differences_s": 2 * ncoef * fwd, "speedup_vs_central_differences": 2 * ncoef * fwd / adj}
+
+
+def run_eigen(torch, Propagator, packets):
+    """Eigen mode on the 1024^2 B + soft-core workload: plain Lanczos up to
+    2000 iterations stopping at 8 converged values in E - mc^2 in [-2, 5], and
+    500 iterations with full reorthogonalisation (sustained CGS2 bandwidth)."""
+    cfg = packets.landau_softcore_1024(seed=0)
+    prob = cfg["problem"]
+    mc2 = prob["c"] ** 2 * prob["mass"]
+    psi0 = torch.from_numpy(packets.initial_state(cfg)).to("cuda")
+    out = {"workload": cfg["name"], "window": "E - mc^2 in [-2, 5]", "tol": 1e-6}
+    pr = Propagator(prob, 1, "fp64", k_eigen=2000)
+    pr.eigen(psi0, 64, mc2 - 2.0, mc2 + 5.0, 1e-6, n_wanted=8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev, bd = pr.eigen(psi0, 2000, mc2 - 2.0, mc2 + 5.0, 1e-6, n_wanted=8)
+    wall = time.perf_counter() - t0
+    pr.close()
+    out["plain"] = {"k_max": 2000, "n_wanted": 8, "found": len(ev), "seconds": wall,
+                    "values_minus_mc2": [round(float(e - mc2), 9) for e in ev]}
+    K = 500
+    pr = Propagator(prob, 1, "fp64", k_eigen=K, reorth=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev, bd = pr.eigen(psi0, K, mc2 - 2.0, mc2 + 5.0, 1e-6, n_wanted=64, reorth=True)
+    wall = time.perf_counter() - t0
+    pr.close()
+    nel = psi0.numel()
+    byt = sum(2 * (2 * i + 3) * 16 * nel for i in range(1, K + 1))
+    out["full_reorthogonalisation"] = {"k": K, "found": len(ev), "seconds": wall,
+                                       "cgs2_bytes": byt, "cgs2_GBps": byt / wall / 1e9,
+                                       "values_minus_mc2": [round(float(e - mc2), 9) for e in ev]}
+    log(f"eigen 1024^2: plain {out['plain']['seconds']:.2f} s ({out['plain']['found']} values), reorth K={K} "
+        f"{wall:.2f} s, {byt / wall / 1e9:.0f} GB/s")
+    return out
+
+
 def run_batch(torch, packets, steps):
     """The 256-packet batch (grids 128^2..512^2, B_z ~ U[0,2], mixed, m = 12):
     one batched step call vs the same packets propagated one context at a
@@ -190,6 +253,8 @@ def main():
                     help="steps of the 256-packet batch measurement (0: skip)")
     ap.add_argument("--lowmem-steps", type=int, default=20,
                     help="steps of the memory-saving (second Lanczos run) measurement (0: skip)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the adjoint and eigen-mode measurements")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run a plain copy of this many MiB (counter calibration for rocprofv3)")
     args = ap.parse_args()
@@ -306,6 +371,10 @@ def main():
 
     if args.batch_steps > 0:
         out["batch_packets"] = run_batch(torch, packets, args.batch_steps)
+
+    if not args.no_extras:
+        out["adjoint"] = run_adjoint(torch, Propagator, packets)
+        out["eigen"] = run_eigen(torch, Propagator, packets)
 
     if not args.no_cpu_baseline:
         import oracle
