@@ -253,8 +253,8 @@ def main():
                     help="steps of the 256-packet batch measurement (0: skip)")
     ap.add_argument("--lowmem-steps", type=int, default=20,
                     help="steps of the memory-saving (second Lanczos run) measurement (0: skip)")
-    ap.add_argument("--no-extras", action="store_true",
-                    help="skip the adjoint and eigen-mode measurements")
+    ap.add_argument("--extras", default="adjoint,eigen",
+                    help="comma-separated extra measurements: adjoint, eigen (empty: none)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run a plain copy of this many MiB (counter calibration for rocprofv3)")
     args = ap.parse_args()
@@ -372,8 +372,10 @@ def main():
     if args.batch_steps > 0:
         out["batch_packets"] = run_batch(torch, packets, args.batch_steps)
 
-    if not args.no_extras:
+    extras = {e for e in args.extras.split(",") if e}
+    if "adjoint" in extras:
         out["adjoint"] = run_adjoint(torch, Propagator, packets)
+    if "eigen" in extras:
         out["eigen"] = run_eigen(torch, Propagator, packets)
 
     if not args.no_cpu_baseline:
