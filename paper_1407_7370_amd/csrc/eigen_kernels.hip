@@ -15,13 +15,24 @@
 // (0-based) of the basis at q + j * vstride bytes.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device_reduce.h"
 #include "dl_internal.h"
 
 namespace dl {
 namespace {
 
-constexpr int kDotVecs = 16;  // basis vectors per workgroup of a projection
+#ifndef DL_DOT_VECS
+#define DL_DOT_VECS 16
+#endif
+#ifndef DL_PROJ_WORKGROUPS
+#define DL_PROJ_WORKGROUPS 8192
+#endif
+constexpr int kDotVecs = DL_DOT_VECS;  // basis vectors per workgroup of a projection
+// workgroups of a projection launch (at most kProjTiles per vector chunk);
+// measured on 1024^2 with K = 500: 2048 -> 3.30 s, 4096 -> 3.26 s, 8192 -> 3.21 s
+constexpr int kProjWorkgroups = DL_PROJ_WORKGROUPS;
 constexpr int kSubChunk = 256;  // coefficients staged in LDS per chunk of the update
 constexpr int kRitzChunk = 64;  // basis rows of t staged in LDS per chunk
 
@@ -243,8 +254,8 @@ __global__ __launch_bounds__(kBlock) void k_ritz(const char *__restrict__ q, siz
 void launch_proj(const char *q, size_t vstride, int nvec, const double2 *z, size_t nelem, double *pproj,
                  double *h, hipStream_t st)
 {
-    const int ntiles = proj_tiles(nelem);
     const int nchunk = (nvec + kDotVecs - 1) / kDotVecs;
+    const int ntiles = std::max(1, std::min(proj_tiles(nelem), kProjWorkgroups / nchunk));
     hipLaunchKernelGGL(k_proj, dim3(ntiles, nchunk), dim3(kBlock), 0, st, q, vstride, nvec, z, nelem, pproj,
                        ntiles);
     hipLaunchKernelGGL(k_proj_fold, dim3(nvec), dim3(kBlock), 0, st, pproj, ntiles, h);

@@ -758,12 +758,17 @@ __global__ __launch_bounds__(kBlock) void k_recur(PassArgs a)
 // ---------------------------------------------------------------------------
 // exp(-iT') e_1 for the k x k tridiagonal T' (Sec. 4, any standard method for
 // the small exponential; T' = T - sigma I is the shifted matrix of the sweeps)
-// in one wave, lane j holding row j.  Two methods, chosen by the Gershgorin
-// bound B of T':
-//  - B <= 64: scaling and Taylor series on the vector, exp(-iT') e_1 =
-//    (exp(-iT'/2^s))^(2^s) e_1 with 2^s >= B and 20 terms per factor (the
-//    truncation error of each factor is below 1/20!); one term is a
-//    tridiagonal product from the neighbouring lanes.  A few microseconds.
+// in one wave, lane j holding row j.  Two methods, chosen by the half-width R
+// of the Gershgorin interval [c0 - R, c0 + R] of T':
+//  - R <= ~150: Chebyshev expansion (Tal-Ezer and Kosloff),
+//    exp(-iT') = exp(-i c0) sum_n a_n T_n(X), X = (T' - c0 I) / R,
+//    a_0 = J_0(R), a_n = 2 (-i)^n J_n(R), with N = R + 10 R^(1/3) + 20 terms
+//    (the neglected coefficients sum to below 1e-17).  T_n(X) e_1 follows the
+//    three-term recurrence t_{n+1} = 2 X t_n - t_{n-1} in real arithmetic, one
+//    tridiagonal product from the neighbouring lanes per term.  The Bessel
+//    values J_0..J_N(R) come from Miller's backward recurrence
+//    J_{n-1} = (2n/R) J_n - J_{n+1}, started well above N, rescaled when large
+//    and normalised by J_0 + 2 sum J_2k = 1.  A few microseconds.
 //  - otherwise the eigendecomposition T' = Z Lambda Z^T by implicit symmetric
 //    QR steps with Wilkinson shift: lane i holds d_i and the coupling e_i in
 //    registers, the bulge chase fetches the next entries by shuffles one step
@@ -772,14 +777,51 @@ __global__ __launch_bounds__(kBlock) void k_recur(PassArgs a)
 // Output: coef[j] = c_j / gamma_j with c = ||psi|| exp(-i sigma) exp(-iT') e_1,
 // and the step's error estimate beta_k |c_k| (eq. matrix_exponential_error).
 // ---------------------------------------------------------------------------
-constexpr int kTaylorTerms = 20;
-constexpr int kTaylorMaxDoublings = 6;
+constexpr int kChebMaxTerms = 224;
 
 __device__ __forceinline__ double wave_max(double v)
 {
 #pragma unroll
     for (int s = 32; s >= 1; s >>= 1) v = fmax(v, __shfl_xor(v, s, 64));
     return v;
+}
+
+__device__ __forceinline__ double wave_min(double v)
+{
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) v = fmin(v, __shfl_xor(v, s, 64));
+    return v;
+}
+
+__device__ __forceinline__ int cheb_terms(double R)
+{
+    return (int)ceil(R + 10.0 * cbrt(R) + 20.0);
+}
+
+// J_0(R) .. J_N(R) into jb[0..N] (one thread; R > 0).
+__device__ void bessel_miller(double R, int N, double *jb)
+{
+    int M = N + 16 + (int)ceil(2.0 * sqrt((double)N));
+    M += M & 1;
+    const double ir = 1.0 / R;
+    double jp1 = 0.0, j = 1e-300, sum = 0.0;
+    for (int n = M; n >= 1; --n) {
+        const double jm1 = (2.0 * n * ir) * j - jp1;  // J_{n-1} from J_n, J_{n+1}
+        if (n <= N) jb[n] = j;
+        if ((n & 1) == 0) sum += 2.0 * j;
+        jp1 = j;
+        j = jm1;
+        if (fabs(j) > 1e250) {
+            j *= 1e-250;
+            jp1 *= 1e-250;
+            sum *= 1e-250;
+            for (int i = n; i <= N; ++i) jb[i] *= 1e-250;
+        }
+    }
+    jb[0] = j;
+    sum += j;
+    const double is = 1.0 / sum;
+    for (int i = 0; i <= N; ++i) jb[i] *= is;
 }
 
 __device__ __forceinline__ void tridiag_body(const double *alpha, const double *gamma, Scalars *sc, StepStat *stat)
@@ -802,31 +844,44 @@ __device__ __forceinline__ void tridiag_body(const double *alpha, const double *
     double e = (lane + 1 < k) ? gamma[lane + 2] : 0.0;  // zero for lanes >= k-1
     double em = from_left(e);                           // e_{j-1}
     if (lane == 0) em = 0.0;
-    const double bound = wave_max(fabs(d) + fabs(e) + fabs(em));
-    int sdbl = 0;
-    while (sdbl <= kTaylorMaxDoublings && ldexp(1.0, sdbl) < bound) ++sdbl;
+    const double rad = fabs(e) + fabs(em);
+    const double glo = wave_min(lane < k ? d - rad : INFINITY);
+    const double ghi = wave_max(lane < k ? d + rad : -INFINITY);
+    const double c0 = 0.5 * (glo + ghi), R = 0.5 * (ghi - glo);
+    const int N = R > 0.0 ? (R < 1e4 ? cheb_terms(R) : kChebMaxTerms + 1) : 0;
     double cr = 0.0, ci = 0.0;
-    if (sdbl <= kTaylorMaxDoublings) {
-        // v <- exp(-i h T') v, 2^s times, h = 2^-s
-        const double h = ldexp(1.0, -sdbl);
-        double vr = lane == 0 ? 1.0 : 0.0, vi = 0.0;
-        for (int rep = 0; rep < (1 << sdbl); ++rep) {
-            double tr = vr, ti = vi, wr = vr, wi = vi;
-            for (int n = 1; n <= kTaylorTerms; ++n) {
-                // u = T' t from the neighbouring lanes; t <- (-i h / n) u
-                const double ur = em * from_left(tr) + d * tr + e * from_right(tr);
-                const double ui = em * from_left(ti) + d * ti + e * from_right(ti);
-                const double f = h / n;
-                tr = f * ui;
-                ti = -f * ur;
-                wr += tr;
-                wi += ti;
-            }
-            vr = wr;
-            vi = wi;
+    if (N <= kChebMaxTerms) {
+        __shared__ double jb[kChebMaxTerms + 1];
+        if (lane == 0) {
+            if (N > 0)
+                bessel_miller(R, N, jb);
+            else
+                jb[0] = 1.0;
         }
-        cr = vr;
-        ci = vi;
+        __syncthreads();
+        // X = (T' - c0 I) / R on this lane's row (zero rows beyond k)
+        const double ir = N > 0 ? 1.0 / R : 0.0;
+        const double xd = lane < k ? (d - c0) * ir : 0.0, xe = e * ir, xem = em * ir;
+        double tm = lane == 0 ? 1.0 : 0.0;  // T_0(X) e_1
+        double vr = jb[0] * tm, vi = 0.0;
+        double tc = xem * from_left(tm) + xd * tm + xe * from_right(tm);  // T_1(X) e_1
+        if (N >= 1) vi -= 2.0 * jb[1] * tc;
+        for (int n = 2; n <= N; ++n) {
+            const double tn = 2.0 * (xem * from_left(tc) + xd * tc + xe * from_right(tc)) - tm;
+            const double f = 2.0 * jb[n];
+            switch (n & 3) {
+            case 0: vr += f * tn; break;
+            case 1: vi -= f * tn; break;
+            case 2: vr -= f * tn; break;
+            default: vi += f * tn; break;
+            }
+            tm = tc;
+            tc = tn;
+        }
+        double sn, cs;
+        sincos(c0, &sn, &cs);
+        cr = cs * vr + sn * vi;
+        ci = cs * vi - sn * vr;
     } else {
 #define ZZ(i) zpr[(i) * 64 + lane]
         for (int i = 0; i < k; ++i) ZZ(i) = (i == lane) ? 1.0 : 0.0;

@@ -169,6 +169,31 @@ def test_small_krylov_dims(torch_cuda, Prop, orc, m):
     assert np.allclose(st["err_est"], rst["err_est"], rtol=1e-6, atol=1e-300)
 
 
+@pytest.mark.parametrize("dt", [1e-5, 1e-3, 3e-3, 1e-2, 3e-2])
+def test_small_exponential_ranges(torch_cuda, Prop, orc, dt):
+    """The half-width R of the spectrum of the shifted T grows with dt
+    (R = 0.2 .. 600 here, m = 16): the Chebyshev expansion (R up to ~190) and
+    the QR eigendecomposition (beyond) both match the oracle's Jacobi
+    eigendecomposition."""
+    prob = box(48, 40, 0, bz=0.7, pot_kind=1, pot_z=1.0, pot_a=1.0)
+    psi0 = packets.gaussian_packet(prob, 0.8, (3.0, -2.0))
+    keff, _, al, be = orc.lanczos(prob, psi0, 16, dt=dt)
+    d, e = al - al[0], be[:keff - 1]
+    rad = np.abs(np.r_[e, 0.0]) + np.abs(np.r_[0.0, e])
+    R = 0.5 * (np.max(d + rad) - np.min(d - rad))
+    say(f"small exponential dt={dt} (R = {R:.1f}) 48x40 m=16")
+    got, st = gpu_run(torch_cuda, Prop, prob, 16, "fp64", psi0, 0.0, dt, 3)
+    ref, rst = orc.propagate(prob, psi0, 0.0, dt, 3, 16)
+    assert hz.rel_l2(got, ref) <= 1e-10
+    # |c_k| from a dense eigendecomposition carries an absolute rounding error
+    # of a few eps (1 + ||T'||) ||psi||, so the estimate beta_k ||psi|| |c_k| is
+    # compared above that floor (the oracle's value is that noise when the true
+    # one is far smaller: |c_k| = 3e-50 at dt = 1e-5, checked in 60-digit
+    # arithmetic, which the expansion resolves)
+    floor = 20 * np.finfo(float).eps * (1.0 + R) * be[keff - 1] * np.linalg.norm(psi0)
+    assert np.allclose(st["err_est"], rst["err_est"], rtol=1e-6, atol=floor)
+
+
 def test_backward_returns(torch_cuda, Prop, orc):
     cfg = packets.with_grid(packets.laser_4096(precision="fp64"), 120)
     prob = dict(cfg["problem"], t_pulse=0.01, a0=300.0)
