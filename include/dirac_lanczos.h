@@ -163,6 +163,22 @@ dl_status dirac_lanczos_step(dl_context *ctx, void *psi, double t0, double dt, i
                              dl_step_stat *stats);
 
 /*
+ * Adaptive Krylov dimension (Sec. 4: the estimate eq.
+ * matrix_exponential_error can steer k): as dirac_lanczos_step, with each step
+ * running k in [k_min, krylov_dim] iterations.  The first step of a call uses
+ * krylov_dim; every step then predicts the next step's k on the device from
+ * its own tridiagonal T: if its estimate exceeded tol, k grows by two;
+ * otherwise k becomes the smallest j >= k_min whose estimate
+ * beta_j ||psi|| |e_j^T exp(-iT_j) e_1| for the leading j x j block of T is at
+ * most tol / 2 (no host round trip per step).  tol bounds the per-step
+ * estimate; a step whose spectrum widened past the prediction may exceed it,
+ * which stats reports (err_est, and k_eff = the k used).  tol > 0 finite,
+ * 1 <= k_min <= krylov_dim (DL_ERR_INVALID).  Workspace as for step.
+ */
+dl_status dirac_lanczos_step_ktol(dl_context *ctx, void *psi, double t0, double dt, int32_t n_steps, double tol,
+                                  int32_t k_min, dl_step_stat *stats);
+
+/*
  * Memory-saving variant of dirac_lanczos_step (Sec. 4: instead of storing
  * the Krylov basis, the Lanczos recurrence is run a second time when Q is
  * multiplied by exp(-iT) e_1).  Same arguments and results as

@@ -28,7 +28,7 @@ EXPORTS = ("dirac_lanczos_workspace_bytes", "dirac_lanczos_init", "dirac_lanczos
            "dirac_lanczos_last_error", "dirac_lanczos_batch_workspace_bytes", "dirac_lanczos_batch_init",
            "dirac_lanczos_batch_step", "dirac_lanczos_batch_destroy", "dirac_lanczos_batch_last_error",
            "dirac_lanczos_set_launch", "dirac_lanczos_batch_set_launch", "dirac_lanczos_step_adaptive",
-           "dirac_lanczos_step_lowmem", "dirac_lanczos_eigen_vectors")
+           "dirac_lanczos_step_lowmem", "dirac_lanczos_eigen_vectors", "dirac_lanczos_step_ktol")
 DL_LOSS_X, DL_LOSS_Y, DL_LOSS_PX, DL_LOSS_PY = 1, 2, 4, 8
 
 
@@ -100,6 +100,9 @@ def load_library():
     lib.dirac_lanczos_step.restype = ctypes.c_int
     lib.dirac_lanczos_step_lowmem.argtypes = lib.dirac_lanczos_step.argtypes
     lib.dirac_lanczos_step_lowmem.restype = ctypes.c_int
+    lib.dirac_lanczos_step_ktol.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                            ctypes.c_double, ctypes.c_int32, ctypes.POINTER(DlStepStat)]
+    lib.dirac_lanczos_step_ktol.restype = ctypes.c_int
     lib.dirac_lanczos_eigen.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                         ctypes.c_double, ctypes.c_double, ctypes.c_int32, D, D,
                                         ctypes.POINTER(ctypes.c_int32)]
@@ -326,13 +329,19 @@ class Propagator:
         _check(self.lib, self.ctx, dirac_lanczos_apply(self.ctx, x.data_ptr(), y.data_ptr(), t))
         return y
 
-    def step(self, psi, t0: float, dt: float, n_steps: int, want_stats: bool = True, lowmem: bool = False):
+    def step(self, psi, t0: float, dt: float, n_steps: int, want_stats: bool = True, lowmem: bool = False,
+             ktol: float = 0.0, k_min: int = 1):
         """In-place propagation of psi by n_steps steps (lowmem: the second-run
-        variant).  Returns a dict of numpy stats."""
+        variant; ktol > 0: adaptive Krylov dimension in [k_min, m] with the
+        per-step estimate bounded by ktol).  Returns a dict of numpy stats."""
         self._check_psi(psi)
         stats = (DlStepStat * max(n_steps, 1))() if want_stats else None
-        fn = self.lib.dirac_lanczos_step_lowmem if lowmem else self.lib.dirac_lanczos_step
-        st = fn(self.ctx, ctypes.c_void_p(psi.data_ptr()), t0, dt, n_steps, stats)
+        if ktol > 0.0:
+            st = self.lib.dirac_lanczos_step_ktol(self.ctx, ctypes.c_void_p(psi.data_ptr()), t0, dt, n_steps,
+                                                  ktol, int(k_min), stats)
+        else:
+            fn = self.lib.dirac_lanczos_step_lowmem if lowmem else self.lib.dirac_lanczos_step
+            st = fn(self.ctx, ctypes.c_void_p(psi.data_ptr()), t0, dt, n_steps, stats)
         out = None
         if want_stats:
             out = {

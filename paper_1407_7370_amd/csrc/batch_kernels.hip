@@ -118,6 +118,8 @@ __global__ void k_reset_batch(const BatchPacket *pk, int n)
     sc->cabs_k = 0.0;
     sc->beta_k = 0.0;
     sc->sigma = 0.0;
+    sc->kmin = sc->kmax = sc->knext = 0;
+    sc->ktol = 0.0;
 }
 
 struct BatchRecur {

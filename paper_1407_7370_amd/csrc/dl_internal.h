@@ -33,7 +33,10 @@ struct Scalars {
     int status;                    // 0 ok, 3 non-finite (whole call aborted)
     int steps_done;                // completed steps of the current call
     unsigned int ticket;           // last-workgroup-done counter (self-resetting)
-    int pad[3];
+    // adaptive Krylov dimension (ktol > 0): each step runs knext iterations
+    // (0: m), and the small exponential predicts knext for the next step
+    int kmin, kmax, knext;
+    double ktol;                   // per-step bound on the error estimate (0: off)
 };
 
 struct StepStat {

@@ -584,7 +584,7 @@ dl_status dirac_lanczos_apply(dl_context *ctx, const void *x, void *y, double t)
 }
 
 static dl_status run_steps(dl_context *ctx, void *psi_v, double t0, double dt, int32_t n_steps,
-                           dl_step_stat *stats, bool lowmem)
+                           dl_step_stat *stats, bool lowmem, double ktol = 0.0, int kmin = 0)
 {
     if (!ctx) return DL_ERR_INVALID;
     if (!psi_v) return ctx->fail(DL_ERR_INVALID, "psi is NULL");
@@ -622,6 +622,13 @@ static dl_status run_steps(dl_context *ctx, void *psi_v, double t0, double dt, i
 
     dl::launch_reset(sc, st);
     DL_HIP(ctx, hipGetLastError());
+    if (ktol > 0.0) {
+        // adaptive dimension: the first step runs m iterations, later ones the
+        // dimension the previous step predicted
+        const int kk[3] = {kmin, m, 0};
+        DL_HIP(ctx, hipMemcpyAsync(&sc->kmin, kk, sizeof(kk), hipMemcpyHostToDevice, st));
+        DL_HIP(ctx, hipMemcpyAsync(&sc->ktol, &ktol, sizeof(double), hipMemcpyHostToDevice, st));
+    }
     double cum = 0.0;
     int completed = 0;
     bool aborted = false;
@@ -700,6 +707,16 @@ dl_status dirac_lanczos_step_lowmem(dl_context *ctx, void *psi, double t0, doubl
                                     dl_step_stat *stats)
 {
     return run_steps(ctx, psi, t0, dt, n_steps, stats, true);
+}
+
+dl_status dirac_lanczos_step_ktol(dl_context *ctx, void *psi, double t0, double dt, int32_t n_steps, double tol,
+                                  int32_t k_min, dl_step_stat *stats)
+{
+    if (!ctx) return DL_ERR_INVALID;
+    if (!(tol > 0.0) || !std::isfinite(tol)) return ctx->fail(DL_ERR_INVALID, "tol must be finite and > 0");
+    if (k_min < 1 || k_min > ctx->p.krylov_dim)
+        return ctx->fail(DL_ERR_INVALID, "k_min must be in 1..krylov_dim");
+    return run_steps(ctx, psi, t0, dt, n_steps, stats, false, tol, k_min);
 }
 
 dl_status dirac_lanczos_eigen(dl_context *ctx, const void *psi0, int32_t k_max, int32_t reorth,

@@ -549,8 +549,10 @@ __device__ __forceinline__ void first_tail(const double (&tot)[3], double *alpha
     sc->sigma = shift ? al : 0.0;
     alpha[1] = shift ? 0.0 : al;
     sc->scale = fabs(al);
-    sc->keff = m;
-    sc->kstop = m;
+    // fixed dimension m, or the dimension predicted by the previous step
+    const int kk = (sc->knext > 0 && sc->knext < m) ? sc->knext : m;
+    sc->keff = kk;
+    sc->kstop = kk;
     // ||A psi - alpha_1 psi||^2 = ||A psi||^2 - a^2/n
     sc->beta_k = sqrt(fmax(yy - a * (a / n), 0.0)) / g;
 }
@@ -594,7 +596,7 @@ __device__ __forceinline__ void recur_body(const PassArgs &a, const WaveTask &wt
     using T2 = typename V2::T;
     const Scalars *sc = a.sc;
     const int p = a.pass;
-    const bool last = (p == a.m);
+    const bool last = (p == a.m) || (p == sc->kstop);
     const Op &op = a.op;
     const int ny = op.ny;
     const int lane = threadIdx.x & 63;
@@ -710,7 +712,7 @@ __device__ __forceinline__ void recur_tail(const PassArgs &a, const double (&tot
 {
     Scalars *sc = a.sc;
     const int p = a.pass;
-    const bool last = (p == a.m);
+    const bool last = (p == a.m) || (p == sc->kstop);
     const double g1 = a.gamma[p - 1];
     const double sig = sc->sigma;
     const double n = tot[0], an = tot[1], o = tot[2], yy = tot[3], yv = tot[4];
@@ -824,6 +826,85 @@ __device__ void bessel_miller(double R, int N, double *jb)
     for (int i = 0; i <= N; ++i) jb[i] *= is;
 }
 
+// This lane's component of exp(-iT') e_1 for the leading kd x kd block of
+// the tridiagonal T' (diagonal d, coupling e to the next row, em to the
+// previous one; lanes >= kd must hold d = e = em = 0 outside the block) by the
+// Chebyshev expansion.  Returns false, computing nothing, when the spectrum is
+// too wide for kChebMaxTerms terms.  Called by the whole wave.
+__device__ bool cheb_exp_e1(double d, double e, double em, int kd, int lane, double &cr, double &ci)
+{
+    __shared__ double jb[kChebMaxTerms + 1];
+    const double rad = fabs(e) + fabs(em);
+    const double glo = wave_min(lane < kd ? d - rad : INFINITY);
+    const double ghi = wave_max(lane < kd ? d + rad : -INFINITY);
+    const double c0 = 0.5 * (glo + ghi), R = 0.5 * (ghi - glo);
+    const int N = R > 0.0 ? (R < 1e4 ? cheb_terms(R) : kChebMaxTerms + 1) : 0;
+    if (N > kChebMaxTerms) return false;
+    __syncthreads();  // jb of a previous call is read up to here
+    if (lane == 0) {
+        if (N > 0)
+            bessel_miller(R, N, jb);
+        else
+            jb[0] = 1.0;
+    }
+    __syncthreads();
+    // X = (T' - c0 I) / R on this lane's row (zero rows beyond kd)
+    const double ir = N > 0 ? 1.0 / R : 0.0;
+    const double xd = lane < kd ? (d - c0) * ir : 0.0, xe = e * ir, xem = em * ir;
+    double tm = lane == 0 ? 1.0 : 0.0;  // T_0(X) e_1
+    double vr = jb[0] * tm, vi = 0.0;
+    double tc = xem * from_left(tm) + xd * tm + xe * from_right(tm);  // T_1(X) e_1
+    if (N >= 1) vi -= 2.0 * jb[1] * tc;
+    for (int n = 2; n <= N; ++n) {
+        const double tn = 2.0 * (xem * from_left(tc) + xd * tc + xe * from_right(tc)) - tm;
+        const double f = 2.0 * jb[n];
+        switch (n & 3) {
+        case 0: vr += f * tn; break;
+        case 1: vi -= f * tn; break;
+        case 2: vr -= f * tn; break;
+        default: vi += f * tn; break;
+        }
+        tm = tc;
+        tc = tn;
+    }
+    double sn, cs;
+    sincos(c0, &sn, &cs);
+    cr = cs * vr + sn * vi;
+    ci = cs * vi - sn * vr;
+    return true;
+}
+
+// Adaptive Krylov dimension (Sec. 4: the estimate can steer k): the
+// dimension of the next step, from this step's T.  If this step's estimate
+// beta_k ||psi|| |c_k| exceeded ktol, grow by two; otherwise take the smallest
+// j >= kmin whose estimate beta_j ||psi|| |(exp(-iT'_j) e_1)_j| for the
+// leading j x j block is at most ktol / 2 (the next step's spectrum is close
+// to this one's), else keep k.  Called by the whole wave after the
+// coefficients of this step are written.
+__device__ void predict_k(const double *alpha, const double *gamma, Scalars *sc, int k, int lane, double errk)
+{
+    const double g1 = gamma[1];
+    int knext = k;
+    if (errk > sc->ktol) {
+        knext = min(k + 2, sc->kmax);
+    } else {
+        for (int j = max(sc->kmin, 1); j < k; ++j) {
+            const double d = (lane < j) ? alpha[lane + 1] : 0.0;
+            const double e = (lane + 1 < j) ? gamma[lane + 2] : 0.0;
+            double em = from_left(e);
+            if (lane == 0) em = 0.0;
+            double cr = 0.0, ci = 0.0;
+            if (!cheb_exp_e1(d, e, em, j, lane, cr, ci)) break;
+            const double cj = __shfl(sqrt(cr * cr + ci * ci), j - 1, 64);
+            if (gamma[j + 1] * g1 * cj <= 0.5 * sc->ktol) {
+                knext = j;
+                break;
+            }
+        }
+    }
+    if (lane == 0) sc->knext = max(knext, max(sc->kmin, 1));
+}
+
 __device__ __forceinline__ void tridiag_body(const double *alpha, const double *gamma, Scalars *sc, StepStat *stat)
 {
     __shared__ double zpr[(kMaxM + 1) * 64];
@@ -844,45 +925,8 @@ __device__ __forceinline__ void tridiag_body(const double *alpha, const double *
     double e = (lane + 1 < k) ? gamma[lane + 2] : 0.0;  // zero for lanes >= k-1
     double em = from_left(e);                           // e_{j-1}
     if (lane == 0) em = 0.0;
-    const double rad = fabs(e) + fabs(em);
-    const double glo = wave_min(lane < k ? d - rad : INFINITY);
-    const double ghi = wave_max(lane < k ? d + rad : -INFINITY);
-    const double c0 = 0.5 * (glo + ghi), R = 0.5 * (ghi - glo);
-    const int N = R > 0.0 ? (R < 1e4 ? cheb_terms(R) : kChebMaxTerms + 1) : 0;
     double cr = 0.0, ci = 0.0;
-    if (N <= kChebMaxTerms) {
-        __shared__ double jb[kChebMaxTerms + 1];
-        if (lane == 0) {
-            if (N > 0)
-                bessel_miller(R, N, jb);
-            else
-                jb[0] = 1.0;
-        }
-        __syncthreads();
-        // X = (T' - c0 I) / R on this lane's row (zero rows beyond k)
-        const double ir = N > 0 ? 1.0 / R : 0.0;
-        const double xd = lane < k ? (d - c0) * ir : 0.0, xe = e * ir, xem = em * ir;
-        double tm = lane == 0 ? 1.0 : 0.0;  // T_0(X) e_1
-        double vr = jb[0] * tm, vi = 0.0;
-        double tc = xem * from_left(tm) + xd * tm + xe * from_right(tm);  // T_1(X) e_1
-        if (N >= 1) vi -= 2.0 * jb[1] * tc;
-        for (int n = 2; n <= N; ++n) {
-            const double tn = 2.0 * (xem * from_left(tc) + xd * tc + xe * from_right(tc)) - tm;
-            const double f = 2.0 * jb[n];
-            switch (n & 3) {
-            case 0: vr += f * tn; break;
-            case 1: vi -= f * tn; break;
-            case 2: vr -= f * tn; break;
-            default: vi += f * tn; break;
-            }
-            tm = tc;
-            tc = tn;
-        }
-        double sn, cs;
-        sincos(c0, &sn, &cs);
-        cr = cs * vr + sn * vi;
-        ci = cs * vi - sn * vr;
-    } else {
+    if (!cheb_exp_e1(d, e, em, k, lane, cr, ci)) {
 #define ZZ(i) zpr[(i) * 64 + lane]
         for (int i = 0; i < k; ++i) ZZ(i) = (i == lane) ? 1.0 : 0.0;
         const double eps = 2.220446049250313e-16;
@@ -962,6 +1006,7 @@ __device__ __forceinline__ void tridiag_body(const double *alpha, const double *
         }
 #undef ZZ
     }
+    double ck = 0.0;
     if (lane < k) {
         // exp(-iT) = exp(-i sigma) exp(-iT') for the shifted tridiagonal T'
         double ss, sc0;
@@ -971,13 +1016,14 @@ __device__ __forceinline__ void tridiag_body(const double *alpha, const double *
         const double ig = 1.0 / gamma[lane + 1];
         sc->coef[2 * (lane + 1)] = tr * ig;
         sc->coef[2 * (lane + 1) + 1] = ti * ig;
+        ck = sqrt(tr * tr + ti * ti);
         if (lane == k - 1) {
-            const double ck = sqrt(tr * tr + ti * ti);
             sc->cabs_k = ck;
             stat->keff = k;
             stat->err_est = sc->beta_k * ck;
         }
     }
+    if (sc->ktol > 0.0) predict_k(alpha, gamma, sc, k, lane, sc->beta_k * __shfl(ck, k - 1, 64));
 }
 
 __global__ __launch_bounds__(64) void k_tridiag(const double *alpha, const double *gamma, Scalars *sc,
@@ -1236,6 +1282,8 @@ __global__ void k_reset(Scalars *sc)
         sc->cabs_k = 0.0;
         sc->beta_k = 0.0;
         sc->sigma = 0.0;
+        sc->kmin = sc->kmax = sc->knext = 0;
+        sc->ktol = 0.0;
     }
 }
 
