@@ -132,6 +132,33 @@ def run_lowmem(torch, Propagator, cfg, psi0_dev, steps):
             "rel_l2_vs_stored_basis": err}
 
 
+def run_ktol(torch, Propagator, cfg, psi0_dev, steps, ktol=1e-12, k_min=4):
+    """Adaptive Krylov dimension on the same workload (mixed): the per-step
+    estimate bounded by ktol, k in [k_min, 16], against the fixed m = 16."""
+    prob, m, dt = cfg["problem"], cfg["m"], cfg["dt"]
+    sites = prob["nx"] * prob["ny"]
+    prop = Propagator(prob, m, "mixed", tuning_cache=True)
+    ref = psi0_dev.clone()
+    prop.step(ref, 0.0, dt, steps, want_stats=False)
+    psi = psi0_dev.clone()
+    prop.step(psi, 0.0, dt, 2, want_stats=False, ktol=ktol, k_min=k_min)
+    psi.copy_(psi0_dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = prop.step(psi, 0.0, dt, steps, ktol=ktol, k_min=k_min)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prop.close()
+    err = float(torch.linalg.vector_norm(psi - ref) / torch.linalg.vector_norm(ref))
+    k = st["k_eff"]
+    log(f"adaptive k (tol {ktol:g} per step): {wall * 1e3 / steps:.3f} ms/step, mean k {k.mean():.2f}, "
+        f"rel-L2 vs m={m} {err:.1e}")
+    return {"what": f"adaptive Krylov dimension in [{k_min}, {m}], per-step estimate <= {ktol:g} (mixed)",
+            "steps": steps, "ms_per_step": wall * 1e3 / steps, "mean_k": float(k.mean()), "min_k": int(k.min()),
+            "matvecs_per_s": float(sites * k.sum() / wall), "sum_err_est": float(st["err_est"].sum()),
+            "rel_l2_vs_fixed_m": err}
+
+
 def run_adjoint(torch, Propagator, packets):
     """Gradient of <x> + <p_y> after the 2000-step 512^2 Fourier-pulse workload
     with respect to its 16 laser coefficients (checkpoints every 50 steps),
@@ -253,8 +280,8 @@ def main():
                     help="steps of the 256-packet batch measurement (0: skip)")
     ap.add_argument("--lowmem-steps", type=int, default=20,
                     help="steps of the memory-saving (second Lanczos run) measurement (0: skip)")
-    ap.add_argument("--extras", default="adjoint,eigen",
-                    help="comma-separated extra measurements: adjoint, eigen (empty: none)")
+    ap.add_argument("--extras", default="ktol,adjoint,eigen",
+                    help="comma-separated extra measurements: ktol, adjoint, eigen (empty: none)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run a plain copy of this many MiB (counter calibration for rocprofv3)")
     args = ap.parse_args()
@@ -373,6 +400,8 @@ def main():
         out["batch_packets"] = run_batch(torch, packets, args.batch_steps)
 
     extras = {e for e in args.extras.split(",") if e}
+    if "ktol" in extras and "mixed" in res:
+        out["adaptive_k"] = run_ktol(torch, Propagator, cfg, psi0_dev, 100)
     if "adjoint" in extras:
         out["adjoint"] = run_adjoint(torch, Propagator, packets)
     if "eigen" in extras:
