@@ -149,20 +149,29 @@ __global__ __launch_bounds__(kBlock) void k_contract(ContractArgs a)
         }
         __syncthreads();
     }
-    double *dst = a.partials + ((size_t)blockIdx.x * kBlock + t) * 4;
-    dst[0] = s01r;
-    dst[1] = s01i;
-    dst[2] = s10r;
-    dst[3] = s10i;
+    // output o = 4 t + c of this workgroup at partials[o * nblocks + block]:
+    // the fold then reads each output's partials contiguously
+    const size_t nb = gridDim.x, b = blockIdx.x;
+    a.partials[(size_t)(4 * t + 0) * nb + b] = s01r;
+    a.partials[(size_t)(4 * t + 1) * nb + b] = s01i;
+    a.partials[(size_t)(4 * t + 2) * nb + b] = s10r;
+    a.partials[(size_t)(4 * t + 3) * nb + b] = s10i;
 }
 
+// One wave per output (4 kBlock outputs, kWaves per workgroup): lane l sums
+// partials l, l + 64, ... of its output in order, then a butterfly; the
+// order is fixed by nblocks, so the result is bitwise reproducible.  The
+// first workgroup also copies the chains and scalars into the record.
 __global__ __launch_bounds__(kBlock) void k_contract_fold(ContractArgs a, int nblocks)
 {
-    const int t = threadIdx.x;
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int b = 0; b < nblocks; ++b)
-        for (int c = 0; c < 4; ++c) v[c] += a.partials[((size_t)b * kBlock + t) * 4 + c];
-    for (int c = 0; c < 4; ++c) a.rec[kRecS + t * 4 + c] = v[c];
+    const int t = threadIdx.x, lane = t & 63;
+    const int o = blockIdx.x * kWaves + (t >> 6);
+    double v[1] = {0.0};
+    const double *src = a.partials + (size_t)o * nblocks;
+    for (int b = lane; b < nblocks; b += 64) v[0] += src[b];
+    wave_sum(v);
+    if (lane == 0) a.rec[kRecS + o] = v[0];
+    if (blockIdx.x != 0) return;
     if (t < kContractM + 2) {
         // entries 0..k+1 of each chain exist (the chains hold m + 3 >= k + 3 values)
         const bool inl = t <= a.sc_lam->keff + 1, inp = t <= a.sc_psi->keff + 1;
@@ -200,7 +209,7 @@ void launch_adjoint_seed(const Op &op, const double2 *psi, int loss_kind, const 
 void launch_contract(const ContractArgs &a, int nblocks, hipStream_t st)
 {
     hipLaunchKernelGGL(k_contract, dim3(nblocks), dim3(kBlock), 0, st, a);
-    hipLaunchKernelGGL(k_contract_fold, dim3(1), dim3(kBlock), 0, st, a, nblocks);
+    hipLaunchKernelGGL(k_contract_fold, dim3(4 * kBlock / kWaves), dim3(kBlock), 0, st, a, nblocks);
 }
 
 }  // namespace dl
