@@ -216,6 +216,30 @@ dl_status build_tables(dl_batch *b, int rows_per_chunk)
             for (int l = 0; l < nb; ++l) blk[dl::kGridCombine].push_back(dl::BatchBlock{i, l, nb, first});
         }
     }
+    // The resident sweeps take entries in list order: longest marches first,
+    // so the short ones fill the tail.  An entry keeps its packet segment and
+    // index (partials slot and fold order), so the order changes no result.
+    for (int k = 0; k < 2; ++k) {
+        const int kind = k == 0 ? dl::kGridSweep : dl::kGridFirst;
+        const size_t ne = blk[kind].size();
+        std::vector<int> rows(ne, 0), order(ne);
+        for (size_t e = 0; e < ne; ++e) {
+            order[e] = (int)e;
+            for (int w = 0; w < dl::kWaves; ++w) {
+                const dl::BatchTask &t = task[k][e * dl::kWaves + w];
+                rows[e] = std::max(rows[e], t.y1 - t.y0);
+            }
+        }
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return rows[x] > rows[y]; });
+        std::vector<dl::BatchBlock> nb(ne);
+        std::vector<dl::BatchTask> nt(task[k].size());
+        for (size_t e = 0; e < ne; ++e) {
+            nb[e] = blk[kind][order[e]];
+            for (int w = 0; w < dl::kWaves; ++w) nt[e * dl::kWaves + w] = task[k][(size_t)order[e] * dl::kWaves + w];
+        }
+        blk[kind].swap(nb);
+        task[k].swap(nt);
+    }
     for (int k = 0; k < dl::kGridKinds; ++k) {
         if (blk[k].size() > b->max_blocks[k]) return b->fail(DL_ERR_WORKSPACE, "batch tables exceed the workspace");
         b->nblk[k] = (int)blk[k].size();
@@ -388,14 +412,17 @@ dl_status dirac_lanczos_batch_step(dl_batch *b, void *const *psi, double t0, dou
             a.step = j;
             a.parity = (s0 + j) & 1;
             a.pass = 1;
+            const int pwg = dl::kBatchWgsPerCu * b->cus;  // resident workgroups per launch
             a.blocks = b->d_blk[dl::kGridFirst];
             a.tasks = b->d_task[1];
-            dl::launch_first_batch(a, b->nblk[dl::kGridFirst], b->py, b->terms, st);
+            a.ntasks = b->nblk[dl::kGridFirst];
+            dl::launch_first_batch(a, std::min(a.ntasks, pwg), b->py, b->terms, st);
             a.blocks = b->d_blk[dl::kGridSweep];
             a.tasks = b->d_task[0];
+            a.ntasks = b->nblk[dl::kGridSweep];
             for (int p = 2; p <= m; ++p) {
                 a.pass = p;
-                dl::launch_recur_batch(a, b->nblk[dl::kGridSweep], b->mixed, b->py, b->terms, st);
+                dl::launch_recur_batch(a, std::min(a.ntasks, pwg), b->mixed, b->py, b->terms, st);
             }
             dl::launch_tridiag_batch(a, n, st);
             a.blocks = b->d_blk[dl::kGridCombine];

@@ -14,10 +14,10 @@
 namespace dl {
 namespace {
 
-__device__ __forceinline__ WaveTask batch_wave_task(const BatchArgs &b)
+__device__ __forceinline__ WaveTask batch_wave_task(const BatchArgs &b, int entry)
 {
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const BatchTask tk = b.tasks[(size_t)blockIdx.x * kWaves + wave];
+    const BatchTask tk = b.tasks[(size_t)entry * kWaves + wave];
     WaveTask w;
     w.strip = tk.strip;
     w.y0 = tk.y0;
@@ -26,52 +26,68 @@ __device__ __forceinline__ WaveTask batch_wave_task(const BatchArgs &b)
     return w;
 }
 
+// Resident loop of the batched sweeps: workgroup g takes the block entries
+// g, g + G, g + 2G, ... (G workgroups, all resident).  The list holds the
+// longest marches first, so every workgroup starts with long entries and the
+// short ones even out the end.  The entry index is a scalar induction
+// variable: the loop and every branch around the barriers in `body` stay
+// wave-uniform.
+template <class Body>
+__device__ __forceinline__ void resident_loop(const BatchArgs &b, Body body)
+{
+    for (int e = (int)blockIdx.x; e < b.ntasks; e += (int)gridDim.x) body(e);
+}
+
 template <int PF, bool PY, int TERMS>
 __global__ __launch_bounds__(kBlock) void k_first_batch(BatchArgs b)
 {
-    const BatchBlock bb = b.blocks[blockIdx.x];
-    const BatchPacket &pk = b.pk[bb.packet];
-    Scalars *sc = pk.sc;
-    if (sc->status != 0) return;
-    const WaveTask wt = batch_wave_task(b);
-    const double2 *in = b.parity ? pk.state : pk.psi;
-    double acc[3] = {0.0, 0.0, 0.0};
-    first_body<PF, PY, TERMS>(pk.op, pk.tiles[1], wt, in, pk.fields + 2 * b.step, acc);
-    double tot[3];
-    if (!seg_reduce(acc, b.partials + (size_t)bb.first * kPartialStride, &sc->ticket, bb.nblk, bb.local, tot))
-        return;
-    if (threadIdx.x == 0) first_tail(tot, pk.alpha, pk.gamma, sc, b.m, 1);
+    resident_loop(b, [&](int entry) {
+        const BatchBlock bb = b.blocks[entry];
+        const BatchPacket &pk = b.pk[bb.packet];
+        Scalars *sc = pk.sc;
+        if (sc->status != 0) return;
+        const WaveTask wt = batch_wave_task(b, entry);
+        const double2 *in = b.parity ? pk.state : pk.psi;
+        double acc[3] = {0.0, 0.0, 0.0};
+        first_body<PF, PY, TERMS>(pk.op, pk.tiles[1], wt, in, pk.fields + 2 * b.step, acc);
+        double tot[3];
+        if (!seg_reduce(acc, b.partials + (size_t)bb.first * kPartialStride, &sc->ticket, bb.nblk, bb.local, tot))
+            return;
+        if (threadIdx.x == 0) first_tail(tot, pk.alpha, pk.gamma, sc, b.m, 1);
+    });
 }
 
 template <class V1, class V2, class TO, bool HAS2, int PF, bool PY, int TERMS>
 __global__ __launch_bounds__(kBlock) void k_recur_batch(BatchArgs b)
 {
-    const BatchBlock bb = b.blocks[blockIdx.x];
-    const BatchPacket &pk = b.pk[bb.packet];
-    PassArgs a;
-    a.op = pk.op;
-    a.t = pk.tiles[0];
-    const int p = b.pass;
-    const double2 *in = b.parity ? pk.state : pk.psi;
-    auto bvec = [&](int j) { return static_cast<void *>(pk.basis + (size_t)(j - 2) * pk.vstride); };
-    a.u1 = (p - 1 == 1) ? static_cast<const void *>(in) : bvec(p - 1);
-    a.u2 = (p - 2 == 1) ? static_cast<const void *>(in) : (p - 2 >= 2 ? bvec(p - 2) : nullptr);
-    a.uo = bvec(p);
-    a.field = pk.fields + 2 * b.step;
-    a.alpha = pk.alpha;
-    a.gamma = pk.gamma;
-    a.sc = pk.sc;
-    a.partials = b.partials + (size_t)bb.first * kPartialStride;
-    a.pass = p;
-    a.m = b.m;
-    a.replay = 0;
-    if (a.sc->kstop < p) return;
-    const WaveTask wt = batch_wave_task(b);
-    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    recur_body<V1, V2, TO, HAS2, PF, PY, TERMS>(a, wt, acc);
-    double tot[5];
-    if (!seg_reduce(acc, a.partials, &a.sc->ticket, bb.nblk, bb.local, tot)) return;
-    if (threadIdx.x == 0) recur_tail(a, tot);
+    resident_loop(b, [&](int entry) {
+        const BatchBlock bb = b.blocks[entry];
+        const BatchPacket &pk = b.pk[bb.packet];
+        PassArgs a;
+        a.op = pk.op;
+        a.t = pk.tiles[0];
+        const int p = b.pass;
+        const double2 *in = b.parity ? pk.state : pk.psi;
+        auto bvec = [&](int j) { return static_cast<void *>(pk.basis + (size_t)(j - 2) * pk.vstride); };
+        a.u1 = (p - 1 == 1) ? static_cast<const void *>(in) : bvec(p - 1);
+        a.u2 = (p - 2 == 1) ? static_cast<const void *>(in) : (p - 2 >= 2 ? bvec(p - 2) : nullptr);
+        a.uo = bvec(p);
+        a.field = pk.fields + 2 * b.step;
+        a.alpha = pk.alpha;
+        a.gamma = pk.gamma;
+        a.sc = pk.sc;
+        a.partials = b.partials + (size_t)bb.first * kPartialStride;
+        a.pass = p;
+        a.m = b.m;
+        a.replay = 0;
+        if (a.sc->kstop < p) return;
+        const WaveTask wt = batch_wave_task(b, entry);
+        double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        recur_body<V1, V2, TO, HAS2, PF, PY, TERMS>(a, wt, acc);
+        double tot[5];
+        if (!seg_reduce(acc, a.partials, &a.sc->ticket, bb.nblk, bb.local, tot)) return;
+        if (threadIdx.x == 0) recur_tail(a, tot);
+    });
 }
 
 // one wave per packet

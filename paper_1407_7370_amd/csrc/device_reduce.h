@@ -50,7 +50,9 @@ __device__ bool seg_reduce(double (&v)[NV], double *partials, unsigned int *tick
         last = (t == (unsigned int)nblk - 1u) ? 1 : 0;
     }
     __syncthreads();
-    if (!last) return false;
+    // `last` is the same in every thread; a scalar copy keeps the branch (and
+    // the barriers of callers that loop over this) wave-uniform
+    if (!__builtin_amdgcn_readfirstlane(last)) return false;
     __threadfence();
     double s[NV];
 #pragma unroll

@@ -216,7 +216,10 @@ struct BatchArgs {
     const BatchTask *tasks;    // kWaves per workgroup (sweeps and iteration 1)
     double *partials;          // kPartialStride doubles per workgroup
     int pass, m, step, parity; // step: index in the chunk tables; parity 1: the input is `state`
+    int ntasks;                // block entries of the sweeps (each workgroup loops over them)
 };
+// Resident workgroups per compute unit of the batched sweeps.
+constexpr int kBatchWgsPerCu = 2;
 
 void launch_first_batch(const BatchArgs &b, int nblocks, bool py, int terms, hipStream_t st);
 void launch_recur_batch(const BatchArgs &b, int nblocks, bool mixed, bool py, int terms, hipStream_t st);
