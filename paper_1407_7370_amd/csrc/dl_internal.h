@@ -218,8 +218,13 @@ struct BatchArgs {
     int pass, m, step, parity; // step: index in the chunk tables; parity 1: the input is `state`
     int ntasks;                // block entries of the sweeps (each workgroup loops over them)
 };
-// Resident workgroups per compute unit of the batched sweeps.
-constexpr int kBatchWgsPerCu = 2;
+// Resident workgroups per compute unit of the batched sweeps (the sweep's
+// occupancy; measured on the 256-packet batch, R = 256: 2 -> 7.54 ms,
+// 3 -> 6.79 ms, 4 and 6 -> 6.78 ms per step).
+#ifndef DL_BATCH_WGS_PER_CU
+#define DL_BATCH_WGS_PER_CU 3
+#endif
+constexpr int kBatchWgsPerCu = DL_BATCH_WGS_PER_CU;
 
 void launch_first_batch(const BatchArgs &b, int nblocks, bool py, int terms, hipStream_t st);
 void launch_recur_batch(const BatchArgs &b, int nblocks, bool mixed, bool py, int terms, hipStream_t st);
