@@ -95,12 +95,19 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_seed(Op op, const double2 *_
 }
 
 // ---------------------------------------------------------------------------
-// Contraction of the two Krylov bases of one adjoint step (see ContractArgs).
-// A workgroup stages a tile of sites of every basis vector in LDS; thread
-// t = 16 a + b accumulates pair (a, b); per-workgroup partials are folded in
-// fixed order by k_contract_fold.
+// Contraction of the two Krylov bases of one adjoint step (see ContractArgs):
+// S01 = L0^H P1 and S10 = L1^H P0 (16 x 16 complex; L, P the lambda and psi
+// bases, 0/1 the spinor components) are dense products over the sites, so
+// they run on the FP64 matrix cores: v_mfma_f64_16x16x4f64 multiplies a
+// 16 x 4 block A by a 4 x 16 block B, with lane l holding A[l % 16][l / 16],
+// B[l / 16][l % 16] and D[4 r + l / 16][l % 16] in its register r (the
+// layout checked on the device before use).  Per step of four sites lane l
+// loads site s0 + l / 16 of basis vector l % 16 of both bases, and the eight
+// real products of the two complex contractions accumulate in four 16 x 16
+// blocks.  Waves stride over the four-site groups; a workgroup sums its four
+// waves in order and writes its partials for k_contract_fold.
 // ---------------------------------------------------------------------------
-constexpr int kTileSites = 32;
+typedef double v4d __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ Site basis_site(const double2 *u1, const char *basis, size_t vec_bytes,
                                                    size_t sites, int v, size_t site)
@@ -109,53 +116,57 @@ __device__ __forceinline__ Site basis_site(const double2 *u1, const char *basis,
     return *reinterpret_cast<const Site *>(basis + (size_t)(v - 1) * vec_bytes + site * 32);
 }
 
+__device__ __forceinline__ v4d mfma(double x, double y, v4d c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0);
+}
+
 __global__ __launch_bounds__(kBlock) void k_contract(ContractArgs a)
 {
-    __shared__ double ls[kContractM][kTileSites][4];
-    __shared__ double ps[kContractM][kTileSites][4];
+    static_assert(kContractM == 16, "one 16 x 16 block per contraction");
+    __shared__ double red[kWaves][4][64][4];
     const int kl = a.sc_lam->keff, kp = a.sc_psi->keff;
-    const int t = threadIdx.x, pa = t >> 4, pb = t & 15;
-    const bool act = pa < kl && pb < kp;
-    double s01r = 0.0, s01i = 0.0, s10r = 0.0, s10i = 0.0;
-    for (size_t s0 = (size_t)blockIdx.x * kTileSites; s0 < a.sites; s0 += (size_t)gridDim.x * kTileSites) {
-        for (int idx = t; idx < kContractM * kTileSites; idx += kBlock) {
-            const int v = idx / kTileSites, s = idx % kTileSites;
-            const size_t site = s0 + s;
-            Site x = Site{make_double2(0.0, 0.0), make_double2(0.0, 0.0)}, y = Site{make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
-            if (site < a.sites) {
-                if (v < kl) x = basis_site(a.lam1, a.lam_basis, a.vec_bytes, a.sites, v, site);
-                if (v < kp) y = basis_site(a.psi1, a.psi_basis, a.vec_bytes, a.sites, v, site);
-            }
-            ls[v][s][0] = x.a.x;
-            ls[v][s][1] = x.a.y;
-            ls[v][s][2] = x.b.x;
-            ls[v][s][3] = x.b.y;
-            ps[v][s][0] = y.a.x;
-            ps[v][s][1] = y.a.y;
-            ps[v][s][2] = y.b.x;
-            ps[v][s][3] = y.b.y;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int v = lane & 15, ks = lane >> 4;
+    v4d s01r = {0.0, 0.0, 0.0, 0.0}, s01i = s01r, s10r = s01r, s10i = s01r;
+    const size_t groups = (a.sites + 3) / 4;
+    for (size_t g = (size_t)blockIdx.x * kWaves + w; g < groups; g += (size_t)gridDim.x * kWaves) {
+        const size_t site = g * 4 + ks;
+        Site x = Site{make_double2(0.0, 0.0), make_double2(0.0, 0.0)}, y = x;
+        if (site < a.sites) {
+            if (v < kl) x = basis_site(a.lam1, a.lam_basis, a.vec_bytes, a.sites, v, site);
+            if (v < kp) y = basis_site(a.psi1, a.psi_basis, a.vec_bytes, a.sites, v, site);
         }
-        __syncthreads();
-        if (act) {
-            for (int s = 0; s < kTileSites; ++s) {
-                const double l0r = ls[pa][s][0], l0i = ls[pa][s][1], l1r = ls[pa][s][2], l1i = ls[pa][s][3];
-                const double p0r = ps[pb][s][0], p0i = ps[pb][s][1], p1r = ps[pb][s][2], p1i = ps[pb][s][3];
-                // conj(l0) p1 and conj(l1) p0
-                s01r += l0r * p1r + l0i * p1i;
-                s01i += l0r * p1i - l0i * p1r;
-                s10r += l1r * p0r + l1i * p0i;
-                s10i += l1r * p0i - l1i * p0r;
-            }
-        }
-        __syncthreads();
+        // conj(l0) p1 and conj(l1) p0, real and imaginary parts
+        s01r = mfma(x.a.x, y.b.x, s01r);
+        s01r = mfma(x.a.y, y.b.y, s01r);
+        s01i = mfma(x.a.x, y.b.y, s01i);
+        s01i = mfma(-x.a.y, y.b.x, s01i);
+        s10r = mfma(x.b.x, y.a.x, s10r);
+        s10r = mfma(x.b.y, y.a.y, s10r);
+        s10i = mfma(x.b.x, y.a.y, s10i);
+        s10i = mfma(-x.b.y, y.a.x, s10i);
     }
-    // output o = 4 t + c of this workgroup at partials[o * nblocks + block]:
-    // the fold then reads each output's partials contiguously
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        red[w][0][lane][r] = s01r[r];
+        red[w][1][lane][r] = s01i[r];
+        red[w][2][lane][r] = s10r[r];
+        red[w][3][lane][r] = s10i[r];
+    }
+    __syncthreads();
+    // thread t = 16 a + b owns pair (a, b), held by lane b + 16 (a % 4), register a / 4;
+    // output o = 4 t + c at partials[o * nblocks + block]: the fold reads each
+    // output's partials contiguously
+    const int t = threadIdx.x, pa = t >> 4, pb = t & 15;
+    const int src = pb + 16 * (pa & 3), reg = pa >> 2;
     const size_t nb = gridDim.x, b = blockIdx.x;
-    a.partials[(size_t)(4 * t + 0) * nb + b] = s01r;
-    a.partials[(size_t)(4 * t + 1) * nb + b] = s01i;
-    a.partials[(size_t)(4 * t + 2) * nb + b] = s10r;
-    a.partials[(size_t)(4 * t + 3) * nb + b] = s10i;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        double acc = red[0][c][src][reg];
+        for (int i = 1; i < kWaves; ++i) acc += red[i][c][src][reg];
+        a.partials[(size_t)(4 * t + c) * nb + b] = acc;
+    }
 }
 
 // One wave per output (4 kBlock outputs, kWaves per workgroup): lane l sums
