@@ -316,7 +316,8 @@ dl_status dirac_lanczos_adjoint(dl_context *ctx, const void *psi0, double t0, do
  *   n_packets * n_steps entries (packet-major) or NULL.  Synchronous.  A
  *   packet whose reduction becomes non-finite stops (its psi holds its last
  *   completed step, later stats have k_eff = -1) while the others continue;
- *   the call then returns DL_ERR_NONFINITE naming the packets.
+ *   the call then returns DL_ERR_NONFINITE naming the packets.  Calls on one
+ *   batch must not overlap (they share its tables and reduction scratch).
  */
 typedef struct dl_batch dl_batch;
 
@@ -333,8 +334,10 @@ const char *dirac_lanczos_batch_last_error(const dl_batch *batch);
 /*
  * Launch shape (tuning; results are equal to rounding for every shape).
  * dirac_lanczos_set_launch: at most sweep_waves_per_cu waves per compute unit
- *   in the Lanczos sweeps (0: the built-in default, eight); the row chunks
- *   are re-planned for one resident round of waves.  *waves_out (HOST, may
+ *   in the Lanczos sweeps (0: the built-in default, floor(strips * ny /
+ *   (24 * compute units)) within 2..8, i.e. row chunks of at least 24 rows
+ *   where the grid allows); the row chunks are re-planned for one resident
+ *   round of waves.  *waves_out (HOST, may
  *   be NULL) receives the value in use (capped by occupancy).
  * dirac_lanczos_batch_set_launch: rows per chunk of the batched sweeps
  *   (>= 4; 0: the default choice, the smallest power of two giving at most
