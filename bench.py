@@ -286,8 +286,8 @@ def main():
                     help="run a plain copy of this many MiB (counter calibration for rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(see DESIGN.md for how the propagator would shard).", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the propagator has no multi-GPU path "
+              "(sharding the lattice into row strips with halo exchange is not implemented).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -52,7 +52,7 @@ typedef enum {
     DL_ERR_DEVICE = 2,      /* HIP runtime error (message in last_error) */
     DL_ERR_NONFINITE = 3,   /* a Lanczos reduction became NaN/Inf */
     DL_ERR_WORKSPACE = 4,   /* workspace missing, too small or misaligned */
-    DL_ERR_UNSUPPORTED = 5  /* valid request that this build does not provide */
+    DL_ERR_UNSUPPORTED = 5  /* valid request that the library does not provide */
 } dl_status;
 
 enum { DL_BC_DIRICHLET = 0, DL_BC_PERIODIC = 1 };

@@ -56,13 +56,14 @@ __global__ __launch_bounds__(kBlock) void k_proj(const char *__restrict__ q, siz
     for (int jj = 0; jj < kDotVecs; ++jj) re[jj] = im[jj] = 0.0;
     for (size_t e = (size_t)t * kBlock + threadIdx.x; e < nelem; e += (size_t)ntiles * kBlock) {
         const double2 zv = z[e];
+        // every load unconditional (a short last chunk re-reads its last
+        // vector into accumulators that are never written out), so the 16
+        // loads of a site are in flight together
 #pragma unroll
         for (int jj = 0; jj < kDotVecs; ++jj) {
-            if (jj < nj) {
-                const double2 qv = qvec(q, vstride, j0 + jj)[e];
-                re[jj] += qv.x * zv.x + qv.y * zv.y;
-                im[jj] += qv.x * zv.y - qv.y * zv.x;
-            }
+            const double2 qv = qvec(q, vstride, j0 + min(jj, nj - 1))[e];
+            re[jj] += qv.x * zv.x + qv.y * zv.y;
+            im[jj] += qv.x * zv.y - qv.y * zv.x;
         }
     }
     wave_sum(re);
@@ -121,16 +122,24 @@ __global__ __launch_bounds__(kBlock) void k_sub_q(const char *__restrict__ q, si
         double ar = 0.0, ai = 0.0;
         for (int j0 = 0; j0 < nvec; j0 += kSubChunk) {
             const int nj = min(kSubChunk, nvec - j0);
+            // coefficients padded with zeros to whole groups of kDotVecs, so
+            // each group issues all its loads before the first use
+            const int njp = (nj + kDotVecs - 1) / kDotVecs * kDotVecs;
             __syncthreads();
-            for (int i = threadIdx.x; i < 2 * nj; i += kBlock) hs[i] = h[2 * (size_t)j0 + i];
+            for (int i = threadIdx.x; i < 2 * njp; i += kBlock) hs[i] = i < 2 * nj ? h[2 * (size_t)j0 + i] : 0.0;
             __syncthreads();
             if (live) {
-#pragma unroll 8
-                for (int jj = 0; jj < nj; ++jj) {
-                    const double2 qv = qvec(q, vstride, j0 + jj)[e];
-                    const double hr = hs[2 * jj], hi = hs[2 * jj + 1];
-                    ar += hr * qv.x - hi * qv.y;
-                    ai += hr * qv.y + hi * qv.x;
+                for (int jb = 0; jb < njp; jb += kDotVecs) {
+                    double2 qv[kDotVecs];
+#pragma unroll
+                    for (int u = 0; u < kDotVecs; ++u) qv[u] = qvec(q, vstride, j0 + min(jb + u, nj - 1))[e];
+                    __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the arithmetic
+#pragma unroll
+                    for (int u = 0; u < kDotVecs; ++u) {
+                        const double hr = hs[2 * (jb + u)], hi = hs[2 * (jb + u) + 1];
+                        ar += hr * qv[u].x - hi * qv[u].y;
+                        ai += hr * qv[u].y + hi * qv[u].x;
+                    }
                 }
             }
         }
