@@ -134,16 +134,20 @@ def main():
     ap.add_argument("--precision", choices=("mixed", "fp64"), default="mixed")
     ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--cache", default=DEFAULT_CACHE)
+    ap.add_argument("--candidates", default="",
+                    help="comma-separated shapes to time (waves per CU, or rows per chunk for batches)")
     args = ap.parse_args()
+    cand = tuple(int(c) for c in args.candidates.split(",") if c)
     if args.workload == "laser_4096":
         cfg = packets.laser_4096(seed=0, precision=args.precision)
         psi0 = torch.from_numpy(packets.initial_state(cfg)).to("cuda")
-        e = tune_single(cfg["problem"], psi0, cfg["m"], args.precision, cfg["dt"], args.steps, cache=args.cache)
+        e = tune_single(cfg["problem"], psi0, cfg["m"], args.precision, cfg["dt"], args.steps,
+                        candidates=cand or SINGLE_CANDIDATES, cache=args.cache)
     else:
         cfgs = packets.packet_batch(seed=0)
         psi0 = [torch.from_numpy(packets.initial_state(c)).to("cuda") for c in cfgs]
         e = tune_batch([c["problem"] for c in cfgs], psi0, cfgs[0]["m"], args.precision, cfgs[0]["dt"],
-                       args.steps, cache=args.cache)
+                       args.steps, candidates=cand or BATCH_CANDIDATES, cache=args.cache)
     print(json.dumps(e))
 
 
