@@ -132,6 +132,51 @@ def run_lowmem(torch, Propagator, cfg, psi0_dev, steps):
             "rel_l2_vs_stored_basis": err}
 
 
+def run_adaptive_dt(torch, Propagator, cfg, psi0_dev, n_fixed=50, rel_tol=1e-10):
+    """Adaptive time steps on the grid and packet of the workload in FP64: the
+    interval of n_fixed steps of the fixed dt, covered with step sizes chosen
+    from each step's error estimate (cumulative bound rel_tol * ||psi||),
+    against the fixed steps over the same interval.  With the field off the
+    step is exact up to the Lanczos error, so the distance to the fixed steps
+    must stay within the bound; with the laser field on, larger steps also
+    change the Magnus truncation, which the estimate does not measure."""
+    m, dt = cfg["m"], cfg["dt"]
+    t_end = n_fixed * dt
+    tol = rel_tol * float(torch.linalg.vector_norm(psi0_dev))
+    out = {"what": f"adaptive step sizes over t in [0, {t_end:g}] (FP64, m={m}), cumulative bound "
+                   f"<= {rel_tol:g} ||psi||, against {n_fixed} fixed steps of {dt:g}"}
+    for name, prob in (("field_off", dict(cfg["problem"], pulse_kind=0)), ("laser", cfg["problem"])):
+        sites = prob["nx"] * prob["ny"]
+        prop = Propagator(prob, m, "fp64", tuning_cache=True)
+        ref = psi0_dev.clone()
+        prop.step(ref, 0.0, dt, 2, want_stats=False)
+        ref.copy_(psi0_dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prop.step(ref, 0.0, dt, n_fixed, want_stats=False)
+        torch.cuda.synchronize()
+        wall_fixed = time.perf_counter() - t0
+        psi = psi0_dev.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, dts = prop.step_adaptive(psi, 0.0, t_end, dt, tol, 1e-3 * dt, 100 * dt)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        prop.close()
+        dist = float(torch.linalg.vector_norm(psi - ref))
+        err = dist / float(torch.linalg.vector_norm(ref))
+        log(f"adaptive dt ({name}) over {n_fixed} fixed steps: {st['accepted']} accepted, {st['rejected']} "
+            f"rejected, {wall * 1e3:.1f} ms vs {wall_fixed * 1e3:.1f} ms fixed, |psi - psi_fixed| {dist:.1e} "
+            f"(bound {st['cum_bound']:.1e}), rel-L2 {err:.1e}")
+        out[name] = {"accepted": st["accepted"], "rejected": st["rejected"], "seconds": wall,
+                     "fixed_seconds": wall_fixed, "speedup_vs_fixed": wall_fixed / wall,
+                     "dt_min": float(dts.min()), "dt_max": float(dts.max()), "cum_bound": st["cum_bound"],
+                     "dist_to_fixed": dist, "rel_l2_vs_fixed": err,
+                     "matvecs_per_s": float(sites * m * (st["accepted"] + st["rejected"]) / wall)}
+        del psi, ref
+    return out
+
+
 def run_ktol(torch, Propagator, cfg, psi0_dev, steps, ktol=1e-12, k_min=4):
     """Adaptive Krylov dimension on the same workload (mixed): the per-step
     estimate bounded by ktol, k in [k_min, 16], against the fixed m = 16."""
@@ -280,8 +325,8 @@ def main():
                     help="steps of the 256-packet batch measurement (0: skip)")
     ap.add_argument("--lowmem-steps", type=int, default=20,
                     help="steps of the memory-saving (second Lanczos run) measurement (0: skip)")
-    ap.add_argument("--extras", default="ktol,adjoint,eigen",
-                    help="comma-separated extra measurements: ktol, adjoint, eigen (empty: none)")
+    ap.add_argument("--extras", default="ktol,adaptive_dt,adjoint,eigen",
+                    help="comma-separated extra measurements: ktol, adaptive_dt, adjoint, eigen (empty: none)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run a plain copy of this many MiB (counter calibration for rocprofv3)")
     args = ap.parse_args()
@@ -402,6 +447,8 @@ def main():
     extras = {e for e in args.extras.split(",") if e}
     if "ktol" in extras and "mixed" in res:
         out["adaptive_k"] = run_ktol(torch, Propagator, cfg, psi0_dev, 100)
+    if "adaptive_dt" in extras:
+        out["adaptive_dt"] = run_adaptive_dt(torch, Propagator, cfg, psi0_dev)
     if "adjoint" in extras:
         out["adjoint"] = run_adjoint(torch, Propagator, packets)
     if "eigen" in extras:
