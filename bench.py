@@ -211,7 +211,7 @@ def run_adjoint(torch, Propagator, packets):
     cfg = packets.fourier_pulse_512(seed=0)
     prob, m, dt, n = cfg["problem"], cfg["m"], cfg["dt"], cfg["steps"]
     psi0 = torch.from_numpy(packets.initial_state(cfg)).to("cuda")
-    prop = Propagator(prob, m, "fp64")
+    prop = Propagator(prob, m, "fp64", tuning_cache=True)
     psi = psi0.clone()
     prop.step(psi, 0.0, dt, 10, want_stats=False)
     psi.copy_(psi0)

@@ -12,6 +12,7 @@ Every shape computes the same result to rounding (the reductions are folded
 over other partial sums); the cache only changes speed.
 
   python -m paper_1407_7370_amd.autotune --workload laser_4096 --precision mixed
+  python -m paper_1407_7370_amd.autotune --workload fourier_pulse_512 --precision fp64
   python -m paper_1407_7370_amd.autotune --workload packet_batch
 """
 from __future__ import annotations
@@ -130,7 +131,7 @@ def main():
     import torch
     from . import packets
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--workload", choices=("laser_4096", "packet_batch"), default="laser_4096")
+    ap.add_argument("--workload", choices=("laser_4096", "fourier_pulse_512", "packet_batch"), default="laser_4096")
     ap.add_argument("--precision", choices=("mixed", "fp64"), default="mixed")
     ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--cache", default=DEFAULT_CACHE)
@@ -138,8 +139,11 @@ def main():
                     help="comma-separated shapes to time (waves per CU, or rows per chunk for batches)")
     args = ap.parse_args()
     cand = tuple(int(c) for c in args.candidates.split(",") if c)
-    if args.workload == "laser_4096":
-        cfg = packets.laser_4096(seed=0, precision=args.precision)
+    if args.workload in ("laser_4096", "fourier_pulse_512"):
+        if args.workload == "laser_4096":
+            cfg = packets.laser_4096(seed=0, precision=args.precision)
+        else:
+            cfg = packets.fourier_pulse_512(seed=0)
         psi0 = torch.from_numpy(packets.initial_state(cfg)).to("cuda")
         e = tune_single(cfg["problem"], psi0, cfg["m"], args.precision, cfg["dt"], args.steps,
                         candidates=cand or SINGLE_CANDIDATES, cache=args.cache)
