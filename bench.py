@@ -177,6 +177,29 @@ def run_adaptive_dt(torch, Propagator, cfg, psi0_dev, n_fixed=50, rel_tol=1e-10)
     return out
 
 
+def run_chirality(torch, Propagator, cfg, psi0_dev, steps=50):
+    """The workload with the other 2D representation (alpha2 = -sigma2,
+    chirality -1), mixed: the same kernels with the sign of every sigma2 term
+    flipped, so the rate must match chirality +1."""
+    prob, m, dt = dict(cfg["problem"], chirality=-1), cfg["m"], cfg["dt"]
+    sites = prob["nx"] * prob["ny"]
+    prop = Propagator(prob, m, "mixed", tuning_cache=True)
+    psi = psi0_dev.clone()
+    prop.step(psi, 0.0, dt, 2, want_stats=False)
+    psi.copy_(psi0_dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = prop.step(psi, 0.0, dt, steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prop.close()
+    n0 = float(torch.linalg.vector_norm(psi0_dev)) ** 2
+    log(f"chirality -1: {wall * 1e3 / steps:.3f} ms/step")
+    return {"what": "chirality -1 (alpha2 = -sigma2), mixed, same workload", "steps": steps,
+            "ms_per_step": wall * 1e3 / steps, "value": sites * m * steps / wall, "unit": "site-matvecs/s",
+            "norm_drift": abs(float(st["norm2"][-1]) / n0 - 1.0)}
+
+
 def run_ktol(torch, Propagator, cfg, psi0_dev, steps, ktol=1e-12, k_min=4):
     """Adaptive Krylov dimension on the same workload (mixed): the per-step
     estimate bounded by ktol, k in [k_min, 16], against the fixed m = 16."""
@@ -200,6 +223,8 @@ def run_ktol(torch, Propagator, cfg, psi0_dev, steps, ktol=1e-12, k_min=4):
         f"rel-L2 vs m={m} {err:.1e}")
     return {"what": f"adaptive Krylov dimension in [{k_min}, {m}], per-step estimate <= {ktol:g} (mixed)",
             "steps": steps, "ms_per_step": wall * 1e3 / steps, "mean_k": float(k.mean()), "min_k": int(k.min()),
+            # algorithmic bytes of a mixed step of dimension k: (64 k + 48) per site
+            "hbm_frac_step": round(float(sites * (64 * k + 48).sum()) / wall / 1e9 / HBM_PEAK_GBS, 4),
             "matvecs_per_s": float(sites * k.sum() / wall), "sum_err_est": float(st["err_est"].sum()),
             "rel_l2_vs_fixed_m": err}
 
@@ -310,7 +335,9 @@ def run_batch(torch, packets, steps):
             "sites": sites, "steps": steps, "ms_per_step": wall * 1e3 / steps, "value": rate,
             "unit": "site-matvecs/s", "per_packet_contexts": {"ms_per_step": seq * 1e3 / seq_steps,
                                                               "value": seq_rate},
-            "speedup": seq_rate and rate / seq_rate}
+            "speedup": seq_rate and rate / seq_rate,
+            # algorithmic bytes of a mixed step: (64 m + 48) per site
+            "hbm_frac_step": round(sites * (64 * m + 48) * steps / wall / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 def main():
@@ -325,8 +352,9 @@ def main():
                     help="steps of the 256-packet batch measurement (0: skip)")
     ap.add_argument("--lowmem-steps", type=int, default=20,
                     help="steps of the memory-saving (second Lanczos run) measurement (0: skip)")
-    ap.add_argument("--extras", default="ktol,adaptive_dt,adjoint,eigen",
-                    help="comma-separated extra measurements: ktol, adaptive_dt, adjoint, eigen (empty: none)")
+    ap.add_argument("--extras", default="ktol,adaptive_dt,chirality,adjoint,eigen",
+                    help="comma-separated extra measurements: ktol, adaptive_dt, chirality, adjoint, eigen "
+                         "(empty: none)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run a plain copy of this many MiB (counter calibration for rocprofv3)")
     args = ap.parse_args()
@@ -449,6 +477,8 @@ def main():
         out["adaptive_k"] = run_ktol(torch, Propagator, cfg, psi0_dev, 100)
     if "adaptive_dt" in extras:
         out["adaptive_dt"] = run_adaptive_dt(torch, Propagator, cfg, psi0_dev)
+    if "chirality" in extras and "mixed" in res:
+        out["chirality_minus"] = run_chirality(torch, Propagator, cfg, psi0_dev)
     if "adjoint" in extras:
         out["adjoint"] = run_adjoint(torch, Propagator, packets)
     if "eigen" in extras:
