@@ -910,8 +910,11 @@ __device__ __forceinline__ void tridiag_body(const double *alpha, const double *
     __shared__ double zpr[(kMaxM + 1) * 64];
     __shared__ double wre[kMaxM], wim[kMaxM];
     const int lane = threadIdx.x;
-    if (sc->status != 0) return;
-    const int k = sc->keff;
+    // every scalar of the step read up front, so the loads overlap (the last
+    // sweep wrote them just before)
+    const int status = sc->status, k = sc->keff;
+    const double sigma = sc->sigma, beta_k = sc->beta_k, ktol = sc->ktol;
+    if (status != 0) return;
     if (k <= 0) {
         for (int j = lane; j < 2 * (kMaxM + 2); j += 64) sc->coef[j] = 0.0;
         if (lane == 0) {
@@ -923,6 +926,7 @@ __device__ __forceinline__ void tridiag_body(const double *alpha, const double *
     }
     double d = (lane < k) ? alpha[lane + 1] : 0.0;
     double e = (lane + 1 < k) ? gamma[lane + 2] : 0.0;  // zero for lanes >= k-1
+    const double gl = (lane < k) ? gamma[lane + 1] : 1.0, g1 = gamma[1];
     double em = from_left(e);                           // e_{j-1}
     if (lane == 0) em = 0.0;
     double cr = 0.0, ci = 0.0;
@@ -1010,20 +1014,19 @@ __device__ __forceinline__ void tridiag_body(const double *alpha, const double *
     if (lane < k) {
         // exp(-iT) = exp(-i sigma) exp(-iT') for the shifted tridiagonal T'
         double ss, sc0;
-        sincos(sc->sigma, &ss, &sc0);
-        const double g1 = gamma[1];
+        sincos(sigma, &ss, &sc0);
         const double tr = g1 * (cr * sc0 + ci * ss), ti = g1 * (ci * sc0 - cr * ss);
-        const double ig = 1.0 / gamma[lane + 1];
+        const double ig = 1.0 / gl;
         sc->coef[2 * (lane + 1)] = tr * ig;
         sc->coef[2 * (lane + 1) + 1] = ti * ig;
         ck = sqrt(tr * tr + ti * ti);
         if (lane == k - 1) {
             sc->cabs_k = ck;
             stat->keff = k;
-            stat->err_est = sc->beta_k * ck;
+            stat->err_est = beta_k * ck;
         }
     }
-    if (sc->ktol > 0.0) predict_k(alpha, gamma, sc, k, lane, sc->beta_k * __shfl(ck, k - 1, 64));
+    if (ktol > 0.0) predict_k(alpha, gamma, sc, k, lane, beta_k * __shfl(ck, k - 1, 64));
 }
 
 __global__ __launch_bounds__(64) void k_tridiag(const double *alpha, const double *gamma, Scalars *sc,
