@@ -200,6 +200,36 @@ def run_chirality(torch, Propagator, cfg, psi0_dev, steps=50):
             "norm_drift": abs(float(st["norm2"][-1]) / n0 - 1.0)}
 
 
+def run_paper_shape(torch, Propagator, packets, steps=10):
+    """The paper's own benchmark shape (Sec. 7): 8192^2 periodic grid, FP64,
+    k = 10, dt = 1e-7, a free packet of mean momentum (100, 0); the paper
+    quotes about two minutes per step for it on one CPU core."""
+    cfg = packets.paper_packet_8192(seed=0)
+    prob, m, dt = cfg["problem"], cfg["m"], cfg["dt"]
+    sites = prob["nx"] * prob["ny"]
+    psi0 = torch.from_numpy(packets.initial_state(cfg)).to("cuda")
+    prop = Propagator(prob, m, "fp64", tuning_cache=True)
+    psi = psi0.clone()
+    prop.step(psi, 0.0, dt, 1, want_stats=False)
+    psi.copy_(psi0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = prop.step(psi, 0.0, dt, steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prop.close()
+    n0 = float(torch.linalg.vector_norm(psi0)) ** 2
+    del psi, psi0
+    ms = wall * 1e3 / steps
+    log(f"paper shape 8192^2 FP64 k={m}: {ms:.2f} ms/step")
+    return {"workload": cfg["name"] + f" (k={m}, dt={dt:g}, {steps} steps)", "ms_per_step": ms,
+            "value": sites * m * steps / wall, "unit": "site-matvecs/s",
+            # algorithmic bytes of an FP64 step: (4 m - 2) complex128 vectors per site
+            "hbm_frac_step": round(sites * 32 * (4 * m - 2) * steps / wall / 1e9 / HBM_PEAK_GBS, 4),
+            "norm_drift": abs(float(st["norm2"][-1]) / n0 - 1.0),
+            "paper_seconds_per_step": 120.0, "ratio_vs_paper_one_core": 120.0 / (ms / 1e3)}
+
+
 def run_ktol(torch, Propagator, cfg, psi0_dev, steps, ktol=1e-12, k_min=4):
     """Adaptive Krylov dimension on the same workload (mixed): the per-step
     estimate bounded by ktol, k in [k_min, 16], against the fixed m = 16."""
@@ -352,9 +382,9 @@ def main():
                     help="steps of the 256-packet batch measurement (0: skip)")
     ap.add_argument("--lowmem-steps", type=int, default=20,
                     help="steps of the memory-saving (second Lanczos run) measurement (0: skip)")
-    ap.add_argument("--extras", default="ktol,adaptive_dt,chirality,adjoint,eigen",
-                    help="comma-separated extra measurements: ktol, adaptive_dt, chirality, adjoint, eigen "
-                         "(empty: none)")
+    ap.add_argument("--extras", default="ktol,adaptive_dt,chirality,paper_shape,adjoint,eigen",
+                    help="comma-separated extra measurements: ktol, adaptive_dt, chirality, paper_shape, "
+                         "adjoint, eigen (empty: none)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run a plain copy of this many MiB (counter calibration for rocprofv3)")
     args = ap.parse_args()
@@ -479,6 +509,8 @@ def main():
         out["adaptive_dt"] = run_adaptive_dt(torch, Propagator, cfg, psi0_dev)
     if "chirality" in extras and "mixed" in res:
         out["chirality_minus"] = run_chirality(torch, Propagator, cfg, psi0_dev)
+    if "paper_shape" in extras:
+        out["paper_shape"] = run_paper_shape(torch, Propagator, packets)
     if "adjoint" in extras:
         out["adjoint"] = run_adjoint(torch, Propagator, packets)
     if "eigen" in extras:

@@ -4,7 +4,8 @@ over every site.
 
 Two steps from t = 0 (the field changes between them); the oracle needs about
 10 s of one CPU core per step at this size.  FP64 must match to 1e-10 relative
-L2, the mixed path (complex64 Krylov vectors) to 1e-6.
+L2, the mixed path (complex64 Krylov vectors) to 1e-6.  Also one step of the
+paper's own 8192^2 benchmark shape.
 """
 import numpy as np
 import pytest
@@ -60,3 +61,28 @@ def test_laser_4096_full_grid(torch_cuda, full, prec, tol):
     assert np.allclose(st["norm2"], rst["norm2"], rtol=tol, atol=0.0)
     # per-step estimates (Sec. 4 eq. matrix_exponential_error): the same size, both far below the tolerance
     assert np.all(st["err_est"] <= np.maximum(10 * rst["err_est"], 1e-4 * tol))
+
+
+def test_paper_shape_8192_one_step(torch_cuda, orc):
+    """The paper's own benchmark shape (Sec. 7: 8192^2, k = 10, dt = 1e-7,
+    periodic, FP64; 2.1 GB per vector) for one step against the oracle over
+    every site (about 30 s of one CPU core)."""
+    from paper_1407_7370_amd.binding import Propagator
+    torch = torch_cuda
+    cfg = packets.paper_packet_8192()
+    psi0 = packets.initial_state(cfg)
+    say(f"paper shape 8192x8192 k={cfg['m']} one step fp64, tuned launch shapes")
+    prop = Propagator(cfg["problem"], cfg["m"], "fp64", tuning_cache=True)
+    psi = torch.from_numpy(psi0).to("cuda")
+    st = prop.step(psi, 0.0, cfg["dt"], 1)
+    got = psi.cpu().numpy()
+    prop.close()
+    del psi
+    say("oracle: paper shape 8192x8192 one step (CPU)")
+    ref, rst = orc.propagate(cfg["problem"], psi0, 0.0, cfg["dt"], 1, cfg["m"])
+    err = hz.rel_l2(got, ref)
+    print(f"8192^2: rel-L2 {err:.3e}", flush=True)
+    assert err <= 1e-10
+    assert np.array_equal(st["k_eff"], rst["k_eff"])
+    assert np.allclose(st["norm2"], rst["norm2"], rtol=1e-12, atol=0.0)
+    assert np.allclose(st["err_est"], rst["err_est"], rtol=1e-6)
