@@ -11,7 +11,7 @@
 // multiple of four so that a workgroup's waves belong to one packet; the
 // workgroups of a packet are a contiguous segment of the grid.  The
 // recombination gives every packet a number of workgroups proportional to its
-// tiles (four workgroups per compute unit in total).
+// tiles (DL_BATCH_COMB_WGS_PER_CU workgroups per compute unit in total).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -19,6 +19,12 @@
 #include <vector>
 
 #include "context.h"
+
+// Workgroups per compute unit of the batched recombination, shared among the
+// packets in proportion to their tiles.
+#ifndef DL_BATCH_COMB_WGS_PER_CU
+#define DL_BATCH_COMB_WGS_PER_CU 4
+#endif
 
 using namespace dlh;
 
@@ -208,7 +214,7 @@ dl_status build_tables(dl_batch *b, int rows_per_chunk)
             tiles[i] = ceil_div((size_t)params[i].nx * params[i].ny, tile);
             total_tiles += tiles[i];
         }
-        const double per = (double)(4 * b->cus) / (double)total_tiles;  // workgroups per tile
+        const double per = (double)(DL_BATCH_COMB_WGS_PER_CU * b->cus) / (double)total_tiles;  // workgroups per tile
         for (int i = 0; i < n; ++i) {
             int nb = (int)std::ceil(per * (double)tiles[i]);
             nb = std::max(1, std::min(nb, (int)tiles[i]));
