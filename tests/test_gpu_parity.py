@@ -169,6 +169,24 @@ def test_small_krylov_dims(torch_cuda, Prop, orc, m):
     assert np.allclose(st["err_est"], rst["err_est"], rtol=1e-6, atol=1e-300)
 
 
+@pytest.mark.parametrize("dt,prec,tol", [(1e-3, "fp64", 1e-10), (1e-2, "fp64", 1e-10), (1e-2, "mixed", 1e-6)])
+def test_max_krylov_dim(torch_cuda, Prop, orc, dt, prec, tol):
+    """The largest Krylov dimension, m = 64 (the small exponential then uses
+    all 64 lanes of its wave): the Chebyshev expansion (dt = 1e-3, R = 20) and
+    the QR eigendecomposition (dt = 1e-2, R = 205), three steps against the
+    oracle."""
+    prob = box(48, 40, 0, bz=0.7, pot_kind=1, pot_z=1.0, pot_a=1.0)
+    psi0 = packets.gaussian_packet(prob, 0.8, (3.0, -2.0))
+    say(f"max Krylov m=64 dt={dt} {prec} 48x40")
+    got, st = gpu_run(torch_cuda, Prop, prob, 64, prec, psi0, 0.0, dt, 3)
+    ref, rst = orc.propagate(prob, psi0, 0.0, dt, 3, 64)
+    err = hz.rel_l2(got, ref)
+    print(f"m=64 dt={dt} {prec}: rel-L2 {err:.3e}", flush=True)
+    assert err <= tol
+    assert np.all(st["k_eff"] == 64) and np.all(rst["k_eff"] == 64)
+    assert np.allclose(st["norm2"], rst["norm2"], rtol=tol, atol=0.0)
+
+
 @pytest.mark.parametrize("dt", [1e-5, 1e-3, 3e-3, 1e-2, 3e-2])
 def test_small_exponential_ranges(torch_cuda, Prop, orc, dt):
     """The half-width R of the spectrum of the shifted T grows with dt
