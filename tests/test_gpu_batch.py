@@ -104,6 +104,26 @@ def test_batch_mixed_vs_single(torch_cuda):
         assert rel(outb[i], ref) <= 1e-6, i
 
 
+@pytest.mark.parametrize("m", [1, 2, 64])
+def test_batch_krylov_extremes(torch_cuda, m):
+    """The smallest Krylov dimensions (m = 1: iteration 1 alone; m = 2: no
+    recurrence sweep beyond iteration 2) and the largest (m = 64; the 8x8
+    packet, whose positive-energy space has 64 states, is left out there):
+    every packet against its single-grid run."""
+    probs = small_batch(0)
+    if m == 64:
+        probs = [p for p in probs if p["nx"] * p["ny"] > 64]
+    psi0 = states(probs, 30)
+    dt, n = 1e-3, 4
+    say(f"batch fp64 m={m} {len(probs)} packets {n} steps")
+    outb, stb = run_batch(torch_cuda, probs, psi0, m, "fp64", dt, n)
+    for i, p in enumerate(probs):
+        outs, sts = run_single(torch_cuda, p, psi0[i], m, "fp64", dt, n)
+        assert rel(outb[i], outs) <= 1e-11, (m, i)
+        assert np.array_equal(stb[i]["k_eff"], sts["k_eff"])
+        np.testing.assert_allclose(stb[i]["norm2"], sts["norm2"], rtol=1e-12)
+
+
 def test_batch_odd_and_even_step_counts(torch_cuda):
     """The ping-pong between psi and the workspace ends in psi for both parities."""
     probs = small_batch(0)[:3]
