@@ -1083,6 +1083,20 @@ __device__ __forceinline__ void combine_body(const CombArgs &a, int blk, int nbl
 {
     const Scalars *sc = a.sc;
     const int k = sc->keff;
+    // complex64 form: the coefficients c_j / gamma_j staged once per workgroup
+    // in LDS (the FP64 form reads them from the scalars)
+    constexpr bool kPairs = sizeof(TB) == 8;
+    __shared__ double cs[kPairs ? 2 * (kMaxM + 2) : 1];
+    if constexpr (kPairs) {
+        for (int i = threadIdx.x; i < 2 * (k + 1); i += kBlock) cs[i] = sc->coef[i];
+        __syncthreads();
+    }
+    auto cf = [&](int i) -> double {
+        if constexpr (kPairs)
+            return cs[i];
+        else
+            return sc->coef[i];
+    };
     const char *__restrict__ basis = static_cast<const char *>(a.basis);
     const size_t sites = a.sites;
     const size_t tile = (size_t)kBlock * S;
@@ -1090,7 +1104,7 @@ __device__ __forceinline__ void combine_body(const CombArgs &a, int blk, int nbl
     for (size_t s0 = (size_t)blk * tile; s0 < sites; s0 += (size_t)nblk * tile) {
         Sp acc[S];
         {
-            const double cr = k >= 1 ? sc->coef[2] : 0.0, ci = k >= 1 ? sc->coef[3] : 0.0;
+            const double cr = k >= 1 ? cf(2) : 0.0, ci = k >= 1 ? cf(3) : 0.0;
 #pragma unroll
             for (int q = 0; q < S; ++q) {
                 const size_t s = s0 + (size_t)q * kBlock + threadIdx.x;
@@ -1105,22 +1119,59 @@ __device__ __forceinline__ void combine_body(const CombArgs &a, int blk, int nbl
                 acc[q].i1 = cr * p1.y + ci * p1.x;
             }
         }
-        for (int j = 2; j <= k; ++j) {
-            const char *u = basis + (size_t)(j - 2) * a.vec_bytes;
-            Raw<TB> v[S];
+        if constexpr (kPairs) {
+            auto load = [&](int j, Raw<TB>(&v)[S]) {
+                const char *u = basis + (size_t)(j - 2) * a.vec_bytes;
 #pragma unroll
-            for (int q = 0; q < S; ++q) {
-                const size_t s = s0 + (size_t)q * kBlock + threadIdx.x;
-                v[q] = s < sites ? ld_site<TB>(u + s * kSite) : raw_zero<TB>();
+                for (int q = 0; q < S; ++q) {
+                    const size_t s = s0 + (size_t)q * kBlock + threadIdx.x;
+                    v[q] = s < sites ? ld_site<TB>(u + s * kSite) : raw_zero<TB>();
+                }
+            };
+            auto add = [&](int j, const Raw<TB>(&v)[S]) {
+                const double cr = cf(2 * j), ci = cf(2 * j + 1);
+#pragma unroll
+                for (int q = 0; q < S; ++q) {
+                    const Sp w = to_sp(v[q]);
+                    acc[q].r0 += cr * w.r0 - ci * w.i0;
+                    acc[q].i0 += cr * w.i0 + ci * w.r0;
+                    acc[q].r1 += cr * w.r1 - ci * w.i1;
+                    acc[q].i1 += cr * w.i1 + ci * w.r1;
+                }
+            };
+            // two vectors at a time, so that 2S loads are in flight before
+            // the arithmetic (the terms are still added in order j = 2..k)
+            int j = 2;
+            for (; j + 1 <= k; j += 2) {
+                Raw<TB> v0[S], v1[S];
+                load(j, v0);
+                load(j + 1, v1);
+                add(j, v0);
+                add(j + 1, v1);
             }
-            const double cr = sc->coef[2 * j], ci = sc->coef[2 * j + 1];
+            if (j <= k) {
+                Raw<TB> v[S];
+                load(j, v);
+                add(j, v);
+            }
+        } else {
+            for (int j = 2; j <= k; ++j) {
+                const char *u = basis + (size_t)(j - 2) * a.vec_bytes;
+                Raw<TB> v[S];
 #pragma unroll
-            for (int q = 0; q < S; ++q) {
-                const Sp w = to_sp(v[q]);
-                acc[q].r0 += cr * w.r0 - ci * w.i0;
-                acc[q].i0 += cr * w.i0 + ci * w.r0;
-                acc[q].r1 += cr * w.r1 - ci * w.i1;
-                acc[q].i1 += cr * w.i1 + ci * w.r1;
+                for (int q = 0; q < S; ++q) {
+                    const size_t s = s0 + (size_t)q * kBlock + threadIdx.x;
+                    v[q] = s < sites ? ld_site<TB>(u + s * kSite) : raw_zero<TB>();
+                }
+                const double cr = sc->coef[2 * j], ci = sc->coef[2 * j + 1];
+#pragma unroll
+                for (int q = 0; q < S; ++q) {
+                    const Sp w = to_sp(v[q]);
+                    acc[q].r0 += cr * w.r0 - ci * w.i0;
+                    acc[q].i0 += cr * w.i0 + ci * w.r0;
+                    acc[q].r1 += cr * w.r1 - ci * w.i1;
+                    acc[q].i1 += cr * w.i1 + ci * w.r1;
+                }
             }
         }
 #pragma unroll
@@ -1228,8 +1279,8 @@ __global__ __launch_bounds__(kBlock) void k_accum(AccumArgs a)
     }
 }
 
-// sites per thread of the recombination and the occupancy asked for (five
-// waves per SIMD fit the complex64 form without spills)
+// sites per thread of the recombination and the occupancy asked for (the
+// complex64 form with two vectors in flight: four waves per SIMD)
 #ifndef DL_COMB_S_MIXED
 #define DL_COMB_S_MIXED 4
 #endif
@@ -1238,7 +1289,10 @@ __global__ __launch_bounds__(kBlock) void k_accum(AccumArgs a)
 #endif
 constexpr int kCombMixed = DL_COMB_S_MIXED;
 constexpr int kCombFp64 = 8;
-constexpr int kCombWpeMixed = 5;
+#ifndef DL_COMB_WPE_MIXED
+#define DL_COMB_WPE_MIXED 4
+#endif
+constexpr int kCombWpeMixed = DL_COMB_WPE_MIXED;
 constexpr int kCombWpeFp64 = 1;
 
 // ---------------------------------------------------------------------------
