@@ -34,6 +34,7 @@ constexpr int kDotVecs = DL_DOT_VECS;  // basis vectors per workgroup of a proje
 // measured on 1024^2 with K = 500: 2048 -> 3.30 s, 4096 -> 3.26 s, 8192 -> 3.21 s
 constexpr int kProjWorkgroups = DL_PROJ_WORKGROUPS;
 constexpr int kSubChunk = 256;  // coefficients staged in LDS per chunk of the update
+static_assert(kSubChunk % kDotVecs == 0, "the update pads a chunk to whole groups of kDotVecs");
 constexpr int kRitzChunk = 64;  // basis rows of t staged in LDS per chunk
 
 __device__ __forceinline__ const double2 *qvec(const char *q, size_t vstride, int j)
