@@ -138,3 +138,12 @@ def test_autotune_cache_roundtrip(tmp_path):
     assert autotune.lookup(ka, cache) == 6
     assert autotune.lookup(kbat, cache) == 64
     assert autotune.lookup(kb, cache) is None
+
+
+def test_missing_library_raises(monkeypatch, tmp_path):
+    """No CPU fallback: without the built HIP library the binding refuses to load."""
+    from paper_1407_7370_amd import binding
+    monkeypatch.setattr(binding, "_lib", None)
+    monkeypatch.setattr(binding, "LIB_PATH", str(tmp_path / "libdirac_lanczos.so"))
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        binding.load_library()
