@@ -274,7 +274,11 @@ dl_status dirac_lanczos_eigen_vectors(dl_context *ctx, const void *psi0, int32_t
  * spaces of step n (the forward one of psi_n and the backward one of
  * lam_{n+1}), with the divided difference of exp(-i .) between their Ritz
  * values.  States psi_n are stored every ckpt_every steps during the forward
- * pass and recomputed segment by segment during the backward pass.
+ * pass and recomputed segment by segment during the backward pass.  When the
+ * forward Krylov bases of one segment (ckpt_every * (krylov_dim - 1)
+ * vectors) fit in 32 GiB, the workspace also holds them, and the backward
+ * pass uses the bases of the recomputation instead of building them again
+ * (the same result, bit for bit; the workspace size reflects the choice).
  *
  * Requirements: precision DL_PREC_FP64, krylov_dim <= 16, pulse_kind
  * DL_PULSE_FOURIER_SIN2, loss_kind in 1..15, n_steps >= 1, ckpt_every >= 1,

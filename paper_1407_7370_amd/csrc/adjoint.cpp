@@ -44,10 +44,22 @@ namespace {
 constexpr int kContractBlocks = 1024;
 constexpr int kObserveBlocks = 1024;
 
+// Largest store of one segment's forward Krylov bases (see AdjLayout::keep).
+#ifndef DL_ADJ_KEEP_GIB
+#define DL_ADJ_KEEP_GIB 32
+#endif
+constexpr size_t kKeepBasesBytes = size_t(DL_ADJ_KEEP_GIB) << 30;
+
 struct AdjLayout {
     size_t sc = 0, alpha = 0, gamma = 0, obs = 0, fields = 0, cpart = 0, rec = 0, basis = 0, lam = 0,
-           seg = 0, ckpt = 0, total = 0;
+           seg = 0, ckpt = 0, kbasis = 0, kscal = 0, total = 0;
     int seglen = 0, nseg = 0;
+    // keep: the forward sweep of a segment leaves every step's Krylov basis
+    // (kbasis, kb_stride apart) and its scalars, alpha and gamma (kscal,
+    // ks_stride apart) in place, so the backward pass does not build them
+    // again; only when one segment's bases fit in kKeepBasesBytes.
+    bool keep = false;
+    size_t kb_stride = 0, ks_stride = 0, ks_alpha = 0, ks_gamma = 0;
 };
 
 AdjLayout adj_plan(const dl_params &p, int n_steps, int ckpt_every)
@@ -81,6 +93,18 @@ AdjLayout adj_plan(const dl_params &p, int n_steps, int ckpt_every)
     off += (size_t)(A.seglen + 1) * vb;
     A.ckpt = off;
     off += (size_t)(A.nseg - 1) * vb;  // starts of segments 1 .. nseg-1 (segment 0 starts at psi0)
+    A.kb_stride = (size_t)(m - 1) * vec_stride(n, 16);
+    A.keep = A.kb_stride * (size_t)A.seglen <= kKeepBasesBytes;
+    if (A.keep) {
+        A.ks_alpha = align256(sizeof(dl::Scalars));
+        A.ks_gamma = A.ks_alpha + align256(sizeof(double) * (m + 3));
+        A.ks_stride = A.ks_gamma + align256(sizeof(double) * (m + 3));
+        off = align256(off);
+        A.kbasis = off;
+        off += A.kb_stride * (size_t)A.seglen;
+        A.kscal = off;
+        off += A.ks_stride * (size_t)A.seglen;
+    }
     A.total = off;
     return A;
 }
@@ -241,14 +265,32 @@ dl_status dirac_lanczos_adjoint(dl_context *ctx, const void *psi0_v, double t0, 
     const int C = A.seglen, G = A.nseg;
     auto seg_len = [&](int g) { return std::min(C, n_steps - g * C); };
     // forward states of segment g into seg(0..len)
+    // step i of a segment: its own basis when the bases are kept, else the context's
+    auto step_engine = [&](int i) {
+        Engine e = ep;
+        if (A.keep) e.basis = aw + A.kbasis + (size_t)i * A.kb_stride;
+        return e;
+    };
+    auto kept_scal = [&](int i) { return aw + A.kscal + (size_t)i * A.ks_stride; };
     auto run_segment = [&](int g) -> dl_status {
         const int len = seg_len(g);
         DL_HIP(ctx, hipMemcpyAsync(seg(0), ckpt(g), n * 16, hipMemcpyDeviceToDevice, st));
         for (int i = 0; i < len; ++i) {
             const double *fp = fields + 4 * (size_t)(g * C + i);
-            const dl_status sb = run_build(ctx, ep, opf, seg(i), fp, partials, 1);
+            const Engine ei = step_engine(i);
+            const dl_status sb = run_build(ctx, ei, opf, seg(i), fp, partials, 1);
             if (sb != DL_OK) return sb;
-            const dl_status sf = run_finish(ctx, ep, seg(i), seg(i + 1), dstat, partials);
+            if (A.keep) {
+                // what the backward contraction reads of this step: k_eff, shift,
+                // status, alpha and gamma (the small exponential leaves them alone)
+                char *ks = kept_scal(i);
+                DL_HIP(ctx, hipMemcpyAsync(ks, ep.sc, sizeof(dl::Scalars), hipMemcpyDeviceToDevice, st));
+                DL_HIP(ctx, hipMemcpyAsync(ks + A.ks_alpha, ep.alpha, sizeof(double) * (m + 3),
+                                           hipMemcpyDeviceToDevice, st));
+                DL_HIP(ctx, hipMemcpyAsync(ks + A.ks_gamma, ep.gamma, sizeof(double) * (m + 3),
+                                           hipMemcpyDeviceToDevice, st));
+            }
+            const dl_status sf = run_finish(ctx, ei, seg(i), seg(i + 1), dstat, partials);
             if (sf != DL_OK) return sf;
         }
         DL_HIP(ctx, hipGetLastError());
@@ -302,23 +344,34 @@ dl_status dirac_lanczos_adjoint(dl_context *ctx, const void *psi0_v, double t0, 
         }
         for (int i = len - 1; i >= 0; --i) {
             const size_t ns = (size_t)g * C + i;
-            dl_status s = run_build(ctx, ep, opf, seg(i), fields + 4 * ns, partials, 1);
-            if (s != DL_OK) return s;
+            dl_status s = DL_OK;
+            const Engine ei = step_engine(i);
+            if (!A.keep) {
+                s = run_build(ctx, ei, opf, seg(i), fields + 4 * ns, partials, 1);
+                if (s != DL_OK) return s;
+            }
             s = run_build(ctx, el, opb, lam(cur), fields + 4 * ns + 2, partials, 1);
             if (s != DL_OK) return s;
             dl::ContractArgs ca{};
             ca.lam1 = lam(cur);
             ca.lam_basis = el.basis;
             ca.psi1 = seg(i);
-            ca.psi_basis = ep.basis;
+            ca.psi_basis = ei.basis;
             ca.vec_bytes = vstride;
             ca.sites = sites;
             ca.sc_lam = el.sc;
-            ca.sc_psi = ep.sc;
             ca.alpha_lam = el.alpha;
             ca.gamma_lam = el.gamma;
-            ca.alpha_psi = ep.alpha;
-            ca.gamma_psi = ep.gamma;
+            if (A.keep) {
+                char *ks = kept_scal(i);
+                ca.sc_psi = reinterpret_cast<const dl::Scalars *>(ks);
+                ca.alpha_psi = reinterpret_cast<const double *>(ks + A.ks_alpha);
+                ca.gamma_psi = reinterpret_cast<const double *>(ks + A.ks_gamma);
+            } else {
+                ca.sc_psi = ep.sc;
+                ca.alpha_psi = ep.alpha;
+                ca.gamma_psi = ep.gamma;
+            }
             ca.partials = cpart;
             ca.rec = rec + (size_t)i * dl::kRecLen;
             dl::launch_contract(ca, ncb, st);
