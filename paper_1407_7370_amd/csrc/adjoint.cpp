@@ -283,12 +283,7 @@ dl_status dirac_lanczos_adjoint(dl_context *ctx, const void *psi0_v, double t0, 
             if (A.keep) {
                 // what the backward contraction reads of this step: k_eff, shift,
                 // status, alpha and gamma (the small exponential leaves them alone)
-                char *ks = kept_scal(i);
-                DL_HIP(ctx, hipMemcpyAsync(ks, ep.sc, sizeof(dl::Scalars), hipMemcpyDeviceToDevice, st));
-                DL_HIP(ctx, hipMemcpyAsync(ks + A.ks_alpha, ep.alpha, sizeof(double) * (m + 3),
-                                           hipMemcpyDeviceToDevice, st));
-                DL_HIP(ctx, hipMemcpyAsync(ks + A.ks_gamma, ep.gamma, sizeof(double) * (m + 3),
-                                           hipMemcpyDeviceToDevice, st));
+                dl::launch_keep_step(ep.sc, ep.alpha, ep.gamma, m + 3, kept_scal(i), A.ks_alpha, A.ks_gamma, st);
             }
             const dl_status sf = run_finish(ctx, ei, seg(i), seg(i + 1), dstat, partials);
             if (sf != DL_OK) return sf;

@@ -163,6 +163,9 @@ struct ContractArgs {
     double *rec;       // record of this step (kRecLen doubles)
 };
 void launch_contract(const ContractArgs &a, int nblocks, hipStream_t st);
+// dst <- the scalars (raw), alpha[0..nab) at dst + off_alpha, gamma[0..nab) at dst + off_gamma
+void launch_keep_step(const Scalars *sc, const double *alpha, const double *gamma, int nab, char *dst,
+                      size_t off_alpha, size_t off_gamma, hipStream_t st);
 
 void launch_first(const Op &op, const Tiles &t, const double2 *psi, const double *field,
                   double *alpha, double *gamma, Scalars *sc, double *partials, int m,
