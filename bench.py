@@ -36,6 +36,18 @@ KERNEL_SRCS = [os.path.join(ROOT, "paper_1407_7370_amd", "csrc", f)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_recur_laser4096.json")
 
 
+def cpu_model():
+    """The host CPU's model name (Linux), for the CPU baseline."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -526,7 +538,8 @@ def main():
         out["cpu_baseline"] = {"value": sites * m / cw, "unit": "site-matvecs/s", "cores": 1,
                                "kind": "oracle",
                                "sample": f"one time step (m={m}) of the {nx}x{ny} laser workload, "
-                                         f"single-threaded C oracle, {cw:.1f} s"}
+                                         f"single-threaded C oracle, {cw:.1f} s",
+                               "cpu": cpu_model()}
     print(json.dumps(out), flush=True)
 
 
