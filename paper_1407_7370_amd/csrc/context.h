@@ -131,7 +131,9 @@ struct dl_context {
     dl::Tiles tiles_first{}, tiles_recur{}, tiles_p2{}, tiles_p3{}, tiles_apply{};
     // tiles of recurrence sweep p (each sweep kind has its own occupancy)
     const dl::Tiles &tiles_pass(int p) const { return p == 2 ? tiles_p2 : (p == 3 ? tiles_p3 : tiles_recur); }
-    int combine_blocks = 1024;
+    int combine_blocks = 1024;       // recombination (narrow form) and second-run accumulation
+    bool combine_wide = false;       // recombination in the wide complex64 form
+    int combine_blocks_wide = 1024;  // its workgroups
     int sweep_waves = 8;  // waves per compute unit of the sweeps (launch shape)
     std::vector<double> host_fields;
     std::vector<dl::StepStat> host_stats;

@@ -173,7 +173,8 @@ void launch_first(const Op &op, const Tiles &t, const double2 *psi, const double
 void launch_recur(const PassArgs &a, bool mixed, hipStream_t st);
 void launch_tridiag(const double *alpha, const double *gamma, Scalars *sc, StepStat *stat,
                     hipStream_t st);
-void launch_combine(const CombArgs &a, bool mixed, int nblocks, hipStream_t st);
+// wide: the complex64 form with 16 sites per thread (see combine_wide)
+void launch_combine(const CombArgs &a, bool mixed, bool wide, int nblocks, hipStream_t st);
 void launch_apply(const Op &op, const Tiles &t, const double2 *x, double2 *y, double gxh,
                   double gyh, hipStream_t st);
 void launch_reset(Scalars *sc, hipStream_t st);
@@ -240,8 +241,12 @@ int batch_waves_per_cu(int which, bool mixed, bool py, int terms);
 int combine_tile_sites(bool mixed);
 
 Tiles make_tiles(int nx, int ny, int halo, int target_waves);
-// Workgroups of the recombination for `sites` sites (<= kMaxBlocks).
-int combine_grid(size_t sites, bool mixed, int cus);
+// Whether the recombination of `sites` sites uses the wide complex64 form
+// (at least one wide tile per compute unit).
+bool combine_wide(size_t sites, bool mixed, int cus);
+// Workgroups of the recombination for `sites` sites (<= kMaxBlocks); wide as
+// above (the second Lanczos run's accumulation uses the narrow form).
+int combine_grid(size_t sites, bool mixed, int cus, bool wide);
 // Resident waves per compute unit of a kernel family: 0 first iteration,
 // 1 recurrence sweep p >= 4, 2 sweep p = 2, 3 sweep p = 3, 4 apply; py:
 // periodic in y, terms: site-dependent terms (sweep_terms).

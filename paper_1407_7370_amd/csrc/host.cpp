@@ -431,7 +431,9 @@ dl_status run_finish(dl_context *ctx, const Engine &e, const double2 *in, double
     r.sc = e.sc;
     r.partials = partials;
     r.stat = stat;
-    DL_HIP(ctx, ctx->timed(4, [&] { dl::launch_combine(r, e.mixed, ctx->combine_blocks, st); }));
+    DL_HIP(ctx, ctx->timed(4, [&] {
+        dl::launch_combine(r, e.mixed, ctx->combine_wide, ctx->combine_blocks_wide, st);
+    }));
     return DL_OK;
 }
 
@@ -489,7 +491,9 @@ void set_tiles(dl_context *ctx, int cap)
     ctx->tiles_p2 = dl::make_tiles(p.nx, p.ny, 2, w2 * ctx->cus * DL_RECUR_ROUNDS);
     ctx->tiles_p3 = dl::make_tiles(p.nx, p.ny, 2, w3 * ctx->cus * DL_RECUR_ROUNDS);
     ctx->tiles_apply = dl::make_tiles(p.nx, p.ny, 1, wa * ctx->cus);
-    ctx->combine_blocks = dl::combine_grid(vec_elems(p) / 2, mixed, ctx->cus);
+    ctx->combine_blocks = dl::combine_grid(vec_elems(p) / 2, mixed, ctx->cus, false);
+    ctx->combine_wide = dl::combine_wide(vec_elems(p) / 2, mixed, ctx->cus);
+    ctx->combine_blocks_wide = dl::combine_grid(vec_elems(p) / 2, mixed, ctx->cus, ctx->combine_wide);
 }
 
 }  // namespace

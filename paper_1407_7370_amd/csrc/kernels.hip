@@ -29,11 +29,16 @@ int sweep_waves_per_cu(int which, bool mixed, bool py, int terms)
 
 int sweep_terms(const Op &op) { return op_terms(op); }
 
-int combine_grid(size_t sites, bool mixed, int cus)
+bool combine_wide(size_t sites, bool mixed, int cus)
+{
+    return mixed && sites >= (size_t)cus * kBlock * kCombMixedWide;
+}
+
+int combine_grid(size_t sites, bool mixed, int cus, bool wide)
 {
     // a fixed number of workgroups per compute unit (four measured best for
     // the tiled stream), never more than there are tiles
-    const size_t tile = (size_t)kBlock * (mixed ? kCombMixed : kCombFp64);
+    const size_t tile = (size_t)kBlock * (wide ? kCombMixedWide : (mixed ? kCombMixed : kCombFp64));
     size_t nb = std::min<size_t>((size_t)DL_COMB_BLOCKS_PER_CU * cus, (sites + tile - 1) / tile);
     nb = std::max<size_t>(nb, 1);
     return (int)std::min<size_t>(nb, kMaxBlocks);
@@ -93,9 +98,12 @@ void launch_tridiag(const double *alpha, const double *gamma, Scalars *sc, StepS
     hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(64), 0, st, alpha, gamma, sc, stat);
 }
 
-void launch_combine(const CombArgs &a, bool mixed, int nblocks, hipStream_t st)
+void launch_combine(const CombArgs &a, bool mixed, bool wide, int nblocks, hipStream_t st)
 {
-    if (mixed)
+    if (mixed && wide)
+        hipLaunchKernelGGL((k_combine<float2, kCombMixedWide, kCombWpeMixedWide>), dim3(nblocks), dim3(kBlock), 0,
+                           st, a);
+    else if (mixed)
         hipLaunchKernelGGL((k_combine<float2, kCombMixed, kCombWpeMixed>), dim3(nblocks), dim3(kBlock), 0, st, a);
     else
         hipLaunchKernelGGL((k_combine<double2, kCombFp64, kCombWpeFp64>), dim3(nblocks), dim3(kBlock), 0, st, a);

@@ -1280,14 +1280,21 @@ __global__ __launch_bounds__(kBlock) void k_accum(AccumArgs a)
 }
 
 // sites per thread of the recombination and the occupancy asked for (the
-// complex64 form with two vectors in flight: four waves per SIMD)
+// complex64 form with two vectors in flight: four waves per SIMD; its wide
+// form, for grids of at least one wide tile per compute unit and for
+// batches, holds 16 sites per thread at one wave per SIMD)
 #ifndef DL_COMB_S_MIXED
 #define DL_COMB_S_MIXED 4
+#endif
+#ifndef DL_COMB_S_MIXED_WIDE
+#define DL_COMB_S_MIXED_WIDE 16
 #endif
 #ifndef DL_COMB_BLOCKS_PER_CU
 #define DL_COMB_BLOCKS_PER_CU 4
 #endif
 constexpr int kCombMixed = DL_COMB_S_MIXED;
+constexpr int kCombMixedWide = DL_COMB_S_MIXED_WIDE;
+constexpr int kCombWpeMixedWide = 1;
 constexpr int kCombFp64 = 8;
 #ifndef DL_COMB_WPE_MIXED
 #define DL_COMB_WPE_MIXED 4
