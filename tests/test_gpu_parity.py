@@ -343,6 +343,23 @@ def test_mixed_vs_fp64_reduced(torch_cuda, Prop, orc):
     assert np.all(smx["k_eff"] == 16)
 
 
+def test_wide_recombination_ragged(torch_cuda, Prop, orc):
+    """A mixed-precision grid above the size where the recombination switches
+    to 16 sites per thread (one wide tile per compute unit: 1,048,576 sites
+    on 256 CUs), with a partial last tile: two steps against the oracle."""
+    cfg = packets.with_grid(packets.laser_4096(), 1100)
+    prob = dict(cfg["problem"], ny=997, t_pulse=50 * cfg["dt"])
+    assert prob["nx"] * prob["ny"] > 256 * 256 * 16 and (prob["nx"] * prob["ny"]) % 4096 != 0
+    say("wide recombination 1100x997 mixed m=16 2 steps")
+    psi0 = packets.initial_state(dict(cfg, problem=prob))
+    got, st = gpu_run(torch_cuda, Prop, prob, 16, "mixed", psi0, 0.0, cfg["dt"], 2)
+    ref, rst = orc.propagate(prob, psi0, 0.0, cfg["dt"], 2, 16)
+    err = hz.rel_l2(got, ref)
+    print(f"1100x997 mixed: rel-L2 {err:.3e}", flush=True)
+    assert err <= 1e-6
+    np.testing.assert_allclose(st["norm2"], rst["norm2"], rtol=1e-6)
+
+
 # ---------------------------------------------------------------------------
 # Eigenvalue mode
 # ---------------------------------------------------------------------------
