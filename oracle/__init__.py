@@ -11,6 +11,7 @@ Functions take a plain ``dict`` describing the physical problem (the keys of
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -75,6 +76,8 @@ def _load():
         lib.orc_field_average.argtypes = [P, ctypes.c_double, ctypes.c_double, D]
         lib.orc_lanczos.argtypes = [P, D, ctypes.c_double, D, ctypes.c_int, ctypes.c_int, D, D, D]
         lib.orc_lanczos.restype = ctypes.c_int
+        lib.orc_lanczos_plain.argtypes = [P, D, ctypes.c_double, D, ctypes.c_int, D, D]
+        lib.orc_lanczos_plain.restype = ctypes.c_int
         lib.orc_tridiag_eig.argtypes = [ctypes.c_int, D, D, D, D]
         lib.orc_expm_e1.argtypes = [ctypes.c_int, D, D, ctypes.c_double, D]
         lib.orc_propagate.argtypes = [P, D, ctypes.c_double, ctypes.c_double, ctypes.c_int,
@@ -176,6 +179,69 @@ def lanczos(prob: dict, psi: np.ndarray, k: int, dt: float = 1.0, a_hom=(0.0, 0.
     keff = lib.orc_lanczos(pb.ref, _dp(a), float(dt), _dp(psi.view(np.float64)), int(k),
                            int(bool(reorth)), _dp(Q.view(np.float64)), _dp(al), _dp(be))
     return keff, Q[:keff], al[:keff], be[:keff]
+
+
+def lanczos_plain(prob: dict, psi: np.ndarray, k: int, dt: float = 1.0, a_hom=(0.0, 0.0)):
+    """The recurrence of ``lanczos`` (no reorthogonalisation) with three stored
+    vectors: returns (k_eff, alpha[k_eff], beta[k_eff]) only."""
+    lib = _load()
+    pb = _Problem(prob)
+    psi = _check_psi(prob, psi)
+    al = np.zeros(k)
+    be = np.zeros(k)
+    a = np.array(a_hom, dtype=np.float64)
+    keff = lib.orc_lanczos_plain(pb.ref, _dp(a), float(dt), _dp(psi.view(np.float64)), int(k), _dp(al),
+                                 _dp(be))
+    return keff, al[:keff], be[:keff]
+
+
+def ritz_clusters(alpha, beta, e_lo: float, e_hi: float, tol: float, max_out: int = 64):
+    """Ritz values of T_k (diagonal alpha, off-diagonal beta[:-1]) in
+    [e_lo, e_hi] with the bound of Sec. 2 eq. error_est, |beta_k| times the
+    last eigenvector components, taken over clusters of neighbours closer than
+    tol (a converged value and its copies after the loss of orthogonality form
+    one cluster).  Clusters with bound <= tol are returned ascending as their
+    mean: (values, bounds).  The eigenpairs of T come from LAPACK's tridiagonal
+    solver (scipy eigh_tridiagonal), restricted to the window."""
+    from scipy.linalg import eigh_tridiagonal
+
+    al = np.asarray(alpha, dtype=np.float64)
+    be = np.asarray(beta, dtype=np.float64)
+    k = len(al)
+    if k == 0:
+        return np.zeros(0), np.zeros(0)
+    if k == 1:
+        lam, last = al.copy(), np.ones(1)
+        keep = (lam >= e_lo) & (lam <= e_hi)
+        lam, last = lam[keep], last[keep]
+    else:
+        lam, vec = eigh_tridiagonal(al, be[:k - 1], select="v", select_range=(e_lo, e_hi))
+        last = vec[k - 1, :] if len(lam) else np.zeros(0)
+    order = np.argsort(lam, kind="stable")
+    lam, last = lam[order], last[order]
+    vals, bnds = [], []
+    a = 0
+    while a < len(lam):
+        b = a + 1
+        while b < len(lam) and lam[b] - lam[b - 1] <= tol:
+            b += 1
+        bound = abs(be[k - 1]) * math.sqrt(float(np.sum(last[a:b] ** 2)))
+        if bound <= tol and len(vals) < max_out:
+            vals.append(float(np.mean(lam[a:b])))
+            bnds.append(bound)
+        a = b
+    return np.array(vals), np.array(bnds)
+
+
+def eigen_plain(prob: dict, psi0: np.ndarray, k: int, e_lo: float, e_hi: float, tol: float,
+                max_out: int = 64):
+    """Eigenvalue mode without reorthogonalisation at any grid size: k
+    iterations of the three-vector recurrence on H (fields at t = 0), then the
+    converged Ritz clusters of T_k in the window (``ritz_clusters``).
+    Returns (values, bounds, k_eff)."""
+    keff, al, be = lanczos_plain(prob, psi0, k)
+    ev, bd = ritz_clusters(al, be, e_lo, e_hi, tol, max_out)
+    return ev, bd, keff
 
 
 def tridiag_eig(alpha, beta):

@@ -28,6 +28,8 @@
  *   orc_propagate     Sec. 4, eq. matrix_exp_approx, error estimate
  *                     eq. matrix_exponential_error and its cumulative sum
  *                     (Sec. 6).
+ *   orc_lanczos_plain Sec. 2, the same recurrence with three stored vectors
+ *                     (no reorthogonalisation; eigenvalue mode at scale).
  *   orc_eigen         Sec. 2, Ritz values and bound eq. error_est; Sec. 5.
  *   orc_eigen_vectors Sec. 2 eq. eigenvec_approx (Ritz vectors, full reorth).
  *
@@ -327,6 +329,55 @@ int orc_lanczos(const orc_params *p, const double *a_hom, double dt, const doubl
         apply_a(p, a_hom, dt, qn, z);
         for (size_t t = 0; t < n; ++t) z[t] -= beta[i - 1] * qi[t];
     }
+    free(z);
+    return keff;
+}
+
+/*
+ * Plain Lanczos recurrence with three stored vectors (Sec. 2: without
+ * reorthogonalisation only q_{i-1}, q_i and z are needed; the Ritz values
+ * follow from alpha and beta alone).  The loop is the one of orc_lanczos with
+ * reorth = 0 -- the same operations in the same order -- so alpha and beta
+ * agree with it bit for bit; only the storage differs.  Used by the eigenvalue
+ * mode on grids where k stored vectors would not fit in memory.  Returns
+ * k_eff (0 for b = 0); alpha[0..k_eff-1], beta[0..k_eff-1] (beta[k_eff-1] is
+ * ||z - alpha_k q_k|| after the last iteration, the input of eq. error_est).
+ */
+int orc_lanczos_plain(const orc_params *p, const double *a_hom, double dt, const double *b_d, int k,
+                      double *alpha, double *beta)
+{
+    const size_t n = (size_t)2 * p->nx * p->ny;
+    const cplx *b = (const cplx *)b_d;
+    const double nb = vnorm(n, b);
+    if (nb == 0.0) return 0;
+    cplx *qprev = (cplx *)malloc(n * sizeof(cplx));
+    cplx *qcur = (cplx *)malloc(n * sizeof(cplx));
+    cplx *z = (cplx *)malloc(n * sizeof(cplx));
+    for (size_t t = 0; t < n; ++t) qcur[t] = b[t] / nb;
+    apply_a(p, a_hom, dt, qcur, z);
+    double scale = 0.0;
+    int keff = k;
+    for (int i = 1; i <= k; ++i) {
+        alpha[i - 1] = creal(vdot(n, qcur, z));
+        for (size_t t = 0; t < n; ++t) z[t] -= alpha[i - 1] * qcur[t];
+        beta[i - 1] = vnorm(n, z);
+        if (fabs(alpha[i - 1]) > scale) scale = fabs(alpha[i - 1]);
+        if (i > 1 && beta[i - 2] > scale) scale = beta[i - 2];
+        if (i == k) break;
+        if (beta[i - 1] <= 1e-13 * scale) {
+            keff = i;
+            break;
+        }
+        /* q_{i+1} = z / beta_i replaces q_{i-1}; z = A q_{i+1} - beta_i q_i */
+        cplx *qn = qprev;
+        for (size_t t = 0; t < n; ++t) qn[t] = z[t] / beta[i - 1];
+        apply_a(p, a_hom, dt, qn, z);
+        for (size_t t = 0; t < n; ++t) z[t] -= beta[i - 1] * qcur[t];
+        qprev = qcur;
+        qcur = qn;
+    }
+    free(qprev);
+    free(qcur);
     free(z);
     return keff;
 }

@@ -134,18 +134,20 @@ def grid_axes(prob: dict):
 
 def positive_energy_projection(psi: np.ndarray, prob: dict) -> np.ndarray:
     """Project each DFT mode of a (2, ny, nx) spinor onto the positive-energy
-    eigenspace of the free periodic lattice Hamiltonian."""
+    eigenspace of the free periodic lattice Hamiltonian of the problem's
+    chirality (alpha2 = chi sigma2, chi = -1 when prob["chirality"] < 0)."""
     _, _, hx, hy = grid_axes(prob)
     nx, ny = prob["nx"], prob["ny"]
     c, m = prob["c"], prob["mass"]
-    kx = np.sin(2 * np.pi * np.fft.fftfreq(nx) ) / hx  # sin(k h)/h with k h = 2 pi f
-    ky = np.sin(2 * np.pi * np.fft.fftfreq(ny)) / hy
+    chi = -1.0 if prob.get("chirality", 0) < 0 else 1.0
+    kx = np.sin(2 * np.pi * np.fft.fftfreq(nx)) / hx  # sin(k h)/h with k h = 2 pi f
+    ky = chi * np.sin(2 * np.pi * np.fft.fftfreq(ny)) / hy
     KX, KY = np.meshgrid(kx, ky)
     mc2 = m * c * c
     E = np.sqrt(mc2 * mc2 + c * c * (KX * KX + KY * KY))
     f0 = np.fft.fft2(psi[0])
     f1 = np.fft.fft2(psi[1])
-    # H0 = [[mc2, c(kx - i ky)], [c(kx + i ky), -mc2]]
+    # H0 = [[mc2, c(kx - i chi ky)], [c(kx + i chi ky), -mc2]] (chi folded into KY)
     g0 = 0.5 * (f0 + (mc2 * f0 + c * (KX - 1j * KY) * f1) / E)
     g1 = 0.5 * (f1 + (c * (KX + 1j * KY) * f0 - mc2 * f1) / E)
     out = np.empty_like(psi)

@@ -1,0 +1,44 @@
+"""Write eigen_landau_softcore_1024.txt: the oracle's converged Ritz clusters
+for the 1024^2 B + soft-core workload (plain Lanczos, three stored vectors,
+K = 2000 iterations, window E - mc^2 in [-2, 5], tolerance 1e-6 a.u.).
+
+Calls only the oracle (and the seeded input generator); takes a few minutes
+on one core.  Usage: python tests/golden/make_eigen_landau1024.py
+"""
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import oracle  # noqa: E402
+from paper_1407_7370_amd import packets  # noqa: E402
+
+K, LO, HI, TOL = 2000, -2.0, 5.0, 1e-6
+OUT = os.path.join(HERE, "eigen_landau_softcore_1024.txt")
+
+
+def main():
+    oracle.build(force=False)
+    cfg = packets.landau_softcore_1024()
+    prob = cfg["problem"]
+    mc2 = prob["mass"] * prob["c"] ** 2
+    psi0 = packets.initial_state(cfg)
+    ev, bd, keff = oracle.eigen_plain(prob, psi0, K, mc2 + LO, mc2 + HI, TOL)
+    with open(OUT, "w") as f:
+        f.write("# Oracle eigenvalue mode, plain Lanczos (three stored vectors), written by\n")
+        f.write("# tests/golden/make_eigen_landau1024.py: 1024x1024 Dirichlet grid over [-40,40)^2,\n")
+        f.write("# B_z = 0.5 (symmetric gauge), V = -1/sqrt(r^2+1), start vector = the workload's\n")
+        f.write(f"# packet (sigma 3, p0 = 0, positive-energy projected); K = {K}, k_eff = {keff},\n")
+        f.write(f"# window E - mc^2 in [{LO}, {HI}], tolerance {TOL}.\n")
+        f.write("# columns: E - mc^2 (a.u.), bound (a.u.)\n")
+        for e, b in zip(ev, bd):
+            f.write(f"{e - mc2:.10f} {b:.3e}\n")
+    print(f"{len(ev)} values -> {OUT}")
+
+
+if __name__ == "__main__":
+    main()

@@ -171,3 +171,30 @@ def dense_h4(prob, a_hom=(0.0, 0.0)):
     Ieye = sp.identity(nx * ny)
     H = c * (sp.kron(ax4, PIx) + sp.kron(ay4, PIy)) + m * c * c * sp.kron(b4, Ieye) + sp.kron(np.eye(4), V)
     return H.tocsr()
+
+
+def lanczos_dense(A, psi, k):
+    """Textbook Lanczos on a dense Hermitian matrix with full
+    reorthogonalisation (numpy): returns (alpha[k], beta[k], Q) with beta[k-1]
+    = ||A q_k - alpha_k q_k - beta_{k-1} q_{k-1}|| (the residual norm that
+    multiplies the last Krylov coefficient in the step error estimate)."""
+    A = np.asarray(A)
+    v = np.asarray(psi, dtype=np.complex128).ravel()
+    q = v / np.linalg.norm(v)
+    Q = [q]
+    al, be = [], []
+    prev, bprev = np.zeros_like(q), 0.0
+    for i in range(k):
+        w = A @ Q[i] - bprev * prev
+        a = float(np.vdot(Q[i], w).real)
+        w = w - a * Q[i]
+        for _ in range(2):
+            for qj in Q:
+                w = w - np.vdot(qj, w) * qj
+        b = float(np.linalg.norm(w))
+        al.append(a)
+        be.append(b)
+        if i + 1 < k:
+            prev, bprev = Q[i], b
+            Q.append(w / b)
+    return np.array(al), np.array(be), np.stack(Q, axis=1)

@@ -311,6 +311,94 @@ def test_error_estimate_overestimates(orc):
         assert actual <= st["err_est"][0]
 
 
+@pytest.mark.parametrize("m", [2, 3, 5, 7, 12, 20])
+def test_error_estimate_pinned(orc, m):
+    """The step estimate of eq. matrix_exponential_error, beta_k ||psi||
+    |e_k^T exp(-iT_k) e_1|, against the same quantity from an independent
+    dense Lanczos (numpy, full reorthogonalisation) on the independently
+    assembled H, with scipy's matrix exponential: beta_k is the norm of the
+    residual A q_k - alpha_k q_k - beta_{k-1} q_{k-1} (a beta_{k-1} in its
+    place, a missing or squared norm factor, or the wrong component of the
+    exponential would each fail).  ||psi|| = 3.7 on purpose; massless, so the
+    spectrum is one wide band and ||A|| = m/2 leaves a visible Krylov error."""
+    prob = small_prob(8, 7, 0, bz=0.6, pot_kind=1, mass=0.0)
+    H = hz.dense_h(prob).toarray()
+    dt = 0.5 * m / np.abs(np.linalg.eigvalsh(H)).max()
+    psi = packets.random_spinor(prob, 21)
+    psi *= 3.7 / np.linalg.norm(psi)
+    _, st = orc.propagate(prob, psi, 0.0, dt, 1, m)
+    al, be, _ = hz.lanczos_dense(dt * H, psi, m)
+    T = _tridiag(al, be)
+    ck = 3.7 * scipy.linalg.expm(-1j * T)[m - 1, 0]
+    expect = be[m - 1] * abs(ck)
+    assert expect > 1e-7  # well above rounding, so the relative check is meaningful
+    assert st["k_eff"][0] == m
+    assert abs(st["err_est"][0] - expect) <= 1e-9 * expect, (st["err_est"][0], expect)
+    # the neighbouring beta would give a different number
+    assert abs(be[m - 2] - be[m - 1]) > 1e-3 * be[m - 1]
+
+
+def test_error_estimate_two_by_two_closed_form(orc):
+    """m = 2: exp(-iT) e_1 for T = [[a1, b1], [b1, a2]] has second component
+    -i e^{-i(a1+a2)/2} b1 sin(w)/w, w = sqrt(((a1-a2)/2)^2 + b1^2), so the
+    estimate is beta_2 ||psi|| b1 |sin w| / w with beta_2 the norm of the dense
+    residual."""
+    prob = small_prob(6, 6, 1, bz=0.4)
+    H = hz.dense_h(prob).toarray()
+    dt = 0.8 / np.abs(np.linalg.eigvalsh(H)).max()
+    psi = packets.random_spinor(prob, 22) * 0.3
+    nrm = np.linalg.norm(psi)
+    _, st = orc.propagate(prob, psi, 0.0, dt, 1, 2)
+    A = dt * H
+    q1 = psi.ravel() / nrm
+    a1 = float(np.vdot(q1, A @ q1).real)
+    r1 = A @ q1 - a1 * q1
+    b1 = float(np.linalg.norm(r1))
+    q2 = r1 / b1
+    a2 = float(np.vdot(q2, A @ q2).real)
+    b2 = float(np.linalg.norm(A @ q2 - a2 * q2 - b1 * q1))
+    w = math.sqrt((0.5 * (a1 - a2)) ** 2 + b1 * b1)
+    expect = b2 * nrm * b1 * abs(math.sin(w)) / w
+    assert abs(st["err_est"][0] - expect) <= 1e-10 * expect
+
+
+def test_lanczos_plain_equals_stored(orc):
+    """The three-vector recurrence (eigenvalue mode at scale) is the stored
+    recurrence with other storage: alpha and beta agree bit for bit, also
+    through a breakdown."""
+    cfg = packets.with_grid(packets.landau_softcore_1024(), 40)
+    prob = cfg["problem"]
+    psi = packets.initial_state(cfg)
+    k1, _, a1, b1 = orc.lanczos(prob, psi, 150)
+    k2, a2, b2 = orc.lanczos_plain(prob, psi, 150)
+    assert k1 == k2 == 150
+    assert np.array_equal(a1, a2) and np.array_equal(b1, b2)
+    pw = small_prob(8, 8, 1, lo=-0.04, hi=0.04)
+    x, y, _, _ = hz.axes(pw)
+    X, _ = np.meshgrid(x, y)
+    psi = np.stack([np.exp(1j * 2 * math.pi * 2 / 0.08 * X), np.zeros_like(X, dtype=complex)])
+    assert orc.lanczos_plain(pw, psi, 10, dt=1e-3)[0] == orc.lanczos(pw, psi, 10, dt=1e-3)[0] == 2
+    assert orc.lanczos_plain(pw, np.zeros_like(psi), 5)[0] == 0
+
+
+def test_eigen_plain_landau_and_clusters(orc):
+    """Plain Lanczos (no reorthogonalisation, so converged values reappear as
+    copies) with the cluster selection: the first relativistic Landau level of
+    a 64^2 lattice within its O(h^2) error, the same clusters as the stored
+    recurrence's selection, and every reported bound below tol."""
+    prob = _landau_prob(64)
+    mc2 = C * C
+    psi0 = packets.gaussian_packet(prob, 0.9, (0.0, 0.0))
+    ev, bd, keff = orc.eigen_plain(prob, psi0, 400, mc2 - 0.5, mc2 + 9.0, 1e-5)
+    rev, rbd, _ = orc.eigen(prob, psi0, 400, mc2 - 0.5, mc2 + 9.0, 1e-5)
+    assert keff == 400 and len(ev) >= 2
+    assert len(ev) == len(rev) and np.allclose(ev, rev, atol=1e-8)
+    assert np.allclose(bd, rbd, rtol=1e-3)
+    assert np.all(bd <= 1e-5) and np.all(np.diff(ev) > 1e-5)
+    lvl = hz.landau_levels(prob, 1)[0]
+    assert abs(ev[0] - lvl) < 0.01 * (lvl - mc2)
+
+
 def test_positive_energy_projection():
     cfg = packets.free_packet_64(seed=3)
     prob = cfg["problem"]
@@ -321,6 +409,28 @@ def test_positive_energy_projection():
     # exactly positive energy: evolving with exp(-iHt) = FFT phases only
     x, y, hx, hy = hz.axes(prob)
     assert abs(hx * hy * np.sum(np.abs(psi) ** 2) - 1.0) < 1e-13
+
+
+@pytest.mark.parametrize("chirality", [1, -1])
+def test_positive_energy_projection_chirality(chirality):
+    """The initial packets lie in the positive-energy eigenspace of the free
+    periodic lattice H of their own chirality: no weight on the negative
+    eigenvectors of the independently assembled dense H, the projection is
+    idempotent, and <psi|H|psi> > m c^2.  The other chirality's projector
+    would leave weight there."""
+    prob = dict(small_prob(10, 8, 1, lo=-2.0, hi=2.0), chirality=chirality)
+    psi = packets.gaussian_packet(prob, 0.5, (3.0, -4.0), project=True)
+    w, v = np.linalg.eigh(hz.dense_h(prob).toarray())
+    coef = v.conj().T @ psi.ravel()
+    neg = np.linalg.norm(coef[w < 0]) / np.linalg.norm(coef)
+    assert neg <= 1e-13, neg
+    again = packets.positive_energy_projection(psi, prob)
+    assert np.max(np.abs(again - psi)) <= 1e-13 * np.max(np.abs(psi))
+    e = np.vdot(psi.ravel(), hz.dense_h(prob) @ psi.ravel()).real / np.vdot(psi.ravel(), psi.ravel()).real
+    assert e > prob["c"] ** 2
+    other = packets.gaussian_packet(dict(prob, chirality=-chirality), 0.5, (3.0, -4.0), project=True)
+    coef_o = v.conj().T @ other.ravel()
+    assert np.linalg.norm(coef_o[w < 0]) / np.linalg.norm(coef_o) > 1e-6
 
 
 # ---------------------------------------------------------------------------
