@@ -106,12 +106,27 @@ typedef struct {
 } dl_params;
 
 /* Per-step statistics (Sec. 4 eq. matrix_exponential_error and its running
- * sum over the steps of one call, Sec. 6). */
+ * sum over the steps of one call, Sec. 6).
+ * round_bound (DL_PREC_MIXED; 0 in FP64): a bound, in the units of ||psi||,
+ * of the part of the step's error that comes from storing the Krylov vectors
+ * u_2..u_k in complex64.  The stored vectors obey the Lanczos relation with a
+ * perturbation F whose column j is the rounding of u_{j+1} (norm at most
+ * (2^-24 beta_j + 2^-126 sqrt(4 nx ny)) / (1 - 2^-24)); for Hermitian A the
+ * difference between ||psi|| Q exp(-iT) e_1 and exp(-iA) psi is then at most
+ * the Krylov term plus int_0^1 ||F s(t)|| dt, s(t) = ||psi|| exp(-itT) e_1,
+ * and |s_j(t)| <= ||psi|| min(1, R^(j-1) e^R / (j-1)!) with R the Gershgorin
+ * half-width of T shifted to its centre.  round_bound = ||psi|| sum_j
+ * min(1, R^(j-1) e^R / (j-1)!) (2^-24 beta_j + 2^-126 sqrt(4 nx ny)) /
+ * (1 - 2^-24), j = 1..k-1.  It holds without orthogonality of the basis; the
+ * FP64 arithmetic of both precisions is not included.  Summed over the steps
+ * it bounds the distance between a mixed-precision and an FP64 run beyond
+ * their Krylov and FP64 rounding terms. */
 typedef struct {
-    int32_t k_eff;     /* Krylov dimension used (< m after breakdown, 0 for psi = 0) */
-    double err_est;    /* beta_k ||psi|| |e_k^T exp(-iT) e_1| */
-    double cum_bound;  /* sum of err_est over the steps of this call so far */
-    double norm2;      /* ||psi||^2 after the step (never renormalised) */
+    int32_t k_eff;       /* Krylov dimension used (< m after breakdown, 0 for psi = 0) */
+    double err_est;      /* beta_k ||psi|| |e_k^T exp(-iT) e_1| */
+    double cum_bound;    /* sum of err_est over the steps of this call so far */
+    double norm2;        /* ||psi||^2 after the step (never renormalised) */
+    double round_bound;  /* complex64 storage bound of this step (see above) */
 } dl_step_stat;
 
 /*
@@ -151,16 +166,41 @@ dl_status dirac_lanczos_apply(dl_context *ctx, const void *x, void *y, double t)
  * time t0 (dt may be negative: backward propagation).  Step n uses the exact
  * average of A_L over [t0 + n dt, t0 + (n+1) dt] (first Magnus term).  Each step
  * runs the m-step Lanczos recurrence of Fig. 1 (in an algebraically equal,
- * single-sweep-per-iteration order), exp(-iT) by an eigendecomposition of T,
- * and recombines the Krylov basis (eq. matrix_exp_approx).  psi (DEVICE) is
- * updated in place and never renormalised.  stats: HOST array of n_steps
- * entries, or NULL.
- * The call returns after the stream has finished the work.  On
- * DL_ERR_NONFINITE psi holds the state after the last completed step and the
- * stats of the completed steps are filled (later entries have k_eff = -1).
+ * single-sweep-per-iteration order), the small exponential exp(-iT) e_1
+ * (Sec. 4, "any standard method": a Chebyshev expansion on the vector while
+ * the Gershgorin half-width of T shifted to its centre is below about 190,
+ * otherwise an eigendecomposition of T by implicit QR), and recombines the
+ * Krylov basis (eq. matrix_exp_approx).  psi (DEVICE) is updated in place and
+ * never renormalised.
+ * stats != NULL (HOST array of n_steps entries): the call returns after the
+ * stream has finished the work.  On DL_ERR_NONFINITE psi holds the state
+ * after the last completed step and the stats of the completed steps are
+ * filled (later entries have k_eff = -1).
+ * stats == NULL: the call only enqueues the work on the context's stream and
+ * returns; psi holds the result once the stream reaches that point (a
+ * non-finite reduction stops the remaining steps on the device, and psi then
+ * holds the state after the last completed step).  dirac_lanczos_wait
+ * synchronises and reports the outcome and the statistics; a failure not yet
+ * reported by it is reported (DL_ERR_NONFINITE, the call doing nothing else)
+ * by the next synchronous call on the context.  The per-step fields of an
+ * asynchronous call are staged through pinned host buffers the context
+ * allocates on first use.
  */
 dl_status dirac_lanczos_step(dl_context *ctx, void *psi, double t0, double dt, int32_t n_steps,
                              dl_step_stat *stats);
+
+/*
+ * Wait for the work of the context's asynchronous step calls (stats == NULL
+ * in dirac_lanczos_step, _step_lowmem, _step_ktol) and report the last one:
+ * DL_OK, or DL_ERR_NONFINITE if a reduction became non-finite (psi then holds
+ * the state after the last completed step).  steps_done (HOST, may be NULL)
+ * receives the number of completed steps of the last call.  stats (HOST,
+ * n_stats entries, may be NULL with n_stats = 0) receives the statistics of
+ * the last call's steps as dirac_lanczos_step would have returned them, for
+ * calls of up to 2048 steps (of the last 2048 steps, cum_bound summed from
+ * the first of them, for longer calls); entries beyond them have k_eff = -1.
+ */
+dl_status dirac_lanczos_wait(dl_context *ctx, dl_step_stat *stats, int32_t n_stats, int32_t *steps_done);
 
 /*
  * Adaptive Krylov dimension (Sec. 4: the estimate eq.
@@ -192,21 +232,32 @@ dl_status dirac_lanczos_step_lowmem(dl_context *ctx, void *psi, double t0, doubl
 /*
  * Adaptive time steps (Sec. 4: the error estimate eq.
  * matrix_exponential_error used to adjust the step size).  Propagates psi
- * (DEVICE, in place) from t0 to t_end > t0 with steps of variable size, each
- * one step of dirac_lanczos_step.  A step of size dt may spend
- * tol * dt / (t_end - t0) of error estimate, so the cumulative bound stays
- * below tol; a step over its share is rejected (psi untouched) and retried
- * smaller; the next dt follows from the ratio (share / estimate)^(1/(k-1)),
- * within [dt_min, dt_max], and the last step ends at t_end exactly.
- * dt_taken: HOST array of max_steps doubles receiving the accepted sizes, or
- * NULL.  out (HOST) receives the counts, the time reached, the next dt, the
- * cumulative bound and ||psi||^2.  Errors: DL_ERR_INVALID (arguments; or
- * max_steps exhausted / tol needing dt < dt_min: psi then holds the state at
- * out->t_reached), DL_ERR_NONFINITE, DL_ERR_DEVICE.  Synchronous.
+ * (DEVICE, in place) from t0 to t_end > t0 with steps of variable size h, each
+ * one step of dirac_lanczos_step.  The step's estimate covers both parts of
+ * its error:
+ *   - the Krylov error of exp(-i h H), by eq. matrix_exponential_error (an
+ *     estimate; it tends to overestimate, Sec. 4);
+ *   - the replacement of H(s) by its average over the step (the first
+ *     Magnus term, Sec. 3, eq. time_evolution_approx), by the bound
+ *     c |q| ||psi|| int_t^{t+h} |a(s) - a_bar| ds of the laser field a(s)
+ *     (H_bar - H(s) = -c q (a_bar - a(s)) . alpha has that norm on any
+ *     spinor, and the propagation is unitary), taken by quadrature on the
+ *     host.  It grows like |da/dt| h^2 per step.
+ * A step of size h may spend tol * h / (t_end - t0), so the cumulative
+ * estimate stays below tol; a step over its share is rejected (psi untouched)
+ * and retried smaller; the next h follows from the ratio
+ * (share / estimate)^e, e = 1 where the field part dominates and 1/(k-1)
+ * otherwise, within [dt_min, dt_max], and the last step ends at t_end
+ * exactly.  dt_taken: HOST array of max_steps doubles receiving the accepted
+ * sizes, or NULL.  out (HOST) receives the counts, the time reached, the next
+ * dt, the cumulative estimate (cum_bound), its field part (cum_magnus) and
+ * ||psi||^2.  Errors: DL_ERR_INVALID (arguments; or max_steps exhausted / tol
+ * needing dt < dt_min: psi then holds the state at out->t_reached),
+ * DL_ERR_NONFINITE, DL_ERR_DEVICE.  Synchronous.
  */
 typedef struct {
     int32_t accepted, rejected;
-    double t_reached, dt_next, cum_bound, norm2;
+    double t_reached, dt_next, cum_bound, norm2, cum_magnus;
 } dl_adapt_stat;
 
 dl_status dirac_lanczos_step_adaptive(dl_context *ctx, void *psi, double t0, double t_end, double dt_init,
@@ -222,12 +273,19 @@ dl_status dirac_lanczos_step_adaptive(dl_context *ctx, void *psi, double t0, dou
  * to evals/bounds (HOST arrays of n_wanted doubles), ascending; *n_found
  * receives the count.  reorth == 0: the plain three-term recurrence in the
  * fused sweep order, three rolling vectors, a workspace sized for
- * DL_MODE_EIGEN with k_eigen >= k_max.  reorth != 0: full
+ * DL_MODE_EIGEN with k_eigen >= k_max; converged clusters are accumulated
+ * over the leading blocks T_k, k = 64, 128, ... and the last k: once
+ * orthogonality is lost a converged value acquires copies whose eigenvectors
+ * of T mix with its own and its bound can grow again, while the value stays
+ * within its earlier bound of an eigenvalue of H (Paige); values closer than
+ * tol are one eigenvalue and keep their smallest bound; the call stops at
+ * the first checkpoint with n_wanted values and reports the lowest n_wanted.
+ * reorth != 0: full
  * reorthogonalisation applied twice (Sec. 2), as classical Gram-Schmidt
  * against all stored vectors (h = Q^H z, z -= Q h, two passes; the first
  * pass also removes the alpha_i q_i and beta_{i-1} q_{i-1} terms of the
  * recurrence, alpha_i = Re h_i of that pass), a workspace sized for
- * DL_MODE_EIGEN_REORTH with k_eigen >= k_max.  Every 64 iterations the
+ * DL_MODE_EIGEN_REORTH with k_eigen >= k_max; every 64 iterations the
  * Ritz values of the current T are computed on the host, and the recurrence
  * stops early once n_wanted clusters have converged (the values are then
  * those of that T); otherwise it runs k_max iterations.  A start vector of

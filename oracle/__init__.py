@@ -233,14 +233,41 @@ def ritz_clusters(alpha, beta, e_lo: float, e_hi: float, tol: float, max_out: in
     return np.array(vals), np.array(bnds)
 
 
+def converged_union(alpha, beta, e_lo: float, e_hi: float, tol: float, check_every: int = 64,
+                    max_out: int = 64):
+    """Converged Ritz clusters accumulated over the leading blocks T_j,
+    j = check_every, 2 check_every, ..., and j = k (all of T).  Once
+    orthogonality is lost a converged Ritz value acquires copies whose
+    eigenvectors of T mix with its own, so its bound |beta_j t_j| can grow
+    again while the value stays put; a value whose bound was <= tol at some j
+    lies within that bound of an eigenvalue of H all the same (Paige's
+    analysis of the finite-precision recurrence).  Values closer than tol are
+    one eigenvalue; each keeps the value and bound of its smallest bound.
+    Returns (values, bounds), ascending (at most max_out, the lowest)."""
+    k = len(alpha)
+    marks = list(range(check_every, k, check_every)) + [k]
+    found = []  # [value, bound]
+    for j in marks:
+        ev, bd = ritz_clusters(alpha[:j], beta[:j], e_lo, e_hi, tol, max_out=1 << 30)
+        for e, b in zip(ev, bd):
+            near = [f for f in found if abs(f[0] - e) <= tol]
+            if not near:
+                found.append([e, b])
+            elif b < near[0][1]:
+                near[0][0], near[0][1] = e, b
+    found.sort()
+    found = found[:max_out]
+    return np.array([f[0] for f in found]), np.array([f[1] for f in found])
+
+
 def eigen_plain(prob: dict, psi0: np.ndarray, k: int, e_lo: float, e_hi: float, tol: float,
-                max_out: int = 64):
+                max_out: int = 64, check_every: int = 64):
     """Eigenvalue mode without reorthogonalisation at any grid size: k
     iterations of the three-vector recurrence on H (fields at t = 0), then the
-    converged Ritz clusters of T_k in the window (``ritz_clusters``).
-    Returns (values, bounds, k_eff)."""
+    converged Ritz clusters of the leading blocks of T accumulated over the
+    checkpoints (``converged_union``).  Returns (values, bounds, k_eff)."""
     keff, al, be = lanczos_plain(prob, psi0, k)
-    ev, bd = ritz_clusters(al, be, e_lo, e_hi, tol, max_out)
+    ev, bd = converged_union(al, be, e_lo, e_hi, tol, check_every, max_out)
     return ev, bd, keff
 
 

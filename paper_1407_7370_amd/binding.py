@@ -28,7 +28,8 @@ EXPORTS = ("dirac_lanczos_workspace_bytes", "dirac_lanczos_init", "dirac_lanczos
            "dirac_lanczos_last_error", "dirac_lanczos_batch_workspace_bytes", "dirac_lanczos_batch_init",
            "dirac_lanczos_batch_step", "dirac_lanczos_batch_destroy", "dirac_lanczos_batch_last_error",
            "dirac_lanczos_set_launch", "dirac_lanczos_batch_set_launch", "dirac_lanczos_step_adaptive",
-           "dirac_lanczos_step_lowmem", "dirac_lanczos_eigen_vectors", "dirac_lanczos_step_ktol")
+           "dirac_lanczos_step_lowmem", "dirac_lanczos_eigen_vectors", "dirac_lanczos_step_ktol",
+           "dirac_lanczos_wait")
 DL_LOSS_X, DL_LOSS_Y, DL_LOSS_PX, DL_LOSS_PY = 1, 2, 4, 8
 
 
@@ -53,12 +54,26 @@ class DlParams(ctypes.Structure):
 
 class DlStepStat(ctypes.Structure):
     _fields_ = [("k_eff", ctypes.c_int32), ("err_est", ctypes.c_double),
-                ("cum_bound", ctypes.c_double), ("norm2", ctypes.c_double)]
+                ("cum_bound", ctypes.c_double), ("norm2", ctypes.c_double),
+                ("round_bound", ctypes.c_double)]
+
+
+def stats_dict(stats) -> dict:
+    """Numpy arrays of a sequence of DlStepStat (cum_round_bound: the running
+    sum of round_bound)."""
+    rb = np.array([s.round_bound for s in stats])
+    return {"k_eff": np.array([s.k_eff for s in stats], dtype=np.int32),
+            "err_est": np.array([s.err_est for s in stats]),
+            "cum_bound": np.array([s.cum_bound for s in stats]),
+            "norm2": np.array([s.norm2 for s in stats]),
+            "round_bound": rb,
+            "cum_round_bound": np.cumsum(rb)}
 
 
 class DlAdaptStat(ctypes.Structure):
     _fields_ = [("accepted", ctypes.c_int32), ("rejected", ctypes.c_int32), ("t_reached", ctypes.c_double),
-                ("dt_next", ctypes.c_double), ("cum_bound", ctypes.c_double), ("norm2", ctypes.c_double)]
+                ("dt_next", ctypes.c_double), ("cum_bound", ctypes.c_double), ("norm2", ctypes.c_double),
+                ("cum_magnus", ctypes.c_double)]
 
 
 class DlTiming(ctypes.Structure):
@@ -103,6 +118,8 @@ def load_library():
     lib.dirac_lanczos_step_ktol.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                             ctypes.c_double, ctypes.c_int32, ctypes.POINTER(DlStepStat)]
     lib.dirac_lanczos_step_ktol.restype = ctypes.c_int
+    lib.dirac_lanczos_wait.argtypes = [vp, ctypes.POINTER(DlStepStat), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    lib.dirac_lanczos_wait.restype = ctypes.c_int
     lib.dirac_lanczos_eigen.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                         ctypes.c_double, ctypes.c_double, ctypes.c_int32, D, D,
                                         ctypes.POINTER(ctypes.c_int32)]
@@ -204,6 +221,10 @@ def dirac_lanczos_apply(ctx, x_ptr: int, y_ptr: int, t: float) -> int:
 
 def dirac_lanczos_step(ctx, psi_ptr: int, t0: float, dt: float, n_steps: int, stats=None) -> int:
     return load_library().dirac_lanczos_step(ctx, ctypes.c_void_p(psi_ptr), t0, dt, n_steps, stats)
+
+
+def dirac_lanczos_wait(ctx, stats=None, n_stats: int = 0, steps_done=None) -> int:
+    return load_library().dirac_lanczos_wait(ctx, stats, n_stats, steps_done)
 
 
 def dirac_lanczos_eigen(ctx, psi_ptr: int, k_max: int, reorth: int, e_lo: float, e_hi: float,
@@ -329,41 +350,63 @@ class Propagator:
         _check(self.lib, self.ctx, dirac_lanczos_apply(self.ctx, x.data_ptr(), y.data_ptr(), t))
         return y
 
+    def _call_step(self, psi, t0, dt, n_steps, stats, lowmem, ktol, k_min):
+        if ktol > 0.0:
+            return self.lib.dirac_lanczos_step_ktol(self.ctx, ctypes.c_void_p(psi.data_ptr()), t0, dt, n_steps,
+                                                    ktol, int(k_min), stats)
+        fn = self.lib.dirac_lanczos_step_lowmem if lowmem else self.lib.dirac_lanczos_step
+        return fn(self.ctx, ctypes.c_void_p(psi.data_ptr()), t0, dt, n_steps, stats)
+
     def step(self, psi, t0: float, dt: float, n_steps: int, want_stats: bool = True, lowmem: bool = False,
              ktol: float = 0.0, k_min: int = 1):
         """In-place propagation of psi by n_steps steps (lowmem: the second-run
         variant; ktol > 0: adaptive Krylov dimension in [k_min, m] with the
-        per-step estimate bounded by ktol).  Returns a dict of numpy stats."""
+        per-step estimate bounded by ktol).  Returns a dict of numpy stats
+        (want_stats), or None after waiting for the work (no statistics)."""
         self._check_psi(psi)
-        stats = (DlStepStat * max(n_steps, 1))() if want_stats else None
-        if ktol > 0.0:
-            st = self.lib.dirac_lanczos_step_ktol(self.ctx, ctypes.c_void_p(psi.data_ptr()), t0, dt, n_steps,
-                                                  ktol, int(k_min), stats)
-        else:
-            fn = self.lib.dirac_lanczos_step_lowmem if lowmem else self.lib.dirac_lanczos_step
-            st = fn(self.ctx, ctypes.c_void_p(psi.data_ptr()), t0, dt, n_steps, stats)
-        out = None
-        if want_stats:
-            out = {
-                "k_eff": np.array([s.k_eff for s in stats[:n_steps]], dtype=np.int32),
-                "err_est": np.array([s.err_est for s in stats[:n_steps]]),
-                "cum_bound": np.array([s.cum_bound for s in stats[:n_steps]]),
-                "norm2": np.array([s.norm2 for s in stats[:n_steps]]),
-            }
+        if not want_stats:
+            self.step_async(psi, t0, dt, n_steps, lowmem=lowmem, ktol=ktol, k_min=k_min)
+            self.wait()
+            return None
+        stats = (DlStepStat * max(n_steps, 1))()
+        st = self._call_step(psi, t0, dt, n_steps, stats, lowmem, ktol, k_min)
+        out = stats_dict(stats[:n_steps])
         _check(self.lib, self.ctx, st)
         return out
+
+    def step_async(self, psi, t0: float, dt: float, n_steps: int, lowmem: bool = False, ktol: float = 0.0,
+                   k_min: int = 1):
+        """Enqueue n_steps in-place steps of psi on the context's stream and
+        return at once (the C call with stats = NULL); wait() reports them."""
+        self._check_psi(psi)
+        self._last_async = n_steps
+        _check(self.lib, self.ctx, self._call_step(psi, t0, dt, n_steps, None, lowmem, ktol, k_min))
+
+    def wait(self, want_stats: bool = False):
+        """Wait for the asynchronous steps; raise DlError on a device-side
+        failure.  With want_stats, the statistics of the last call's steps
+        (up to 2048) as step() returns them."""
+        n = min(int(getattr(self, "_last_async", 0)), 2048) if want_stats else 0
+        stats = (DlStepStat * max(n, 1))()
+        done = ctypes.c_int32(0)
+        st = dirac_lanczos_wait(self.ctx, stats if n else None, n, ctypes.byref(done))
+        _check(self.lib, self.ctx, st)
+        return stats_dict(stats[:n]) if want_stats else None
 
     def step_adaptive(self, psi, t0: float, t_end: float, dt_init: float, tol: float, dt_min: float,
                       dt_max: float, max_steps: int = 100000):
         """In-place propagation from t0 to t_end with adaptive step sizes
-        (cumulative error bound <= tol).  Returns (stats dict, accepted step sizes)."""
+        (cumulative error estimate <= tol: the Krylov estimates plus the bound
+        of the field's deviation from its step average).  Returns (stats
+        dict, accepted step sizes)."""
         self._check_psi(psi)
         out = DlAdaptStat()
         dts = (ctypes.c_double * max_steps)()
         st = self.lib.dirac_lanczos_step_adaptive(self.ctx, ctypes.c_void_p(psi.data_ptr()), t0, t_end, dt_init,
                                                   tol, dt_min, dt_max, max_steps, dts, ctypes.byref(out))
         stats = {"accepted": out.accepted, "rejected": out.rejected, "t_reached": out.t_reached,
-                 "dt_next": out.dt_next, "cum_bound": out.cum_bound, "norm2": out.norm2}
+                 "dt_next": out.dt_next, "cum_bound": out.cum_bound, "norm2": out.norm2,
+                 "cum_magnus": out.cum_magnus}
         _check(self.lib, self.ctx, st)
         return stats, np.array(dts[:out.accepted])
 
@@ -487,11 +530,7 @@ class BatchPropagator:
         if want_stats:
             out = []
             for i in range(self.n):
-                ss = stats[i * n_steps:(i + 1) * n_steps]
-                out.append({"k_eff": np.array([s.k_eff for s in ss], dtype=np.int32),
-                            "err_est": np.array([s.err_est for s in ss]),
-                            "cum_bound": np.array([s.cum_bound for s in ss]),
-                            "norm2": np.array([s.norm2 for s in ss])})
+                out.append(stats_dict(stats[i * n_steps:(i + 1) * n_steps]))
         if st != DL_OK:
             raise DlError(st, dirac_lanczos_batch_last_error(self.batch))
         return out

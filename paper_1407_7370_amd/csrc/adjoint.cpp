@@ -258,6 +258,8 @@ dl_status dirac_lanczos_adjoint(dl_context *ctx, const void *psi0_v, double t0, 
     }
     DL_HIP(ctx, hipMemcpyAsync(fields, hf.data(), sizeof(double) * hf.size(), hipMemcpyHostToDevice, st));
     const dl::Op opf = ctx->op(dt), opb = ctx->op(-dt), op1 = ctx->op(1.0);
+    const dl_status pend = take_async_failure(ctx);
+    if (pend != DL_OK) return pend;
     dl::launch_reset(ep.sc, st);
     dl::launch_reset(el.sc, st);
     DL_HIP(ctx, hipGetLastError());

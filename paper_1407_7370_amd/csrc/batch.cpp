@@ -349,6 +349,7 @@ dl_status dirac_lanczos_batch_init(const dl_params *params, int32_t n_packets, v
         pk.sc = reinterpret_cast<dl::Scalars *>(b->ws + B.scalars + B.sc_stride * i);
         pk.stats = reinterpret_cast<dl::StepStat *>(b->ws + B.stats) + (size_t)dl::kChunk * i;
         pk.fields = reinterpret_cast<double *>(b->ws + B.fields) + (size_t)2 * dl::kChunk * i;
+        store_rounding(pi, pk.reps, pk.rabs);
     }
     b->d_pk = reinterpret_cast<dl::BatchPacket *>(b->ws + B.pk);
     for (int k = 0; k < dl::kGridKinds; ++k) {
@@ -453,9 +454,10 @@ dl_status dirac_lanczos_batch_step(dl_batch *b, void *const *psi, double t0, dou
                     o.err_est = h.err_est;
                     o.cum_bound = cum[i];
                     o.norm2 = h.norm2;
+                    o.round_bound = h.round_bound;
                 } else {
                     o.k_eff = -1;
-                    o.err_est = o.cum_bound = o.norm2 = 0.0;
+                    o.err_est = o.cum_bound = o.norm2 = o.round_bound = 0.0;
                 }
             }
             completed[i] = hs.steps_done;

@@ -94,7 +94,7 @@ __global__ __launch_bounds__(kBlock) void k_recur_batch(BatchArgs b)
 __global__ __launch_bounds__(64) void k_tridiag_batch(BatchArgs b)
 {
     const BatchPacket &pk = b.pk[blockIdx.x];
-    tridiag_body(pk.alpha, pk.gamma, pk.sc, pk.stats + b.step);
+    tridiag_body(pk.alpha, pk.gamma, pk.sc, pk.stats + b.step, pk.reps, pk.rabs);
 }
 
 template <class TB, int S, int WPE>

@@ -4,8 +4,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "dirac_lanczos.h"
@@ -83,6 +85,25 @@ int ritz_chain(const double *alpha1, const double *beta1, int k, double e_lo, do
 // stops once n_wanted clusters have converged.
 constexpr int kEigenCheckEvery = 64;
 
+// Add converged clusters (values ev, bounds bd) to `found` (ascending by
+// value): a value within tol of a found one is the same eigenvalue and keeps
+// the smaller bound.  Once orthogonality is lost a converged Ritz value gets
+// copies whose eigenvectors of T mix with its own, so its bound can grow
+// again while the value stays within its earlier bound of an eigenvalue of H
+// (Paige's analysis of the finite-precision recurrence).
+void merge_converged(std::vector<std::pair<double, double>> &found, const double *ev, const double *bd, int n,
+                     double tol);
+
+// Rounding of one stored Krylov vector of nx*ny sites (mixed precision:
+// complex64 storage, see dl::kStoreEps32), or zero in FP64.
+inline void store_rounding(const dl_params &p, double &reps, double &rabs)
+{
+    reps = rabs = 0.0;
+    if (p.precision != DL_PREC_MIXED) return;
+    reps = dl::kStoreEps32;
+    rabs = dl::kStoreTiny32 * std::sqrt(4.0 * (double)p.nx * (double)p.ny);
+}
+
 // Sign of the sigma2 terms: alpha2 = chir * sigma2.
 inline double chir(const dl_params &p) { return p.chirality < 0 ? -1.0 : 1.0; }
 
@@ -145,11 +166,25 @@ struct dl_context {
     size_t ev_used = 0;
     int64_t t_launches[5] = {0, 0, 0, 0, 0};
     double t_ms[5] = {0, 0, 0, 0, 0};
+    // asynchronous steps (stats == NULL): two pinned host buffers stage the
+    // per-step fields of a chunk; an event after each upload guards the
+    // buffer's reuse.  The statistics of the last chunk stay on the device
+    // until dirac_lanczos_wait.
+    double *pin_fields[2] = {nullptr, nullptr};
+    hipEvent_t pin_ev[2] = {nullptr, nullptr};
+    int pin_next = 0;
+    bool async_pending = false;
+    int async_s0 = 0, async_nc = 0;
 
     ~dl_context()
     {
         for (hipEvent_t e : ev0) (void)hipEventDestroy(e);
         for (hipEvent_t e : ev1) (void)hipEventDestroy(e);
+        for (int i = 0; i < 2; ++i) {
+            if (pin_ev[i]) (void)hipEventSynchronize(pin_ev[i]);
+            if (pin_ev[i]) (void)hipEventDestroy(pin_ev[i]);
+            if (pin_fields[i]) (void)hipHostFree(pin_fields[i]);
+        }
     }
 
     // Fold the recorded event pairs into the per-class totals.
@@ -236,6 +271,11 @@ dl_status run_twice(dl_context *ctx, const Engine &e, const dl::Op &op, const do
 // exp(-iT) and the recombination into `out` (stat receives k_eff, estimate, norm).
 dl_status run_finish(dl_context *ctx, const Engine &e, const double2 *in, double2 *out,
                      dl::StepStat *stat, double *partials);
+
+// Report (DL_ERR_NONFINITE) and clear a failure of an earlier asynchronous
+// step call that dirac_lanczos_wait has not reported; DL_OK otherwise.  Every
+// synchronous entry point that resets the scalars calls it first.
+dl_status take_async_failure(dl_context *ctx);
 
 // Eigen mode with full reorthogonalisation (eigen.cpp); vecs (device, may be
 // NULL) receives the Ritz vectors of the reported values.

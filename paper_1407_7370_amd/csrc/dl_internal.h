@@ -44,7 +44,14 @@ struct StepStat {
     double norm2;
     int keff;
     int pad;
+    double round_bound;  // a-priori bound of the step's error from complex64 storage (0 in FP64)
 };
+
+// Rounding of the complex64 Krylov storage (mixed precision): each real
+// component of a stored vector is rounded to nearest with relative error at
+// most 2^-24; a component below the normal range adds at most 2^-126.
+constexpr double kStoreEps32 = 5.9604644775390625e-8;    // 2^-24
+constexpr double kStoreTiny32 = 1.1754943508222875e-38;  // 2^-126
 
 // Coefficients of the operator A = s * H applied by the sweeps, s = dt for a
 // time step and s = 1 for the plain Hamiltonian.
@@ -171,13 +178,20 @@ void launch_first(const Op &op, const Tiles &t, const double2 *psi, const double
                   double *alpha, double *gamma, Scalars *sc, double *partials, int m,
                   int shift, hipStream_t st);
 void launch_recur(const PassArgs &a, bool mixed, hipStream_t st);
-void launch_tridiag(const double *alpha, const double *gamma, Scalars *sc, StepStat *stat,
-                    hipStream_t st);
+// reps, rabs: relative and absolute rounding of one stored Krylov vector
+// (kStoreEps32 and kStoreTiny32 * sqrt(4 * sites) in mixed precision, 0 in FP64)
+void launch_tridiag(const double *alpha, const double *gamma, Scalars *sc, StepStat *stat, double reps,
+                    double rabs, hipStream_t st);
 // wide: the complex64 form with 16 sites per thread (see combine_wide)
 void launch_combine(const CombArgs &a, bool mixed, bool wide, int nblocks, hipStream_t st);
 void launch_apply(const Op &op, const Tiles &t, const double2 *x, double2 *y, double gxh,
                   double gyh, hipStream_t st);
 void launch_reset(Scalars *sc, hipStream_t st);
+// Reset at the start of a step call (see k_reset): keep_status for
+// asynchronous calls, the adaptive-dimension parameters (ktol = 0: off).
+void launch_reset_call(Scalars *sc, int keep_status, int kmin, int kmax, double ktol, hipStream_t st);
+// psi <- state (n complex128 values) when sc->steps_done is odd.
+void launch_finish_copy(const Scalars *sc, const double2 *state, double2 *psi, size_t n, int cus, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Batches of independent packets (grids of different sizes and fields, one
@@ -201,6 +215,7 @@ struct BatchPacket {
     Scalars *sc;
     StepStat *stats;   // kChunk entries
     double *fields;    // (gx_hom, gy_hom) per step of the chunk
+    double reps, rabs; // rounding of one stored Krylov vector (see launch_tridiag)
 };
 
 struct BatchBlock {    // one workgroup of a batched launch

@@ -62,6 +62,8 @@ dl_status eigen_reorth(dl_context *ctx, const void *psi0, int k_max, double e_lo
     const size_t tiles = (n + dl::kBlock - 1) / dl::kBlock;
     const int nb = (int)std::max<size_t>(1, std::min<size_t>(tiles, (size_t)8 * ctx->cus));
 
+    const dl_status pend = take_async_failure(ctx);
+    if (pend != DL_OK) return pend;
     dl::launch_reset(sc, st);
     dl::launch_first_q(static_cast<const double2 *>(psi0), n, qv(1), sc, beta, partials, nb, st);
     DL_HIP(ctx, hipGetLastError());

@@ -330,6 +330,22 @@ int ritz_chain(const double *alpha1, const double *beta1, int k, double e_lo, do
     return ritz_select(lam, zl, beta1[k - 1], e_lo, e_hi, tol, n_wanted, evals, bounds, rep);
 }
 
+void merge_converged(std::vector<std::pair<double, double>> &found, const double *ev, const double *bd, int n,
+                     double tol)
+{
+    for (int i = 0; i < n; ++i) {
+        bool merged = false;
+        for (auto &f : found)
+            if (std::fabs(f.first - ev[i]) <= tol) {
+                if (bd[i] < f.second) f = {ev[i], bd[i]};
+                merged = true;
+                break;
+            }
+        if (!merged) found.push_back({ev[i], bd[i]});
+    }
+    std::sort(found.begin(), found.end());
+}
+
 dl_status run_build(dl_context *ctx, const Engine &e, const dl::Op &op, const double2 *in,
                     const double *field, double *partials, int shift)
 {
@@ -386,7 +402,9 @@ dl_status run_twice(dl_context *ctx, const Engine &e, const dl::Op &op, const do
         dl::launch_first(op, ctx->tiles_first, in, field, e.alpha, e.gamma, e.sc, partials, e.m, 1, st);
     }));
     for (int pp = 2; pp <= e.m; ++pp) DL_HIP(ctx, pass(pp, 0));
-    DL_HIP(ctx, ctx->timed(3, [&] { dl::launch_tridiag(e.alpha, e.gamma, e.sc, stat, st); }));
+    double reps, rabs;
+    store_rounding(ctx->p, reps, rabs);
+    DL_HIP(ctx, ctx->timed(3, [&] { dl::launch_tridiag(e.alpha, e.gamma, e.sc, stat, reps, rabs, st); }));
     dl::AccumArgs c{};
     c.psi = in;
     c.sites = vec_elems(ctx->p) / 2;
@@ -421,7 +439,9 @@ dl_status run_finish(dl_context *ctx, const Engine &e, const double2 *in, double
                      dl::StepStat *stat, double *partials)
 {
     hipStream_t st = ctx->stream;
-    DL_HIP(ctx, ctx->timed(3, [&] { dl::launch_tridiag(e.alpha, e.gamma, e.sc, stat, st); }));
+    double reps, rabs;
+    store_rounding(ctx->p, reps, rabs);
+    DL_HIP(ctx, ctx->timed(3, [&] { dl::launch_tridiag(e.alpha, e.gamma, e.sc, stat, reps, rabs, st); }));
     dl::CombArgs r{};
     r.psi = in;
     r.basis = e.basis;
@@ -435,6 +455,22 @@ dl_status run_finish(dl_context *ctx, const Engine &e, const double2 *in, double
         dl::launch_combine(r, e.mixed, ctx->combine_wide, ctx->combine_blocks_wide, st);
     }));
     return DL_OK;
+}
+
+// A failure of an earlier asynchronous call that dirac_lanczos_wait has not
+// reported yet: synchronise, read the scalars, and report and clear it.
+dl_status take_async_failure(dl_context *ctx)
+{
+    if (!ctx->async_pending) return DL_OK;
+    ctx->async_pending = false;
+    DL_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    dl::Scalars hs;
+    DL_HIP(ctx, hipMemcpy(&hs, ctx->sc(), sizeof(hs), hipMemcpyDeviceToHost));
+    if (hs.status == 0) return DL_OK;
+    dl::launch_reset(ctx->sc(), ctx->stream);
+    DL_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return ctx->fail(DL_ERR_NONFINITE, "non-finite Lanczos reduction in an asynchronous call after " +
+                                           std::to_string(hs.steps_done) + " of its steps");
 }
 
 }  // namespace dlh
@@ -587,6 +623,46 @@ dl_status dirac_lanczos_apply(dl_context *ctx, const void *x, void *y, double t)
     return DL_OK;
 }
 
+// Stage the per-step fields of steps s0 .. s0+nc-1 into a pinned buffer (for
+// an asynchronous upload) or the context's pageable one.
+static dl_status stage_fields(dl_context *ctx, bool async, double t0, double dt, int s0, int nc, double *dev)
+{
+    const dl_params &p = ctx->p;
+    const double kf = -dt * p.c * p.charge;
+    double *h;
+    if (async) {
+        const int b = ctx->pin_next;
+        ctx->pin_next ^= 1;
+        if (!ctx->pin_fields[b]) {
+            DL_HIP(ctx, hipHostMalloc(reinterpret_cast<void **>(&ctx->pin_fields[b]), sizeof(double) * 2 * kChunk,
+                                      hipHostMallocDefault));
+            DL_HIP(ctx, hipEventCreateWithFlags(&ctx->pin_ev[b], hipEventDisableTiming));
+        } else {
+            DL_HIP(ctx, hipEventSynchronize(ctx->pin_ev[b]));  // its previous upload has been consumed
+        }
+        h = ctx->pin_fields[b];
+        for (int i = 0; i < nc; ++i) {
+            double a[2];
+            pulse_average(p, ctx->coef, t0 + (double)(s0 + i) * dt, dt, a);
+            h[2 * i] = kf * a[0];
+            h[2 * i + 1] = kf * chir(p) * a[1];
+        }
+        DL_HIP(ctx, hipMemcpyAsync(dev, h, sizeof(double) * 2 * nc, hipMemcpyHostToDevice, ctx->stream));
+        DL_HIP(ctx, hipEventRecord(ctx->pin_ev[b], ctx->stream));
+        return DL_OK;
+    }
+    ctx->host_fields.resize(2 * kChunk);
+    h = ctx->host_fields.data();
+    for (int i = 0; i < nc; ++i) {
+        double a[2];
+        pulse_average(p, ctx->coef, t0 + (double)(s0 + i) * dt, dt, a);
+        h[2 * i] = kf * a[0];
+        h[2 * i + 1] = kf * chir(p) * a[1];
+    }
+    DL_HIP(ctx, hipMemcpyAsync(dev, h, sizeof(double) * 2 * nc, hipMemcpyHostToDevice, ctx->stream));
+    return DL_OK;
+}
+
 static dl_status run_steps(dl_context *ctx, void *psi_v, double t0, double dt, int32_t n_steps,
                            dl_step_stat *stats, bool lowmem, double ktol = 0.0, int kmin = 0)
 {
@@ -595,6 +671,11 @@ static dl_status run_steps(dl_context *ctx, void *psi_v, double t0, double dt, i
     if (n_steps < 0) return ctx->fail(DL_ERR_INVALID, "n_steps must be >= 0");
     if (!(dt != 0.0) || !std::isfinite(dt) || !std::isfinite(t0))
         return ctx->fail(DL_ERR_INVALID, "dt must be finite and non-zero, t0 finite");
+    const bool async = stats == nullptr;
+    if (!async) {
+        const dl_status pend = take_async_failure(ctx);
+        if (pend != DL_OK) return pend;
+    }
     if (n_steps == 0) return DL_OK;
     const dl_params &p = ctx->p;
     const size_t need = plan(p, lowmem ? DL_MODE_LOWMEM : DL_MODE_STEP, 0).total;
@@ -621,33 +702,21 @@ static dl_status run_steps(dl_context *ctx, void *psi_v, double t0, double dt, i
     const Engine eng{sc, alpha, gamma, basis, vstride, m, mixed};
 
     const dl::Op op = ctx->op(dt);
-    const double kf = -dt * p.c * p.charge;
     hipStream_t st = ctx->stream;
 
-    dl::launch_reset(sc, st);
+    // adaptive dimension (ktol > 0): the first step runs m iterations, later
+    // ones the dimension the previous step predicted
+    dl::launch_reset_call(sc, async ? 1 : 0, ktol > 0.0 ? kmin : 0, ktol > 0.0 ? m : 0, ktol > 0.0 ? ktol : 0.0,
+                          st);
     DL_HIP(ctx, hipGetLastError());
-    if (ktol > 0.0) {
-        // adaptive dimension: the first step runs m iterations, later ones the
-        // dimension the previous step predicted
-        const int kk[3] = {kmin, m, 0};
-        DL_HIP(ctx, hipMemcpyAsync(&sc->kmin, kk, sizeof(kk), hipMemcpyHostToDevice, st));
-        DL_HIP(ctx, hipMemcpyAsync(&sc->ktol, &ktol, sizeof(double), hipMemcpyHostToDevice, st));
-    }
     double cum = 0.0;
     int completed = 0;
     bool aborted = false;
-    ctx->host_fields.resize(2 * kChunk);
     ctx->host_stats.resize(kChunk);
     for (int s0 = 0; s0 < n_steps && !aborted; s0 += kChunk) {
         const int nc = std::min(kChunk, n_steps - s0);
-        for (int i = 0; i < nc; ++i) {
-            double a[2];
-            pulse_average(p, ctx->coef, t0 + (double)(s0 + i) * dt, dt, a);
-            ctx->host_fields[2 * i] = kf * a[0];
-            ctx->host_fields[2 * i + 1] = kf * chir(p) * a[1];
-        }
-        DL_HIP(ctx, hipMemcpyAsync(fields, ctx->host_fields.data(), sizeof(double) * 2 * nc,
-                                   hipMemcpyHostToDevice, st));
+        const dl_status sf = stage_fields(ctx, async, t0, dt, s0, nc, fields);
+        if (sf != DL_OK) return sf;
         for (int i = 0; i < nc; ++i) {
             const int g = s0 + i;
             double2 *in = (g % 2 == 0) ? psi : state;
@@ -657,11 +726,16 @@ static dl_status run_steps(dl_context *ctx, void *psi_v, double t0, double dt, i
                                         : run_build(ctx, eng, op, in, fp, partials, 1);
             if (sb != DL_OK) return sb;
             if (!lowmem) {
-                const dl_status sf = run_finish(ctx, eng, in, out, dstats + i, partials);
-                if (sf != DL_OK) return sf;
+                const dl_status sr = run_finish(ctx, eng, in, out, dstats + i, partials);
+                if (sr != DL_OK) return sr;
             }
         }
         DL_HIP(ctx, hipGetLastError());
+        if (async) {
+            ctx->async_s0 = s0;
+            ctx->async_nc = nc;
+            continue;
+        }
         dl::Scalars hs;
         DL_HIP(ctx, hipMemcpyAsync(ctx->host_stats.data(), dstats, sizeof(dl::StepStat) * nc,
                                    hipMemcpyDeviceToHost, st));
@@ -669,7 +743,6 @@ static dl_status run_steps(dl_context *ctx, void *psi_v, double t0, double dt, i
         DL_HIP(ctx, hipStreamSynchronize(st));
         const int done_here = hs.steps_done - completed;
         for (int i = 0; i < nc; ++i) {
-            if (!stats) break;
             dl_step_stat &o = stats[s0 + i];
             if (i < done_here) {
                 cum += ctx->host_stats[i].err_est;
@@ -677,18 +750,26 @@ static dl_status run_steps(dl_context *ctx, void *psi_v, double t0, double dt, i
                 o.err_est = ctx->host_stats[i].err_est;
                 o.cum_bound = cum;
                 o.norm2 = ctx->host_stats[i].norm2;
+                o.round_bound = ctx->host_stats[i].round_bound;
             } else {
                 o.k_eff = -1;
-                o.err_est = o.cum_bound = o.norm2 = 0.0;
+                o.err_est = o.cum_bound = o.norm2 = o.round_bound = 0.0;
             }
         }
         completed = hs.steps_done;
         if (hs.status != 0) aborted = true;
     }
-    if (stats && aborted)
+    if (async) {
+        // the state after the completed steps is copied to psi on the device
+        dl::launch_finish_copy(sc, state, psi, n, ctx->cus, st);
+        DL_HIP(ctx, hipGetLastError());
+        ctx->async_pending = true;
+        return DL_OK;
+    }
+    if (aborted)
         for (int i = completed; i < n_steps; ++i) {
             stats[i].k_eff = -1;
-            stats[i].err_est = stats[i].cum_bound = stats[i].norm2 = 0.0;
+            stats[i].err_est = stats[i].cum_bound = stats[i].norm2 = stats[i].round_bound = 0.0;
         }
     // the state after `completed` steps sits in psi (even) or in the workspace (odd)
     if (completed % 2 == 1) {
@@ -732,6 +813,8 @@ dl_status dirac_lanczos_eigen(dl_context *ctx, const void *psi0, int32_t k_max, 
         !(e_hi >= e_lo))
         return ctx->fail(DL_ERR_INVALID, "invalid eigen arguments");
     *n_found = 0;
+    const dl_status pend = take_async_failure(ctx);
+    if (pend != DL_OK) return pend;
     if (reorth) return eigen_reorth(ctx, psi0, k_max, e_lo, e_hi, tol, n_wanted, evals, bounds, n_found, nullptr);
     const dl_params &p = ctx->p;
     const Layout E = plan(p, DL_MODE_EIGEN, k_max);
@@ -775,8 +858,16 @@ dl_status dirac_lanczos_eigen(dl_context *ctx, const void *psi0, int32_t k_max, 
         return DL_OK;
     };
     // T_k after pass p: alpha_1..alpha_k in ha[1..], beta_1..beta_k in hg[2..]
-    // (gamma_{j+1} = beta_j), so k = p - 1 is complete after pass p
-    int k_early = 0;
+    // (gamma_{j+1} = beta_j), so k = p - 1 is complete after pass p.  Converged
+    // clusters are accumulated over the checkpoints k = 64, 128, ... and the
+    // final k (merge_converged).
+    std::vector<std::pair<double, double>> found;
+    std::vector<double> ev((size_t)k_max + 1), bd(ev.size());  // at most k Ritz values per T_k
+    auto harvest = [&](int k) {
+        const int nf = ritz_chain(ha.data() + 1, hg.data() + 2, k, e_lo, e_hi, tol, (int)ev.size(), ev.data(),
+                                  bd.data(), nullptr, nullptr);
+        merge_converged(found, ev.data(), bd.data(), nf, tol);
+    };
     for (int pp = 2; pp <= K1; ++pp) {
         dl::PassArgs a{};
         a.op = op;
@@ -792,26 +883,73 @@ dl_status dirac_lanczos_eigen(dl_context *ctx, const void *psi0, int32_t k_max, 
         a.pass = pp;
         a.m = K1;
         dl::launch_recur(a, false, st);
-        if (pp % kEigenCheckEvery == 0 && pp < K1) {
+        if ((pp - 1) % kEigenCheckEvery == 0 && pp < K1) {
             DL_HIP(ctx, hipGetLastError());
             const dl_status s = fetch();
             if (s != DL_OK) return s;
             if (hs.kstop < pp) break;  // breakdown: the recurrence is over
-            std::vector<double> ev(n_wanted), bd(n_wanted);
-            if (ritz_chain(ha.data() + 1, hg.data() + 2, pp - 1, e_lo, e_hi, tol, n_wanted, ev.data(), bd.data(),
-                           nullptr, nullptr) >= n_wanted) {
-                k_early = pp - 1;
-                break;
-            }
+            harvest(pp - 1);
+            if ((int)found.size() >= n_wanted) break;
         }
     }
     DL_HIP(ctx, hipGetLastError());
     const dl_status s = fetch();
     if (s != DL_OK) return s;
-    const int k = k_early > 0 ? k_early : std::min(hs.keff, k_max);
-    if (k <= 0) return DL_OK;
-    *n_found = ritz_chain(ha.data() + 1, hg.data() + 2, k, e_lo, e_hi, tol, n_wanted, evals, bounds, nullptr,
-                          nullptr);
+    if ((int)found.size() < n_wanted) {
+        const int k = std::min(hs.keff, k_max);
+        if (k > 0) harvest(k);
+    }
+    const int nf = std::min((int)found.size(), n_wanted);
+    for (int i = 0; i < nf; ++i) {
+        evals[i] = found[i].first;
+        bounds[i] = found[i].second;
+    }
+    *n_found = nf;
+    return DL_OK;
+}
+
+dl_status dirac_lanczos_wait(dl_context *ctx, dl_step_stat *stats, int32_t n_stats, int32_t *steps_done)
+{
+    if (!ctx) return DL_ERR_INVALID;
+    if (n_stats < 0 || (n_stats > 0 && !stats)) return ctx->fail(DL_ERR_INVALID, "stats must hold n_stats entries");
+    DL_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    dl::Scalars hs;
+    DL_HIP(ctx, hipMemcpy(&hs, ctx->sc(), sizeof(hs), hipMemcpyDeviceToHost));
+    if (steps_done) *steps_done = hs.steps_done;
+    const int nc = ctx->async_pending ? ctx->async_nc : 0;
+    const int nfill = std::min(n_stats, nc);
+    if (nfill > 0) {
+        ctx->host_stats.resize(kChunk);
+        DL_HIP(ctx, hipMemcpy(ctx->host_stats.data(), ctx->ws + ctx->L.stats, sizeof(dl::StepStat) * nc,
+                              hipMemcpyDeviceToHost));
+        const int done_here = hs.steps_done - ctx->async_s0;
+        double cum = 0.0;
+        for (int i = 0; i < nfill; ++i) {
+            dl_step_stat &o = stats[i];
+            if (i < done_here) {
+                cum += ctx->host_stats[i].err_est;
+                o.k_eff = ctx->host_stats[i].keff;
+                o.err_est = ctx->host_stats[i].err_est;
+                o.cum_bound = cum;
+                o.norm2 = ctx->host_stats[i].norm2;
+                o.round_bound = ctx->host_stats[i].round_bound;
+            } else {
+                o.k_eff = -1;
+                o.err_est = o.cum_bound = o.norm2 = o.round_bound = 0.0;
+            }
+        }
+    }
+    for (int i = nfill; i < n_stats; ++i) {
+        stats[i].k_eff = -1;
+        stats[i].err_est = stats[i].cum_bound = stats[i].norm2 = stats[i].round_bound = 0.0;
+    }
+    ctx->async_pending = false;
+    if (hs.status != 0) {
+        dl::launch_reset(ctx->sc(), ctx->stream);
+        DL_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        return ctx->fail(DL_ERR_NONFINITE, "non-finite Lanczos reduction after " + std::to_string(hs.steps_done) +
+                                               " completed steps of the last call");
+    }
     return DL_OK;
 }
 

@@ -92,10 +92,10 @@ void launch_recur(const PassArgs &a, bool mixed, hipStream_t st)
         with_kind<RecurPn, SingleRecur>(mixed, py, terms, go);
 }
 
-void launch_tridiag(const double *alpha, const double *gamma, Scalars *sc, StepStat *stat,
-                    hipStream_t st)
+void launch_tridiag(const double *alpha, const double *gamma, Scalars *sc, StepStat *stat, double reps,
+                    double rabs, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(64), 0, st, alpha, gamma, sc, stat);
+    hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(64), 0, st, alpha, gamma, sc, stat, reps, rabs);
 }
 
 void launch_combine(const CombArgs &a, bool mixed, bool wide, int nblocks, hipStream_t st)
@@ -123,9 +123,18 @@ void launch_apply(const Op &op, const Tiles &t, const double2 *x, double2 *y, do
     hipLaunchKernelGGL(k_apply, dim3(t.nblocks), dim3(kBlock), 0, st, op, t, x, y, gxh, gyh);
 }
 
-void launch_reset(Scalars *sc, hipStream_t st)
+void launch_reset(Scalars *sc, hipStream_t st) { launch_reset_call(sc, 0, 0, 0, 0.0, st); }
+
+void launch_reset_call(Scalars *sc, int keep_status, int kmin, int kmax, double ktol, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, sc);
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, sc, keep_status, kmin, kmax, ktol);
+}
+
+void launch_finish_copy(const Scalars *sc, const double2 *state, double2 *psi, size_t n, int cus, hipStream_t st)
+{
+    const size_t blocks = std::min<size_t>((size_t)4 * cus, (n + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_finish_copy, dim3((unsigned)std::max<size_t>(blocks, 1)), dim3(kBlock), 0, st, sc, state,
+                       psi, n);
 }
 
 }  // namespace dl

@@ -905,7 +905,52 @@ __device__ void predict_k(const double *alpha, const double *gamma, Scalars *sc,
     if (lane == 0) sc->knext = max(knext, max(sc->kmin, 1));
 }
 
-__device__ __forceinline__ void tridiag_body(const double *alpha, const double *gamma, Scalars *sc, StepStat *stat)
+// Bound of the step's error caused by storing u_2..u_k rounded (mixed
+// precision).  The stored vectors satisfy the perturbed Lanczos relation
+// A Q = Q T + beta_k q_{k+1} e_k^T - F, column j of F being the rounding of
+// u_{j+1} = beta_j q_{j+1}, ||F e_j|| <= (reps beta_j + rabs) / (1 - reps).
+// y(t) = ||psi|| Q exp(-itT) e_1 then solves y' = -iAy + i(beta_k q_{k+1} e_k^T
+// - F) s(t) with s(t) = ||psi|| exp(-itT) e_1 and y(0) = psi, so for Hermitian
+// A the error at t = 1 is at most int_0^1 ||F s(t)|| dt (plus the Krylov term
+// of eq. matrix_exponential_error), with no assumption of orthogonality.
+// With X = T' - c0 I (c0, R: centre and half-width of T's Gershgorin
+// interval) and |X| its entrywise absolute value, the path sums of X^n give
+// |s_j(t)| <= ||psi|| [exp(t|X|) e_1]_j <= ||psi|| [exp(|X|) e_1]_j for t in
+// [0, 1]; exp(|X|) e_1 is summed as its Taylor series (non-negative terms, no
+// cancellation) with N = 3R + 40 terms plus the tail bound
+// R^(N+1) e^R / (N+1)!, and capped at 1 (|s_j| <= ||psi||).  Beyond R = 30 the
+// factor is 1.  Lane l handles j = l + 1; beta_j is lane l's coupling e.
+constexpr double kStoreBoundMaxR = 30.0;
+
+__device__ double storage_bound(double d, double e, double em, int k, int lane, double g1, double reps,
+                                double rabs)
+{
+    if (!(reps > 0.0) && !(rabs > 0.0)) return 0.0;
+    const double rad = fabs(e) + fabs(em);
+    const double glo = wave_min(lane < k ? d - rad : INFINITY);
+    const double ghi = wave_max(lane < k ? d + rad : -INFINITY);
+    const double c0 = 0.5 * (glo + ghi), R = 0.5 * (ghi - glo);
+    double f = 1.0;
+    if (R <= kStoreBoundMaxR) {
+        // rows of |X| beyond k are zero (d, e, em are zero there)
+        const double xd = lane < k ? fabs(d - c0) : 0.0, xe = fabs(e), xem = fabs(em);
+        const int N = (int)ceil(3.0 * R) + 40;
+        double t = lane == 0 ? 1.0 : 0.0, v = t;
+        for (int n = 1; n <= N; ++n) {
+            t = (xem * from_left(t) + xd * t + xe * from_right(t)) / (double)n;
+            v += t;
+        }
+        const double tail = R > 0.0 ? exp((double)(N + 1) * log(R) + R - lgamma((double)N + 2.0)) : 0.0;
+        f = fmin(1.0, v + tail);
+    }
+    double v = (lane + 1 < k) ? f * (reps * fabs(e) + rabs) / (1.0 - reps) : 0.0;
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) v += __shfl_xor(v, s, 64);
+    return g1 * v;
+}
+
+__device__ __forceinline__ void tridiag_body(const double *alpha, const double *gamma, Scalars *sc, StepStat *stat,
+                                             double reps, double rabs)
 {
     __shared__ double zpr[(kMaxM + 1) * 64];
     __shared__ double wre[kMaxM], wim[kMaxM];
@@ -921,6 +966,7 @@ __device__ __forceinline__ void tridiag_body(const double *alpha, const double *
             sc->cabs_k = 0.0;
             stat->keff = 0;
             stat->err_est = 0.0;
+            stat->round_bound = 0.0;
         }
         return;
     }
@@ -929,6 +975,7 @@ __device__ __forceinline__ void tridiag_body(const double *alpha, const double *
     const double gl = (lane < k) ? gamma[lane + 1] : 1.0, g1 = gamma[1];
     double em = from_left(e);                           // e_{j-1}
     if (lane == 0) em = 0.0;
+    const double rb = storage_bound(d, e, em, k, lane, g1, reps, rabs);
     double cr = 0.0, ci = 0.0;
     if (!cheb_exp_e1(d, e, em, k, lane, cr, ci)) {
 #define ZZ(i) zpr[(i) * 64 + lane]
@@ -1024,15 +1071,16 @@ __device__ __forceinline__ void tridiag_body(const double *alpha, const double *
             sc->cabs_k = ck;
             stat->keff = k;
             stat->err_est = beta_k * ck;
+            stat->round_bound = rb;
         }
     }
     if (ktol > 0.0) predict_k(alpha, gamma, sc, k, lane, beta_k * __shfl(ck, k - 1, 64));
 }
 
 __global__ __launch_bounds__(64) void k_tridiag(const double *alpha, const double *gamma, Scalars *sc,
-                                                StepStat *stat)
+                                                StepStat *stat, double reps, double rabs)
 {
-    tridiag_body(alpha, gamma, sc, stat);
+    tridiag_body(alpha, gamma, sc, stat, reps, rabs);
 }
 
 // ---------------------------------------------------------------------------
@@ -1334,21 +1382,38 @@ __global__ __launch_bounds__(kBlock) void k_apply(Op op, Tiles t, const double2 
     }
 }
 
-__global__ void k_reset(Scalars *sc)
+// Scalars to the start-of-call state.  keep_status: an asynchronous call
+// leaves a failure of an earlier call in place (its kernels then do nothing)
+// until the host has read it.  kmin, kmax, ktol: adaptive Krylov dimension
+// (ktol = 0: off).
+__global__ void k_reset(Scalars *sc, int keep_status, int kmin, int kmax, double ktol)
 {
     if (threadIdx.x == 0) {
-        sc->status = 0;
+        if (!keep_status) sc->status = 0;
         sc->steps_done = 0;
         sc->ticket = 0u;
-        sc->kstop = 0;
+        sc->kstop = sc->status != 0 ? -1 : 0;
         sc->keff = 0;
         sc->scale = 0.0;
         sc->cabs_k = 0.0;
         sc->beta_k = 0.0;
         sc->sigma = 0.0;
-        sc->kmin = sc->kmax = sc->knext = 0;
-        sc->ktol = 0.0;
+        sc->kmin = kmin;
+        sc->kmax = kmax;
+        sc->knext = 0;
+        sc->ktol = ktol;
     }
+}
+
+// End of an asynchronous call: the state after the completed steps is in
+// `state` when their number is odd (the steps alternate between the caller's
+// psi and the workspace); copy it to psi there, do nothing otherwise.
+__global__ __launch_bounds__(kBlock) void k_finish_copy(const Scalars *sc, const double2 *__restrict__ state,
+                                                        double2 *__restrict__ psi, size_t n)
+{
+    if ((sc->steps_done & 1) == 0) return;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
+        psi[i] = state[i];
 }
 
 // FIFO depths (rows of loads in flight per wave).

@@ -33,7 +33,8 @@ def main():
         f.write("# tests/golden/make_eigen_landau1024.py: 1024x1024 Dirichlet grid over [-40,40)^2,\n")
         f.write("# B_z = 0.5 (symmetric gauge), V = -1/sqrt(r^2+1), start vector = the workload's\n")
         f.write(f"# packet (sigma 3, p0 = 0, positive-energy projected); K = {K}, k_eff = {keff},\n")
-        f.write(f"# window E - mc^2 in [{LO}, {HI}], tolerance {TOL}.\n")
+        f.write(f"# window E - mc^2 in [{LO}, {HI}], tolerance {TOL}; converged clusters accumulated over\n")
+        f.write("# the leading blocks of T every 64 iterations and at K (oracle.converged_union).\n")
         f.write("# columns: E - mc^2 (a.u.), bound (a.u.)\n")
         for e, b in zip(ev, bd):
             f.write(f"{e - mc2:.10f} {b:.3e}\n")

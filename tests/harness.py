@@ -198,3 +198,60 @@ def lanczos_dense(A, psi, k):
             prev, bprev = Q[i], b
             Q.append(w / b)
     return np.array(al), np.array(be), np.stack(Q, axis=1)
+
+
+def storage_bound(alpha, beta, nrm, reps, rabs):
+    """Bound of the error from rounding the stored Krylov vectors u_2..u_k
+    (relative rounding reps, absolute rabs per vector):
+    ||psi|| sum_{j<k} f_j (reps beta_j + rabs) / (1 - reps), where f_j bounds
+    max_{t in [0,1]} |[exp(-itT)]_{j1}|: with X = T - c0 I (c0 the centre of
+    T's Gershgorin interval, half-width R) and |X| its entrywise absolute
+    value, |[exp(-itX)]_{j1}| <= [exp(t|X|)]_{j1} <= [exp(|X|)]_{j1} (path sums
+    of non-negative terms), capped at 1; scipy's expm evaluates exp(|X|)."""
+    import scipy.linalg
+    al = np.asarray(alpha, dtype=float)
+    be = np.asarray(beta, dtype=float)
+    k = len(al)
+    off = np.r_[be[:k - 1], 0.0]
+    rad = np.abs(off) + np.abs(np.r_[0.0, be[:k - 1]])
+    lo, hi = np.min(al - rad), np.max(al + rad)
+    c0, R = 0.5 * (lo + hi), 0.5 * (hi - lo)
+    X = np.diag(np.abs(al - c0)) + np.diag(np.abs(be[:k - 1]), 1) + np.diag(np.abs(be[:k - 1]), -1)
+    f = np.minimum(1.0, scipy.linalg.expm(X)[:, 0]) if R <= 30 else np.ones(k)
+    tot = sum(f[j - 1] * (reps * be[j - 1] + rabs) / (1.0 - reps) for j in range(1, k))
+    return nrm * tot
+
+
+def round_to_bits(z, bits):
+    """Round the real and imaginary parts of z to `bits` significand bits
+    (round to nearest), emulating a narrower storage format."""
+    def rnd(x):
+        m, e = np.frexp(x)
+        scale = 2.0 ** bits
+        return np.ldexp(np.round(m * scale) / scale, e)
+    return rnd(z.real) + 1j * rnd(z.imag)
+
+
+def match_converged(a_vals, a_bds, b_vals, b_bds, tol, robust=0.25):
+    """Compare two sets of converged Ritz values (each within its bound of an
+    eigenvalue of H).  Every value of either set whose bound is <= robust*tol
+    must have a partner in the other set within 2 (b_a + b_b) + 1e-8; a value
+    with a larger bound (it converged near the end, or only just) may be
+    missing on the other side, but if a partner lies within tol it must meet
+    the same closeness.  Returns the number of matched pairs; raises
+    AssertionError with the offending value otherwise."""
+    a_vals, a_bds = np.asarray(a_vals), np.asarray(a_bds)
+    b_vals, b_bds = np.asarray(b_vals), np.asarray(b_bds)
+    matched = 0
+    for (xv, xb, yv, yb, side) in ((a_vals, a_bds, b_vals, b_bds, "first"), (b_vals, b_bds, a_vals, a_bds, "second")):
+        for v, bd in zip(xv, xb):
+            d = np.abs(yv - v) if len(yv) else np.array([np.inf])
+            i = int(np.argmin(d))
+            close = len(yv) > 0 and d[i] <= 2.0 * (bd + yb[i]) + 1e-8
+            if bd <= robust * tol:
+                assert close, (side, float(v), float(bd), "no partner")
+            elif len(yv) and d[i] <= tol:
+                assert close, (side, float(v), float(bd), float(yv[i]), "partner too far")
+            if side == "first" and close:
+                matched += 1
+    return matched

@@ -33,25 +33,24 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_params_layout_matches_c(tmp_path):
-    fields = [f[0] for f in binding.DlParams._fields_]
-    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "dirac_lanczos.h"', "int main(){",
-           'printf("%zu\\n", sizeof(dl_params));', 'printf("%zu\\n", sizeof(dl_step_stat));']
-    for f in fields:
-        src.append(f'printf("%zu\\n", offsetof(dl_params, {f}));')
-    for f in ("k_eff", "err_est", "cum_bound", "norm2"):
-        src.append(f'printf("%zu\\n", offsetof(dl_step_stat, {f}));')
+    """Every struct of the header has the binding's size and field offsets."""
+    structs = [("dl_params", binding.DlParams), ("dl_step_stat", binding.DlStepStat),
+               ("dl_adapt_stat", binding.DlAdaptStat), ("dl_timing", binding.DlTiming)]
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "dirac_lanczos.h"', "int main(){"]
+    for cname, cls in structs:
+        src.append(f'printf("%zu\\n", sizeof({cname}));')
+        for f in cls._fields_:
+            src.append(f'printf("%zu\\n", offsetof({cname}, {f[0]}));')
     src.append("return 0;}")
     c = tmp_path / "layout.c"
     c.write_text("\n".join(src))
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-I", os.path.dirname(HEADER), str(c), "-o", str(exe)])
-    vals = [int(v) for v in subprocess.check_output([str(exe)], text=True).split()]
-    assert vals[0] == ctypes.sizeof(binding.DlParams)
-    assert vals[1] == ctypes.sizeof(binding.DlStepStat)
-    for f, off in zip(fields, vals[2:2 + len(fields)]):
-        assert getattr(binding.DlParams, f).offset == off, f
-    for f, off in zip(("k_eff", "err_est", "cum_bound", "norm2"), vals[2 + len(fields):]):
-        assert getattr(binding.DlStepStat, f).offset == off, f
+    vals = iter(int(v) for v in subprocess.check_output([str(exe)], text=True).split())
+    for cname, cls in structs:
+        assert next(vals) == ctypes.sizeof(cls), cname
+        for f in cls._fields_:
+            assert next(vals) == getattr(cls, f[0]).offset, (cname, f[0])
 
 
 def _params(cfg, m, prec):

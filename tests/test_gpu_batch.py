@@ -91,17 +91,30 @@ def test_batch_fp64_vs_single_and_oracle(torch_cuda, orc, bc):
         assert rel(outb[i], ref) <= 1e-10, i
 
 
-def test_batch_mixed_vs_single(torch_cuda):
+def mixed_tolerance(st, psi0, rst):
+    """Summed a-priori storage bounds of a mixed run plus both runs' Krylov
+    estimates, relative to ||psi_0||, plus the FP64 tolerance."""
+    return (st["cum_round_bound"][-1] + st["cum_bound"][-1] + rst["cum_bound"][-1]) / np.linalg.norm(psi0) + 1e-10
+
+
+def test_batch_mixed_vs_single_and_oracle(torch_cuda, orc):
+    """The batch's own precision (complex64 Krylov vectors, the wide
+    recombination) against the oracle, at the a-priori storage bound each
+    packet's statistics report, and against the single-grid mixed run."""
     probs = small_batch(0)
     psi0 = states(probs, 20)
     dt, n, m = 1e-3, 12, 12
     say(f"batch mixed {len(probs)} packets {n} steps")
-    outb, _ = run_batch(torch_cuda, probs, psi0, m, "mixed", dt, n)
+    outb, stb = run_batch(torch_cuda, probs, psi0, m, "mixed", dt, n)
     for i, p in enumerate(probs):
         outs, _ = run_single(torch_cuda, p, psi0[i], m, "mixed", dt, n)
-        ref, _ = run_single(torch_cuda, p, psi0[i], m, "fp64", dt, n)
         assert rel(outb[i], outs) <= 1e-8, i
-        assert rel(outb[i], ref) <= 1e-6, i
+        ref, rst = orc.propagate(p, psi0[i], 0.0, dt, n, m)
+        tol = mixed_tolerance(stb[i], psi0[i], rst)
+        err = rel(outb[i], ref)
+        print(f"packet {i} {p['nx']}x{p['ny']}: mixed vs oracle {err:.3e} (bound {tol:.3e})", flush=True)
+        assert err <= tol and tol <= 1e-6, i
+        assert np.all(stb[i]["round_bound"] > 0)
 
 
 @pytest.mark.parametrize("m", [1, 2, 64])
@@ -147,9 +160,10 @@ def test_batch_rejections(torch_cuda):
     assert e.value.status == DL_ERR_INVALID
 
 
-def test_batch_256_packets_sampled(torch_cuda):
+def test_batch_256_packets_sampled(torch_cuda, orc):
     """The 256-packet workload (28M sites, mixed, m = 12): a few steps of the
-    whole batch, sampled packets against their single-grid runs."""
+    whole batch, sampled packets against their single-grid runs and against
+    the oracle at their a-priori storage bounds."""
     torch = torch_cuda
     cfgs = packets.packet_batch(seed=0)
     probs = [c["problem"] for c in cfgs]
@@ -158,9 +172,14 @@ def test_batch_256_packets_sampled(torch_cuda):
     say(f"batch 256 packets mixed {n} steps")
     outb, stb = run_batch(torch, probs, psi0, m, "mixed", dt, n)
     assert all(np.all(s["k_eff"] == m) for s in stb)
-    for i in (0, 1, 77, 128, 255):
+    for i in (0, 1, 77, 128, 200, 255):
         outs, _ = run_single(torch, probs[i], psi0[i], m, "mixed", dt, n)
         assert rel(outb[i], outs) <= 1e-8, i
+        ref, rst = orc.propagate(probs[i], psi0[i], 0.0, dt, n, m)
+        tol = mixed_tolerance(stb[i], psi0[i], rst)
+        err = rel(outb[i], ref)
+        print(f"packet {i} {probs[i]['nx']}^2: mixed vs oracle {err:.3e} (bound {tol:.3e})", flush=True)
+        assert err <= tol and tol <= 1e-6, i
 
 
 def test_launch_shapes_agree_to_rounding(torch_cuda, tmp_path):

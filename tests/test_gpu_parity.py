@@ -5,6 +5,7 @@ the FP64 propagator); single-operator applications to 1e-13.  Every case
 prints its name before touching the GPU.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -181,7 +182,9 @@ def test_max_krylov_dim(torch_cuda, Prop, orc, dt, prec, tol):
     got, st = gpu_run(torch_cuda, Prop, prob, 64, prec, psi0, 0.0, dt, 3)
     ref, rst = orc.propagate(prob, psi0, 0.0, dt, 3, 64)
     err = hz.rel_l2(got, ref)
-    print(f"m=64 dt={dt} {prec}: rel-L2 {err:.3e}", flush=True)
+    if prec == "mixed":
+        tol = mixed_tolerance(st, psi0, rst)
+    print(f"m=64 dt={dt} {prec}: rel-L2 {err:.3e} (tolerance {tol:.3e})", flush=True)
     assert err <= tol
     assert np.all(st["k_eff"] == 64) and np.all(rst["k_eff"] == 64)
     assert np.allclose(st["norm2"], rst["norm2"], rtol=tol, atol=0.0)
@@ -330,17 +333,37 @@ def test_invalid_calls(torch_cuda, Prop):
 # ---------------------------------------------------------------------------
 # Mixed precision
 # ---------------------------------------------------------------------------
+def mixed_tolerance(st, psi0, rst=None):
+    """Relative distance allowed between a mixed-precision run and the FP64
+    oracle: the summed a-priori storage bounds of the steps (round_bound) plus
+    both runs' Krylov estimates, relative to ||psi_0||, plus the FP64 parity
+    tolerance 1e-10 for the arithmetic both share."""
+    nrm = np.linalg.norm(psi0)
+    kry = st["cum_bound"][-1] + (rst["cum_bound"][-1] if rst is not None else 0.0)
+    return (st["cum_round_bound"][-1] + kry) / nrm + 1e-10
+
+
 def test_mixed_vs_fp64_reduced(torch_cuda, Prop, orc):
     cfg = packets.with_grid(packets.laser_4096(), 256)
     prob = dict(cfg["problem"], t_pulse=100 * cfg["dt"])
     say("mixed vs fp64 laser 256x256 m=16 100 steps")
     psi0 = packets.initial_state(cfg)
     mx, smx = gpu_run(torch_cuda, Prop, prob, 16, "mixed", psi0, 0.0, cfg["dt"], 100)
-    ref, _ = orc.propagate(prob, psi0, 0.0, cfg["dt"], 100, 16)
+    ref, rst = orc.propagate(prob, psi0, 0.0, cfg["dt"], 100, 16)
     err = hz.rel_l2(mx, ref)
-    print(f"mixed rel-L2 vs oracle after 100 steps: {err:.3e}", flush=True)
-    assert err <= 1e-6
+    tol = mixed_tolerance(smx, psi0, rst)
+    print(f"mixed rel-L2 vs oracle after 100 steps: {err:.3e} (bound {tol:.3e})", flush=True)
+    assert err <= tol and tol <= 1e-6
     assert np.all(smx["k_eff"] == 16)
+    assert np.all(smx["round_bound"] > 0)
+    # the device's bound of step 1 is the formula on the step's tridiagonal T
+    # (here the oracle's T, which differs from the mixed run's by rounding)
+    _, _, al, be = orc.lanczos(prob, psi0, 16, dt=cfg["dt"], a_hom=tuple(orc.field_average(prob, 0.0, cfg["dt"])))
+    expect = hz.storage_bound(al, be, np.linalg.norm(psi0), 2.0 ** -24,
+                              2.0 ** -126 * math.sqrt(4 * prob["nx"] * prob["ny"]))
+    assert abs(smx["round_bound"][0] - expect) <= 1e-3 * expect, (smx["round_bound"][0], expect)
+    _, sfp = gpu_run(torch_cuda, Prop, prob, 16, "fp64", psi0, 0.0, cfg["dt"], 3)
+    assert np.all(sfp["round_bound"] == 0.0)
 
 
 def test_wide_recombination_ragged(torch_cuda, Prop, orc):
@@ -355,9 +378,10 @@ def test_wide_recombination_ragged(torch_cuda, Prop, orc):
     got, st = gpu_run(torch_cuda, Prop, prob, 16, "mixed", psi0, 0.0, cfg["dt"], 2)
     ref, rst = orc.propagate(prob, psi0, 0.0, cfg["dt"], 2, 16)
     err = hz.rel_l2(got, ref)
-    print(f"1100x997 mixed: rel-L2 {err:.3e}", flush=True)
-    assert err <= 1e-6
-    np.testing.assert_allclose(st["norm2"], rst["norm2"], rtol=1e-6)
+    tol = mixed_tolerance(st, psi0, rst)
+    print(f"1100x997 mixed: rel-L2 {err:.3e} (bound {tol:.3e})", flush=True)
+    assert err <= tol
+    np.testing.assert_allclose(st["norm2"], rst["norm2"], rtol=2 * tol)
 
 
 # ---------------------------------------------------------------------------
@@ -374,7 +398,7 @@ def test_eigen_landau_vs_oracle(torch_cuda, Prop, orc):
     prop = Prop(prob, 1, "fp64", k_eigen=200)
     ev, bd = prop.eigen(torch.from_numpy(psi0).cuda(), 200, mc2 - 0.5, mc2 + 9.0, 1e-5)
     prop.close()
-    rev, rbd, _ = orc.eigen(prob, psi0, 200, mc2 - 0.5, mc2 + 9.0, 1e-5)
+    rev, rbd, _ = orc.eigen_plain(prob, psi0, 200, mc2 - 0.5, mc2 + 9.0, 1e-5)
     assert len(ev) >= 1 and len(ev) == len(rev)
     assert np.allclose(ev, rev, atol=1e-8)
     # first Landau level of this lattice (h = 10/64) within its O(h^2) error
@@ -384,7 +408,9 @@ def test_eigen_landau_vs_oracle(torch_cuda, Prop, orc):
 
 def test_eigen_landau_softcore_vs_oracle(torch_cuda, Prop, orc):
     """B = 0.5 plus soft-core potential (the 1024^2 workload's physics) on a
-    256^2 grid over the same box: converged Ritz clusters agree with the oracle."""
+    256^2 grid over the same box: the converged Ritz values of the GPU's plain
+    recurrence and of the oracle's (both accumulated over the checkpoints
+    k = 64, 128, ...) are the same eigenvalues, every one of them."""
     torch = torch_cuda
     mc2 = C * C
     cfg = packets.with_grid(packets.landau_softcore_1024(), 256)
@@ -395,30 +421,50 @@ def test_eigen_landau_softcore_vs_oracle(torch_cuda, Prop, orc):
     prop = Prop(prob, 1, "fp64", k_eigen=600)
     ev, bd = prop.eigen(torch.from_numpy(psi0).cuda(), 600, lo, hi, tol)
     prop.close()
-    rev, rbd, _ = orc.eigen(prob, psi0, 600, lo, hi, tol)
+    rev, rbd, _ = orc.eigen_plain(prob, psi0, 600, lo, hi, tol)
     print("eigen 256^2 gpu:", np.round(ev - mc2, 9).tolist(), "oracle:", np.round(rev - mc2, 9).tolist(),
           flush=True)
     assert len(rev) >= 2
-    # every value converged on both sides is the same eigenvalue
-    common = [e for e in ev if np.min(np.abs(rev - e)) <= 1e-7]
-    assert len(common) >= max(1, min(len(ev), len(rev)) - 1)
-    assert np.all(bd <= tol) and np.all(np.diff(ev) > 0)
+    assert hz.match_converged(ev, bd, rev, rbd, tol) == len(ev) == len(rev)
+    assert np.all(bd <= tol) and np.all(np.diff(ev) > tol)
 
 
-def test_eigen_full_grid_properties(torch_cuda, Prop):
-    """Full 1024^2 eigen run: converged, sorted, distinct values inside the window."""
+def _golden_eigen_1024():
+    path = os.path.join(os.path.dirname(__file__), "golden", "eigen_landau_softcore_1024.txt")
+    rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    return np.array([float(r[0]) for r in rows]), np.array([float(r[1]) for r in rows])
+
+
+def test_eigen_full_grid_vs_oracle(torch_cuda, Prop):
+    """The full 1024^2 eigen workload (plain Lanczos, K = 2000, window
+    E - mc^2 in [-2, 5], tol 1e-6) against the oracle's converged values for
+    the same start vector (tests/golden/eigen_landau_softcore_1024.txt, written
+    by make_eigen_landau1024.py from the oracle alone): every value converged
+    on either side with a bound below tol/4 is found by the other, and the
+    eight lowest values of a run that stops once eight have converged (the
+    benchmark's call) are all oracle values."""
     torch = torch_cuda
     mc2 = C * C
     cfg = packets.landau_softcore_1024()
     prob = cfg["problem"]
-    say("eigen B+soft-core 1024x1024 K=2000")
+    say("eigen B+soft-core 1024x1024 K=2000 vs oracle")
     psi0 = packets.initial_state(cfg)
     lo, hi, tol = mc2 - 2.0, mc2 + 5.0, 1e-6
+    gold, gbd = _golden_eigen_1024()
     prop = Prop(prob, 1, "fp64", k_eigen=2000)
-    ev, bd = prop.eigen(torch.from_numpy(psi0).cuda(), 2000, lo, hi, tol, n_wanted=8)
+    x = torch.from_numpy(psi0).cuda()
+    ev, bd = prop.eigen(x, 2000, lo, hi, tol, n_wanted=64)
+    ev8, bd8 = prop.eigen(x, 2000, lo, hi, tol, n_wanted=8)
     prop.close()
-    print("eigen 1024^2 (E - mc^2):", np.round(ev - mc2, 8).tolist(), flush=True)
-    assert 1 <= len(ev) <= 8
+    print("eigen 1024^2 (E - mc^2) gpu:", np.round(ev - mc2, 9).tolist(), flush=True)
+    print("                      oracle:", np.round(gold, 9).tolist(), flush=True)
+    print("            gpu, stop at 8:", np.round(ev8 - mc2, 9).tolist(), flush=True)
+    n = hz.match_converged(ev - mc2, bd, gold, gbd, tol)
+    assert n >= len(gold) - 2 and n >= 8
+    assert len(ev8) == 8
+    for v, b in zip(ev8 - mc2, bd8):
+        i = int(np.argmin(np.abs(gold - v)))
+        assert abs(gold[i] - v) <= 2 * (b + gbd[i]) + 1e-8, (v, b)
     assert np.all(bd <= tol) and np.all(np.diff(ev) > tol)
     assert np.all(ev >= lo) and np.all(ev <= hi)
 
@@ -434,6 +480,6 @@ def test_chirality_minus_propagation(torch_cuda, Prop, orc, prec):
     out, st = gpu_run(torch_cuda, Prop, prob, 12, prec, psi0, 0.0, 1e-3, 20)
     ref, rst = orc.propagate(prob, psi0, 0.0, 1e-3, 20, 12)
     err = hz.rel_l2(out, ref)
-    assert err <= (1e-10 if prec == "fp64" else 1e-6), err
+    assert err <= (1e-10 if prec == "fp64" else mixed_tolerance(st, psi0, rst)), err
     plus, _ = orc.propagate(dict(prob, chirality=1), psi0, 0.0, 1e-3, 20, 12)
     assert hz.rel_l2(plus, ref) > 1e-3  # the chirality matters for this state
