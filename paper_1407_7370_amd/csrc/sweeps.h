@@ -912,27 +912,112 @@ __device__ void predict_k(const double *alpha, const double *gamma, Scalars *sc,
 // y(t) = ||psi|| Q exp(-itT) e_1 then solves y' = -iAy + i(beta_k q_{k+1} e_k^T
 // - F) s(t) with s(t) = ||psi|| exp(-itT) e_1 and y(0) = psi, so for Hermitian
 // A the error at t = 1 is at most int_0^1 ||F s(t)|| dt (plus the Krylov term
-// of eq. matrix_exponential_error), with no assumption of orthogonality.
-// With X = T' - c0 I (c0, R: centre and half-width of T's Gershgorin
-// interval) and |X| its entrywise absolute value, the path sums of X^n give
-// |s_j(t)| <= ||psi|| [exp(t|X|) e_1]_j <= ||psi|| [exp(|X|) e_1]_j for t in
-// [0, 1]; exp(|X|) e_1 is summed as its Taylor series (non-negative terms, no
-// cancellation) with N = 3R + 40 terms plus the tail bound
-// R^(N+1) e^R / (N+1)!, and capped at 1 (|s_j| <= ||psi||).  Beyond R = 30 the
-// factor is 1.  Lane l handles j = l + 1; beta_j is lane l's coupling e.
-constexpr double kStoreBoundMaxR = 30.0;
+// of eq. matrix_exponential_error), with no assumption of orthogonality, and
+// int_0^1 |s_j(t)| dt <= (int_0^1 |s_j(t)|^2 dt)^(1/2) (Cauchy-Schwarz).
+// While the Gershgorin half-width R of T (centre c0) is at most 40 the
+// integral is taken by 48-node Gauss-Legendre quadrature on [0, 1] (|s_j|^2
+// is a trigonometric sum of frequencies below 2R, far inside the rule's
+// resolution), with s carried from node to node by short Chebyshev expansions
+// of exp(-i delta (T - c0 I)) (Bessel coefficients J_n(delta R) by Miller's
+// backward recurrence, one lane per node) and a 1% margin on the integral.
+// The scalar phase exp(-i delta c0) of each Chebyshev step does not change
+// |s_j| and is left out.  For 40 < R <= 70: |s_j(t)| <= ||psi||
+// [exp(t|X|) e_1]_j for X = T - c0 I (path sums of X^n), a Taylor series of
+// non-negative terms with N = 3R + 40 terms plus its tail bound, capped at 1;
+// beyond R = 70 the factor is 1.  Lane l handles j = l + 1; beta_j is lane
+// l's coupling e.
+constexpr int kBoundNodes = 48;
+constexpr int kBoundMaxTerms = 40;
+constexpr double kBoundMaxR = 40.0;
+
+// Gauss-Legendre node (on [0, 1], ascending in q) and weight of rule size n
+// for node q < n (Newton's method on P_n).
+__device__ void gauss_legendre01(int n, int q, double &t, double &w)
+{
+    double x = cos(3.14159265358979323846 * (q + 0.75) / (n + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+        double p0 = 1.0, p1 = 0.0;
+        for (int j = 1; j <= n; ++j) {
+            const double p2 = p1;
+            p1 = p0;
+            p0 = ((2.0 * j - 1.0) * x * p1 - (j - 1.0) * p2) / j;
+        }
+        dp = n * (x * p0 - p1) / (x * x - 1.0);
+        const double dx = p0 / dp;
+        x -= dx;
+        if (fabs(dx) < 1e-16) break;
+    }
+    t = 0.5 * (1.0 - x);
+    w = 1.0 / ((1.0 - x * x) * dp * dp);
+}
 
 __device__ double storage_bound(double d, double e, double em, int k, int lane, double g1, double reps,
                                 double rabs)
 {
+    __shared__ double jtab[kBoundNodes][kBoundMaxTerms + 1];
+    __shared__ double tnode[kBoundNodes], wnode[kBoundNodes];
     if (!(reps > 0.0) && !(rabs > 0.0)) return 0.0;
     const double rad = fabs(e) + fabs(em);
     const double glo = wave_min(lane < k ? d - rad : INFINITY);
     const double ghi = wave_max(lane < k ? d + rad : -INFINITY);
     const double c0 = 0.5 * (glo + ghi), R = 0.5 * (ghi - glo);
     double f = 1.0;
-    if (R <= kStoreBoundMaxR) {
-        // rows of |X| beyond k are zero (d, e, em are zero there)
+    if (R <= kBoundMaxR) {
+        double tq = 0.0, wq = 0.0;
+        if (lane < kBoundNodes) gauss_legendre01(kBoundNodes, lane, tq, wq);
+        __syncthreads();  // tables of an earlier call are read up to here
+        if (lane < kBoundNodes) {
+            tnode[lane] = tq;
+            wnode[lane] = wq;
+        }
+        const double tprev = __shfl_up(tq, 1, 64);
+        const double delta = lane < kBoundNodes ? (lane == 0 ? tq : tq - tprev) : 0.0;
+        const double xmax = wave_max(delta) * R;
+        const int N = xmax > 0.0 ? min(cheb_terms(xmax), kBoundMaxTerms) : 0;
+        if (lane < kBoundNodes) {
+            if (delta * R > 0.0) {
+                bessel_miller(delta * R, N, &jtab[lane][0]);
+            } else {
+                jtab[lane][0] = 1.0;
+                for (int n = 1; n <= N; ++n) jtab[lane][n] = 0.0;
+            }
+        }
+        __syncthreads();
+        const double ir = R > 0.0 ? 1.0 / R : 0.0;
+        const double xd = lane < k ? (d - c0) * ir : 0.0, xe = e * ir, xem = em * ir;
+        auto xmul = [&](double v) { return xem * from_left(v) + xd * v + xe * from_right(v); };
+        double sr = lane == 0 ? 1.0 : 0.0, si = 0.0, integral = 0.0;
+        for (int q = 0; q < kBoundNodes; ++q) {
+            // exp(-i dq (T - c0)) s = sum_n a_n T_n(X) s, a_0 = J_0, a_n = 2 (-i)^n J_n(dq R),
+            // dq = t_q - t_{q-1}
+            double pr = sr, pi = si;                // T_{n-1}(X) s
+            double cr = xmul(sr), ci = xmul(si);    // T_n(X) s
+            double ar = jtab[q][0] * sr, ai = jtab[q][0] * si;
+            if (N >= 1) {
+                ar += 2.0 * jtab[q][1] * ci;
+                ai -= 2.0 * jtab[q][1] * cr;
+            }
+            for (int n = 2; n <= N; ++n) {
+                const double nr = 2.0 * xmul(cr) - pr, ni = 2.0 * xmul(ci) - pi;
+                const double fj = 2.0 * jtab[q][n];
+                switch (n & 3) {
+                case 0: ar += fj * nr; ai += fj * ni; break;
+                case 1: ar += fj * ni; ai -= fj * nr; break;
+                case 2: ar -= fj * nr; ai -= fj * ni; break;
+                default: ar -= fj * ni; ai += fj * nr; break;
+                }
+                pr = cr;
+                pi = ci;
+                cr = nr;
+                ci = ni;
+            }
+            sr = ar;
+            si = ai;
+            integral += wnode[q] * (sr * sr + si * si);
+        }
+        f = fmin(1.0, sqrt(1.01 * integral));
+    } else if (R <= 30.0 + kBoundMaxR) {
+        // X = T - c0 I with entrywise absolute value: |s_j(t)| <= [exp(|X|) e_1]_j
         const double xd = lane < k ? fabs(d - c0) : 0.0, xe = fabs(e), xem = fabs(em);
         const int N = (int)ceil(3.0 * R) + 40;
         double t = lane == 0 ? 1.0 : 0.0, v = t;
@@ -940,7 +1025,7 @@ __device__ double storage_bound(double d, double e, double em, int k, int lane, 
             t = (xem * from_left(t) + xd * t + xe * from_right(t)) / (double)n;
             v += t;
         }
-        const double tail = R > 0.0 ? exp((double)(N + 1) * log(R) + R - lgamma((double)N + 2.0)) : 0.0;
+        const double tail = exp((double)(N + 1) * log(R) + R - lgamma((double)N + 2.0));
         f = fmin(1.0, v + tail);
     }
     double v = (lane + 1 < k) ? f * (reps * fabs(e) + rabs) / (1.0 - reps) : 0.0;

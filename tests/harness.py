@@ -203,11 +203,12 @@ def lanczos_dense(A, psi, k):
 def storage_bound(alpha, beta, nrm, reps, rabs):
     """Bound of the error from rounding the stored Krylov vectors u_2..u_k
     (relative rounding reps, absolute rabs per vector):
-    ||psi|| sum_{j<k} f_j (reps beta_j + rabs) / (1 - reps), where f_j bounds
-    max_{t in [0,1]} |[exp(-itT)]_{j1}|: with X = T - c0 I (c0 the centre of
-    T's Gershgorin interval, half-width R) and |X| its entrywise absolute
-    value, |[exp(-itX)]_{j1}| <= [exp(t|X|)]_{j1} <= [exp(|X|)]_{j1} (path sums
-    of non-negative terms), capped at 1; scipy's expm evaluates exp(|X|)."""
+    ||psi|| sum_{j<k} f_j (reps beta_j + rabs) / (1 - reps) with f_j a bound
+    of int_0^1 |[exp(-itT)]_{j1}| dt.  T's Gershgorin interval has centre c0
+    and half-width R.  R <= 40: f_j = (1.01 int_0^1 |[exp(-itT)]_{j1}|^2 dt)^(1/2)
+    (Cauchy-Schwarz), the integral by 48-node Gauss-Legendre quadrature of the
+    eigendecomposition (numpy eigh); R <= 70: f_j = [exp(|T - c0 I|)]_{j1}
+    (path sums; scipy expm); both capped at 1, and 1 beyond."""
     import scipy.linalg
     al = np.asarray(alpha, dtype=float)
     be = np.asarray(beta, dtype=float)
@@ -216,8 +217,19 @@ def storage_bound(alpha, beta, nrm, reps, rabs):
     rad = np.abs(off) + np.abs(np.r_[0.0, be[:k - 1]])
     lo, hi = np.min(al - rad), np.max(al + rad)
     c0, R = 0.5 * (lo + hi), 0.5 * (hi - lo)
-    X = np.diag(np.abs(al - c0)) + np.diag(np.abs(be[:k - 1]), 1) + np.diag(np.abs(be[:k - 1]), -1)
-    f = np.minimum(1.0, scipy.linalg.expm(X)[:, 0]) if R <= 30 else np.ones(k)
+    if R <= 40:
+        T = np.diag(al - c0) + np.diag(be[:k - 1], 1) + np.diag(be[:k - 1], -1)
+        lam, V = np.linalg.eigh(T)
+        x, wq = np.polynomial.legendre.leggauss(48)
+        integral = np.zeros(k)
+        for tq, w in zip(0.5 * (x + 1.0), 0.5 * wq):
+            integral += w * np.abs(V @ (np.exp(-1j * tq * lam) * V[0, :])) ** 2
+        f = np.minimum(1.0, np.sqrt(1.01 * integral))
+    elif R <= 70:
+        X = np.diag(np.abs(al - c0)) + np.diag(np.abs(be[:k - 1]), 1) + np.diag(np.abs(be[:k - 1]), -1)
+        f = np.minimum(1.0, scipy.linalg.expm(X)[:, 0])
+    else:
+        f = np.ones(k)
     tot = sum(f[j - 1] * (reps * be[j - 1] + rabs) / (1.0 - reps) for j in range(1, k))
     return nrm * tot
 
