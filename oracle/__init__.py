@@ -234,7 +234,7 @@ def ritz_clusters(alpha, beta, e_lo: float, e_hi: float, tol: float, max_out: in
 
 
 def converged_union(alpha, beta, e_lo: float, e_hi: float, tol: float, check_every: int = 64,
-                    max_out: int = 64):
+                    max_out: int = 64, return_first: bool = False):
     """Converged Ritz clusters accumulated over the leading blocks T_j,
     j = check_every, 2 check_every, ..., and j = k (all of T).  Once
     orthogonality is lost a converged Ritz value acquires copies whose
@@ -243,21 +243,25 @@ def converged_union(alpha, beta, e_lo: float, e_hi: float, tol: float, check_eve
     lies within that bound of an eigenvalue of H all the same (Paige's
     analysis of the finite-precision recurrence).  Values closer than tol are
     one eigenvalue; each keeps the value and bound of its smallest bound.
-    Returns (values, bounds), ascending (at most max_out, the lowest)."""
+    Returns (values, bounds), ascending (at most max_out, the lowest), and
+    with return_first also the first j at which each value converged."""
     k = len(alpha)
     marks = list(range(check_every, k, check_every)) + [k]
-    found = []  # [value, bound]
+    found = []  # [value, bound, first j]
     for j in marks:
         ev, bd = ritz_clusters(alpha[:j], beta[:j], e_lo, e_hi, tol, max_out=1 << 30)
         for e, b in zip(ev, bd):
             near = [f for f in found if abs(f[0] - e) <= tol]
             if not near:
-                found.append([e, b])
+                found.append([e, b, j])
             elif b < near[0][1]:
                 near[0][0], near[0][1] = e, b
     found.sort()
     found = found[:max_out]
-    return np.array([f[0] for f in found]), np.array([f[1] for f in found])
+    out = (np.array([f[0] for f in found]), np.array([f[1] for f in found]))
+    if return_first:
+        out += (np.array([f[2] for f in found], dtype=np.int64),)
+    return out
 
 
 def eigen_plain(prob: dict, psi0: np.ndarray, k: int, e_lo: float, e_hi: float, tol: float,

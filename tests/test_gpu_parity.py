@@ -434,17 +434,20 @@ def test_eigen_landau_softcore_vs_oracle(torch_cuda, Prop, orc):
 def _golden_eigen_1024():
     path = os.path.join(os.path.dirname(__file__), "golden", "eigen_landau_softcore_1024.txt")
     rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
-    return np.array([float(r[0]) for r in rows]), np.array([float(r[1]) for r in rows])
+    return (np.array([float(r[0]) for r in rows]), np.array([float(r[1]) for r in rows]),
+            np.array([int(r[2]) for r in rows]))
 
 
 def test_eigen_full_grid_vs_oracle(torch_cuda, Prop):
     """The full 1024^2 eigen workload (plain Lanczos, K = 2000, window
     E - mc^2 in [-2, 5], tol 1e-6) against the oracle's converged values for
     the same start vector (tests/golden/eigen_landau_softcore_1024.txt, written
-    by make_eigen_landau1024.py from the oracle alone): every value converged
-    on either side with a bound below tol/4 is found by the other, and the
-    eight lowest values of a run that stops once eight have converged (the
-    benchmark's call) are all oracle values."""
+    by make_eigen_landau1024.py from the oracle alone, K = 4000, with the
+    iteration at which each value first converged).  Which values converge
+    near the end of a run depends on the rounding history, so: every GPU value
+    with a bound below tol/4 is an oracle value; every oracle value converged
+    by k = 1500 is a GPU value; and the eight values of a run that stops once
+    eight have converged (the benchmark's call) are oracle values."""
     torch = torch_cuda
     mc2 = C * C
     cfg = packets.landau_softcore_1024()
@@ -452,21 +455,30 @@ def test_eigen_full_grid_vs_oracle(torch_cuda, Prop):
     say("eigen B+soft-core 1024x1024 K=2000 vs oracle")
     psi0 = packets.initial_state(cfg)
     lo, hi, tol = mc2 - 2.0, mc2 + 5.0, 1e-6
-    gold, gbd = _golden_eigen_1024()
+    gold, gbd, gfirst = _golden_eigen_1024()
     prop = Prop(prob, 1, "fp64", k_eigen=2000)
     x = torch.from_numpy(psi0).cuda()
     ev, bd = prop.eigen(x, 2000, lo, hi, tol, n_wanted=64)
     ev8, bd8 = prop.eigen(x, 2000, lo, hi, tol, n_wanted=8)
     prop.close()
     print("eigen 1024^2 (E - mc^2) gpu:", np.round(ev - mc2, 9).tolist(), flush=True)
-    print("                      oracle:", np.round(gold, 9).tolist(), flush=True)
+    print("               oracle K=4000:", np.round(gold, 9).tolist(), flush=True)
     print("            gpu, stop at 8:", np.round(ev8 - mc2, 9).tolist(), flush=True)
-    n = hz.match_converged(ev - mc2, bd, gold, gbd, tol)
-    assert n >= len(gold) - 2 and n >= 8
+
+    def partner(v, b, vals, bds):
+        i = int(np.argmin(np.abs(vals - v)))
+        return abs(vals[i] - v) <= 2.0 * (b + bds[i]) + 1e-8
+
+    for v, b in zip(ev - mc2, bd):
+        if b <= 0.25 * tol:
+            assert partner(v, b, gold, gbd), ("gpu value not in the oracle set", v, b)
+    early = gfirst <= 1500
+    assert early.sum() >= 8
+    for v, b in zip(gold[early], gbd[early]):
+        assert partner(v, b, ev - mc2, bd), ("oracle value converged by k = 1500 missing", v, b)
     assert len(ev8) == 8
     for v, b in zip(ev8 - mc2, bd8):
-        i = int(np.argmin(np.abs(gold - v)))
-        assert abs(gold[i] - v) <= 2 * (b + gbd[i]) + 1e-8, (v, b)
+        assert partner(v, b, gold, gbd), ("stop-at-8 value not in the oracle set", v, b)
     assert np.all(bd <= tol) and np.all(np.diff(ev) > tol)
     assert np.all(ev >= lo) and np.all(ev <= hi)
 
