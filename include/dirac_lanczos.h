@@ -427,6 +427,29 @@ typedef struct {
 
 dl_status dirac_lanczos_timing(dl_context *ctx, int32_t enable, dl_timing *out);
 
+/*
+ * For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): n_steps steps of
+ * dirac_lanczos_step for the problem `params`, on hip_stream (NULL: the
+ * default stream), without a context or a caller workspace.  The workspace of
+ * the step lives in a static device array of 64 MiB that every GPU the
+ * library runs on holds until the process ends; the problem must fit it
+ * (dirac_lanczos_workspace_bytes(params, DL_MODE_STEP, 0) <= 64 MiB: about
+ * 350^2 sites in FP64 or 490^2 in mixed precision at m = 16), otherwise
+ * DL_ERR_WORKSPACE before any device work.  The call allocates nothing on the
+ * device or the host.  Calls on one GPU share that array: calls that overlap
+ * in time on a GPU (from several threads or streams) race; sequential calls
+ * are independent (each starts from zeroed scalars).  params->coef is read
+ * during the call only.  psi (DEVICE) as for dirac_lanczos_step.
+ * stats != NULL (HOST, n_steps entries): synchronous, statistics and
+ * DL_ERR_NONFINITE as for dirac_lanczos_step.  stats == NULL: the work is only
+ * enqueued (kernels only, no host copies), and a non-finite reduction is not
+ * reported.  Errors: DL_ERR_INVALID, DL_ERR_WORKSPACE, DL_ERR_DEVICE (no
+ * gfx950 device, or a HIP failure); no message is kept.
+ */
+dl_status dirac_lanczos_step_noalloc(const dl_params *params, void *psi, double t0, double dt, int32_t n_steps,
+                                     void *hip_stream, dl_step_stat *stats);
+
 /* Free the host context (the caller frees its own device buffers). */
 dl_status dirac_lanczos_destroy(dl_context *ctx);
 

@@ -29,7 +29,7 @@ EXPORTS = ("dirac_lanczos_workspace_bytes", "dirac_lanczos_init", "dirac_lanczos
            "dirac_lanczos_batch_step", "dirac_lanczos_batch_destroy", "dirac_lanczos_batch_last_error",
            "dirac_lanczos_set_launch", "dirac_lanczos_batch_set_launch", "dirac_lanczos_step_adaptive",
            "dirac_lanczos_step_lowmem", "dirac_lanczos_eigen_vectors", "dirac_lanczos_step_ktol",
-           "dirac_lanczos_wait")
+           "dirac_lanczos_wait", "dirac_lanczos_step_noalloc")
 DL_LOSS_X, DL_LOSS_Y, DL_LOSS_PX, DL_LOSS_PY = 1, 2, 4, 8
 
 
@@ -120,6 +120,9 @@ def load_library():
     lib.dirac_lanczos_step_ktol.restype = ctypes.c_int
     lib.dirac_lanczos_wait.argtypes = [vp, ctypes.POINTER(DlStepStat), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     lib.dirac_lanczos_wait.restype = ctypes.c_int
+    lib.dirac_lanczos_step_noalloc.argtypes = [P, vp, ctypes.c_double, ctypes.c_double, ctypes.c_int32, vp,
+                                               ctypes.POINTER(DlStepStat)]
+    lib.dirac_lanczos_step_noalloc.restype = ctypes.c_int
     lib.dirac_lanczos_eigen.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                         ctypes.c_double, ctypes.c_double, ctypes.c_int32, D, D,
                                         ctypes.POINTER(ctypes.c_int32)]
@@ -221,6 +224,12 @@ def dirac_lanczos_apply(ctx, x_ptr: int, y_ptr: int, t: float) -> int:
 
 def dirac_lanczos_step(ctx, psi_ptr: int, t0: float, dt: float, n_steps: int, stats=None) -> int:
     return load_library().dirac_lanczos_step(ctx, ctypes.c_void_p(psi_ptr), t0, dt, n_steps, stats)
+
+
+def dirac_lanczos_step_noalloc(params: DlParams, psi_ptr: int, t0: float, dt: float, n_steps: int,
+                               stream_ptr: int, stats=None) -> int:
+    return load_library().dirac_lanczos_step_noalloc(ctypes.byref(params), ctypes.c_void_p(psi_ptr), t0, dt,
+                                                     n_steps, ctypes.c_void_p(stream_ptr), stats)
 
 
 def dirac_lanczos_wait(ctx, stats=None, n_stats: int = 0, steps_done=None) -> int:

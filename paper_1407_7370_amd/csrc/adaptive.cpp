@@ -32,7 +32,7 @@ using namespace dlh;
 namespace {
 
 // int_t^{t+h} |a(s) - a_bar| ds for the homogeneous laser field (h > 0).
-double field_deviation(const dl_params &p, const std::vector<double> &coef, double t, double h)
+double field_deviation(const dl_params &p, CoefView coef, double t, double h)
 {
     if (p.pulse_kind == 0 || t >= p.t_pulse || t + h <= 0.0) return 0.0;
     static const double gx[3] = {-0.7745966692414834, 0.0, 0.7745966692414834};

@@ -56,8 +56,19 @@ inline ReorthLayout reorth_layout(size_t n, int k)
     return R;
 }
 const char *validate(const dl_params *p);
-void pulse_now(const dl_params &p, const std::vector<double> &coef, double t, double *a);
-void pulse_average(const dl_params &p, const std::vector<double> &coef, double t0, double dt, double *a);
+// Fourier coefficients of the laser field (a context's copy, or a caller's
+// array for the duration of one call).
+struct CoefView {
+    const double *c = nullptr;
+    size_t n = 0;
+    CoefView() = default;
+    CoefView(const std::vector<double> &v) : c(v.data()), n(v.size()) {}
+    CoefView(const double *p, size_t k) : c(p), n(p ? k : 0) {}
+    size_t size() const { return n; }
+    double operator[](size_t i) const { return c[i]; }
+};
+void pulse_now(const dl_params &p, CoefView coef, double t, double *a);
+void pulse_average(const dl_params &p, CoefView coef, double t0, double dt, double *a);
 // Step average of one Fourier basis function of the sin^2-enveloped pulse:
 // harmonic k, sine (cosine = false) or cosine (cosine = true).
 double basis_average(const dl_params &p, int k, bool cosine, double t0, double dt);
@@ -271,6 +282,10 @@ dl_status run_twice(dl_context *ctx, const Engine &e, const dl::Op &op, const do
 // exp(-iT) and the recombination into `out` (stat receives k_eff, estimate, norm).
 dl_status run_finish(dl_context *ctx, const Engine &e, const double2 *in, double2 *out,
                      dl::StepStat *stat, double *partials);
+
+// Default launch shapes of a context's sweeps and recombination (ctx->p and
+// ctx->cus set).
+void configure_launch(dl_context *ctx);
 
 // Report (DL_ERR_NONFINITE) and clear a failure of an earlier asynchronous
 // step call that dirac_lanczos_wait has not reported; DL_OK otherwise.  Every

@@ -94,7 +94,7 @@ const char *validate(const dl_params *p)
 // --- homogeneous laser field --------------------------------------------------
 const double kPi = 3.14159265358979323846;
 
-void pulse_now(const dl_params &p, const std::vector<double> &coef, double t, double *a)
+void pulse_now(const dl_params &p, CoefView coef, double t, double *a)
 {
     a[0] = a[1] = 0.0;
     if (p.pulse_kind == 0 || t < 0.0 || t > p.t_pulse) return;
@@ -149,8 +149,7 @@ double basis_average(const dl_params &p, int k, bool cosine, double t0, double d
 // (1/|dt|) integral of A_L over the step [t0, t0 + dt]; the envelope
 // sin^2(pi t/T) = (1 - cos(W t))/2 (W = 2 pi/T) turns every term into single
 // sines and cosines whose integrals are closed forms.
-void pulse_average(const dl_params &p, const std::vector<double> &coef, double t0, double dt,
-                   double *a)
+void pulse_average(const dl_params &p, CoefView coef, double t0, double dt, double *a)
 {
     a[0] = a[1] = 0.0;
     if (p.pulse_kind == 0) return;
@@ -533,6 +532,8 @@ void set_tiles(dl_context *ctx, int cap)
 }
 
 }  // namespace
+
+void dlh::configure_launch(dl_context *ctx) { set_tiles(ctx, 0); }
 
 extern "C" {
 
