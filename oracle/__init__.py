@@ -51,6 +51,24 @@ class _Params(ctypes.Structure):
     ]
 
 
+class _HParams(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("scale", ctypes.c_double), ("mass", ctypes.c_double),
+                ("c", ctypes.c_double), ("charge", ctypes.c_double), ("bz", ctypes.c_double),
+                ("pot_kind", ctypes.c_int32), ("pot_z", ctypes.c_double), ("pot_a", ctypes.c_double),
+                ("chirality", ctypes.c_int32)]
+
+
+def _hparams(hprob: dict) -> _HParams:
+    p = _HParams()
+    p.n = int(hprob["n"])
+    p.scale = float(hprob["scale"])
+    for k, d in (("mass", 1.0), ("c", 137.036), ("charge", -1.0), ("bz", 0.0), ("pot_z", 0.0), ("pot_a", 0.0)):
+        setattr(p, k, float(hprob.get(k, d)))
+    p.pot_kind = int(hprob.get("pot_kind", 0))
+    p.chirality = int(hprob.get("chirality", 0))
+    return p
+
+
 class _Stat(ctypes.Structure):
     _fields_ = [("k_eff", ctypes.c_int32), ("err_est", ctypes.c_double),
                 ("cum_bound", ctypes.c_double), ("norm2", ctypes.c_double)]
@@ -92,6 +110,13 @@ def _load():
                                           ctypes.POINTER(ctypes.c_int), D]
         lib.orc_eigen_vectors.restype = ctypes.c_int
         lib.orc_pauli.argtypes = [ctypes.c_int, D]
+        HP = ctypes.POINTER(_HParams)
+        lib.orc_hermite_nodes.argtypes = [ctypes.c_int, D, D]
+        lib.orc_hermite_dmat.argtypes = [ctypes.c_int, D, D, D]
+        lib.orc_hermite_operator.argtypes = [HP, D, D]
+        lib.orc_apply_h_hermite.argtypes = [HP, D, D]
+        lib.orc_lanczos_plain_hermite.argtypes = [HP, D, ctypes.c_int, D, D]
+        lib.orc_lanczos_plain_hermite.restype = ctypes.c_int
         lib.orc_expectations.argtypes = [P, D, D]
         _lib = lib
     return _lib
@@ -487,3 +512,71 @@ def dense_exact_gradient(prob: dict, psi0: np.ndarray, t0: float, dt: float, n_s
         re_n = float(np.vdot(psi, t).real)
         grad[j] = 2.0 * (re_o - loss * re_n) / nrm
     return loss, grad
+
+
+# ---------------------------------------------------------------------------
+# Hermite pseudospectral discretisation (Sec. 5).  A Hermite problem is a dict
+# with keys n (collocation points per axis), scale (x = scale * xi), mass, c,
+# charge, bz, pot_kind, pot_z, pot_a, chirality; spinors are complex128
+# arrays (2, n, n) of the variables sqrt(lambda_i lambda_j) psi(x_i, y_j).
+# ---------------------------------------------------------------------------
+def hermite_nodes(n: int):
+    """Roots xi of the n-th Hermite polynomial (ascending) and the
+    Christoffel numbers lambda of the Hermite functions (unit scale)."""
+    lib = _load()
+    xi = np.zeros(n)
+    lam = np.zeros(n)
+    lib.orc_hermite_nodes(int(n), _dp(xi), _dp(lam))
+    return xi, lam
+
+
+def hermite_dmat(n: int) -> np.ndarray:
+    """The antisymmetric derivative matrix D~ of the collocation variables
+    (unit scale), built from the Hermite functions."""
+    lib = _load()
+    xi, lam = hermite_nodes(n)
+    D = np.zeros((n, n))
+    lib.orc_hermite_dmat(int(n), _dp(xi), _dp(lam), _dp(D))
+    return D
+
+
+def hermite_operator(hprob: dict):
+    """(scaled nodes x, D~ / scale) of a Hermite problem."""
+    lib = _load()
+    p = _hparams(hprob)
+    n = p.n
+    x = np.zeros(n)
+    D = np.zeros((n, n))
+    lib.orc_hermite_operator(ctypes.byref(p), _dp(x), _dp(D))
+    return x, D
+
+
+def apply_h_hermite(hprob: dict, phi: np.ndarray) -> np.ndarray:
+    lib = _load()
+    p = _hparams(hprob)
+    phi = np.ascontiguousarray(phi, dtype=np.complex128)
+    assert phi.shape == (2, p.n, p.n)
+    out = np.empty_like(phi)
+    lib.orc_apply_h_hermite(ctypes.byref(p), _dp(phi.view(np.float64)), _dp(out.view(np.float64)))
+    return out
+
+
+def lanczos_plain_hermite(hprob: dict, phi: np.ndarray, k: int):
+    """Three-vector Lanczos on the Hermite H: (k_eff, alpha, beta)."""
+    lib = _load()
+    p = _hparams(hprob)
+    phi = np.ascontiguousarray(phi, dtype=np.complex128)
+    assert phi.shape == (2, p.n, p.n)
+    al = np.zeros(k)
+    be = np.zeros(k)
+    keff = lib.orc_lanczos_plain_hermite(ctypes.byref(p), _dp(phi.view(np.float64)), int(k), _dp(al), _dp(be))
+    return keff, al[:keff], be[:keff]
+
+
+def eigen_hermite(hprob: dict, phi0: np.ndarray, k: int, e_lo: float, e_hi: float, tol: float,
+                  max_out: int = 64, check_every: int = 64):
+    """Eigenvalue mode on the Hermite H: converged Ritz clusters accumulated
+    over the checkpoints (converged_union).  Returns (values, bounds, k_eff)."""
+    keff, al, be = lanczos_plain_hermite(hprob, phi0, k)
+    ev, bd = converged_union(al, be, e_lo, e_hi, tol, check_every, max_out)
+    return ev, bd, keff

@@ -32,6 +32,9 @@
  *                     (no reorthogonalisation; eigenvalue mode at scale).
  *   orc_eigen         Sec. 2, Ritz values and bound eq. error_est; Sec. 5.
  *   orc_eigen_vectors Sec. 2 eq. eigenvec_approx (Ritz vectors, full reorth).
+ *   orc_hermite_*     Sec. 5, Hermite pseudospectral discretisation: collocation
+ *                     at the roots of the N-th Hermite polynomial, dense
+ *                     differentiation matrices.
  *
  * Readings where the paper is silent (shared with the GPU library only as
  * written conventions, never as code):
@@ -333,28 +336,27 @@ int orc_lanczos(const orc_params *p, const double *a_hom, double dt, const doubl
     return keff;
 }
 
+/* An operator out = Op in on vectors of n complex entries. */
+typedef void (*orc_op)(const void *ctx, const cplx *in, cplx *out);
+
 /*
  * Plain Lanczos recurrence with three stored vectors (Sec. 2: without
  * reorthogonalisation only q_{i-1}, q_i and z are needed; the Ritz values
  * follow from alpha and beta alone).  The loop is the one of orc_lanczos with
  * reorth = 0 -- the same operations in the same order -- so alpha and beta
- * agree with it bit for bit; only the storage differs.  Used by the eigenvalue
- * mode on grids where k stored vectors would not fit in memory.  Returns
- * k_eff (0 for b = 0); alpha[0..k_eff-1], beta[0..k_eff-1] (beta[k_eff-1] is
+ * agree with it bit for bit; only the storage differs.  Returns k_eff (0 for
+ * b = 0); alpha[0..k_eff-1], beta[0..k_eff-1] (beta[k_eff-1] is
  * ||z - alpha_k q_k|| after the last iteration, the input of eq. error_est).
  */
-int orc_lanczos_plain(const orc_params *p, const double *a_hom, double dt, const double *b_d, int k,
-                      double *alpha, double *beta)
+static int lanczos3(size_t n, orc_op op, const void *ctx, const cplx *b, int k, double *alpha, double *beta)
 {
-    const size_t n = (size_t)2 * p->nx * p->ny;
-    const cplx *b = (const cplx *)b_d;
     const double nb = vnorm(n, b);
     if (nb == 0.0) return 0;
     cplx *qprev = (cplx *)malloc(n * sizeof(cplx));
     cplx *qcur = (cplx *)malloc(n * sizeof(cplx));
     cplx *z = (cplx *)malloc(n * sizeof(cplx));
     for (size_t t = 0; t < n; ++t) qcur[t] = b[t] / nb;
-    apply_a(p, a_hom, dt, qcur, z);
+    op(ctx, qcur, z);
     double scale = 0.0;
     int keff = k;
     for (int i = 1; i <= k; ++i) {
@@ -371,7 +373,7 @@ int orc_lanczos_plain(const orc_params *p, const double *a_hom, double dt, const
         /* q_{i+1} = z / beta_i replaces q_{i-1}; z = A q_{i+1} - beta_i q_i */
         cplx *qn = qprev;
         for (size_t t = 0; t < n; ++t) qn[t] = z[t] / beta[i - 1];
-        apply_a(p, a_hom, dt, qn, z);
+        op(ctx, qn, z);
         for (size_t t = 0; t < n; ++t) z[t] -= beta[i - 1] * qcur[t];
         qprev = qcur;
         qcur = qn;
@@ -380,6 +382,26 @@ int orc_lanczos_plain(const orc_params *p, const double *a_hom, double dt, const
     free(qcur);
     free(z);
     return keff;
+}
+
+typedef struct {
+    const orc_params *p;
+    const double *a_hom;
+    double dt;
+} fd_op_ctx;
+
+static void fd_op(const void *ctx, const cplx *in, cplx *out)
+{
+    const fd_op_ctx *c = (const fd_op_ctx *)ctx;
+    apply_a(c->p, c->a_hom, c->dt, in, out);
+}
+
+/* The finite-difference A = dt H of orc_lanczos with three stored vectors. */
+int orc_lanczos_plain(const orc_params *p, const double *a_hom, double dt, const double *b_d, int k,
+                      double *alpha, double *beta)
+{
+    const fd_op_ctx ctx = {p, a_hom, dt};
+    return lanczos3((size_t)2 * p->nx * p->ny, fd_op, &ctx, (const cplx *)b_d, k, alpha, beta);
 }
 
 /*
@@ -665,4 +687,217 @@ void orc_expectations(const orc_params *p, const double *psi_d, double *out)
     out[2] = n > 0 ? sy / n : 0.0;
     out[3] = n > 0 ? creal(spx) / n : 0.0;
     out[4] = n > 0 ? creal(spy) / n : 0.0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Hermite pseudospectral discretisation (Sec. 5).  Each spinor component is */
+/* represented by its values at the N x N collocation points (x_i, y_j),     */
+/* x_i = scale * xi_i with xi_i the roots of the N-th Hermite polynomial,    */
+/* i.e. in the span of the tensor products of the first N Hermite functions. */
+/* The variables are phi_ij = sqrt(lambda_i lambda_j) psi(x_i, y_j) with the  */
+/* Christoffel numbers lambda (scaled), so that sum |phi|^2 is the L^2 norm   */
+/* of the interpolant and the derivative is an antisymmetric matrix D~:      */
+/* H is Hermitian in the Euclidean inner product, as in the finite-difference */
+/* discretisation.                                                           */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t n;              /* collocation points per axis */
+    double scale;           /* x = scale * xi */
+    double mass, c, charge;
+    double bz;              /* uniform magnetic field, symmetric gauge */
+    int32_t pot_kind;       /* as orc_params */
+    double pot_z, pot_a;
+    int32_t chirality;
+} orc_hparams;
+
+/* Orthonormal Hermite functions h_0..h_nmax at x (three-term recurrence). */
+static void hermite_functions(int nmax, double x, double *h)
+{
+    h[0] = pow(M_PI, -0.25) * exp(-0.5 * x * x);
+    if (nmax >= 1) h[1] = sqrt(2.0) * x * h[0];
+    for (int n = 1; n < nmax; ++n) h[n + 1] = sqrt(2.0 / (n + 1)) * x * h[n] - sqrt((double)n / (n + 1)) * h[n - 1];
+}
+
+/*
+ * Roots xi_0 < ... < xi_{N-1} of the N-th Hermite polynomial (the eigenvalues
+ * of its Jacobi matrix: zero diagonal, off-diagonal sqrt(k/2), k = 1..N-1, by
+ * the oracle's cyclic Jacobi, then Newton on h_N) and the Christoffel numbers
+ * lambda_i = 1 / sum_{n<N} h_n(xi_i)^2 (the quadrature sum_i lambda_i
+ * f(xi_i) integrates h_a h_b exactly for a, b < N).
+ */
+void orc_hermite_nodes(int N, double *xi, double *lambda)
+{
+    double *al = (double *)calloc(N, sizeof(double)), *be = (double *)calloc(N, sizeof(double));
+    double *V = (double *)malloc(sizeof(double) * N * N), *h = (double *)malloc(sizeof(double) * (N + 2));
+    for (int k = 1; k < N; ++k) be[k - 1] = sqrt(0.5 * k);
+    orc_tridiag_eig(N, al, be, xi, V);
+    /* ascending (insertion sort) */
+    for (int a = 1; a < N; ++a) {
+        const double v = xi[a];
+        int b = a - 1;
+        while (b >= 0 && xi[b] > v) {
+            xi[b + 1] = xi[b];
+            --b;
+        }
+        xi[b + 1] = v;
+    }
+    for (int i = 0; i < N; ++i) {
+        double x = xi[i];
+        for (int it = 0; it < 20; ++it) {
+            hermite_functions(N, x, h);
+            /* h_N' = sqrt(2N) h_{N-1} - x h_N */
+            const double d = sqrt(2.0 * N) * h[N - 1] - x * h[N];
+            const double dx = h[N] / d;
+            x -= dx;
+            if (fabs(dx) <= 1e-16 * (1.0 + fabs(x))) break;
+        }
+        xi[i] = x;
+        hermite_functions(N, x, h);
+        double s2 = 0.0;
+        for (int n = 0; n < N; ++n) s2 += h[n] * h[n];
+        lambda[i] = 1.0 / s2;
+    }
+    free(al);
+    free(be);
+    free(V);
+    free(h);
+}
+
+/*
+ * D~ (N x N, row-major, unit scale): the derivative of the interpolant in
+ * span{h_0..h_{N-1}} in the variables phi_i = sqrt(lambda_i) f(xi_i), built
+ * from the basis: with E_in = sqrt(lambda_i) h_n(xi_i) (orthogonal: E^T E =
+ * I by the exact quadrature) and E'_in = sqrt(lambda_i) h_n'(xi_i),
+ * h_n' = sqrt(n/2) h_{n-1} - sqrt((n+1)/2) h_{n+1}, D~ = E' E^T.
+ */
+void orc_hermite_dmat(int N, const double *xi, const double *lambda, double *dmat)
+{
+    double *E = (double *)malloc(sizeof(double) * N * N), *Ed = (double *)malloc(sizeof(double) * N * N);
+    double *h = (double *)malloc(sizeof(double) * (N + 2));
+    for (int i = 0; i < N; ++i) {
+        hermite_functions(N, xi[i], h);
+        const double w = sqrt(lambda[i]);
+        for (int n = 0; n < N; ++n) {
+            E[i * N + n] = w * h[n];
+            const double dn = (n > 0 ? sqrt(0.5 * n) * h[n - 1] : 0.0) - sqrt(0.5 * (n + 1)) * h[n + 1];
+            Ed[i * N + n] = w * dn;
+        }
+    }
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) {
+            double acc = 0.0;
+            for (int n = 0; n < N; ++n) acc += Ed[i * N + n] * E[j * N + n];
+            dmat[i * N + j] = acc;
+        }
+    free(E);
+    free(Ed);
+    free(h);
+}
+
+typedef struct {
+    const orc_hparams *p;
+    double *x;   /* scaled nodes */
+    double *D;   /* D~ / scale */
+} herm_op_ctx;
+
+static void herm_setup(const orc_hparams *p, herm_op_ctx *c)
+{
+    const int N = p->n;
+    double *lam = (double *)malloc(sizeof(double) * N);
+    c->p = p;
+    c->x = (double *)malloc(sizeof(double) * N);
+    c->D = (double *)malloc(sizeof(double) * N * N);
+    orc_hermite_nodes(N, c->x, lam);
+    orc_hermite_dmat(N, c->x, lam, c->D);
+    for (int i = 0; i < N; ++i) c->x[i] *= p->scale;
+    for (int i = 0; i < N * N; ++i) c->D[i] /= p->scale;
+    free(lam);
+}
+
+static void herm_free(herm_op_ctx *c)
+{
+    free(c->x);
+    free(c->D);
+}
+
+static double herm_potential(const orc_hparams *p, double x, double y)
+{
+    if (p->pot_kind == 1) return -p->pot_z / sqrt(x * x + y * y + p->pot_a * p->pot_a);
+    if (p->pot_kind == 2) return -1.5 * p->pot_z / sqrt(x * x + y * y + 3.0 / (p->pot_z * p->pot_z));
+    return 0.0;
+}
+
+/*
+ * out = H in for the Hermite collocation variables (layout (2, N, N), x
+ * fastest): H = c [sigma1 (p_x - q A_x) + chi sigma2 (p_y - q A_y)] +
+ * sigma3 m c^2 + V with p = -i D~ along each axis and A = (B/2)(-y, x)
+ * (Sec. 3 Hamiltonian, Sec. 5 discretisation).
+ */
+static void herm_op(const void *ctx, const cplx *in, cplx *out)
+{
+    const herm_op_ctx *c = (const herm_op_ctx *)ctx;
+    const orc_hparams *p = c->p;
+    const int N = p->n;
+    const double mc2 = p->mass * p->c * p->c;
+    cplx s1[2][2], s2[2][2], s3[2][2];
+    pauli(1, s1);
+    pauli(2, s2);
+    pauli(3, s3);
+    const double chi = p->chirality < 0 ? -1.0 : 1.0;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) s2[a][b] *= chi;
+    for (int j = 0; j < N; ++j) {
+        const double y = c->x[j];
+        for (int i = 0; i < N; ++i) {
+            const double x = c->x[i];
+            const double v = herm_potential(p, x, y);
+            const double ax = -0.5 * p->bz * y, ay = 0.5 * p->bz * x;
+            cplx psi[2], pix[2], piy[2];
+            for (int s = 0; s < 2; ++s) {
+                const cplx *f = in + (size_t)s * N * N;
+                psi[s] = f[j * N + i];
+                cplx dx = 0, dy = 0;
+                for (int k = 0; k < N; ++k) {
+                    dx += c->D[i * N + k] * f[j * N + k];
+                    dy += c->D[j * N + k] * f[k * N + i];
+                }
+                pix[s] = -I * dx - p->charge * ax * psi[s];
+                piy[s] = -I * dy - p->charge * ay * psi[s];
+            }
+            for (int a = 0; a < 2; ++a) {
+                cplx acc = v * psi[a];
+                for (int b = 0; b < 2; ++b)
+                    acc += p->c * (s1[a][b] * pix[b] + s2[a][b] * piy[b]) + mc2 * s3[a][b] * psi[b];
+                out[(size_t)a * N * N + j * N + i] = acc;
+            }
+        }
+    }
+}
+
+/* Scaled nodes x_i and D~ / scale of the problem (x: N, dmat: N*N). */
+void orc_hermite_operator(const orc_hparams *p, double *x, double *dmat)
+{
+    herm_op_ctx c;
+    herm_setup(p, &c);
+    memcpy(x, c.x, sizeof(double) * p->n);
+    memcpy(dmat, c.D, sizeof(double) * p->n * p->n);
+    herm_free(&c);
+}
+
+void orc_apply_h_hermite(const orc_hparams *p, const double *in_d, double *out_d)
+{
+    herm_op_ctx c;
+    herm_setup(p, &c);
+    herm_op(&c, (const cplx *)in_d, (cplx *)out_d);
+    herm_free(&c);
+}
+
+/* The three-vector recurrence (Sec. 2) on the Hermite H (eigenvalue mode). */
+int orc_lanczos_plain_hermite(const orc_hparams *p, const double *b_d, int k, double *alpha, double *beta)
+{
+    herm_op_ctx c;
+    herm_setup(p, &c);
+    const int keff = lanczos3((size_t)2 * p->n * p->n, herm_op, &c, (const cplx *)b_d, k, alpha, beta);
+    herm_free(&c);
+    return keff;
 }

@@ -186,3 +186,38 @@ def random_spinor(prob: dict, seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     shape = (2, prob["ny"], prob["nx"])
     return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+# ----------------------------------------------------------------------------
+# Hermite pseudospectral problems (Sec. 5 of the paper).  A Hermite problem is
+# a dict: n (collocation points per axis), scale (x = scale * xi, xi the roots
+# of the n-th Hermite polynomial), mass, c, charge, bz, pot_kind, pot_z, pot_a,
+# chirality.  Spinors are complex128 arrays (2, n, n) of the collocation
+# variables sqrt(w_i w_j) psi(x_i, y_j) (w: the scaled quadrature weights of
+# the Hermite functions), so that sum |phi|^2 is the L^2 norm.
+# ----------------------------------------------------------------------------
+
+
+def softcore_hermite(Z: float, n: int = 64, kappa: float = 1.8, chirality: int = 0):
+    """The paper's soft-core problem (eq. soft_core_pot, -(3/2) Z / sqrt(r^2 +
+    3/Z^2)) on n x n Hermite collocation points with length scale kappa / Z
+    (the scale is not stated in the paper; kappa = 1.8 lies on the plateau
+    where the ground states of its soft-core table converge)."""
+    return dict(n=int(n), scale=kappa / Z, mass=1.0, c=C_LIGHT, charge=-1.0, bz=0.0, pot_kind=2,
+                pot_z=float(Z), pot_a=0.0, chirality=int(chirality))
+
+
+def hermite_packet(hprob: dict, width: float, center=(0.0, 0.0)) -> np.ndarray:
+    """Normalised Gaussian start vector exp(-|r - r0|^2 / (2 width^2)) (1, 0)^T
+    in the collocation variables (nodes and weights from numpy's Gauss-Hermite
+    rule; an off-centre r0 couples to every angular momentum)."""
+    from numpy.polynomial.hermite import hermgauss
+    n, s = int(hprob["n"]), float(hprob["scale"])
+    xi, w = hermgauss(n)
+    x = s * xi
+    sw = np.sqrt(s * w * np.exp(xi * xi))
+    gx = np.exp(-((x - center[0]) ** 2) / (2 * width * width)) * sw
+    gy = np.exp(-((x - center[1]) ** 2) / (2 * width * width)) * sw
+    phi = np.zeros((2, n, n), dtype=np.complex128)
+    phi[0] = np.outer(gy, gx)
+    return phi / np.linalg.norm(phi)
