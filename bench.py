@@ -372,6 +372,52 @@ def run_eigen(torch, Propagator, packets):
     return out
 
 
+def run_hermite(torch, packets, k=1000):
+    """Hermite pseudospectral eigenvalue mode (64 x 64 collocation points,
+    k Lanczos iterations per problem, one workgroup per problem in one
+    launch): the six problems of the paper's ground-state table, the Z = 50
+    excited-state table, and a 256-problem scan of the soft-core ground state
+    over Z = 1 .. 50 (one problem per compute unit).  The matrix
+    products, 16 n^3 FP64 flops per H application, run on the matrix cores."""
+    from paper_1407_7370_amd import binding
+    mc2 = 137.036 ** 2
+    out = {"what": f"Hermite pseudospectral eigen mode, n = 64, {k} Lanczos iterations per problem"}
+    flops_mv = 16 * 64 ** 3
+
+    def run(probs, lo, hi, tol, nw):
+        starts = [torch.from_numpy(packets.hermite_packet(h, 1.0 / h["pot_z"], (0.4 / h["pot_z"], 0.25 / h["pot_z"])))
+                  .cuda() for h in probs]
+        binding.hermite_eigen(probs[:1], starts[:1], 16, lo[:1], hi[:1], tol, nw)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = binding.hermite_eigen(probs, starts, k, lo, hi, tol, nw)
+        torch.cuda.synchronize()
+        return res, time.perf_counter() - t0
+
+    zs = [1.0, 2.0, 3.0, 5.0, 10.0, 50.0]
+    probs = [packets.softcore_hermite(z) for z in zs]
+    res, sec = run(probs, [mc2 - 0.6 * z * z for z in zs], [mc2 - 0.4 * z * z for z in zs], 2.5e-6, 4)
+    out["ground_state_table"] = {"problems": len(zs), "seconds": sec,
+                                 "values_minus_mc2": {str(z): round(float(r[0][0] - mc2), 10) for z, r in zip(zs, res)},
+                                 "tflops": len(zs) * k * flops_mv / sec / 1e12}
+    hp = packets.softcore_hermite(50.0)
+    res, sec = run([hp], [mc2 - 1500.0], [mc2 - 350.0], 1e-5, 9)
+    out["z50_states"] = {"seconds": sec, "values_minus_mc2": [round(float(v - mc2), 6) for v in res[0][0]]}
+    zscan = [1.0 + 49.0 * i / 255 for i in range(256)]
+    scan = [packets.softcore_hermite(z) for z in zscan]
+    res, sec = run(scan, [mc2 - 0.6 * z * z for z in zscan], [mc2 - 0.4 * z * z for z in zscan], 2.5e-6, 1)
+    achieved = 256 * k * flops_mv / sec / 1e12
+    out["z_scan_256"] = {"problems": 256, "Z": "1 .. 50", "seconds": sec, "tflops": achieved,
+                         "frac_of_fp64_matrix_peak": achieved / 78.6,
+                         "converged": int(sum(len(r[0]) > 0 for r in res)),
+                         "ground_state_Z1_Z50": [round(float(res[0][0][0] - mc2), 9) if len(res[0][0]) else None,
+                                                 round(float(res[-1][0][0] - mc2), 6) if len(res[-1][0]) else None]}
+    log(f"hermite: table of 6 in {out['ground_state_table']['seconds'] * 1e3:.1f} ms, Z=50 in "
+        f"{out['z50_states']['seconds'] * 1e3:.1f} ms, 256-problem Z scan in {sec * 1e3:.1f} ms "
+        f"({achieved:.2f} TFLOP/s FP64 matrix)")
+    return out
+
+
 def run_batch(torch, packets, steps):
     """The 256-packet batch (grids 128^2..512^2, B_z ~ U[0,2], mixed, m = 12):
     one batched step call vs the same packets propagated one context at a
@@ -432,9 +478,9 @@ def main():
                     help="steps of the 256-packet batch measurement (0: skip)")
     ap.add_argument("--lowmem-steps", type=int, default=20,
                     help="steps of the memory-saving (second Lanczos run) measurement (0: skip)")
-    ap.add_argument("--extras", default="ktol,adaptive_dt,chirality,paper_shape,adjoint,eigen",
+    ap.add_argument("--extras", default="ktol,adaptive_dt,chirality,paper_shape,adjoint,eigen,hermite",
                     help="comma-separated extra measurements: ktol, adaptive_dt, chirality, paper_shape, "
-                         "adjoint, eigen (empty: none)")
+                         "adjoint, eigen, hermite (empty: none)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run a plain copy of this many MiB (counter calibration for rocprofv3)")
     args = ap.parse_args()
@@ -567,6 +613,8 @@ def main():
         out["adjoint"] = run_adjoint(torch, Propagator, packets)
     if "eigen" in extras:
         out["eigen"] = run_eigen(torch, Propagator, packets)
+    if "hermite" in extras:
+        out["hermite"] = run_hermite(torch, packets)
 
     if not args.no_cpu_baseline:
         import oracle

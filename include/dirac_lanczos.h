@@ -394,6 +394,64 @@ dl_status dirac_lanczos_batch_destroy(dl_batch *batch);
 const char *dirac_lanczos_batch_last_error(const dl_batch *batch);
 
 /*
+ * Hermite pseudospectral discretisation (Sec. 5): each spinor component is
+ * represented by its values at the n x n collocation points (x_i, y_j),
+ * x_i = scale * xi_i with xi_i the roots of the n-th Hermite polynomial (the
+ * span of the products of the first n Hermite functions; the wave function
+ * vanishes at infinity), and the derivatives by dense n x n matrices.
+ * Spinors are DEVICE arrays of 2 n^2 complex128 in the layout (2, n, n), x
+ * fastest, of the variables phi_ij = sqrt(w_i w_j) psi(x_i, y_j) with w the
+ * weights of dirac_lanczos_hermite_nodes, so that the Euclidean norm is the
+ * L^2 norm; in them the derivative D~_ij = (-1)^(i+j) / (x_i - x_j) (i != j,
+ * zero diagonal) is antisymmetric and H = c [sigma1 (p_x - q A_x) +
+ * chi sigma2 (p_y - q A_y)] + sigma3 m c^2 + V, p = -i D~ along each axis,
+ * A = (B/2)(-y, x), is Hermitian.  V as in dl_params (pot_kind 0, 1 or 2).
+ * n is 16, 32, 48 or 64.  The matrix products run on the FP64 matrix cores.
+ */
+typedef struct {
+    int32_t n;          /* collocation points per axis */
+    double scale;       /* length scale of the Hermite functions */
+    double mass, c, charge;
+    double bz;          /* uniform B_z, symmetric gauge about the origin */
+    int32_t pot_kind;
+    double pot_z, pot_a;
+    int32_t chirality;  /* as dl_params */
+} dl_hermite_params;
+
+/* HOST: the n collocation points x (ascending, times scale) and weights w
+ * (Christoffel numbers of the Hermite functions, times scale: sum_i w_i f(x_i)
+ * integrates f exactly on products of the first n Hermite functions). */
+dl_status dirac_lanczos_hermite_nodes(int32_t n, double scale, double *x, double *w);
+
+/* Bytes of DEVICE workspace (256-byte aligned) for n_problems problems and up
+ * to k_max Lanczos iterations (0 for invalid parameters). */
+size_t dirac_lanczos_hermite_workspace_bytes(const dl_hermite_params *params, int32_t n_problems, int32_t k_max);
+
+/* y = H x for one problem (x, y DEVICE spinors, distinct); the workspace is
+ * sized for (params, 1, 1).  Synchronous on hip_stream. */
+dl_status dirac_lanczos_hermite_apply(const dl_hermite_params *params, const void *x, void *y, void *workspace,
+                                      size_t ws_bytes, void *hip_stream);
+
+/* Eigenvalue mode for a batch of problems (Sec. 2, Sec. 5): k_max
+ * iterations of the plain Lanczos recurrence of Fig. 1 from psi0[i] (HOST
+ * array of DEVICE start vectors), one workgroup per problem and all
+ * iterations in one launch; then, per problem, the converged Ritz clusters
+ * of the leading blocks T_k, k = 64, 128, ... and k_max, in [e_lo[i],
+ * e_hi[i]] with bound <= tol, accumulated as in dirac_lanczos_eigen with
+ * reorth = 0.  evals/bounds: HOST arrays of n_problems * n_wanted (problem i
+ * at offset i * n_wanted, ascending), n_found: HOST array of n_problems.  A
+ * start vector of norm 0 reports nothing.  Errors: DL_ERR_INVALID,
+ * DL_ERR_WORKSPACE, DL_ERR_NONFINITE (a reduction of some problem became
+ * non-finite; the others are reported), DL_ERR_DEVICE.  Synchronous. */
+dl_status dirac_lanczos_hermite_eigen(const dl_hermite_params *params, int32_t n_problems, const void *const *psi0,
+                                      int32_t k_max, const double *e_lo, const double *e_hi, double tol,
+                                      int32_t n_wanted, void *workspace, size_t ws_bytes, void *hip_stream,
+                                      double *evals, double *bounds, int32_t *n_found);
+
+/* Message of the last failing Hermite call on this thread ("" if none). */
+const char *dirac_lanczos_hermite_last_error(void);
+
+/*
  * Launch shape (tuning; results are equal to rounding for every shape).
  * dirac_lanczos_set_launch: at most sweep_waves_per_cu waves per compute unit
  *   in the Lanczos sweeps (0: the built-in default, floor(strips * ny /

@@ -29,7 +29,9 @@ EXPORTS = ("dirac_lanczos_workspace_bytes", "dirac_lanczos_init", "dirac_lanczos
            "dirac_lanczos_batch_step", "dirac_lanczos_batch_destroy", "dirac_lanczos_batch_last_error",
            "dirac_lanczos_set_launch", "dirac_lanczos_batch_set_launch", "dirac_lanczos_step_adaptive",
            "dirac_lanczos_step_lowmem", "dirac_lanczos_eigen_vectors", "dirac_lanczos_step_ktol",
-           "dirac_lanczos_wait", "dirac_lanczos_step_noalloc")
+           "dirac_lanczos_wait", "dirac_lanczos_step_noalloc", "dirac_lanczos_hermite_nodes",
+           "dirac_lanczos_hermite_workspace_bytes", "dirac_lanczos_hermite_apply", "dirac_lanczos_hermite_eigen",
+           "dirac_lanczos_hermite_last_error")
 DL_LOSS_X, DL_LOSS_Y, DL_LOSS_PX, DL_LOSS_PY = 1, 2, 4, 8
 
 
@@ -68,6 +70,25 @@ def stats_dict(stats) -> dict:
             "norm2": np.array([s.norm2 for s in stats]),
             "round_bound": rb,
             "cum_round_bound": np.cumsum(rb)}
+
+
+class DlHermiteParams(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("scale", ctypes.c_double), ("mass", ctypes.c_double),
+                ("c", ctypes.c_double), ("charge", ctypes.c_double), ("bz", ctypes.c_double),
+                ("pot_kind", ctypes.c_int32), ("pot_z", ctypes.c_double), ("pot_a", ctypes.c_double),
+                ("chirality", ctypes.c_int32)]
+
+
+def make_hermite_params(hprob: dict) -> DlHermiteParams:
+    """dl_hermite_params from a Hermite problem dict (keys as in packets.py)."""
+    p = DlHermiteParams()
+    p.n = int(hprob["n"])
+    p.scale = float(hprob["scale"])
+    for k, d in (("mass", 1.0), ("c", 137.036), ("charge", -1.0), ("bz", 0.0), ("pot_z", 0.0), ("pot_a", 0.0)):
+        setattr(p, k, float(hprob.get(k, d)))
+    p.pot_kind = int(hprob.get("pot_kind", 0))
+    p.chirality = int(hprob.get("chirality", 0))
+    return p
 
 
 class DlAdaptStat(ctypes.Structure):
@@ -123,6 +144,19 @@ def load_library():
     lib.dirac_lanczos_step_noalloc.argtypes = [P, vp, ctypes.c_double, ctypes.c_double, ctypes.c_int32, vp,
                                                ctypes.POINTER(DlStepStat)]
     lib.dirac_lanczos_step_noalloc.restype = ctypes.c_int
+    HP = ctypes.POINTER(DlHermiteParams)
+    lib.dirac_lanczos_hermite_nodes.argtypes = [ctypes.c_int32, ctypes.c_double, D, D]
+    lib.dirac_lanczos_hermite_nodes.restype = ctypes.c_int
+    lib.dirac_lanczos_hermite_workspace_bytes.argtypes = [HP, ctypes.c_int32, ctypes.c_int32]
+    lib.dirac_lanczos_hermite_workspace_bytes.restype = ctypes.c_size_t
+    lib.dirac_lanczos_hermite_apply.argtypes = [HP, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.dirac_lanczos_hermite_apply.restype = ctypes.c_int
+    lib.dirac_lanczos_hermite_eigen.argtypes = [HP, ctypes.c_int32, ctypes.POINTER(vp), ctypes.c_int32, D, D,
+                                                ctypes.c_double, ctypes.c_int32, vp, ctypes.c_size_t, vp, D, D,
+                                                ctypes.POINTER(ctypes.c_int32)]
+    lib.dirac_lanczos_hermite_eigen.restype = ctypes.c_int
+    lib.dirac_lanczos_hermite_last_error.argtypes = []
+    lib.dirac_lanczos_hermite_last_error.restype = ctypes.c_char_p
     lib.dirac_lanczos_eigen.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                         ctypes.c_double, ctypes.c_double, ctypes.c_int32, D, D,
                                         ctypes.POINTER(ctypes.c_int32)]
@@ -562,3 +596,67 @@ class BatchPropagator:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# Hermite pseudospectral problems (dl_hermite_params; spinors (2, n, n) of the
+# collocation variables)
+# ---------------------------------------------------------------------------
+def _herm_check(st):
+    if st != DL_OK:
+        msg = load_library().dirac_lanczos_hermite_last_error()
+        raise DlError(st, msg.decode() if msg else "")
+
+
+def hermite_nodes(n: int, scale: float):
+    """Collocation points and weights of the library (numpy arrays)."""
+    lib = load_library()
+    x = np.zeros(n)
+    w = np.zeros(n)
+    _herm_check(lib.dirac_lanczos_hermite_nodes(int(n), float(scale), x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return x, w
+
+
+def hermite_apply(hprob: dict, x, stream=None):
+    """y = H x for a Hermite problem (x: complex128 CUDA tensor (2, n, n))."""
+    import torch
+    lib = load_library()
+    p = make_hermite_params(hprob)
+    nb = int(lib.dirac_lanczos_hermite_workspace_bytes(ctypes.byref(p), 1, 1))
+    if nb == 0:
+        raise DlError(DL_ERR_INVALID, "invalid Hermite parameters")
+    ws = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
+    ptr = (ws.data_ptr() + 255) & ~255
+    y = torch.empty_like(x)
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _herm_check(lib.dirac_lanczos_hermite_apply(ctypes.byref(p), ctypes.c_void_p(x.data_ptr()),
+                                                ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(ptr), nb,
+                                                ctypes.c_void_p(st.cuda_stream)))
+    return y
+
+
+def hermite_eigen(hprobs, psi0s, k_max: int, e_lo, e_hi, tol: float, n_wanted: int = 16, stream=None):
+    """Eigenvalue mode for a batch of Hermite problems (one start vector and
+    window per problem).  Returns a list of (values, bounds) numpy pairs."""
+    import torch
+    lib = load_library()
+    n = len(hprobs)
+    arr = (DlHermiteParams * n)(*[make_hermite_params(h) for h in hprobs])
+    nb = int(lib.dirac_lanczos_hermite_workspace_bytes(arr, n, int(k_max)))
+    if nb == 0:
+        raise DlError(DL_ERR_INVALID, "invalid Hermite parameters")
+    ws = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
+    ptr = (ws.data_ptr() + 255) & ~255
+    ptrs = (ctypes.c_void_p * n)(*[ctypes.c_void_p(p.data_ptr()) for p in psi0s])
+    lo = (ctypes.c_double * n)(*[float(v) for v in e_lo])
+    hi = (ctypes.c_double * n)(*[float(v) for v in e_hi])
+    ev = (ctypes.c_double * (n * n_wanted))()
+    bd = (ctypes.c_double * (n * n_wanted))()
+    nf = (ctypes.c_int32 * n)()
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _herm_check(lib.dirac_lanczos_hermite_eigen(arr, n, ptrs, int(k_max), lo, hi, float(tol), int(n_wanted),
+                                                ctypes.c_void_p(ptr), nb, ctypes.c_void_p(st.cuda_stream), ev, bd,
+                                                nf))
+    return [(np.array(ev[i * n_wanted:i * n_wanted + nf[i]]), np.array(bd[i * n_wanted:i * n_wanted + nf[i]]))
+            for i in range(n)]

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libdirac_lanczos.so")
 SOURCES = ["kernels.hip", "batch_kernels.hip", "adjoint_kernels.hip", "host.cpp", "batch.cpp", "adjoint.cpp", "adaptive.cpp",
-           "noalloc.hip",
+           "noalloc.hip", "hermite.cpp", "hermite_kernels.hip",
            "eigen_kernels.hip", "eigen.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

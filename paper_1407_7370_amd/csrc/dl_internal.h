@@ -268,6 +268,28 @@ int combine_grid(size_t sites, bool mixed, int cus, bool wide);
 int sweep_waves_per_cu(int which, bool mixed, bool py, int terms);
 int sweep_terms(const Op &op);
 
+// Hermite pseudospectral problems (hermite_kernels.hip): n x n collocation
+// points, n a multiple of 16 up to 64.
+struct HermOp {
+    int n;
+    int pot_kind;        // 0 none, 1 -vz / sqrt(r^2 + va2)
+    double c, chi;       // speed of light, alpha2 = chi sigma2
+    double mc2;          // m c^2
+    double bq;           // c q B / 2 (symmetric gauge)
+    double vz, va2;
+    const double *dmat;  // D~ / scale, n x n row-major (device)
+    const double *x;     // scaled nodes (device)
+};
+struct HermRun {
+    const double2 *b;    // start vector (device, layout (2, n, n))
+    double2 *q[2];       // two Lanczos vectors (device)
+    double *alpha, *beta;
+    int keff;            // iterations done; 0 for b = 0, -1 for a non-finite reduction
+    int pad;
+};
+void launch_herm_apply(const HermOp *ops, const double2 *const *x, double2 *const *y, int n, hipStream_t st);
+void launch_herm_lanczos(const HermOp *ops, HermRun *runs, int n, int k_max, hipStream_t st);
+
 // Eigen mode with full reorthogonalisation (eigen_kernels.hip).  Stored
 // complex128 vectors q_1..q_K at q + (j-1) * vstride; the projection partial
 // table holds 2 * proj_tiles(n) doubles per vector.

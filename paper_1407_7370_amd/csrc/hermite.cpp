@@ -1,0 +1,300 @@
+// Host runtime of the Hermite pseudospectral discretisation (Sec. 5): the
+// collocation points and weights, the differentiation matrix, the device
+// tables of a batch of problems, and the eigenvalue mode (Ritz values of the
+// tridiagonal T from the device's Lanczos recurrence, Sec. 2 eq. error_est).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "context.h"
+
+using namespace dlh;
+
+namespace {
+
+thread_local std::string g_herm_error;
+
+dl_status herm_fail(dl_status s, const std::string &msg)
+{
+    g_herm_error = msg;
+    return s;
+}
+
+const char *herm_validate(const dl_hermite_params &p)
+{
+    if (p.n < 16 || p.n > 64 || p.n % 16 != 0) return "n must be 16, 32, 48 or 64";
+    if (!(p.scale > 0.0) || !std::isfinite(p.scale)) return "scale must be positive";
+    if (!(p.c > 0.0) || !std::isfinite(p.c)) return "c must be positive";
+    if (!(p.mass >= 0.0) || !std::isfinite(p.mass)) return "mass must be >= 0";
+    if (!std::isfinite(p.charge) || !std::isfinite(p.bz)) return "charge and bz must be finite";
+    if (p.chirality < -1 || p.chirality > 1) return "chirality must be -1, 0 or +1";
+    if (p.pot_kind < 0 || p.pot_kind > 2) return "unknown pot_kind";
+    if (p.pot_kind == 1 && !(p.pot_a != 0.0 && std::isfinite(p.pot_a) && std::isfinite(p.pot_z)))
+        return "soft-core potential needs pot_a != 0";
+    if (p.pot_kind == 2 && !(p.pot_z != 0.0 && std::isfinite(p.pot_z))) return "paper soft-core potential needs pot_z != 0";
+    return nullptr;
+}
+
+// Orthonormal Hermite function values h_{n-1}(x), h_n(x) (recurrence).
+void hermite_pair(int n, double x, double &hm1, double &hn)
+{
+    double a = std::pow(3.14159265358979323846, -0.25) * std::exp(-0.5 * x * x), b = 0.0;
+    // a = h_k, b = h_{k-1}
+    for (int k = 0; k < n; ++k) {
+        const double next = std::sqrt(2.0 / (k + 1)) * x * a - std::sqrt((double)k / (k + 1)) * b;
+        b = a;
+        a = next;
+    }
+    hm1 = b;
+    hn = a;
+}
+
+// Roots xi (ascending) of the n-th Hermite polynomial and the weights w_i of
+// the collocation variables (Christoffel numbers of the Hermite functions):
+// Golub-Welsch (eigenvalues of the Jacobi matrix with off-diagonal sqrt(k/2))
+// polished by Newton steps on h_n, and w_i = 1 / (n h_{n-1}(xi_i)^2)
+// (Christoffel-Darboux at the zeros of h_n).
+void nodes(int n, std::vector<double> &xi, std::vector<double> &w)
+{
+    std::vector<double> d(n, 0.0), e(n, 0.0), lam, v;
+    for (int k = 1; k < n; ++k) e[k - 1] = std::sqrt(0.5 * k);
+    tridiag_full(d, e, lam, v);
+    xi = lam;
+    std::sort(xi.begin(), xi.end());
+    w.assign(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        double x = xi[i], hm1 = 0.0, hn = 0.0;
+        for (int it = 0; it < 8; ++it) {
+            hermite_pair(n, x, hm1, hn);
+            const double dx = hn / (std::sqrt(2.0 * n) * hm1 - x * hn);  // h_n' = sqrt(2n) h_{n-1} - x h_n
+            x -= dx;
+            if (std::fabs(dx) <= 1e-16 * (1.0 + std::fabs(x))) break;
+        }
+        hermite_pair(n, x, hm1, hn);
+        xi[i] = x;
+        w[i] = 1.0 / (n * hm1 * hm1);
+    }
+}
+
+// The device image of one problem: D~ / scale with D~_ij = (-1)^(i+j) /
+// (xi_i - xi_j) (i != j; the derivative of the interpolant in the span of the
+// first n Hermite functions, in the variables sqrt(w) f), and the nodes times
+// scale.
+void tables(const dl_hermite_params &p, std::vector<double> &dm, std::vector<double> &x)
+{
+    std::vector<double> xi, w;
+    nodes(p.n, xi, w);
+    dm.assign((size_t)p.n * p.n, 0.0);
+    for (int i = 0; i < p.n; ++i)
+        for (int j = 0; j < p.n; ++j)
+            if (i != j) dm[(size_t)i * p.n + j] = (((i + j) & 1) ? -1.0 : 1.0) / ((xi[i] - xi[j]) * p.scale);
+    x.resize(p.n);
+    for (int i = 0; i < p.n; ++i) x[i] = xi[i] * p.scale;
+}
+
+dl::HermOp make_hop(const dl_hermite_params &p, const double *dmat, const double *x)
+{
+    dl::HermOp o{};
+    o.n = p.n;
+    o.c = p.c;
+    o.chi = p.chirality < 0 ? -1.0 : 1.0;
+    o.mc2 = p.mass * p.c * p.c;
+    o.bq = p.c * p.charge * p.bz * 0.5;
+    o.pot_kind = p.pot_kind ? 1 : 0;
+    if (p.pot_kind == 1) {
+        o.vz = p.pot_z;
+        o.va2 = p.pot_a * p.pot_a;
+    } else if (p.pot_kind == 2) {
+        o.vz = 1.5 * p.pot_z;
+        o.va2 = 3.0 / (p.pot_z * p.pot_z);
+    }
+    o.dmat = dmat;
+    o.x = x;
+    return o;
+}
+
+struct HermLayout {
+    size_t ops = 0, runs = 0, ptrs = 0, total = 0;
+    std::vector<size_t> dmat, x, q0, q1, ab;
+};
+
+HermLayout herm_plan(const dl_hermite_params *p, int np, int k_max)
+{
+    HermLayout L;
+    size_t off = 0;
+    L.ops = off;
+    off = align256(off + sizeof(dl::HermOp) * np);
+    L.runs = off;
+    off = align256(off + sizeof(dl::HermRun) * np);
+    L.ptrs = off;
+    off = align256(off + sizeof(void *) * 2 * np);
+    for (int i = 0; i < np; ++i) {
+        const size_t n2 = (size_t)p[i].n * p[i].n;
+        L.dmat.push_back(off);
+        off = align256(off + sizeof(double) * n2);
+        L.x.push_back(off);
+        off = align256(off + sizeof(double) * p[i].n);
+        L.q0.push_back(off);
+        off = align256(off + 16 * 2 * n2);
+        L.q1.push_back(off);
+        off = align256(off + 16 * 2 * n2);
+        L.ab.push_back(off);
+        off = align256(off + sizeof(double) * 2 * (size_t)std::max(k_max, 1));
+    }
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+dl_status dirac_lanczos_hermite_nodes(int32_t n, double scale, double *x, double *w)
+{
+    if (n < 1 || n > 4096 || !(scale > 0.0) || !std::isfinite(scale) || !x || !w)
+        return herm_fail(DL_ERR_INVALID, "need 1 <= n <= 4096, scale > 0 and output arrays");
+    std::vector<double> xi, wi;
+    nodes(n, xi, wi);
+    for (int i = 0; i < n; ++i) {
+        x[i] = xi[i] * scale;
+        w[i] = wi[i] * scale;
+    }
+    return DL_OK;
+}
+
+size_t dirac_lanczos_hermite_workspace_bytes(const dl_hermite_params *params, int32_t n_problems, int32_t k_max)
+{
+    if (!params || n_problems < 1 || k_max < 1 || k_max > 1000000) return 0;
+    for (int i = 0; i < n_problems; ++i)
+        if (herm_validate(params[i])) return 0;
+    return herm_plan(params, n_problems, k_max).total;
+}
+
+dl_status dirac_lanczos_hermite_apply(const dl_hermite_params *params, const void *x, void *y, void *workspace,
+                                      size_t ws_bytes, void *hip_stream)
+{
+    if (!params) return herm_fail(DL_ERR_INVALID, "params is NULL");
+    if (const char *m = herm_validate(*params)) return herm_fail(DL_ERR_INVALID, m);
+    if (!x || !y || x == y) return herm_fail(DL_ERR_INVALID, "apply needs distinct non-NULL x and y");
+    const HermLayout L = herm_plan(params, 1, 1);
+    if (!workspace || ((uintptr_t)workspace & 255u) != 0 || ws_bytes < L.total)
+        return herm_fail(DL_ERR_WORKSPACE, "workspace must be 256-byte aligned with " + std::to_string(L.total) +
+                                               " bytes");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    char *ws = static_cast<char *>(workspace);
+    std::vector<double> dm, xs;
+    tables(*params, dm, xs);
+    const dl::HermOp op = make_hop(*params, reinterpret_cast<double *>(ws + L.dmat[0]),
+                                   reinterpret_cast<double *>(ws + L.x[0]));
+    const void *ptrs[2] = {x, y};
+    if (hipMemcpyAsync(ws + L.dmat[0], dm.data(), sizeof(double) * dm.size(), hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(ws + L.x[0], xs.data(), sizeof(double) * xs.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(ws + L.ops, &op, sizeof(op), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(ws + L.ptrs, ptrs, sizeof(ptrs), hipMemcpyHostToDevice, st) != hipSuccess)
+        return herm_fail(DL_ERR_DEVICE, "upload of the problem tables failed");
+    const void *const *dp = reinterpret_cast<const void *const *>(ws + L.ptrs);
+    dl::launch_herm_apply(reinterpret_cast<const dl::HermOp *>(ws + L.ops),
+                          reinterpret_cast<const double2 *const *>(dp),
+                          reinterpret_cast<double2 *const *>(const_cast<void **>(dp) + 1), 1, st);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+        return herm_fail(DL_ERR_DEVICE, "kernel launch failed");
+    return DL_OK;
+}
+
+dl_status dirac_lanczos_hermite_eigen(const dl_hermite_params *params, int32_t n_problems, const void *const *psi0,
+                                      int32_t k_max, const double *e_lo, const double *e_hi, double tol,
+                                      int32_t n_wanted, void *workspace, size_t ws_bytes, void *hip_stream,
+                                      double *evals, double *bounds, int32_t *n_found)
+{
+    if (!params || n_problems < 1 || !psi0 || !e_lo || !e_hi || !evals || !bounds || !n_found || n_wanted < 1 ||
+        k_max < 1 || k_max > 1000000 || !(tol >= 0.0))
+        return herm_fail(DL_ERR_INVALID, "invalid Hermite eigen arguments");
+    for (int i = 0; i < n_problems; ++i) {
+        if (const char *m = herm_validate(params[i])) return herm_fail(DL_ERR_INVALID, m);
+        if (!psi0[i] || !(e_hi[i] >= e_lo[i])) return herm_fail(DL_ERR_INVALID, "invalid start vector or window");
+        n_found[i] = 0;
+    }
+    const HermLayout L = herm_plan(params, n_problems, k_max);
+    if (!workspace || ((uintptr_t)workspace & 255u) != 0 || ws_bytes < L.total)
+        return herm_fail(DL_ERR_WORKSPACE, "workspace must be 256-byte aligned with " + std::to_string(L.total) +
+                                               " bytes");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    char *ws = static_cast<char *>(workspace);
+    std::vector<dl::HermOp> ops(n_problems);
+    std::vector<dl::HermRun> runs(n_problems);
+    std::vector<std::vector<double>> dms(n_problems), xss(n_problems);
+    for (int i = 0; i < n_problems; ++i) {
+        tables(params[i], dms[i], xss[i]);
+        ops[i] = make_hop(params[i], reinterpret_cast<double *>(ws + L.dmat[i]), reinterpret_cast<double *>(ws + L.x[i]));
+        dl::HermRun r{};
+        r.b = static_cast<const double2 *>(psi0[i]);
+        r.q[0] = reinterpret_cast<double2 *>(ws + L.q0[i]);
+        r.q[1] = reinterpret_cast<double2 *>(ws + L.q1[i]);
+        r.alpha = reinterpret_cast<double *>(ws + L.ab[i]);
+        r.beta = r.alpha + k_max;
+        runs[i] = r;
+        if (hipMemcpyAsync(ws + L.dmat[i], dms[i].data(), sizeof(double) * dms[i].size(), hipMemcpyHostToDevice, st) !=
+                hipSuccess ||
+            hipMemcpyAsync(ws + L.x[i], xss[i].data(), sizeof(double) * xss[i].size(), hipMemcpyHostToDevice, st) !=
+                hipSuccess)
+            return herm_fail(DL_ERR_DEVICE, "upload of the problem tables failed");
+    }
+    if (hipMemcpyAsync(ws + L.ops, ops.data(), sizeof(dl::HermOp) * n_problems, hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(ws + L.runs, runs.data(), sizeof(dl::HermRun) * n_problems, hipMemcpyHostToDevice, st) !=
+            hipSuccess)
+        return herm_fail(DL_ERR_DEVICE, "upload of the problem tables failed");
+    dl::launch_herm_lanczos(reinterpret_cast<const dl::HermOp *>(ws + L.ops), reinterpret_cast<dl::HermRun *>(ws + L.runs),
+                            n_problems, k_max, st);
+    if (hipGetLastError() != hipSuccess) return herm_fail(DL_ERR_DEVICE, "kernel launch failed");
+    std::vector<double> ab((size_t)2 * k_max * n_problems);
+    for (int i = 0; i < n_problems; ++i)
+        if (hipMemcpyAsync(ab.data() + (size_t)2 * k_max * i, ws + L.ab[i], sizeof(double) * 2 * k_max,
+                           hipMemcpyDeviceToHost, st) != hipSuccess)
+            return herm_fail(DL_ERR_DEVICE, "download of the recurrences failed");
+    if (hipMemcpyAsync(runs.data(), ws + L.runs, sizeof(dl::HermRun) * n_problems, hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return herm_fail(DL_ERR_DEVICE, "synchronisation failed");
+    bool nonfinite = false;
+    std::vector<double> ev((size_t)k_max + 1), bd(ev.size());
+    for (int i = 0; i < n_problems; ++i) {
+        const int k = runs[i].keff;
+        if (k < 0) {
+            nonfinite = true;
+            continue;
+        }
+        if (k == 0) continue;
+        const double *al = ab.data() + (size_t)2 * k_max * i, *be = al + k_max;
+        // converged clusters accumulated over the leading blocks k = 64, 128, ... and k
+        std::vector<std::pair<double, double>> found;
+        for (int j = kEigenCheckEvery; j <= k; j += kEigenCheckEvery) {
+            const int nf = ritz_chain(al, be, j, e_lo[i], e_hi[i], tol, (int)ev.size(), ev.data(), bd.data(), nullptr,
+                                      nullptr);
+            merge_converged(found, ev.data(), bd.data(), nf, tol);
+        }
+        if (k % kEigenCheckEvery != 0) {
+            const int nf = ritz_chain(al, be, k, e_lo[i], e_hi[i], tol, (int)ev.size(), ev.data(), bd.data(), nullptr,
+                                      nullptr);
+            merge_converged(found, ev.data(), bd.data(), nf, tol);
+        }
+        const int nf = std::min((int)found.size(), n_wanted);
+        for (int r = 0; r < nf; ++r) {
+            evals[(size_t)i * n_wanted + r] = found[r].first;
+            bounds[(size_t)i * n_wanted + r] = found[r].second;
+        }
+        n_found[i] = nf;
+    }
+    if (nonfinite) return herm_fail(DL_ERR_NONFINITE, "non-finite Lanczos reduction in a Hermite problem");
+    return DL_OK;
+}
+
+const char *dirac_lanczos_hermite_last_error(void) { return g_herm_error.c_str(); }
+
+}  // extern "C"

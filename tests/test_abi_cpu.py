@@ -6,6 +6,8 @@ import os
 import re
 import subprocess
 
+import numpy as np
+
 import pytest
 
 from paper_1407_7370_amd import binding, packets
@@ -146,3 +148,25 @@ def test_missing_library_raises(monkeypatch, tmp_path):
     monkeypatch.setattr(binding, "LIB_PATH", str(tmp_path / "libdirac_lanczos.so"))
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         binding.load_library()
+
+
+def test_hermite_nodes_host():
+    """The library's collocation points and weights (a host computation:
+    Golub-Welsch with Newton polish, Christoffel-Darboux weights) against
+    numpy's Gauss-Hermite rule."""
+    from numpy.polynomial.hermite import hermgauss
+    for n, s in ((16, 0.5), (64, 0.036)):
+        x, w = binding.hermite_nodes(n, s)
+        xi, wg = hermgauss(n)
+        assert np.max(np.abs(x / s - xi)) <= 1e-13 * np.abs(xi).max()
+        assert np.max(np.abs(w / (s * wg * np.exp(xi * xi)) - 1.0)) <= 1e-11
+
+
+def test_hermite_rejections_host():
+    """Invalid Hermite problems are rejected before any device work."""
+    p = binding.make_hermite_params(dict(n=20, scale=1.0))
+    assert binding.load_library().dirac_lanczos_hermite_workspace_bytes(ctypes.byref(p), 1, 10) == 0
+    p = binding.make_hermite_params(dict(n=32, scale=-1.0))
+    assert binding.load_library().dirac_lanczos_hermite_workspace_bytes(ctypes.byref(p), 1, 10) == 0
+    p = binding.make_hermite_params(dict(n=32, scale=0.1))
+    assert binding.load_library().dirac_lanczos_hermite_workspace_bytes(ctypes.byref(p), 1, 10) > 0

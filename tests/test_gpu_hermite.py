@@ -1,0 +1,131 @@
+"""Hermite pseudospectral discretisation (Sec. 5) on the GPU through the C
+ABI: H applied by the matrix-core kernel against the oracle's plain-loop H,
+the batched eigenvalue mode against the oracle's three-vector Lanczos, and the
+paper's printed soft-core energies (tab:soft_core_groundstates,
+tab:soft_core_eigenstates_Z_50)."""
+import os
+
+import numpy as np
+import pytest
+
+import harness as hz
+from paper_1407_7370_amd import packets
+
+pytestmark = pytest.mark.gpu
+
+C = 137.036
+MC2 = C * C
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def say(msg):
+    print(f"[gpu case] {msg}", flush=True)
+
+
+def hprob(n, scale, **kw):
+    p = dict(n=n, scale=scale, mass=1.0, c=C, charge=-1.0, bz=0.0, pot_kind=0, pot_z=0.0, pot_a=0.0, chirality=0)
+    p.update(kw)
+    return p
+
+
+APPLY = {
+    "n16_free": hprob(16, 0.3),
+    "n32_softcore_b": hprob(32, 0.2, bz=0.8, pot_kind=1, pot_z=1.0, pot_a=0.7),
+    "n48_paper_softcore_chi_minus": hprob(48, 0.05, pot_kind=2, pot_z=20.0, chirality=-1),
+    "n64_paper_softcore_b": hprob(64, 0.036, bz=-3.0, pot_kind=2, pot_z=50.0),
+}
+
+
+@pytest.mark.parametrize("case", sorted(APPLY))
+def test_hermite_apply_vs_oracle(torch_cuda, orc, case):
+    from paper_1407_7370_amd import binding
+    hp = APPLY[case]
+    n = hp["n"]
+    say(f"hermite apply {case}")
+    rng = np.random.default_rng(n)
+    x = rng.standard_normal((2, n, n)) + 1j * rng.standard_normal((2, n, n))
+    y = binding.hermite_apply(hp, torch_cuda.from_numpy(x).cuda()).cpu().numpy()
+    ref = orc.apply_h_hermite(hp, x)
+    err = np.max(np.abs(y - ref)) / np.max(np.abs(ref))
+    print(f"{case}: max |diff| / max |Hx| = {err:.2e}", flush=True)
+    assert err <= 1e-13
+
+
+def _start(hp, Z):
+    return packets.hermite_packet(hp, 1.0 / Z, (0.4 / Z, 0.25 / Z))
+
+
+def test_hermite_eigen_z50_vs_oracle_and_table(torch_cuda, orc):
+    """Z = 50, 64 x 64 Hermite functions, 1000 iterations (the paper's
+    setting): the converged values of the GPU and of the oracle for the same
+    start vector agree, and states 1-3 match the printed digits."""
+    from paper_1407_7370_amd import binding
+    torch = torch_cuda
+    Z = 50.0
+    hp = packets.softcore_hermite(Z)
+    psi0 = _start(hp, Z)
+    lo, hi, tol = MC2 - 0.6 * Z * Z, MC2 - 0.14 * Z * Z, 1e-5
+    say("hermite eigen Z=50 n=64 K=1000")
+    (ev, bd), = binding.hermite_eigen([hp], [torch.from_numpy(psi0).cuda()], 1000, [lo], [hi], tol)
+    rev, rbd, _ = orc.eigen_hermite(hp, psi0, 1000, lo, hi, tol)
+    print("gpu:", np.round(ev - MC2, 6).tolist(), "oracle:", np.round(rev - MC2, 6).tolist(), flush=True)
+    assert len(ev) >= 6
+    assert hz.match_converged(ev, bd, rev, rbd, tol) == len(ev) == len(rev)
+    rows = [ln.split() for ln in open(os.path.join(GOLDEN, "softcore_z50_states.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    for k in range(3):
+        printed = rows[k][1]
+        assert abs(ev[k] - MC2 - float(printed)) <= 1.5e-5, (k + 1, ev[k] - MC2, printed)
+
+
+def test_hermite_ground_state_table_batch(torch_cuda, orc):
+    """The six problems of tab:soft_core_groundstates in one launch (one
+    workgroup each, 1000 iterations): every ground state to within 1.5 units
+    of the last printed digit, and equal to the oracle's to 1e-10 relative.
+    Chirality -1 (the other two-component block of the four-component
+    equation) gives the same energies for the radial potential."""
+    from paper_1407_7370_amd import binding
+    torch = torch_cuda
+    rows = {}
+    for line in open(os.path.join(GOLDEN, "softcore_ground_states.txt")):
+        if line.strip() and not line.startswith("#"):
+            z, lanczos, _, _ = line.split()
+            rows[float(z)] = lanczos
+    zs = sorted(rows)
+    probs = [packets.softcore_hermite(Z) for Z in zs] + [packets.softcore_hermite(Z, chirality=-1) for Z in zs]
+    starts = [_start(hp, hp["pot_z"]) for hp in probs]
+    lo = [MC2 - 0.6 * hp["pot_z"] ** 2 for hp in probs]
+    hi = [MC2 - 0.4 * hp["pot_z"] ** 2 for hp in probs]
+    say(f"hermite ground-state table: {len(probs)} problems n=64 K=1000 in one launch")
+    res = binding.hermite_eigen(probs, [torch.from_numpy(s).cuda() for s in starts], 1000, lo, hi, 1e-9 * 2500)
+    for i, (Z, hp) in enumerate(zip(zs, probs)):
+        ev, bd = res[i]
+        assert len(ev) >= 1, Z
+        e = ev[0] - MC2
+        printed = rows[Z]
+        ulp = 10.0 ** -len(printed.split(".")[1])
+        rev, _, _ = orc.eigen_hermite(hp, starts[i], 1000, lo[i], hi[i], 1e-9 * 2500)
+        print(f"Z={Z}: gpu {e:.10f} oracle {rev[0] - MC2:.10f} paper {printed}", flush=True)
+        assert abs(e - float(printed)) <= 1.5 * ulp, (Z, e, printed)
+        assert abs(ev[0] - rev[0]) <= 1e-10 * abs(e)
+        em = res[len(zs) + i][0]
+        assert len(em) >= 1 and abs(em[0] - ev[0]) <= 1e-10 * abs(e), (Z, em, ev)
+
+
+def test_hermite_rejections(torch_cuda):
+    from paper_1407_7370_amd import binding
+    say("hermite rejections")
+    x = torch_cuda.zeros((2, 16, 16), dtype=torch_cuda.complex128, device="cuda")
+    with pytest.raises(binding.DlError) as e:
+        binding.hermite_apply(hprob(20, 0.3), torch_cuda.zeros((2, 20, 20), dtype=torch_cuda.complex128,
+                                                                device="cuda"))
+    assert e.value.status == binding.DL_ERR_INVALID
+    (ev, bd), = binding.hermite_eigen([hprob(16, 0.3)], [x], 10, [0.0], [1e9], 1e-6)
+    assert len(ev) == 0  # a zero start vector reports nothing
