@@ -111,16 +111,17 @@ typedef struct {
  * of the part of the step's error that comes from storing the Krylov vectors
  * u_2..u_k in complex64.  The stored vectors obey the Lanczos relation with a
  * perturbation F whose column j is the rounding of u_{j+1} (norm at most
- * (2^-24 beta_j + 2^-126 sqrt(4 nx ny)) / (1 - 2^-24)); for Hermitian A the
- * difference between ||psi|| Q exp(-iT) e_1 and exp(-iA) psi is then at most
- * the Krylov term plus int_0^1 ||F s(t)|| dt, s(t) = ||psi|| exp(-itT) e_1,
- * and |s_j(t)| <= ||psi|| min(1, R^(j-1) e^R / (j-1)!) with R the Gershgorin
- * half-width of T shifted to its centre.  round_bound = ||psi|| sum_j
- * min(1, R^(j-1) e^R / (j-1)!) (2^-24 beta_j + 2^-126 sqrt(4 nx ny)) /
- * (1 - 2^-24), j = 1..k-1.  It holds without orthogonality of the basis; the
- * FP64 arithmetic of both precisions is not included.  Summed over the steps
- * it bounds the distance between a mixed-precision and an FP64 run beyond
- * their Krylov and FP64 rounding terms. */
+ * e_j = (2^-24 beta_j + 2^-126 sqrt(4 nx ny)) / (1 - 2^-24)); for Hermitian A
+ * the difference between ||psi|| Q exp(-iT) e_1 and exp(-iA) psi is then at
+ * most the Krylov term plus int_0^1 ||F s(t)|| dt, s(t) = ||psi|| exp(-itT) e_1,
+ * so round_bound = sum_j e_j I_j, j = 1..k-1, with I_j >= int_0^1 |s_j(t)| dt:
+ * with R the Gershgorin half-width of T about its centre, I_j = 1.01
+ * (int_0^1 |s_j|^2 dt)^(1/2) by 48-point Gauss-Legendre quadrature for
+ * R <= 40 (Cauchy-Schwarz), ||psi|| [exp(|T - centre|) e_1]_j for 40 < R <= 70,
+ * else ||psi||, each capped at ||psi||.  It holds without orthogonality of
+ * the basis; the FP64 arithmetic of both precisions is not included.  Summed
+ * over the steps it bounds the distance between a mixed-precision and an FP64
+ * run beyond their Krylov and FP64 rounding terms. */
 typedef struct {
     int32_t k_eff;       /* Krylov dimension used (< m after breakdown, 0 for psi = 0) */
     double err_est;      /* beta_k ||psi|| |e_k^T exp(-iT) e_1| */
@@ -296,6 +297,26 @@ dl_status dirac_lanczos_step_adaptive(dl_context *ctx, void *psi, double t0, dou
 dl_status dirac_lanczos_eigen(dl_context *ctx, const void *psi0, int32_t k_max, int32_t reorth,
                               double e_lo, double e_hi, double tol, int32_t n_wanted,
                               double *evals, double *bounds, int32_t *n_found);
+
+/*
+ * The host half of the eigen modes, for a recurrence the caller already has
+ * (Sec. 2 eq. error_est): the converged Ritz clusters of the tridiagonal T_k
+ * with diagonal alpha[0..k) and off-diagonal beta[0..k-1), bound factor
+ * beta[k-1] = beta_k (the norm of the next residual), all HOST arrays.  With
+ * check_every > 0 the clusters of the leading blocks T_j, j = check_every,
+ * 2 check_every, ... and k, are accumulated as in dirac_lanczos_eigen with
+ * reorth = 0; with check_every == 0 only T_k is taken.  Eigenvalues of a block
+ * in (e_lo, e_hi] come from bisection on Sturm counts to full precision, the
+ * last eigenvector components from inverse iteration, vectors of eigenvalues
+ * closer than max(tol, 1e-8 ||T||) kept orthogonal.  Up to n_wanted values
+ * (the lowest) go to evals/bounds, ascending; *n_found receives the count.
+ * Blocks are solved on up to 16 host threads.  DL_ERR_INVALID for k < 1,
+ * check_every < 0, n_wanted < 1, e_hi < e_lo, tol < 0 or null pointers.
+ * Needs no device.
+ */
+dl_status dirac_lanczos_ritz(const double *alpha, const double *beta, int32_t k, double e_lo, double e_hi,
+                             double tol, int32_t check_every, int32_t n_wanted, double *evals, double *bounds,
+                             int32_t *n_found);
 
 /*
  * Ritz vectors (Sec. 2 eq. eigenvec_approx): dirac_lanczos_eigen with

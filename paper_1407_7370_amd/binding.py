@@ -31,7 +31,7 @@ EXPORTS = ("dirac_lanczos_workspace_bytes", "dirac_lanczos_init", "dirac_lanczos
            "dirac_lanczos_step_lowmem", "dirac_lanczos_eigen_vectors", "dirac_lanczos_step_ktol",
            "dirac_lanczos_wait", "dirac_lanczos_step_noalloc", "dirac_lanczos_hermite_nodes",
            "dirac_lanczos_hermite_workspace_bytes", "dirac_lanczos_hermite_apply", "dirac_lanczos_hermite_eigen",
-           "dirac_lanczos_hermite_last_error")
+           "dirac_lanczos_hermite_last_error", "dirac_lanczos_ritz")
 DL_LOSS_X, DL_LOSS_Y, DL_LOSS_PX, DL_LOSS_PY = 1, 2, 4, 8
 
 
@@ -145,6 +145,9 @@ def load_library():
                                                ctypes.POINTER(DlStepStat)]
     lib.dirac_lanczos_step_noalloc.restype = ctypes.c_int
     HP = ctypes.POINTER(DlHermiteParams)
+    lib.dirac_lanczos_ritz.argtypes = [D, D, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_int32, ctypes.c_int32, D, D, ctypes.POINTER(ctypes.c_int32)]
+    lib.dirac_lanczos_ritz.restype = ctypes.c_int
     lib.dirac_lanczos_hermite_nodes.argtypes = [ctypes.c_int32, ctypes.c_double, D, D]
     lib.dirac_lanczos_hermite_nodes.restype = ctypes.c_int
     lib.dirac_lanczos_hermite_workspace_bytes.argtypes = [HP, ctypes.c_int32, ctypes.c_int32]
@@ -606,6 +609,26 @@ def _herm_check(st):
     if st != DL_OK:
         msg = load_library().dirac_lanczos_hermite_last_error()
         raise DlError(st, msg.decode() if msg else "")
+
+
+def ritz(alpha, beta, e_lo: float, e_hi: float, tol: float, check_every: int = 64, n_wanted: int = 64):
+    """Converged Ritz clusters of the tridiagonal (alpha, beta) in [e_lo, e_hi]
+    (dirac_lanczos_ritz, host only): (values, bounds) numpy arrays."""
+    lib = load_library()
+    al = np.ascontiguousarray(alpha, dtype=np.float64)
+    be = np.ascontiguousarray(beta, dtype=np.float64)
+    if al.shape != be.shape or al.ndim != 1:
+        raise ValueError("alpha and beta must be 1-D arrays of one length")
+    ev = np.zeros(max(int(n_wanted), 1))
+    bd = np.zeros_like(ev)
+    nf = ctypes.c_int32(0)
+    D = ctypes.POINTER(ctypes.c_double)
+    st = lib.dirac_lanczos_ritz(al.ctypes.data_as(D), be.ctypes.data_as(D), int(len(al)), float(e_lo), float(e_hi),
+                                float(tol), int(check_every), int(n_wanted), ev.ctypes.data_as(D),
+                                bd.ctypes.data_as(D), ctypes.byref(nf))
+    if st != DL_OK:
+        raise DlError(st, "invalid arguments of dirac_lanczos_ritz")
+    return ev[:nf.value].copy(), bd[:nf.value].copy()
 
 
 def hermite_nodes(n: int, scale: float):

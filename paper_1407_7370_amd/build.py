@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libdirac_lanczos.so")
-SOURCES = ["kernels.hip", "batch_kernels.hip", "adjoint_kernels.hip", "host.cpp", "batch.cpp", "adjoint.cpp", "adaptive.cpp",
+SOURCES = ["kernels.hip", "batch_kernels.hip", "adjoint_kernels.hip", "host.cpp", "batch.cpp", "adjoint.cpp", "adaptive.cpp", "ritz.cpp",
            "noalloc.hip", "hermite.cpp", "hermite_kernels.hip",
            "eigen_kernels.hip", "eigen.cpp"]
 

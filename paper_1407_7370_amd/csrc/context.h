@@ -12,6 +12,7 @@
 
 #include "dirac_lanczos.h"
 #include "dl_internal.h"
+#include "ritz.h"
 
 namespace dlh {
 
@@ -72,38 +73,6 @@ void pulse_average(const dl_params &p, CoefView coef, double t0, double dt, doub
 // Step average of one Fourier basis function of the sin^2-enveloped pulse:
 // harmonic k, sine (cosine = false) or cosine (cosine = true).
 double basis_average(const dl_params &p, int k, bool cosine, double t0, double dt);
-void tridiag_last_row(std::vector<double> d, std::vector<double> e, std::vector<double> &lam,
-                      std::vector<double> &zlast);
-// Eigenvalues and all eigenvectors (column l of v, row-major k x k).
-void tridiag_full(std::vector<double> d, std::vector<double> e, std::vector<double> &lam,
-                  std::vector<double> &v);
-
-// Ritz values of T (eigenvalues lam, last eigenvector components zl) in
-// [e_lo, e_hi], grouped into clusters of neighbours closer than tol; a
-// cluster with bound |beta_k| ||zl over the cluster|| <= tol is reported as its
-// mean (at most n_wanted, ascending).  rep (optional) receives, per reported
-// cluster, the index of its member with the smallest |zl|.  Returns the count.
-int ritz_select(const std::vector<double> &lam, const std::vector<double> &zl, double beta_k, double e_lo,
-                double e_hi, double tol, int n_wanted, double *evals, double *bounds, std::vector<int> *rep);
-
-// Ritz values (and with V, all eigenvectors of T: column l of V, row-major
-// k x k) of the tridiagonal T_k with diagonal alpha1[0..k) and off-diagonal
-// beta1[0..k-1), bound factor beta1[k-1] = beta_k; selection as ritz_select.
-int ritz_chain(const double *alpha1, const double *beta1, int k, double e_lo, double e_hi, double tol, int n_wanted,
-               double *evals, double *bounds, std::vector<int> *rep, std::vector<double> *V);
-
-// The eigen mode computes the Ritz values every this many iterations and
-// stops once n_wanted clusters have converged.
-constexpr int kEigenCheckEvery = 64;
-
-// Add converged clusters (values ev, bounds bd) to `found` (ascending by
-// value): a value within tol of a found one is the same eigenvalue and keeps
-// the smaller bound.  Once orthogonality is lost a converged Ritz value gets
-// copies whose eigenvectors of T mix with its own, so its bound can grow
-// again while the value stays within its earlier bound of an eigenvalue of H
-// (Paige's analysis of the finite-precision recurrence).
-void merge_converged(std::vector<std::pair<double, double>> &found, const double *ev, const double *bd, int n,
-                     double tol);
 
 // Rounding of one stored Krylov vector of nx*ny sites (mixed precision:
 // complex64 storage, see dl::kStoreEps32), or zero in FP64.

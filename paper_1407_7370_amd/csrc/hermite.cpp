@@ -5,10 +5,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "context.h"
@@ -263,34 +265,33 @@ dl_status dirac_lanczos_hermite_eigen(const dl_hermite_params *params, int32_t n
         hipStreamSynchronize(st) != hipSuccess)
         return herm_fail(DL_ERR_DEVICE, "synchronisation failed");
     bool nonfinite = false;
-    std::vector<double> ev((size_t)k_max + 1), bd(ev.size());
     for (int i = 0; i < n_problems; ++i) {
-        const int k = runs[i].keff;
-        if (k < 0) {
-            nonfinite = true;
-            continue;
-        }
-        if (k == 0) continue;
-        const double *al = ab.data() + (size_t)2 * k_max * i, *be = al + k_max;
-        // converged clusters accumulated over the leading blocks k = 64, 128, ... and k
-        std::vector<std::pair<double, double>> found;
-        for (int j = kEigenCheckEvery; j <= k; j += kEigenCheckEvery) {
-            const int nf = ritz_chain(al, be, j, e_lo[i], e_hi[i], tol, (int)ev.size(), ev.data(), bd.data(), nullptr,
-                                      nullptr);
-            merge_converged(found, ev.data(), bd.data(), nf, tol);
-        }
-        if (k % kEigenCheckEvery != 0) {
-            const int nf = ritz_chain(al, be, k, e_lo[i], e_hi[i], tol, (int)ev.size(), ev.data(), bd.data(), nullptr,
-                                      nullptr);
-            merge_converged(found, ev.data(), bd.data(), nf, tol);
-        }
-        const int nf = std::min((int)found.size(), n_wanted);
-        for (int r = 0; r < nf; ++r) {
-            evals[(size_t)i * n_wanted + r] = found[r].first;
-            bounds[(size_t)i * n_wanted + r] = found[r].second;
-        }
-        n_found[i] = nf;
+        if (runs[i].keff < 0) nonfinite = true;
+        n_found[i] = 0;
     }
+    // converged clusters accumulated over the leading blocks k = 64, 128, ...
+    // and k; problems are independent and spread over host threads
+    std::atomic<int> next{0};
+    auto worker = [&] {
+        for (int i; (i = next.fetch_add(1)) < n_problems;) {
+            const int k = runs[i].keff;
+            if (k <= 0) continue;
+            const double *al = ab.data() + (size_t)2 * k_max * i, *be = al + k_max;
+            std::vector<std::pair<double, double>> found;
+            converged_union(al, be, k, e_lo[i], e_hi[i], tol, kEigenCheckEvery, 1, found);
+            const int nf = std::min((int)found.size(), n_wanted);
+            for (int r = 0; r < nf; ++r) {
+                evals[(size_t)i * n_wanted + r] = found[r].first;
+                bounds[(size_t)i * n_wanted + r] = found[r].second;
+            }
+            n_found[i] = nf;
+        }
+    };
+    const int nt = std::max(1, std::min<int>(n_problems, host_threads()));
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nt; ++t) pool.emplace_back(worker);
+    worker();
+    for (auto &th : pool) th.join();
     if (nonfinite) return herm_fail(DL_ERR_NONFINITE, "non-finite Lanczos reduction in a Hermite problem");
     return DL_OK;
 }

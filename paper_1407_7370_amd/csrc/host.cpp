@@ -176,175 +176,6 @@ void pulse_average(const dl_params &p, CoefView coef, double t0, double dt, doub
     a[1] /= std::fabs(dt);
 }
 
-// Symmetric tridiagonal eigenvalues and the last component of each
-// eigenvector: implicit QR steps with Wilkinson shift (Golub & Van Loan,
-// symmetric QR algorithm), accumulating only the last row of the eigenvector
-// matrix.
-void tridiag_last_row(std::vector<double> d, std::vector<double> e, std::vector<double> &lam,
-                      std::vector<double> &zlast)
-{
-    const int k = (int)d.size();
-    zlast.assign(k, 0.0);
-    zlast[k - 1] = 1.0;
-    e.resize(k, 0.0);
-    const double eps = 2.220446049250313e-16;
-    int h = k - 1, iter = 0;
-    while (h > 0) {
-        if (std::fabs(e[h - 1]) <= eps * (std::fabs(d[h - 1]) + std::fabs(d[h]))) {
-            e[h - 1] = 0.0;
-            --h;
-            iter = 0;
-            continue;
-        }
-        if (++iter > 200) break;
-        int l = h - 1;
-        while (l > 0 && std::fabs(e[l - 1]) > eps * (std::fabs(d[l - 1]) + std::fabs(d[l]))) --l;
-        const double delta = 0.5 * (d[h - 1] - d[h]);
-        const double b2 = e[h - 1] * e[h - 1];
-        const double mu = d[h] - b2 / (delta + std::copysign(std::sqrt(delta * delta + b2), delta));
-        double x = d[l] - mu, z = e[l];
-        for (int q = l; q < h; ++q) {
-            const double r = std::hypot(x, z);
-            double c = 1.0, s = 0.0;
-            if (r != 0.0) {
-                c = x / r;
-                s = -z / r;
-            }
-            if (q > l) e[q - 1] = r;
-            const double aq = d[q], aq1 = d[q + 1], bq = e[q];
-            const double cc = c * c, ss = s * s, cs = c * s;
-            d[q] = cc * aq - 2.0 * cs * bq + ss * aq1;
-            d[q + 1] = ss * aq + 2.0 * cs * bq + cc * aq1;
-            e[q] = cs * (aq - aq1) + (cc - ss) * bq;
-            if (q + 1 < h) {
-                const double bq1 = e[q + 1];
-                x = e[q];
-                z = -s * bq1;
-                e[q + 1] = c * bq1;
-            }
-            const double zq = zlast[q], zq1 = zlast[q + 1];
-            zlast[q] = c * zq - s * zq1;
-            zlast[q + 1] = s * zq + c * zq1;
-        }
-    }
-    lam = d;
-}
-
-
-void tridiag_full(std::vector<double> d, std::vector<double> e, std::vector<double> &lam,
-                  std::vector<double> &v)
-{
-    const int k = (int)d.size();
-    v.assign((size_t)k * k, 0.0);
-    for (int i = 0; i < k; ++i) v[(size_t)i * k + i] = 1.0;
-    e.resize(k, 0.0);
-    const double eps = 2.220446049250313e-16;
-    int h = k - 1, iter = 0;
-    while (h > 0) {
-        if (std::fabs(e[h - 1]) <= eps * (std::fabs(d[h - 1]) + std::fabs(d[h]))) {
-            e[h - 1] = 0.0;
-            --h;
-            iter = 0;
-            continue;
-        }
-        if (++iter > 200) break;
-        int l = h - 1;
-        while (l > 0 && std::fabs(e[l - 1]) > eps * (std::fabs(d[l - 1]) + std::fabs(d[l]))) --l;
-        const double delta = 0.5 * (d[h - 1] - d[h]);
-        const double b2 = e[h - 1] * e[h - 1];
-        const double mu = d[h] - b2 / (delta + std::copysign(std::sqrt(delta * delta + b2), delta));
-        double x = d[l] - mu, z = e[l];
-        for (int q = l; q < h; ++q) {
-            const double r = std::hypot(x, z);
-            double c = 1.0, s = 0.0;
-            if (r != 0.0) {
-                c = x / r;
-                s = -z / r;
-            }
-            if (q > l) e[q - 1] = r;
-            const double aq = d[q], aq1 = d[q + 1], bq = e[q];
-            const double cc = c * c, ss = s * s, cs = c * s;
-            d[q] = cc * aq - 2.0 * cs * bq + ss * aq1;
-            d[q + 1] = ss * aq + 2.0 * cs * bq + cc * aq1;
-            e[q] = cs * (aq - aq1) + (cc - ss) * bq;
-            if (q + 1 < h) {
-                const double bq1 = e[q + 1];
-                x = e[q];
-                z = -s * bq1;
-                e[q + 1] = c * bq1;
-            }
-            for (int row = 0; row < k; ++row) {
-                double &zq = v[(size_t)row * k + q], &zq1 = v[(size_t)row * k + q + 1];
-                const double a0 = zq, a1 = zq1;
-                zq = c * a0 - s * a1;
-                zq1 = s * a0 + c * a1;
-            }
-        }
-    }
-    lam = d;
-}
-
-int ritz_select(const std::vector<double> &lam, const std::vector<double> &zl, double beta_k, double e_lo,
-                double e_hi, double tol, int n_wanted, double *evals, double *bounds, std::vector<int> *rep)
-{
-    // candidates in the window, ascending, with their index into lam
-    std::vector<int> cand;
-    for (int i = 0; i < (int)lam.size(); ++i)
-        if (lam[i] >= e_lo && lam[i] <= e_hi) cand.push_back(i);
-    std::sort(cand.begin(), cand.end(), [&](int a, int b) { return lam[a] < lam[b]; });
-    int nf = 0;
-    for (size_t a = 0; a < cand.size();) {
-        size_t b = a + 1;
-        while (b < cand.size() && lam[cand[b]] - lam[cand[b - 1]] <= tol) ++b;
-        double sum = 0.0, t2s = 0.0;
-        int best = cand[a];
-        for (size_t c = a; c < b; ++c) {
-            sum += lam[cand[c]];
-            t2s += zl[cand[c]] * zl[cand[c]];
-            if (std::fabs(zl[cand[c]]) < std::fabs(zl[best])) best = cand[c];
-        }
-        const double bound = std::fabs(beta_k) * std::sqrt(t2s);
-        if (bound <= tol && nf < n_wanted) {
-            evals[nf] = sum / (double)(b - a);
-            bounds[nf] = bound;
-            if (rep) rep->push_back(best);
-            ++nf;
-        }
-        a = b;
-    }
-    return nf;
-}
-
-int ritz_chain(const double *alpha1, const double *beta1, int k, double e_lo, double e_hi, double tol, int n_wanted,
-               double *evals, double *bounds, std::vector<int> *rep, std::vector<double> *V)
-{
-    std::vector<double> d(alpha1, alpha1 + k), e(k, 0.0), lam, zl;
-    for (int j = 0; j + 1 < k; ++j) e[j] = beta1[j];
-    if (V) {
-        tridiag_full(d, e, lam, *V);
-        zl.assign(V->begin() + (size_t)(k - 1) * k, V->begin() + (size_t)k * k);
-    } else {
-        tridiag_last_row(d, e, lam, zl);
-    }
-    return ritz_select(lam, zl, beta1[k - 1], e_lo, e_hi, tol, n_wanted, evals, bounds, rep);
-}
-
-void merge_converged(std::vector<std::pair<double, double>> &found, const double *ev, const double *bd, int n,
-                     double tol)
-{
-    for (int i = 0; i < n; ++i) {
-        bool merged = false;
-        for (auto &f : found)
-            if (std::fabs(f.first - ev[i]) <= tol) {
-                if (bd[i] < f.second) f = {ev[i], bd[i]};
-                merged = true;
-                break;
-            }
-        if (!merged) found.push_back({ev[i], bd[i]});
-    }
-    std::sort(found.begin(), found.end());
-}
-
 dl_status run_build(dl_context *ctx, const Engine &e, const dl::Op &op, const double2 *in,
                     const double *field, double *partials, int shift)
 {
@@ -869,6 +700,7 @@ dl_status dirac_lanczos_eigen(dl_context *ctx, const void *psi0, int32_t k_max, 
                                   bd.data(), nullptr, nullptr);
         merge_converged(found, ev.data(), bd.data(), nf, tol);
     };
+    int pending = 0;  // checkpoint fetched but not yet solved
     for (int pp = 2; pp <= K1; ++pp) {
         dl::PassArgs a{};
         a.op = op;
@@ -886,16 +718,24 @@ dl_status dirac_lanczos_eigen(dl_context *ctx, const void *psi0, int32_t k_max, 
         dl::launch_recur(a, false, st);
         if ((pp - 1) % kEigenCheckEvery == 0 && pp < K1) {
             DL_HIP(ctx, hipGetLastError());
+            // the previous checkpoint is solved while the device runs the
+            // passes since then; the decision to stop is the same, only the
+            // passes queued meanwhile are extra work
+            if (pending > 0) {
+                harvest(pending);
+                pending = 0;
+                if ((int)found.size() >= n_wanted) break;
+            }
             const dl_status s = fetch();
             if (s != DL_OK) return s;
             if (hs.kstop < pp) break;  // breakdown: the recurrence is over
-            harvest(pp - 1);
-            if ((int)found.size() >= n_wanted) break;
+            pending = pp - 1;
         }
     }
     DL_HIP(ctx, hipGetLastError());
     const dl_status s = fetch();
     if (s != DL_OK) return s;
+    if (pending > 0) harvest(pending);
     if ((int)found.size() < n_wanted) {
         const int k = std::min(hs.keff, k_max);
         if (k > 0) harvest(k);
