@@ -282,7 +282,6 @@ struct HermOp {
 };
 struct HermRun {
     const double2 *b;    // start vector (device, layout (2, n, n))
-    double2 *q[2];       // two Lanczos vectors (device)
     double *alpha, *beta;
     int keff;            // iterations done; 0 for b = 0, -1 for a non-finite reduction
     int pad;

@@ -122,7 +122,7 @@ dl::HermOp make_hop(const dl_hermite_params &p, const double *dmat, const double
 
 struct HermLayout {
     size_t ops = 0, runs = 0, ptrs = 0, total = 0;
-    std::vector<size_t> dmat, x, q0, q1, ab;
+    std::vector<size_t> dmat, x, ab;
 };
 
 HermLayout herm_plan(const dl_hermite_params *p, int np, int k_max)
@@ -141,10 +141,6 @@ HermLayout herm_plan(const dl_hermite_params *p, int np, int k_max)
         off = align256(off + sizeof(double) * n2);
         L.x.push_back(off);
         off = align256(off + sizeof(double) * p[i].n);
-        L.q0.push_back(off);
-        off = align256(off + 16 * 2 * n2);
-        L.q1.push_back(off);
-        off = align256(off + 16 * 2 * n2);
         L.ab.push_back(off);
         off = align256(off + sizeof(double) * 2 * (size_t)std::max(k_max, 1));
     }
@@ -236,8 +232,6 @@ dl_status dirac_lanczos_hermite_eigen(const dl_hermite_params *params, int32_t n
         ops[i] = make_hop(params[i], reinterpret_cast<double *>(ws + L.dmat[i]), reinterpret_cast<double *>(ws + L.x[i]));
         dl::HermRun r{};
         r.b = static_cast<const double2 *>(psi0[i]);
-        r.q[0] = reinterpret_cast<double2 *>(ws + L.q0[i]);
-        r.q[1] = reinterpret_cast<double2 *>(ws + L.q1[i]);
         r.alpha = reinterpret_cast<double *>(ws + L.ab[i]);
         r.beta = r.alpha + k_max;
         runs[i] = r;
@@ -272,13 +266,15 @@ dl_status dirac_lanczos_hermite_eigen(const dl_hermite_params *params, int32_t n
     // converged clusters accumulated over the leading blocks k = 64, 128, ...
     // and k; problems are independent and spread over host threads
     std::atomic<int> next{0};
+    const int nt = std::max(1, std::min<int>(n_problems, host_threads()));
+    const int per_problem = std::max(1, host_threads() / nt);  // a few problems: checkpoints in parallel too
     auto worker = [&] {
         for (int i; (i = next.fetch_add(1)) < n_problems;) {
             const int k = runs[i].keff;
             if (k <= 0) continue;
             const double *al = ab.data() + (size_t)2 * k_max * i, *be = al + k_max;
             std::vector<std::pair<double, double>> found;
-            converged_union(al, be, k, e_lo[i], e_hi[i], tol, kEigenCheckEvery, 1, found);
+            converged_union(al, be, k, e_lo[i], e_hi[i], tol, kEigenCheckEvery, per_problem, found);
             const int nf = std::min((int)found.size(), n_wanted);
             for (int r = 0; r < nf; ++r) {
                 evals[(size_t)i * n_wanted + r] = found[r].first;
@@ -287,7 +283,6 @@ dl_status dirac_lanczos_hermite_eigen(const dl_hermite_params *params, int32_t n
             n_found[i] = nf;
         }
     };
-    const int nt = std::max(1, std::min<int>(n_problems, host_threads()));
     std::vector<std::thread> pool;
     for (int t = 1; t < nt; ++t) pool.emplace_back(worker);
     worker();

@@ -133,16 +133,30 @@ void bisect_window(const std::vector<double> &d, const std::vector<double> &e2, 
                 batch.push_back(iv);
         }
         if (batch.empty()) continue;
+        // multisection: the kShifts points are shared out over the intervals
+        // of the batch (kShifts / batch size interior points each, equally
+        // spaced), so that a lone interval gains log2(kShifts + 1) bits a pass
+        const int nb = (int)batch.size(), per = kShifts / nb;
         for (int s = 0; s < kShifts; ++s) {
-            const Interval &iv = batch[std::min<size_t>(s, batch.size() - 1)];
-            x[s] = 0.5 * (iv.a + iv.b);
+            const int i = std::min(s / per, nb - 1), r = std::min(s - i * per, per - 1);
+            const Interval &iv = batch[i];
+            const double x_r = iv.a + (iv.b - iv.a) * ((double)(r + 1) / (double)(per + 1));
+            x[s] = std::min(std::max(x_r, iv.a), iv.b);
         }
         sturm_counts(d.data(), e2.data(), k, x, pivmin, c);
-        for (size_t s = 0; s < batch.size(); ++s) {
-            const Interval &iv = batch[s];
-            const int cm = std::min(std::max(c[s], iv.ca), iv.cb);
-            if (cm > iv.ca) work.push_back({iv.a, x[s], iv.ca, cm});
-            if (iv.cb > cm) work.push_back({x[s], iv.b, cm, iv.cb});
+        for (int i = 0; i < nb; ++i) {
+            const Interval &iv = batch[i];
+            double a = iv.a;
+            int ca = iv.ca;
+            for (int r = 0; r <= per; ++r) {
+                const double b = r < per ? x[i * per + r] : iv.b;
+                const int cb = r < per ? std::min(std::max(c[i * per + r], ca), iv.cb) : iv.cb;
+                if (cb > ca && b > a) work.push_back({a, b, ca, cb});
+                if (b > a) {
+                    a = b;
+                    ca = cb;
+                }
+            }
         }
     }
     std::sort(leaves.begin(), leaves.end());
