@@ -116,8 +116,8 @@ typedef struct {
  * most the Krylov term plus int_0^1 ||F s(t)|| dt, s(t) = ||psi|| exp(-itT) e_1,
  * so round_bound = sum_j e_j I_j, j = 1..k-1, with I_j >= int_0^1 |s_j(t)| dt:
  * with R the Gershgorin half-width of T about its centre, I_j = 1.01
- * (int_0^1 |s_j|^2 dt)^(1/2) by 48-point Gauss-Legendre quadrature for
- * R <= 40 (Cauchy-Schwarz), ||psi|| [exp(|T - centre|) e_1]_j for 40 < R <= 70,
+ * (int_0^1 |s_j|^2 dt)^(1/2) by Gauss-Legendre quadrature with
+ * min(48, ceil(R) + 10) points for R <= 40 (Cauchy-Schwarz), ||psi|| [exp(|T - centre|) e_1]_j for 40 < R <= 70,
  * else ||psi||, each capped at ||psi||.  It holds without orthogonality of
  * the basis; the FP64 arithmetic of both precisions is not included.  Summed
  * over the steps it bounds the distance between a mixed-precision and an FP64

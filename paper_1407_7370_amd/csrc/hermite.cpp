@@ -8,6 +8,8 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <thread>
@@ -87,15 +89,27 @@ void nodes(int n, std::vector<double> &xi, std::vector<double> &w)
 // (xi_i - xi_j) (i != j; the derivative of the interpolant in the span of the
 // first n Hermite functions, in the variables sqrt(w) f), and the nodes times
 // scale.
-void tables(const dl_hermite_params &p, std::vector<double> &dm, std::vector<double> &x)
+// The nodes depend on n only: computed once per n for the process.
+const std::vector<double> &cached_nodes(int n)
 {
-    std::vector<double> xi, w;
-    nodes(p.n, xi, w);
-    dm.assign((size_t)p.n * p.n, 0.0);
+    static std::mutex mu;
+    static std::map<int, std::vector<double>> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(n);
+    if (it == cache.end()) {
+        std::vector<double> xi, w;
+        nodes(n, xi, w);
+        it = cache.emplace(n, std::move(xi)).first;
+    }
+    return it->second;
+}
+
+void tables(const dl_hermite_params &p, double *dm, double *x)
+{
+    const std::vector<double> xi = cached_nodes(p.n);
     for (int i = 0; i < p.n; ++i)
         for (int j = 0; j < p.n; ++j)
-            if (i != j) dm[(size_t)i * p.n + j] = (((i + j) & 1) ? -1.0 : 1.0) / ((xi[i] - xi[j]) * p.scale);
-    x.resize(p.n);
+            dm[(size_t)i * p.n + j] = i == j ? 0.0 : (((i + j) & 1) ? -1.0 : 1.0) / ((xi[i] - xi[j]) * p.scale);
     for (int i = 0; i < p.n; ++i) x[i] = xi[i] * p.scale;
 }
 
@@ -120,8 +134,11 @@ dl::HermOp make_hop(const dl_hermite_params &p, const double *dmat, const double
     return o;
 }
 
+// Workspace: the problem table, the run table, the pointer table and the
+// per-problem D and nodes (one block, uploaded in one copy), then the alpha
+// and beta arrays of every problem (one block, downloaded in one copy).
 struct HermLayout {
-    size_t ops = 0, runs = 0, ptrs = 0, total = 0;
+    size_t ops = 0, runs = 0, ptrs = 0, tables_end = 0, ab0 = 0, total = 0;
     std::vector<size_t> dmat, x, ab;
 };
 
@@ -141,10 +158,14 @@ HermLayout herm_plan(const dl_hermite_params *p, int np, int k_max)
         off = align256(off + sizeof(double) * n2);
         L.x.push_back(off);
         off = align256(off + sizeof(double) * p[i].n);
-        L.ab.push_back(off);
-        off = align256(off + sizeof(double) * 2 * (size_t)std::max(k_max, 1));
     }
-    L.total = off;
+    L.tables_end = off;
+    L.ab0 = off;
+    for (int i = 0; i < np; ++i) {
+        L.ab.push_back(off);
+        off += sizeof(double) * 2 * (size_t)std::max(k_max, 1);
+    }
+    L.total = align256(off);
     return L;
 }
 
@@ -185,16 +206,14 @@ dl_status dirac_lanczos_hermite_apply(const dl_hermite_params *params, const voi
                                                " bytes");
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     char *ws = static_cast<char *>(workspace);
-    std::vector<double> dm, xs;
-    tables(*params, dm, xs);
+    std::vector<char> img(L.tables_end, 0);
+    tables(*params, reinterpret_cast<double *>(img.data() + L.dmat[0]), reinterpret_cast<double *>(img.data() + L.x[0]));
     const dl::HermOp op = make_hop(*params, reinterpret_cast<double *>(ws + L.dmat[0]),
                                    reinterpret_cast<double *>(ws + L.x[0]));
     const void *ptrs[2] = {x, y};
-    if (hipMemcpyAsync(ws + L.dmat[0], dm.data(), sizeof(double) * dm.size(), hipMemcpyHostToDevice, st) !=
-            hipSuccess ||
-        hipMemcpyAsync(ws + L.x[0], xs.data(), sizeof(double) * xs.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(ws + L.ops, &op, sizeof(op), hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(ws + L.ptrs, ptrs, sizeof(ptrs), hipMemcpyHostToDevice, st) != hipSuccess)
+    std::memcpy(img.data() + L.ops, &op, sizeof(op));
+    std::memcpy(img.data() + L.ptrs, ptrs, sizeof(ptrs));
+    if (hipMemcpyAsync(ws, img.data(), img.size(), hipMemcpyHostToDevice, st) != hipSuccess)
         return herm_fail(DL_ERR_DEVICE, "upload of the problem tables failed");
     const void *const *dp = reinterpret_cast<const void *const *>(ws + L.ptrs);
     dl::launch_herm_apply(reinterpret_cast<const dl::HermOp *>(ws + L.ops),
@@ -224,37 +243,29 @@ dl_status dirac_lanczos_hermite_eigen(const dl_hermite_params *params, int32_t n
                                                " bytes");
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     char *ws = static_cast<char *>(workspace);
-    std::vector<dl::HermOp> ops(n_problems);
-    std::vector<dl::HermRun> runs(n_problems);
-    std::vector<std::vector<double>> dms(n_problems), xss(n_problems);
+    // host image of the tables block, uploaded in one copy
+    std::vector<char> img(L.tables_end, 0);
+    dl::HermOp *ops = reinterpret_cast<dl::HermOp *>(img.data() + L.ops);
+    dl::HermRun *runs0 = reinterpret_cast<dl::HermRun *>(img.data() + L.runs);
     for (int i = 0; i < n_problems; ++i) {
-        tables(params[i], dms[i], xss[i]);
+        tables(params[i], reinterpret_cast<double *>(img.data() + L.dmat[i]),
+               reinterpret_cast<double *>(img.data() + L.x[i]));
         ops[i] = make_hop(params[i], reinterpret_cast<double *>(ws + L.dmat[i]), reinterpret_cast<double *>(ws + L.x[i]));
         dl::HermRun r{};
         r.b = static_cast<const double2 *>(psi0[i]);
         r.alpha = reinterpret_cast<double *>(ws + L.ab[i]);
         r.beta = r.alpha + k_max;
-        runs[i] = r;
-        if (hipMemcpyAsync(ws + L.dmat[i], dms[i].data(), sizeof(double) * dms[i].size(), hipMemcpyHostToDevice, st) !=
-                hipSuccess ||
-            hipMemcpyAsync(ws + L.x[i], xss[i].data(), sizeof(double) * xss[i].size(), hipMemcpyHostToDevice, st) !=
-                hipSuccess)
-            return herm_fail(DL_ERR_DEVICE, "upload of the problem tables failed");
+        runs0[i] = r;
     }
-    if (hipMemcpyAsync(ws + L.ops, ops.data(), sizeof(dl::HermOp) * n_problems, hipMemcpyHostToDevice, st) !=
-            hipSuccess ||
-        hipMemcpyAsync(ws + L.runs, runs.data(), sizeof(dl::HermRun) * n_problems, hipMemcpyHostToDevice, st) !=
-            hipSuccess)
+    if (hipMemcpyAsync(ws, img.data(), img.size(), hipMemcpyHostToDevice, st) != hipSuccess)
         return herm_fail(DL_ERR_DEVICE, "upload of the problem tables failed");
     dl::launch_herm_lanczos(reinterpret_cast<const dl::HermOp *>(ws + L.ops), reinterpret_cast<dl::HermRun *>(ws + L.runs),
                             n_problems, k_max, st);
     if (hipGetLastError() != hipSuccess) return herm_fail(DL_ERR_DEVICE, "kernel launch failed");
     std::vector<double> ab((size_t)2 * k_max * n_problems);
-    for (int i = 0; i < n_problems; ++i)
-        if (hipMemcpyAsync(ab.data() + (size_t)2 * k_max * i, ws + L.ab[i], sizeof(double) * 2 * k_max,
-                           hipMemcpyDeviceToHost, st) != hipSuccess)
-            return herm_fail(DL_ERR_DEVICE, "download of the recurrences failed");
-    if (hipMemcpyAsync(runs.data(), ws + L.runs, sizeof(dl::HermRun) * n_problems, hipMemcpyDeviceToHost, st) !=
+    std::vector<dl::HermRun> runs(n_problems);
+    if (hipMemcpyAsync(ab.data(), ws + L.ab0, sizeof(double) * ab.size(), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(runs.data(), ws + L.runs, sizeof(dl::HermRun) * n_problems, hipMemcpyDeviceToHost, st) !=
             hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
         return herm_fail(DL_ERR_DEVICE, "synchronisation failed");

@@ -319,7 +319,7 @@ using namespace dlh;
 #define DL_RECUR_ROUNDS 1
 #endif
 #ifndef DL_RECUR_WAVES_PER_CU
-#define DL_RECUR_WAVES_PER_CU 8
+#define DL_RECUR_WAVES_PER_CU 4
 #endif
 
 namespace {
@@ -330,7 +330,10 @@ namespace {
 // the grid allows, between 2 and DL_RECUR_WAVES_PER_CU waves per compute unit:
 // on small grids short chunks spend their time in the march prologue
 // (measured per step, FP64: 512^2 m = 12 278 -> 222 us, 1024^2 m = 20
-// 1034 -> 769 us; 4096^2 keeps eight waves).
+// 1034 -> 769 us).  Four waves (one per SIMD, one workgroup per compute
+// unit) is the cap: with the FIFO of loads really in flight, fewer and
+// longer row streams use the DRAM better (dominant sweep, 4096^2 mixed:
+// 4 waves 154 us, 8 waves 167 us; 2048^2 52 vs 67 us; FP64 alike).
 int default_sweep_waves(const dl_params &p, int cus)
 {
     const long strips = (p.nx + 59) / 60;

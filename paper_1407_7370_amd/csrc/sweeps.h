@@ -110,6 +110,20 @@ __device__ __forceinline__ Sp to_sp(const Raw<T> &r)
     return Sp{(double)r.a.x, (double)r.a.y, (double)r.b.x, (double)r.b.y};
 }
 
+// A FIFO slot's row, taken out of the registers the next load will refill.
+// complex64 rows are widened anyway; complex128 rows get a real operation
+// (x + 0.0, which the compiler may not drop), so the refill can reuse the
+// slot's registers instead of leaving copies of in-flight loads at the loop's
+// back edge, which would wait for them.
+template <class T>
+__device__ __forceinline__ Sp fifo_take(const Raw<T> &r)
+{
+    if constexpr (sizeof(r.a.x) == 8)
+        return Sp{r.a.x + 0.0, r.a.y + 0.0, r.b.x + 0.0, r.b.y + 0.0};
+    else
+        return to_sp(r);
+}
+
 // The value that a later sweep reads back from storage of type T.
 template <class T>
 __device__ __forceinline__ Sp stored_value(const Sp &s);
@@ -486,36 +500,36 @@ __device__ __forceinline__ void first_body(const Op &op, const Tiles &t, const W
         const uint32_t off = lg.inx ? PlanarF::lane_offset(lg.colw) : kOob;
         const int y0 = wt.y0, y1 = wt.y1, base = y0 - 1;
         RowCursor<PY> cin = row_cursor<PY>(psi, vin.row_bytes, ny, base, base, y1);
+        // empty FIFO, march from PF rows early: every load comes from the loop
+        // (see recur_body)
         Raw<double2> F[PF];
 #pragma unroll
-        for (int i = 0; i < PF; ++i) {
-            F[i] = vin.load_at(cin.ptr(ny), cin.bytes(), off);
-            cin.next();
-        }
+        for (int i = 0; i < PF; ++i) F[i] = raw_zero<double2>();
         Sp P[4] = {sp_zero(), sp_zero(), sp_zero(), sp_zero()};
-        int R0 = base;
+        const double mo = lg.own ? 1.0 : 0.0;
+        int R0 = base - PF;
         auto step = [&](auto kc) {
             constexpr int k = decltype(kc)::value & 3;
             constexpr int f = decltype(kc)::value % PF;
             const int R = R0 + decltype(kc)::value;
-            if (R > y1) return;
-            P[k] = to_sp(F[f]);
+            __builtin_amdgcn_sched_barrier(0);
+            P[k] = fifo_take(F[f]);
             F[f] = vin.load_at(cin.ptr(ny), cin.bytes(), off);
             cin.next();
-            if (R - 1 < y0) return;
-            const Sp &c = P[(k + 3) & 3];  // row R-1 (inside the domain)
+            // A psi at row R-1, reduced over the owned rows y0 .. y1-1
+            const Sp &c = P[(k + 3) & 3];
             double v = 0.0, gx = gxh;
             if constexpr (TERMS != 0) {
-                const double y = op.ymin + (R - 1) * op.hy;
-                if constexpr (TERMS & kTermPot) v = site_pot_row(op, lg, R - 1, y);
+                const int jr = min(max(R - 1, 0), ny - 1);
+                const double y = op.ymin + jr * op.hy;
+                if constexpr (TERMS & kTermPot) v = site_pot_row(op, lg, jr, y);
                 if constexpr (TERMS & kTermB) gx = gxh + op.bq * y;
             }
             const Sp y = hop(op, c, sp_left(c), sp_right(c), P[(k + 2) & 3], P[k], v, gx, gy);
-            if (lg.own) {
-                acc[0] += sp_norm2(c);
-                acc[1] += sp_redot(c, y);
-                acc[2] += sp_norm2(y);
-            }
+            const double m = (unsigned)(R - 1 - y0) < (unsigned)(y1 - y0) ? mo : 0.0;
+            acc[0] += m * sp_norm2(c);
+            acc[1] += m * sp_redot(c, y);
+            acc[2] += m * sp_norm2(y);
         };
         for (; R0 <= y1; R0 += U) unroll_steps(step, std::make_integer_sequence<int, U>{});
     }
@@ -596,7 +610,6 @@ __device__ __forceinline__ void recur_body(const PassArgs &a, const WaveTask &wt
     using T2 = typename V2::T;
     const Scalars *sc = a.sc;
     const int p = a.pass;
-    const bool last = (p == a.m) || (p == sc->kstop);
     const Op &op = a.op;
     const int ny = op.ny;
     const int lane = threadIdx.x & 63;
@@ -623,33 +636,42 @@ __device__ __forceinline__ void recur_body(const PassArgs &a, const WaveTask &wt
         // cursors: u_{p-1} rows from base, u_{p-2} rows from base-1, u_p rows from base-1
         RowCursor<PY> c1 = row_cursor<PY>(a.u1, v1.row_bytes, ny, base, base, y1 + 1);
         RowCursor<PY> c2 = row_cursor<PY>(a.u2, v2.row_bytes, ny, base - 1, y0 - 1, y1);
-        RowCursor<PY> co = row_cursor<PY>(a.uo, vo.row_bytes, ny, base - 1, y0, y1 - 1);
+        // the march starts PF rows early with empty FIFOs, so that the first
+        // loads are issued by the same loop code as every later refill
+        RowCursor<PY> co = row_cursor<PY>(a.uo, vo.row_bytes, ny, base - PF - 1, y0, y1 - 1);
         // FIFOs: u_{p-1} row r in slot (r-base) mod PF, needed rows y0-2 .. y1+1;
         //        u_{p-2} row r-1 in the same slot, needed rows y0-1 .. y1.
         Raw<T1> F1[PF];
         Raw<T2> F2[PF];
 #pragma unroll
         for (int i = 0; i < PF; ++i) {
-            F1[i] = v1.load_at(c1.ptr(ny), c1.bytes(), off1);
-            c1.next();
-            if (HAS2) {
-                F2[i] = v2.load_at(c2.ptr(ny), c2.bytes(), off2);
-                c2.next();
-            } else {
-                F2[i] = raw_zero<T2>();
-            }
+            F1[i] = raw_zero<T1>();
+            F2[i] = raw_zero<T2>();
         }
         Sp P[4] = {sp_zero(), sp_zero(), sp_zero(), sp_zero()};  // u_{p-1} rows
         Sp Q[4] = {sp_zero(), sp_zero(), sp_zero(), sp_zero()};  // u_p rows
         double Vr[4] = {0.0, 0.0, 0.0, 0.0};                      // potential of the rows (kTermPot)
-        int R0 = base;
+        const double mo = lg.own ? 1.0 : 0.0;                     // lanes whose sites this wave owns
+        int R0 = base - PF;
+        // One row R of the march, with no branch: rows the wave does not
+        // produce are masked instead.  u_p is formed at row R-1 for every R
+        // (the cursor of u_p drops the stores outside rows y0 .. y1-1, a
+        // Dirichlet row outside the domain gets zero coefficients) and A u_p
+        // at row R-2 enters the reductions only for rows y0 .. y1-1.  The loop
+        // blocks are then identical, so the compiler waits for one row of
+        // loads at a time while PF rows are in flight; a branch per row makes
+        // it wait for all of them.  Rows past y1+1 in the last block load
+        // nothing (zero-size descriptors) and are discarded.
         auto step = [&](auto kc) {
-            constexpr int k = decltype(kc)::value & 3;   // ring slot of row R
-            constexpr int f = decltype(kc)::value % PF;  // FIFO slot of row R
-            const int R = R0 + decltype(kc)::value;
-            if (R > y1 + 1) return;
-            P[k] = to_sp(F1[f]);
-            const Sp o2 = to_sp(F2[f]);
+            constexpr int kk = decltype(kc)::value;
+            constexpr int k = kk & 3;   // ring slot of row R
+            constexpr int f = kk % PF;  // FIFO slot of row R
+            const int R = R0 + kk;
+            // keep each row's work in its place: hoisted FIFO reads would make
+            // the loop head wait for the rows still in flight
+            __builtin_amdgcn_sched_barrier(0);
+            P[k] = fifo_take(F1[f]);
+            const Sp o2 = fifo_take(F2[f]);
             // refill: u_{p-1} row R+PF, u_{p-2} row R+PF-1
             F1[f] = v1.load_at(c1.ptr(ny), c1.bytes(), off1);
             c1.next();
@@ -657,50 +679,50 @@ __device__ __forceinline__ void recur_body(const PassArgs &a, const WaveTask &wt
                 F2[f] = v2.load_at(c2.ptr(ny), c2.bytes(), off2);
                 c2.next();
             }
-            // u_p at row R-1 (rows y0-1 .. y1)
-            if (R >= y0) {
+            // u_p at row R-1, zero outside a Dirichlet domain
+            {
                 const int rr = R - 1;
-                Sp u = sp_zero();
-                if (PY || (unsigned)rr < (unsigned)ny) {
-                    const Sp &c = P[(k + 3) & 3];
-                    double v = 0.0, gx = gxh;
-                    if constexpr (TERMS != 0) {
-                        const int jw = rr < 0 ? rr + ny : (rr >= ny ? rr - ny : rr);
-                        const double y = op.ymin + jw * op.hy;
-                        if constexpr (TERMS & kTermPot) {
-                            v = site_pot_row(op, lg, jw, y);
-                            Vr[(k + 3) & 3] = v;
-                        }
-                        if constexpr (TERMS & kTermB) gx = gxh + op.bq * y;
+                const double mr = (PY || (unsigned)rr < (unsigned)ny) ? 1.0 : 0.0;
+                const Sp &c = P[(k + 3) & 3];
+                double v = 0.0, gx = gxh;
+                if constexpr (TERMS != 0) {
+                    // periodic image of the row; rows masked out clamp into the grid
+                    const int jw = min(max(rr < 0 ? rr + ny : (rr >= ny ? rr - ny : rr), 0), ny - 1);
+                    const double y = op.ymin + jw * op.hy;
+                    if constexpr (TERMS & kTermPot) {
+                        v = site_pot_row(op, lg, jw, y);
+                        Vr[(k + 3) & 3] = v;
                     }
-                    const Sp w = hop(op, c, sp_left(c), sp_right(c), P[(k + 2) & 3], P[k], v, gx, gy, sig);
-                    u.r0 = cw * w.r0 - cc * c.r0 - cu * o2.r0;
-                    u.i0 = cw * w.i0 - cc * c.i0 - cu * o2.i0;
-                    u.r1 = cw * w.r1 - cc * c.r1 - cu * o2.r1;
-                    u.i1 = cw * w.i1 - cc * c.i1 - cu * o2.i1;
+                    if constexpr (TERMS & kTermB) gx = gxh + op.bq * y;
                 }
+                const Sp w = hop(op, c, sp_left(c), sp_right(c), P[(k + 2) & 3], P[k], v, gx, gy, sig);
+                const double cwr = mr * cw, ccr = mr * cc, cur = mr * cu;
+                Sp u;
+                u.r0 = cwr * w.r0 - ccr * c.r0 - cur * o2.r0;
+                u.i0 = cwr * w.i0 - ccr * c.i0 - cur * o2.i0;
+                u.r1 = cwr * w.r1 - ccr * c.r1 - cur * o2.r1;
+                u.i1 = cwr * w.i1 - ccr * c.i1 - cur * o2.i1;
                 const Raw<TO> ur = to_raw<TO>(u);
                 Q[(k + 3) & 3] = to_sp(ur);
                 vo.store_at(co.ptr(ny), co.bytes(), offo, ur);
             }
             co.next();
-            // A u_p at row R-2 (rows y0 .. y1-1, inside the domain) and the reductions
-            if (R >= y0 + 2) {
+            // A u_p at row R-2 and the reductions over rows y0 .. y1-1 (the
+            // last pass's two extra ones are formed every pass and reduced
+            // only in the last)
+            {
                 const Sp &c = Q[(k + 2) & 3];
                 double v = 0.0, gx = gxh;
                 if constexpr (TERMS & kTermPot) v = Vr[(k + 2) & 3];
                 if constexpr (TERMS & kTermB) gx = gxh + op.bq * (op.ymin + (R - 2) * op.hy);
                 const Sp y = hop(op, c, sp_left(c), sp_right(c), Q[(k + 1) & 3], Q[(k + 3) & 3], v, gx, gy, sig);
-                if (lg.own) {
-                    const Sp &prev = P[(k + 2) & 3];  // u_{p-1} row R-2
-                    acc[0] += sp_norm2(c);
-                    acc[1] += sp_redot(c, y);
-                    acc[2] += sp_redot(c, prev);
-                    if (last) {
-                        acc[3] += sp_norm2(y);
-                        acc[4] += sp_redot(y, prev);
-                    }
-                }
+                const Sp &prev = P[(k + 2) & 3];  // u_{p-1} row R-2
+                const double m = (unsigned)(R - 2 - y0) < (unsigned)(y1 - y0) ? mo : 0.0;
+                acc[0] += m * sp_norm2(c);
+                acc[1] += m * sp_redot(c, y);
+                acc[2] += m * sp_redot(c, prev);
+                acc[3] += m * sp_norm2(y);
+                acc[4] += m * sp_redot(y, prev);
             }
         };
         for (; R0 <= y1 + 1; R0 += U) unroll_steps(step, std::make_integer_sequence<int, U>{});
@@ -915,9 +937,10 @@ __device__ void predict_k(const double *alpha, const double *gamma, Scalars *sc,
 // of eq. matrix_exponential_error), with no assumption of orthogonality, and
 // int_0^1 |s_j(t)| dt <= (int_0^1 |s_j(t)|^2 dt)^(1/2) (Cauchy-Schwarz).
 // While the Gershgorin half-width R of T (centre c0) is at most 40 the
-// integral is taken by 48-node Gauss-Legendre quadrature on [0, 1] (|s_j|^2
-// is a trigonometric sum of frequencies below 2R, far inside the rule's
-// resolution), with s carried from node to node by short Chebyshev expansions
+// integral is taken by Gauss-Legendre quadrature on [0, 1] with
+// min(48, ceil(R) + 10) nodes (|s_j|^2 is a trigonometric sum of frequencies
+// below 2R, inside the rule's resolution), with s carried from node to node
+// by short Chebyshev expansions
 // of exp(-i delta (T - c0 I)) (Bessel coefficients J_n(delta R) by Miller's
 // backward recurrence, one lane per node) and a 1% margin on the integral.
 // The scalar phase exp(-i delta c0) of each Chebyshev step does not change
@@ -963,18 +986,23 @@ __device__ double storage_bound(double d, double e, double em, int k, int lane, 
     const double c0 = 0.5 * (glo + ghi), R = 0.5 * (ghi - glo);
     double f = 1.0;
     if (R <= kBoundMaxR) {
+        // |s_j|^2 has frequencies below 2R: ceil(R) + 10 nodes integrate it to
+        // ~1e-8 relative, far inside the margin
+        const int nn = min(kBoundNodes, max(8, (int)ceil(R) + 10));
         double tq = 0.0, wq = 0.0;
-        if (lane < kBoundNodes) gauss_legendre01(kBoundNodes, lane, tq, wq);
+        if (lane < nn) gauss_legendre01(nn, lane, tq, wq);
         __syncthreads();  // tables of an earlier call are read up to here
-        if (lane < kBoundNodes) {
+        if (lane < nn) {
             tnode[lane] = tq;
             wnode[lane] = wq;
         }
         const double tprev = __shfl_up(tq, 1, 64);
-        const double delta = lane < kBoundNodes ? (lane == 0 ? tq : tq - tprev) : 0.0;
+        const double delta = lane < nn ? (lane == 0 ? tq : tq - tprev) : 0.0;
         const double xmax = wave_max(delta) * R;
-        const int N = xmax > 0.0 ? min(cheb_terms(xmax), kBoundMaxTerms) : 0;
-        if (lane < kBoundNodes) {
+        // hops are short (x = delta R < 2): x + 4 x^(1/3) + 8 terms leave a
+        // truncation below 1e-13
+        const int N = xmax > 0.0 ? min((int)ceil(xmax + 4.0 * cbrt(xmax) + 8.0), kBoundMaxTerms) : 0;
+        if (lane < nn) {
             if (delta * R > 0.0) {
                 bessel_miller(delta * R, N, &jtab[lane][0]);
             } else {
@@ -987,7 +1015,7 @@ __device__ double storage_bound(double d, double e, double em, int k, int lane, 
         const double xd = lane < k ? (d - c0) * ir : 0.0, xe = e * ir, xem = em * ir;
         auto xmul = [&](double v) { return xem * from_left(v) + xd * v + xe * from_right(v); };
         double sr = lane == 0 ? 1.0 : 0.0, si = 0.0, integral = 0.0;
-        for (int q = 0; q < kBoundNodes; ++q) {
+        for (int q = 0; q < nn; ++q) {
             // exp(-i dq (T - c0)) s = sum_n a_n T_n(X) s, a_0 = J_0, a_n = 2 (-i)^n J_n(dq R),
             // dq = t_q - t_{q-1}
             double pr = sr, pi = si;                // T_{n-1}(X) s

@@ -2,7 +2,8 @@
 
   python -m paper_1407_7370_amd.rocprof_summary --stats DIR/trace_kernel_stats.csv \
       [--fetch DIR/fetch_counter_collection.csv --write DIR/write_counter_collection.csv] \
-      [--calib-mib N] [--traffic-json profiles/traffic_recur_laser4096.json] [--command "..."]
+      [--calib-mib N] [--traffic-json profiles/traffic_recur_laser4096.json] [--command "..."] \
+      [--sq DIR/sq_counter_collection.csv] [--counters DIR/x_counter_collection.csv ...]
 
 Kernel statistics: calls and average duration per kernel.  Counters: HBM read
 and write bytes per dispatch from FETCH_SIZE / WRITE_SIZE (KiB), each scaled
@@ -77,6 +78,8 @@ def main():
     ap.add_argument("--sites", type=int, default=4096 * 4096)
     ap.add_argument("--command", default="")
     ap.add_argument("--sq", help="counter CSV of SQ_WAVES, SQ_INSTS_VALU, SQ_INSTS_SALU, SQ_BUSY_CYCLES")
+    ap.add_argument("--counters", action="append", default=[],
+                    help="counter CSV of any other pass: mean value per dispatch of each counter, per kernel")
     ap.add_argument("--clock-ghz", type=float, default=2.4)
     ap.add_argument("--simds", type=int, default=1024)
     args = ap.parse_args()
@@ -145,6 +148,18 @@ def main():
             cap = args.simds * dur[k] * 1e-6 * args.clock_ghz * 1e9 / 4.0
             lines.append(f"{short_name(k)[:78]:78s} {a.get('SQ_WAVES', 0):7.0f} {a.get('SQ_INSTS_VALU', 0) / 1e6:8.1f} "
                          f"{a.get('SQ_INSTS_SALU', 0) / 1e6:8.1f} {a.get('SQ_INSTS_VALU', 0) / cap * 100:8.1f}%")
+    for path in args.counters:
+        cs = collections.defaultdict(lambda: collections.defaultdict(list))
+        for r in csv.DictReader(open(path)):
+            cs[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        names = sorted({c for k in cs for c in cs[k]})
+        lines.append("")
+        lines.append(f"{'kernel':78s} " + " ".join(f"{c:>22s}" for c in names) + "   (mean per dispatch)")
+        for k in sorted(cs):
+            if "dl::" not in k:
+                continue
+            vals = [sum(cs[k][c]) / len(cs[k][c]) if cs[k][c] else 0.0 for c in names]
+            lines.append(f"{short_name(k)[:78]:78s} " + " ".join(f"{v:22.0f}" for v in vals))
     text = "\n".join(lines)
     print(text)
     if args.traffic_json and traffic:
