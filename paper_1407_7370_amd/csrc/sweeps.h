@@ -963,21 +963,38 @@ constexpr double kBoundMaxR = 40.0;
 
 // Gauss-Legendre node (on [0, 1], ascending in q) and weight of rule size n
 // for node q < n (Newton's method on P_n).
+struct InvTable {
+    double v[kBoundNodes + 1];
+};
+constexpr InvTable make_inv_table()
+{
+    InvTable tb{};
+    for (int j = 1; j <= kBoundNodes; ++j) tb.v[j] = 1.0 / j;
+    return tb;
+}
+
 __device__ void gauss_legendre01(int n, int q, double &t, double &w)
 {
-    double x = cos(3.14159265358979323846 * (q + 0.75) / (n + 0.5)), dp = 1.0;
-    for (int it = 0; it < 100; ++it) {
-        double p0 = 1.0, p1 = 0.0;
+    // three Newton steps from the classical starting guess reach the node to
+    // a few ulps for every n <= 48 (checked against numpy's rule); the
+    // Legendre recurrence multiplies by 1/j from a table
+    constexpr InvTable inv = make_inv_table();
+    double x = cos(3.14159265358979323846 * (q + 0.75) / (n + 0.5)), p0 = 1.0, p1 = 0.0, dp = 1.0;
+    auto legendre = [&](double xx) {
+        p0 = 1.0;
+        p1 = 0.0;
         for (int j = 1; j <= n; ++j) {
             const double p2 = p1;
             p1 = p0;
-            p0 = ((2.0 * j - 1.0) * x * p1 - (j - 1.0) * p2) / j;
+            p0 = ((2.0 * j - 1.0) * xx * p1 - (j - 1.0) * p2) * inv.v[j];
         }
-        dp = n * (x * p0 - p1) / (x * x - 1.0);
-        const double dx = p0 / dp;
-        x -= dx;
-        if (fabs(dx) < 1e-16) break;
+        dp = n * (xx * p0 - p1) / (xx * xx - 1.0);
+    };
+    for (int it = 0; it < 3; ++it) {
+        legendre(x);
+        x -= p0 / dp;
     }
+    legendre(x);
     t = 0.5 * (1.0 - x);
     w = 1.0 / ((1.0 - x * x) * dp * dp);
 }

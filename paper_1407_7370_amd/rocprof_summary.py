@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--sq", help="counter CSV of SQ_WAVES, SQ_INSTS_VALU, SQ_INSTS_SALU, SQ_BUSY_CYCLES")
     ap.add_argument("--counters", action="append", default=[],
                     help="counter CSV of any other pass: mean value per dispatch of each counter, per kernel")
+    ap.add_argument("--dispatches", nargs=2, metavar=("TRACE_CSV", "NAME"),
+                    help="every dispatch of the kernels whose name contains NAME: grid size and duration")
     ap.add_argument("--clock-ghz", type=float, default=2.4)
     ap.add_argument("--simds", type=int, default=1024)
     args = ap.parse_args()
@@ -160,6 +162,16 @@ def main():
                 continue
             vals = [sum(cs[k][c]) / len(cs[k][c]) if cs[k][c] else 0.0 for c in names]
             lines.append(f"{short_name(k)[:78]:78s} " + " ".join(f"{v:22.0f}" for v in vals))
+    if args.dispatches:
+        path, needle = args.dispatches
+        lines.append("")
+        lines.append(f"dispatches of {needle}: grid (work-items), workgroup, duration")
+        for r in csv.DictReader(open(path)):
+            if needle not in r.get("Kernel_Name", ""):
+                continue
+            dur = (float(r["End_Timestamp"]) - float(r["Start_Timestamp"])) / 1e3
+            lines.append(f"  grid {r.get('Grid_Size_X', r.get('Grid_Size', '?')):>8s}  workgroup "
+                         f"{r.get('Workgroup_Size_X', r.get('Workgroup_Size', '?')):>5s}  {dur:12.2f} us")
     text = "\n".join(lines)
     print(text)
     if args.traffic_json and traffic:
