@@ -52,7 +52,19 @@ def test_lowmem_vs_stored_basis(torch_cuda, orc, case, prec):
     sa = prop.step(a, 0.0, dt, n)
     sb = prop.step(b, 0.0, dt, n, lowmem=True)
     prop.close()
-    assert hz.rel_l2(b.cpu().numpy(), a.cpu().numpy()) <= 1e-14
+    dist = hz.rel_l2(b.cpu().numpy(), a.cpu().numpy())
+    if prec == "fp64":
+        assert dist <= 1e-14
+    else:
+        # the two recombinations add the same terms in other groupings; a
+        # last-bit difference of the state changes the complex64 rounding of
+        # some Krylov vectors of the next steps, so in mixed precision the two
+        # agree to the storage bound of both runs (each is within its summed
+        # round_bound of the FP64 steps), not to FP64 rounding
+        nrm = np.linalg.norm(psi0)
+        tol = (sa["cum_round_bound"][-1] + sb["cum_round_bound"][-1]) / nrm + 1e-14
+        print(f"mixed stored vs second run: {dist:.2e} (storage bounds {tol:.2e})", flush=True)
+        assert dist <= tol
     assert np.array_equal(sa["k_eff"], sb["k_eff"])
     # estimates near 1e-15 are rounding-level numbers: relative agreement is looser
     np.testing.assert_allclose(sb["err_est"], sa["err_est"], rtol=1e-6, atol=1e-22)
