@@ -5,11 +5,11 @@
 // exponentials, the recombination) whatever the number of packets.
 //
 // Launch shape.  The sweeps of all packets use one common number R of rows per
-// chunk: the smallest power of two (>= 4) for which the batch has at most one
-// resident round of waves (eight per compute unit), or one chunk per strip
-// when even that is more.  A packet's tasks (strip, chunk) are padded to a
-// multiple of four so that a workgroup's waves belong to one packet; the
-// workgroups of a packet are a contiguous segment of the grid.  The
+// chunk: the smallest power of two (>= 16) for which the batch has at most
+// eight block entries per resident workgroup, or one chunk per strip when
+// even that is more.  A packet's tasks (strip, chunk) are padded to a
+// multiple of four so that a block entry's waves belong to one packet; the
+// entries of a packet form a contiguous segment (partials slots).  The
 // recombination gives every packet a number of workgroups proportional to its
 // tiles (DL_BATCH_COMB_WGS_PER_CU workgroups per compute unit in total).
 #include <algorithm>
@@ -24,6 +24,13 @@
 // packets in proportion to their tiles.
 #ifndef DL_BATCH_COMB_WGS_PER_CU
 #define DL_BATCH_COMB_WGS_PER_CU 4
+#endif
+
+// Fixed cost of one block entry of the resident sweeps, in rows of its march
+// (the march starts a FIFO depth plus four rows early; the entry's table
+// loads and its segment reduction), for balancing the entries.
+#ifndef DL_BATCH_ENTRY_ROWS
+#define DL_BATCH_ENTRY_ROWS 16
 #endif
 
 using namespace dlh;
@@ -42,6 +49,8 @@ struct dl_batch {
     dl::BatchPacket *d_pk = nullptr;
     dl::BatchBlock *d_blk[dl::kGridKinds] = {nullptr, nullptr, nullptr};
     dl::BatchTask *d_task[2] = {nullptr, nullptr};
+    int *d_wgf[2] = {nullptr, nullptr};  // per resident workgroup: first entry (and the end)
+    int nwg[2] = {0, 0};                 // resident workgroups of the sweeps and of iteration 1
     double *partials = nullptr;
     double *fields = nullptr;     // n x 2 x kChunk
     dl::StepStat *stats = nullptr; // n x kChunk
@@ -74,7 +83,8 @@ thread_local std::string g_batch_init_error;
 
 struct BatchPlan {
     // layout
-    size_t pk = 0, blk[dl::kGridKinds] = {0, 0, 0}, task[2] = {0, 0}, partials = 0, fields = 0, stats = 0,
+    size_t pk = 0, blk[dl::kGridKinds] = {0, 0, 0}, task[2] = {0, 0}, wgf[2] = {0, 0}, partials = 0, fields = 0,
+           stats = 0,
            scalars = 0, alpha = 0, gamma = 0, vecs = 0, total = 0;
     size_t sc_stride = 0, ab_stride = 0;
     std::vector<size_t> vec_off;  // per packet: state vector, then the basis
@@ -121,6 +131,8 @@ BatchPlan batch_plan(const dl_params *params, int n)
     for (int k = 0; k < 2; ++k) {
         B.task[k] = off;
         off = align256(off + sizeof(dl::BatchTask) * tasks[k]);
+        B.wgf[k] = off;
+        off = align256(off + sizeof(int) * (tasks[k] / dl::kWaves + 1));
     }
     const size_t maxb = std::max({B.max_blocks[0], B.max_blocks[1], B.max_blocks[2]});
     B.partials = off;
@@ -161,23 +173,25 @@ const char *batch_validate(const dl_params *params, int n)
 }
 
 // Task and workgroup tables for rows_per_chunk R (0: the default choice):
-// the smallest power of two >= 4 with at most one resident round of sweep
-// waves, or one chunk per strip when even that is more.
+// the smallest power of two >= 16 with at most eight block entries per
+// resident workgroup, or one chunk per strip when even that is more (256
+// packets of 128^2..512^2, 2 resident workgroups per CU, ms per step:
+// R = 32 5.54, 64 5.58, 128 5.75).
 dl_status build_tables(dl_batch *b, int rows_per_chunk)
 {
     const int n = b->n;
     const std::vector<dl_params> &params = b->p;
     int R = rows_per_chunk;
     if (R <= 0) {
-        const int wr = std::min(dl::batch_waves_per_cu(1, b->mixed, b->py, b->terms), 8);
-        const size_t target = (size_t)wr * b->cus;
+        const size_t target = (size_t)8 * dl::kBatchWgsPerCu * b->cus;
         int max_ny = 0;
         for (int i = 0; i < n; ++i) max_ny = std::max(max_ny, params[i].ny);
-        R = 4;
+        R = 16;
         for (;;) {
-            size_t t = 0;
-            for (int i = 0; i < n; ++i) t += (size_t)strips(params[i].nx, 2) * ceil_div(params[i].ny, R);
-            if (t <= target || R >= max_ny) break;
+            size_t e = 0;
+            for (int i = 0; i < n; ++i)
+                e += ceil_div((size_t)strips(params[i].nx, 2) * ceil_div(params[i].ny, R), dl::kWaves);
+            if (e <= target || R >= max_ny) break;
             R *= 2;
         }
     }
@@ -222,29 +236,60 @@ dl_status build_tables(dl_batch *b, int rows_per_chunk)
             for (int l = 0; l < nb; ++l) blk[dl::kGridCombine].push_back(dl::BatchBlock{i, l, nb, first});
         }
     }
-    // The resident sweeps take entries in list order: longest marches first,
-    // so the short ones fill the tail.  An entry keeps its packet segment and
-    // index (partials slot and fold order), so the order changes no result.
+    // The entries of the resident sweeps are spread over the G resident
+    // workgroups by longest-processing-time-first: in order of decreasing cost
+    // (rows of the longest march plus a fixed cost per entry), each to the
+    // workgroup with the least total so far.  A workgroup runs its entries as
+    // one contiguous range of the list.  An entry keeps its packet segment and
+    // index (partials slot and fold order), so the assignment changes no
+    // result.
+    const int pwg = dl::kBatchWgsPerCu * b->cus;
+    std::vector<int> wgf[2];
     for (int k = 0; k < 2; ++k) {
         const int kind = k == 0 ? dl::kGridSweep : dl::kGridFirst;
         const size_t ne = blk[kind].size();
-        std::vector<int> rows(ne, 0), order(ne);
+        std::vector<long> cost(ne, 0);
+        std::vector<int> order(ne);
         for (size_t e = 0; e < ne; ++e) {
             order[e] = (int)e;
+            int rows = 0;
             for (int w = 0; w < dl::kWaves; ++w) {
                 const dl::BatchTask &t = task[k][e * dl::kWaves + w];
-                rows[e] = std::max(rows[e], t.y1 - t.y0);
+                rows = std::max(rows, t.y1 - t.y0);
             }
+            cost[e] = rows + DL_BATCH_ENTRY_ROWS;
         }
-        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return rows[x] > rows[y]; });
-        std::vector<dl::BatchBlock> nb(ne);
-        std::vector<dl::BatchTask> nt(task[k].size());
-        for (size_t e = 0; e < ne; ++e) {
-            nb[e] = blk[kind][order[e]];
-            for (int w = 0; w < dl::kWaves; ++w) nt[e * dl::kWaves + w] = task[k][(size_t)order[e] * dl::kWaves + w];
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+        const int G = (int)std::min<size_t>(ne, (size_t)pwg);
+        std::vector<long> load(G, 0);
+        std::vector<std::vector<int>> own(G);
+        // least-loaded workgroup, ties to the lowest index: a heap of (load, index)
+        std::vector<std::pair<long, int>> heap;
+        for (int g = 0; g < G; ++g) heap.push_back({0L, g});
+        auto later = [](const std::pair<long, int> &x, const std::pair<long, int> &y) { return x > y; };
+        std::make_heap(heap.begin(), heap.end(), later);
+        for (size_t i = 0; i < ne; ++i) {
+            std::pop_heap(heap.begin(), heap.end(), later);
+            auto &h = heap.back();
+            own[h.second].push_back(order[i]);
+            h.first += cost[order[i]];
+            std::push_heap(heap.begin(), heap.end(), later);
+        }
+        std::vector<dl::BatchBlock> nb;
+        std::vector<dl::BatchTask> nt;
+        nb.reserve(ne);
+        nt.reserve(task[k].size());
+        wgf[k].assign(1, 0);
+        for (int g = 0; g < G; ++g) {
+            for (int e : own[g]) {
+                nb.push_back(blk[kind][e]);
+                for (int w = 0; w < dl::kWaves; ++w) nt.push_back(task[k][(size_t)e * dl::kWaves + w]);
+            }
+            wgf[k].push_back((int)nb.size());
         }
         blk[kind].swap(nb);
         task[k].swap(nt);
+        b->nwg[k] = G;
     }
     for (int k = 0; k < dl::kGridKinds; ++k) {
         if (blk[k].size() > b->max_blocks[k]) return b->fail(DL_ERR_WORKSPACE, "batch tables exceed the workspace");
@@ -252,9 +297,12 @@ dl_status build_tables(dl_batch *b, int rows_per_chunk)
         DL_HIP(b, hipMemcpyAsync(b->d_blk[k], blk[k].data(), sizeof(dl::BatchBlock) * blk[k].size(),
                                  hipMemcpyHostToDevice, b->stream));
     }
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < 2; ++k) {
         DL_HIP(b, hipMemcpyAsync(b->d_task[k], task[k].data(), sizeof(dl::BatchTask) * task[k].size(),
                                  hipMemcpyHostToDevice, b->stream));
+        DL_HIP(b, hipMemcpyAsync(b->d_wgf[k], wgf[k].data(), sizeof(int) * wgf[k].size(), hipMemcpyHostToDevice,
+                                 b->stream));
+    }
     DL_HIP(b, hipStreamSynchronize(b->stream));
     return DL_OK;
 }
@@ -356,7 +404,10 @@ dl_status dirac_lanczos_batch_init(const dl_params *params, int32_t n_packets, v
         b->d_blk[k] = reinterpret_cast<dl::BatchBlock *>(b->ws + B.blk[k]);
         b->max_blocks[k] = B.max_blocks[k];
     }
-    for (int k = 0; k < 2; ++k) b->d_task[k] = reinterpret_cast<dl::BatchTask *>(b->ws + B.task[k]);
+    for (int k = 0; k < 2; ++k) {
+        b->d_task[k] = reinterpret_cast<dl::BatchTask *>(b->ws + B.task[k]);
+        b->d_wgf[k] = reinterpret_cast<int *>(b->ws + B.wgf[k]);
+    }
     b->partials = reinterpret_cast<double *>(b->ws + B.partials);
     b->fields = reinterpret_cast<double *>(b->ws + B.fields);
     b->stats = reinterpret_cast<dl::StepStat *>(b->ws + B.stats);
@@ -419,21 +470,23 @@ dl_status dirac_lanczos_batch_step(dl_batch *b, void *const *psi, double t0, dou
             a.step = j;
             a.parity = (s0 + j) & 1;
             a.pass = 1;
-            const int pwg = dl::kBatchWgsPerCu * b->cus;  // resident workgroups per launch
             a.blocks = b->d_blk[dl::kGridFirst];
             a.tasks = b->d_task[1];
+            a.wg_first = b->d_wgf[1];
             a.ntasks = b->nblk[dl::kGridFirst];
-            dl::launch_first_batch(a, std::min(a.ntasks, pwg), b->py, b->terms, st);
+            dl::launch_first_batch(a, b->nwg[1], b->py, b->terms, st);
             a.blocks = b->d_blk[dl::kGridSweep];
             a.tasks = b->d_task[0];
+            a.wg_first = b->d_wgf[0];
             a.ntasks = b->nblk[dl::kGridSweep];
             for (int p = 2; p <= m; ++p) {
                 a.pass = p;
-                dl::launch_recur_batch(a, std::min(a.ntasks, pwg), b->mixed, b->py, b->terms, st);
+                dl::launch_recur_batch(a, b->nwg[0], b->mixed, b->py, b->terms, st);
             }
             dl::launch_tridiag_batch(a, n, st);
             a.blocks = b->d_blk[dl::kGridCombine];
             a.tasks = nullptr;
+            a.wg_first = nullptr;
             dl::launch_combine_batch(a, b->nblk[dl::kGridCombine], b->mixed, st);
         }
         DL_HIP(b, hipGetLastError());

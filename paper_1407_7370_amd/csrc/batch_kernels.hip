@@ -26,16 +26,16 @@ __device__ __forceinline__ WaveTask batch_wave_task(const BatchArgs &b, int entr
     return w;
 }
 
-// Resident loop of the batched sweeps: workgroup g takes the block entries
-// g, g + G, g + 2G, ... (G workgroups, all resident).  The list holds the
-// longest marches first, so every workgroup starts with long entries and the
-// short ones even out the end.  The entry index is a scalar induction
-// variable: the loop and every branch around the barriers in `body` stay
-// wave-uniform.
+// Resident loop of the batched sweeps: workgroup g runs the block entries
+// wg_first[g] .. wg_first[g + 1] - 1, a list the host balanced over the
+// resident workgroups (longest first, each to the least loaded).  The entry
+// index is a scalar induction variable: the loop and every branch around the
+// barriers in `body` stay wave-uniform.
 template <class Body>
 __device__ __forceinline__ void resident_loop(const BatchArgs &b, Body body)
 {
-    for (int e = (int)blockIdx.x; e < b.ntasks; e += (int)gridDim.x) body(e);
+    const int e0 = b.wg_first[blockIdx.x], e1 = b.wg_first[blockIdx.x + 1];
+    for (int e = e0; e < e1; ++e) body(e);
 }
 
 template <int PF, bool PY, int TERMS>
@@ -185,13 +185,6 @@ void launch_combine_batch(const BatchArgs &b, int nblocks, bool mixed, hipStream
     else
         hipLaunchKernelGGL((k_combine_batch<double2, kCombFp64, kCombWpeFp64>), dim3(nblocks), dim3(kBlock), 0,
                            st, b);
-}
-
-int batch_waves_per_cu(int which, bool mixed, bool py, int terms)
-{
-    auto occ = [](auto kernel) { return waves_per_cu(kernel); };
-    if (which == 0) return dispatch_terms<PickFirstBatch>(py, terms, occ);
-    return with_kind<RecurPn, BatchRecur>(mixed, py, terms, occ);
 }
 
 void launch_reset_batch(const BatchPacket *pk, int n, hipStream_t st)

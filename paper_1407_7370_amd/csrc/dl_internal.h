@@ -233,15 +233,16 @@ struct BatchArgs {
     const BatchPacket *pk;
     const BatchBlock *blocks;  // of this launch's grid kind
     const BatchTask *tasks;    // kWaves per workgroup (sweeps and iteration 1)
+    const int *wg_first;       // resident workgroup g runs entries wg_first[g] .. wg_first[g + 1] - 1
     double *partials;          // kPartialStride doubles per workgroup
     int pass, m, step, parity; // step: index in the chunk tables; parity 1: the input is `state`
-    int ntasks;                // block entries of the sweeps (each workgroup loops over them)
+    int ntasks;                // block entries of the launch (spread over the resident workgroups)
 };
-// Resident workgroups per compute unit of the batched sweeps (the sweep's
-// occupancy; measured on the 256-packet batch, R = 256: 2 -> 7.54 ms,
-// 3 -> 6.79 ms, 4 and 6 -> 6.78 ms per step).
+// Resident workgroups per compute unit of the batched sweeps (measured on the
+// 256-packet batch with balanced entry lists, ms per step: 2 per CU 5.54-5.58
+// for R = 32..64, 3 per CU 5.63-5.91, 1 per CU 5.73-5.82).
 #ifndef DL_BATCH_WGS_PER_CU
-#define DL_BATCH_WGS_PER_CU 3
+#define DL_BATCH_WGS_PER_CU 2
 #endif
 constexpr int kBatchWgsPerCu = DL_BATCH_WGS_PER_CU;
 
@@ -251,7 +252,6 @@ void launch_tridiag_batch(const BatchArgs &b, int npackets, hipStream_t st);
 void launch_reset_batch(const BatchPacket *pk, int n, hipStream_t st);
 void launch_combine_batch(const BatchArgs &b, int nblocks, bool mixed, hipStream_t st);
 // Resident waves per compute unit of the batched kernels (0 first, 1 sweeps).
-int batch_waves_per_cu(int which, bool mixed, bool py, int terms);
 // Sites per recombination tile.
 int combine_tile_sites(bool mixed);
 

@@ -107,8 +107,11 @@ def test_batch_mixed_vs_single_and_oracle(torch_cuda, orc):
     say(f"batch mixed {len(probs)} packets {n} steps")
     outb, stb = run_batch(torch_cuda, probs, psi0, m, "mixed", dt, n)
     for i, p in enumerate(probs):
-        outs, _ = run_single(torch_cuda, p, psi0[i], m, "mixed", dt, n)
-        assert rel(outb[i], outs) <= 1e-8, i
+        outs, sts = run_single(torch_cuda, p, psi0[i], m, "mixed", dt, n)
+        # two mixed runs whose reductions are ordered differently (launch
+        # shapes) each lie within their own storage bound of the exact result
+        two = (stb[i]["cum_round_bound"][-1] + sts["cum_round_bound"][-1]) / np.linalg.norm(psi0[i]) + 1e-10
+        assert rel(outb[i], outs) <= two, i
         ref, rst = orc.propagate(p, psi0[i], 0.0, dt, n, m)
         tol = mixed_tolerance(stb[i], psi0[i], rst)
         err = rel(outb[i], ref)
@@ -173,8 +176,9 @@ def test_batch_256_packets_sampled(torch_cuda, orc):
     outb, stb = run_batch(torch, probs, psi0, m, "mixed", dt, n)
     assert all(np.all(s["k_eff"] == m) for s in stb)
     for i in (0, 1, 77, 128, 200, 255):
-        outs, _ = run_single(torch, probs[i], psi0[i], m, "mixed", dt, n)
-        assert rel(outb[i], outs) <= 1e-8, i
+        outs, sts = run_single(torch, probs[i], psi0[i], m, "mixed", dt, n)
+        two = (stb[i]["cum_round_bound"][-1] + sts["cum_round_bound"][-1]) / np.linalg.norm(psi0[i]) + 1e-10
+        assert rel(outb[i], outs) <= two, i
         ref, rst = orc.propagate(probs[i], psi0[i], 0.0, dt, n, m)
         tol = mixed_tolerance(stb[i], psi0[i], rst)
         err = rel(outb[i], ref)
