@@ -854,6 +854,45 @@ __device__ void bessel_miller(double R, int N, double *jb)
     sum += j;
     const double is = 1.0 / sum;
     for (int i = 0; i <= N; ++i) jb[i] *= is;
+    // the expansions read up to three orders past N, in groups of four
+    for (int i = N + 1; i <= N + 3; ++i) jb[i] = 0.0;
+}
+
+// Start order of Miller's recurrence for J_0 .. J_N (even, as in bessel_miller).
+__device__ __forceinline__ int miller_order(int N)
+{
+    const int M = N + 16 + (int)ceil(2.0 * sqrt((double)N));
+    return M + (M & 1);
+}
+
+// |J_n| / J_M grows by at most (2M + x)/x per order below M, so from
+// J_M = 1e-300 nothing can overflow while M log10((2M + x)/x) < 590.
+__device__ __forceinline__ bool miller_safe(double x, int M)
+{
+    return (double)M * log10((2.0 * M + x) / x) < 590.0;
+}
+
+// Miller's backward recurrence with no rescaling and no branch (x > 0, M even,
+// miller_safe(x, M)): J_M = 1e-300, J_{M+1} = 0, J_{n-1} = (2n/x) J_n -
+// J_{n+1}; put(n, v) receives the unnormalised J_n for n = M .. 0, and the
+// return value is the normalising factor 1 / (J_0 + 2 sum_k J_2k).
+template <class Put>
+__device__ __forceinline__ double miller_run(double x, int M, Put put)
+{
+    const double tx = 2.0 / x;
+    double jp1 = 0.0, j = 1e-300, se = 0.0, nd = (double)M;
+    for (int n = M; n >= 2; n -= 2) {
+        put(n, j);
+        se += j;  // even orders
+        const double jm1 = (nd * tx) * j - jp1;
+        put(n - 1, jm1);
+        const double jm2 = ((nd - 1.0) * tx) * jm1 - j;
+        jp1 = jm1;
+        j = jm2;
+        nd -= 2.0;
+    }
+    put(0, j);
+    return 1.0 / (j + 2.0 * se);
 }
 
 // This lane's component of exp(-iT') e_1 for the leading kd x kd block of
@@ -863,7 +902,9 @@ __device__ void bessel_miller(double R, int N, double *jb)
 // too wide for kChebMaxTerms terms.  Called by the whole wave.
 __device__ bool cheb_exp_e1(double d, double e, double em, int kd, int lane, double &cr, double &ci)
 {
-    __shared__ double jb[kChebMaxTerms + 1];
+    // Bessel values up to the start order of the recurrence (N + 47 at most)
+    __shared__ double jb[kChebMaxTerms + 48];
+    __shared__ double jscale;
     const double rad = fabs(e) + fabs(em);
     const double glo = wave_min(lane < kd ? d - rad : INFINITY);
     const double ghi = wave_max(lane < kd ? d + rad : -INFINITY);
@@ -872,30 +913,43 @@ __device__ bool cheb_exp_e1(double d, double e, double em, int kd, int lane, dou
     if (N > kChebMaxTerms) return false;
     __syncthreads();  // jb of a previous call is read up to here
     if (lane == 0) {
-        if (N > 0)
-            bessel_miller(R, N, jb);
-        else
+        double s = 1.0;
+        if (N > 0) {
+            const int M = miller_order(N);
+            if (miller_safe(R, M))
+                s = miller_run(R, M, [&](int n, double v) { jb[n] = v; });
+            else
+                bessel_miller(R, N, jb);  // rescaled as it goes, normalised
+        } else {
             jb[0] = 1.0;
+        }
+        jscale = s;
     }
     __syncthreads();
     // X = (T' - c0 I) / R on this lane's row (zero rows beyond kd)
     const double ir = N > 0 ? 1.0 / R : 0.0;
     const double xd = lane < kd ? (d - c0) * ir : 0.0, xe = e * ir, xem = em * ir;
+    auto xmul = [&](double v) { return xem * from_left(v) + xd * v + xe * from_right(v); };
+    const double s1 = jscale, s2 = 2.0 * s1;
     double tm = lane == 0 ? 1.0 : 0.0;  // T_0(X) e_1
-    double vr = jb[0] * tm, vi = 0.0;
-    double tc = xem * from_left(tm) + xd * tm + xe * from_right(tm);  // T_1(X) e_1
-    if (N >= 1) vi -= 2.0 * jb[1] * tc;
-    for (int n = 2; n <= N; ++n) {
-        const double tn = 2.0 * (xem * from_left(tc) + xd * tc + xe * from_right(tc)) - tm;
-        const double f = 2.0 * jb[n];
-        switch (n & 3) {
-        case 0: vr += f * tn; break;
-        case 1: vi -= f * tn; break;
-        case 2: vr -= f * tn; break;
-        default: vi += f * tn; break;
-        }
-        tm = tc;
-        tc = tn;
+    double vr = s1 * jb[0] * tm, vi = 0.0;
+    double tc = xmul(tm);  // T_1(X) e_1
+    if (N >= 1) vi -= s2 * jb[1] * tc;
+    // terms n .. n+3 with n = 2 mod 4: phases (-i)^n = -1, i, 1, -i; the
+    // last group runs up to three orders past N (more terms of the same
+    // expansion; T_n(X) e_1 stays bounded by 1)
+    for (int n = 2; n <= N; n += 4) {
+        const double f0 = s2 * jb[n], f1 = s2 * jb[n + 1], f2 = s2 * jb[n + 2], f3 = s2 * jb[n + 3];
+        const double t2 = 2.0 * xmul(tc) - tm;
+        const double t3 = 2.0 * xmul(t2) - tc;
+        const double t4 = 2.0 * xmul(t3) - t2;
+        const double t5 = 2.0 * xmul(t4) - t3;
+        vr -= f0 * t2;
+        vi += f1 * t3;
+        vr += f2 * t4;
+        vi -= f3 * t5;
+        tm = t4;
+        tc = t5;
     }
     double sn, cs;
     sincos(c0, &sn, &cs);
@@ -960,6 +1014,9 @@ __device__ void predict_k(const double *alpha, const double *gamma, Scalars *sc,
 constexpr int kBoundNodes = 48;
 constexpr int kBoundMaxTerms = 40;
 constexpr double kBoundMaxR = 40.0;
+// one node's Bessel values up to the recurrence's start order (at most 70),
+// an odd row length so the lanes' rows start on different LDS banks
+constexpr int kBoundRow = 73;
 
 // Gauss-Legendre node (on [0, 1], ascending in q) and weight of rule size n
 // for node q < n (Newton's method on P_n).
@@ -1002,7 +1059,8 @@ __device__ void gauss_legendre01(int n, int q, double &t, double &w)
 __device__ double storage_bound(double d, double e, double em, int k, int lane, double g1, double reps,
                                 double rabs)
 {
-    __shared__ double jtab[kBoundNodes][kBoundMaxTerms + 1];
+    __shared__ double jtab[kBoundNodes][kBoundRow];
+    __shared__ double jsc[kBoundNodes];
     __shared__ double tnode[kBoundNodes], wnode[kBoundNodes];
     if (!(reps > 0.0) && !(rabs > 0.0)) return 0.0;
     const double rad = fabs(e) + fabs(em);
@@ -1028,12 +1086,20 @@ __device__ double storage_bound(double d, double e, double em, int k, int lane, 
         // truncation below 1e-13
         const int N = xmax > 0.0 ? min((int)ceil(xmax + 4.0 * cbrt(xmax) + 8.0), kBoundMaxTerms) : 0;
         if (lane < nn) {
-            if (delta * R > 0.0) {
-                bessel_miller(delta * R, N, &jtab[lane][0]);
+            double *row = &jtab[lane][0];
+            const double x = delta * R;
+            double s = 1.0;
+            if (x > 0.0) {
+                const int M = miller_order(N);
+                if (miller_safe(x, M))
+                    s = miller_run(x, M, [&](int n, double v) { row[n] = v; });
+                else
+                    bessel_miller(x, N, row);  // rescaled as it goes, normalised
             } else {
-                jtab[lane][0] = 1.0;
-                for (int n = 1; n <= N; ++n) jtab[lane][n] = 0.0;
+                row[0] = 1.0;
+                for (int n = 1; n <= N + 3; ++n) row[n] = 0.0;
             }
+            jsc[lane] = s;
         }
         __syncthreads();
         const double ir = R > 0.0 ? 1.0 / R : 0.0;
@@ -1043,26 +1109,35 @@ __device__ double storage_bound(double d, double e, double em, int k, int lane, 
         for (int q = 0; q < nn; ++q) {
             // exp(-i dq (T - c0)) s = sum_n a_n T_n(X) s, a_0 = J_0, a_n = 2 (-i)^n J_n(dq R),
             // dq = t_q - t_{q-1}
+            const double s1 = jsc[q], s2 = 2.0 * s1;
+            const double *row = &jtab[q][0];
             double pr = sr, pi = si;                // T_{n-1}(X) s
             double cr = xmul(sr), ci = xmul(si);    // T_n(X) s
-            double ar = jtab[q][0] * sr, ai = jtab[q][0] * si;
+            double ar = s1 * row[0] * sr, ai = s1 * row[0] * si;
             if (N >= 1) {
-                ar += 2.0 * jtab[q][1] * ci;
-                ai -= 2.0 * jtab[q][1] * cr;
+                ar += s2 * row[1] * ci;
+                ai -= s2 * row[1] * cr;
             }
-            for (int n = 2; n <= N; ++n) {
-                const double nr = 2.0 * xmul(cr) - pr, ni = 2.0 * xmul(ci) - pi;
-                const double fj = 2.0 * jtab[q][n];
-                switch (n & 3) {
-                case 0: ar += fj * nr; ai += fj * ni; break;
-                case 1: ar += fj * ni; ai -= fj * nr; break;
-                case 2: ar -= fj * nr; ai -= fj * ni; break;
-                default: ar -= fj * ni; ai += fj * nr; break;
-                }
-                pr = cr;
-                pi = ci;
-                cr = nr;
-                ci = ni;
+            // orders n .. n+3 with n = 2 mod 4, phases -1, i, 1, -i (up to
+            // three orders past N: more terms of the same expansion)
+            for (int n = 2; n <= N; n += 4) {
+                const double f0 = s2 * row[n], f1 = s2 * row[n + 1], f2 = s2 * row[n + 2], f3 = s2 * row[n + 3];
+                const double t2r = 2.0 * xmul(cr) - pr, t2i = 2.0 * xmul(ci) - pi;
+                const double t3r = 2.0 * xmul(t2r) - cr, t3i = 2.0 * xmul(t2i) - ci;
+                const double t4r = 2.0 * xmul(t3r) - t2r, t4i = 2.0 * xmul(t3i) - t2i;
+                const double t5r = 2.0 * xmul(t4r) - t3r, t5i = 2.0 * xmul(t4i) - t3i;
+                ar -= f0 * t2r;
+                ai -= f0 * t2i;
+                ar -= f1 * t3i;
+                ai += f1 * t3r;
+                ar += f2 * t4r;
+                ai += f2 * t4i;
+                ar += f3 * t5i;
+                ai -= f3 * t5r;
+                pr = t4r;
+                pi = t4i;
+                cr = t5r;
+                ci = t5i;
             }
             sr = ar;
             si = ai;
