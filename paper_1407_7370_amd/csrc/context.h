@@ -133,7 +133,7 @@ struct dl_context {
     // tiles of recurrence sweep p (each sweep kind has its own occupancy)
     const dl::Tiles &tiles_pass(int p) const { return p == 2 ? tiles_p2 : (p == 3 ? tiles_p3 : tiles_recur); }
     int combine_blocks = 1024;       // recombination (narrow form) and second-run accumulation
-    bool combine_wide = false;       // recombination in the wide complex64 form
+    bool combine_wide = false;       // recombination in the wide form (more sites per thread)
     int combine_blocks_wide = 1024;  // its workgroups
     int sweep_waves = 8;  // waves per compute unit of the sweeps (launch shape)
     std::vector<double> host_fields;

@@ -360,7 +360,9 @@ void set_tiles(dl_context *ctx, int cap)
     ctx->tiles_p2 = dl::make_tiles(p.nx, p.ny, 2, w2 * ctx->cus * DL_RECUR_ROUNDS);
     ctx->tiles_p3 = dl::make_tiles(p.nx, p.ny, 2, w3 * ctx->cus * DL_RECUR_ROUNDS);
     ctx->tiles_apply = dl::make_tiles(p.nx, p.ny, 1, wa * ctx->cus);
-    ctx->combine_blocks = dl::combine_grid(vec_elems(p) / 2, mixed, ctx->cus, false);
+    // the accumulation of the second run takes the narrow complex64 form and
+    // the 8-site FP64 form
+    ctx->combine_blocks = dl::combine_grid(vec_elems(p) / 2, mixed, ctx->cus, !mixed);
     ctx->combine_wide = dl::combine_wide(vec_elems(p) / 2, mixed, ctx->cus);
     ctx->combine_blocks_wide = dl::combine_grid(vec_elems(p) / 2, mixed, ctx->cus, ctx->combine_wide);
 }

@@ -31,14 +31,19 @@ int sweep_terms(const Op &op) { return op_terms(op); }
 
 bool combine_wide(size_t sites, bool mixed, int cus)
 {
-    return mixed && sites >= (size_t)cus * kBlock * kCombMixedWide;
+    // complex64: the wide form from one wide tile per compute unit; FP64: the
+    // wide form (8 sites per thread) from four wide tiles per compute unit,
+    // below that two sites per thread, so that a small grid still spreads
+    // over every compute unit
+    return mixed ? sites >= (size_t)cus * kBlock * kCombMixedWide : sites >= (size_t)4 * cus * kBlock * kCombFp64;
 }
 
 int combine_grid(size_t sites, bool mixed, int cus, bool wide)
 {
     // a fixed number of workgroups per compute unit (four measured best for
     // the tiled stream), never more than there are tiles
-    const size_t tile = (size_t)kBlock * (wide ? kCombMixedWide : (mixed ? kCombMixed : kCombFp64));
+    const int S = mixed ? (wide ? kCombMixedWide : kCombMixed) : (wide ? kCombFp64 : kCombFp64Narrow);
+    const size_t tile = (size_t)kBlock * S;
     size_t nb = std::min<size_t>((size_t)DL_COMB_BLOCKS_PER_CU * cus, (sites + tile - 1) / tile);
     nb = std::max<size_t>(nb, 1);
     return (int)std::min<size_t>(nb, kMaxBlocks);
@@ -105,8 +110,11 @@ void launch_combine(const CombArgs &a, bool mixed, bool wide, int nblocks, hipSt
                            st, a);
     else if (mixed)
         hipLaunchKernelGGL((k_combine<float2, kCombMixed, kCombWpeMixed>), dim3(nblocks), dim3(kBlock), 0, st, a);
-    else
+    else if (wide)
         hipLaunchKernelGGL((k_combine<double2, kCombFp64, kCombWpeFp64>), dim3(nblocks), dim3(kBlock), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_combine<double2, kCombFp64Narrow, kCombWpeFp64Narrow>), dim3(nblocks), dim3(kBlock), 0,
+                           st, a);
 }
 
 void launch_accum(const AccumArgs &a, bool mixed, int nblocks, hipStream_t st)

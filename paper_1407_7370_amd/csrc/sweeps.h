@@ -1557,11 +1557,13 @@ constexpr int kCombMixed = DL_COMB_S_MIXED;
 constexpr int kCombMixedWide = DL_COMB_S_MIXED_WIDE;
 constexpr int kCombWpeMixedWide = 1;
 constexpr int kCombFp64 = 8;
+constexpr int kCombFp64Narrow = 2;  // FP64 grids below four wide tiles per compute unit
 #ifndef DL_COMB_WPE_MIXED
 #define DL_COMB_WPE_MIXED 4
 #endif
 constexpr int kCombWpeMixed = DL_COMB_WPE_MIXED;
 constexpr int kCombWpeFp64 = 1;
+constexpr int kCombWpeFp64Narrow = 4;
 
 // ---------------------------------------------------------------------------
 // y = H x (test hook; operator scale 1).
