@@ -83,7 +83,7 @@ __global__ __launch_bounds__(kBlock) void k_recur_batch(BatchArgs b)
         if (a.sc->kstop < p) return;
         const WaveTask wt = batch_wave_task(b, entry);
         double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        recur_body<V1, V2, TO, HAS2, PF, PY, TERMS>(a, wt, acc);
+        recur_body<V1, V2, TO, HAS2, PF, PY, TERMS>(a, wt, a.gamma[p - 1], a.alpha[p - 1], acc);
         double tot[5];
         if (!seg_reduce(acc, a.partials, &a.sc->ticket, bb.nblk, bb.local, tot)) return;
         if (threadIdx.x == 0) recur_tail(a, tot);

@@ -243,14 +243,16 @@ struct Engine {
 };
 
 // Iterations 1..m on `in` (sweeps; shift: run on A - alpha_1 I after iteration 1).
+// The last iteration's scalar update is left to run_finish unless `complete`
+// (then T is whole on return, and run_finish must be told it is).
 dl_status run_build(dl_context *ctx, const Engine &e, const dl::Op &op, const double2 *in,
-                    const double *field, double *partials, int shift);
+                    const double *field, double *partials, int shift, bool complete = false);
 // One whole step by the second Lanczos run (three rolling Krylov vectors).
 dl_status run_twice(dl_context *ctx, const Engine &e, const dl::Op &op, const double2 *in, double2 *out,
                     const double *field, dl::StepStat *stat, double *partials);
 // exp(-iT) and the recombination into `out` (stat receives k_eff, estimate, norm).
 dl_status run_finish(dl_context *ctx, const Engine &e, const double2 *in, double2 *out,
-                     dl::StepStat *stat, double *partials);
+                     dl::StepStat *stat, double *partials, bool folded = false);
 
 // Default launch shapes of a context's sweeps and recombination (ctx->p and
 // ctx->cus set).

@@ -20,6 +20,77 @@ __device__ __forceinline__ void wave_sum(double (&v)[NV])
         for (int k = 0; k < NV; ++k) v[k] += __shfl_xor(v[k], s, 64);
 }
 
+// This workgroup's partial: the wave sums, then the waves in order (thread 0
+// ends with the partial in s).
+template <int NV>
+__device__ __forceinline__ void block_partial(double (&v)[NV], double (&red)[kWaves][NV], double (&s)[NV])
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    wave_sum(v);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) red[w][k] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double a = red[0][k];
+        for (int i = 1; i < kWaves; ++i) a += red[i][k];
+        s[k] = a;
+    }
+}
+
+// The totals of partials[0 .. nblk) folded by the whole workgroup in a fixed
+// order (thread t sums partials t, t + kBlock, ...; then the wave sums and
+// the waves in order); every thread ends with them.  Device-scope loads: the
+// partials may come from other XCDs within this kernel.
+template <int NV>
+__device__ __forceinline__ void fold_partials(const double *partials, int nblk, double (&red)[kWaves][NV],
+                                              double (&tot)[NV])
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double s[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) s[k] = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kBlock)
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+            s[k] += __hip_atomic_load(&partials[(size_t)b * kPartialStride + k], __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+    wave_sum(s);
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) red[w][k] = s[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double a = red[0][k];
+        for (int i = 1; i < kWaves; ++i) a += red[i][k];
+        tot[k] = a;
+    }
+}
+
+// The same fold by a single wave (each of the kWaves thread groups of the
+// workgroup fold in turn), bit for bit the totals of fold_partials.
+template <int NV>
+__device__ __forceinline__ void fold_partials_wave(const double *partials, int nblk, double (&tot)[NV])
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) tot[k] = 0.0;
+    for (int w = 0; w < kWaves; ++w) {
+        double s[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) s[k] = 0.0;
+        for (int b = w * 64 + lane; b < nblk; b += kBlock)
+#pragma unroll
+            for (int k = 0; k < NV; ++k) s[k] += partials[(size_t)b * kPartialStride + k];
+        wave_sum(s);
+#pragma unroll
+        for (int k = 0; k < NV; ++k) tot[k] = w == 0 ? s[k] : tot[k] + s[k];
+    }
+}
+
 // Fold the per-lane sums of a segment of `nblk` workgroups (this one is number
 // `blk` of the segment) in a fixed order: per-workgroup partials in
 // partials[0 .. nblk), a ticket counting the finished workgroups.  Returns true
@@ -43,20 +114,13 @@ __device__ bool seg_reduce(double (&v)[NV], double *partials, unsigned int *tick
     static_assert(NV <= kPartialStride, "partial table stride");
     __shared__ double red[kWaves][NV];
     __shared__ int last;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    wave_sum(v);
-    if (lane == 0)
-#pragma unroll
-        for (int k = 0; k < NV; ++k) red[w][k] = v[k];
-    __syncthreads();
+    double s[NV];
+    block_partial(v, red, s);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            double s = red[0][k];
-            for (int i = 1; i < kWaves; ++i) s += red[i][k];
-            __hip_atomic_store(&partials[(size_t)blk * kPartialStride + k], s, __ATOMIC_RELAXED,
+        for (int k = 0; k < NV; ++k)
+            __hip_atomic_store(&partials[(size_t)blk * kPartialStride + k], s[k], __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
-        }
         // the partials' stores complete before the ticket is taken
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         const unsigned int t = atomicAdd(ticket, 1u);
@@ -66,28 +130,22 @@ __device__ bool seg_reduce(double (&v)[NV], double *partials, unsigned int *tick
     // `last` is the same in every thread; a scalar copy keeps the branch (and
     // the barriers of callers that loop over this) wave-uniform
     if (!__builtin_amdgcn_readfirstlane(last)) return false;
-    double s[NV];
-#pragma unroll
-    for (int k = 0; k < NV; ++k) s[k] = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += kBlock)
-#pragma unroll
-        for (int k = 0; k < NV; ++k)
-            s[k] += __hip_atomic_load(&partials[(size_t)b * kPartialStride + k], __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_AGENT);
-    wave_sum(s);
-    __syncthreads();
-    if (lane == 0)
-#pragma unroll
-        for (int k = 0; k < NV; ++k) red[w][k] = s[k];
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        double a = red[0][k];
-        for (int i = 1; i < kWaves; ++i) a += red[i][k];
-        tot[k] = a;
-    }
+    fold_partials(partials, nblk, red, tot);
     if (threadIdx.x == 0) *ticket = 0u;
     return true;
+}
+
+// This workgroup's partial stored for a fold by the next kernel (no ticket).
+template <int NV>
+__device__ __forceinline__ void store_partial(double (&v)[NV], double *partials, int blk)
+{
+    static_assert(NV <= kPartialStride, "partial table stride");
+    __shared__ double red[kWaves][NV];
+    double s[NV];
+    block_partial(v, red, s);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) partials[(size_t)blk * kPartialStride + k] = s[k];
 }
 
 // The whole grid as one segment.

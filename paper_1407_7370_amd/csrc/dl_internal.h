@@ -100,6 +100,20 @@ struct PassArgs {
     int pass;
     int m;
     int replay;          // 1: recompute u_p only (second Lanczos run), no reductions or scalar updates
+    // 1: this iteration's partials are folded by the next kernel, and (p >= 3)
+    // this kernel folds those of iteration p-1 from prev_partials (prev_nblk
+    // workgroups) before its march
+    int defer;
+    const double *prev_partials;
+    int prev_nblk;
+};
+
+// The last iteration's partials, folded by the small exponential's kernel
+// (pass 0: nothing to fold).
+struct TailFold {
+    const double *partials;
+    int nblk;
+    int pass;
 };
 
 // Arguments of the recombination psi_new = sum_j coef_j u_j (flat streaming).
@@ -180,8 +194,10 @@ void launch_first(const Op &op, const Tiles &t, const double2 *psi, const double
 void launch_recur(const PassArgs &a, bool mixed, hipStream_t st);
 // reps, rabs: relative and absolute rounding of one stored Krylov vector
 // (kStoreEps32 and kStoreTiny32 * sqrt(4 * sites) in mixed precision, 0 in FP64)
-void launch_tridiag(const double *alpha, const double *gamma, Scalars *sc, StepStat *stat, double reps,
-                    double rabs, hipStream_t st);
+void launch_tridiag(double *alpha, double *gamma, Scalars *sc, StepStat *stat, double reps, double rabs,
+                    const TailFold &fold, hipStream_t st);
+// the last iteration's scalar update from the partials it left (TailFold)
+void launch_fold_tail(double *alpha, double *gamma, Scalars *sc, const TailFold &fold, hipStream_t st);
 // wide: the complex64 form with 16 sites per thread (see combine_wide)
 void launch_combine(const CombArgs &a, bool mixed, bool wide, int nblocks, hipStream_t st);
 void launch_apply(const Op &op, const Tiles &t, const double2 *x, double2 *y, double gxh,

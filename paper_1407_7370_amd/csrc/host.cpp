@@ -176,8 +176,17 @@ void pulse_average(const dl_params &p, CoefView coef, double t0, double dt, doub
     a[1] /= std::fabs(dt);
 }
 
+namespace {
+// The sweeps of a step alternate between the two halves of the partials table:
+// iteration p writes half p mod 2 while the next kernel folds it.
+double *partials_half(double *partials, int p)
+{
+    return partials + (size_t)(p & 1) * (size_t)(kMaxBlocks / 2) * dl::kPartialStride;
+}
+}  // namespace
+
 dl_status run_build(dl_context *ctx, const Engine &e, const dl::Op &op, const double2 *in,
-                    const double *field, double *partials, int shift)
+                    const double *field, double *partials, int shift, bool complete)
 {
     hipStream_t st = ctx->stream;
     DL_HIP(ctx, ctx->timed(0, [&] {
@@ -194,11 +203,19 @@ dl_status run_build(dl_context *ctx, const Engine &e, const dl::Op &op, const do
         a.alpha = e.alpha;
         a.gamma = e.gamma;
         a.sc = e.sc;
-        a.partials = partials;
+        a.partials = partials_half(partials, pp);
         a.pass = pp;
         a.m = e.m;
+        a.defer = 1;
+        if (pp >= 3) {
+            a.prev_partials = partials_half(partials, pp - 1);
+            a.prev_nblk = ctx->tiles_pass(pp - 1).nblocks;
+        }
         DL_HIP(ctx, ctx->timed(pp >= 4 ? 1 : 2, [&] { dl::launch_recur(a, e.mixed, st); }));
     }
+    if (complete && e.m >= 2)
+        dl::launch_fold_tail(e.alpha, e.gamma, e.sc,
+                             dl::TailFold{partials_half(partials, e.m), ctx->tiles_pass(e.m).nblocks, e.m}, st);
     return DL_OK;
 }
 
@@ -234,7 +251,9 @@ dl_status run_twice(dl_context *ctx, const Engine &e, const dl::Op &op, const do
     for (int pp = 2; pp <= e.m; ++pp) DL_HIP(ctx, pass(pp, 0));
     double reps, rabs;
     store_rounding(ctx->p, reps, rabs);
-    DL_HIP(ctx, ctx->timed(3, [&] { dl::launch_tridiag(e.alpha, e.gamma, e.sc, stat, reps, rabs, st); }));
+    DL_HIP(ctx, ctx->timed(3, [&] {
+        dl::launch_tridiag(e.alpha, e.gamma, e.sc, stat, reps, rabs, dl::TailFold{nullptr, 0, 0}, st);
+    }));
     dl::AccumArgs c{};
     c.psi = in;
     c.sites = vec_elems(ctx->p) / 2;
@@ -266,12 +285,15 @@ dl_status run_twice(dl_context *ctx, const Engine &e, const dl::Op &op, const do
 }
 
 dl_status run_finish(dl_context *ctx, const Engine &e, const double2 *in, double2 *out,
-                     dl::StepStat *stat, double *partials)
+                     dl::StepStat *stat, double *partials, bool folded)
 {
     hipStream_t st = ctx->stream;
     double reps, rabs;
     store_rounding(ctx->p, reps, rabs);
-    DL_HIP(ctx, ctx->timed(3, [&] { dl::launch_tridiag(e.alpha, e.gamma, e.sc, stat, reps, rabs, st); }));
+    // the last iteration's partials (run_build leaves them for this kernel)
+    const dl::TailFold fold{partials_half(partials, e.m), ctx->tiles_pass(e.m).nblocks,
+                            (e.m >= 2 && !folded) ? e.m : 0};
+    DL_HIP(ctx, ctx->timed(3, [&] { dl::launch_tridiag(e.alpha, e.gamma, e.sc, stat, reps, rabs, fold, st); }));
     dl::CombArgs r{};
     r.psi = in;
     r.basis = e.basis;

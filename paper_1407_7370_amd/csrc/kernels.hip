@@ -97,10 +97,15 @@ void launch_recur(const PassArgs &a, bool mixed, hipStream_t st)
         with_kind<RecurPn, SingleRecur>(mixed, py, terms, go);
 }
 
-void launch_tridiag(const double *alpha, const double *gamma, Scalars *sc, StepStat *stat, double reps,
-                    double rabs, hipStream_t st)
+void launch_tridiag(double *alpha, double *gamma, Scalars *sc, StepStat *stat, double reps, double rabs,
+                    const TailFold &fold, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(64), 0, st, alpha, gamma, sc, stat, reps, rabs);
+    hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(64), 0, st, alpha, gamma, sc, stat, reps, rabs, fold);
+}
+
+void launch_fold_tail(double *alpha, double *gamma, Scalars *sc, const TailFold &fold, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fold_tail, dim3(1), dim3(64), 0, st, alpha, gamma, sc, fold);
 }
 
 void launch_combine(const CombArgs &a, bool mixed, bool wide, int nblocks, hipStream_t st)

@@ -615,7 +615,8 @@ __global__ __launch_bounds__(kBlock) void k_first(Op op, Tiles t, const double2 
 // Re<u_p, A u_p>, Re<u_p, u_(p-1)> and, in the last iteration, ||A u_p||^2 and
 // Re<A u_p, u_(p-1)> of its owned sites).
 template <class V1, class V2, class TO, bool HAS2, int PF, bool PY, int TERMS>
-__device__ __forceinline__ void recur_body(const PassArgs &a, const WaveTask &wt, double (&acc)[5])
+__device__ __forceinline__ void recur_body(const PassArgs &a, const WaveTask &wt, double g1, double alpha_pm1,
+                                           double (&acc)[5])
 {
     // rows are marched U at a time so that every ring and FIFO slot index is a
     // compile-time constant; the rings hold four rows (slot = row mod 4)
@@ -628,9 +629,8 @@ __device__ __forceinline__ void recur_body(const PassArgs &a, const WaveTask &wt
     const Op &op = a.op;
     const int ny = op.ny;
     const int lane = threadIdx.x & 63;
-    const double g1 = a.gamma[p - 1];
     const double inv_g1 = 1.0 / g1;
-    const double ca = a.alpha[p - 1] * inv_g1;
+    const double ca = alpha_pm1 * inv_g1;
     const double cb = HAS2 ? g1 / a.gamma[p - 2] : 0.0;
     const double sig = sc->sigma;
     const double gxh = a.field[0], gyh = a.field[1];
@@ -747,53 +747,115 @@ __device__ __forceinline__ void recur_body(const PassArgs &a, const WaveTask &wt
     }
 }
 
-// Scalar update of iteration p from the grid totals (one thread).
-__device__ __forceinline__ void recur_tail(const PassArgs &a, const double (&tot)[5])
+// Scalar update of iteration p from the grid totals: evaluated from the
+// scalars of the iterations before p (the same in every thread that calls
+// it), then stored by one thread.
+struct RecurTail {
+    bool fail;       // a non-finite total: the call is aborted
+    bool breakdown;  // invariant Krylov subspace: k_eff = p - 1
+    bool last;       // p is the last iteration of the step
+    double gp;       // gamma_p = beta_{p-1}
+    double al;       // alpha_p
+    double scale;    // running scale of the breakdown test
+    double beta_k;   // beta_k of the step (last iteration or breakdown)
+};
+
+__device__ __forceinline__ RecurTail recur_tail_eval(const Scalars *sc, const double *alpha, const double *gamma,
+                                                     int p, int m, const double (&tot)[5])
 {
-    Scalars *sc = a.sc;
-    const int p = a.pass;
-    const bool last = (p == a.m) || (p == sc->kstop);
-    const double g1 = a.gamma[p - 1];
+    RecurTail o{};
+    o.last = (p == m) || (p == sc->kstop);
+    const double g1 = gamma[p - 1];
     const double sig = sc->sigma;
-    const double n = tot[0], an = tot[1], o = tot[2], yy = tot[3], yv = tot[4];
-    if (!isfinite(n) || !isfinite(an) || !isfinite(o) || !isfinite(yy) || !isfinite(yv)) {
+    const double n = tot[0], an = tot[1], ov = tot[2], yy = tot[3], yv = tot[4];
+    if (!isfinite(n) || !isfinite(an) || !isfinite(ov) || !isfinite(yy) || !isfinite(yv)) {
+        o.fail = true;
+        return o;
+    }
+    const double gp = sqrt(n);  // beta_{p-1}
+    o.gp = gp;
+    // breakdown scale on the unshifted alpha (the reading shared with the oracle)
+    const double scale = fmax(sc->scale, fabs(alpha[p - 1] + sig));
+    if (gp <= 1e-13 * scale) {
+        // invariant Krylov subspace: stop with k_eff = p - 1, beta_k = gamma_p
+        o.breakdown = true;
+        o.beta_k = gp;
+        return o;
+    }
+    o.scale = fmax(scale, gp);
+    const double al = an / n - ov / g1;
+    o.al = al;
+    if (o.last) {
+        // w = A u_m - alpha_m u_m - (gamma_m^2/gamma_{m-1}) u_{m-1} = gamma_m u_{m+1}
+        const double bp = n / g1;
+        const double w2 = yy + al * al * n + bp * bp * (g1 * g1) - 2.0 * al * an - 2.0 * bp * yv +
+                          2.0 * al * bp * ov;
+        o.beta_k = sqrt(fmax(w2, 0.0)) / gp;
+    }
+    return o;
+}
+
+__device__ __forceinline__ void recur_tail_store(Scalars *sc, double *alpha, double *gamma, int p,
+                                                 const RecurTail &o)
+{
+    if (o.fail) {
         sc->status = 3;
         sc->kstop = -1;
         return;
     }
-    const double gp = sqrt(n);  // beta_{p-1}
-    // breakdown scale on the unshifted alpha (the reading shared with the oracle)
-    const double scale = fmax(sc->scale, fabs(a.alpha[p - 1] + sig));
-    a.gamma[p] = gp;
-    if (gp <= 1e-13 * scale) {
-        // invariant Krylov subspace: stop with k_eff = p - 1, beta_k = gamma_p
+    gamma[p] = o.gp;
+    if (o.breakdown) {
         sc->keff = p - 1;
         sc->kstop = p - 1;
-        sc->beta_k = gp;
+        sc->beta_k = o.beta_k;
         return;
     }
-    sc->scale = fmax(scale, gp);
-    const double al = an / n - o / g1;
-    a.alpha[p] = al;
-    if (last) {
-        // w = A u_m - alpha_m u_m - (gamma_m^2/gamma_{m-1}) u_{m-1} = gamma_m u_{m+1}
-        const double bp = n / g1;
-        const double w2 = yy + al * al * n + bp * bp * (g1 * g1) - 2.0 * al * an - 2.0 * bp * yv +
-                          2.0 * al * bp * o;
-        sc->beta_k = sqrt(fmax(w2, 0.0)) / gp;
-    }
+    sc->scale = o.scale;
+    alpha[p] = o.al;
+    if (o.last) sc->beta_k = o.beta_k;
+}
+
+__device__ __forceinline__ void recur_tail(const PassArgs &a, const double (&tot)[5])
+{
+    recur_tail_store(a.sc, a.alpha, a.gamma, a.pass, recur_tail_eval(a.sc, a.alpha, a.gamma, a.pass, a.m, tot));
 }
 
 template <class V1, class V2, class TO, bool HAS2, int PF, bool PY, int TERMS>
 __global__ __launch_bounds__(kBlock) void k_recur(PassArgs a)
 {
-    if (a.sc->kstop < a.pass) return;
+    Scalars *sc = a.sc;
+    const int p = a.pass;
+    double g1, alpha_pm1;
+    if (a.defer && p >= 3) {
+        // iteration p-1 left its partials for this kernel: every workgroup
+        // folds them in the same order (so all agree bit for bit), takes the
+        // scalars of p-1 from its own evaluation and workgroup 0 stores them
+        // (iteration p-1 did not run when kstop < p-1)
+        if (sc->kstop < p - 1) return;
+        __shared__ double red[kWaves][5];
+        double tot[5];
+        fold_partials(a.prev_partials, a.prev_nblk, red, tot);
+        const RecurTail o = recur_tail_eval(sc, a.alpha, a.gamma, p - 1, a.m, tot);
+        if (blockIdx.x == 0 && threadIdx.x == 0) recur_tail_store(sc, a.alpha, a.gamma, p - 1, o);
+        if (o.fail || o.breakdown || o.last) return;  // kstop < p from here on
+        g1 = o.gp;
+        alpha_pm1 = o.al;
+    } else {
+        if (sc->kstop < p) return;
+        g1 = a.gamma[p - 1];
+        alpha_pm1 = a.alpha[p - 1];
+    }
     const WaveTask wt = wave_task(a.op, a.t);
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    recur_body<V1, V2, TO, HAS2, PF, PY, TERMS>(a, wt, acc);
+    recur_body<V1, V2, TO, HAS2, PF, PY, TERMS>(a, wt, g1, alpha_pm1, acc);
     if (a.replay) return;  // the second run only regenerates u_p
+    if (a.defer) {
+        // folded by the next iteration's kernel (or the small exponential's)
+        store_partial(acc, a.partials, (int)blockIdx.x);
+        return;
+    }
     double tot[5];
-    if (!grid_reduce(acc, a.partials, &a.sc->ticket, tot)) return;
+    if (!grid_reduce(acc, a.partials, &sc->ticket, tot)) return;
     if (threadIdx.x == 0) recur_tail(a, tot);
 }
 
@@ -1300,10 +1362,32 @@ __device__ __forceinline__ void tridiag_body(const double *alpha, const double *
     if (ktol > 0.0) predict_k(alpha, gamma, sc, k, lane, beta_k * __shfl(ck, k - 1, 64));
 }
 
-__global__ __launch_bounds__(64) void k_tridiag(const double *alpha, const double *gamma, Scalars *sc,
-                                                StepStat *stat, double reps, double rabs)
+// The scalar update of the step's last iteration from the partials it left
+// for the next kernel (one wave; iteration f.pass ran when kstop >= f.pass).
+__device__ __forceinline__ void fold_last_tail(double *alpha, double *gamma, Scalars *sc, const TailFold &f)
 {
+    if (f.pass >= 2 && sc->status == 0 && sc->kstop >= f.pass) {
+        double tot[5];
+        fold_partials_wave(f.partials, f.nblk, tot);
+        const RecurTail o = recur_tail_eval(sc, alpha, gamma, f.pass, f.pass, tot);
+        if (threadIdx.x == 0) recur_tail_store(sc, alpha, gamma, f.pass, o);
+        __threadfence_block();
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(64) void k_tridiag(double *alpha, double *gamma, Scalars *sc, StepStat *stat,
+                                                double reps, double rabs, TailFold f)
+{
+    fold_last_tail(alpha, gamma, sc, f);
     tridiag_body(alpha, gamma, sc, stat, reps, rabs);
+}
+
+// The last iteration's scalar update alone, for callers that need the whole
+// tridiagonal T before the small exponential runs.
+__global__ __launch_bounds__(64) void k_fold_tail(double *alpha, double *gamma, Scalars *sc, TailFold f)
+{
+    fold_last_tail(alpha, gamma, sc, f);
 }
 
 // ---------------------------------------------------------------------------
