@@ -280,17 +280,16 @@ dl_status dirac_lanczos_adjoint(dl_context *ctx, const void *psi0_v, double t0, 
         for (int i = 0; i < len; ++i) {
             const double *fp = fields + 4 * (size_t)(g * C + i);
             const Engine ei = step_engine(i);
-            // T whole before the copy below (complete: the last iteration's
-            // scalars are not left to the small exponential)
-            const dl_status sb = run_build(ctx, ei, opf, seg(i), fp, partials, 1, true);
+            const dl_status sb = run_build(ctx, ei, opf, seg(i), fp, partials, 1);
             if (sb != DL_OK) return sb;
+            const dl_status sf = run_finish(ctx, ei, seg(i), seg(i + 1), dstat, partials);
+            if (sf != DL_OK) return sf;
             if (A.keep) {
                 // what the backward contraction reads of this step: k_eff, shift,
-                // status, alpha and gamma (the small exponential leaves them alone)
+                // status, alpha and gamma, whole once the small exponential has
+                // folded the last iteration (the recombination leaves them alone)
                 dl::launch_keep_step(ep.sc, ep.alpha, ep.gamma, m + 3, kept_scal(i), A.ks_alpha, A.ks_gamma, st);
             }
-            const dl_status sf = run_finish(ctx, ei, seg(i), seg(i + 1), dstat, partials, true);
-            if (sf != DL_OK) return sf;
         }
         DL_HIP(ctx, hipGetLastError());
         return DL_OK;
@@ -349,8 +348,12 @@ dl_status dirac_lanczos_adjoint(dl_context *ctx, const void *psi0_v, double t0, 
                 s = run_build(ctx, ei, opf, seg(i), fields + 4 * ns, partials, 1, true);
                 if (s != DL_OK) return s;
             }
-            // both tridiagonals whole before the contraction reads them
-            s = run_build(ctx, el, opb, lam(cur), fields + 4 * ns + 2, partials, 1, true);
+            // the backward step first: its small exponential completes T of the
+            // lambda basis, and the recombination leaves the basis and lam(cur)
+            // for the contraction below
+            s = run_build(ctx, el, opb, lam(cur), fields + 4 * ns + 2, partials, 1);
+            if (s != DL_OK) return s;
+            s = run_finish(ctx, el, lam(cur), lam(1 - cur), dstat, partials);
             if (s != DL_OK) return s;
             dl::ContractArgs ca{};
             ca.lam1 = lam(cur);
@@ -375,8 +378,6 @@ dl_status dirac_lanczos_adjoint(dl_context *ctx, const void *psi0_v, double t0, 
             ca.partials = cpart;
             ca.rec = rec + (size_t)i * dl::kRecLen;
             dl::launch_contract(ca, ncb, st);
-            s = run_finish(ctx, el, lam(cur), lam(1 - cur), dstat, partials, true);
-            if (s != DL_OK) return s;
             cur = 1 - cur;
         }
         DL_HIP(ctx, hipGetLastError());
