@@ -142,7 +142,7 @@ struct dl_context {
     // event timing (dirac_lanczos_timing)
     bool timing = false;
     std::vector<hipEvent_t> ev0, ev1;
-    std::vector<int> ev_cls;
+    std::vector<int> ev_cls, ev_cnt;  // class and number of launches of each event pair
     size_t ev_used = 0;
     int64_t t_launches[5] = {0, 0, 0, 0, 0};
     double t_ms[5] = {0, 0, 0, 0, 0};
@@ -178,15 +178,16 @@ struct dl_context {
             e = hipEventElapsedTime(&ms, ev0[i], ev1[i]);
             if (e != hipSuccess) return e;
             t_ms[ev_cls[i]] += ms;
-            t_launches[ev_cls[i]] += 1;
+            t_launches[ev_cls[i]] += ev_cnt[i];
         }
         ev_used = 0;
         return hipSuccess;
     }
 
-    // Launch `fn` bracketed by an event pair when timing is on.
+    // Launch `fn` (`count` launches of class cls, back to back) bracketed by
+    // an event pair when timing is on.
     template <class F>
-    hipError_t timed(int cls, F &&fn)
+    hipError_t timed(int cls, F &&fn, int count = 1)
     {
         if (!timing) {
             fn();
@@ -201,7 +202,8 @@ struct dl_context {
         fn();
         e = hipEventRecord(ev1[ev_used], stream);
         if (e != hipSuccess) return e;
-        ev_cls[ev_used++] = cls;
+        ev_cls[ev_used] = cls;
+        ev_cnt[ev_used++] = count;
         return hipSuccess;
     }
 

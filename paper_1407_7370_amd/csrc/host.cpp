@@ -192,7 +192,7 @@ dl_status run_build(dl_context *ctx, const Engine &e, const dl::Op &op, const do
     DL_HIP(ctx, ctx->timed(0, [&] {
         dl::launch_first(op, ctx->tiles_first, in, field, e.alpha, e.gamma, e.sc, partials, e.m, shift, st);
     }));
-    for (int pp = 2; pp <= e.m; ++pp) {
+    auto launch = [&](int pp) {
         dl::PassArgs a{};
         a.op = op;
         a.t = ctx->tiles_pass(pp);
@@ -211,8 +211,15 @@ dl_status run_build(dl_context *ctx, const Engine &e, const dl::Op &op, const do
             a.prev_partials = partials_half(partials, pp - 1);
             a.prev_nblk = ctx->tiles_pass(pp - 1).nblocks;
         }
-        DL_HIP(ctx, ctx->timed(pp >= 4 ? 1 : 2, [&] { dl::launch_recur(a, e.mixed, st); }));
-    }
+        dl::launch_recur(a, e.mixed, st);
+    };
+    for (int pp = 2; pp <= std::min(e.m, 3); ++pp) DL_HIP(ctx, ctx->timed(2, [&] { launch(pp); }));
+    // iterations 4..m back to back, timed as one block (an event pair per
+    // launch would sit between the kernels)
+    if (e.m >= 4)
+        DL_HIP(ctx, ctx->timed(1, [&] {
+            for (int pp = 4; pp <= e.m; ++pp) launch(pp);
+        }, e.m - 3));
     if (complete && e.m >= 2)
         dl::launch_fold_tail(e.alpha, e.gamma, e.sc,
                              dl::TailFold{partials_half(partials, e.m), ctx->tiles_pass(e.m).nblocks, e.m}, st);
@@ -847,6 +854,7 @@ dl_status dirac_lanczos_timing(dl_context *ctx, int32_t enable, dl_timing *out)
             ctx->ev0.resize(n);
             ctx->ev1.resize(n);
             ctx->ev_cls.resize(n);
+            ctx->ev_cnt.resize(n);
             for (size_t i = 0; i < n; ++i) {
                 DL_HIP(ctx, hipEventCreate(&ctx->ev0[i]));
                 DL_HIP(ctx, hipEventCreate(&ctx->ev1[i]));
