@@ -71,23 +71,44 @@ __device__ __forceinline__ void fold_partials(const double *partials, int nblk, 
 }
 
 // The same fold by a single wave (each of the kWaves thread groups of the
-// workgroup fold in turn), bit for bit the totals of fold_partials.
+// workgroup fold in turn), bit for bit the totals of fold_partials.  With at
+// most kBlock partials every group's loads are issued before any sum waits.
 template <int NV>
 __device__ __forceinline__ void fold_partials_wave(const double *partials, int nblk, double (&tot)[NV])
 {
     const int lane = threadIdx.x & 63;
+    double s[kWaves][NV];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) tot[k] = 0.0;
-    for (int w = 0; w < kWaves; ++w) {
-        double s[NV];
+    for (int w = 0; w < kWaves; ++w)
 #pragma unroll
-        for (int k = 0; k < NV; ++k) s[k] = 0.0;
-        for (int b = w * 64 + lane; b < nblk; b += kBlock)
+        for (int k = 0; k < NV; ++k) s[w][k] = 0.0;
+    if (nblk <= kBlock) {
+        double v[kWaves][NV];
 #pragma unroll
-            for (int k = 0; k < NV; ++k) s[k] += partials[(size_t)b * kPartialStride + k];
-        wave_sum(s);
+        for (int w = 0; w < kWaves; ++w) {
+            const int b = w * 64 + lane;
 #pragma unroll
-        for (int k = 0; k < NV; ++k) tot[k] = w == 0 ? s[k] : tot[k] + s[k];
+            for (int k = 0; k < NV; ++k) v[w][k] = b < nblk ? partials[(size_t)b * kPartialStride + k] : 0.0;
+        }
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w)
+#pragma unroll
+            for (int k = 0; k < NV; ++k)
+                if (w * 64 + lane < nblk) s[w][k] += v[w][k];
+    } else {
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w)
+            for (int b = w * 64 + lane; b < nblk; b += kBlock)
+#pragma unroll
+                for (int k = 0; k < NV; ++k) s[w][k] += partials[(size_t)b * kPartialStride + k];
+    }
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) wave_sum(s[w]);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double a = s[0][k];
+        for (int w = 1; w < kWaves; ++w) a += s[w][k];
+        tot[k] = a;
     }
 }
 

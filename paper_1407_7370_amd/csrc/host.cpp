@@ -192,6 +192,10 @@ dl_status run_build(dl_context *ctx, const Engine &e, const dl::Op &op, const do
     DL_HIP(ctx, ctx->timed(0, [&] {
         dl::launch_first(op, ctx->tiles_first, in, field, e.alpha, e.gamma, e.sc, partials, e.m, shift, st);
     }));
+    // each half of the partials table holds one iteration's workgroups
+    for (int pp = 2; pp <= e.m; ++pp)
+        if (ctx->tiles_pass(pp).nblocks > kMaxBlocks / 2)
+            return ctx->fail(DL_ERR_WORKSPACE, "sweep grid exceeds half of the partials table");
     auto launch = [&](int pp) {
         dl::PassArgs a{};
         a.op = op;
