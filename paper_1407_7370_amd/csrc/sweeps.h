@@ -1073,67 +1073,93 @@ __device__ void predict_k(const double *alpha, const double *gamma, Scalars *sc,
 // While the Gershgorin half-width R of T (centre c0) is at most 40 the
 // integral is taken by Gauss-Legendre quadrature on [0, 1] with
 // min(48, ceil(R) + 10) nodes (|s_j|^2 is a trigonometric sum of frequencies
-// below 2R, inside the rule's resolution), with s carried from node to node
-// by short Chebyshev expansions
-// of exp(-i delta (T - c0 I)) (Bessel coefficients J_n(delta R) by Miller's
-// backward recurrence, one lane per node) and a 1% margin on the integral.
-// The scalar phase exp(-i delta c0) of each Chebyshev step does not change
-// |s_j| and is left out.  For 40 < R <= 70: |s_j(t)| <= ||psi||
-// [exp(t|X|) e_1]_j for X = T - c0 I (path sums of X^n), a Taylor series of
-// non-negative terms with N = 3R + 40 terms plus its tail bound, capped at 1;
-// beyond R = 70 the factor is 1.  Lane l handles j = l + 1; beta_j is lane
-// l's coupling e.
+// below 2R, inside the rule's resolution) and a 1% margin on the integral.
+// s(t_q) at every node is one Chebyshev expansion of exp(-i t_q (T - c0 I))
+// e_1 = sum_n a_n T_n(X) e_1 (X = (T - c0 I) / R, a_0 = J_0(t_q R), a_n =
+// 2 (-i)^n J_n(t_q R)): the vectors T_n(X) e_1 are formed once and shared by
+// all nodes, the Bessel values by Miller's backward recurrence, one lane per
+// node.  The scalar phase exp(-i t c0) does not change |s_j| and is left
+// out.  For 40 < R <= 70: |s_j(t)| <= ||psi|| [exp(t|X|) e_1]_j for X = T -
+// c0 I (path sums of X^n), a Taylor series of non-negative terms with N = 3R +
+// 40 terms plus its tail bound, capped at 1; beyond R = 70 the factor is 1.
+// Lane l handles j = l + 1; beta_j is lane l's coupling e.
 constexpr int kBoundNodes = 48;
-constexpr int kBoundMaxTerms = 40;
+constexpr int kBoundMinNodes = 8;
 constexpr double kBoundMaxR = 40.0;
-// one node's Bessel values up to the recurrence's start order (at most 70),
-// an odd row length so the lanes' rows start on different LDS banks
-constexpr int kBoundRow = 73;
+// terms of the expansion at t R <= R <= 40: ceil(R + 6 R^(1/3) + 12) <= 73
+// leaves a truncation below 1e-13
+constexpr int kBoundMaxTerms = 73;
+// one node's Bessel values J_0 .. J_{N+3} and a slot that takes the
+// recurrence's higher orders; an odd row length so the lanes' rows start on
+// different LDS banks
+constexpr int kBoundRow = kBoundMaxTerms + 6;
+// LDS (doubles) of the quadrature: the vectors T_n(X) e_1 (rows of 64) and
+// the Bessel rows of the nodes
+constexpr int kBoundVecRows = kBoundMaxTerms + 4;
+constexpr int kBoundLds = kBoundVecRows * 64 + kBoundNodes * kBoundRow;
 
-// Gauss-Legendre node (on [0, 1], ascending in q) and weight of rule size n
-// for node q < n (Newton's method on P_n).
-struct InvTable {
-    double v[kBoundNodes + 1];
+// Gauss-Legendre rules on [0, 1] of sizes kBoundMinNodes .. kBoundNodes,
+// concatenated (rule n from gl_base(n), nodes ascending), built at compile
+// time by Newton's method on P_n from the classical starting guess
+// cos(pi (q + 3/4) / (n + 1/2)) (six steps; the rule is symmetric about 1/2).
+constexpr int gl_base(int n)
+{
+    return n * (n - 1) / 2 - kBoundMinNodes * (kBoundMinNodes - 1) / 2;
+}
+constexpr int kGLTotal = gl_base(kBoundNodes + 1);
+struct GLRules {
+    double t[kGLTotal];
+    double w[kGLTotal];
 };
-constexpr InvTable make_inv_table()
+constexpr double cx_cos(double x)
 {
-    InvTable tb{};
-    for (int j = 1; j <= kBoundNodes; ++j) tb.v[j] = 1.0 / j;
-    return tb;
-}
-
-__device__ void gauss_legendre01(int n, int q, double &t, double &w)
-{
-    // three Newton steps from the classical starting guess reach the node to
-    // a few ulps for every n <= 48 (checked against numpy's rule); the
-    // Legendre recurrence multiplies by 1/j from a table
-    constexpr InvTable inv = make_inv_table();
-    double x = cos(3.14159265358979323846 * (q + 0.75) / (n + 0.5)), p0 = 1.0, p1 = 0.0, dp = 1.0;
-    auto legendre = [&](double xx) {
-        p0 = 1.0;
-        p1 = 0.0;
-        for (int j = 1; j <= n; ++j) {
-            const double p2 = p1;
-            p1 = p0;
-            p0 = ((2.0 * j - 1.0) * xx * p1 - (j - 1.0) * p2) * inv.v[j];
-        }
-        dp = n * (xx * p0 - p1) / (xx * xx - 1.0);
-    };
-    for (int it = 0; it < 3; ++it) {
-        legendre(x);
-        x -= p0 / dp;
+    // Taylor series, |x| <= pi
+    double term = 1.0, sum = 1.0;
+    for (int i = 1; i < 24; ++i) {
+        term *= -x * x / ((2.0 * i - 1.0) * (2.0 * i));
+        sum += term;
     }
-    legendre(x);
-    t = 0.5 * (1.0 - x);
-    w = 1.0 / ((1.0 - x * x) * dp * dp);
+    return sum;
 }
-
-__device__ double storage_bound(double d, double e, double em, int k, int lane, double g1, double reps,
-                                double rabs)
+constexpr void cx_legendre(int n, double x, double &p, double &dp)
 {
-    __shared__ double jtab[kBoundNodes][kBoundRow];
-    __shared__ double jsc[kBoundNodes];
-    __shared__ double tnode[kBoundNodes], wnode[kBoundNodes];
+    double p0 = 1.0, p1 = 0.0;
+    for (int j = 1; j <= n; ++j) {
+        const double p2 = p1;
+        p1 = p0;
+        p0 = ((2.0 * j - 1.0) * x * p1 - (j - 1.0) * p2) / j;
+    }
+    p = p0;
+    dp = n * (x * p0 - p1) / (x * x - 1.0);
+}
+constexpr GLRules make_gl_rules()
+{
+    GLRules g{};
+    for (int n = kBoundMinNodes; n <= kBoundNodes; ++n) {
+        for (int q = 0; q < (n + 1) / 2; ++q) {
+            double x = cx_cos(3.14159265358979323846 * (q + 0.75) / (n + 0.5)), p = 0.0, dp = 1.0;
+            for (int it = 0; it < 6; ++it) {
+                cx_legendre(n, x, p, dp);
+                x -= p / dp;
+            }
+            cx_legendre(n, x, p, dp);
+            const double w = 1.0 / ((1.0 - x * x) * dp * dp);
+            g.t[gl_base(n) + q] = 0.5 * (1.0 - x);
+            g.w[gl_base(n) + q] = w;
+            g.t[gl_base(n) + n - 1 - q] = 0.5 * (1.0 + x);
+            g.w[gl_base(n) + n - 1 - q] = w;
+        }
+    }
+    return g;
+}
+constexpr GLRules kGLRules = make_gl_rules();
+
+// lds: kBoundLds doubles of the calling workgroup's LDS (free on entry,
+// reused by the caller afterwards).
+__device__ double storage_bound(double d, double e, double em, int k, int lane, double g1, double reps,
+                                double rabs, double *lds)
+{
+    __shared__ double jsc[kBoundNodes], wnode[kBoundNodes];
     if (!(reps > 0.0) && !(rabs > 0.0)) return 0.0;
     const double rad = fabs(e) + fabs(em);
     const double glo = wave_min(lane < k ? d - rad : INFINITY);
@@ -1142,80 +1168,96 @@ __device__ double storage_bound(double d, double e, double em, int k, int lane, 
     double f = 1.0;
     if (R <= kBoundMaxR) {
         // |s_j|^2 has frequencies below 2R: ceil(R) + 10 nodes integrate it to
-        // ~1e-8 relative, far inside the margin
-        const int nn = min(kBoundNodes, max(8, (int)ceil(R) + 10));
-        double tq = 0.0, wq = 0.0;
-        if (lane < nn) gauss_legendre01(nn, lane, tq, wq);
-        __syncthreads();  // tables of an earlier call are read up to here
-        if (lane < nn) {
-            tnode[lane] = tq;
-            wnode[lane] = wq;
-        }
-        const double tprev = __shfl_up(tq, 1, 64);
-        const double delta = lane < nn ? (lane == 0 ? tq : tq - tprev) : 0.0;
-        const double xmax = wave_max(delta) * R;
-        // hops are short (x = delta R < 2): x + 4 x^(1/3) + 8 terms leave a
-        // truncation below 1e-13
-        const int N = xmax > 0.0 ? min((int)ceil(xmax + 4.0 * cbrt(xmax) + 8.0), kBoundMaxTerms) : 0;
-        if (lane < nn) {
-            double *row = &jtab[lane][0];
-            const double x = delta * R;
-            double s = 1.0;
-            if (x > 0.0) {
-                const int M = miller_order(N);
-                if (miller_safe(x, M))
-                    s = miller_run(x, M, [&](int n, double v) { row[n] = v; });
-                else
-                    bessel_miller(x, N, row);  // rescaled as it goes, normalised
+        // ~1e-8 relative, far inside the margin; nodes in blocks of four
+        // (the padding has zero weight)
+        const int nn = min(kBoundNodes, max(kBoundMinNodes, (int)ceil(R) + 10));
+        const int nb = (nn + 3) & ~3;
+        const int N = R > 0.0 ? min((int)ceil(R + 6.0 * cbrt(R) + 12.0), kBoundMaxTerms) : 0;
+        double *vt = lds;                // row n: T_n(X) e_1 (n <= N + 3)
+        double *jt = lds + kBoundVecRows * 64;  // row q: J_n(t_q R), unnormalised
+        __syncthreads();  // LDS of an earlier use is read up to here
+        if (lane < nb) {
+            double *row = jt + lane * kBoundRow;
+            double s = 0.0, wq = 0.0;
+            if (lane < nn) {
+                const double x = kGLRules.t[gl_base(nn) + lane] * R;
+                wq = kGLRules.w[gl_base(nn) + lane];
+                s = 1.0;
+                if (x > 0.0) {
+                    const int M = miller_order(N), top = N + 4;  // orders above N + 3 land in row[top]
+                    if (miller_safe(x, M))
+                        s = miller_run(x, M, [&](int n, double v) { row[min(n, top)] = v; });
+                    else
+                        bessel_miller(x, N, row);  // rescaled as it goes, normalised
+                } else {
+                    row[0] = 1.0;
+                    for (int n = 1; n <= N + 3; ++n) row[n] = 0.0;
+                }
             } else {
-                row[0] = 1.0;
-                for (int n = 1; n <= N + 3; ++n) row[n] = 0.0;
+                for (int n = 0; n <= N + 3; ++n) row[n] = 0.0;
             }
             jsc[lane] = s;
+            wnode[lane] = wq;
         }
-        __syncthreads();
         const double ir = R > 0.0 ? 1.0 / R : 0.0;
         const double xd = lane < k ? (d - c0) * ir : 0.0, xe = e * ir, xem = em * ir;
         auto xmul = [&](double v) { return xem * from_left(v) + xd * v + xe * from_right(v); };
-        double sr = lane == 0 ? 1.0 : 0.0, si = 0.0, integral = 0.0;
-        for (int q = 0; q < nn; ++q) {
-            // exp(-i dq (T - c0)) s = sum_n a_n T_n(X) s, a_0 = J_0, a_n = 2 (-i)^n J_n(dq R),
-            // dq = t_q - t_{q-1}
-            const double s1 = jsc[q], s2 = 2.0 * s1;
-            const double *row = &jtab[q][0];
-            double pr = sr, pi = si;                // T_{n-1}(X) s
-            double cr = xmul(sr), ci = xmul(si);    // T_n(X) s
-            double ar = s1 * row[0] * sr, ai = s1 * row[0] * si;
-            if (N >= 1) {
-                ar += s2 * row[1] * ci;
-                ai -= s2 * row[1] * cr;
-            }
+        double tm = lane == 0 ? 1.0 : 0.0, tc = xmul(tm);
+        vt[lane] = tm;
+        vt[64 + lane] = tc;
+        for (int n = 2; n <= N + 3; ++n) {
+            const double tn = 2.0 * xmul(tc) - tm;
+            vt[n * 64 + lane] = tn;
+            tm = tc;
+            tc = tn;
+        }
+        __syncthreads();
+        // per node, halved: a = J_0 v_0 / 2 - J_2 v_2 + J_4 v_4 - ..., b = -J_1 v_1
+        // + J_3 v_3 - ..., so that s_j(t_q) = 2 (a + i b) times the
+        // normalisation of the node's Bessel values
+        const double v0 = vt[lane], v1 = vt[64 + lane];
+        double integral = 0.0;
+        for (int q = 0; q < nb; q += 4) {
+            const double *r0 = jt + q * kBoundRow, *r1 = r0 + kBoundRow, *r2 = r1 + kBoundRow,
+                         *r3 = r2 + kBoundRow;
+            double a0 = 0.5 * r0[0] * v0, a1 = 0.5 * r1[0] * v0, a2 = 0.5 * r2[0] * v0, a3 = 0.5 * r3[0] * v0;
+            double b0 = -r0[1] * v1, b1 = -r1[1] * v1, b2 = -r2[1] * v1, b3 = -r3[1] * v1;
             // orders n .. n+3 with n = 2 mod 4, phases -1, i, 1, -i (up to
             // three orders past N: more terms of the same expansion)
             for (int n = 2; n <= N; n += 4) {
-                const double f0 = s2 * row[n], f1 = s2 * row[n + 1], f2 = s2 * row[n + 2], f3 = s2 * row[n + 3];
-                const double t2r = 2.0 * xmul(cr) - pr, t2i = 2.0 * xmul(ci) - pi;
-                const double t3r = 2.0 * xmul(t2r) - cr, t3i = 2.0 * xmul(t2i) - ci;
-                const double t4r = 2.0 * xmul(t3r) - t2r, t4i = 2.0 * xmul(t3i) - t2i;
-                const double t5r = 2.0 * xmul(t4r) - t3r, t5i = 2.0 * xmul(t4i) - t3i;
-                ar -= f0 * t2r;
-                ai -= f0 * t2i;
-                ar -= f1 * t3i;
-                ai += f1 * t3r;
-                ar += f2 * t4r;
-                ai += f2 * t4i;
-                ar += f3 * t5i;
-                ai -= f3 * t5r;
-                pr = t4r;
-                pi = t4i;
-                cr = t5r;
-                ci = t5i;
+                const double w2 = vt[n * 64 + lane], w3 = vt[(n + 1) * 64 + lane], w4 = vt[(n + 2) * 64 + lane],
+                             w5 = vt[(n + 3) * 64 + lane];
+                a0 -= r0[n] * w2;
+                b0 += r0[n + 1] * w3;
+                a1 -= r1[n] * w2;
+                b1 += r1[n + 1] * w3;
+                a2 -= r2[n] * w2;
+                b2 += r2[n + 1] * w3;
+                a3 -= r3[n] * w2;
+                b3 += r3[n + 1] * w3;
+                a0 += r0[n + 2] * w4;
+                b0 -= r0[n + 3] * w5;
+                a1 += r1[n + 2] * w4;
+                b1 -= r1[n + 3] * w5;
+                a2 += r2[n + 2] * w4;
+                b2 -= r2[n + 3] * w5;
+                a3 += r3[n + 2] * w4;
+                b3 -= r3[n + 3] * w5;
             }
-            sr = ar;
-            si = ai;
-            integral += wnode[q] * (sr * sr + si * si);
+            // normalised before squaring: the unnormalised sums reach 1e290
+            const double s0 = jsc[q], s1 = jsc[q + 1], s2 = jsc[q + 2], s3 = jsc[q + 3];
+            a0 *= s0;
+            b0 *= s0;
+            a1 *= s1;
+            b1 *= s1;
+            a2 *= s2;
+            b2 *= s2;
+            a3 *= s3;
+            b3 *= s3;
+            integral += wnode[q] * (a0 * a0 + b0 * b0) + wnode[q + 1] * (a1 * a1 + b1 * b1) +
+                        wnode[q + 2] * (a2 * a2 + b2 * b2) + wnode[q + 3] * (a3 * a3 + b3 * b3);
         }
-        f = fmin(1.0, sqrt(1.01 * integral));
+        f = fmin(1.0, sqrt(4.04 * integral));
     } else if (R <= 30.0 + kBoundMaxR) {
         // X = T - c0 I with entrywise absolute value: |s_j(t)| <= [exp(|X|) e_1]_j
         const double xd = lane < k ? fabs(d - c0) : 0.0, xe = fabs(e), xem = fabs(em);
@@ -1237,7 +1279,8 @@ __device__ double storage_bound(double d, double e, double em, int k, int lane, 
 __device__ __forceinline__ void tridiag_body(const double *alpha, const double *gamma, Scalars *sc, StepStat *stat,
                                              double reps, double rabs)
 {
-    __shared__ double zpr[(kMaxM + 1) * 64];
+    // eigenvector columns of the QR path; first the storage bound's quadrature
+    __shared__ double zpr[(kMaxM + 1) * 64 > kBoundLds ? (kMaxM + 1) * 64 : kBoundLds];
     __shared__ double wre[kMaxM], wim[kMaxM];
     const int lane = threadIdx.x;
     // every scalar of the step read up front, so the loads overlap (the last
@@ -1260,7 +1303,7 @@ __device__ __forceinline__ void tridiag_body(const double *alpha, const double *
     const double gl = (lane < k) ? gamma[lane + 1] : 1.0, g1 = gamma[1];
     double em = from_left(e);                           // e_{j-1}
     if (lane == 0) em = 0.0;
-    const double rb = storage_bound(d, e, em, k, lane, g1, reps, rabs);
+    const double rb = storage_bound(d, e, em, k, lane, g1, reps, rabs, zpr);
     double cr = 0.0, ci = 0.0;
     if (!cheb_exp_e1(d, e, em, k, lane, cr, ci)) {
 #define ZZ(i) zpr[(i) * 64 + lane]
