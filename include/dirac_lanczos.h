@@ -362,8 +362,10 @@ dl_status dirac_lanczos_eigen_vectors(dl_context *ctx, const void *psi0, int32_t
  * Requirements: precision DL_PREC_FP64, krylov_dim <= 16, pulse_kind
  * DL_PULSE_FOURIER_SIN2, loss_kind in 1..15, n_steps >= 1, ckpt_every >= 1,
  * dt > 0.  adj_ws: DEVICE, 256-byte aligned, adj_bytes >=
- * dirac_lanczos_adjoint_workspace_bytes(params, n_steps, ckpt_every); the
- * context's own workspace is used for the forward Krylov basis.
+ * dirac_lanczos_adjoint_workspace_bytes(params, n_steps, ckpt_every): the
+ * checkpoints and, while they fit in 32 GiB, the forward Krylov bases and
+ * states of the last segments, which the backward pass then does not
+ * recompute (otherwise the context's own workspace holds the forward basis).
  * psi0 (DEVICE) is read only.  loss (HOST, 1 double) receives L, grad (HOST,
  * n_coef doubles) the gradient in the order of params->coef.  Synchronous.
  * Errors: DL_ERR_INVALID, DL_ERR_WORKSPACE, DL_ERR_UNSUPPORTED (other

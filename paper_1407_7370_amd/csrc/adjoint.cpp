@@ -41,10 +41,15 @@ using namespace dlh;
 
 namespace {
 
-constexpr int kContractBlocks = 1024;
+// workgroups of the contraction (its partials: 8 KiB each)
+#ifndef DL_CONTRACT_BLOCKS
+#define DL_CONTRACT_BLOCKS 1024
+#endif
+constexpr int kContractBlocks = DL_CONTRACT_BLOCKS;
 constexpr int kObserveBlocks = 1024;
 
-// Largest store of one segment's forward Krylov bases (see AdjLayout::keep).
+// Largest store of kept forward segments (Krylov bases and states; see
+// AdjLayout::keep).
 #ifndef DL_ADJ_KEEP_GIB
 #define DL_ADJ_KEEP_GIB 32
 #endif
@@ -57,9 +62,15 @@ struct AdjLayout {
     // keep: the forward sweep of a segment leaves every step's Krylov basis
     // (kbasis, kb_stride apart) and its scalars, alpha and gamma (kscal,
     // ks_stride apart) in place, so the backward pass does not build them
-    // again; only when one segment's bases fit in kKeepBasesBytes.
+    // again; only when one segment's bases fit in kKeepBasesBytes.  nslot
+    // segments (bases, scalars and states) are held at once, segment g in
+    // slot g mod nslot, as many as fit in kKeepBasesBytes: the last nslot
+    // segments of the forward pass are still there when the backward pass
+    // reaches them and are not run again.
     bool keep = false;
+    int nslot = 1;
     size_t kb_stride = 0, ks_stride = 0, ks_alpha = 0, ks_gamma = 0;
+    size_t seg_slot = 0, kb_slot = 0, ks_slot = 0;  // bytes per slot
 };
 
 AdjLayout adj_plan(const dl_params &p, int n_steps, int ckpt_every)
@@ -89,21 +100,28 @@ AdjLayout adj_plan(const dl_params &p, int n_steps, int ckpt_every)
     off += (size_t)(m - 1) * vec_stride(n, 16);
     A.lam = off;
     off += 2 * vb;
-    A.seg = off;
-    off += (size_t)(A.seglen + 1) * vb;
-    A.ckpt = off;
-    off += (size_t)(A.nseg - 1) * vb;  // starts of segments 1 .. nseg-1 (segment 0 starts at psi0)
     A.kb_stride = (size_t)(m - 1) * vec_stride(n, 16);
     A.keep = A.kb_stride * (size_t)A.seglen <= kKeepBasesBytes;
+    A.seg_slot = (size_t)(A.seglen + 1) * vb;
     if (A.keep) {
         A.ks_alpha = align256(sizeof(dl::Scalars));
         A.ks_gamma = A.ks_alpha + align256(sizeof(double) * (m + 3));
         A.ks_stride = A.ks_gamma + align256(sizeof(double) * (m + 3));
+        A.kb_slot = A.kb_stride * (size_t)A.seglen;
+        A.ks_slot = A.ks_stride * (size_t)A.seglen;
+        const size_t per = A.kb_slot + A.ks_slot + A.seg_slot;
+        A.nslot = (int)std::min<size_t>((size_t)A.nseg, std::max<size_t>(1, kKeepBasesBytes / per));
+    }
+    A.seg = off;
+    off += (size_t)A.nslot * A.seg_slot;
+    A.ckpt = off;
+    off += (size_t)(A.nseg - 1) * vb;  // starts of segments 1 .. nseg-1 (segment 0 starts at psi0)
+    if (A.keep) {
         off = align256(off);
         A.kbasis = off;
-        off += A.kb_stride * (size_t)A.seglen;
+        off += (size_t)A.nslot * A.kb_slot;
         A.kscal = off;
-        off += A.ks_stride * (size_t)A.seglen;
+        off += (size_t)A.nslot * A.ks_slot;
     }
     A.total = off;
     return A;
@@ -239,7 +257,10 @@ dl_status dirac_lanczos_adjoint(dl_context *ctx, const void *psi0_v, double t0, 
     double *rec = reinterpret_cast<double *>(aw + A.rec);
     const double2 *psi0 = static_cast<const double2 *>(psi0_v);
     auto lam = [&](int i) { return reinterpret_cast<double2 *>(aw + A.lam + (size_t)i * vb); };
-    auto seg = [&](int i) { return reinterpret_cast<double2 *>(aw + A.seg + (size_t)i * vb); };
+    // state i of segment g (its slot)
+    auto seg = [&](int g, int i) {
+        return reinterpret_cast<double2 *>(aw + A.seg + (size_t)(g % A.nslot) * A.seg_slot + (size_t)i * vb);
+    };
     auto ckpt = [&](int g) -> const double2 * {
         return g == 0 ? psi0 : reinterpret_cast<const double2 *>(aw + A.ckpt + (size_t)(g - 1) * vb);
     };
@@ -266,30 +287,31 @@ dl_status dirac_lanczos_adjoint(dl_context *ctx, const void *psi0_v, double t0, 
 
     const int C = A.seglen, G = A.nseg;
     auto seg_len = [&](int g) { return std::min(C, n_steps - g * C); };
-    // forward states of segment g into seg(0..len)
+    // forward states of segment g into seg(g, 0..len)
     // step i of a segment: its own basis when the bases are kept, else the context's
-    auto step_engine = [&](int i) {
+    auto step_engine = [&](int g, int i) {
         Engine e = ep;
-        if (A.keep) e.basis = aw + A.kbasis + (size_t)i * A.kb_stride;
+        if (A.keep) e.basis = aw + A.kbasis + (size_t)(g % A.nslot) * A.kb_slot + (size_t)i * A.kb_stride;
         return e;
     };
-    auto kept_scal = [&](int i) { return aw + A.kscal + (size_t)i * A.ks_stride; };
+    auto kept_scal = [&](int g, int i) {
+        return aw + A.kscal + (size_t)(g % A.nslot) * A.ks_slot + (size_t)i * A.ks_stride;
+    };
     auto run_segment = [&](int g) -> dl_status {
         const int len = seg_len(g);
-        DL_HIP(ctx, hipMemcpyAsync(seg(0), ckpt(g), n * 16, hipMemcpyDeviceToDevice, st));
+        DL_HIP(ctx, hipMemcpyAsync(seg(g, 0), ckpt(g), n * 16, hipMemcpyDeviceToDevice, st));
         for (int i = 0; i < len; ++i) {
             const double *fp = fields + 4 * (size_t)(g * C + i);
-            const Engine ei = step_engine(i);
-            const dl_status sb = run_build(ctx, ei, opf, seg(i), fp, partials, 1);
+            const Engine ei = step_engine(g, i);
+            const dl_status sb = run_build(ctx, ei, opf, seg(g, i), fp, partials, 1);
             if (sb != DL_OK) return sb;
-            const dl_status sf = run_finish(ctx, ei, seg(i), seg(i + 1), dstat, partials);
+            // what the backward contraction reads of this step (k_eff, shift,
+            // status, alpha and gamma, whole once the small exponential has
+            // folded the last iteration) is copied by the recombination
+            KeepDst keep;
+            if (A.keep) keep = KeepDst{kept_scal(g, i), A.ks_alpha, A.ks_gamma, m + 3};
+            const dl_status sf = run_finish(ctx, ei, seg(g, i), seg(g, i + 1), dstat, partials, false, keep);
             if (sf != DL_OK) return sf;
-            if (A.keep) {
-                // what the backward contraction reads of this step: k_eff, shift,
-                // status, alpha and gamma, whole once the small exponential has
-                // folded the last iteration (the recombination leaves them alone)
-                dl::launch_keep_step(ep.sc, ep.alpha, ep.gamma, m + 3, kept_scal(i), A.ks_alpha, A.ks_gamma, st);
-            }
         }
         DL_HIP(ctx, hipGetLastError());
         return DL_OK;
@@ -307,7 +329,7 @@ dl_status dirac_lanczos_adjoint(dl_context *ctx, const void *psi0_v, double t0, 
         const dl_status s = run_segment(g);
         if (s != DL_OK) return s;
         if (g + 1 < G)
-            DL_HIP(ctx, hipMemcpyAsync(const_cast<double2 *>(ckpt(g + 1)), seg(seg_len(g)), n * 16,
+            DL_HIP(ctx, hipMemcpyAsync(const_cast<double2 *>(ckpt(g + 1)), seg(g, seg_len(g)), n * 16,
                                        hipMemcpyDeviceToDevice, st));
     }
     {
@@ -315,7 +337,7 @@ dl_status dirac_lanczos_adjoint(dl_context *ctx, const void *psi0_v, double t0, 
         if (s != DL_OK) return s;
     }
     // loss and adjoint seed from psi_N (the end of the last segment, still in seg)
-    const double2 *psin = seg(seg_len(G - 1));
+    const double2 *psin = seg(G - 1, seg_len(G - 1));
     const int nbo = (int)std::max<size_t>(1, std::min<size_t>(kObserveBlocks, (sites + dl::kBlock - 1) / dl::kBlock));
     dl::launch_observe(op1, psin, loss_kind, el.sc, partials, obs, nbo, st);
     dl::launch_adjoint_seed(op1, psin, loss_kind, obs, lam(0), st);
@@ -336,16 +358,16 @@ dl_status dirac_lanczos_adjoint(dl_context *ctx, const void *psi0_v, double t0, 
     int cur = 0;
     for (int g = G - 1; g >= 0; --g) {
         const int len = seg_len(g);
-        if (g != G - 1) {
+        if (g < G - A.nslot) {  // the last nslot segments are still in their slots
             const dl_status s = run_segment(g);
             if (s != DL_OK) return s;
         }
         for (int i = len - 1; i >= 0; --i) {
             const size_t ns = (size_t)g * C + i;
             dl_status s = DL_OK;
-            const Engine ei = step_engine(i);
+            const Engine ei = step_engine(g, i);
             if (!A.keep) {
-                s = run_build(ctx, ei, opf, seg(i), fields + 4 * ns, partials, 1, true);
+                s = run_build(ctx, ei, opf, seg(g, i), fields + 4 * ns, partials, 1, true);
                 if (s != DL_OK) return s;
             }
             // the backward step first: its small exponential completes T of the
@@ -358,7 +380,7 @@ dl_status dirac_lanczos_adjoint(dl_context *ctx, const void *psi0_v, double t0, 
             dl::ContractArgs ca{};
             ca.lam1 = lam(cur);
             ca.lam_basis = el.basis;
-            ca.psi1 = seg(i);
+            ca.psi1 = seg(g, i);
             ca.psi_basis = ei.basis;
             ca.vec_bytes = vstride;
             ca.sites = sites;
@@ -366,7 +388,7 @@ dl_status dirac_lanczos_adjoint(dl_context *ctx, const void *psi0_v, double t0, 
             ca.alpha_lam = el.alpha;
             ca.gamma_lam = el.gamma;
             if (A.keep) {
-                char *ks = kept_scal(i);
+                char *ks = kept_scal(g, i);
                 ca.sc_psi = reinterpret_cast<const dl::Scalars *>(ks);
                 ca.alpha_psi = reinterpret_cast<const double *>(ks + A.ks_alpha);
                 ca.gamma_psi = reinterpret_cast<const double *>(ks + A.ks_gamma);

@@ -201,23 +201,6 @@ __global__ __launch_bounds__(kBlock) void k_contract_fold(ContractArgs a, int nb
     }
 }
 
-// The scalars, alpha and gamma of one forward step, kept for the backward
-// pass (one launch instead of three copies).
-__global__ __launch_bounds__(kBlock) void k_keep_step(const Scalars *sc, const double *alpha, const double *gamma,
-                                                      int nab, char *dst, size_t off_alpha, size_t off_gamma)
-{
-    static_assert(sizeof(Scalars) % 8 == 0, "the scalars are copied as 8-byte words");
-    constexpr int kWords = (int)(sizeof(Scalars) / 8);
-    const auto *src = reinterpret_cast<const unsigned long long *>(sc);
-    auto *d = reinterpret_cast<unsigned long long *>(dst);
-    for (int i = threadIdx.x; i < kWords; i += kBlock) d[i] = src[i];
-    double *da = reinterpret_cast<double *>(dst + off_alpha), *dg = reinterpret_cast<double *>(dst + off_gamma);
-    for (int i = threadIdx.x; i < nab; i += kBlock) {
-        da[i] = alpha[i];
-        dg[i] = gamma[i];
-    }
-}
-
 }  // namespace
 
 void launch_observe(const Op &op, const double2 *psi, int loss_kind, Scalars *sc, double *partials,
@@ -238,12 +221,6 @@ void launch_contract(const ContractArgs &a, int nblocks, hipStream_t st)
 {
     hipLaunchKernelGGL(k_contract, dim3(nblocks), dim3(kBlock), 0, st, a);
     hipLaunchKernelGGL(k_contract_fold, dim3(4 * kBlock / kWaves), dim3(kBlock), 0, st, a, nblocks);
-}
-
-void launch_keep_step(const Scalars *sc, const double *alpha, const double *gamma, int nab, char *dst,
-                      size_t off_alpha, size_t off_gamma, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_keep_step, dim3(1), dim3(kBlock), 0, st, sc, alpha, gamma, nab, dst, off_alpha, off_gamma);
 }
 
 }  // namespace dl

@@ -103,7 +103,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE, 8))
     const BatchBlock bb = b.blocks[blockIdx.x];
     const BatchPacket &pk = b.pk[bb.packet];
     if (pk.sc->status != 0) return;
-    CombArgs a;
+    CombArgs a{};
     a.psi = b.parity ? pk.state : pk.psi;
     a.basis = pk.basis;
     a.vec_bytes = pk.vstride;

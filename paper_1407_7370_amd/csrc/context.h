@@ -252,9 +252,16 @@ dl_status run_build(dl_context *ctx, const Engine &e, const dl::Op &op, const do
 // One whole step by the second Lanczos run (three rolling Krylov vectors).
 dl_status run_twice(dl_context *ctx, const Engine &e, const dl::Op &op, const double2 *in, double2 *out,
                     const double *field, dl::StepStat *stat, double *partials);
+// Where the recombination also copies the step's scalars, alpha and gamma
+// (dst == NULL: nowhere); see dl::CombArgs::keep.
+struct KeepDst {
+    char *dst = nullptr;
+    size_t off_alpha = 0, off_gamma = 0;
+    int nab = 0;
+};
 // exp(-iT) and the recombination into `out` (stat receives k_eff, estimate, norm).
 dl_status run_finish(dl_context *ctx, const Engine &e, const double2 *in, double2 *out,
-                     dl::StepStat *stat, double *partials, bool folded = false);
+                     dl::StepStat *stat, double *partials, bool folded = false, const KeepDst &keep = KeepDst{});
 
 // Default launch shapes of a context's sweeps and recombination (ctx->p and
 // ctx->cus set).

@@ -126,6 +126,13 @@ struct CombArgs {
     Scalars *sc;
     double *partials;
     StepStat *stat;      // entry of this step
+    // keep != NULL: workgroup 0 also copies the step's scalars (raw words) to
+    // keep, alpha[0..keep_nab) to keep + keep_alpha and gamma[0..keep_nab) to
+    // keep + keep_gamma (what a later pass reads of this step)
+    const double *alpha, *gamma;
+    char *keep;
+    size_t keep_alpha, keep_gamma;
+    int keep_nab;
 };
 
 // One term of the recombination during a second Lanczos run (the basis is not
@@ -184,9 +191,6 @@ struct ContractArgs {
     double *rec;       // record of this step (kRecLen doubles)
 };
 void launch_contract(const ContractArgs &a, int nblocks, hipStream_t st);
-// dst <- the scalars (raw), alpha[0..nab) at dst + off_alpha, gamma[0..nab) at dst + off_gamma
-void launch_keep_step(const Scalars *sc, const double *alpha, const double *gamma, int nab, char *dst,
-                      size_t off_alpha, size_t off_gamma, hipStream_t st);
 
 void launch_first(const Op &op, const Tiles &t, const double2 *psi, const double *field,
                   double *alpha, double *gamma, Scalars *sc, double *partials, int m,

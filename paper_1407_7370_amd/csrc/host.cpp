@@ -296,7 +296,7 @@ dl_status run_twice(dl_context *ctx, const Engine &e, const dl::Op &op, const do
 }
 
 dl_status run_finish(dl_context *ctx, const Engine &e, const double2 *in, double2 *out,
-                     dl::StepStat *stat, double *partials, bool folded)
+                     dl::StepStat *stat, double *partials, bool folded, const KeepDst &keep)
 {
     hipStream_t st = ctx->stream;
     double reps, rabs;
@@ -314,6 +314,12 @@ dl_status run_finish(dl_context *ctx, const Engine &e, const double2 *in, double
     r.sc = e.sc;
     r.partials = partials;
     r.stat = stat;
+    r.alpha = e.alpha;
+    r.gamma = e.gamma;
+    r.keep = keep.dst;
+    r.keep_alpha = keep.off_alpha;
+    r.keep_gamma = keep.off_gamma;
+    r.keep_nab = keep.nab;
     DL_HIP(ctx, ctx->timed(4, [&] {
         dl::launch_combine(r, e.mixed, ctx->combine_wide, ctx->combine_blocks_wide, st);
     }));

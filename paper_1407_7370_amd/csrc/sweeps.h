@@ -1601,6 +1601,22 @@ template <class TB, int S, int WPE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_combine(CombArgs a)
 {
     if (a.sc->status != 0) return;
+    if (a.keep != nullptr && blockIdx.x == 0) {
+        // the scalars, alpha and gamma are final once the small exponential
+        // has run; the recombination changes only the ticket, the step count
+        // and, for a non-finite norm, the status (which the caller checks on
+        // the live scalars)
+        static_assert(sizeof(Scalars) % 8 == 0, "the scalars are copied as 8-byte words");
+        constexpr int kWords = (int)(sizeof(Scalars) / 8);
+        const auto *src = reinterpret_cast<const unsigned long long *>(a.sc);
+        auto *d = reinterpret_cast<unsigned long long *>(a.keep);
+        for (int i = threadIdx.x; i < kWords; i += kBlock) d[i] = src[i];
+        double *da = reinterpret_cast<double *>(a.keep + a.keep_alpha), *dg = reinterpret_cast<double *>(a.keep + a.keep_gamma);
+        for (int i = threadIdx.x; i < a.keep_nab; i += kBlock) {
+            da[i] = a.alpha[i];
+            dg[i] = a.gamma[i];
+        }
+    }
     double nrm = 0.0;
     combine_body<TB, S>(a, (int)blockIdx.x, (int)gridDim.x, nrm);
     double accv[1] = {nrm}, tot[1];
