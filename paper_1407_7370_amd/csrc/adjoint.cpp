@@ -46,6 +46,8 @@ namespace {
 #define DL_CONTRACT_BLOCKS 1024
 #endif
 constexpr int kContractBlocks = DL_CONTRACT_BLOCKS;
+// backward steps whose contraction partials are folded by one launch
+constexpr int kFoldSteps = 64;
 constexpr int kObserveBlocks = 1024;
 
 // Largest store of kept forward segments (Krylov bases and states; see
@@ -71,6 +73,7 @@ struct AdjLayout {
     int nslot = 1;
     size_t kb_stride = 0, ks_stride = 0, ks_alpha = 0, ks_gamma = 0;
     size_t seg_slot = 0, kb_slot = 0, ks_slot = 0;  // bytes per slot
+    int nfold = 1;  // contraction partial tables (one per backward step until the fold)
 };
 
 AdjLayout adj_plan(const dl_params &p, int n_steps, int ckpt_every)
@@ -92,8 +95,9 @@ AdjLayout adj_plan(const dl_params &p, int n_steps, int ckpt_every)
     off = align256(off + sizeof(double) * 8);
     A.fields = off;
     off = align256(off + sizeof(double) * 4 * (size_t)n_steps);
+    A.nfold = std::min(kFoldSteps, A.seglen);
     A.cpart = off;
-    off = align256(off + sizeof(double) * 4 * dl::kBlock * (size_t)kContractBlocks);
+    off = align256(off + sizeof(double) * 4 * dl::kBlock * (size_t)kContractBlocks * (size_t)A.nfold);
     A.rec = off;
     off = align256(off + sizeof(double) * dl::kRecLen * (size_t)A.seglen);
     A.basis = off;
@@ -355,7 +359,7 @@ dl_status dirac_lanczos_adjoint(dl_context *ctx, const void *psi0_v, double t0, 
     std::vector<double> hrec((size_t)dl::kRecLen * C);
     const int ncb = (int)std::max<size_t>(
         1, std::min<size_t>(kContractBlocks, (sites + 31) / 32));  // one 32-site tile per block and round
-    int cur = 0;
+    int cur = 0, pending = 0;
     for (int g = G - 1; g >= 0; --g) {
         const int len = seg_len(g);
         if (g < G - A.nslot) {  // the last nslot segments are still in their slots
@@ -397,9 +401,15 @@ dl_status dirac_lanczos_adjoint(dl_context *ctx, const void *psi0_v, double t0, 
                 ca.alpha_psi = ep.alpha;
                 ca.gamma_psi = ep.gamma;
             }
-            ca.partials = cpart;
+            ca.partials = cpart + (size_t)(i % A.nfold) * 4 * dl::kBlock * (size_t)ncb;
             ca.rec = rec + (size_t)i * dl::kRecLen;
             dl::launch_contract(ca, ncb, st);
+            // the sums of the pending steps i .. i + pending - 1 (distinct
+            // partial tables) are folded together
+            if (++pending == A.nfold || i == 0) {
+                dl::launch_contract_fold(cpart, A.nfold, ncb, rec, i, pending, st);
+                pending = 0;
+            }
             cur = 1 - cur;
         }
         DL_HIP(ctx, hipGetLastError());

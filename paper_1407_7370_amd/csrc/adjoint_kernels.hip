@@ -167,25 +167,12 @@ __global__ __launch_bounds__(kBlock) void k_contract(ContractArgs a)
         for (int i = 1; i < kWaves; ++i) acc += red[i][c][src][reg];
         a.partials[(size_t)(4 * t + c) * nb + b] = acc;
     }
-}
-
-// One wave per output (4 kBlock outputs, kWaves per workgroup): lane l sums
-// partials l, l + 64, ... of its output in order, then a butterfly; the
-// order is fixed by nblocks, so the result is bitwise reproducible.  The
-// first workgroup also copies the chains and scalars into the record.
-__global__ __launch_bounds__(kBlock) void k_contract_fold(ContractArgs a, int nblocks)
-{
-    const int t = threadIdx.x, lane = t & 63;
-    const int o = blockIdx.x * kWaves + (t >> 6);
-    double v[1] = {0.0};
-    const double *src = a.partials + (size_t)o * nblocks;
-    for (int b = lane; b < nblocks; b += 64) v[0] += src[b];
-    wave_sum(v);
-    if (lane == 0) a.rec[kRecS + o] = v[0];
     if (blockIdx.x != 0) return;
+    // the step's chains and scalars into its record (the fold of the sums
+    // runs later, for several steps at once)
     if (t < kContractM + 2) {
         // entries 0..k+1 of each chain exist (the chains hold m + 3 >= k + 3 values)
-        const bool inl = t <= a.sc_lam->keff + 1, inp = t <= a.sc_psi->keff + 1;
+        const bool inl = t <= kl + 1, inp = t <= kp + 1;
         a.rec[kRecAlphaL + t] = inl ? a.alpha_lam[t] : 0.0;
         a.rec[kRecGammaL + t] = inl ? a.gamma_lam[t] : 0.0;
         a.rec[kRecAlphaP + t] = inp ? a.alpha_psi[t] : 0.0;
@@ -194,11 +181,32 @@ __global__ __launch_bounds__(kBlock) void k_contract_fold(ContractArgs a, int nb
     if (t == 0) {
         a.rec[kRecMeta + 0] = a.sc_lam->sigma;
         a.rec[kRecMeta + 1] = a.sc_psi->sigma;
-        a.rec[kRecMeta + 2] = (double)a.sc_lam->keff;
-        a.rec[kRecMeta + 3] = (double)a.sc_psi->keff;
+        a.rec[kRecMeta + 2] = (double)kl;
+        a.rec[kRecMeta + 3] = (double)kp;
         a.rec[kRecMeta + 4] = (double)a.sc_lam->status;
         a.rec[kRecMeta + 5] = (double)a.sc_psi->status;
     }
+}
+
+// One wave per output (4 kBlock outputs of each of nsteps steps, kWaves per
+// workgroup): lane l sums partials l, l + 64, ... of its output in order,
+// then a butterfly; the order is fixed by nblocks, so the result is bitwise
+// reproducible.  Step i0 + j (j < nsteps) reads its partials from slot
+// (i0 + j) % nslot of the partial table (slot stride 4 kBlock nblocks) and
+// writes its record rec + (i0 + j) kRecLen.
+__global__ __launch_bounds__(kBlock) void k_contract_fold(const double *partials, int nslot, int nblocks,
+                                                          double *rec, int i0)
+{
+    constexpr int kPerStep = 4 * kBlock / kWaves;  // workgroups per step
+    const int t = threadIdx.x, lane = t & 63;
+    const int step = i0 + (int)blockIdx.x / kPerStep;
+    const int o = ((int)blockIdx.x % kPerStep) * kWaves + (t >> 6);
+    double v[1] = {0.0};
+    const double *src =
+        partials + ((size_t)(step % nslot) * 4 * kBlock + (size_t)o) * (size_t)nblocks;
+    for (int b = lane; b < nblocks; b += 64) v[0] += src[b];
+    wave_sum(v);
+    if (lane == 0) rec[(size_t)step * kRecLen + kRecS + o] = v[0];
 }
 
 }  // namespace
@@ -220,7 +228,13 @@ void launch_adjoint_seed(const Op &op, const double2 *psi, int loss_kind, const 
 void launch_contract(const ContractArgs &a, int nblocks, hipStream_t st)
 {
     hipLaunchKernelGGL(k_contract, dim3(nblocks), dim3(kBlock), 0, st, a);
-    hipLaunchKernelGGL(k_contract_fold, dim3(4 * kBlock / kWaves), dim3(kBlock), 0, st, a, nblocks);
+}
+
+void launch_contract_fold(const double *partials, int nslot, int nblocks, double *rec, int i0, int nsteps,
+                          hipStream_t st)
+{
+    hipLaunchKernelGGL(k_contract_fold, dim3(nsteps * (4 * kBlock / kWaves)), dim3(kBlock), 0, st, partials, nslot,
+                       nblocks, rec, i0);
 }
 
 }  // namespace dl

@@ -187,10 +187,14 @@ struct ContractArgs {
     const Scalars *sc_lam;
     const Scalars *sc_psi;
     const double *alpha_lam, *gamma_lam, *alpha_psi, *gamma_psi;
-    double *partials;  // nblocks x 256 x 4
-    double *rec;       // record of this step (kRecLen doubles)
+    double *partials;  // this step's partial table: 4 kBlock outputs x nblocks
+    double *rec;       // record of this step (kRecLen doubles); the contraction writes the chains and scalars
 };
 void launch_contract(const ContractArgs &a, int nblocks, hipStream_t st);
+// The contraction sums of steps i0 .. i0 + nsteps - 1 into their records (rec
+// + step * kRecLen); step s's partials are in slot s % nslot of `partials`.
+void launch_contract_fold(const double *partials, int nslot, int nblocks, double *rec, int i0, int nsteps,
+                          hipStream_t st);
 
 void launch_first(const Op &op, const Tiles &t, const double2 *psi, const double *field,
                   double *alpha, double *gamma, Scalars *sc, double *partials, int m,
