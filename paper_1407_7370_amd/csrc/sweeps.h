@@ -760,13 +760,22 @@ struct RecurTail {
     double beta_k;   // beta_k of the step (last iteration or breakdown)
 };
 
-__device__ __forceinline__ RecurTail recur_tail_eval(const Scalars *sc, const double *alpha, const double *gamma,
-                                                     int p, int m, const double (&tot)[5])
+// What the scalar update of iteration p reads besides the sums.
+struct TailIn {
+    int kstop;
+    double g1, sig, scale, alpha_pm1;
+};
+__device__ __forceinline__ TailIn tail_inputs(const Scalars *sc, const double *alpha, const double *gamma, int p)
+{
+    return TailIn{sc->kstop, gamma[p - 1], sc->sigma, sc->scale, alpha[p - 1]};
+}
+
+__device__ __forceinline__ RecurTail recur_tail_eval(const TailIn &in, int p, int m, const double (&tot)[5])
 {
     RecurTail o{};
-    o.last = (p == m) || (p == sc->kstop);
-    const double g1 = gamma[p - 1];
-    const double sig = sc->sigma;
+    o.last = (p == m) || (p == in.kstop);
+    const double g1 = in.g1;
+    const double sig = in.sig;
     const double n = tot[0], an = tot[1], ov = tot[2], yy = tot[3], yv = tot[4];
     if (!isfinite(n) || !isfinite(an) || !isfinite(ov) || !isfinite(yy) || !isfinite(yv)) {
         o.fail = true;
@@ -775,7 +784,7 @@ __device__ __forceinline__ RecurTail recur_tail_eval(const Scalars *sc, const do
     const double gp = sqrt(n);  // beta_{p-1}
     o.gp = gp;
     // breakdown scale on the unshifted alpha (the reading shared with the oracle)
-    const double scale = fmax(sc->scale, fabs(alpha[p - 1] + sig));
+    const double scale = fmax(in.scale, fabs(in.alpha_pm1 + sig));
     if (gp <= 1e-13 * scale) {
         // invariant Krylov subspace: stop with k_eff = p - 1, beta_k = gamma_p
         o.breakdown = true;
@@ -793,6 +802,12 @@ __device__ __forceinline__ RecurTail recur_tail_eval(const Scalars *sc, const do
         o.beta_k = sqrt(fmax(w2, 0.0)) / gp;
     }
     return o;
+}
+
+__device__ __forceinline__ RecurTail recur_tail_eval(const Scalars *sc, const double *alpha, const double *gamma,
+                                                     int p, int m, const double (&tot)[5])
+{
+    return recur_tail_eval(tail_inputs(sc, alpha, gamma, p), p, m, tot);
 }
 
 __device__ __forceinline__ void recur_tail_store(Scalars *sc, double *alpha, double *gamma, int p,
@@ -1409,10 +1424,17 @@ __device__ __forceinline__ void tridiag_body(const double *alpha, const double *
 // for the next kernel (one wave; iteration f.pass ran when kstop >= f.pass).
 __device__ __forceinline__ void fold_last_tail(double *alpha, double *gamma, Scalars *sc, const TailFold &f)
 {
-    if (f.pass >= 2 && sc->status == 0 && sc->kstop >= f.pass) {
-        double tot[5];
-        fold_partials_wave(f.partials, f.nblk, tot);
-        const RecurTail o = recur_tail_eval(sc, alpha, gamma, f.pass, f.pass, tot);
+    if (f.pass < 2) return;
+    // the partials (inside the table whether or not they are used), the
+    // scalars and the chain entries the update reads are loaded together,
+    // before the status decides whether to use them: one memory round trip
+    // instead of three
+    const int status = sc->status;
+    const TailIn in = tail_inputs(sc, alpha, gamma, f.pass);
+    double tot[5];
+    fold_partials_wave(f.partials, f.nblk, tot);
+    if (status == 0 && in.kstop >= f.pass) {
+        const RecurTail o = recur_tail_eval(in, f.pass, f.pass, tot);
         if (threadIdx.x == 0) recur_tail_store(sc, alpha, gamma, f.pass, o);
         __threadfence_block();
         __syncthreads();
