@@ -1229,10 +1229,15 @@ __device__ double storage_bound(double d, double e, double em, int k, int lane, 
         __syncthreads();
         // per node, halved: a = J_0 v_0 / 2 - J_2 v_2 + J_4 v_4 - ..., b = -J_1 v_1
         // + J_3 v_3 - ..., so that s_j(t_q) = 2 (a + i b) times the
-        // normalisation of the node's Bessel values
-        const double v0 = vt[lane], v1 = vt[64 + lane];
+        // normalisation of the node's Bessel values.  The vector needs kk
+        // lanes (the power of two >= k); the wave's 64 / kk lane groups take
+        // every (64 / kk)-th block of four nodes, and their integrals are
+        // added in a fixed order below.
+        const int kk = k <= 16 ? 16 : (k <= 32 ? 32 : 64);
+        const int jl = lane & (kk - 1), grp = lane / kk, ng = 64 / kk;
+        const double v0 = vt[jl], v1 = vt[64 + jl];
         double integral = 0.0;
-        for (int q = 0; q < nb; q += 4) {
+        for (int q = 4 * grp; q < nb; q += 4 * ng) {
             const double *r0 = jt + q * kBoundRow, *r1 = r0 + kBoundRow, *r2 = r1 + kBoundRow,
                          *r3 = r2 + kBoundRow;
             double a0 = 0.5 * r0[0] * v0, a1 = 0.5 * r1[0] * v0, a2 = 0.5 * r2[0] * v0, a3 = 0.5 * r3[0] * v0;
@@ -1240,8 +1245,8 @@ __device__ double storage_bound(double d, double e, double em, int k, int lane, 
             // orders n .. n+3 with n = 2 mod 4, phases -1, i, 1, -i (up to
             // three orders past N: more terms of the same expansion)
             for (int n = 2; n <= N; n += 4) {
-                const double w2 = vt[n * 64 + lane], w3 = vt[(n + 1) * 64 + lane], w4 = vt[(n + 2) * 64 + lane],
-                             w5 = vt[(n + 3) * 64 + lane];
+                const double w2 = vt[n * 64 + jl], w3 = vt[(n + 1) * 64 + jl], w4 = vt[(n + 2) * 64 + jl],
+                             w5 = vt[(n + 3) * 64 + jl];
                 a0 -= r0[n] * w2;
                 b0 += r0[n + 1] * w3;
                 a1 -= r1[n] * w2;
@@ -1272,6 +1277,9 @@ __device__ double storage_bound(double d, double e, double em, int k, int lane, 
             integral += wnode[q] * (a0 * a0 + b0 * b0) + wnode[q + 1] * (a1 * a1 + b1 * b1) +
                         wnode[q + 2] * (a2 * a2 + b2 * b2) + wnode[q + 3] * (a3 * a3 + b3 * b3);
         }
+        // lane j (< k) receives the sum over the groups of component j
+        if (kk <= 32) integral += __shfl_xor(integral, 32, 64);
+        if (kk <= 16) integral += __shfl_xor(integral, 16, 64);
         f = fmin(1.0, sqrt(4.04 * integral));
     } else if (R <= 30.0 + kBoundMaxR) {
         // X = T - c0 I with entrywise absolute value: |s_j(t)| <= [exp(|X|) e_1]_j
