@@ -368,6 +368,31 @@ def test_mixed_vs_fp64_reduced(torch_cuda, Prop, orc):
     assert np.all(sfp["round_bound"] == 0.0)
 
 
+@pytest.mark.parametrize("m,dt_scale", [(24, 1.0), (40, 1.0), (24, 4.0)])
+def test_storage_bound_wide_krylov(torch_cuda, Prop, orc, m, dt_scale):
+    """The storage bound of one mixed step at Krylov dimensions whose vector
+    spans 32 and 64 lanes (the quadrature's node sums over two lane groups or
+    one), and over a longer step (a wider Gershgorin interval, more nodes and
+    terms), against the formula on the oracle's tridiagonal T (Sec. 4 with the
+    perturbed Lanczos relation of the stored vectors)."""
+    cfg = packets.with_grid(packets.laser_4096(), 256)
+    dt = cfg["dt"] * dt_scale
+    prob = dict(cfg["problem"], t_pulse=100 * cfg["dt"])
+    say(f"storage bound 256x256 m={m} dt={dt}")
+    psi0 = packets.initial_state(cfg)
+    _, st = gpu_run(torch_cuda, Prop, prob, m, "mixed", psi0, 0.0, dt, 1)
+    assert st["k_eff"][0] == m
+    keff, _, al, be = orc.lanczos(prob, psi0, m, dt=dt, a_hom=tuple(orc.field_average(prob, 0.0, dt)))
+    assert keff == m
+    rad = np.abs(np.r_[be[:m - 1], 0.0]) + np.abs(np.r_[0.0, be[:m - 1]])
+    half_width = 0.5 * (np.max(al + rad) - np.min(al - rad))
+    expect = hz.storage_bound(al, be, np.linalg.norm(psi0), 2.0 ** -24,
+                              2.0 ** -126 * math.sqrt(4 * prob["nx"] * prob["ny"]))
+    print(f"R = {half_width:.2f}: device {st['round_bound'][0]:.6e}, formula {expect:.6e}", flush=True)
+    assert half_width <= 40.0  # the quadrature branch
+    assert abs(st["round_bound"][0] - expect) <= 2e-2 * expect, (st["round_bound"][0], expect)
+
+
 def test_wide_recombination_ragged(torch_cuda, Prop, orc):
     """A mixed-precision grid above the size where the recombination switches
     to 16 sites per thread (one wide tile per compute unit: 1,048,576 sites
