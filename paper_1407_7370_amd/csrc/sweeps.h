@@ -1264,7 +1264,9 @@ __device__ double storage_bound(double d, double e, double em, int k, int lane, 
                 a3 += r3[n + 2] * w4;
                 b3 -= r3[n + 3] * w5;
             }
-            // normalised before squaring: the unnormalised sums reach 1e290
+            // normalised before squaring: the unnormalised sums and their
+            // normalising factor each span up to 1e+-270, beyond the range
+            // of their squares
             const double s0 = jsc[q], s1 = jsc[q + 1], s2 = jsc[q + 2], s3 = jsc[q + 3];
             a0 *= s0;
             b0 *= s0;
