@@ -175,8 +175,8 @@ def test_adjoint_rejections(torch_cuda, Prop):
 
 def test_adjoint_fourier_512_full(torch_cuda, Prop, orc):
     """The 512^2, 2000-step Fourier-pulse workload (checkpoints every 50):
-    gradient components against central differences of the GPU forward map,
-    whose loss is evaluated by the oracle on the final state."""
+    every gradient component against central differences of the GPU forward
+    map, whose loss is evaluated by the oracle on the final state."""
     torch = torch_cuda
     cfg = packets.fourier_pulse_512(seed=0)
     prob, m, dt, n = cfg["problem"], cfg["m"], cfg["dt"], cfg["steps"]
@@ -196,8 +196,7 @@ def test_adjoint_fourier_512_full(torch_cuda, Prop, orc):
 
     c0 = np.asarray(prob["coef"], dtype=np.float64)
     assert abs(loss - loss_at(c0)) <= 1e-10 * max(1.0, abs(loss))
-    j_big = int(np.argmax(np.abs(grad)))
-    for j in sorted({j_big, 1}):
+    for j in range(len(c0)):
         # over 2000 steps the loss is far from quadratic at h ~ 0.5; central
         # differences enter their O(h^2) regime below h ~ 0.1
         h = 0.0625
