@@ -1531,6 +1531,54 @@ __device__ __forceinline__ void combine_body(const CombArgs &a, int blk, int nbl
     const size_t sites = a.sites;
     const size_t tile = (size_t)kBlock * S;
     constexpr size_t kSite = 2 * sizeof(TB);
+    if constexpr (!kPairs) {
+        // FP64: element by element (one complex128 of one component per lane
+        // and slot: element e is component e & 1 of site e >> 1), so that
+        // consecutive lanes read consecutive 16-byte elements of the paired
+        // basis; a tile of kBlock * S sites is 2 S elements per thread.  Each
+        // element is c_1 psi + sum_j c_j u_j in order j = 2..k, as one
+        // component of the complex64 site form below.
+        const size_t nel = 2 * sites;
+        for (size_t s0 = (size_t)blk * tile; s0 < sites; s0 += (size_t)nblk * tile) {
+            const size_t e0 = 2 * s0;
+            double ar[2 * S], ai[2 * S];
+            {
+                const double cr = k >= 1 ? cf(2) : 0.0, ci = k >= 1 ? cf(3) : 0.0;
+#pragma unroll
+                for (int q = 0; q < 2 * S; ++q) {
+                    const size_t e = e0 + (size_t)q * kBlock + threadIdx.x;
+                    double2 p = make_double2(0.0, 0.0);
+                    if (e < nel) p = ld_stream(a.psi + (e & 1) * sites + (e >> 1));
+                    ar[q] = cr * p.x - ci * p.y;
+                    ai[q] = cr * p.y + ci * p.x;
+                }
+            }
+            for (int j = 2; j <= k; ++j) {
+                const double2 *u = reinterpret_cast<const double2 *>(basis + (size_t)(j - 2) * a.vec_bytes);
+                double2 v[2 * S];
+#pragma unroll
+                for (int q = 0; q < 2 * S; ++q) {
+                    const size_t e = e0 + (size_t)q * kBlock + threadIdx.x;
+                    v[q] = e < nel ? ld_stream(u + e) : make_double2(0.0, 0.0);
+                }
+                const double cr = sc->coef[2 * j], ci = sc->coef[2 * j + 1];
+#pragma unroll
+                for (int q = 0; q < 2 * S; ++q) {
+                    ar[q] += cr * v[q].x - ci * v[q].y;
+                    ai[q] += cr * v[q].y + ci * v[q].x;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 2 * S; ++q) {
+                const size_t e = e0 + (size_t)q * kBlock + threadIdx.x;
+                if (e < nel) {
+                    st_stream(a.out + (e & 1) * sites + (e >> 1), ar[q], ai[q]);
+                    nrm += ar[q] * ar[q] + ai[q] * ai[q];
+                }
+            }
+        }
+        return;
+    }
     for (size_t s0 = (size_t)blk * tile; s0 < sites; s0 += (size_t)nblk * tile) {
         Sp acc[S];
         {
@@ -1583,25 +1631,6 @@ __device__ __forceinline__ void combine_body(const CombArgs &a, int blk, int nbl
                 Raw<TB> v[S];
                 load(j, v);
                 add(j, v);
-            }
-        } else {
-            for (int j = 2; j <= k; ++j) {
-                const char *u = basis + (size_t)(j - 2) * a.vec_bytes;
-                Raw<TB> v[S];
-#pragma unroll
-                for (int q = 0; q < S; ++q) {
-                    const size_t s = s0 + (size_t)q * kBlock + threadIdx.x;
-                    v[q] = s < sites ? ld_site<TB>(u + s * kSite) : raw_zero<TB>();
-                }
-                const double cr = sc->coef[2 * j], ci = sc->coef[2 * j + 1];
-#pragma unroll
-                for (int q = 0; q < S; ++q) {
-                    const Sp w = to_sp(v[q]);
-                    acc[q].r0 += cr * w.r0 - ci * w.i0;
-                    acc[q].i0 += cr * w.i0 + ci * w.r0;
-                    acc[q].r1 += cr * w.r1 - ci * w.i1;
-                    acc[q].i1 += cr * w.i1 + ci * w.r1;
-                }
             }
         }
 #pragma unroll
