@@ -12,7 +12,7 @@
  * beta = sigma3):
  *     H = c [sigma1 (p_x - q A_x) + sigma2 (p_y - q A_y)] + m c^2 sigma3 + V
  * with p = -i d/dx realised by central first-derivative differences
- * (f[i+1] - f[i-1]) / (2h) (Sec. 7 "first order finite differences"),
+ * (f[i+1] - f[i-1]) / (2h) (Sec. 7, first-order finite differences),
  * A = (B/2)(-y, x) + A_L(t) (uniform B_z in the symmetric gauge plus a
  * homogeneous laser field), and V the potential energy q*phi.
  *
@@ -168,7 +168,7 @@ dl_status dirac_lanczos_apply(dl_context *ctx, const void *x, void *y, double t)
  * average of A_L over [t0 + n dt, t0 + (n+1) dt] (first Magnus term).  Each step
  * runs the m-step Lanczos recurrence of Fig. 1 (in an algebraically equal,
  * single-sweep-per-iteration order), the small exponential exp(-iT) e_1
- * (Sec. 4, "any standard method": a Chebyshev expansion on the vector while
+ * (Sec. 4 leaves the method open: a Chebyshev expansion on the vector while
  * the Gershgorin half-width of T shifted to its centre is below about 190,
  * otherwise an eigendecomposition of T by implicit QR), and recombines the
  * Krylov basis (eq. matrix_exp_approx).  psi (DEVICE) is updated in place and

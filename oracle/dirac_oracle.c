@@ -38,7 +38,7 @@
  *
  * Readings where the paper is silent (shared with the GPU library only as
  * written conventions, never as code):
- *   - "first order finite differences" = central first-derivative
+ *   - first-order finite differences (Sec. 7) = central first-derivative
  *     differences (f[j+1]-f[j-1])/(2h), the 3-point form that keeps -iD
  *     Hermitian (Hermiticity is required in Sec. 4 and Sec. 8).
  *   - grid x_i = x_min + i*h, h = (x_max-x_min)/n; Dirichlet boundaries mean
